@@ -1,0 +1,289 @@
+"""FP64 CPU oracle of the FGS mapping hot path (arXiv 2503.01109), as a ctypes binding.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU
+baseline leg use it to check and time the HIP library. The product path never imports
+it, and it shares no code with the HIP library.
+
+Inputs are numpy arrays; gaussian parameters are the (14, N) SoA block described in
+``synth``. Cameras are any object with width, height, fx, fy, cx, cy, R (3x3), t (3,),
+z_near attributes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("R", C.c_double * 9), ("t", C.c_double * 3),
+                ("z_near", C.c_double)]
+
+
+class _RenderOpts(C.Structure):
+    _fields_ = [("sigma_cut", C.c_double), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("T_min", C.c_double), ("lowpass", C.c_double), ("bg", C.c_double * 3),
+                ("bg_depth", C.c_double)]
+
+
+class _SeedOpts(C.Structure):
+    _fields_ = [("D0", C.c_double), ("m", C.c_int32), ("n", C.c_int32), ("tile", C.c_int32),
+                ("alpha_h", C.c_double), ("alpha_l", C.c_double), ("opacity_logit", C.c_double),
+                ("depth_min", C.c_double), ("depth_max", C.c_double)]
+
+
+@dataclass
+class RenderOpts:
+    """Cutoffs of the compositing (3-sigma, alpha >= 1/255, alpha <= 0.99, stop before T < 1e-4)."""
+    sigma_cut: float = 3.0
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    lowpass: float = 0.3
+    bg: tuple = (0.0, 0.0, 0.0)
+    bg_depth: float = 0.0
+
+    def c(self) -> _RenderOpts:
+        o = _RenderOpts()
+        o.sigma_cut, o.alpha_min, o.alpha_max = self.sigma_cut, self.alpha_min, self.alpha_max
+        o.T_min, o.lowpass, o.bg_depth = self.T_min, self.lowpass, self.bg_depth
+        o.bg[:] = [float(v) for v in self.bg]
+        return o
+
+
+@dataclass
+class SeedOpts:
+    """Fourier seeding constants: high-pass radius D0 (frequency samples), lattice strides m < n,
+    tile edge for the per-tile count, Eq. 11 radius factors, initial opacity logit, depth range."""
+    D0: float = 30.0
+    m: int = 2
+    n: int = 8
+    tile: int = 16
+    alpha_h: float = 1.0
+    alpha_l: float = 4.0
+    opacity_logit: float = 0.0
+    depth_min: float = 0.1
+    depth_max: float = 10.0
+
+    def c(self) -> _SeedOpts:
+        o = _SeedOpts()
+        for k in ("D0", "m", "n", "tile", "alpha_h", "alpha_l", "opacity_logit", "depth_min", "depth_max"):
+            setattr(o, k, getattr(self, k))
+        return o
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.fgso_project.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), _dp]
+        L.fgso_render_fwd.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), C.c_int,
+                                      C.c_int64, _i64p, _dp, _dp, _dp, _dp, _i32p, _u8p, C.c_double, _dp]
+        L.fgso_render_bwd.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), C.c_int,
+                                      C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp]
+        L.fgso_count_duplicates.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts),
+                                            C.c_int32, C.c_int32]
+        L.fgso_count_duplicates.restype = C.c_int64
+        L.fgso_loss_l1.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
+        L.fgso_adam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _dp, C.c_double, C.c_double,
+                                C.c_double]
+        L.fgso_highpass.argtypes = [C.c_int32, C.c_int32, _fp, C.c_double, _dp, _i64p, _i32p, _dp]
+        L.fgso_triangle.argtypes = [_i64p]
+        L.fgso_triangle.restype = C.c_int32
+        L.fgso_seed.argtypes = [C.c_int32, C.c_int32, _fp, _fp, _fp, _fp, C.c_float, C.c_float, C.c_float,
+                                C.c_float, C.POINTER(_SeedOpts), C.c_int64, _i32p, _u8p, _fp, _fp, _fp,
+                                _i32p, _i32p, _dp]
+        L.fgso_seed.restype = C.c_int64
+        L.fgso_tile_features.argtypes = [C.c_int32, C.c_int32, _fp, _fp, C.c_int32, C.c_int32, C.c_double,
+                                         C.c_double, _dp]
+        L.fgso_mlp_fwd.argtypes = [C.c_int64, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.fgso_mlp_bwd.argtypes = [C.c_int64, _dp, _dp, C.c_int, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cam(cam) -> _Camera:
+    c = _Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float64).reshape(9)]
+    c.t[:] = [float(v) for v in np.asarray(cam.t, np.float64).reshape(3)]
+    c.z_near = float(cam.z_near)
+    return c
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ValueError(f"oracle {what} rejected its arguments (status {rc})")
+
+
+def project(params, cam, opts: RenderOpts | None = None) -> np.ndarray:
+    """(N, 16) per-gaussian projection: valid, t(3), cov2(3), conic(3), mean2(2), depth, opacity, 0, 0."""
+    p = _d(params)
+    n = p.shape[1]
+    out = np.zeros((n, 16))
+    _check(lib().fgso_project(n, _ptr(p, _dp), C.byref(_cam(cam)), C.byref((opts or RenderOpts()).c()),
+                              _ptr(out, _dp)), "project")
+    return out
+
+
+def render_fwd(params, cam, opts: RenderOpts | None = None, mode: int = 0, pix=None,
+               amb_rel: float = 1e-5) -> dict:
+    """Eq. 1 for every pixel (or for the pixel indices `pix`). mode 0: tile-bucketed, 1: brute force."""
+    p = _d(params)
+    n = p.shape[1]
+    pixa = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    m = cam.width * cam.height if pixa is None else pixa.shape[0]
+    rgb = np.zeros((3, m)); depth = np.zeros(m); alpha = np.zeros(m); T = np.zeros(m)
+    nc = np.zeros(m, np.int32); amb = np.zeros(m, np.uint8); stats = np.zeros(4)
+    rc = lib().fgso_render_fwd(n, _ptr(p, _dp), C.byref(_cam(cam)), C.byref((opts or RenderOpts()).c()),
+                               mode, m, _ptr(pixa, _i64p), _ptr(rgb, _dp), _ptr(depth, _dp),
+                               _ptr(alpha, _dp), _ptr(T, _dp), _ptr(nc, _i32p), _ptr(amb, _u8p),
+                               float(amb_rel), _ptr(stats, _dp))
+    _check(rc, "render_fwd")
+    out = dict(rgb=rgb, depth=depth, alpha=alpha, T_final=T, n_contrib=nc, amb=amb.astype(bool),
+               E_f=stats[0], E_c=stats[1], n_amb=int(stats[2]))
+    if pixa is None:
+        H, W = cam.height, cam.width
+        for k in ("depth", "alpha", "T_final", "n_contrib", "amb"):
+            out[k] = out[k].reshape(H, W)
+        out["rgb"] = rgb.reshape(3, H, W)
+    return out
+
+
+def render_bwd(params, cam, g_rgb, g_depth, g_alpha=None, opts: RenderOpts | None = None,
+               mode: int = 0, pix=None):
+    """Analytic backward: returns (dL/dparams (14, N), dL/d2D (10, N))."""
+    p = _d(params)
+    n = p.shape[1]
+    pixa = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    m = cam.width * cam.height if pixa is None else pixa.shape[0]
+    gr = _d(np.reshape(g_rgb, (3, m))); gd = _d(np.reshape(g_depth, (m,)))
+    ga = None if g_alpha is None else _d(np.reshape(g_alpha, (m,)))
+    grad = np.zeros((14, n)); grad2d = np.zeros((10, n))
+    rc = lib().fgso_render_bwd(n, _ptr(p, _dp), C.byref(_cam(cam)), C.byref((opts or RenderOpts()).c()),
+                               mode, m, _ptr(pixa, _i64p), _ptr(gr, _dp), _ptr(gd, _dp), _ptr(ga, _dp),
+                               _ptr(grad, _dp), _ptr(grad2d, _dp))
+    _check(rc, "render_bwd")
+    return grad, grad2d
+
+
+def count_duplicates(params, cam, tile_w=16, tile_h=16, opts: RenderOpts | None = None) -> int:
+    p = _d(params)
+    return int(lib().fgso_count_duplicates(p.shape[1], _ptr(p, _dp), C.byref(_cam(cam)),
+                                           C.byref((opts or RenderOpts()).c()), tile_w, tile_h))
+
+
+def loss_l1(rgb, depth, rgb_t, depth_t, lambda_rgb=1.0, lambda_depth=0.1):
+    """Returns (loss, psnr, dL/drgb, dL/ddepth)."""
+    r, d, rt, dt = _d(rgb).ravel(), _d(depth).ravel(), _d(rgb_t).ravel(), _d(depth_t).ravel()
+    P = d.shape[0]
+    gr = np.zeros_like(r); gd = np.zeros_like(d)
+    L = C.c_double(); ps = C.c_double()
+    _check(lib().fgso_loss_l1(P, _ptr(r, _dp), _ptr(d, _dp), _ptr(rt, _dp), _ptr(dt, _dp), lambda_rgb,
+                              lambda_depth, _ptr(gr, _dp), _ptr(gd, _dp), C.byref(L), C.byref(ps)), "loss")
+    return L.value, ps.value, gr.reshape(np.shape(rgb)), gd.reshape(np.shape(depth))
+
+
+def adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam update; returns new (params, m, v) as float64 copies."""
+    p, mm, vv, g = _d(params).copy(), _d(m).copy(), _d(v).copy(), _d(grad)
+    lra = _d(lr)
+    _check(lib().fgso_adam(p.shape[1], _ptr(p, _dp), _ptr(mm, _dp), _ptr(vv, _dp), _ptr(g, _dp), int(step),
+                           _ptr(lra, _dp), beta1, beta2, eps), "adam")
+    return p, mm, vv
+
+
+def highpass(rgb, D0=30.0):
+    """Returns (E (H, W), hist (256,), threshold, margin)."""
+    r = np.ascontiguousarray(rgb, dtype=np.float32)
+    _, H, W = r.shape
+    E = np.zeros((H, W)); hist = np.zeros(256, np.int64); t = C.c_int32(); mg = C.c_double()
+    _check(lib().fgso_highpass(W, H, _ptr(r, _fp), D0, _ptr(E, _dp), _ptr(hist, _i64p), C.byref(t),
+                               C.byref(mg)), "highpass")
+    return E, hist, t.value, mg.value
+
+
+def triangle(hist) -> int:
+    h = np.ascontiguousarray(hist, dtype=np.int64)
+    assert h.shape == (256,)
+    return int(lib().fgso_triangle(_ptr(h, _i64p)))
+
+
+def seed(rgb, depth, cam, opts: SeedOpts | None = None, capacity: int | None = None) -> dict:
+    """Fourier seeding of one RGB-D frame; float outputs are binary32."""
+    o = opts or SeedOpts()
+    r = np.ascontiguousarray(rgb, dtype=np.float32)
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    _, H, W = r.shape
+    cap = capacity if capacity is not None else (W * H) // (o.m * o.m) + W + H + 16
+    pixel = np.zeros(cap, np.int32); hi = np.zeros(cap, np.uint8)
+    mean = np.zeros((3, cap), np.float32); rad = np.zeros(cap, np.float32)
+    srgb = np.zeros((3, cap), np.float32)
+    tx, ty = (W + o.tile - 1) // o.tile, (H + o.tile - 1) // o.tile
+    tc = np.zeros(tx * ty, np.int32)
+    t = C.c_int32(); mg = C.c_double()
+    R = np.ascontiguousarray(cam.R, np.float32).reshape(9)
+    tt = np.ascontiguousarray(cam.t, np.float32).reshape(3)
+    n = lib().fgso_seed(W, H, _ptr(r, _fp), _ptr(d, _fp), _ptr(R, _fp), _ptr(tt, _fp), cam.fx, cam.fy, cam.cx,
+                        cam.cy, C.byref(o.c()), cap, _ptr(pixel, _i32p), _ptr(hi, _u8p), _ptr(mean, _fp),
+                        _ptr(rad, _fp), _ptr(srgb, _fp), _ptr(tc, _i32p), C.byref(t), C.byref(mg))
+    _check(n, "seed")
+    k = min(n, cap)
+    return dict(n=int(n), pixel=pixel[:k], is_high=hi[:k].astype(bool), mean=mean[:, :k], radius=rad[:k],
+                rgb=srgb[:, :k], tile_count=tc.reshape(ty, tx), threshold=t.value, margin=mg.value)
+
+
+def tile_features(rgb, depth, tx, ty, depth_min=0.1, depth_max=10.0):
+    r = np.ascontiguousarray(rgb, dtype=np.float32)
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    _, H, W = r.shape
+    f = np.zeros(260)
+    nv = lib().fgso_tile_features(W, H, _ptr(r, _fp), _ptr(d, _fp), tx, ty, depth_min, depth_max, _ptr(f, _dp))
+    _check(nv, "tile_features")
+    return f, nv
+
+
+MLP_PARAMS = 133636
+
+
+def mlp_fwd(x, w, bf16=True):
+    xx = _d(x)
+    rows = xx.shape[0]
+    y = np.zeros((rows, 4))
+    _check(lib().fgso_mlp_fwd(rows, _ptr(xx, _dp), _ptr(_d(w), _dp), int(bf16), _ptr(y, _dp), None, None,
+                              None, None), "mlp_fwd")
+    return y
+
+
+def mlp_bwd(x, w, target, bf16=True):
+    """Gradient of the mean squared error w.r.t. the packed weights; returns (grad, loss)."""
+    xx, ww, tt = _d(x), _d(w), _d(target)
+    g = np.zeros(MLP_PARAMS); L = C.c_double()
+    _check(lib().fgso_mlp_bwd(xx.shape[0], _ptr(xx, _dp), _ptr(ww, _dp), int(bf16), _ptr(tt, _dp),
+                              _ptr(g, _dp), C.byref(L)), "mlp_bwd")
+    return g, L.value

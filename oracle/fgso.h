@@ -1,0 +1,137 @@
+/*
+ * FGS oracle: a plain, slow, FP64 CPU implementation of the mapping hot path of
+ * "FGS-SLAM: Fourier-based Gaussian Splatting for Real-time SLAM with Sparse and
+ * Dense Map Fusion" (arXiv 2503.01109).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. The product path (the
+ * HIP library) never calls it, and the two share no code.
+ *
+ * Every function takes host pointers. Gaussian parameters are one SoA block of
+ * 14 planes of length n (stride n):
+ *   0-2 mean, 3-5 log-scale, 6-9 quaternion (w,x,y,z), 10 opacity logit, 11-13 rgb.
+ * Images are planes of width*height doubles, row-major (index y*width + x).
+ * Functions return 0 on success and a negative value on invalid arguments.
+ */
+#ifndef FGSO_H
+#define FGSO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+    double R[9];   /* world -> camera rotation, row-major: x_c = R x_w + t */
+    double t[3];
+    double z_near; /* gaussians with camera-space z <= z_near are culled */
+} fgso_camera;
+
+typedef struct {
+    double sigma_cut;  /* per-pixel cutoff: Mahalanobis distance <= sigma_cut (3) */
+    double alpha_min;  /* contributions with alpha < alpha_min are skipped (1/255) */
+    double alpha_max;  /* alpha is clamped to alpha_max (0.99) */
+    double T_min;      /* stop before transmittance would drop below T_min (1e-4) */
+    double lowpass;    /* added to the diagonal of the screen-space covariance (0.3 px^2) */
+    double bg[3];      /* background colour */
+    double bg_depth;   /* background depth */
+} fgso_render_opts;
+
+/* Per-gaussian projection, 16 doubles per gaussian:
+ * valid, t_x, t_y, t_z, cov2_xx, cov2_xy, cov2_yy, conic_a, conic_b, conic_c,
+ * mean2_x, mean2_y, depth, opacity, reserved, reserved. */
+#define FGSO_PROJ_STRIDE 16
+int fgso_project(int64_t n, const double *params, const fgso_camera *cam,
+                 const fgso_render_opts *o, double *proj);
+
+/* Forward render (Eq. 1 with gamma = colour, depth and 1).
+ * mode 0: tile-bucketed candidate lists (a conservative pre-cull); mode 1: brute force.
+ * pix: optional list of n_pix pixel indices to render (NULL = all pixels); outputs are
+ * then indexed by list position. Outputs: rgb (3 planes), depth, alpha, T_final, n_contrib.
+ * amb (nullable): per-pixel flag set when any decision at this pixel lies within a
+ * relative amb_rel of its cutoff, or two contributors' depths tie within 1e-6 relative.
+ * stats (nullable, 4 doubles): pairs tested until termination (E_f), contributing pairs
+ * (E_c), flagged pixels, candidates (Q <= cut^2) before termination. */
+int fgso_render_fwd(int64_t n, const double *params, const fgso_camera *cam,
+                    const fgso_render_opts *o, int mode, int64_t n_pix, const int64_t *pix,
+                    double *rgb, double *depth, double *alpha, double *T_final,
+                    int32_t *n_contrib, uint8_t *amb, double amb_rel, double *stats);
+
+/* Analytic backward of fgso_render_fwd. g_rgb (3 planes), g_depth, g_alpha (nullable) are the
+ * upstream gradients of the rendered planes (indexed like the forward's outputs when pix is
+ * given). grad (14 planes) receives dL/dparams (overwritten). grad2d (nullable, 10 planes of n):
+ * dL/d(mean2_x, mean2_y, conic_a, conic_b, conic_c, opacity, r, g, b, depth). */
+int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
+                    const fgso_render_opts *o, int mode, int64_t n_pix, const int64_t *pix,
+                    const double *g_rgb, const double *g_depth, const double *g_alpha,
+                    double *grad, double *grad2d);
+
+/* Number of (tile, gaussian) duplicates under axis-aligned 3-sigma-box binning. */
+int64_t fgso_count_duplicates(int64_t n, const double *params, const fgso_camera *cam,
+                              const fgso_render_opts *o, int32_t tile_w, int32_t tile_h);
+
+/* L1 colour + depth loss (the L1 terms of the mapping loss, Eq. 16), mean-reduced.
+ * Writes dL/d(rgb planes) and dL/d(depth) and returns loss and PSNR. */
+int fgso_loss_l1(int64_t P, const double *rgb, const double *depth, const double *rgb_t,
+                 const double *depth_t, double lambda_rgb, double lambda_depth,
+                 double *g_rgb, double *g_depth, double *loss, double *psnr);
+
+/* Adam (Kingma and Ba) over 14 parameter planes; lr per group (mean, log-scale, quat,
+ * opacity, rgb). step = number of updates already done; this update is step+1. */
+int fgso_adam(int64_t n, double *params, double *m, double *v, const double *grad,
+              int64_t step, const double lr[5], double beta1, double beta2, double eps);
+
+/* ---------------------------- Fourier seeding (Sec. III-A) ---------------------------- */
+typedef struct {
+    double D0;               /* high-pass cutoff radius, frequency samples (Eq. 5) */
+    int32_t m, n;            /* lattice strides in high- and low-frequency regions */
+    int32_t tile;            /* tile edge for the per-tile seed count (16) */
+    double alpha_h, alpha_l; /* radius factors in pixels (Eq. 11) */
+    double opacity_logit;    /* initial opacity logit of every seed */
+    double depth_min, depth_max;
+} fgso_seed_opts;
+
+/* Seeding diagnostics (all outputs nullable):
+ *  E       (W*H) high-pass magnitude |I_h|
+ *  hist    (256) histogram of q = floor(255 E / E_max)
+ *  thresh  triangle threshold t (q > t is high frequency); -1 when E_max == 0
+ *  margin  min over pixels of the distance of 255 E / E_max to the nearest integer */
+int fgso_highpass(int32_t W, int32_t H, const float *rgb, double D0, double *E,
+                  int64_t *hist, int32_t *thresh, double *margin);
+
+/* Triangle threshold over a 256-bin histogram. */
+int32_t fgso_triangle(const int64_t *hist);
+
+/* Full seeding: returns the number of seeds (or < 0 on error). Seeds are written in
+ * ascending pixel order, at most `capacity`: pixel id, class (1 = high frequency),
+ * mean (3 planes of capacity), radius, rgb (3 planes of capacity). tile_count has
+ * ceil(W/tile)*ceil(H/tile) entries. Float outputs are binary32 values. */
+int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
+                  const float cam_R[9], const float cam_t[3], float fx, float fy, float cx, float cy,
+                  const fgso_seed_opts *o, int64_t capacity, int32_t *pixel, uint8_t *is_high,
+                  float *mean, float *radius, float *seed_rgb, int32_t *tile_count,
+                  int32_t *thresh_out, double *margin_out);
+
+/* ------------------------------- Learned prior MLP ------------------------------- */
+/* Tile features: 256 values log(1 + |F_c|) of the tile's 16x16 luma DFT (Eq. 2-4, centred),
+ * then mean, std, min, max of valid depth. Returns the number of valid-depth pixels. */
+int fgso_tile_features(int32_t W, int32_t H, const float *rgb, const float *depth,
+                       int32_t tx, int32_t ty, double depth_min, double depth_max, double *feat);
+
+/* MLP 260 -> 256 -> 256 -> 4 with exact-erf GELU. Weights row-major W1[256][260], b1[256],
+ * W2[256][256], b2[256], W3[4][256], b3[4], packed in that order (133,636 doubles).
+ * bf16 != 0 rounds every GEMM operand (weights, activations, upstream gradients) to
+ * bfloat16 (round to nearest even) before use; accumulation is FP64. */
+#define FGSO_MLP_PARAMS 133636
+int fgso_mlp_fwd(int64_t rows, const double *x, const double *w, int bf16, double *y,
+                 double *h1, double *h2, double *a1, double *a2);
+/* Backward of the mean-squared error 1/(rows*4) sum (y - target)^2; writes dL/dw (FP64). */
+int fgso_mlp_bwd(int64_t rows, const double *x, const double *w, int bf16, const double *target,
+                 double *gw, double *loss);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
