@@ -1,0 +1,198 @@
+/*
+ * fgs.h - C ABI of the MI355X (gfx950) implementation of the mapping hot path of
+ * "FGS-SLAM: Fourier-based Gaussian Splatting for Real-time SLAM with Sparse and
+ * Dense Map Fusion" (arXiv 2503.01109).
+ *
+ * The library renders a set of 3D gaussians G{mu, S, R, alpha, c} (Sec. III) by front-to-
+ * back alpha blending (Eq. 1, with gamma = colour, depth and 1), differentiates that
+ * rendering, optimises the map against an RGB-D frame with the L1 colour and depth terms of
+ * the mapping loss (Eq. 16) and Adam, and seeds new gaussians from a frame by the Fourier
+ * high-pass analysis of Sec. III-A (Eq. 2-8, the triangle threshold, Eq. 11).
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless a parameter is marked [host].
+ *  - The caller owns every buffer it passes; the library never frees them.
+ *  - Gaussian parameters are SoA float32 planes. A block of k planes with plane stride s holds
+ *    plane j at ptr + j*s. Quaternions are (w, x, y, z); scales are log-scales; opacity is a
+ *    logit (opacity = sigmoid); colour is RGB without view dependence.
+ *  - Images are float32 planes of width*height, row-major (index y*width + x). Pixel (x, y)
+ *    samples the continuous point (x + 0.5, y + 0.5).
+ *  - Every call enqueues its work on the context's HIP stream and returns without waiting;
+ *    outputs are valid once that stream reaches the point of the call.
+ *  - Argument checks run on the host before anything is enqueued; a rejected call enqueues
+ *    nothing and returns FGS_ERR_INVALID_ARG. Conditions only the device can see (more
+ *    (tile, gaussian) pairs than a buffer holds, more seeds than the output holds) are
+ *    recorded on the device and reported by fgs_ctx_check. No C++ exception crosses the ABI.
+ *  - A context is not thread-safe; use one context per host thread and stream.
+ */
+#ifndef FGS_H
+#define FGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FGS_OK = 0,
+    FGS_ERR_INVALID_ARG = -1, /* bad size, stride, null pointer or option; nothing enqueued */
+    FGS_ERR_CAPACITY = -2,    /* a device buffer was too small; fgs_last_error gives the size */
+    FGS_ERR_HIP = -3,         /* a HIP runtime call failed; fgs_last_error gives its message */
+    FGS_ERR_UNSUPPORTED = -5  /* no gfx950 device, or an option this build does not provide */
+} fgs_status;
+
+typedef struct fgs_ctx fgs_ctx; /* opaque: stream, workspace, device status words */
+
+/* [host] Pinhole camera. World to camera: x_c = R_cw x_w + t_cw (R_cw row-major); the camera
+ * looks along +z with x to the right and y down. Gaussians with camera z <= z_near are culled. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R_cw[9];
+    float t_cw[3];
+    float z_near;
+} fgs_camera;
+
+/* Gaussian parameters (device). n gaussians; every plane has stride `stride` >= n elements.
+ * mean: 3 planes, log_scale: 3 planes, quat: 4 planes, opacity_logit: 1 plane, rgb: 3 planes.
+ * The same struct carries gradients (same layout) and Adam moments. */
+typedef struct {
+    int64_t n;
+    int64_t stride;
+    float *mean;
+    float *log_scale;
+    float *quat;
+    float *opacity_logit;
+    float *rgb;
+} fgs_gaussians;
+
+/* [host] Rendering cutoffs. A gaussian reaches a pixel when its Mahalanobis distance there is
+ * at most sigma_cut; its alpha = min(alpha_max, opacity * exp(-Q/2)) is skipped below alpha_min;
+ * a pixel stops before the first gaussian that would take its transmittance below T_min.
+ * lowpass is added to the diagonal of every projected 2D covariance (pixels^2). The background
+ * (bg, bg_depth) fills the remaining transmittance. tile_w x tile_h is the screen tile of the
+ * rasterizer (0, 0 = 16 x 16); supported shapes: 16x16, 32x8, 8x32, 32x16, 16x32, 8x8. */
+typedef struct {
+    float sigma_cut;
+    float alpha_min;
+    float alpha_max;
+    float T_min;
+    float lowpass;
+    float bg[3];
+    float bg_depth;
+    int32_t tile_w, tile_h;
+} fgs_render_opts;
+
+/* Rendered planes (device), each width*height; rgb holds 3 planes (stride width*height).
+ * alpha = sum_i w_i (Eq. 1 with gamma = 1), T_final = the remaining transmittance, n_contrib =
+ * the number of gaussians blended. alpha, T_final and n_contrib may be NULL. */
+typedef struct {
+    float *rgb;
+    float *depth;
+    float *alpha;
+    float *T_final;
+    int32_t *n_contrib;
+} fgs_image;
+
+/* [host] Adam state. m and v have the parameters' layout. step = updates already applied; a
+ * call applies update step+1 and increments step. lr per group: mean, log-scale, quaternion,
+ * opacity logit, rgb. */
+typedef struct {
+    fgs_gaussians m, v;
+    int64_t step;
+    float lr[5];
+    float beta1, beta2, eps;
+} fgs_adam;
+
+/* One RGB-D target view (device): rgb 3 planes and depth, width*height each. Depth <= 0 marks
+ * pixels without a depth measurement; they are left out of the depth term. */
+typedef struct {
+    const float *rgb;
+    const float *depth;
+} fgs_target;
+
+/* [host] Loss weights of the L1 colour and depth terms of Eq. 16 (mean over pixels; the depth
+ * mean runs over pixels with target depth > 0). */
+typedef struct {
+    float lambda_rgb, lambda_depth;
+} fgs_loss_opts;
+
+/* ------------------------------------------------------------------------------------------ */
+
+/* Create a context on the current HIP device bound to `hip_stream` (a hipStream_t; NULL = the
+ * null stream). Fails with FGS_ERR_UNSUPPORTED when the device is not gfx950. */
+fgs_status fgs_ctx_create(fgs_ctx **out, void *hip_stream);
+fgs_status fgs_ctx_destroy(fgs_ctx *ctx);
+/* Rebind the context to another stream (work already enqueued stays where it is). */
+fgs_status fgs_ctx_set_stream(fgs_ctx *ctx, void *hip_stream);
+
+/* Waits for the context's stream, then reports device-side conditions recorded since the last
+ * check: FGS_ERR_CAPACITY when a forward state or a seed output was too small (the required
+ * size is in fgs_last_error and fgs_ctx_stats). Clears the recorded conditions. */
+fgs_status fgs_ctx_check(fgs_ctx *ctx);
+
+/* [host] stats[0] = (tile, gaussian) pairs of the last forward, stats[1] = gaussians that
+ * survived culling, stats[2] = the largest pair count that overflowed a state (0 if none).
+ * Waits for the stream. */
+fgs_status fgs_ctx_stats(fgs_ctx *ctx, int64_t stats[4]);
+
+const char *fgs_status_str(fgs_status s);
+/* Copies the context's last error message (NUL-terminated, truncated to len). */
+fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len);
+
+/* ---------------------------- rendering (Eq. 1) and its gradient ---------------------------- */
+
+/* [host] Size in bytes of a forward state for n gaussians, a width x height image, the tile of
+ * `o` and room for max_pairs (tile, gaussian) pairs. */
+fgs_status fgs_state_bytes(int64_t n, int32_t width, int32_t height, int64_t max_pairs,
+                           const fgs_render_opts *o, int64_t *bytes);
+
+/* Forward render of g through cam (Sec. III, Eq. 1): EWA projection of every gaussian
+ * (covariance R S S^T R^T), binning into screen tiles, ordering of every tile's list by
+ * (depth, index), and front-to-back blending of colour, depth and opacity into `out`.
+ * `state` (device, state_bytes, caller-owned) receives what the backward needs; its pair
+ * capacity is what fgs_state_bytes reserved. If the scene needs more pairs than that, the
+ * image is incomplete and the next fgs_ctx_check returns FGS_ERR_CAPACITY. */
+fgs_status fgs_render_fwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam,
+                          const fgs_render_opts *o, const fgs_image *out, void *state,
+                          int64_t state_bytes);
+
+/* Gradient of a scalar loss through the forward that filled `state` (same g, cam and o).
+ * dL_drgb (3 planes), dL_ddepth and dL_dalpha (may be NULL) are the loss's gradients with
+ * respect to the rendered planes. The parameter gradients are ADDED to `grad` (same n;
+ * any stride >= n), so several views accumulate into one buffer. */
+fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam,
+                          const fgs_render_opts *o, const void *state, int64_t state_bytes,
+                          const float *dL_drgb, const float *dL_ddepth, const float *dL_dalpha,
+                          const fgs_gaussians *grad);
+
+/* ------------------------------------ mapping step ------------------------------------ */
+
+/* One mapping iteration over a window of n_views keyframes (Sec. III-E, map optimisation):
+ * for every view, render (Eq. 1), take the L1 colour and depth terms of Eq. 16 against the
+ * view's target, and accumulate the gradient; then one Adam update of `params` (opt->step is
+ * incremented on the host). cams and targets are [host] arrays of n_views. loss_dev and
+ * psnr_dev (device, n_views floats each, may be NULL) receive each view's loss and PSNR.
+ * grad_out (may be NULL) receives the summed gradient (overwritten). The context keeps the
+ * per-view states; it grows them when a scene needs more pairs than before. */
+fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt,
+                        int32_t n_views, const fgs_camera *cams, const fgs_target *targets,
+                        const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev,
+                        float *psnr_dev, const fgs_gaussians *grad_out);
+
+/* L1 loss of one rendered view (the L1 terms of Eq. 16) and its gradient: writes dL_drgb
+ * (3 planes), dL_ddepth, and the loss and PSNR (device floats, may be NULL). */
+fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth,
+                       const fgs_target *target, const fgs_loss_opts *l, float *dL_drgb,
+                       float *dL_ddepth, float *loss_dev, float *psnr_dev);
+
+/* One Adam update of params with gradient grad (opt->step is incremented on the host). */
+fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad,
+                         fgs_adam *opt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGS_H */

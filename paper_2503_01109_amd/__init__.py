@@ -1,0 +1,337 @@
+"""MI355X (gfx950) implementation of the FGS-SLAM mapping hot path (arXiv 2503.01109).
+
+This module is a thin ctypes binding of ``libfgs.so`` (include/fgs.h): it marshals torch
+tensors (device memory) and plain Python values into the C structs and calls the library.
+Every step of rendering, differentiation, loss, optimisation and seeding runs in the
+library's HIP kernels; nothing here computes any part of the method. There is no CPU
+fallback: without the built library the import fails.
+
+Gaussian parameters live in one float32 device tensor of shape (14, capacity), rows:
+0-2 mean, 3-5 log-scale, 6-9 quaternion (w, x, y, z), 10 opacity logit, 11-13 rgb;
+the first n columns are the gaussians.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(the HIP library is required; there is no fallback)")
+
+# torch ships its own HIP runtime (same soname as /opt/rocm's). Loading torch first makes the
+# library bind to that one runtime instead of pulling in a second copy from /opt/rocm.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, ERR_INVALID_ARG, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -5
+_fp = C.POINTER(C.c_float)
+_i32p = C.POINTER(C.c_int32)
+
+
+class FgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} [{_lib.fgs_status_str(status).decode()}]")
+        self.status = status
+
+
+class CCamera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R_cw", C.c_float * 9), ("t_cw", C.c_float * 3),
+                ("z_near", C.c_float)]
+
+
+class CGaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("stride", C.c_int64), ("mean", _fp), ("log_scale", _fp), ("quat", _fp),
+                ("opacity_logit", _fp), ("rgb", _fp)]
+
+
+class CRenderOpts(C.Structure):
+    _fields_ = [("sigma_cut", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
+                ("T_min", C.c_float), ("lowpass", C.c_float), ("bg", C.c_float * 3), ("bg_depth", C.c_float),
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+
+
+class CImage(C.Structure):
+    _fields_ = [("rgb", _fp), ("depth", _fp), ("alpha", _fp), ("T_final", _fp), ("n_contrib", _i32p)]
+
+
+class CAdam(C.Structure):
+    _fields_ = [("m", CGaussians), ("v", CGaussians), ("step", C.c_int64), ("lr", C.c_float * 5),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class CTarget(C.Structure):
+    _fields_ = [("rgb", _fp), ("depth", _fp)]
+
+
+class CLossOpts(C.Structure):
+    _fields_ = [("lambda_rgb", C.c_float), ("lambda_depth", C.c_float)]
+
+
+_vp = C.c_void_p
+_P = C.POINTER
+_sigs = {
+    "fgs_ctx_create": [_P(_vp), _vp],
+    "fgs_ctx_destroy": [_vp],
+    "fgs_ctx_set_stream": [_vp, _vp],
+    "fgs_ctx_check": [_vp],
+    "fgs_ctx_stats": [_vp, _P(C.c_int64)],
+    "fgs_last_error": [_vp, C.c_char_p, C.c_size_t],
+    "fgs_state_bytes": [C.c_int64, C.c_int32, C.c_int32, C.c_int64, _P(CRenderOpts), _P(C.c_int64)],
+    "fgs_render_fwd": [_vp, _P(CGaussians), _P(CCamera), _P(CRenderOpts), _P(CImage), _vp, C.c_int64],
+    "fgs_render_bwd": [_vp, _P(CGaussians), _P(CCamera), _P(CRenderOpts), _vp, C.c_int64, _fp, _fp, _fp,
+                       _P(CGaussians)],
+    "fgs_map_step": [_vp, _P(CGaussians), _P(CAdam), C.c_int32, _P(CCamera), _P(CTarget), _P(CRenderOpts),
+                     _P(CLossOpts), _fp, _fp, _P(CGaussians)],
+    "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
+    "fgs_adam_step": [_vp, _P(CGaussians), _P(CGaussians), _P(CAdam)],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.fgs_status_str.argtypes = [C.c_int]
+_lib.fgs_status_str.restype = C.c_char_p
+
+EXPORTED = sorted(list(_sigs) + ["fgs_status_str"])
+
+
+def last_error(ctx=None) -> str:
+    buf = C.create_string_buffer(1024)
+    _lib.fgs_last_error(ctx, buf, len(buf))
+    return buf.value.decode()
+
+
+def _check(st: int, ctx=None):
+    if st != OK:
+        raise FgsError(st, last_error(ctx))
+
+
+def _f32(t):
+    """Device float pointer of a contiguous float32 tensor (None -> NULL)."""
+    if t is None:
+        return None
+    assert t.dtype.is_floating_point and t.element_size() == 4, "float32 tensor expected"
+    assert t.is_contiguous(), "contiguous tensor expected"
+    return C.cast(C.c_void_p(t.data_ptr()), _fp)
+
+
+@dataclass
+class RenderOpts:
+    """Compositing cutoffs and the rasterizer tile (see fgs_render_opts)."""
+    sigma_cut: float = 3.0
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    lowpass: float = 0.3
+    bg: tuple = (0.0, 0.0, 0.0)
+    bg_depth: float = 0.0
+    tile_w: int = 16
+    tile_h: int = 16
+
+    def c(self) -> CRenderOpts:
+        o = CRenderOpts()
+        o.sigma_cut, o.alpha_min, o.alpha_max, o.T_min = self.sigma_cut, self.alpha_min, self.alpha_max, self.T_min
+        o.lowpass, o.bg_depth, o.tile_w, o.tile_h = self.lowpass, self.bg_depth, self.tile_w, self.tile_h
+        o.bg[:] = [float(v) for v in self.bg]
+        return o
+
+
+def camera(cam) -> CCamera:
+    """C camera from any object with width, height, fx, fy, cx, cy, R (3x3), t (3,), z_near."""
+    c = CCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = [float(v) for row in cam.R for v in row]
+    c.R_cw[:] = R
+    c.t_cw[:] = [float(v) for v in cam.t]
+    c.z_near = float(getattr(cam, "z_near", 0.2))
+    return c
+
+
+def gaussians(block, n: int | None = None) -> CGaussians:
+    """C view of a (14, capacity) float32 device tensor holding n gaussians."""
+    assert block.dim() == 2 and block.shape[0] == 14
+    assert block.is_contiguous()
+    cap = block.shape[1]
+    n = cap if n is None else n
+    base = block.data_ptr()
+    g = CGaussians()
+    g.n, g.stride = n, cap
+
+    def row(k):
+        return C.cast(C.c_void_p(base + 4 * k * cap), _fp)
+    g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb = row(0), row(3), row(6), row(10), row(11)
+    return g
+
+
+class Context:
+    """An fgs_ctx bound to a HIP stream (default: torch's current stream on the current device)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        p = C.c_void_p()
+        _check(_lib.fgs_ctx_create(C.byref(p), C.c_void_p(h)))
+        self._p = p
+
+    @property
+    def handle(self):
+        return self._p
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.fgs_ctx_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(_lib.fgs_ctx_set_stream(self._p, C.c_void_p(h)), self._p)
+
+    def check(self):
+        """Waits for the stream and raises FgsError(ERR_CAPACITY) on a recorded overflow."""
+        _check(_lib.fgs_ctx_check(self._p), self._p)
+
+    def stats(self) -> dict:
+        s = (C.c_int64 * 4)()
+        _check(_lib.fgs_ctx_stats(self._p, s), self._p)
+        return dict(pairs=s[0], visible=s[1], overflow=s[2], seeds=s[3])
+
+
+def state_bytes(n: int, width: int, height: int, max_pairs: int, opts: RenderOpts | None = None) -> int:
+    b = C.c_int64()
+    _check(_lib.fgs_state_bytes(n, width, height, max_pairs, C.byref((opts or RenderOpts()).c()), C.byref(b)))
+    return b.value
+
+
+def render_fwd(ctx: Context, params, n: int, cam, opts: RenderOpts, rgb, depth, state, alpha=None, T_final=None,
+               n_contrib=None):
+    img = CImage(_f32(rgb), _f32(depth), _f32(alpha), _f32(T_final),
+                 None if n_contrib is None else C.cast(C.c_void_p(n_contrib.data_ptr()), _i32p))
+    _check(_lib.fgs_render_fwd(ctx.handle, C.byref(gaussians(params, n)), C.byref(camera(cam)),
+                               C.byref(opts.c()), C.byref(img), C.c_void_p(state.data_ptr()),
+                               state.numel() * state.element_size()), ctx.handle)
+
+
+def render_bwd(ctx: Context, params, n: int, cam, opts: RenderOpts, state, dL_drgb, dL_ddepth, dL_dalpha, grad):
+    _check(_lib.fgs_render_bwd(ctx.handle, C.byref(gaussians(params, n)), C.byref(camera(cam)),
+                               C.byref(opts.c()), C.c_void_p(state.data_ptr()),
+                               state.numel() * state.element_size(), _f32(dL_drgb), _f32(dL_ddepth),
+                               _f32(dL_dalpha), C.byref(gaussians(grad, n))), ctx.handle)
+
+
+@dataclass
+class Adam:
+    """Adam state over a (14, capacity) parameter block (moments share its layout)."""
+    m: object
+    v: object
+    step: int = 0
+    lr: tuple = (1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3)
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+
+    @staticmethod
+    def like(params, **kw):
+        import torch
+        return Adam(torch.zeros_like(params), torch.zeros_like(params), **kw)
+
+    def c(self, n: int) -> CAdam:
+        a = CAdam()
+        a.m, a.v = gaussians(self.m, n), gaussians(self.v, n)
+        a.step = self.step
+        a.lr[:] = [float(x) for x in self.lr]
+        a.beta1, a.beta2, a.eps = self.beta1, self.beta2, self.eps
+        return a
+
+
+@dataclass
+class LossOpts:
+    lambda_rgb: float = 1.0
+    lambda_depth: float = 0.1
+
+    def c(self) -> CLossOpts:
+        return CLossOpts(self.lambda_rgb, self.lambda_depth)
+
+
+def map_step(ctx: Context, params, n: int, adam: Adam, cams, targets, opts: RenderOpts,
+             loss_opts: LossOpts | None = None, loss=None, psnr=None, grad_out=None):
+    """One mapping iteration over len(cams) views. targets: list of (rgb (3,H,W), depth (H,W)) tensors."""
+    V = len(cams)
+    ccams = (CCamera * V)(*[camera(c) for c in cams])
+    ctg = (CTarget * V)(*[CTarget(_f32(r), _f32(d)) for r, d in targets])
+    ca = adam.c(n)
+    _check(_lib.fgs_map_step(ctx.handle, C.byref(gaussians(params, n)), C.byref(ca), V, ccams, ctg,
+                             C.byref(opts.c()), C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
+                             None if grad_out is None else C.byref(gaussians(grad_out, n))), ctx.handle)
+    adam.step = ca.step
+
+
+def loss_l1(ctx: Context, rgb, depth, target_rgb, target_depth, loss_opts: LossOpts | None, dL_drgb, dL_ddepth,
+            loss=None, psnr=None):
+    tg = CTarget(_f32(target_rgb), _f32(target_depth))
+    _check(_lib.fgs_loss_l1(ctx.handle, depth.numel(), _f32(rgb), _f32(depth), C.byref(tg),
+                            C.byref((loss_opts or LossOpts()).c()), _f32(dL_drgb), _f32(dL_ddepth), _f32(loss),
+                            _f32(psnr)), ctx.handle)
+
+
+def adam_step(ctx: Context, params, grad, n: int, adam: Adam):
+    ca = adam.c(n)
+    _check(_lib.fgs_adam_step(ctx.handle, C.byref(gaussians(params, n)), C.byref(gaussians(grad, n)),
+                              C.byref(ca)), ctx.handle)
+    adam.step = ca.step
+
+
+def render(ctx: Context, params, n: int, cam, opts: RenderOpts | None = None, max_pairs: int | None = None,
+           aux: bool = True) -> dict:
+    """Allocate output planes and a forward state, render, and check for a pair overflow (growing the
+    state once to the reported size). Returns a dict of device tensors plus the state."""
+    import torch
+    opts = opts or RenderOpts()
+    dev = params.device
+    H, W = int(cam.height), int(cam.width)
+    pairs = max_pairs if max_pairs is not None else 64 * n + (1 << 16)
+    for _ in range(2):
+        nbytes = state_bytes(n, W, H, pairs, opts)
+        state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        out = dict(rgb=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                   depth=torch.empty((H, W), dtype=torch.float32, device=dev))
+        if aux:
+            out.update(alpha=torch.empty((H, W), dtype=torch.float32, device=dev),
+                       T_final=torch.empty((H, W), dtype=torch.float32, device=dev),
+                       n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
+        render_fwd(ctx, params, n, cam, opts, out["rgb"], out["depth"], state, out.get("alpha"),
+                   out.get("T_final"), out.get("n_contrib"))
+        try:
+            ctx.check()
+        except FgsError as e:
+            if e.status != ERR_CAPACITY:
+                raise
+            pairs = ctx_required_pairs(e) + 1024
+            continue
+        out["state"] = state
+        out["pairs"] = pairs
+        return out
+    raise FgsError(ERR_CAPACITY, "forward state still too small after growing it")
+
+
+def ctx_required_pairs(err: FgsError) -> int:
+    import re
+    m = re.search(r"(\d+) \(tile, gaussian\) pairs needed", str(err))
+    if not m:
+        raise err
+    return int(m.group(1))

@@ -1,0 +1,649 @@
+// C ABI of the FGS HIP library: context, workspace, argument checks and the enqueueing of the
+// forward, backward and mapping-step pipelines. See include/fgs.h for the contract of every call.
+#include "fgs.h"
+#include "fgs_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+namespace fgs {
+bool tile_supported(int tw, int th);
+void launch_scale(float *x, int64_t n, const float *s, hipStream_t st);
+}  // namespace fgs
+
+using namespace fgs;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want)
+    {
+        if (want <= bytes && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            bytes = 0;
+            if (e != hipSuccess) return e;
+        }
+        size_t b = want < 256 ? 256 : want;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as(size_t byte_off = 0) const { return (T *)((char *)p + byte_off); }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct fgs_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    // workspace of one forward (sized for the largest n / pair capacity seen)
+    DBuf rec_by_id, rect, count, dkA, dkB, idA, idB, blocksums, pkA, pkB, pvA, pvB, hist, grad2d;
+    DBuf words;  // status words (ST_WORDS) + small device scalars
+    int64_t ws_n = -1, ws_cap = -1;
+    // mapping-step buffers
+    DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
+    int64_t ms_cap = 0;
+    uint32_t *host_words = nullptr;  // pinned copy of the status words
+};
+
+namespace {
+
+// device words inside ctx->words
+constexpr int W_STATUS = 0;            // ST_WORDS u32
+constexpr int W_NDEV = ST_WORDS;       // n for the depth sort
+constexpr int W_NPAIRS = ST_WORDS + 1; // pairs to sort
+constexpr int W_DSCALE = ST_WORDS + 2; // float: 1/P_v of the depth term
+constexpr int W_TOTAL = ST_WORDS + 8;
+
+fgs_status fail(fgs_ctx *ctx, fgs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_thread_error = buf;
+    if (ctx) ctx->err = buf;
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess) return fail((ctx), FGS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+fgs_status check_camera(fgs_ctx *ctx, const fgs_camera *c, const char *what)
+{
+    if (!c) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: camera is NULL", what);
+    if (c->width <= 0 || c->height <= 0 || c->width > 16384 || c->height > 16384)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: image size %dx%d outside [1, 16384]", what, c->width, c->height);
+    if (!finite_pos(c->fx) || !finite_pos(c->fy))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: focal lengths must be finite and positive", what);
+    if (!isfinite(c->cx) || !isfinite(c->cy) || !isfinite(c->z_near) || c->z_near < 0.0f)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: principal point / z_near not finite (or z_near < 0)", what);
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(c->R_cw[k])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: R_cw not finite", what);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(c->t_cw[k])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: t_cw not finite", what);
+    return FGS_OK;
+}
+
+fgs_status check_opts(fgs_ctx *ctx, const fgs_render_opts *o, const char *what, int *tw, int *th)
+{
+    if (!o) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: render options are NULL", what);
+    if (!finite_pos(o->sigma_cut)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: sigma_cut must be > 0", what);
+    if (!(o->alpha_max > 0.0f && o->alpha_max < 1.0f))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: alpha_max must be in (0, 1)", what);
+    if (!(o->alpha_min >= 0.0f && o->alpha_min <= o->alpha_max))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: alpha_min must be in [0, alpha_max]", what);
+    if (!(o->T_min >= 0.0f && o->T_min < 1.0f)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: T_min must be in [0, 1)", what);
+    if (!(o->lowpass >= 0.0f) || !isfinite(o->lowpass))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: lowpass must be finite and >= 0", what);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(o->bg[k])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: background not finite", what);
+    if (!isfinite(o->bg_depth)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: background depth not finite", what);
+    int a = o->tile_w, b = o->tile_h;
+    if (a == 0 && b == 0) a = b = 16;
+    if (!tile_supported(a, b)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: unsupported tile %dx%d", what, a, b);
+    *tw = a;
+    *th = b;
+    return FGS_OK;
+}
+
+fgs_status check_gauss(fgs_ctx *ctx, const fgs_gaussians *g, const char *what, const char *name)
+{
+    if (!g) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %s is NULL", what, name);
+    if (g->n < 0 || g->n > (int64_t)1 << 30)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %s.n = %lld outside [0, 2^30]", what, name, (long long)g->n);
+    if (g->stride < g->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %s.stride < n", what, name);
+    if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->rgb))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %s has a NULL plane", what, name);
+    return FGS_OK;
+}
+
+int key_bits_for(int64_t T)
+{
+    int b = 1;
+    while (((int64_t)1 << b) < T) ++b;
+    return b;
+}
+
+CamK to_camk(const fgs_camera &c)
+{
+    CamK k;
+    k.W = c.width;
+    k.H = c.height;
+    k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy;
+    for (int i = 0; i < 9; ++i) k.R[i] = c.R_cw[i];
+    for (int i = 0; i < 3; ++i) k.t[i] = c.t_cw[i];
+    k.z_near = c.z_near;
+    return k;
+}
+
+RasterK to_rk(const fgs_render_opts &o, int tw, int th, int W, int H)
+{
+    RasterK r;
+    r.sigma_cut = o.sigma_cut; r.alpha_min = o.alpha_min; r.alpha_max = o.alpha_max;
+    r.T_min = o.T_min; r.lowpass = o.lowpass;
+    for (int k = 0; k < 3; ++k) r.bg[k] = o.bg[k];
+    r.bg_depth = o.bg_depth;
+    r.tile_w = tw; r.tile_h = th;
+    r.tiles_x = (W + tw - 1) / tw;
+    r.tiles_y = (H + th - 1) / th;
+    return r;
+}
+
+ParamsK to_pk(const fgs_gaussians &g)
+{
+    return ParamsK{g.n, g.stride, g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb};
+}
+
+GradK to_gk(const fgs_gaussians &g)
+{
+    return GradK{g.n, g.stride, g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb};
+}
+
+fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
+{
+    if (n <= ctx->ws_n && cap <= ctx->ws_cap) return FGS_OK;
+    const int64_t nn = n > ctx->ws_n ? n : ctx->ws_n;
+    const int64_t cc = cap > ctx->ws_cap ? cap : ctx->ws_cap;
+    const size_t N = (size_t)(nn > 0 ? nn : 1), C = (size_t)(cc > 0 ? cc : 1);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, ctx->rec_by_id.ensure(N * sizeof(Rec)));
+    HIP_TRY(ctx, ctx->rect.ensure(N * sizeof(uint2)));
+    HIP_TRY(ctx, ctx->count.ensure(N * 4));
+    HIP_TRY(ctx, ctx->dkA.ensure(N * 4));
+    HIP_TRY(ctx, ctx->dkB.ensure(N * 4));
+    HIP_TRY(ctx, ctx->idA.ensure(N * 4));
+    HIP_TRY(ctx, ctx->idB.ensure(N * 4));
+    HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks(nn) + 2) * 4));
+    HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
+    HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
+    HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
+    HIP_TRY(ctx, ctx->pvB.ensure(C * 4));
+    const int64_t G = sort_blocks(cc > nn ? cc : nn);
+    HIP_TRY(ctx, ctx->hist.ensure(((size_t)G * 256 + 256) * 4));
+    HIP_TRY(ctx, ctx->grad2d.ensure(N * 10 * 4));
+    ctx->ws_n = nn;
+    ctx->ws_cap = cc;
+    return FGS_OK;
+}
+
+SortWS sort_ws(fgs_ctx *ctx, int64_t elems)
+{
+    SortWS s;
+    s.G = sort_blocks(elems);
+    s.hist = ctx->hist.as<uint32_t>();
+    s.totals = ctx->hist.as<uint32_t>() + (size_t)sort_blocks(ctx->ws_cap > ctx->ws_n ? ctx->ws_cap : ctx->ws_n) * 256;
+    return s;
+}
+
+struct StatePtrs {
+    Rec *rec;
+    uint32_t *ids, *last, *vals;
+    uint2 *ranges;
+    float *tfinal;
+};
+
+StatePtrs state_ptrs(void *state, const StateLayout &L)
+{
+    char *b = (char *)state;
+    return StatePtrs{(Rec *)(b + L.off_rec), (uint32_t *)(b + L.off_ids), (uint32_t *)(b + L.off_last),
+                     (uint32_t *)(b + L.off_vals), (uint2 *)(b + L.off_ranges), (float *)(b + L.off_tfinal)};
+}
+
+uint32_t *status_words(fgs_ctx *ctx) { return ctx->words.as<uint32_t>() + W_STATUS; }
+
+fgs_status read_words(fgs_ctx *ctx);
+
+// Enqueue the forward pipeline into a state with layout L. With K_check, the call waits for the
+// pair count after the scan and, when it exceeds the state's capacity, returns FGS_ERR_CAPACITY
+// with the count in *K_check before enqueueing the rest.
+fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
+                           int tw, int th, const ImageK &img, void *state, const StateLayout &L,
+                           int64_t *K_check = nullptr)
+{
+    fgs_status st = ensure_ws(ctx, g.n, L.cap);
+    if (st != FGS_OK) return st;
+    hipStream_t s = ctx->stream;
+    const CamK ck = to_camk(cam);
+    const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
+    const ParamsK pk = to_pk(g);
+    const StatePtrs sp = state_ptrs(state, L);
+    uint32_t *words = ctx->words.as<uint32_t>();
+    uint32_t *ndev = words + W_NDEV, *npairs = words + W_NPAIRS;
+
+    launch_project(pk, ck, rk, ctx->rec_by_id.as<Rec>(), ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
+                   ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, s);
+    launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
+                      ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n), s);
+    launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx), s);
+    if (K_check) {
+        fgs_status st2 = read_words(ctx);
+        if (st2 != FGS_OK) return st2;
+        *K_check = ctx->host_words[ST_PAIRS];
+        if (*K_check > L.cap) return FGS_ERR_CAPACITY;
+    }
+    launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
+                ctx->blocksums.as<uint32_t>(), g.n, rk.tiles_x, L.cap, ctx->pkA.as<uint32_t>(),
+                ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs, s);
+    uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
+                                       ctx->pvB.as<uint32_t>(), sp.vals, npairs, L.cap, key_bits_for(L.T),
+                                       sort_ws(ctx, L.cap), s);
+    launch_ranges(keys, npairs, L.cap, sp.ranges, L.T, s);
+    launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
+                            int tw, int th, const void *state, const StateLayout &L, const float *drgb,
+                            const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians &grad)
+{
+    fgs_status st = ensure_ws(ctx, g.n, 0);
+    if (st != FGS_OK) return st;
+    hipStream_t s = ctx->stream;
+    const CamK ck = to_camk(cam);
+    const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
+    const StatePtrs sp = state_ptrs((void *)state, L);
+    float *g2 = ctx->grad2d.as<float>();
+    launch_zero_f32(g2, 10 * g.n, s);
+    launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb, ddepth, dalpha,
+                      dscale, g2, g.n, s);
+    launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), s);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+}  // namespace
+
+namespace fgs {
+
+bool state_layout(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64_t max_pairs, StateLayout *L)
+{
+    if (n < 0 || W <= 0 || H <= 0 || tw <= 0 || th <= 0 || max_pairs < 0) return false;
+    StateLayout l;
+    l.n = n; l.W = W; l.H = H; l.tw = tw; l.th = th;
+    l.tiles_x = (W + tw - 1) / tw;
+    l.tiles_y = (H + th - 1) / th;
+    l.T = (int64_t)l.tiles_x * l.tiles_y;
+    l.P = (int64_t)W * H;
+    size_t o = 0;
+    l.off_rec = o; o = align256(o + (size_t)n * sizeof(Rec));
+    l.off_ids = o; o = align256(o + (size_t)n * 4);
+    l.off_ranges = o; o = align256(o + (size_t)l.T * 8);
+    l.off_last = o; o = align256(o + (size_t)l.P * 4);
+    l.off_tfinal = o; o = align256(o + (size_t)l.P * 4);
+    l.fixed = o;
+    l.off_vals = o;
+    l.cap = max_pairs;
+    l.bytes = o + (size_t)max_pairs * 4;
+    *L = l;
+    return true;
+}
+
+int64_t state_capacity(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64_t bytes, StateLayout *L)
+{
+    if (!state_layout(n, W, H, tw, th, 0, L)) return -1;
+    if (bytes < (int64_t)L->fixed) return -1;
+    L->cap = (bytes - (int64_t)L->fixed) / 4;
+    if (L->cap > 0xFFFFFFF0ll) L->cap = 0xFFFFFFF0ll;  // pair indices are 32-bit
+    L->bytes = L->fixed + (size_t)L->cap * 4;
+    return L->cap;
+}
+
+}  // namespace fgs
+
+extern "C" {
+
+const char *fgs_status_str(fgs_status s)
+{
+    switch (s) {
+    case FGS_OK: return "ok";
+    case FGS_ERR_INVALID_ARG: return "invalid argument";
+    case FGS_ERR_CAPACITY: return "capacity exceeded";
+    case FGS_ERR_HIP: return "HIP runtime error";
+    case FGS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len)
+{
+    if (!buf || len == 0) return FGS_ERR_INVALID_ARG;
+    const std::string &e = ctx ? ctx->err : g_thread_error;
+    snprintf(buf, len, "%s", e.c_str());
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_create(fgs_ctx **out, void *hip_stream)
+{
+    if (!out) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_create: out is NULL");
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, FGS_ERR_UNSUPPORTED, "fgs_ctx_create: no HIP device (%s)", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(nullptr, FGS_ERR_HIP, "fgs_ctx_create: %s", hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, FGS_ERR_UNSUPPORTED, "fgs_ctx_create: device is %s, this library is built for gfx950",
+                    prop.gcnArchName);
+    fgs_ctx *c = new (std::nothrow) fgs_ctx();
+    if (!c) return fail(nullptr, FGS_ERR_HIP, "fgs_ctx_create: out of host memory");
+    c->device = dev;
+    c->stream = (hipStream_t)hip_stream;
+    e = c->words.ensure(W_TOTAL * 4);
+    if (e == hipSuccess) e = hipMemset(c->words.p, 0, W_TOTAL * 4);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_words, W_TOTAL * 4, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        fgs_ctx_destroy(c);
+        return fail(nullptr, FGS_ERR_HIP, "fgs_ctx_create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
+{
+    if (!ctx) return FGS_OK;
+    if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
+    DBuf *bufs[] = {&ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
+                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
+                    &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials};
+    for (DBuf *b : bufs) b->release();
+    if (ctx->host_words) (void)hipHostFree(ctx->host_words);
+    delete ctx;
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_set_stream(fgs_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_set_stream: ctx is NULL");
+    ctx->stream = (hipStream_t)hip_stream;
+    return FGS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+fgs_status read_words(fgs_ctx *ctx)
+{
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_words, ctx->words.p, W_TOTAL * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return FGS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_ctx_check(fgs_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_check: ctx is NULL");
+    fgs_status st = read_words(ctx);
+    if (st != FGS_OK) return st;
+    const uint32_t ovf = ctx->host_words[ST_OVERFLOW], sovf = ctx->host_words[ST_SEED_OVF];
+    if (ovf || sovf) {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, ctx->stream));
+        HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_SEED_OVF, 0, 4, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ovf)
+            return fail(ctx, FGS_ERR_CAPACITY, "forward state too small: %u (tile, gaussian) pairs needed", ovf);
+        return fail(ctx, FGS_ERR_CAPACITY, "seed output too small: %u seeds found", sovf);
+    }
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_stats(fgs_ctx *ctx, int64_t stats[4])
+{
+    if (!ctx || !stats) return fail(ctx, FGS_ERR_INVALID_ARG, "fgs_ctx_stats: NULL argument");
+    fgs_status st = read_words(ctx);
+    if (st != FGS_OK) return st;
+    stats[0] = ctx->host_words[ST_PAIRS];
+    stats[1] = ctx->host_words[ST_VISIBLE];
+    stats[2] = ctx->host_words[ST_OVERFLOW];
+    stats[3] = ctx->host_words[ST_SEEDS];
+    return FGS_OK;
+}
+
+fgs_status fgs_state_bytes(int64_t n, int32_t width, int32_t height, int64_t max_pairs, const fgs_render_opts *o,
+                           int64_t *bytes)
+{
+    int tw, th;
+    if (!bytes) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_state_bytes: bytes is NULL");
+    fgs_status st = check_opts(nullptr, o, "fgs_state_bytes", &tw, &th);
+    if (st != FGS_OK) return st;
+    if (max_pairs < 0 || max_pairs > 0xFFFFFFF0ll)
+        return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_state_bytes: max_pairs outside [0, 2^32 - 16]");
+    StateLayout L;
+    if (n < 0 || width <= 0 || height <= 0 || !state_layout(n, width, height, tw, th, max_pairs, &L))
+        return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_state_bytes: bad sizes");
+    *bytes = (int64_t)L.bytes;
+    return FGS_OK;
+}
+
+fgs_status fgs_render_fwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam, const fgs_render_opts *o,
+                          const fgs_image *out, void *state, int64_t state_bytes)
+{
+    const char *w = "fgs_render_fwd";
+    int tw, th;
+    fgs_status st;
+    if ((st = check_gauss(ctx, g, w, "g")) != FGS_OK) return st;
+    if ((st = check_camera(ctx, cam, w)) != FGS_OK) return st;
+    if ((st = check_opts(ctx, o, w, &tw, &th)) != FGS_OK) return st;
+    if (!out || !out->rgb || !out->depth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: image rgb/depth is NULL", w);
+    if (!state) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state is NULL", w);
+    StateLayout L;
+    if (state_capacity(g->n, cam->width, cam->height, tw, th, state_bytes, &L) < 0)
+        return fail(ctx, FGS_ERR_CAPACITY, "%s: state of %lld bytes is smaller than the %zu-byte fixed part", w,
+                    (long long)state_bytes, L.fixed);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    ImageK img{out->rgb, out->depth, out->alpha, out->T_final, out->n_contrib};
+    return enqueue_forward(ctx, *g, *cam, *o, tw, th, img, state, L);
+}
+
+fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam, const fgs_render_opts *o,
+                          const void *state, int64_t state_bytes, const float *dL_drgb, const float *dL_ddepth,
+                          const float *dL_dalpha, const fgs_gaussians *grad)
+{
+    const char *w = "fgs_render_bwd";
+    int tw, th;
+    fgs_status st;
+    if ((st = check_gauss(ctx, g, w, "g")) != FGS_OK) return st;
+    if ((st = check_gauss(ctx, grad, w, "grad")) != FGS_OK) return st;
+    if (grad->n != g->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad.n != g.n", w);
+    if ((st = check_camera(ctx, cam, w)) != FGS_OK) return st;
+    if ((st = check_opts(ctx, o, w, &tw, &th)) != FGS_OK) return st;
+    if (!dL_drgb || !dL_ddepth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: dL_drgb/dL_ddepth is NULL", w);
+    if (!state) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state is NULL", w);
+    StateLayout L;
+    if (state_capacity(g->n, cam->width, cam->height, tw, th, state_bytes, &L) < 0)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state of %lld bytes does not match n and the image size", w,
+                    (long long)state_bytes);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, *grad);
+}
+
+fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth, const fgs_target *target,
+                       const fgs_loss_opts *l, float *dL_drgb, float *dL_ddepth, float *loss_dev, float *psnr_dev)
+{
+    const char *w = "fgs_loss_l1";
+    if (n_pixels <= 0) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_pixels must be > 0", w);
+    if (!rgb || !depth || !target || !target->rgb || !target->depth || !l || !dL_drgb || !dL_ddepth)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: NULL argument", w);
+    if (!isfinite(l->lambda_rgb) || !isfinite(l->lambda_depth))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: loss weights not finite", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)loss_partials_size(n_pixels) * 4));
+    float *dscale = ctx->words.as<float>() + W_DSCALE;
+    launch_loss_l1(n_pixels, rgb, depth, target->rgb, target->depth, l->lambda_rgb, l->lambda_depth, dL_drgb,
+                   dL_ddepth, dscale, ctx->ms_partials.as<float>(), loss_dev, psnr_dev, ctx->stream);
+    launch_scale(dL_ddepth, n_pixels, dscale, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+static fgs_status check_adam(fgs_ctx *ctx, const fgs_adam *opt, int64_t n, const char *w)
+{
+    if (!opt) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: opt is NULL", w);
+    fgs_status st;
+    if ((st = check_gauss(ctx, &opt->m, w, "opt.m")) != FGS_OK) return st;
+    if ((st = check_gauss(ctx, &opt->v, w, "opt.v")) != FGS_OK) return st;
+    if (opt->m.n != n || opt->v.n != n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: Adam moments have n != params.n", w);
+    if (opt->step < 0) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: opt.step < 0", w);
+    if (!(opt->beta1 >= 0 && opt->beta1 < 1 && opt->beta2 >= 0 && opt->beta2 < 1) || !(opt->eps >= 0))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: beta1, beta2 must be in [0, 1) and eps >= 0", w);
+    for (int k = 0; k < 5; ++k)
+        if (!isfinite(opt->lr[k])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: learning rate not finite", w);
+    return FGS_OK;
+}
+
+static void enqueue_adam(fgs_ctx *ctx, const fgs_gaussians &p, const fgs_gaussians &grad, fgs_adam *opt)
+{
+    const double k = (double)(opt->step + 1);
+    const float bc1 = (float)(1.0 - pow((double)opt->beta1, k));
+    const float bc2 = (float)(1.0 - pow((double)opt->beta2, k));
+    launch_adam(to_gk(p), to_pk(grad), to_gk(opt->m), to_gk(opt->v), opt->lr, opt->beta1, opt->beta2, opt->eps, bc1,
+                bc2, ctx->stream);
+    opt->step += 1;
+}
+
+fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad, fgs_adam *opt)
+{
+    const char *w = "fgs_adam_step";
+    fgs_status st;
+    if ((st = check_gauss(ctx, params, w, "params")) != FGS_OK) return st;
+    if ((st = check_gauss(ctx, grad, w, "grad")) != FGS_OK) return st;
+    if (grad->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad.n != params.n", w);
+    if ((st = check_adam(ctx, opt, params->n, w)) != FGS_OK) return st;
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    enqueue_adam(ctx, *params, *grad, opt);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt, int32_t n_views,
+                        const fgs_camera *cams, const fgs_target *targets, const fgs_render_opts *o,
+                        const fgs_loss_opts *l, float *loss_dev, float *psnr_dev, const fgs_gaussians *grad_out)
+{
+    const char *w = "fgs_map_step";
+    int tw, th;
+    fgs_status st;
+    if ((st = check_gauss(ctx, params, w, "params")) != FGS_OK) return st;
+    if ((st = check_adam(ctx, opt, params->n, w)) != FGS_OK) return st;
+    if (n_views <= 0 || n_views > 4096) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_views outside [1, 4096]", w);
+    if (!cams || !targets) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: cams/targets is NULL", w);
+    if ((st = check_opts(ctx, o, w, &tw, &th)) != FGS_OK) return st;
+    if (!l || !isfinite(l->lambda_rgb) || !isfinite(l->lambda_depth))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: loss options NULL or not finite", w);
+    int64_t Pmax = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if ((st = check_camera(ctx, &cams[v], w)) != FGS_OK) return st;
+        if (!targets[v].rgb || !targets[v].depth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: target %d is NULL", w, v);
+        const int64_t P = (int64_t)cams[v].width * cams[v].height;
+        if (P > Pmax) Pmax = P;
+    }
+    if (grad_out) {
+        if ((st = check_gauss(ctx, grad_out, w, "grad_out")) != FGS_OK) return st;
+        if (grad_out->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad_out.n != params.n", w);
+    }
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    hipStream_t s = ctx->stream;
+    const int64_t n = params->n;
+    // summed gradient: the caller's buffer, or the context's
+    fgs_gaussians grad;
+    if (grad_out) {
+        grad = *grad_out;
+    } else {
+        HIP_TRY(ctx, ctx->ms_grad.ensure((size_t)(n > 0 ? n : 1) * 14 * 4));
+        float *b = ctx->ms_grad.as<float>();
+        grad = fgs_gaussians{n, n, b, b + 3 * n, b + 6 * n, b + 10 * n, b + 11 * n};
+    }
+    for (int k = 0; k < 14; ++k) {
+        float *pl = k < 3 ? grad.mean + k * grad.stride
+                  : k < 6 ? grad.log_scale + (k - 3) * grad.stride
+                  : k < 10 ? grad.quat + (k - 6) * grad.stride
+                  : k < 11 ? grad.opacity_logit
+                           : grad.rgb + (k - 11) * grad.stride;
+        launch_zero_f32(pl, n, s);
+    }
+    HIP_TRY(ctx, ctx->ms_img.ensure((size_t)Pmax * 4 * 4));
+    HIP_TRY(ctx, ctx->ms_dl.ensure((size_t)Pmax * 4 * 4));
+    HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)loss_partials_size(Pmax) * 4));
+    if (ctx->ms_cap == 0) ctx->ms_cap = n * 16 > ((int64_t)1 << 22) ? n * 16 : ((int64_t)1 << 22);
+    float *dscale = ctx->words.as<float>() + W_DSCALE;
+    for (int v = 0; v < n_views; ++v) {
+        const fgs_camera &cam = cams[v];
+        const int64_t P = (int64_t)cam.width * cam.height;
+        StateLayout L;
+        for (int attempt = 0;; ++attempt) {
+            state_layout(n, cam.width, cam.height, tw, th, ctx->ms_cap, &L);
+            HIP_TRY(ctx, ctx->ms_state.ensure(L.bytes));
+            float *im = ctx->ms_img.as<float>();
+            ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
+            // The pair count is data dependent: the forward waits for it after the scan and the
+            // view restarts with a larger state when it does not fit (the state keeps its size).
+            int64_t K = 0;
+            st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, &K);
+            if (st == FGS_OK) break;
+            if (st != FGS_ERR_CAPACITY || attempt > 0) return st;
+            ctx->ms_cap = K + K / 4 + 1024;
+        }
+        float *im = ctx->ms_img.as<float>();
+        float *dl = ctx->ms_dl.as<float>();
+        launch_loss_l1(P, im, im + 3 * P, targets[v].rgb, targets[v].depth, l->lambda_rgb, l->lambda_depth, dl,
+                       dl + 3 * P, dscale, ctx->ms_partials.as<float>(), loss_dev ? loss_dev + v : nullptr,
+                       psnr_dev ? psnr_dev + v : nullptr, s);
+        if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
+                                   grad)) != FGS_OK)
+            return st;
+    }
+    enqueue_adam(ctx, *params, grad, opt);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations of the FGS HIP library (gfx950): device helpers, kernel launchers,
+// and the layout of a forward state. Not part of the public ABI (include/fgs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fgs {
+
+constexpr int kWave = 64;
+
+// Camera and cutoffs as kernel arguments (by value). Projection runs in FP64, so the pose and
+// intrinsics are carried in double.
+struct CamK {
+    int32_t W, H;
+    double fx, fy, cx, cy;
+    double R[9];
+    double t[3];
+    double z_near;
+};
+
+struct RasterK {
+    float sigma_cut, alpha_min, alpha_max, T_min, lowpass;
+    float bg[3];
+    float bg_depth;
+    int32_t tile_w, tile_h, tiles_x, tiles_y;
+};
+
+// Gaussian parameter planes (device).
+struct ParamsK {
+    int64_t n, stride;
+    const float *mean, *log_scale, *quat, *logit, *rgb;
+};
+struct GradK {
+    int64_t n, stride;
+    float *mean, *log_scale, *quat, *logit, *rgb;
+};
+
+// Projected record of one gaussian, 3 x float4, in depth order inside a forward state:
+//  r0 = {ix, iy (int bits), fx, fy}: the projected mean as integer pixel + fraction
+//  r1 = {conic a, conic b, conic c, opacity}
+//  r2 = {r, g, b, depth}
+struct Rec {
+    float4 r0, r1, r2;
+};
+
+// Device status words of a context.
+enum : int {
+    ST_PAIRS = 0,      // (tile, gaussian) pairs of the last forward (may exceed capacity)
+    ST_VISIBLE = 1,    // gaussians kept by the last forward
+    ST_OVERFLOW = 2,   // largest pair count that did not fit (sticky until checked)
+    ST_SEEDS = 3,      // seeds found by the last seeding (may exceed capacity)
+    ST_SEED_OVF = 4,   // largest seed count that did not fit (sticky)
+    ST_WORDS = 16
+};
+
+// Layout of a forward state (one view). Everything the backward needs lives here; temporaries
+// live in the context's workspace.
+struct StateLayout {
+    int64_t n = 0, P = 0, T = 0;
+    int32_t W = 0, H = 0, tw = 0, th = 0, tiles_x = 0, tiles_y = 0;
+    size_t off_rec = 0;    // Rec x n, depth order
+    size_t off_ids = 0;    // u32 x n: gaussian id of depth rank r
+    size_t off_ranges = 0; // uint2 x T: [start, end) into vals per tile
+    size_t off_last = 0;   // u32 x P: list position after a pixel's last blended gaussian
+    size_t off_tfinal = 0; // f32 x P: final transmittance
+    size_t off_vals = 0;   // u32 x cap: depth ranks, per tile in (depth, index) order
+    int64_t cap = 0;
+    size_t fixed = 0, bytes = 0;
+};
+
+bool state_layout(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64_t max_pairs,
+                  StateLayout *L);
+// Capacity of a state of `bytes` bytes (pairs that fit), or -1 when even the fixed part does not.
+int64_t state_capacity(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64_t bytes,
+                       StateLayout *L);
+
+// ---------------------------------- launchers ----------------------------------
+// All take the stream last and only enqueue work.
+
+struct SortWS {  // radix-sort scratch of one sort
+    uint32_t *hist;    // 256 x G
+    uint32_t *totals;  // 256
+    int G;
+};
+int sort_blocks(int64_t cap);
+
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+void launch_zero_f32(float *p, int64_t n, hipStream_t s);
+
+// Projects every gaussian; writes n to *n_out (the element count of the depth sort).
+void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id,
+                    uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out,
+                    hipStream_t s);
+
+// LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
+// element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
+// (kb, vb); the last pass writes the values to v_final and the keys to the returned buffer.
+uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *v_final,
+                            const uint32_t *n_dev, int64_t n_cap, int key_bits, const SortWS &ws,
+                            hipStream_t s);
+
+// Exclusive scan of count[ids[r]] over depth ranks r, by blocks: blocksums (scan_blocks(n) + 1
+// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs.
+int64_t scan_blocks(int64_t n);
+void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
+                        uint32_t *status, hipStream_t s);
+
+// Emit one (tile, rank) pair per covered tile in depth order, and gather records into depth
+// order. If the pairs exceed cap, nothing is emitted for sorting (*n_pairs_dev = 0) and the
+// required count is recorded in status.
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
+                 const uint32_t *blocksums, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
+                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev,
+                 hipStream_t s);
+
+void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
+                   int64_t T, hipStream_t s);
+
+struct ImageK {
+    float *rgb, *depth, *alpha, *T_final;
+    int32_t *n_contrib;
+};
+
+void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
+                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
+                       hipStream_t s);
+
+// dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
+// to a device float multiplying ddepth (the 1/P_v of the mean depth term).
+void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
+                       const uint2 *ranges, const uint32_t *last, const float *tfinal,
+                       const float *drgb, const float *ddepth, const float *dalpha,
+                       const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s);
+
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
+                        const float *grad2d, const GradK &grad, hipStream_t s);
+
+// L1 loss of Eq. 16 (colour + depth terms) with its gradient; partials is scratch of
+// loss_partials_size(P) floats; writes loss/psnr device scalars (nullable) and the depth-gradient
+// scale 1/P_v into *ddepth_scale.
+int64_t loss_partials_size(int64_t P);
+void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float *trgb,
+                    const float *tdepth, float lrgb, float ldepth, float *drgb, float *ddepth,
+                    float *ddepth_scale, float *partials, float *loss, float *psnr, hipStream_t s);
+
+void launch_adam(const GradK &p, const ParamsK &g, const GradK &m, const GradK &v, const float lr[5],
+                 float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+
+}  // namespace fgs

@@ -1,0 +1,287 @@
+// EWA projection of 3D gaussians (Sec. III: covariance C = R S S^T R^T) and its backward.
+//
+// One thread per gaussian. Parameters are read as coalesced SoA planes; the arithmetic runs in
+// FP64 (a few hundred flops per gaussian, far below the kernel's memory time on gfx950) and the
+// outputs are rounded once to FP32. The projected mean is stored as integer pixel + FP32
+// fraction so that the rasterizer can form tile-local offsets without losing the fraction to
+// the magnitude of the pixel coordinate.
+#include "fgs_internal.h"
+
+namespace fgs {
+
+namespace {
+
+struct Proj {
+    bool valid;
+    double t[3];
+    double Rq[9], s[3], qn[4], qnorm;
+    double Sig[9], A[6];
+    double cov[3];   // Sigma'_xx, Sigma'_xy, Sigma'_yy (with low-pass)
+    double conic[3];
+    double m2[2];
+    double opacity;
+};
+
+__device__ inline void rot_from_quat(const double q[4], double R[9])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ inline void project_gaussian(const ParamsK &g, int64_t i, const CamK &cam, float lowpass,
+                                        Proj &p)
+{
+    p.valid = false;
+    const int64_t S = g.stride;
+    const double mu[3] = {g.mean[i], g.mean[S + i], g.mean[2 * S + i]};
+    const double q[4] = {g.quat[i], g.quat[S + i], g.quat[2 * S + i], g.quat[3 * S + i]};
+    p.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!(p.qnorm > 0.0) || !isfinite(p.qnorm)) return;
+    const double inv = 1.0 / p.qnorm;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p.qn[k] = q[k] * inv;
+    rot_from_quat(p.qn, p.Rq);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p.s[k] = exp((double)g.log_scale[k * S + i]);
+    // Sigma = (R S)(R S)^T
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = p.Rq[3 * r + c] * p.s[c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            p.Sig[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    const double *W = cam.R;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        p.t[r] = W[3 * r] * mu[0] + W[3 * r + 1] * mu[1] + W[3 * r + 2] * mu[2] + cam.t[r];
+    const double tx = p.t[0], ty = p.t[1], tz = p.t[2];
+    if (!(tz > cam.z_near)) return;
+    const double iz = 1.0 / tz;
+    const double J00 = cam.fx * iz, J02 = -cam.fx * tx * iz * iz;
+    const double J11 = cam.fy * iz, J12 = -cam.fy * ty * iz * iz;
+    // A = J W (J has zeros at (0,1) and (1,0))
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p.A[c] = J00 * W[c] + J02 * W[6 + c];
+        p.A[3 + c] = J11 * W[3 + c] + J12 * W[6 + c];
+    }
+    double AS[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            AS[3 * r + c] = p.A[3 * r] * p.Sig[c] + p.A[3 * r + 1] * p.Sig[3 + c] + p.A[3 * r + 2] * p.Sig[6 + c];
+    const double sxx = AS[0] * p.A[0] + AS[1] * p.A[1] + AS[2] * p.A[2];
+    const double sxy = AS[0] * p.A[3] + AS[1] * p.A[4] + AS[2] * p.A[5];
+    const double syy = AS[3] * p.A[3] + AS[4] * p.A[4] + AS[5] * p.A[5];
+    p.cov[0] = sxx + lowpass;
+    p.cov[1] = sxy;
+    p.cov[2] = syy + lowpass;
+    const double det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
+    if (!(det > 0.0) || !isfinite(det)) return;
+    const double idet = 1.0 / det;
+    p.conic[0] = p.cov[2] * idet;
+    p.conic[1] = -p.cov[1] * idet;
+    p.conic[2] = p.cov[0] * idet;
+    p.m2[0] = cam.fx * tx * iz + cam.cx;
+    p.m2[1] = cam.fy * ty * iz + cam.cy;
+    p.opacity = 1.0 / (1.0 + exp(-(double)g.logit[i]));
+    if (!isfinite(p.m2[0]) || !isfinite(p.m2[1]) || !isfinite(p.opacity)) return;
+    p.valid = true;
+}
+
+// Pixel-index range [lo, hi] of centres x + 0.5 within [c - r, c + r], clamped to [0, size).
+__device__ inline bool pixel_span(double c, double r, int32_t size, int32_t &lo, int32_t &hi)
+{
+    const double a = ceil(c - r - 0.5), b = floor(c + r - 0.5);
+    if (!(a <= b) || b < 0.0 || a > (double)(size - 1)) return false;
+    lo = a < 0.0 ? 0 : (int32_t)a;
+    hi = b > (double)(size - 1) ? size - 1 : (int32_t)b;
+    return true;
+}
+
+__global__ void __launch_bounds__(256)
+k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
+          uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
+          uint32_t *__restrict__ n_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *n_out = (uint32_t)g.n;
+    if (i >= g.n) return;
+    ids[i] = (uint32_t)i;
+    Proj p;
+    project_gaussian(g, i, cam, rk.lowpass, p);
+    uint32_t cnt = 0, key = 0xFFFFFFFFu;
+    uint2 rc = make_uint2(1u, 0u);
+    if (p.valid) {
+        // Conservative box of the sigma_cut ellipse (its exact half-widths are
+        // sigma_cut * sqrt(Sigma'_xx) and sigma_cut * sqrt(Sigma'_yy)), padded so that FP32
+        // evaluation of the per-pixel test in the rasterizer can never reach outside it.
+        const double rx = rk.sigma_cut * sqrt(p.cov[0]) * (1.0 + 1e-5) + 1e-3;
+        const double ry = rk.sigma_cut * sqrt(p.cov[2]) * (1.0 + 1e-5) + 1e-3;
+        int32_t x0, x1, y0, y1;
+        if (fabs(p.m2[0]) < 1e9 && fabs(p.m2[1]) < 1e9 && pixel_span(p.m2[0], rx, cam.W, x0, x1) &&
+            pixel_span(p.m2[1], ry, cam.H, y0, y1)) {
+            const uint32_t tx0 = x0 / rk.tile_w, tx1 = x1 / rk.tile_w;
+            const uint32_t ty0 = y0 / rk.tile_h, ty1 = y1 / rk.tile_h;
+            cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+            const double fxm = floor(p.m2[0]), fym = floor(p.m2[1]);
+            const float depth = (float)p.t[2];
+            key = __float_as_uint(depth);
+            Rec r;
+            r.r0 = make_float4(__int_as_float((int)fxm), __int_as_float((int)fym), (float)(p.m2[0] - fxm),
+                               (float)(p.m2[1] - fym));
+            r.r1 = make_float4((float)p.conic[0], (float)p.conic[1], (float)p.conic[2], (float)p.opacity);
+            const int64_t S = g.stride;
+            r.r2 = make_float4(g.rgb[i], g.rgb[S + i], g.rgb[2 * S + i], depth);
+            rec[i] = r;
+        }
+    }
+    count[i] = cnt;
+    dkey[i] = key;
+    rect[i] = rc;
+}
+
+// Backward of the projection for the gaussian of depth rank r (one thread each). grad2d holds
+// 10 planes of length n indexed by depth rank: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b;
+// depth). The 14 parameter gradients are added to grad (each gaussian has one rank, so no
+// atomics are needed).
+__global__ void __launch_bounds__(256)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
+              const float *__restrict__ grad2d, GradK grad)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = g.n;
+    if (r >= n) return;
+    double g2[10];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        g2[k] = grad2d[k * n + r];
+        any |= g2[k] != 0.0;
+    }
+    if (!any) return;
+    const int64_t i = ids[r];
+    Proj p;
+    project_gaussian(g, i, cam, rk.lowpass, p);
+    if (!p.valid) return;
+    // conic = Sigma'^-1: dL/dSigma' = -X Gh X with Gh = [[ga, gb/2], [gb/2, gc]], X the conic.
+    const double a = p.conic[0], b = p.conic[1], c = p.conic[2];
+    const double ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
+    const double XG00 = a * ga + b * gb, XG01 = a * gb + b * gc;
+    const double XG10 = b * ga + c * gb, XG11 = b * gb + c * gc;
+    const double d00 = -(XG00 * a + XG01 * b), d01 = -(XG00 * b + XG01 * c);
+    const double d10 = -(XG10 * a + XG11 * b), d11 = -(XG10 * b + XG11 * c);
+    const double D2[4] = {d00, 0.5 * (d01 + d10), 0.5 * (d01 + d10), d11};
+    // Sigma' = A Sigma A^T + l I: dSigma = A^T D2 A; dA = 2 D2 A Sigma
+    const double *A = p.A;
+    double DA[6];  // D2 A (2x3)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        DA[k] = D2[0] * A[k] + D2[1] * A[3 + k];
+        DA[3 + k] = D2[2] * A[k] + D2[3] * A[3 + k];
+    }
+    double dSig[9];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) dSig[3 * u + v] = A[u] * DA[v] + A[3 + u] * DA[3 + v];
+    double dA[6];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            dA[3 * rr + k] = 2.0 * (DA[3 * rr] * p.Sig[k] + DA[3 * rr + 1] * p.Sig[3 + k] +
+                                    DA[3 * rr + 2] * p.Sig[6 + k]);
+    // A = J W: dJ = dA W^T; only J00, J02, J11, J12 depend on t.
+    const double *W = cam.R;
+    const double dJ00 = dA[0] * W[0] + dA[1] * W[1] + dA[2] * W[2];
+    const double dJ02 = dA[0] * W[6] + dA[1] * W[7] + dA[2] * W[8];
+    const double dJ11 = dA[3] * W[3] + dA[4] * W[4] + dA[5] * W[5];
+    const double dJ12 = dA[3] * W[6] + dA[4] * W[7] + dA[5] * W[8];
+    const double tx = p.t[0], ty = p.t[1], tz = p.t[2], iz = 1.0 / tz;
+    const double fx = cam.fx, fy = cam.fy;
+    double dtx = 0, dty = 0, dtz = 0;
+    dtz += dJ00 * (-fx * iz * iz) + dJ02 * (2.0 * fx * tx * iz * iz * iz);
+    dtx += dJ02 * (-fx * iz * iz);
+    dtz += dJ11 * (-fy * iz * iz) + dJ12 * (2.0 * fy * ty * iz * iz * iz);
+    dty += dJ12 * (-fy * iz * iz);
+    dtx += g2[0] * fx * iz;
+    dtz += g2[0] * (-fx * tx * iz * iz);
+    dty += g2[1] * fy * iz;
+    dtz += g2[1] * (-fy * ty * iz * iz);
+    dtz += g2[9];
+    const int64_t S = grad.stride;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad.mean[k * S + i] += (float)(W[k] * dtx + W[3 + k] * dty + W[6 + k] * dtz);
+    // Sigma = M M^T, M = R diag(s): dM = 2 dSigma M
+    double M[9], dM[9];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) M[3 * u + k] = p.Rq[3 * u + k] * p.s[k];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            dM[3 * u + k] = 2.0 * (dSig[3 * u] * M[k] + dSig[3 * u + 1] * M[3 + k] + dSig[3 * u + 2] * M[6 + k]);
+    double dR[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double ds = p.Rq[k] * dM[k] + p.Rq[3 + k] * dM[3 + k] + p.Rq[6 + k] * dM[6 + k];
+        grad.log_scale[k * S + i] += (float)(ds * p.s[k]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) dR[3 * u + k] = dM[3 * u + k] * p.s[k];
+    }
+    // R(q_hat): partial derivatives of the nine entries by w, x, y, z.
+    const double w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
+    double dq[4];
+    dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
+                   w * dR[7] - 2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                   z * dR[7] - 2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
+                   y * dR[5] + x * dR[6] + y * dR[7]);
+    // q_hat = q/|q|: dq = (I - q_hat q_hat^T) dq_hat / |q|
+    const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    const double iq = 1.0 / p.qnorm;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) grad.quat[k * S + i] += (float)((dq[k] - p.qn[k] * dot) * iq);
+    grad.logit[i] += (float)(g2[5] * p.opacity * (1.0 - p.opacity));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad.rgb[k * S + i] += (float)g2[6 + k];
+}
+
+}  // namespace
+
+void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id, uint2 *rect,
+                    uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, hipStream_t s)
+{
+    const int64_t blocks = g.n > 0 ? (g.n + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec_by_id, rect, count,
+                       dkey, ids, n_out);
+}
+
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
+                        const float *grad2d, const GradK &grad, hipStream_t s)
+{
+    if (g.n <= 0) return;
+    const int64_t blocks = (g.n + 255) / 256;
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, ids, grad2d, grad);
+}
+
+}  // namespace fgs

@@ -1,0 +1,343 @@
+// Tile rasterizer: front-to-back alpha blending of Eq. 1 (colour, depth and opacity) and its
+// backward.
+//
+// One workgroup per screen tile, one pixel per thread. The tile's list (depth-ordered ranks of
+// the gaussians whose 3-sigma box touches the tile) is walked in batches; each batch of records
+// is gathered from HBM once by the whole workgroup, converted to tile-local coordinates and
+// staged in LDS, then every pixel reads the records as LDS broadcasts. A pixel applies the exact
+// per-pixel cutoffs (Mahalanobis distance <= sigma_cut, alpha >= alpha_min, stop before T drops
+// below T_min); the workgroup leaves the list as soon as a barrier count shows every pixel done.
+//
+// The backward walks the same list in reverse from the last blended position of the tile,
+// recovering T_i = T_{i+1}/(1 - alpha_i). Each pair yields 10 gradient terms; they are summed
+// over the wave with DPP row operations, over the workgroup's waves with LDS float atomics, and
+// reach HBM as one FP32 atomic per (tile, gaussian, term).
+//
+// The forward and the backward evaluate the cutoff decisions with the same inline functions in
+// this translation unit, compiled without floating-point contraction, so both take identical
+// decisions for every pair.
+#include "fgs_internal.h"
+
+namespace fgs {
+
+namespace {
+
+struct Pair {
+    float dx, dy, Q;
+};
+
+__device__ __forceinline__ float quad_form(float ca, float cb, float cc, float dx, float dy)
+{
+    // Q = ca dx^2 + 2 cb dx dy + cc dy^2, fixed operation order
+    const float t0 = ca * dx * dx;
+    const float t1 = 2.0f * cb * dx * dy;
+    const float t2 = cc * dy * dy;
+    return (t0 + t1) + t2;
+}
+
+__device__ __forceinline__ void stage(const Rec &R, int x0, int y0, float4 &a, float4 &b, float4 &c)
+{
+    // projected mean in tile-local coordinates: integer part is exact, one rounding for the sum
+    const float mx = (float)(__float_as_int(R.r0.x) - x0) + R.r0.z;
+    const float my = (float)(__float_as_int(R.r0.y) - y0) + R.r0.w;
+    a = make_float4(mx, my, R.r1.x, R.r1.y);          // mean2 (local), conic a, conic b
+    b = make_float4(R.r1.z, R.r1.w, R.r2.w, 0.0f);    // conic c, opacity, depth
+    c = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.0f);    // rgb
+}
+
+// DPP: v + (v moved by ctrl) in the rows enabled by row_mask, v elsewhere.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false);
+    return v + __int_as_float(t);
+}
+
+// Sum over the 64 lanes; the total is valid in lanes 48..63.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror: every lane holds its row's sum
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
+             const uint2 *__restrict__ ranges, uint32_t *__restrict__ last_out, float *__restrict__ tfinal_out,
+             ImageK img)
+{
+    constexpr int NT = TW * TH;
+    __shared__ float4 sa[NT], sb[NT], sc[NT];
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int lx = tid % TW, ly = tid / TW;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inside = x < W && y < H;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const uint2 range = ranges[tile];
+    const float cut2 = rk.sigma_cut * rk.sigma_cut;
+
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
+    uint32_t last = 0;
+    int32_t ncon = 0;
+    bool done = !inside;
+
+    for (uint32_t b = range.x; b < range.y; b += NT) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t j = b + tid;
+        if (j < range.y) {
+            float4 a4, b4, c4;
+            stage(rec[vals[j]], x0, y0, a4, b4, c4);
+            sa[tid] = a4;
+            sb[tid] = b4;
+            sc[tid] = c4;
+        }
+        __syncthreads();
+        const int cnt = min((uint32_t)NT, range.y - b);
+        for (int k = 0; k < cnt; ++k) {
+            if (done) continue;
+            const float4 a4 = sa[k];
+            const float dx = px - a4.x, dy = py - a4.y;
+            const float4 b4 = sb[k];
+            const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
+            if (Q > cut2) continue;
+            const float G = __expf(-0.5f * Q);
+            const float alpha = fminf(rk.alpha_max, b4.y * G);
+            if (alpha < rk.alpha_min) continue;
+            const float Tn = T * (1.0f - alpha);
+            if (Tn < rk.T_min) {
+                done = true;
+                continue;
+            }
+            const float w = alpha * T;
+            const float4 c4 = sc[k];
+            C0 += w * c4.x;
+            C1 += w * c4.y;
+            C2 += w * c4.z;
+            D += w * b4.z;
+            A += w;
+            T = Tn;
+            ++ncon;
+            last = b + k - range.x + 1;
+        }
+    }
+    if (!inside) return;
+    const int64_t P = (int64_t)W * H;
+    const int64_t p = (int64_t)y * W + x;
+    img.rgb[p] = C0 + T * rk.bg[0];
+    img.rgb[P + p] = C1 + T * rk.bg[1];
+    img.rgb[2 * P + p] = C2 + T * rk.bg[2];
+    img.depth[p] = D + T * rk.bg_depth;
+    if (img.alpha) img.alpha[p] = A;
+    if (img.T_final) img.T_final[p] = T;
+    if (img.n_contrib) img.n_contrib[p] = ncon;
+    last_out[p] = last;
+    tfinal_out[p] = T;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
+             const uint2 *__restrict__ ranges, const uint32_t *__restrict__ last_in,
+             const float *__restrict__ tfinal_in, const float *__restrict__ drgb, const float *__restrict__ ddepth,
+             const float *__restrict__ dalpha, const float *__restrict__ ddepth_scale, float *__restrict__ grad2d,
+             int64_t n)
+{
+    constexpr int NT = TW * TH;
+    __shared__ float4 sa[NT], sb[NT], sc[NT];
+    __shared__ uint32_t srank[NT];
+    __shared__ float sacc[10][NT];
+    __shared__ uint32_t smax;
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int tile = blockIdx.x;
+    const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
+    const int x0 = tx * TW, y0 = ty * TH;
+    const int lx = tid % TW, ly = tid / TW;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inside = x < W && y < H;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const uint2 range = ranges[tile];
+    const float cut2 = rk.sigma_cut * rk.sigma_cut;
+    const int64_t P = (int64_t)W * H;
+    const int64_t p = (int64_t)y * W + x;
+
+    uint32_t L = 0;
+    float T = 1.0f, gC0 = 0, gC1 = 0, gC2 = 0, gD = 0, gA = 0;
+    if (inside) {
+        L = last_in[p];
+        T = tfinal_in[p];
+        gC0 = drgb[p];
+        gC1 = drgb[P + p];
+        gC2 = drgb[2 * P + p];
+        gD = ddepth[p] * (ddepth_scale ? *ddepth_scale : 1.0f);
+        gA = dalpha ? dalpha[p] : 0.0f;
+    }
+    const float Tf = T;
+    float BC0 = Tf * rk.bg[0], BC1 = Tf * rk.bg[1], BC2 = Tf * rk.bg[2], BD = Tf * rk.bg_depth;
+
+    if (tid == 0) smax = 0;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) sacc[c][tid] = 0.0f;
+    __syncthreads();
+    if (L) atomicMax(&smax, L);
+    __syncthreads();
+    const uint32_t hi = min(range.x + smax, range.y);
+
+    for (uint32_t bend = hi; bend > range.x; bend -= min((uint32_t)NT, bend - range.x)) {
+        const uint32_t bstart = bend - min((uint32_t)NT, bend - range.x);
+        const int cnt = (int)(bend - bstart);
+        __syncthreads();
+        if (tid < cnt) {
+            const uint32_t r = vals[bstart + tid];
+            float4 a4, b4, c4;
+            stage(rec[r], x0, y0, a4, b4, c4);
+            sa[tid] = a4;
+            sb[tid] = b4;
+            sc[tid] = c4;
+            srank[tid] = r;
+        }
+        __syncthreads();
+        for (int k = cnt - 1; k >= 0; --k) {
+            const uint32_t pos = bstart + k - range.x;  // list position of entry k
+            float g[10];
+            bool contrib = false;
+            if (pos < L) {
+                const float4 a4 = sa[k];
+                const float dx = px - a4.x, dy = py - a4.y;
+                const float4 b4 = sb[k];
+                const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
+                if (!(Q > cut2)) {
+                    const float G = __expf(-0.5f * Q);
+                    const float ar = b4.y * G;
+                    const float alpha = fminf(rk.alpha_max, ar);
+                    if (!(alpha < rk.alpha_min)) {
+                        contrib = true;
+                        const float4 c4 = sc[k];
+                        const float inv = 1.0f / (1.0f - alpha);
+                        const float Ti = T * inv;
+                        const float w = alpha * Ti;
+                        const float dal = Ti * (gC0 * c4.x + gC1 * c4.y + gC2 * c4.z + gD * b4.z) -
+                                          (gC0 * BC0 + gC1 * BC1 + gC2 * BC2 + gD * BD - gA * Tf) * inv;
+                        g[6] = gC0 * w;
+                        g[7] = gC1 * w;
+                        g[8] = gC2 * w;
+                        g[9] = gD * w;
+                        if (ar > rk.alpha_max) {
+                            g[0] = g[1] = g[2] = g[3] = g[4] = g[5] = 0.0f;
+                        } else {
+                            g[5] = dal * G;
+                            const float dQ = -0.5f * alpha * dal;
+                            g[0] = -2.0f * dQ * (a4.z * dx + a4.w * dy);
+                            g[1] = -2.0f * dQ * (a4.w * dx + b4.x * dy);
+                            g[2] = dQ * dx * dx;
+                            g[3] = 2.0f * dQ * dx * dy;
+                            g[4] = dQ * dy * dy;
+                        }
+                        BC0 += w * c4.x;
+                        BC1 += w * c4.y;
+                        BC2 += w * c4.z;
+                        BD += w * b4.z;
+                        T = Ti;
+                    }
+                }
+            }
+            if (!contrib) {
+#pragma unroll
+                for (int c = 0; c < 10; ++c) g[c] = 0.0f;
+            }
+            const uint64_t any = __ballot(contrib);
+            if (any) {
+                if ((any & (any - 1)) == 0) {
+                    // a single contributing lane: no reduction needed
+                    if (contrib) {
+#pragma unroll
+                        for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) g[c] = wave_sum(g[c]);
+                    if (lane == kWave - 1) {
+#pragma unroll
+                        for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            const uint32_t r = srank[tid];
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                const float v = sacc[c][tid];
+                if (v != 0.0f) {
+                    unsafeAtomicAdd(&grad2d[c * n + r], v);
+                    sacc[c][tid] = 0.0f;
+                }
+            }
+        }
+    }
+}
+
+template <int TW, int TH>
+void fwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint2 *ranges,
+           uint32_t *last, float *tfinal, const ImageK &img, hipStream_t s)
+{
+    const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
+    hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ranges, last,
+                       tfinal, img);
+}
+
+template <int TW, int TH>
+void bwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint2 *ranges,
+           const uint32_t *last, const float *tfinal, const float *drgb, const float *ddepth, const float *dalpha,
+           const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s)
+{
+    const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ranges, last,
+                       tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n);
+}
+
+}  // namespace
+
+#define FGS_TILE_SWITCH(CALL)                                          \
+    if (rk.tile_w == 16 && rk.tile_h == 16) CALL(16, 16);              \
+    else if (rk.tile_w == 32 && rk.tile_h == 8) CALL(32, 8);           \
+    else if (rk.tile_w == 8 && rk.tile_h == 32) CALL(8, 32);           \
+    else if (rk.tile_w == 32 && rk.tile_h == 16) CALL(32, 16);         \
+    else if (rk.tile_w == 16 && rk.tile_h == 32) CALL(16, 32);         \
+    else if (rk.tile_w == 8 && rk.tile_h == 8) CALL(8, 8);
+
+bool tile_supported(int tw, int th)
+{
+    return (tw == 16 && th == 16) || (tw == 32 && th == 8) || (tw == 8 && th == 32) || (tw == 32 && th == 16) ||
+           (tw == 16 && th == 32) || (tw == 8 && th == 8);
+}
+
+void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
+                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img, hipStream_t s)
+{
+#define FGS_CALL_FWD(a, b) fwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, img, s)
+    FGS_TILE_SWITCH(FGS_CALL_FWD)
+#undef FGS_CALL_FWD
+}
+
+void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
+                       const uint2 *ranges, const uint32_t *last, const float *tfinal, const float *drgb,
+                       const float *ddepth, const float *dalpha, const float *ddepth_scale, float *grad2d, int64_t n,
+                       hipStream_t s)
+{
+#define FGS_CALL_BWD(a, b) \
+    bwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n, s)
+    FGS_TILE_SWITCH(FGS_CALL_BWD)
+#undef FGS_CALL_BWD
+}
+
+}  // namespace fgs

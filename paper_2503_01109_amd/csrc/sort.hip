@@ -1,0 +1,341 @@
+// Binning of projected gaussians into screen tiles and the (tile, depth) ordering of every
+// tile's list.
+//
+// Ordering scheme: the n gaussians are first sorted by depth (32-bit keys, the bits of the
+// positive FP32 depth; ids emitted in ascending order and a stable sort, so equal depths keep
+// ascending index). Every gaussian then emits one (tile, depth rank) pair per covered tile, in
+// depth order. A stable sort of the pairs by tile alone leaves each tile's list ordered by
+// (depth, index) - the pairs never need a depth key of their own.
+//
+// The radix sort is an LSD sort with 8-bit digits and a fixed grid: block b handles the b-th
+// contiguous chunk of the input, whose length is read from device memory, so no host round
+// trip is needed between passes. Per pass: a per-block digit histogram (LDS atomics), a
+// per-digit scan over blocks, and a stable scatter that ranks equal digits inside a wave with
+// ballots and across the block's waves with LDS counters.
+#include "fgs_internal.h"
+
+namespace fgs {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kScanItems = 4;  // elements per thread in the count scan
+constexpr int kScanBlock = kSortThreads * kScanItems;
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// Block-wide exclusive scan of one u32 per thread (256 threads). Returns the prefix; *total
+// receives the block sum. Uses 8 words of LDS passed in.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t *total)
+{
+    const int lane = __lane_id(), wid = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) lds_w[wid] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+        const uint32_t s = lds_w[w];
+        off += w < wid ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__device__ inline void chunk_of(uint32_t n, int G, int b, uint32_t &lo, uint32_t &hi)
+{
+    uint32_t chunk = (n + G - 1) / G;
+    chunk = (chunk + kSortThreads - 1) / kSortThreads * kSortThreads;
+    lo = min((uint64_t)n, (uint64_t)chunk * b);
+    hi = min((uint64_t)n, (uint64_t)chunk * (b + 1));
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint32_t n_cap, int shift,
+             uint32_t mask, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = min(*n_dev, n_cap);
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kSortThreads) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of the digit's row over blocks, row total to totals.
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t w[8];
+    uint32_t *row = hist + (size_t)blockIdx.x * G;
+    uint32_t carry = 0;
+    for (int base = 0; base < G; base += kSortThreads) {
+        const int j = base + threadIdx.x;
+        const uint32_t v = j < G ? row[j] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, w, &tot);
+        if (j < G) row[j] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, uint32_t n_cap, int shift,
+                uint32_t mask, int bits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kSortThreads / kWave][256];
+    __shared__ uint32_t w8[8];
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    {
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(totals[tid], w8, &tot);
+        base[tid] = ex + hist[(size_t)tid * gridDim.x + blockIdx.x];
+    }
+    const uint32_t n = min(*n_dev, n_cap);
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
+    for (uint32_t it = lo; it < hi; it += kSortThreads) {
+#pragma unroll
+        for (int w = 0; w < kSortThreads / kWave; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        const uint32_t i = it + tid;
+        const bool valid = i < hi;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t d = (key >> shift) & mask;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d] + rank;
+            for (int w = 0; w < wid; ++w) off += wcnt[w][d];
+            kout[off] = key;
+            vout[off] = vin[i];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kSortThreads / kWave; ++w) add += wcnt[w][tid];
+        base[tid] += add;
+        // the next iteration's clear happens after this barrier-free update: every thread only
+        // touches its own digit column here, and the clear above is followed by a barrier.
+        __syncthreads();
+    }
+}
+
+// Per block: sum of count[ids[r]] over the block's kScanBlock ranks.
+__global__ void __launch_bounds__(kSortThreads)
+k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, int64_t n,
+               uint32_t *__restrict__ blocksums)
+{
+    __shared__ uint32_t w[8];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += count[ids[base + k]];
+    uint32_t tot;
+    block_excl_scan(s, w, &tot);
+    if (threadIdx.x == 0) blocksums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the block sums in place; the total number of pairs goes to
+// blocksums[nb] and to the status words.
+__global__ void __launch_bounds__(kSortThreads)
+k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status)
+{
+    __shared__ uint32_t w[8];
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kSortThreads) {
+        const int j = base + threadIdx.x;
+        const uint32_t v = j < nb ? blocksums[j] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, w, &tot);
+        if (j < nb) blocksums[j] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        blocksums[nb] = carry;
+        status[ST_PAIRS] = carry;
+        status[ST_VISIBLE] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_emit(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
+       const Rec *__restrict__ rec_by_id, const uint32_t *__restrict__ blocksums, int64_t n, int32_t tiles_x,
+       int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, Rec *__restrict__ rec_sorted,
+       uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, const uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t w[8];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint32_t c[kScanItems], id[kScanItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t r = base + k;
+        id[k] = r < n ? ids[r] : 0u;
+        c[k] = r < n ? count[id[k]] : 0u;
+        s += c[k];
+    }
+    uint32_t tot;
+    uint32_t off = blocksums[blockIdx.x] + block_excl_scan(s, w, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t r = base + k;
+        if (r >= n) break;
+        if (c[k]) {
+            rec_sorted[r] = rec_by_id[id[k]];
+            const uint2 rc = rect[id[k]];
+            const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+            if ((int64_t)off + c[k] <= cap) {
+                uint32_t o = off;
+                for (uint32_t ty = ty0; ty <= ty1; ++ty)
+                    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+                        keys[o] = ty * (uint32_t)tiles_x + tx;
+                        vals[o] = (uint32_t)r;
+                        ++o;
+                    }
+            }
+        }
+        off += c[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t K = *total;
+        // On overflow nothing is sorted or rendered (the pairs that were written are not a
+        // complete set); the condition is recorded and reported by the next status check.
+        *n_pairs_dev = (int64_t)K <= cap ? K : 0u;
+        if ((int64_t)K > cap) atomicMax(&status[ST_OVERFLOW], K);
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_visible(const uint32_t *__restrict__ count, int64_t n, uint32_t *__restrict__ status)
+{
+    __shared__ uint32_t w[8];
+    uint32_t s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortThreads)
+        s += count[i] != 0;
+    uint32_t tot;
+    block_excl_scan(s, w, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(&status[ST_VISIBLE], tot);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges)
+{
+    const uint32_t K = *n_dev;
+    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < K; i += gridDim.x * kSortThreads) {
+        const uint32_t t = keys[i];
+        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+        if (i + 1 == K || keys[i + 1] != t) ranges[t].y = i + 1;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace
+
+int sort_blocks(int64_t cap)
+{
+    int64_t G = (cap + 2047) / 2048;
+    if (G < 1) G = 1;
+    if (G > 4096) G = 4096;
+    return (int)G;
+}
+
+static unsigned grid_for(int64_t n, int per_block, unsigned max_blocks)
+{
+    int64_t b = (n + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (unsigned)b;
+}
+
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 1024, 2048)), dim3(256), 0, s, p, n);
+}
+
+void launch_zero_f32(float *p, int64_t n, hipStream_t s) { launch_zero_u32((uint32_t *)p, n, s); }
+
+uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t *v_final,
+                            const uint32_t *n_dev, int64_t n_cap, int key_bits, const SortWS &ws, hipStream_t s)
+{
+    // Pass p reads (src) and writes (dst); src/dst alternate between the a and b buffers. The last
+    // pass writes its values to v_final (which must not alias va or vb) and its keys to its usual
+    // destination, which is returned.
+    const int passes = key_bits <= 0 ? 1 : (key_bits + 7) / 8;
+    uint32_t *sk = ka, *sv = va, *dk = kb, *dv = vb;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const int bits = key_bits - shift < 8 ? (key_bits - shift > 0 ? key_bits - shift : 1) : 8;
+        const uint32_t mask = (1u << bits) - 1u;
+        uint32_t *ok = dk, *ov = p == passes - 1 ? v_final : dv;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ws.G), dim3(kSortThreads), 0, s, sk, n_dev, (uint32_t)n_cap, shift,
+                           mask, ws.hist);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, s, ws.hist, ws.G, ws.totals);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ws.G), dim3(kSortThreads), 0, s, sk, sv, ok, ov, n_dev,
+                           (uint32_t)n_cap, shift, mask, bits, ws.hist, ws.totals);
+        if (p == passes - 1) return ok;
+        sk = dk; sv = dv;
+        dk = (dk == kb) ? ka : kb;
+        dv = (dv == vb) ? va : vb;
+    }
+    return nullptr;
+}
+
+int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
+                        uint32_t *status, hipStream_t s)
+{
+    const int nb = (int)scan_blocks(n);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status);
+    hipLaunchKernelGGL(k_visible, dim3(grid_for(n, 4096, 256)), dim3(kSortThreads), 0, s, count, n, status);
+}
+
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
+                 const uint32_t *blocksums, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
+                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev, hipStream_t s)
+{
+    // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
+    const int nb = (int)scan_blocks(n);
+    hipLaunchKernelGGL(k_emit, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, rec_by_id,
+                       blocksums, n, tiles_x, cap, keys, vals, rec_sorted, status, n_pairs_dev, blocksums + nb);
+}
+
+void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,
+                   hipStream_t s)
+{
+    launch_zero_u32((uint32_t *)ranges, 2 * T, s);
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 4096, 2048)), dim3(kSortThreads), 0, s, keys, n_pairs_dev,
+                       ranges);
+}
+
+}  // namespace fgs

@@ -1,0 +1,141 @@
+"""Host-side tests of the C ABI (no GPU needed): exported symbols, struct layouts, argument checks."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2503_01109_amd as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names.update(re.findall(r"\b(fgs_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(F.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (fgs_\w+)", out))
+    assert set(names) <= exported
+    assert set(F.EXPORTED) <= exported
+
+
+LAYOUT_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "fgs.h"
+#define S(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  S(fgs_camera) O(fgs_camera, R_cw) O(fgs_camera, z_near)
+  S(fgs_gaussians) O(fgs_gaussians, rgb)
+  S(fgs_render_opts) O(fgs_render_opts, bg) O(fgs_render_opts, tile_h)
+  S(fgs_image) S(fgs_adam) O(fgs_adam, step) O(fgs_adam, lr) O(fgs_adam, eps)
+  S(fgs_target) S(fgs_loss_opts)
+  %EXTRA%
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    extra = ""
+    if hasattr(F, "CSeedOpts"):
+        extra = "S(fgs_seed_opts) O(fgs_seed_opts, use_prior) S(fgs_seed_out) O(fgs_seed_out, tile_count)"
+    src = tmp_path / "probe.c"
+    src.write_text(LAYOUT_PROBE.replace("%EXTRA%", extra))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                             check=True).stdout.splitlines())
+    mine = {
+        "fgs_camera": C.sizeof(F.CCamera), "fgs_camera.R_cw": F.CCamera.R_cw.offset,
+        "fgs_camera.z_near": F.CCamera.z_near.offset,
+        "fgs_gaussians": C.sizeof(F.CGaussians), "fgs_gaussians.rgb": F.CGaussians.rgb.offset,
+        "fgs_render_opts": C.sizeof(F.CRenderOpts), "fgs_render_opts.bg": F.CRenderOpts.bg.offset,
+        "fgs_render_opts.tile_h": F.CRenderOpts.tile_h.offset,
+        "fgs_image": C.sizeof(F.CImage), "fgs_adam": C.sizeof(F.CAdam), "fgs_adam.step": F.CAdam.step.offset,
+        "fgs_adam.lr": F.CAdam.lr.offset, "fgs_adam.eps": F.CAdam.eps.offset,
+        "fgs_target": C.sizeof(F.CTarget), "fgs_loss_opts": C.sizeof(F.CLossOpts),
+    }
+    if extra:
+        mine.update({"fgs_seed_opts": C.sizeof(F.CSeedOpts), "fgs_seed_opts.use_prior": F.CSeedOpts.use_prior.offset,
+                     "fgs_seed_out": C.sizeof(F.CSeedOut), "fgs_seed_out.tile_count": F.CSeedOut.tile_count.offset})
+    for k, v in mine.items():
+        assert int(got[k]) == v, f"{k}: header {got[k]} vs binding {v}"
+
+
+def test_state_bytes_layout_and_errors():
+    o = F.RenderOpts()
+    b0 = F.state_bytes(100, 64, 48, 0, o)
+    b1 = F.state_bytes(100, 64, 48, 1000, o)
+    assert b1 - b0 == 4000
+    assert b0 >= 100 * 48 + 100 * 4 + 12 * 8 + 64 * 48 * 8
+    with pytest.raises(F.FgsError) as e:
+        F.state_bytes(100, 0, 48, 10, o)
+    assert e.value.status == F.ERR_INVALID_ARG
+    with pytest.raises(F.FgsError) as e:
+        F.state_bytes(100, 64, 48, 10, F.RenderOpts(tile_w=12, tile_h=12))
+    assert "unsupported tile" in str(e.value)
+    with pytest.raises(F.FgsError):
+        F.state_bytes(100, 64, 48, 10, F.RenderOpts(alpha_max=1.5))
+
+
+def _cam(**kw):
+    import synth
+    c = synth.camera_small()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _call_fwd(n=10, cam=None, opts=None, state_bytes=1 << 20, null_rgb=False, stride=None):
+    g = F.CGaussians()
+    g.n, g.stride = n, n if stride is None else stride
+    dummy = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    g.mean = g.log_scale = g.quat = g.opacity_logit = g.rgb = dummy
+    img = F.CImage(None if null_rgb else dummy, dummy, None, None, None)
+    cc = F.camera(cam or _cam())
+    st = F._lib.fgs_render_fwd(None, C.byref(g), C.byref(cc), C.byref((opts or F.RenderOpts()).c()), C.byref(img),
+                               C.c_void_p(0x2000), state_bytes)
+    return st, F.last_error()
+
+
+def test_render_fwd_rejects_bad_arguments_on_host():
+    assert _call_fwd() == (F.ERR_INVALID_ARG, "fgs_render_fwd: ctx is NULL")
+    st, msg = _call_fwd(n=-1)
+    assert st == F.ERR_INVALID_ARG and "g.n" in msg
+    st, msg = _call_fwd(stride=5)
+    assert st == F.ERR_INVALID_ARG and "stride" in msg
+    st, msg = _call_fwd(cam=_cam(fx=-1.0))
+    assert st == F.ERR_INVALID_ARG and "focal" in msg
+    st, msg = _call_fwd(cam=_cam(width=0))
+    assert st == F.ERR_INVALID_ARG and "image size" in msg
+    st, msg = _call_fwd(opts=F.RenderOpts(sigma_cut=0.0))
+    assert st == F.ERR_INVALID_ARG and "sigma_cut" in msg
+    st, msg = _call_fwd(null_rgb=True)
+    assert st == F.ERR_INVALID_ARG and "image" in msg
+    st, msg = _call_fwd(state_bytes=100)
+    assert st == F.ERR_CAPACITY and "fixed part" in msg
+    import numpy as np
+    st, msg = _call_fwd(cam=_cam(t=np.array([np.nan, 0, 0], np.float32)))
+    assert st == F.ERR_INVALID_ARG and "t_cw" in msg
+
+
+def test_status_strings():
+    for s in (F.OK, F.ERR_INVALID_ARG, F.ERR_CAPACITY, F.ERR_HIP, F.ERR_UNSUPPORTED):
+        assert F._lib.fgs_status_str(s)

@@ -1,0 +1,186 @@
+"""GPU parity: render_fwd / render_bwd through the C ABI against the FP64 oracle.
+
+Tolerances: 1e-5 relative for rendered planes, 1e-4 relative for gradients (FP32 path vs FP64
+oracle), the per-tensor/elementwise metric of gpu_helpers.assert_close_rel. Pixels the oracle
+flags as ambiguous (a cutoff decision within 1e-5 relative, or a depth tie) are excluded from the
+forward comparison and get a zero upstream gradient in the backward comparison.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import assert_close_rel, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL, GRAD_TOL, GRAD_FLOOR = 1e-5, 1e-4, 1e-2
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    need_gpu()
+    import paper_2503_01109_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fgs):
+    c = fgs.Context()
+    yield c
+    c.close()
+
+
+def oracle_opts(o):
+    return oracle.RenderOpts(o.sigma_cut, o.alpha_min, o.alpha_max, o.T_min, o.lowpass, o.bg, o.bg_depth)
+
+
+def params_dev(p, cap=None):
+    n = p.shape[1]
+    cap = cap or n
+    block = np.zeros((14, cap), np.float32)
+    block[:, :n] = p
+    return dev(block)
+
+
+def check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.0):
+    pd = params_dev(p)
+    out = fgs.render(ctx, pd, p.shape[1], cam, opts)
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(opts), mode=0, amb_rel=1e-5)
+    ok = ~ref["amb"]
+    assert ref["n_amb"] <= max_amb_frac * cam.width * cam.height, f"{ref['n_amb']} ambiguous pixels"
+    assert_close_rel(host(out["rgb"]), ref["rgb"], FWD_TOL, ok, "rgb")
+    assert_close_rel(host(out["depth"]), ref["depth"], FWD_TOL, ok, "depth")
+    assert_close_rel(host(out["alpha"]), ref["alpha"], FWD_TOL, ok, "alpha")
+    assert_close_rel(host(out["T_final"]), ref["T_final"], FWD_TOL, ok, "T_final")
+    np.testing.assert_array_equal(host(out["n_contrib"])[ok], ref["n_contrib"][ok])
+    return out, ref
+
+
+def check_backward(fgs, ctx, p, cam, opts, out, ref, seed=0, with_alpha=True):
+    P = cam.width * cam.height
+    g = synth.rng(1000 + seed)
+    gr = g.normal(size=(3, P)).astype(np.float32)
+    gd = g.normal(size=P).astype(np.float32)
+    ga = g.normal(size=P).astype(np.float32) if with_alpha else None
+    amb = ref["amb"].ravel()
+    gr[:, amb] = 0
+    gd[amb] = 0
+    if ga is not None:
+        ga[amb] = 0
+    n = p.shape[1]
+    pd = params_dev(p)
+    grad = dev(np.zeros((14, n), np.float32))
+    fgs.render_bwd(ctx, pd, n, cam, opts, out["state"], dev(gr), dev(gd), None if ga is None else dev(ga), grad)
+    ctx.check()
+    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, ga, oracle_opts(opts), mode=0)
+    gg = host(grad)
+    for name, rows in (("mean", slice(0, 3)), ("log_scale", slice(3, 6)), ("quat", slice(6, 10)),
+                       ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+        assert_close_rel(gg[rows], gref[rows], GRAD_TOL, None, f"d{name}", floor=GRAD_FLOOR)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_scene_forward_backward(fgs, ctx, seed):
+    """2,000 gaussians, 64x48, fx = fy = 60: forward planes and all 14 parameter gradients."""
+    p = synth.scene_small(seed)
+    cam = synth.camera_small()
+    opts = fgs.RenderOpts()
+    out, ref = check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.01)
+    check_backward(fgs, ctx, p, cam, opts, out, ref, seed)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (8, 8)])
+def test_tile_shape_independence(fgs, ctx, tile):
+    """P6: every rasterizer tile shape gives the oracle's image (ragged 70x50 frame)."""
+    cam = synth.centred_camera(70, 50, 60.0)
+    p = synth.frustum_scene(7, 1500, cam, 1.0, 5.0)
+    opts = fgs.RenderOpts(tile_w=tile[0], tile_h=tile[1])
+    out, ref = check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.01)
+    check_backward(fgs, ctx, p, cam, opts, out, ref, seed=3)
+
+
+def test_background_lowpass_and_pose(fgs, ctx):
+    """Non-zero background, no low-pass filter, a rotated and translated camera."""
+    import test_oracle_render as tor
+    cam0 = synth.centred_camera(48, 40, 50.0)
+    R = tor.rot_of(np.array([0.95, 0.1, -0.2, 0.15]))
+    t = np.array([0.05, -0.02, 0.1])
+    cam = synth.Camera(48, 40, 50.0, 52.0, 24.0, 20.0, R=R, t=t)
+    p = synth.frustum_scene(11, 800, cam0, 1.0, 4.0).astype(np.float64)
+    p[0:3] = R.T.astype(np.float32).astype(np.float64) @ (p[0:3] - t[:, None])
+    p = p.astype(np.float32)
+    opts = fgs.RenderOpts(lowpass=0.0, bg=(0.2, 0.4, 0.6), bg_depth=3.0)
+    out, ref = check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.01)
+    check_backward(fgs, ctx, p, cam, opts, out, ref, seed=5)
+
+
+def test_termination_stack(fgs, ctx):
+    """P3 on the GPU: 20 stacked alpha = 0.5 gaussians at the centre pixel blend exactly 13."""
+    cam = synth.Camera(16, 16, 40.0, 40.0, 8.5, 8.5)
+    n = 20
+    p = np.zeros((14, n), np.float32)
+    p[2] = 1.0 + 0.1 * np.arange(n)
+    p[3:6] = np.log(0.05)
+    p[6] = 1.0
+    p[11:14] = synth.rng(0).uniform(size=(3, n))
+    out = fgs.render(ctx, params_dev(p), n, cam, fgs.RenderOpts())
+    assert host(out["n_contrib"])[8, 8] == 13
+    assert host(out["T_final"])[8, 8] == np.float32(2.0 ** -13)
+
+
+def test_empty_and_culled(fgs, ctx):
+    """n = 0 and an all-culled scene render the background."""
+    cam = synth.camera_small()
+    opts = fgs.RenderOpts(bg=(0.1, 0.2, 0.3), bg_depth=2.0)
+    for n in (0, 5):
+        p = np.zeros((14, max(n, 1)), np.float32)
+        p[2] = -1.0  # behind the camera
+        p[6] = 1.0
+        out = fgs.render(ctx, params_dev(p), n, cam, opts)
+        rgb = host(out["rgb"])
+        for c in range(3):
+            assert np.all(rgb[c] == np.float32(opts.bg[c]))
+        assert np.all(host(out["depth"]) == 2.0)
+        assert np.all(host(out["T_final"]) == 1.0)
+        assert np.all(host(out["n_contrib"]) == 0)
+
+
+def test_invariant_weights_sum_to_one(fgs, ctx):
+    """P4 on the GPU: alpha + T_final = 1 within FP32 rounding, at every pixel."""
+    p = synth.scene_small(4)
+    cam = synth.camera_small()
+    out = fgs.render(ctx, params_dev(p), p.shape[1], cam, fgs.RenderOpts())
+    s = host(out["alpha"]).astype(np.float64) + host(out["T_final"])
+    assert np.abs(s - 1).max() < 1e-6
+
+
+def test_capacity_overflow_is_reported(fgs, ctx):
+    p = synth.scene_small(0)
+    cam = synth.camera_small()
+    opts = fgs.RenderOpts()
+    pd = params_dev(p)
+    n = p.shape[1]
+    import torch
+    nb = fgs.state_bytes(n, cam.width, cam.height, 16, opts)
+    state = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    rgb = torch.empty((3, cam.height, cam.width), device="cuda")
+    depth = torch.empty((cam.height, cam.width), device="cuda")
+    fgs.render_fwd(ctx, pd, n, cam, opts, rgb, depth, state)
+    with pytest.raises(fgs.FgsError) as e:
+        ctx.check()
+    assert e.value.status == fgs.ERR_CAPACITY
+    K = oracle.count_duplicates(p.astype(np.float64), cam, 16, 16)
+    need = fgs.ctx_required_pairs(e.value)
+    assert K <= need <= K + K // 50 + 16  # GPU machines are padded by 1e-5 relative + 1e-3 px
+    ctx.check()  # the condition is cleared once reported
+
+
+def test_deterministic_forward(fgs, ctx):
+    p = synth.scene_small(6)
+    cam = synth.camera_small()
+    pd = params_dev(p)
+    a = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    b = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    for k in ("rgb", "depth", "alpha", "T_final", "n_contrib"):
+        assert np.array_equal(host(a[k]), host(b[k]))
