@@ -91,6 +91,9 @@ _sigs = {
                      _P(CLossOpts), _fp, _fp, _P(CGaussians)],
     "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
     "fgs_adam_step": [_vp, _P(CGaussians), _P(CGaussians), _P(CAdam)],
+    "fgs_ctx_profile": [_vp, C.c_int32],
+    "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
+    "fgs_ctx_profile_counts": [_vp, _P(C.c_int64)],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -205,6 +208,27 @@ class Context:
     def check(self):
         """Waits for the stream and raises FgsError(ERR_CAPACITY) on a recorded overflow."""
         _check(_lib.fgs_ctx_check(self._p), self._p)
+
+    STAGES = ("project", "depth_sort", "bin", "tile_sort", "raster_fwd", "loss", "raster_bwd", "project_bwd",
+              "adam")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier records) or stop per-stage HIP-event timing and work counters."""
+        _check(_lib.fgs_ctx_profile(self._p, int(enable)), self._p)
+
+    def profile_report(self) -> dict:
+        """{stage: (total_ms, launches)} plus 'counts': pairs examined, pairs blended, entries staged,
+        forward launches."""
+        rep = {}
+        for s in self.STAGES:
+            t = C.c_double()
+            k = C.c_int64()
+            _check(_lib.fgs_ctx_profile_stage(self._p, s.encode(), C.byref(t), C.byref(k)), self._p)
+            rep[s] = (t.value, k.value)
+        c = (C.c_int64 * 4)()
+        _check(_lib.fgs_ctx_profile_counts(self._p, c), self._p)
+        rep["counts"] = dict(pairs_examined=c[0], pairs_blended=c[1], entries_staged=c[2], forwards=c[3])
+        return rep
 
     def stats(self) -> dict:
         s = (C.c_int64 * 4)()

@@ -8,7 +8,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <string>
+#include <utility>
+#include <vector>
 
 namespace fgs {
 bool tile_supported(int tw, int th);
@@ -63,6 +66,11 @@ struct fgs_ctx {
     DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
     int64_t ms_cap = 0;
     uint32_t *host_words = nullptr;  // pinned copy of the status words
+    // profiling
+    bool prof = false;
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+    DBuf prof_counts;  // 4 x u64
+    int64_t prof_fwd = 0;
 };
 
 namespace {
@@ -237,6 +245,42 @@ StatePtrs state_ptrs(void *state, const StateLayout &L)
 
 uint32_t *status_words(fgs_ctx *ctx) { return ctx->words.as<uint32_t>() + W_STATUS; }
 
+// Records a pair of HIP events around the work enqueued during its lifetime (profiling only).
+struct Stage {
+    fgs_ctx *ctx;
+    hipEvent_t a = nullptr, b = nullptr;
+    Stage(fgs_ctx *c, const char *name) : ctx(c)
+    {
+        if (!ctx->prof) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            ctx->prof = false;
+            return;
+        }
+        (void)hipEventRecord(a, ctx->stream);
+        ctx->prof_events[name].push_back({a, b});
+    }
+    ~Stage()
+    {
+        if (a && b) (void)hipEventRecord(b, ctx->stream);
+    }
+};
+
+unsigned long long *prof_counts(fgs_ctx *ctx)
+{
+    return ctx->prof ? ctx->prof_counts.as<unsigned long long>() : nullptr;
+}
+
+void clear_profile(fgs_ctx *ctx)
+{
+    for (auto &kv : ctx->prof_events)
+        for (auto &ab : kv.second) {
+            (void)hipEventDestroy(ab.first);
+            (void)hipEventDestroy(ab.second);
+        }
+    ctx->prof_events.clear();
+    ctx->prof_fwd = 0;
+}
+
 fgs_status read_words(fgs_ctx *ctx);
 
 // Enqueue the forward pipeline into a state with layout L. With K_check, the call waits for the
@@ -256,25 +300,46 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     uint32_t *words = ctx->words.as<uint32_t>();
     uint32_t *ndev = words + W_NDEV, *npairs = words + W_NPAIRS;
 
-    launch_project(pk, ck, rk, ctx->rec_by_id.as<Rec>(), ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
-                   ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, s);
-    launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                      ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n), s);
-    launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx), s);
+    {
+        Stage st_(ctx, "project");
+        launch_project(pk, ck, rk, ctx->rec_by_id.as<Rec>(), ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
+                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, s);
+    }
+    {
+        Stage st_(ctx, "depth_sort");
+        launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
+                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n), s);
+    }
+    {
+        Stage st_(ctx, "bin");
+        launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx),
+                           s);
+    }
     if (K_check) {
         fgs_status st2 = read_words(ctx);
         if (st2 != FGS_OK) return st2;
         *K_check = ctx->host_words[ST_PAIRS];
         if (*K_check > L.cap) return FGS_ERR_CAPACITY;
     }
-    launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
-                ctx->blocksums.as<uint32_t>(), g.n, rk.tiles_x, L.cap, ctx->pkA.as<uint32_t>(),
-                ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs, s);
-    uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
-                                       ctx->pvB.as<uint32_t>(), sp.vals, npairs, L.cap, key_bits_for(L.T),
-                                       sort_ws(ctx, L.cap), s);
-    launch_ranges(keys, npairs, L.cap, sp.ranges, L.T, s);
-    launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img, s);
+    {
+        Stage st_(ctx, "bin");
+        launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
+                    ctx->blocksums.as<uint32_t>(), g.n, rk.tiles_x, L.cap, ctx->pkA.as<uint32_t>(),
+                    ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs, s);
+    }
+    {
+        Stage st_(ctx, "tile_sort");
+        uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
+                                           ctx->pkB.as<uint32_t>(), ctx->pvB.as<uint32_t>(), sp.vals, npairs, L.cap,
+                                           key_bits_for(L.T), sort_ws(ctx, L.cap), s);
+        launch_ranges(keys, npairs, L.cap, sp.ranges, L.T, s);
+    }
+    {
+        Stage st_(ctx, "raster_fwd");
+        launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img,
+                          prof_counts(ctx), s);
+        if (ctx->prof) ctx->prof_fwd++;
+    }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
@@ -291,9 +356,15 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     const StatePtrs sp = state_ptrs((void *)state, L);
     float *g2 = ctx->grad2d.as<float>();
     launch_zero_f32(g2, 10 * g.n, s);
-    launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb, ddepth, dalpha,
-                      dscale, g2, g.n, s);
-    launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), s);
+    {
+        Stage st_(ctx, "raster_bwd");
+        launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb, ddepth,
+                          dalpha, dscale, g2, g.n, s);
+    }
+    {
+        Stage st_(ctx, "project_bwd");
+        launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), s);
+    }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
@@ -391,7 +462,8 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
 {
     if (!ctx) return FGS_OK;
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
-    DBuf *bufs[] = {&ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
+    clear_profile(ctx);
+    DBuf *bufs[] = {&ctx->prof_counts, &ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials};
     for (DBuf *b : bufs) b->release();
@@ -446,6 +518,52 @@ fgs_status fgs_ctx_stats(fgs_ctx *ctx, int64_t stats[4])
     stats[1] = ctx->host_words[ST_VISIBLE];
     stats[2] = ctx->host_words[ST_OVERFLOW];
     stats[3] = ctx->host_words[ST_SEEDS];
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_profile: ctx is NULL");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    clear_profile(ctx);
+    ctx->prof = enable != 0;
+    if (ctx->prof) {
+        HIP_TRY(ctx, ctx->prof_counts.ensure(4 * 8));
+        HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 4 * 8));
+    }
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_profile_stage(fgs_ctx *ctx, const char *stage, double *total_ms, int64_t *launches)
+{
+    if (!ctx || !stage || !total_ms || !launches)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "fgs_ctx_profile_stage: NULL argument");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    double t = 0;
+    int64_t k = 0;
+    auto it = ctx->prof_events.find(stage);
+    if (it != ctx->prof_events.end())
+        for (auto &ab : it->second) {
+            float ms = 0;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ab.first, ab.second));
+            t += ms;
+            ++k;
+        }
+    *total_ms = t;
+    *launches = k;
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4])
+{
+    if (!ctx || !counts) return fail(ctx, FGS_ERR_INVALID_ARG, "fgs_ctx_profile_counts: NULL argument");
+    unsigned long long c[4] = {0, 0, 0, 0};
+    if (ctx->prof_counts.p) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpy(c, ctx->prof_counts.p, sizeof(c), hipMemcpyDeviceToHost));
+    }
+    for (int k = 0; k < 3; ++k) counts[k] = (int64_t)c[k];
+    counts[3] = ctx->prof_fwd;
     return FGS_OK;
 }
 
@@ -543,6 +661,7 @@ static fgs_status check_adam(fgs_ctx *ctx, const fgs_adam *opt, int64_t n, const
 
 static void enqueue_adam(fgs_ctx *ctx, const fgs_gaussians &p, const fgs_gaussians &grad, fgs_adam *opt)
 {
+    Stage st_(ctx, "adam");
     const double k = (double)(opt->step + 1);
     const float bc1 = (float)(1.0 - pow((double)opt->beta1, k));
     const float bc2 = (float)(1.0 - pow((double)opt->beta2, k));
@@ -634,9 +753,12 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         }
         float *im = ctx->ms_img.as<float>();
         float *dl = ctx->ms_dl.as<float>();
-        launch_loss_l1(P, im, im + 3 * P, targets[v].rgb, targets[v].depth, l->lambda_rgb, l->lambda_depth, dl,
-                       dl + 3 * P, dscale, ctx->ms_partials.as<float>(), loss_dev ? loss_dev + v : nullptr,
-                       psnr_dev ? psnr_dev + v : nullptr, s);
+        {
+            Stage st_(ctx, "loss");
+            launch_loss_l1(P, im, im + 3 * P, targets[v].rgb, targets[v].depth, l->lambda_rgb, l->lambda_depth, dl,
+                           dl + 3 * P, dscale, ctx->ms_partials.as<float>(), loss_dev ? loss_dev + v : nullptr,
+                           psnr_dev ? psnr_dev + v : nullptr, s);
+        }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
                                    grad)) != FGS_OK)
             return st;

@@ -122,9 +122,11 @@ struct ImageK {
     int32_t *n_contrib;
 };
 
+// counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel
+// stopped, [1] += pairs blended, [2] += list entries staged.
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
-                       hipStream_t s);
+                       unsigned long long *counts, hipStream_t s);
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
 // to a device float multiplying ddepth (the 1/P_v of the mean depth term).

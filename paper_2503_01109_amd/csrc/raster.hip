@@ -69,7 +69,7 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH)
 k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
              const uint2 *__restrict__ ranges, uint32_t *__restrict__ last_out, float *__restrict__ tfinal_out,
-             ImageK img)
+             ImageK img, unsigned long long *__restrict__ counts)
 {
     constexpr int NT = TW * TH;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
@@ -85,12 +85,13 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
-    uint32_t last = 0;
+    uint32_t last = 0, ntest = 0, staged = 0;
     int32_t ncon = 0;
     bool done = !inside;
 
     for (uint32_t b = range.x; b < range.y; b += NT) {
         if (__syncthreads_count(!done) == 0) break;
+        staged += min((uint32_t)NT, range.y - b);
         const uint32_t j = b + tid;
         if (j < range.y) {
             float4 a4, b4, c4;
@@ -108,6 +109,7 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             const float4 b4 = sb[k];
             const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
             if (Q > cut2) continue;
+            ++ntest;
             const float G = __expf(-0.5f * Q);
             const float alpha = fminf(rk.alpha_max, b4.y * G);
             if (alpha < rk.alpha_min) continue;
@@ -126,6 +128,22 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             T = Tn;
             ++ncon;
             last = b + k - range.x + 1;
+        }
+    }
+    if (counts) {
+        // work counters (profiling only): block sums, one atomic per block and counter
+        __shared__ unsigned long long red[2];
+        if (tid == 0) red[0] = red[1] = 0ull;
+        __syncthreads();
+        if (inside) {
+            atomicAdd(&red[0], (unsigned long long)ntest);
+            atomicAdd(&red[1], (unsigned long long)ncon);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd(&counts[0], red[0]);
+            atomicAdd(&counts[1], red[1]);
+            atomicAdd(&counts[2], (unsigned long long)staged);
         }
     }
     if (!inside) return;
@@ -288,11 +306,11 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
 
 template <int TW, int TH>
 void fwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint2 *ranges,
-           uint32_t *last, float *tfinal, const ImageK &img, hipStream_t s)
+           uint32_t *last, float *tfinal, const ImageK &img, unsigned long long *counts, hipStream_t s)
 {
     const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
     hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ranges, last,
-                       tfinal, img);
+                       tfinal, img, counts);
 }
 
 template <int TW, int TH>
@@ -322,9 +340,10 @@ bool tile_supported(int tw, int th)
 }
 
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img, hipStream_t s)
+                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
+                       unsigned long long *counts, hipStream_t s)
 {
-#define FGS_CALL_FWD(a, b) fwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, img, s)
+#define FGS_CALL_FWD(a, b) fwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, img, counts, s)
     FGS_TILE_SWITCH(FGS_CALL_FWD)
 #undef FGS_CALL_FWD
 }
