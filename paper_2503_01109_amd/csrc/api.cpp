@@ -59,16 +59,20 @@ struct fgs_ctx {
     int device = 0;
     std::string err;
     // workspace of one forward (sized for the largest n / pair capacity seen)
-    DBuf rec_by_id, rect, count, dkA, dkB, idA, idB, blocksums, pkA, pkB, pvA, pvB, hist, grad2d;
+    DBuf rec_by_id, rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
     DBuf words;  // status words (ST_WORDS) + small device scalars
     int64_t ws_n = -1, ws_cap = -1;
     // mapping-step buffers
     DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
     int64_t ms_cap = 0;
     uint32_t *host_words = nullptr;  // pinned copy of the status words
+    // host-mapped per-view pair counts of mapping steps: [2v] = pairs, [2v+1] = overflow flag
+    uint32_t *ms_host = nullptr, *ms_host_dev = nullptr;
+    std::vector<bool> ms_seen;
     // profiling
     bool prof = false;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+    std::vector<hipEvent_t> event_pool;  // reused by Stage
     DBuf prof_counts;  // 4 x u64
     int64_t prof_fwd = 0;
 };
@@ -208,13 +212,18 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->idA.ensure(N * 4));
     HIP_TRY(ctx, ctx->idB.ensure(N * 4));
     HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks(nn) + 2) * 4));
+    HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
     HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvB.ensure(C * 4));
     const int64_t G = sort_blocks(cc > nn ? cc : nn);
     HIP_TRY(ctx, ctx->hist.ensure(((size_t)G * 256 + 256) * 4));
-    HIP_TRY(ctx, ctx->grad2d.ensure(N * 10 * 4));
+    if (nn > ctx->ws_n) {
+        // the backward keeps grad2d all-zero between calls (project_bwd clears what it reads)
+        HIP_TRY(ctx, ctx->grad2d.ensure(N * 10 * 4));
+        HIP_TRY(ctx, hipMemset(ctx->grad2d.p, 0, N * 10 * 4));
+    }
     ctx->ws_n = nn;
     ctx->ws_cap = cc;
     return FGS_OK;
@@ -249,10 +258,23 @@ uint32_t *status_words(fgs_ctx *ctx) { return ctx->words.as<uint32_t>() + W_STAT
 struct Stage {
     fgs_ctx *ctx;
     hipEvent_t a = nullptr, b = nullptr;
+    static hipEvent_t take(fgs_ctx *c)
+    {
+        hipEvent_t e = nullptr;
+        if (!c->event_pool.empty()) {
+            e = c->event_pool.back();
+            c->event_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
     Stage(fgs_ctx *c, const char *name) : ctx(c)
     {
         if (!ctx->prof) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = take(ctx);
+        b = take(ctx);
+        if (!a || !b) {
             ctx->prof = false;
             return;
         }
@@ -270,15 +292,19 @@ unsigned long long *prof_counts(fgs_ctx *ctx)
     return ctx->prof ? ctx->prof_counts.as<unsigned long long>() : nullptr;
 }
 
-void clear_profile(fgs_ctx *ctx)
+void clear_profile(fgs_ctx *ctx, bool destroy = false)
 {
     for (auto &kv : ctx->prof_events)
         for (auto &ab : kv.second) {
-            (void)hipEventDestroy(ab.first);
-            (void)hipEventDestroy(ab.second);
+            ctx->event_pool.push_back(ab.first);
+            ctx->event_pool.push_back(ab.second);
         }
     ctx->prof_events.clear();
     ctx->prof_fwd = 0;
+    if (destroy) {
+        for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+        ctx->event_pool.clear();
+    }
 }
 
 fgs_status read_words(fgs_ctx *ctx);
@@ -288,7 +314,7 @@ fgs_status read_words(fgs_ctx *ctx);
 // with the count in *K_check before enqueueing the rest.
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
-                           int64_t *K_check = nullptr)
+                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr)
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
@@ -324,8 +350,9 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     {
         Stage st_(ctx, "bin");
         launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
-                    ctx->blocksums.as<uint32_t>(), g.n, rk.tiles_x, L.cap, ctx->pkA.as<uint32_t>(),
-                    ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs, s);
+                    ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n, rk.tiles_x, L.cap,
+                    ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs,
+                    host_status, s);
     }
     {
         Stage st_(ctx, "tile_sort");
@@ -346,7 +373,8 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
 
 fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                             int tw, int th, const void *state, const StateLayout &L, const float *drgb,
-                            const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians &grad)
+                            const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians &grad,
+                            bool accumulate)
 {
     fgs_status st = ensure_ws(ctx, g.n, 0);
     if (st != FGS_OK) return st;
@@ -355,7 +383,6 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
     const StatePtrs sp = state_ptrs((void *)state, L);
     float *g2 = ctx->grad2d.as<float>();
-    launch_zero_f32(g2, 10 * g.n, s);
     {
         Stage st_(ctx, "raster_bwd");
         launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb, ddepth,
@@ -363,7 +390,7 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     }
     {
         Stage st_(ctx, "project_bwd");
-        launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), s);
+        launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), accumulate, s);
     }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -462,12 +489,13 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
 {
     if (!ctx) return FGS_OK;
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
-    clear_profile(ctx);
+    clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials};
     for (DBuf *b : bufs) b->release();
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
+    if (ctx->ms_host) (void)hipHostFree(ctx->ms_host);
     delete ctx;
     return FGS_OK;
 }
@@ -527,6 +555,14 @@ fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     clear_profile(ctx);
     ctx->prof = enable != 0;
+    if (ctx->prof && ctx->event_pool.size() < 4096) {
+        // events for a few hundred steps up front, so the timed loop does not create any
+        while (ctx->event_pool.size() < 4096) {
+            hipEvent_t e;
+            HIP_TRY(ctx, hipEventCreate(&e));
+            ctx->event_pool.push_back(e);
+        }
+    }
     if (ctx->prof) {
         HIP_TRY(ctx, ctx->prof_counts.ensure(4 * 8));
         HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 4 * 8));
@@ -622,7 +658,8 @@ fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state of %lld bytes does not match n and the image size", w,
                     (long long)state_bytes);
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
-    return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, *grad);
+    return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, *grad,
+                            true);
 }
 
 fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth, const fgs_target *target,
@@ -712,7 +749,27 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
     hipStream_t s = ctx->stream;
     const int64_t n = params->n;
-    // summed gradient: the caller's buffer, or the context's
+    if (!ctx->ms_host) {
+        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->ms_host, 2 * 4096 * 4, hipHostMallocMapped | hipHostMallocCoherent));
+        memset(ctx->ms_host, 0, 2 * 4096 * 4);
+        HIP_TRY(ctx, hipHostGetDevicePointer((void **)&ctx->ms_host_dev, ctx->ms_host, 0));
+        ctx->ms_seen.assign(4096, false);
+    }
+    // A step whose pair count outgrew the state while running unchecked is reported here, once:
+    // the state is grown and the caller learns that the earlier step used an incomplete gradient.
+    for (int v = 0; v < n_views; ++v) {
+        volatile uint32_t *hs = ctx->ms_host + 2 * v;
+        if (hs[1]) {
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+            const int64_t K = hs[0];
+            hs[1] = 0;
+            if (K + K / 4 + 1024 > ctx->ms_cap) ctx->ms_cap = K + K / 4 + 1024;
+            return fail(ctx, FGS_ERR_CAPACITY,
+                        "%s: an earlier step needed %lld (tile, gaussian) pairs in view %d; the state was grown", w,
+                        (long long)K, v);
+        }
+    }
+    // summed gradient: the caller's buffer, or the context's (the first view overwrites it)
     fgs_gaussians grad;
     if (grad_out) {
         grad = *grad_out;
@@ -720,14 +777,6 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         HIP_TRY(ctx, ctx->ms_grad.ensure((size_t)(n > 0 ? n : 1) * 14 * 4));
         float *b = ctx->ms_grad.as<float>();
         grad = fgs_gaussians{n, n, b, b + 3 * n, b + 6 * n, b + 10 * n, b + 11 * n};
-    }
-    for (int k = 0; k < 14; ++k) {
-        float *pl = k < 3 ? grad.mean + k * grad.stride
-                  : k < 6 ? grad.log_scale + (k - 3) * grad.stride
-                  : k < 10 ? grad.quat + (k - 6) * grad.stride
-                  : k < 11 ? grad.opacity_logit
-                           : grad.rgb + (k - 11) * grad.stride;
-        launch_zero_f32(pl, n, s);
     }
     HIP_TRY(ctx, ctx->ms_img.ensure((size_t)Pmax * 4 * 4));
     HIP_TRY(ctx, ctx->ms_dl.ensure((size_t)Pmax * 4 * 4));
@@ -737,17 +786,31 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     for (int v = 0; v < n_views; ++v) {
         const fgs_camera &cam = cams[v];
         const int64_t P = (int64_t)cam.width * cam.height;
+        uint32_t *hs_dev = v < 4096 ? ctx->ms_host_dev + 2 * v : nullptr;
         StateLayout L;
         for (int attempt = 0;; ++attempt) {
             state_layout(n, cam.width, cam.height, tw, th, ctx->ms_cap, &L);
             HIP_TRY(ctx, ctx->ms_state.ensure(L.bytes));
             float *im = ctx->ms_img.as<float>();
             ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
-            // The pair count is data dependent: the forward waits for it after the scan and the
-            // view restarts with a larger state when it does not fit (the state keeps its size).
+            // The pair count is data dependent. A view is checked synchronously (the forward waits
+            // for the count after the scan and restarts with a larger state when it does not fit)
+            // the first time it is seen and whenever its last observed count came within 10% of the
+            // capacity; otherwise it runs without a host round trip and an overflow is caught by the
+            // flag above on the next call.
+            const bool seen = v < 4096 && ctx->ms_seen[v];
+            const int64_t K_obs = v < 4096 ? (int64_t)((volatile uint32_t *)ctx->ms_host)[2 * v] : 0;
+            const bool checked = !seen || K_obs * 10 > ctx->ms_cap * 9;
             int64_t K = 0;
-            st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, &K);
-            if (st == FGS_OK) break;
+            st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, checked ? &K : nullptr,
+                                 hs_dev);
+            if (st == FGS_OK) {
+                if (v < 4096) ctx->ms_seen[v] = true;
+                // keep 50% headroom above a count seen within 20% of the capacity (the larger state
+                // is allocated before the next step's forward)
+                if (checked && K * 5 > ctx->ms_cap * 4) ctx->ms_cap = K + K / 2 + 1024;
+                break;
+            }
             if (st != FGS_ERR_CAPACITY || attempt > 0) return st;
             ctx->ms_cap = K + K / 4 + 1024;
         }
@@ -760,7 +823,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
                            psnr_dev ? psnr_dev + v : nullptr, s);
         }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
-                                   grad)) != FGS_OK)
+                                   grad, v > 0)) != FGS_OK)
             return st;
     }
     enqueue_adam(ctx, *params, grad, opt);

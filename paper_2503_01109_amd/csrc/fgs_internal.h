@@ -107,12 +107,13 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
                         uint32_t *status, hipStream_t s);
 
 // Emit one (tile, rank) pair per covered tile in depth order, and gather records into depth
-// order. If the pairs exceed cap, nothing is emitted for sorting (*n_pairs_dev = 0) and the
-// required count is recorded in status.
+// order. offsets is scratch of n + 1 words (per-rank exclusive offsets). If the pairs exceed
+// cap, nothing is emitted for sorting (*n_pairs_dev = 0) and the required count is recorded in
+// status. host_status (nullable, host-mapped): [0] = pairs, [1] |= overflow.
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
-                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev,
-                 hipStream_t s);
+                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t tiles_x, int64_t cap,
+                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev,
+                 uint32_t *host_status, hipStream_t s);
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
                    int64_t T, hipStream_t s);
@@ -135,8 +136,10 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        const float *drgb, const float *ddepth, const float *dalpha,
                        const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s);
 
+// Chain rule from the 2D gradients (10 planes by depth rank) to the 14 parameter gradients of
+// every gaussian. accumulate: grad += (else grad =, for every gaussian). grad2d is left zeroed.
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
-                        const float *grad2d, const GradK &grad, hipStream_t s);
+                        float *grad2d, const GradK &grad, bool accumulate, hipStream_t s);
 
 // L1 loss of Eq. 16 (colour + depth terms) with its gradient; partials is scratch of
 // loss_partials_size(P) floats; writes loss/psnr device scalars (nullable) and the depth-gradient

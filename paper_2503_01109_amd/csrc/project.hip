@@ -157,11 +157,12 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
 
 // Backward of the projection for the gaussian of depth rank r (one thread each). grad2d holds
 // 10 planes of length n indexed by depth rank: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b;
-// depth). The 14 parameter gradients are added to grad (each gaussian has one rank, so no
-// atomics are needed).
+// depth); each thread zeroes the slots it read, so grad2d is all-zero again for the next
+// backward. The 14 parameter gradients are added to grad (accumulate) or written to it (each
+// gaussian has one rank, so no atomics are needed).
 __global__ void __launch_bounds__(256)
-k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
-              const float *__restrict__ grad2d, GradK grad)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids, float *__restrict__ grad2d,
+              GradK grad, int accumulate)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
@@ -173,11 +174,26 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
         g2[k] = grad2d[k * n + r];
         any |= g2[k] != 0.0;
     }
-    if (!any) return;
     const int64_t i = ids[r];
+    const int64_t S = grad.stride;
     Proj p;
-    project_gaussian(g, i, cam, rk.lowpass, p);
-    if (!p.valid) return;
+    if (any) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) grad2d[k * n + r] = 0.0f;
+        project_gaussian(g, i, cam, rk.lowpass, p);
+    }
+    if (!any || !p.valid) {
+        if (!accumulate) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) grad.mean[k * S + i] = grad.log_scale[k * S + i] = grad.rgb[k * S + i] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) grad.quat[k * S + i] = 0.0f;
+            grad.logit[i] = 0.0f;
+        }
+        return;
+    }
+    // accumulate: out += v; otherwise out = v
+    auto put = [accumulate](float *dst, double v) { *dst = accumulate ? *dst + (float)v : (float)v; };
     // conic = Sigma'^-1: dL/dSigma' = -X Gh X with Gh = [[ga, gb/2], [gb/2, gc]], X the conic.
     const double a = p.conic[0], b = p.conic[1], c = p.conic[2];
     const double ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
@@ -224,9 +240,8 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
     dty += g2[1] * fy * iz;
     dtz += g2[1] * (-fy * ty * iz * iz);
     dtz += g2[9];
-    const int64_t S = grad.stride;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) grad.mean[k * S + i] += (float)(W[k] * dtx + W[3 + k] * dty + W[6 + k] * dtz);
+    for (int k = 0; k < 3; ++k) put(&grad.mean[k * S + i], W[k] * dtx + W[3 + k] * dty + W[6 + k] * dtz);
     // Sigma = M M^T, M = R diag(s): dM = 2 dSigma M
     double M[9], dM[9];
 #pragma unroll
@@ -242,7 +257,7 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double ds = p.Rq[k] * dM[k] + p.Rq[3 + k] * dM[3 + k] + p.Rq[6 + k] * dM[6 + k];
-        grad.log_scale[k * S + i] += (float)(ds * p.s[k]);
+        put(&grad.log_scale[k * S + i], ds * p.s[k]);
 #pragma unroll
         for (int u = 0; u < 3; ++u) dR[3 * u + k] = dM[3 * u + k] * p.s[k];
     }
@@ -260,10 +275,10 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids,
     const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
     const double iq = 1.0 / p.qnorm;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) grad.quat[k * S + i] += (float)((dq[k] - p.qn[k] * dot) * iq);
-    grad.logit[i] += (float)(g2[5] * p.opacity * (1.0 - p.opacity));
+    for (int k = 0; k < 4; ++k) put(&grad.quat[k * S + i], (dq[k] - p.qn[k] * dot) * iq);
+    put(&grad.logit[i], g2[5] * p.opacity * (1.0 - p.opacity));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) grad.rgb[k * S + i] += (float)g2[6 + k];
+    for (int k = 0; k < 3; ++k) put(&grad.rgb[k * S + i], g2[6 + k]);
 }
 
 }  // namespace
@@ -277,11 +292,12 @@ void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *r
 }
 
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
-                        const float *grad2d, const GradK &grad, hipStream_t s)
+                        float *grad2d, const GradK &grad, bool accumulate, hipStream_t s)
 {
     if (g.n <= 0) return;
     const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, ids, grad2d, grad);
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, ids, grad2d, grad,
+                       (int)accumulate);
 }
 
 }  // namespace fgs

@@ -180,50 +180,94 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
     }
 }
 
+// Per-rank exclusive offsets: offsets[r] = block offset + prefix of count[ids[.]] inside the
+// block (same partition as k_count_reduce); offsets[n] = total. Also gathers the records of
+// the gaussians that cover at least one tile into depth order.
 __global__ void __launch_bounds__(kSortThreads)
-k_emit(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-       const Rec *__restrict__ rec_by_id, const uint32_t *__restrict__ blocksums, int64_t n, int32_t tiles_x,
-       int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, Rec *__restrict__ rec_sorted,
-       uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, const uint32_t *__restrict__ total)
+k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const Rec *__restrict__ rec_by_id,
+             int64_t n, const uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ offsets,
+             Rec *__restrict__ rec_sorted)
 {
     __shared__ uint32_t w[8];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
     uint32_t c[kScanItems], id[kScanItems], s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t r = base + k;
-        id[k] = r < n ? ids[r] : 0u;
-        c[k] = r < n ? count[id[k]] : 0u;
+        id[k] = base + k < n ? ids[base + k] : 0u;
+        c[k] = base + k < n ? count[id[k]] : 0u;
         s += c[k];
     }
     uint32_t tot;
     uint32_t off = blocksums[blockIdx.x] + block_excl_scan(s, w, &tot);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t r = base + k;
-        if (r >= n) break;
-        if (c[k]) {
-            rec_sorted[r] = rec_by_id[id[k]];
-            const uint2 rc = rect[id[k]];
-            const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
-            if ((int64_t)off + c[k] <= cap) {
-                uint32_t o = off;
-                for (uint32_t ty = ty0; ty <= ty1; ++ty)
-                    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-                        keys[o] = ty * (uint32_t)tiles_x + tx;
-                        vals[o] = (uint32_t)r;
-                        ++o;
-                    }
-            }
+        if (base + k < n) {
+            offsets[base + k] = off;
+            if (c[k]) rec_sorted[base + k] = rec_by_id[id[k]];
         }
         off += c[k];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = blocksums[nb];
+}
+
+// Largest r in [lo, hi] with a[r] <= v (a non-decreasing, a[lo] <= v).
+__device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi, uint32_t v)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (a[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr uint32_t kEmitChunk = 4096;  // pairs per block iteration
+
+// Load-balanced emission: the K pairs are cut into chunks of kEmitChunk consecutive pair
+// indices; a block takes a chunk, finds the depth ranks it spans by binary search over the
+// per-rank offsets, and its threads write consecutive pair indices (coalesced), each finding its
+// rank by a binary search inside that span. A gaussian's pairs are its tile rectangle in
+// row-major order.
+__global__ void __launch_bounds__(kSortThreads)
+k_emit(const uint32_t *__restrict__ ids, const uint2 *__restrict__ rect, const uint32_t *__restrict__ offsets,
+       int64_t n, int32_t tiles_x, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+       uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, uint32_t *__restrict__ host_status)
+{
+    __shared__ uint32_t span[2];
+    const uint32_t K = offsets[n];
+    const uint32_t limit = (int64_t)K <= cap ? K : (uint32_t)cap;
+    for (uint64_t chunk = blockIdx.x; chunk * kEmitChunk < limit; chunk += gridDim.x) {
+        const uint32_t j0 = (uint32_t)(chunk * kEmitChunk);
+        const uint32_t j1 = min(j0 + kEmitChunk, limit);
+        if (threadIdx.x == 0) {
+            span[0] = last_le(offsets, 0, (uint32_t)n, j0);
+            span[1] = last_le(offsets, span[0], (uint32_t)n, j1 - 1);
+        }
+        __syncthreads();
+        const uint32_t rlo = span[0], rhi = span[1];
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
+            const uint32_t r = last_le(offsets, rlo, rhi, j);
+            const uint32_t idx = j - offsets[r];
+            const uint2 rc = rect[ids[r]];
+            const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu;
+            const uint32_t w = tx1 - tx0 + 1;
+            const uint32_t dy = idx / w;
+            keys[j] = (ty0 + dy) * (uint32_t)tiles_x + tx0 + (idx - dy * w);
+            vals[j] = r;
+        }
+        __syncthreads();
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t K = *total;
         // On overflow nothing is sorted or rendered (the pairs that were written are not a
         // complete set); the condition is recorded and reported by the next status check.
-        *n_pairs_dev = (int64_t)K <= cap ? K : 0u;
-        if ((int64_t)K > cap) atomicMax(&status[ST_OVERFLOW], K);
+        const bool ovf = (int64_t)K > cap;
+        *n_pairs_dev = ovf ? 0u : K;
+        if (ovf) atomicMax(&status[ST_OVERFLOW], K);
+        if (host_status) {
+            host_status[0] = K;
+            if (ovf) host_status[1] = 1u;
+            __threadfence_system();
+        }
     }
 }
 
@@ -239,15 +283,25 @@ k_visible(const uint32_t *__restrict__ count, int64_t n, uint32_t *__restrict__ 
     if (threadIdx.x == 0 && tot) atomicAdd(&status[ST_VISIBLE], tot);
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges)
+__device__ inline uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v)
 {
-    const uint32_t K = *n_dev;
-    for (uint32_t i = blockIdx.x * kSortThreads + threadIdx.x; i < K; i += gridDim.x * kSortThreads) {
-        const uint32_t t = keys[i];
-        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == K || keys[i + 1] != t) ranges[t].y = i + 1;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
     }
+    return lo;
+}
+
+// [start, end) of every tile's run in the sorted keys, by two binary searches per tile.
+__global__ void __launch_bounds__(kSortThreads)
+k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges, int64_t T)
+{
+    const int64_t t = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (t >= T) return;
+    const uint32_t K = *n_dev;
+    ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t), lower_bound_u32(keys, K, (uint32_t)t + 1));
 }
 
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
@@ -321,21 +375,24 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 }
 
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
-                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev, hipStream_t s)
+                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
+                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status,
+                 hipStream_t s)
 {
     // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
     const int nb = (int)scan_blocks(n);
-    hipLaunchKernelGGL(k_emit, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, rec_by_id,
-                       blocksums, n, tiles_x, cap, keys, vals, rec_sorted, status, n_pairs_dev, blocksums + nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rec_by_id, n,
+                       blocksums, nb, offsets, rec_sorted);
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, ids, rect, offsets, n,
+                       tiles_x, cap, keys, vals, status, n_pairs_dev, host_status);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,
                    hipStream_t s)
 {
-    launch_zero_u32((uint32_t *)ranges, 2 * T, s);
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 4096, 2048)), dim3(kSortThreads), 0, s, keys, n_pairs_dev,
-                       ranges);
+    (void)cap;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((T + kSortThreads - 1) / kSortThreads)), dim3(kSortThreads), 0, s,
+                       keys, n_pairs_dev, ranges, T);
 }
 
 }  // namespace fgs

@@ -1,0 +1,180 @@
+"""GPU parity of the mapping step: L1 loss (Eq. 16 L1 terms), Adam, and fgs_map_step against the
+oracle, plus gradient accumulation across views."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import assert_close_rel, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+LR = (1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3)
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    need_gpu()
+    import paper_2503_01109_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fgs):
+    c = fgs.Context()
+    yield c
+    c.close()
+
+
+def test_loss_l1_matches_oracle(fgs, ctx):
+    import torch
+    g = synth.rng(0)
+    H, W = 37, 53
+    rgb = g.uniform(size=(3, H, W)).astype(np.float32)
+    trgb = g.uniform(size=(3, H, W)).astype(np.float32)
+    d = g.uniform(1, 3, (H, W)).astype(np.float32)
+    td = g.uniform(1, 3, (H, W)).astype(np.float32)
+    td[:5] = 0.0
+    trgb[0, 0, :7] = rgb[0, 0, :7]  # exact ties: sign(0) = 0
+    dr, dd = torch.empty(3, H, W, device="cuda"), torch.empty(H, W, device="cuda")
+    loss, psnr = torch.empty(1, device="cuda"), torch.empty(1, device="cuda")
+    fgs.loss_l1(ctx, dev(rgb), dev(d), dev(trgb), dev(td), fgs.LossOpts(1.0, 0.1), dr, dd, loss, psnr)
+    L, ps, gr, gd = oracle.loss_l1(rgb, d, trgb, td, 1.0, 0.1)
+    assert abs(float(loss) - L) <= 1e-6 * L
+    assert abs(float(psnr) - ps) <= 1e-5 * ps
+    np.testing.assert_allclose(host(dr), gr, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(host(dd), gd, rtol=1e-6, atol=0)
+
+
+def test_adam_matches_oracle(fgs, ctx):
+    """Three Adam steps, each compared with one oracle step (FP64) from the GPU's state before it:
+    the stored parameter within one FP32 ulp (plus 1e-5 of the step), the moments within FP32
+    rounding of their operands. The ABI carries beta1 and beta2 as FP32; the oracle gets exactly
+    those values."""
+    g = synth.rng(1)
+    n = 1000
+    pd = dev(g.normal(size=(14, n)))
+    adam = fgs.Adam.like(pd, lr=LR)
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    for step in range(3):
+        grad = (g.normal(size=(14, n)) * 10.0 ** g.integers(-8, 0, size=(14, n))).astype(np.float32)
+        p0, m0, v0 = (host(t).astype(np.float64) for t in (pd, adam.m, adam.v))
+        fgs.adam_step(ctx, pd, dev(grad), n, adam)
+        ref_p, ref_m, ref_v = oracle.adam(p0, m0, v0, grad, step, LR, beta1=b1, beta2=b2)
+        p1, m1, v1 = (host(t).astype(np.float64) for t in (pd, adam.m, adam.v))
+        ulp = np.spacing(np.abs(ref_p).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(p1 - ref_p) <= ulp + 1e-5 * np.abs(ref_p - p0)), f"params, step {step}"
+        gg = grad.astype(np.float64)
+        # m = b1 m + (1 - b1) g can cancel: bound by the size of its operands
+        assert np.all(np.abs(m1 - ref_m) <= 4e-7 * (b1 * np.abs(m0) + (1 - b1) * np.abs(gg)) + 1e-40), f"m, step {step}"
+        assert np.all(np.abs(v1 - ref_v) <= 4e-7 * np.abs(ref_v) + 1e-44), f"v, step {step}"
+    assert adam.step == 3
+
+
+def zero_ambiguity_scene(n=400):
+    """A small scene (frustum at 1-5 m, 64x48) whose render has no ambiguous pixel, so the whole
+    mapping step is comparable pixel by pixel; found by scanning seeds with the oracle."""
+    cam = synth.camera_small()
+    for seed in range(100, 200):
+        p = synth.frustum_scene(seed, n, cam, 1.0, 5.0)
+        if oracle.render_fwd(p.astype(np.float64), cam, amb_rel=1e-5)["n_amb"] == 0:
+            return p, cam, seed
+    pytest.fail("no zero-ambiguity scene found")
+
+
+def test_map_step_matches_oracle(fgs, ctx):
+    import torch
+    p, cam, seed = zero_ambiguity_scene()
+    n = p.shape[1]
+    ref = oracle.render_fwd(p.astype(np.float64), cam, amb_rel=0)
+    tgt = oracle.render_fwd(synth.frustum_scene(seed + 1000, n, cam, 1.0, 5.0).astype(np.float64), cam, amb_rel=0)
+    trgb, td = tgt["rgb"].astype(np.float32), tgt["depth"].astype(np.float32)
+    # keep every residual away from the sign change of the L1 gradient
+    near = np.abs(ref["rgb"] - trgb) < 1e-3
+    trgb[near] += 0.01
+    dnear = np.abs(ref["depth"] - td) < 1e-3
+    td[dnear] += 0.01
+    L, ps, gr, gd = oracle.loss_l1(ref["rgb"], ref["depth"], trgb, td, 1.0, 0.1)
+    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, None)
+    pd = dev(p)
+    adam = fgs.Adam.like(pd, lr=LR)
+    grad = torch.zeros_like(pd)
+    loss, psnr = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    fgs.map_step(ctx, pd, n, adam, [cam], [(dev(trgb), dev(td))], fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1),
+                 loss, psnr, grad_out=grad)
+    ctx.check()
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert abs(float(psnr) - ps) <= 1e-5 * ps
+    gg = host(grad)
+    for rows in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11), slice(11, 14)):
+        assert_close_rel(gg[rows], gref[rows], 1e-4, what=f"grad rows {rows}", floor=1e-2)
+    # the first Adam step moves every parameter by -lr g/(|g| + eps): check where |g| is well
+    # above the FP32 gradient error
+    rows = np.array([0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4])
+    lr = np.array(LR)[rows][:, None]
+    expect = p - lr * gref / (np.abs(gref) + 1e-15)
+    big = np.abs(gref) >= 1e-2 * np.abs(gref).max(axis=1, keepdims=True)
+    np.testing.assert_allclose(host(pd)[big], expect[big], rtol=1e-6, atol=1e-6)
+
+
+def test_map_step_multiview_sums_views(fgs, ctx):
+    """The mapping step's gradient over three views equals the sum of single-view gradients
+    (render_fwd + loss + render_bwd through the ABI)."""
+    import torch
+    cam0 = synth.camera_small()
+    p = synth.frustum_scene(3, 1500, cam0, 1.0, 5.0)
+    n = p.shape[1]
+    cams = [cam0, synth.centred_camera(70, 50, 55.0),
+            synth.Camera(48, 40, 50.0, 50.0, 24.0, 20.0, t=[0.1, -0.05, 0.2])]
+    targets = []
+    for k, c in enumerate(cams):
+        g = synth.rng(50 + k)
+        targets.append((dev(g.uniform(size=(3, c.height, c.width))), dev(g.uniform(1, 4, (c.height, c.width)))))
+    pd = dev(p)
+    total = torch.zeros_like(pd)
+    opts = fgs.RenderOpts()
+    for c, (tr, tdp) in zip(cams, targets):
+        out = fgs.render(ctx, pd, n, c, opts)
+        dr, dd = torch.empty_like(tr), torch.empty_like(tdp)
+        fgs.loss_l1(ctx, out["rgb"], out["depth"], tr, tdp, fgs.LossOpts(), dr, dd)
+        fgs.render_bwd(ctx, pd, n, c, opts, out["state"], dr, dd, None, total)  # accumulates
+    ctx.check()
+    grad = torch.full_like(pd, 7.0)  # overwritten by map_step
+    adam = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
+    fgs.map_step(ctx, pd, n, adam, cams, targets, opts, grad_out=grad)
+    ctx.check()
+    assert_close_rel(host(grad), host(total), 1e-5, what="multi-view gradient", floor=1e-2)
+
+
+def test_render_bwd_accumulates(fgs, ctx):
+    import torch
+    p = synth.scene_small(2)
+    cam = synth.camera_small()
+    pd = dev(p)
+    n = p.shape[1]
+    out = fgs.render(ctx, pd, n, cam, fgs.RenderOpts())
+    g = synth.rng(9)
+    dr = dev(g.normal(size=(3, cam.height, cam.width)))
+    dd = dev(g.normal(size=(cam.height, cam.width)))
+    a = torch.zeros_like(pd)
+    fgs.render_bwd(ctx, pd, n, cam, fgs.RenderOpts(), out["state"], dr, dd, None, a)
+    b = a.clone()
+    fgs.render_bwd(ctx, pd, n, cam, fgs.RenderOpts(), out["state"], dr, dd, None, b)
+    ctx.check()
+    assert_close_rel(host(b), 2 * host(a), 1e-6, what="accumulated", floor=1e-2)
+
+
+def test_map_step_trains(fgs, ctx):
+    """Twenty steps against a fixed frame lower the loss."""
+    import torch
+    p = synth.scene_small(0)
+    cam = synth.camera_small()
+    n = p.shape[1]
+    tgt = fgs.render(ctx, dev(synth.scene_small(1)), n, cam, fgs.RenderOpts(), aux=False)
+    pd = dev(p)
+    adam = fgs.Adam.like(pd)
+    losses = torch.zeros(20, device="cuda")
+    for k in range(20):
+        fgs.map_step(ctx, pd, n, adam, [cam], [(tgt["rgb"], tgt["depth"])], fgs.RenderOpts(), loss=losses[k:k + 1])
+    ctx.check()
+    ls = host(losses)
+    assert ls[-1] < 0.8 * ls[0]
