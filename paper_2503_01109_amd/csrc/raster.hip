@@ -45,6 +45,68 @@ __device__ __forceinline__ void stage(const Rec &R, int x0, int y0, float4 &a, f
     c = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.0f);    // rgb
 }
 
+// Minimum of the quadratic form Q(p - m) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle
+// [x0, x1] x [y0, y1] (tile-local). Q is convex, so the minimum is 0 with the centre inside,
+// else on one of the four edges, where it is a 1D quadratic minimised by clamping its vertex.
+__device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia, float ic, float mx, float my,
+                                            float x0, float x1, float y0, float y1)
+{
+    // ia = 1/a, ic = 1/c (precomputed by the caller)
+    const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
+    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return 0.0f;
+    float best = INFINITY;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = e ? dx1 : dx0;
+        const float dy = fminf(fmaxf(-b * dx * ic, dy0), dy1);
+        best = fminf(best, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dy = e ? dy1 : dy0;
+        const float dx = fminf(fmaxf(-b * dy * ia, dx0), dx1);
+        best = fminf(best, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    }
+    return best;
+}
+
+// Bit w set when the sigma_cut ellipse of a staged record can reach a pixel centre of wave w's
+// strip (rows [w R, w R + R) of the tile, R = 64 / TW). Conservative by a relative 1e-3 margin:
+// the per-pixel test stays the exact decision.
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t strip_mask(const float4 &a4, const float4 &b4, float cut2)
+{
+    constexpr int R = kWave / TW, NW = TW * TH / kWave;
+    uint32_t m = 0;
+    const float ia = __frcp_rn(a4.z), ic = __frcp_rn(b4.x);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const float q =
+            rect_min_q(a4.z, a4.w, b4.x, ia, ic, a4.x, a4.y, 0.5f, TW - 0.5f, w * R + 0.5f, w * R + R - 0.5f);
+        if (q <= cut2 * 1.001f) m |= 1u << w;
+    }
+    return m;
+}
+
+// Compacts the indices k < cnt whose mask has this wave's bit into this wave's list (ascending);
+// returns the list length. Wave-local: no block barrier needed.
+__device__ __forceinline__ int wave_compact(const uint8_t *smask, int cnt, int wid, uint16_t *list)
+{
+    const int lane = __lane_id();
+    int len = 0;
+    for (int q = 0; q < cnt; q += kWave) {
+        const int e = q + lane;
+        const bool bit = e < cnt && ((smask[e] >> wid) & 1u);
+        const uint64_t bal = __ballot(bit);
+        if (bit) list[len + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)e;
+        len += __popcll(bal);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return len;
+}
+
 // DPP: v + (v moved by ctrl) in the rows enabled by row_mask, v elsewhere.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v)
@@ -71,9 +133,12 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
              const uint2 *__restrict__ ranges, uint32_t *__restrict__ last_out, float *__restrict__ tfinal_out,
              ImageK img, unsigned long long *__restrict__ counts)
 {
-    constexpr int NT = TW * TH;
+    constexpr int NT = TW * TH, NW = NT / kWave;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
+    __shared__ uint8_t smask[NT];
+    __shared__ uint16_t slist[NW][NT];
     const int tid = threadIdx.x;
+    const int wid = tid / kWave;
     const int tile = blockIdx.x;
     const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
@@ -99,11 +164,14 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
+            smask[tid] = (uint8_t)strip_mask<TW, TH>(a4, b4, cut2);
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, range.y - b);
-        for (int k = 0; k < cnt; ++k) {
+        const int len = wave_compact(smask, cnt, wid, slist[wid]);
+        for (int i = 0; i < len; ++i) {
             if (done) continue;
+            const int k = slist[wid][i];
             const float4 a4 = sa[k];
             const float dx = px - a4.x, dy = py - a4.y;
             const float4 b4 = sb[k];
@@ -168,13 +236,16 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
              const float *__restrict__ dalpha, const float *__restrict__ ddepth_scale, float *__restrict__ grad2d,
              int64_t n)
 {
-    constexpr int NT = TW * TH;
+    constexpr int NT = TW * TH, NW = NT / kWave;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint32_t srank[NT];
     __shared__ float sacc[10][NT];
     __shared__ uint32_t smax;
+    __shared__ uint8_t smask[NT];
+    __shared__ uint16_t slist[NW][NT];
     const int tid = threadIdx.x;
     const int lane = __lane_id();
+    const int wid = tid / kWave;
     const int tile = blockIdx.x;
     const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
@@ -221,9 +292,12 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             sb[tid] = b4;
             sc[tid] = c4;
             srank[tid] = r;
+            smask[tid] = (uint8_t)strip_mask<TW, TH>(a4, b4, cut2);
         }
         __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
+        const int len = wave_compact(smask, cnt, wid, slist[wid]);
+        for (int i = len - 1; i >= 0; --i) {
+            const int k = slist[wid][i];
             const uint32_t pos = bstart + k - range.x;  // list position of entry k
             float g[10];
             bool contrib = false;
