@@ -95,9 +95,10 @@ typedef struct {
 
 /* Seeding diagnostics (all outputs nullable):
  *  E       (W*H) high-pass magnitude |I_h|
- *  hist    (256) histogram of q = floor(255 E / E_max)
+ *  hist    (256) histogram of q = floor(255 (E / E_max))
  *  thresh  triangle threshold t (q > t is high frequency); -1 when E_max == 0
- *  margin  min over pixels of the distance of 255 E / E_max to the nearest integer */
+ *  margin  min over pixels (the maximum's aside) of the distance of 255 (E / E_max) to the
+ *          nearest integer k >= 1, the only values where q can change */
 int fgso_highpass(int32_t W, int32_t H, const float *rgb, double D0, double *E,
                   int64_t *hist, int32_t *thresh, double *margin);
 

@@ -12,7 +12,8 @@
  *     ub = u for u < W/2 else u - W (vb likewise); the Gaussian high-pass of Eq. 5,
  *     H = 1 - exp(-D^2/(2 D0^2)), multiplies the spectrum (Eq. 7).
  *  4. The inverse DFT with the 1/(HW) factor (Eq. 8) gives I_h; E = |I_h|.
- *  5. E is quantised to q = floor(255 E / E_max) and histogrammed in 256 bins. A frame whose
+ *  5. E is quantised to q = floor(255 (E / E_max)) and histogrammed in 256 bins (the ratio first,
+ *     so the pixel at the maximum maps exactly to 255: x / x = 1 in IEEE arithmetic). A frame whose
  *     E_max is at rounding level, E_max <= 1e-9 max|I|, is flat: it has no high-frequency
  *     region (a constant frame gives E == 0 in exact arithmetic).
  *  6. The triangle method picks the threshold t (the bin furthest below the line from the
@@ -115,12 +116,14 @@ int fgso_highpass(int32_t W, int32_t H, const float *rgb, double D0, double *E_o
         for (int64_t p = 0; p < P; ++p)
             if (E[p] == Emax) { arg = p; break; }
         for (int64_t p = 0; p < P; ++p) {
-            double r = 255.0 * E[p] / Emax;
+            double r = 255.0 * (E[p] / Emax);
             int32_t q = (int32_t)floor(r);
             if (q > 255) q = 255;
             hist[q]++;
-            if (p != arg && E[p] > 0) {
-                double d = fabs(r - nearbyint(r));
+            /* distance to the nearest integer k >= 1 (floor cannot change on [0, 1), E >= 0) */
+            double k = nearbyint(r);
+            if (p != arg && k >= 1.0) {
+                double d = fabs(r - k);
                 if (d < margin) margin = d;
             }
         }
@@ -187,7 +190,7 @@ int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
             if (!isfinite(d) || !(d >= o->depth_min) || !(d <= o->depth_max)) continue;
             int high = 0;
             if (Emax > 0) {
-                int32_t q = (int32_t)floor(255.0 * E[p] / Emax);
+                int32_t q = (int32_t)floor(255.0 * (E[p] / Emax));
                 if (q > 255) q = 255;
                 high = q > t;
             }

@@ -36,7 +36,7 @@ def test_highpass_matches_numpy_fft(D0):
     E, hist, t, margin = oracle.highpass(rgb, D0)
     ref = np.abs(np.fft.ifft2(np.fft.fft2(luma(rgb)) * hp_filter(W, H, D0)))
     np.testing.assert_allclose(E, ref, rtol=1e-9, atol=1e-12 * ref.max())
-    q = np.minimum(np.floor(255 * ref / ref.max()), 255).astype(int)
+    q = np.minimum(np.floor(255 * (ref / ref.max())), 255).astype(int)
     np.testing.assert_array_equal(hist, np.bincount(q.ravel(), minlength=256))
     assert hist.sum() == W * H
 
@@ -199,8 +199,9 @@ def test_seed_floats_are_binary32():
 def test_margin_reports_quantisation_distance():
     rgb, _ = synth.rgbd_frame(3, W, H, n_rect=6)
     E, hist, t, margin = oracle.highpass(rgb, 30.0)
-    r = 255 * E / E.max()
+    r = 255 * (E / E.max())
     m = np.abs(r - np.rint(r))
+    m[np.rint(r) < 1] = np.inf
     m[np.unravel_index(np.argmax(E), E.shape)] = np.inf
     assert margin == pytest.approx(m.min(), abs=1e-12)
 
@@ -225,7 +226,7 @@ def test_seed_set_from_numpy_mask():
     s = oracle.seed(rgb, depth, cam, o)
     assert s["margin"] > 1e-9
     E = np.abs(np.fft.ifft2(np.fft.fft2(luma(rgb)) * hp_filter(W, H, o.D0)))
-    q = np.minimum(np.floor(255 * E / E.max()), 255).astype(int)
+    q = np.minimum(np.floor(255 * (E / E.max())), 255).astype(int)
     t = oracle.triangle(np.bincount(q.ravel(), minlength=256))
     assert t == s["threshold"]
     hi = q > t
