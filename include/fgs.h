@@ -204,6 +204,58 @@ fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const f
 fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad,
                          fgs_adam *opt);
 
+/* ------------------------------ Fourier seeding (Sec. III-A) ------------------------------ */
+
+/* [host] Seeding constants. D0: cutoff radius of the Gaussian high-pass of Eq. 5, in frequency
+ * samples. m < n: lattice strides inside the high- and low-frequency masks. tile: edge of the
+ * square tiles of the per-tile seed count. alpha_h, alpha_l: radius factors of Eq. 11 (a seed's
+ * radius is alpha d / fx, alpha pixels at its depth). opacity_logit: initial opacity logit.
+ * Seeds need a finite depth in [depth_min, depth_max]. use_prior = 1 replaces the radius rule and
+ * the constant opacity of the emitted gaussians by the learned prior (fgs_prior.h) whose packed
+ * weights `prior` points to (device). */
+typedef struct {
+    double D0;
+    int32_t m, n, tile;
+    float alpha_h, alpha_l, opacity_logit;
+    float depth_min, depth_max;
+    int32_t use_prior;
+    const void *prior;
+} fgs_seed_opts;
+
+/* Seed output (device). Seeds are written in ascending pixel order (y * width + x), at most
+ * `capacity`: pixel index, is_high (1 = high-frequency mask), mean (3 planes of stride capacity,
+ * world coordinates), radius, rgb (3 planes). tile_count (ceil(W/tile) * ceil(H/tile) ints,
+ * row-major tiles) and n_dev (one int64: the number of seeds, which may exceed capacity) may be
+ * NULL. When params.mean is not NULL the seeds are also written as gaussians into params at
+ * [0, count): the mean, log-scale log(radius) on all axes, identity rotation, the initial opacity
+ * logit and the pixel colour (params.stride >= capacity). E (width*height doubles: |I_h|), hist
+ * (256 uint32: histogram of q = floor(255 E / E_max)) and threshold (one int32: the triangle
+ * threshold, -1 for a flat frame) are optional diagnostics. */
+typedef struct {
+    int64_t capacity;
+    int32_t *pixel;
+    uint8_t *is_high;
+    float *mean;
+    float *radius;
+    float *rgb;
+    int32_t *tile_count;
+    int64_t *n_dev;
+    fgs_gaussians params;
+    double *E;
+    uint32_t *hist;
+    int32_t *threshold;
+} fgs_seed_out;
+
+/* Seeds gaussians from one RGB-D frame (rgb: 3 planes, depth: 1 plane, width*height of cam) by the
+ * frequency analysis of Sec. III-A: luma DFT (Eq. 2), Gaussian high-pass centred on DC (Eq. 3, 5,
+ * 7), inverse DFT (Eq. 8), the triangle threshold of the magnitude histogram, lattice sampling
+ * with strides m and n, and back-projection through cam with the radius rule of Eq. 11. Frame
+ * lines must be at most 1920 pixels with prime factors up to 31. n_seeds_host [host] (may be NULL)
+ * waits for the stream and receives the number of seeds; more seeds than capacity then returns
+ * FGS_ERR_CAPACITY (otherwise the next fgs_ctx_check reports it). */
+fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth, const fgs_camera *cam,
+                              const fgs_seed_opts *o, const fgs_seed_out *out, int64_t *n_seeds_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,19 @@ class CLossOpts(C.Structure):
     _fields_ = [("lambda_rgb", C.c_float), ("lambda_depth", C.c_float)]
 
 
+class CSeedOpts(C.Structure):
+    _fields_ = [("D0", C.c_double), ("m", C.c_int32), ("n", C.c_int32), ("tile", C.c_int32),
+                ("alpha_h", C.c_float), ("alpha_l", C.c_float), ("opacity_logit", C.c_float),
+                ("depth_min", C.c_float), ("depth_max", C.c_float), ("use_prior", C.c_int32), ("prior", C.c_void_p)]
+
+
+class CSeedOut(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("pixel", _i32p), ("is_high", C.POINTER(C.c_uint8)), ("mean", _fp),
+                ("radius", _fp), ("rgb", _fp), ("tile_count", _i32p), ("n_dev", C.POINTER(C.c_int64)),
+                ("params", CGaussians), ("E", C.POINTER(C.c_double)), ("hist", C.POINTER(C.c_uint32)),
+                ("threshold", _i32p)]
+
+
 _vp = C.c_void_p
 _P = C.POINTER
 _sigs = {
@@ -94,6 +107,7 @@ _sigs = {
     "fgs_ctx_profile": [_vp, C.c_int32],
     "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
     "fgs_ctx_profile_counts": [_vp, _P(C.c_int64)],
+    "fgs_seed_gaussians": [_vp, _fp, _fp, _P(CCamera), _P(CSeedOpts), _P(CSeedOut), _P(C.c_int64)],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -359,3 +373,68 @@ def ctx_required_pairs(err: FgsError) -> int:
     if not m:
         raise err
     return int(m.group(1))
+
+
+@dataclass
+class SeedOpts:
+    """Fourier seeding constants (see fgs_seed_opts)."""
+    D0: float = 30.0
+    m: int = 2
+    n: int = 8
+    tile: int = 16
+    alpha_h: float = 1.0
+    alpha_l: float = 4.0
+    opacity_logit: float = 0.0
+    depth_min: float = 0.1
+    depth_max: float = 10.0
+    use_prior: int = 0
+    prior: object = None
+
+    def c(self) -> CSeedOpts:
+        o = CSeedOpts()
+        o.D0, o.m, o.n, o.tile = self.D0, self.m, self.n, self.tile
+        o.alpha_h, o.alpha_l, o.opacity_logit = self.alpha_h, self.alpha_l, self.opacity_logit
+        o.depth_min, o.depth_max, o.use_prior = self.depth_min, self.depth_max, self.use_prior
+        o.prior = None if self.prior is None else C.c_void_p(self.prior.data_ptr())
+        return o
+
+
+def _ptr(t, ctype):
+    return None if t is None else C.cast(C.c_void_p(t.data_ptr()), ctype)
+
+
+def seed_gaussians(ctx: Context, rgb, depth, cam, opts: SeedOpts | None = None, capacity: int | None = None,
+                   params=None, diagnostics: bool = False, sync: bool = True) -> dict:
+    """Seed gaussians from an RGB-D frame (rgb (3,H,W), depth (H,W) float32 device tensors).
+    params: optional (14, >= capacity) block that receives the seeds as gaussians."""
+    import torch
+    o = opts or SeedOpts()
+    H, W = int(cam.height), int(cam.width)
+    cap = capacity if capacity is not None else (W * H) // (o.m * o.m) + W + H + 16
+    dev = rgb.device
+    tx, ty = (W + o.tile - 1) // o.tile, (H + o.tile - 1) // o.tile
+    r = dict(pixel=torch.empty(cap, dtype=torch.int32, device=dev), is_high=torch.empty(cap, dtype=torch.uint8, device=dev),
+             mean=torch.empty((3, cap), dtype=torch.float32, device=dev), radius=torch.empty(cap, dtype=torch.float32, device=dev),
+             rgb=torch.empty((3, cap), dtype=torch.float32, device=dev),
+             tile_count=torch.empty((ty, tx), dtype=torch.int32, device=dev),
+             n_dev=torch.zeros(1, dtype=torch.int64, device=dev))
+    if diagnostics:
+        r.update(E=torch.empty((H, W), dtype=torch.float64, device=dev), hist=torch.empty(256, dtype=torch.int32, device=dev),
+                 threshold=torch.empty(1, dtype=torch.int32, device=dev))
+    out = CSeedOut()
+    out.capacity = cap
+    out.pixel, out.is_high = _ptr(r["pixel"], _i32p), _ptr(r["is_high"], C.POINTER(C.c_uint8))
+    out.mean, out.radius, out.rgb = _f32(r["mean"]), _f32(r["radius"]), _f32(r["rgb"])
+    out.tile_count, out.n_dev = _ptr(r["tile_count"], _i32p), _ptr(r["n_dev"], C.POINTER(C.c_int64))
+    if params is not None:
+        assert params.shape[1] >= cap
+        out.params = gaussians(params, cap)
+    if diagnostics:
+        out.E, out.hist = _ptr(r["E"], C.POINTER(C.c_double)), _ptr(r["hist"], C.POINTER(C.c_uint32))
+        out.threshold = _ptr(r["threshold"], _i32p)
+    n = C.c_int64(-1)
+    _check(_lib.fgs_seed_gaussians(ctx.handle, _f32(rgb), _f32(depth), C.byref(camera(cam)), C.byref(o.c()),
+                                   C.byref(out), C.byref(n) if sync else None), ctx.handle)
+    r["n"] = n.value
+    r["capacity"] = cap
+    return r

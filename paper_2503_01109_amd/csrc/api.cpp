@@ -2,6 +2,7 @@
 // forward, backward and mapping-step pipelines. See include/fgs.h for the contract of every call.
 #include "fgs.h"
 #include "fgs_internal.h"
+#include "seed_internal.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -64,6 +65,7 @@ struct fgs_ctx {
     int64_t ws_n = -1, ws_cap = -1;
     // mapping-step buffers
     DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
+    DBuf seed_ws, seed_sc;
     int64_t ms_cap = 0;
     uint32_t *host_words = nullptr;  // pinned copy of the status words
     // host-mapped per-view pair counts of mapping steps: [2v] = pairs, [2v+1] = overflow flag
@@ -492,7 +494,8 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
-                    &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials};
+                    &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
+                    &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets};
     for (DBuf *b : bufs) b->release();
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
     if (ctx->ms_host) (void)hipHostFree(ctx->ms_host);
@@ -828,6 +831,66 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     }
     enqueue_adam(ctx, *params, grad, opt);
     HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth, const fgs_camera *cam,
+                              const fgs_seed_opts *o, const fgs_seed_out *out, int64_t *n_seeds_host)
+{
+    const char *w = "fgs_seed_gaussians";
+    fgs_status st;
+    if ((st = check_camera(ctx, cam, w)) != FGS_OK) return st;
+    if (!rgb || !depth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: rgb/depth is NULL", w);
+    if (!o) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: options are NULL", w);
+    if (!(o->D0 > 0) || !isfinite(o->D0)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: D0 must be finite and > 0", w);
+    if (o->m <= 0 || o->n <= 0 || o->tile <= 0)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: m, n and tile must be positive", w);
+    if (!isfinite(o->alpha_h) || !isfinite(o->alpha_l) || !isfinite(o->opacity_logit) ||
+        !(o->depth_min <= o->depth_max))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: radius factors, opacity or depth range invalid", w);
+    if (o->use_prior) return fail(ctx, FGS_ERR_UNSUPPORTED, "%s: the learned prior is not built into this call", w);
+    if (!out || out->capacity < 0 || (out->capacity > 0 && (!out->pixel || !out->is_high || !out->mean ||
+                                                            !out->radius || !out->rgb)))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: seed output incomplete", w);
+    if (out->params.mean) {
+        if ((st = check_gauss(ctx, &out->params, w, "out.params")) != FGS_OK) return st;
+        if (out->params.stride < out->capacity)
+            return fail(ctx, FGS_ERR_INVALID_ARG, "%s: out.params.stride < capacity", w);
+    }
+    const int W = cam->width, H = cam->height;
+    if (!seed_size_supported(W, H))
+        return fail(ctx, FGS_ERR_UNSUPPORTED, "%s: frame %dx%d: lines must be 2..%d long with prime factors <= 31", w, W,
+                    H, kSeedMaxLine);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    HIP_TRY(ctx, ctx->seed_ws.ensure(seed_ws_bytes(W, H)));
+    HIP_TRY(ctx, ctx->seed_sc.ensure(sizeof(SeedScalars)));
+    SeedK sk;
+    sk.m = o->m; sk.n = o->n; sk.tile = o->tile;
+    sk.dmin = o->depth_min; sk.dmax = o->depth_max;
+    sk.alpha_h = o->alpha_h; sk.alpha_l = o->alpha_l; sk.opacity_logit = o->opacity_logit;
+    sk.fx = cam->fx; sk.fy = cam->fy; sk.cx = cam->cx; sk.cy = cam->cy;
+    for (int k = 0; k < 9; ++k) sk.R[k] = cam->R_cw[k];
+    for (int k = 0; k < 3; ++k) sk.t[k] = cam->t_cw[k];
+    SeedOutK so;
+    so.capacity = out->capacity;
+    so.pixel = out->pixel; so.is_high = out->is_high; so.mean = out->mean; so.radius = out->radius; so.rgb = out->rgb;
+    so.tile_count = out->tile_count;
+    so.n_dev = out->n_dev;
+    so.params = out->params.mean ? to_gk(out->params) : GradK{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+    so.E = out->E;
+    so.hist = out->hist;
+    SeedScalars *sc = ctx->seed_sc.as<SeedScalars>();
+    launch_seed(rgb, depth, W, H, o->D0, sk, so, ctx->seed_ws.p, sc, status_words(ctx), ctx->stream);
+    if (out->threshold)
+        HIP_TRY(ctx, hipMemcpyAsync(out->threshold, &sc->thresh, 4, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipGetLastError());
+    if (n_seeds_host) {
+        if ((st = read_words(ctx)) != FGS_OK) return st;
+        *n_seeds_host = ctx->host_words[ST_SEEDS];
+        if (*n_seeds_host > out->capacity)
+            return fail(ctx, FGS_ERR_CAPACITY, "%s: %lld seeds found, capacity %lld", w, (long long)*n_seeds_host,
+                        (long long)out->capacity);
+    }
     return FGS_OK;
 }
 

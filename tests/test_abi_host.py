@@ -139,3 +139,33 @@ def test_render_fwd_rejects_bad_arguments_on_host():
 def test_status_strings():
     for s in (F.OK, F.ERR_INVALID_ARG, F.ERR_CAPACITY, F.ERR_HIP, F.ERR_UNSUPPORTED):
         assert F._lib.fgs_status_str(s)
+
+
+def test_seed_rejects_bad_arguments_on_host():
+    import numpy as np
+    o = F.SeedOpts()
+    out = F.CSeedOut()
+    out.capacity = 10
+    dummy = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+
+    def call(cam, opts=o, capacity=10):
+        out.capacity = capacity
+        out.pixel = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_int32))
+        out.is_high = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_uint8))
+        out.mean = out.radius = out.rgb = dummy
+        st = F._lib.fgs_seed_gaussians(None, dummy, dummy, C.byref(F.camera(cam)), C.byref(opts.c()), C.byref(out),
+                                       None)
+        return st, F.last_error()
+
+    import synth
+    assert call(synth.camera_tum()) == (F.ERR_INVALID_ARG, "fgs_seed_gaussians: ctx is NULL")
+    st, msg = call(synth.centred_camera(74, 48, 60.0))  # 74 = 2 * 37
+    assert st == F.ERR_UNSUPPORTED and "prime factors" in msg
+    st, msg = call(synth.centred_camera(2048, 64, 60.0))
+    assert st == F.ERR_UNSUPPORTED
+    st, msg = call(synth.camera_tum(), F.SeedOpts(D0=0.0))
+    assert st == F.ERR_INVALID_ARG and "D0" in msg
+    st, msg = call(synth.camera_tum(), F.SeedOpts(m=0))
+    assert st == F.ERR_INVALID_ARG
+    st, msg = call(synth.camera_tum(), capacity=-1)
+    assert st == F.ERR_INVALID_ARG and "output" in msg

@@ -1,0 +1,131 @@
+"""GPU parity of Fourier seeding (fgs_seed_gaussians) against the FP64 oracle.
+
+The seeded set (pixel ids, class bits), the per-tile counts and every binary32 value (mean,
+radius, colour) must be identical. The FFT magnitude E is compared to the oracle's naive DFT at
+1e-12 of E_max. Identity of the histogram and threshold is asserted when the oracle's margin
+(distance of 255 (E / E_max) to an integer >= 1) exceeds 1e-9; the synthetic frames used here are
+checked to satisfy that, else the test would say so.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    need_gpu()
+    import paper_2503_01109_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fgs):
+    c = fgs.Context()
+    yield c
+    c.close()
+
+
+def oracle_opts(o):
+    return oracle.SeedOpts(o.D0, o.m, o.n, o.tile, o.alpha_h, o.alpha_l, o.opacity_logit, o.depth_min, o.depth_max)
+
+
+def compare(fgs, ctx, rgb, depth, cam, opts, check_margin=True):
+    g = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, opts, diagnostics=True)
+    ref = oracle.seed(rgb, depth, cam, oracle_opts(opts))
+    if check_margin and ref["threshold"] >= 0:
+        assert ref["margin"] > 1e-9, f"ambiguous frame: quantisation margin {ref['margin']:.2e}"
+    E, hist, thr, _ = oracle.highpass(rgb, opts.D0)
+    Eg = host(g["E"])
+    if E.max() > 0:
+        assert np.abs(Eg - E).max() <= 1e-12 * max(E.max(), 1e-300) + 1e-15
+    assert int(host(g["threshold"])[0]) == ref["threshold"]
+    if ref["threshold"] >= 0:
+        np.testing.assert_array_equal(host(g["hist"]), hist)
+    n = g["n"]
+    assert n == ref["n"]
+    np.testing.assert_array_equal(host(g["pixel"])[:n], ref["pixel"])
+    np.testing.assert_array_equal(host(g["is_high"])[:n].astype(bool), ref["is_high"])
+    np.testing.assert_array_equal(host(g["mean"])[:, :n], ref["mean"])      # bit-exact binary32
+    np.testing.assert_array_equal(host(g["radius"])[:n], ref["radius"])
+    np.testing.assert_array_equal(host(g["rgb"])[:, :n], ref["rgb"])
+    np.testing.assert_array_equal(host(g["tile_count"]), ref["tile_count"])
+    assert int(host(g["n_dev"])[0]) == n
+    return g, ref
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tum_sized_frame_is_bit_exact(fgs, ctx, seed):
+    """640x480 synthetic RGB-D frames (TUM-sized), D0 = 30, m = 2, n = 8."""
+    rgb, depth = synth.rgbd_frame(seed)
+    g, ref = compare(fgs, ctx, rgb, depth, synth.camera_tum(), fgs.SeedOpts())
+    assert 0 < ref["is_high"].sum() < ref["n"]
+
+
+def test_posed_camera_and_options(fgs, ctx):
+    """A rotated, translated camera; other strides, radii and cutoff; fx != fy."""
+    import test_oracle_render as tor
+    R = tor.rot_of(np.array([0.9, 0.2, -0.3, 0.1]))
+    cam = synth.Camera(640, 480, 530.0, 520.0, 318.5, 241.0, R=R, t=[0.3, -0.2, 1.1])
+    rgb, depth = synth.rgbd_frame(7)
+    compare(fgs, ctx, rgb, depth, cam, fgs.SeedOpts(D0=12.0, m=3, n=7, alpha_h=0.8, alpha_l=3.5, tile=8))
+
+
+@pytest.mark.parametrize("W,H", [(70, 50), (68, 34), (96, 60), (128, 96)])
+def test_ragged_and_odd_sizes(fgs, ctx, W, H):
+    """Frame sizes with factors 3, 5, 7 and 17, ragged 16x16 tiles."""
+    rgb, depth = synth.rgbd_frame(11, W, H, n_rect=6)
+    cam = synth.centred_camera(W, H, 60.0)
+    compare(fgs, ctx, rgb, depth, cam, fgs.SeedOpts(D0=6.0))
+
+
+def test_replica_sized_frame(fgs, ctx):
+    """1200x680 (680 = 2^3 5 17: a radix-17 pass)."""
+    rgb, depth = synth.rgbd_frame(5, 1200, 680, n_rect=60)
+    compare(fgs, ctx, rgb, depth, synth.camera_replica(), fgs.SeedOpts())
+
+
+def test_flat_frame_has_no_high_frequency(fgs, ctx):
+    W, H = 64, 48
+    rgb = np.full((3, H, W), 0.4, np.float32)
+    depth = np.full((H, W), 2.0, np.float32)
+    g, ref = compare(fgs, ctx, rgb, depth, synth.centred_camera(W, H, 60.0), fgs.SeedOpts(), check_margin=False)
+    assert ref["threshold"] == -1 and g["n"] == (W // 8) * (H // 8)
+
+
+def test_invalid_depth_and_capacity(fgs, ctx):
+    rgb, depth = synth.rgbd_frame(3, 128, 96, n_rect=8)
+    depth[:, :40] = np.nan
+    depth[50:60] = 0.0
+    cam = synth.centred_camera(128, 96, 100.0)
+    g, ref = compare(fgs, ctx, rgb, depth, cam, fgs.SeedOpts(D0=10.0))
+    with pytest.raises(fgs.FgsError) as e:
+        fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, fgs.SeedOpts(D0=10.0), capacity=ref["n"] - 1)
+    assert e.value.status == fgs.ERR_CAPACITY and f"{ref['n']} seeds" in str(e.value)
+
+
+def test_seeds_as_gaussians(fgs, ctx):
+    """The seeds written into a parameter block: mean, log(radius) on all axes, identity rotation,
+    the initial opacity logit, the pixel colour; the block renders to a non-empty image."""
+    import torch
+    rgb, depth = synth.rgbd_frame(1)
+    cam = synth.camera_tum()
+    opts = fgs.SeedOpts(opacity_logit=0.5)
+    cap = 80_000
+    params = torch.zeros((14, cap), dtype=torch.float32, device="cuda")
+    g = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, opts, capacity=cap, params=params)
+    n = g["n"]
+    p = host(params)
+    np.testing.assert_array_equal(p[0:3, :n], host(g["mean"])[:, :n])
+    np.testing.assert_allclose(p[3:6, :n], np.broadcast_to(np.log(host(g["radius"])[:n].astype(np.float64)), (3, n)),
+                               rtol=0, atol=2e-6)
+    np.testing.assert_array_equal(p[6, :n], 1.0)
+    np.testing.assert_array_equal(p[7:10, :n], 0.0)
+    np.testing.assert_array_equal(p[10, :n], np.float32(0.5))
+    np.testing.assert_array_equal(p[11:14, :n], host(g["rgb"])[:, :n])
+    out = fgs.render(ctx, params, n, cam, fgs.RenderOpts(), aux=True)
+    assert host(out["alpha"]).mean() > 0.5
