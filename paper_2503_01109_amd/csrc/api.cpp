@@ -887,9 +887,13 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     if (n_seeds_host) {
         if ((st = read_words(ctx)) != FGS_OK) return st;
         *n_seeds_host = ctx->host_words[ST_SEEDS];
-        if (*n_seeds_host > out->capacity)
+        if (*n_seeds_host > out->capacity) {
+            // reported here, so not again by the next fgs_ctx_check
+            HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_SEED_OVF, 0, 4, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
             return fail(ctx, FGS_ERR_CAPACITY, "%s: %lld seeds found, capacity %lld", w, (long long)*n_seeds_host,
                         (long long)out->capacity);
+        }
     }
     return FGS_OK;
 }

@@ -106,6 +106,7 @@ def test_invalid_depth_and_capacity(fgs, ctx):
     with pytest.raises(fgs.FgsError) as e:
         fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, fgs.SeedOpts(D0=10.0), capacity=ref["n"] - 1)
     assert e.value.status == fgs.ERR_CAPACITY and f"{ref['n']} seeds" in str(e.value)
+    ctx.check()  # reported once, by the call itself
 
 
 def test_seeds_as_gaussians(fgs, ctx):
