@@ -1,0 +1,93 @@
+"""Form 3: the autograd.Function over render_fwd/render_bwd, against the oracle gradient and
+against FP32 finite differences of a smooth configuration."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import assert_close_rel, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    need_gpu()
+    import torch
+
+    import paper_2503_01109_amd as F
+    from paper_2503_01109_amd import autograd as A
+    return F, A, torch
+
+
+def split(p, torch, requires_grad=True):
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda", requires_grad=requires_grad)
+    return t(p[0:3]), t(p[3:6]), t(p[6:10]), t(p[10]), t(p[11:14])
+
+
+def test_autograd_matches_oracle(mods):
+    F, A, torch = mods
+    p = synth.scene_small(3)
+    cam = synth.camera_small()
+    ref = oracle.render_fwd(p.astype(np.float64), cam, amb_rel=1e-5)
+    ok = ~ref["amb"]
+    g = synth.rng(77)
+    gr = g.normal(size=(3, cam.height, cam.width)) * ok
+    gd = g.normal(size=(cam.height, cam.width)) * ok
+    ga = g.normal(size=(cam.height, cam.width)) * ok
+    tens = split(p, torch)
+    rgb, depth, alpha = A.render(*tens, cam)
+    loss = (rgb * torch.tensor(gr, dtype=torch.float32, device="cuda")).sum() + \
+        (depth * torch.tensor(gd, dtype=torch.float32, device="cuda")).sum() + \
+        (alpha * torch.tensor(ga, dtype=torch.float32, device="cuda")).sum()
+    loss.backward()
+    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, ga)
+    got = np.concatenate([tens[0].grad.cpu().numpy(), tens[1].grad.cpu().numpy(), tens[2].grad.cpu().numpy(),
+                          tens[3].grad.cpu().numpy()[None], tens[4].grad.cpu().numpy()])
+    for rows in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11), slice(11, 14)):
+        assert_close_rel(got[rows], gref[rows], 1e-4, what=f"rows {rows}", floor=1e-2)
+    assert_close_rel(rgb.detach().cpu().numpy(), ref["rgb"], 1e-5, ok, "rgb")
+
+
+def test_autograd_matches_finite_differences(mods):
+    """FP32 central differences (relative step 1e-3) of L = sum g * render on a configuration made
+    smooth by wide cutoffs (sigma_cut 5, alpha_min 1e-7, T_min 1e-7), so no pair enters or leaves."""
+    F, A, torch = mods
+    cam = synth.Camera(32, 24, 30.0, 30.0, 16.0, 12.0)
+    g = synth.rng(5)
+    n = 6
+    p = np.zeros((14, n), np.float32)
+    p[2] = g.uniform(1.5, 2.5, n)
+    p[0] = g.uniform(-0.3, 0.3, n) * p[2]
+    p[1] = g.uniform(-0.2, 0.2, n) * p[2]
+    p[3:6] = g.normal(-2.0, 0.2, (3, n))
+    q = g.normal(size=(4, n)); p[6:10] = q / np.linalg.norm(q, axis=0)
+    p[10] = g.normal(-0.5, 0.5, n)
+    p[11:14] = g.uniform(0, 1, (3, n))
+    opts = F.RenderOpts(sigma_cut=5.0, alpha_min=1e-7, T_min=1e-7)
+    W = [torch.tensor(g.normal(size=s), dtype=torch.float64, device="cuda")
+         for s in ((3, cam.height, cam.width), (cam.height, cam.width), (cam.height, cam.width))]
+
+    def L(pp):
+        r, d, a = A.render(*split(pp, torch, requires_grad=False), cam, opts)
+        return float((r.double() * W[0]).sum() + (d.double() * W[1]).sum() + (a.double() * W[2]).sum())
+
+    tens = split(p, torch)
+    r, d, a = A.render(*tens, cam, opts)
+    ((r.double() * W[0]).sum() + (d.double() * W[1]).sum() + (a.double() * W[2]).sum()).backward()
+    got = np.concatenate([tens[0].grad.cpu().numpy(), tens[1].grad.cpu().numpy(), tens[2].grad.cpu().numpy(),
+                          tens[3].grad.cpu().numpy()[None], tens[4].grad.cpu().numpy()])
+    scale = np.abs(got).max()
+    checked = 0
+    for row in range(14):
+        for i in range(n):
+            if abs(got[row, i]) < 0.05 * scale:
+                continue
+            h = 1e-3 * max(1.0, abs(float(p[row, i])))
+            pp, pm = p.copy(), p.copy()
+            pp[row, i] += h
+            pm[row, i] -= h
+            fd = (L(pp) - L(pm)) / (float(pp[row, i]) - float(pm[row, i]))
+            assert abs(fd - got[row, i]) <= 1e-2 * abs(got[row, i]) + 1e-3 * scale, (row, i, fd, got[row, i])
+            checked += 1
+    assert checked >= 20
