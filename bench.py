@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=10, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
+                    help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -78,6 +81,14 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        x = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.add(x, 0.0, out=y)  # reads and writes exactly MB mebibytes each
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_mib": args.copy_calib}))
+        return
     tw, th = (int(v) for v in args.tile.split("x"))
     cam = synth.camera_replica()
     p = synth.scene_replica(0)
@@ -96,7 +107,9 @@ def main():
     ctx.check()
     torch.cuda.synchronize()
 
-    ctx.profile(True)
+    # timed region: HIP events around the two rasterizer kernels only (level 1), so the timing of
+    # the dominant kernel is live without breaking up the rest of the step
+    ctx.profile(1)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -108,8 +121,15 @@ def main():
     ms = e0.elapsed_time(e1)
     ctx.check()
     rep = ctx.profile_report()
-    ctx.profile(False)
     stats = ctx.stats()
+    # per-stage breakdown (events around every stage), from a short untimed continuation
+    ctx.profile(2)
+    brk = 10
+    for _ in range(brk):
+        F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
+    ctx.check()
+    rep2 = ctx.profile_report()
+    ctx.profile(0)
 
     steps = args.steps
     value = steps / (ms / 1e3)
@@ -121,8 +141,8 @@ def main():
         "raster_fwd": F_FWD_EXAMINED * E_f + F_FWD_BLENDED * E_c,
         "raster_bwd": F_BWD_BLENDED * E_c,
     }
-    stages = {k: v for k, v in rep.items() if k != "counts"}
-    kernel_ms = {k: (t / max(l, 1)) for k, (t, l) in stages.items()}
+    stages = {k: v for k, v in rep2.items() if k != "counts"}
+    kernel_ms = {k: (t / max(l, 1)) for k, (t, l) in rep.items() if k != "counts"}
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: kernel_ms[k])
     achieved = flops[dom] / (kernel_ms[dom] / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": f"k_raster_{dom.split('_')[1]}", "achieved": round(achieved, 3),
@@ -146,7 +166,7 @@ def main():
                                "fx=fy=600, depth 0.5-8 m", "n_gaussians": n, "width": cam.width,
                    "height": cam.height, "tile": args.tile, "parallelism": "single GPU"},
         "roofline": roofline,
-        "stages_ms_per_step": {k: round(t / steps, 4) for k, (t, l) in stages.items()},
+        "stages_ms_per_step": {k: round(t / brk, 4) for k, (t, l) in stages.items()},
         "pairs": {"tile_pairs": stats["pairs"], "examined_per_iter": E_f, "blended_per_iter": E_c,
                   "entries_staged_per_iter": cnt["entries_staged"] / fwd},
         "final_loss": float(loss), "final_psnr": float(psnr),

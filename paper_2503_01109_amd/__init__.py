@@ -226,9 +226,10 @@ class Context:
     STAGES = ("project", "depth_sort", "bin", "tile_sort", "raster_fwd", "loss", "raster_bwd", "project_bwd",
               "adam")
 
-    def profile(self, enable: bool = True):
-        """Start (clearing earlier records) or stop per-stage HIP-event timing and work counters."""
-        _check(_lib.fgs_ctx_profile(self._p, int(enable)), self._p)
+    def profile(self, level: int = 2):
+        """Start (clearing earlier records) or stop (0) HIP-event timing and work counters:
+        level 1 times the rasterizer kernels only, level 2 every pipeline stage."""
+        _check(_lib.fgs_ctx_profile(self._p, int(level)), self._p)
 
     def profile_report(self) -> dict:
         """{stage: (total_ms, launches)} plus 'counts': pairs examined, pairs blended, entries staged,

@@ -71,8 +71,8 @@ struct fgs_ctx {
     // host-mapped per-view pair counts of mapping steps: [2v] = pairs, [2v+1] = overflow flag
     uint32_t *ms_host = nullptr, *ms_host_dev = nullptr;
     std::vector<bool> ms_seen;
-    // profiling
-    bool prof = false;
+    // profiling: 0 off, 1 rasterizer kernels only, 2 every stage
+    int prof = 0;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
     std::vector<hipEvent_t> event_pool;  // reused by Stage
     DBuf prof_counts;  // 4 x u64
@@ -273,11 +273,12 @@ struct Stage {
     }
     Stage(fgs_ctx *c, const char *name) : ctx(c)
     {
-        if (!ctx->prof) return;
+        const bool raster = name[0] == 'r' && name[1] == 'a';  // raster_fwd, raster_bwd
+        if (ctx->prof < (raster ? 1 : 2)) return;
         a = take(ctx);
         b = take(ctx);
         if (!a || !b) {
-            ctx->prof = false;
+            ctx->prof = 0;
             return;
         }
         (void)hipEventRecord(a, ctx->stream);
@@ -387,12 +388,12 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     float *g2 = ctx->grad2d.as<float>();
     {
         Stage st_(ctx, "raster_bwd");
-        launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb, ddepth,
-                          dalpha, dscale, g2, g.n, s);
+        launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ids, sp.ranges, sp.last, sp.tfinal, drgb,
+                          ddepth, dalpha, dscale, g2, g.n, s);
     }
     {
         Stage st_(ctx, "project_bwd");
-        launch_project_bwd(to_pk(g), ck, rk, sp.ids, g2, to_gk(grad), accumulate, s);
+        launch_project_bwd(to_pk(g), ck, rk, g2, to_gk(grad), accumulate, s);
     }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -557,7 +558,7 @@ fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_profile: ctx is NULL");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     clear_profile(ctx);
-    ctx->prof = enable != 0;
+    ctx->prof = enable < 0 ? 0 : enable > 2 ? 2 : enable;
     if (ctx->prof && ctx->event_pool.size() < 4096) {
         // events for a few hundred steps up front, so the timed loop does not create any
         while (ctx->event_pool.size() < 4096) {

@@ -130,16 +130,17 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        unsigned long long *counts, hipStream_t s);
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
-// to a device float multiplying ddepth (the 1/P_v of the mean depth term).
+// to a device float multiplying ddepth (the 1/P_v of the mean depth term). grad2d: 10 planes of n,
+// indexed by gaussian id (ids maps depth rank -> id).
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint2 *ranges, const uint32_t *last, const float *tfinal,
+                       const uint32_t *ids, const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha,
                        const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s);
 
-// Chain rule from the 2D gradients (10 planes by depth rank) to the 14 parameter gradients of
+// Chain rule from the 2D gradients (10 planes by gaussian id) to the 14 parameter gradients of
 // every gaussian. accumulate: grad += (else grad =, for every gaussian). grad2d is left zeroed.
-void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
-                        float *grad2d, const GradK &grad, bool accumulate, hipStream_t s);
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,
+                        bool accumulate, hipStream_t s);
 
 // L1 loss of Eq. 16 (colour + depth terms) with its gradient; partials is scratch of
 // loss_partials_size(P) floats; writes loss/psnr device scalars (nullable) and the depth-gradient

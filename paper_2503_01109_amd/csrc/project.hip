@@ -155,31 +155,28 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
     rect[i] = rc;
 }
 
-// Backward of the projection for the gaussian of depth rank r (one thread each). grad2d holds
-// 10 planes of length n indexed by depth rank: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b;
-// depth); each thread zeroes the slots it read, so grad2d is all-zero again for the next
-// backward. The 14 parameter gradients are added to grad (accumulate) or written to it (each
-// gaussian has one rank, so no atomics are needed).
+// Backward of the projection, one thread per gaussian. grad2d holds 10 planes of length n
+// indexed by gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
+// zeroes the slots it read, so grad2d is all-zero again for the next backward. The 14 parameter
+// gradients are added to grad (accumulate) or written to it. Every access is coalesced.
 __global__ void __launch_bounds__(256)
-k_project_bwd(ParamsK g, CamK cam, RasterK rk, const uint32_t *__restrict__ ids, float *__restrict__ grad2d,
-              GradK grad, int accumulate)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad, int accumulate)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
-    if (r >= n) return;
+    if (i >= n) return;
     double g2[10];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
-        g2[k] = grad2d[k * n + r];
+        g2[k] = grad2d[k * n + i];
         any |= g2[k] != 0.0;
     }
-    const int64_t i = ids[r];
     const int64_t S = grad.stride;
     Proj p;
     if (any) {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) grad2d[k * n + r] = 0.0f;
+        for (int k = 0; k < 10; ++k) grad2d[k * n + i] = 0.0f;
         project_gaussian(g, i, cam, rk.lowpass, p);
     }
     if (!any || !p.valid) {
@@ -291,12 +288,12 @@ void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *r
                        dkey, ids, n_out);
 }
 
-void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, const uint32_t *ids,
-                        float *grad2d, const GradK &grad, bool accumulate, hipStream_t s)
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,
+                        bool accumulate, hipStream_t s)
 {
     if (g.n <= 0) return;
     const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, ids, grad2d, grad,
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, grad2d, grad,
                        (int)accumulate);
 }
 

@@ -231,7 +231,7 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW *TH)
 k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
-             const uint2 *__restrict__ ranges, const uint32_t *__restrict__ last_in,
+             const uint32_t *__restrict__ ids, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ last_in,
              const float *__restrict__ tfinal_in, const float *__restrict__ drgb, const float *__restrict__ ddepth,
              const float *__restrict__ dalpha, const float *__restrict__ ddepth_scale, float *__restrict__ grad2d,
              int64_t n)
@@ -291,7 +291,7 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
-            srank[tid] = r;
+            srank[tid] = ids[r];  // gradients are accumulated by gaussian id
             smask[tid] = (uint8_t)strip_mask<TW, TH>(a4, b4, cut2);
         }
         __syncthreads();
@@ -388,13 +388,13 @@ void fwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32
 }
 
 template <int TW, int TH>
-void bwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint2 *ranges,
-           const uint32_t *last, const float *tfinal, const float *drgb, const float *ddepth, const float *dalpha,
-           const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s)
+void bwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint32_t *ids,
+           const uint2 *ranges, const uint32_t *last, const float *tfinal, const float *drgb, const float *ddepth,
+           const float *dalpha, const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s)
 {
     const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
-    hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ranges, last,
-                       tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n);
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ids, ranges,
+                       last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n);
 }
 
 }  // namespace
@@ -423,12 +423,12 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 }
 
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint2 *ranges, const uint32_t *last, const float *tfinal, const float *drgb,
-                       const float *ddepth, const float *dalpha, const float *ddepth_scale, float *grad2d, int64_t n,
-                       hipStream_t s)
+                       const uint32_t *ids, const uint2 *ranges, const uint32_t *last, const float *tfinal,
+                       const float *drgb, const float *ddepth, const float *dalpha, const float *ddepth_scale,
+                       float *grad2d, int64_t n, hipStream_t s)
 {
 #define FGS_CALL_BWD(a, b) \
-    bwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n, s)
+    bwd_t<a, b>(rk, W, H, rec, vals, ids, ranges, last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n, s)
     FGS_TILE_SWITCH(FGS_CALL_BWD)
 #undef FGS_CALL_BWD
 }
