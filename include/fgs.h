@@ -205,6 +205,32 @@ fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const f
 fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad,
                          fgs_adam *opt);
 
+/* ------------------------------------ keyframe window ------------------------------------ */
+
+typedef struct fgs_window fgs_window; /* opaque: per-view states, work queue, captured graph */
+
+/* A keyframe window (Sec. III-D, III-E: the co-visible and random keyframes optimised together)
+ * of n_views cameras ([host] array, copied) that may differ in size. tiles ([host], 2 ints per
+ * view: tile_w, tile_h; NULL = 16x16) picks each view's rasterizer tile among 16x16, 32x8 and
+ * 8x32; blocks_per_cu sizes the persistent rasterizer grid (0 = 4 per compute unit). The window
+ * keeps its own stream for graph capture and orders it against the context's stream. */
+fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *cams, const int32_t *tiles,
+                             int32_t blocks_per_cu, fgs_window **out);
+fgs_status fgs_window_destroy(fgs_window *w);
+
+/* One mapping iteration over the window, with the semantics of fgs_map_step: every view is
+ * binned and ordered, all views' tiles are rendered (Eq. 1) by ONE persistent launch pulling
+ * (view, tile) items longest list first, the L1 terms of Eq. 15 are taken per view, ONE persistent
+ * launch runs every view's backward, and one pass per gaussian sums the views' gradients through
+ * their projections and applies Adam. targets: [host] array of n_views. use_graph != 0 captures
+ * the step in a hipGraph on its first call and replays it afterwards (re-captured when a pointer,
+ * n, an option or the profiling level changes). The first call for a given n sizes the per-view
+ * states from a synchronous pair count (50% headroom); a later step that outgrows a state is
+ * reported by the next call with FGS_ERR_CAPACITY after the window has grown. */
+fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam *opt, const fgs_target *targets,
+                           const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev, float *psnr_dev,
+                           const fgs_gaussians *grad_out, int32_t use_graph);
+
 /* ------------------------------ Fourier seeding (Sec. III-A) ------------------------------ */
 
 /* [host] Seeding constants. D0: cutoff radius of the Gaussian high-pass of Eq. 5, in frequency
@@ -212,8 +238,9 @@ fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_ga
  * square tiles of the per-tile seed count. alpha_h, alpha_l: radius factors of Eq. 11 (a seed's
  * radius is alpha d / fx, alpha pixels at its depth). opacity_logit: initial opacity logit.
  * Seeds need a finite depth in [depth_min, depth_max]. use_prior = 1 replaces the radius rule and
- * the constant opacity of the emitted gaussians by the learned prior (fgs_prior.h) whose packed
- * weights `prior` points to (device). */
+ * the constant opacity of the gaussians written into out->params (required then) by the learned
+ * prior of fgs_prior.h, evaluated on the frame's 16x16 tiles, whose packed FP32 weights `prior`
+ * points to (device); the seed set and the seed arrays are unchanged. */
 typedef struct {
     double D0;
     int32_t m, n, tile;
@@ -231,7 +258,8 @@ typedef struct {
  * [0, count): the mean, log-scale log(radius) on all axes, identity rotation, the initial opacity
  * logit and the pixel colour (params.stride >= capacity). E (width*height doubles: |I_h|), hist
  * (256 uint32: histogram of q = floor(255 E / E_max)) and threshold (one int32: the triangle
- * threshold, -1 for a flat frame) are optional diagnostics. */
+ * threshold, -1 for a flat frame) are optional diagnostics. With the learned prior, from_prior
+ * (capacity bytes, nullable) marks the seeds whose shape and opacity came from the prior. */
 typedef struct {
     int64_t capacity;
     int32_t *pixel;
@@ -245,6 +273,7 @@ typedef struct {
     double *E;
     uint32_t *hist;
     int32_t *threshold;
+    uint8_t *from_prior;
 } fgs_seed_out;
 
 /* Seeds gaussians from one RGB-D frame (rgb: 3 planes, depth: 1 plane, width*height of cam) by the

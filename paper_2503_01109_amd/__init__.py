@@ -84,7 +84,12 @@ class CSeedOut(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("pixel", _i32p), ("is_high", C.POINTER(C.c_uint8)), ("mean", _fp),
                 ("radius", _fp), ("rgb", _fp), ("tile_count", _i32p), ("n_dev", C.POINTER(C.c_int64)),
                 ("params", CGaussians), ("E", C.POINTER(C.c_double)), ("hist", C.POINTER(C.c_uint32)),
-                ("threshold", _i32p)]
+                ("threshold", _i32p), ("from_prior", C.POINTER(C.c_uint8))]
+
+
+class CPriorAdam(C.Structure):
+    _fields_ = [("m", _fp), ("v", _fp), ("step", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 _vp = C.c_void_p
@@ -108,6 +113,14 @@ _sigs = {
     "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
     "fgs_ctx_profile_counts": [_vp, _P(C.c_int64)],
     "fgs_seed_gaussians": [_vp, _fp, _fp, _P(CCamera), _P(CSeedOpts), _P(CSeedOut), _P(C.c_int64)],
+    "fgs_tile_features": [_vp, _fp, _fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_int64, _P(C.c_int32), _fp,
+                          _P(C.c_int32)],
+    "fgs_prior_forward": [_vp, C.c_int64, _fp, _fp, _fp],
+    "fgs_prior_train_step": [_vp, C.c_int64, _fp, _fp, _fp, _P(CPriorAdam), _fp, _fp],
+    "fgs_window_create": [_vp, C.c_int32, _P(CCamera), _P(C.c_int32), C.c_int32, _P(_vp)],
+    "fgs_window_destroy": [_vp],
+    "fgs_window_step": [_vp, _P(CGaussians), _P(CAdam), _P(CTarget), _P(CRenderOpts), _P(CLossOpts), _fp, _fp,
+                        _P(CGaussians), C.c_int32],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -320,6 +333,51 @@ def map_step(ctx: Context, params, n: int, adam: Adam, cams, targets, opts: Rend
     adam.step = ca.step
 
 
+class Window:
+    """A keyframe window (fgs_window): n views of possibly different sizes mapped together, every
+    view's tiles rendered by one persistent launch and back-propagated by another, the gradients
+    summed per gaussian and Adam applied in one pass; optionally captured in a hipGraph."""
+
+    def __init__(self, ctx: Context, cams, tiles=None, blocks_per_cu: int = 0):
+        V = len(cams)
+        ccams = (CCamera * V)(*[camera(c) for c in cams])
+        ct = None
+        if tiles is not None:
+            flat = [int(x) for t in tiles for x in t]
+            ct = (C.c_int32 * len(flat))(*flat)
+        p = C.c_void_p()
+        _check(_lib.fgs_window_create(ctx.handle, V, ccams, ct, int(blocks_per_cu), C.byref(p)), ctx.handle)
+        self._p, self.ctx, self.n_views = p, ctx, V
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.fgs_window_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, params, n: int, adam: Adam, targets, opts: RenderOpts, loss_opts: LossOpts | None = None,
+             loss=None, psnr=None, grad_out=None, graph: bool = True):
+        """One mapping iteration over the window. targets: list of (rgb (3,H,W), depth (H,W));
+        loss / psnr: optional float32 device tensors of n_views entries."""
+        if len(targets) != self.n_views:
+            raise ValueError(f"window has {self.n_views} views, got {len(targets)} targets")
+        for t in (loss, psnr):
+            if t is not None and t.numel() < self.n_views:
+                raise ValueError("loss / psnr need one entry per view")
+        ctg = (CTarget * self.n_views)(*[CTarget(_f32(r), _f32(d)) for r, d in targets])
+        ca = adam.c(n)
+        _check(_lib.fgs_window_step(self._p, C.byref(gaussians(params, n)), C.byref(ca), ctg, C.byref(opts.c()),
+                                    C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
+                                    None if grad_out is None else C.byref(gaussians(grad_out, n)), int(bool(graph))),
+               self.ctx.handle)
+        adam.step = ca.step
+
+
 def loss_l1(ctx: Context, rgb, depth, target_rgb, target_depth, loss_opts: LossOpts | None, dL_drgb, dL_ddepth,
             loss=None, psnr=None):
     tg = CTarget(_f32(target_rgb), _f32(target_depth))
@@ -433,9 +491,66 @@ def seed_gaussians(ctx: Context, rgb, depth, cam, opts: SeedOpts | None = None, 
     if diagnostics:
         out.E, out.hist = _ptr(r["E"], C.POINTER(C.c_double)), _ptr(r["hist"], C.POINTER(C.c_uint32))
         out.threshold = _ptr(r["threshold"], _i32p)
+    if o.use_prior:
+        r["from_prior"] = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        out.from_prior = _ptr(r["from_prior"], C.POINTER(C.c_uint8))
     n = C.c_int64(-1)
     _check(_lib.fgs_seed_gaussians(ctx.handle, _f32(rgb), _f32(depth), C.byref(camera(cam)), C.byref(o.c()),
                                    C.byref(out), C.byref(n) if sync else None), ctx.handle)
     r["n"] = n.value
     r["capacity"] = cap
     return r
+
+
+# ------------------------------------- learned prior -------------------------------------
+
+PRIOR_INPUTS, PRIOR_HIDDEN, PRIOR_OUTPUTS, PRIOR_PARAMS = 260, 256, 4, 133636
+
+
+def tile_features(ctx: Context, rgb, depth, depth_min: float = 0.1, depth_max: float = 10.0, tile_ids=None):
+    """Features of 16x16 tiles of a frame (rgb (3,H,W), depth (H,W)): ([T, 260] float32, [T] int32
+    valid-depth counts). tile_ids: optional int32 device tensor of row-major tile indices."""
+    import torch
+    H, W = int(depth.shape[0]), int(depth.shape[1])
+    T = int(tile_ids.numel()) if tile_ids is not None else ((W + 15) // 16) * ((H + 15) // 16)
+    feat = torch.empty((T, PRIOR_INPUTS), dtype=torch.float32, device=depth.device)
+    valid = torch.empty(T, dtype=torch.int32, device=depth.device)
+    _check(_lib.fgs_tile_features(ctx.handle, _f32(rgb), _f32(depth), W, H, depth_min, depth_max, T,
+                                  _ptr(tile_ids, C.POINTER(C.c_int32)), _f32(feat),
+                                  _ptr(valid, C.POINTER(C.c_int32))), ctx.handle)
+    return feat, valid
+
+
+def prior_forward(ctx: Context, x, weights, y=None):
+    """y [rows, 4] = network(x [rows, 260]) with packed FP32 weights (PRIOR_PARAMS)."""
+    import torch
+    rows = int(x.shape[0])
+    if y is None:
+        y = torch.empty((rows, PRIOR_OUTPUTS), dtype=torch.float32, device=x.device)
+    _check(_lib.fgs_prior_forward(ctx.handle, rows, _f32(x), _f32(weights), _f32(y)), ctx.handle)
+    return y
+
+
+@dataclass
+class PriorAdam:
+    """Adam state of the prior's packed weights."""
+    m: object
+    v: object
+    step: int = 0
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    @staticmethod
+    def like(weights, **kw):
+        import torch
+        return PriorAdam(torch.zeros_like(weights), torch.zeros_like(weights), **kw)
+
+
+def prior_train_step(ctx: Context, x, target, weights, adam: PriorAdam, loss=None, grad_out=None):
+    """One Adam step of the network on the MSE against target [rows, 4] (weights updated in place)."""
+    a = CPriorAdam(_f32(adam.m), _f32(adam.v), adam.step, adam.lr, adam.beta1, adam.beta2, adam.eps)
+    _check(_lib.fgs_prior_train_step(ctx.handle, int(x.shape[0]), _f32(x), _f32(target), _f32(weights), C.byref(a),
+                                     _f32(loss), _f32(grad_out)), ctx.handle)
+    adam.step = a.step

@@ -2,6 +2,8 @@
 // forward, backward and mapping-step pipelines. See include/fgs.h for the contract of every call.
 #include "fgs.h"
 #include "fgs_internal.h"
+#include "fgs_prior.h"
+#include "mlp_internal.h"
 #include "seed_internal.h"
 
 #include <math.h>
@@ -9,13 +11,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <utility>
 #include <vector>
 
 namespace fgs {
-bool tile_supported(int tw, int th);
 void launch_scale(float *x, int64_t n, const float *s, hipStream_t st);
 }  // namespace fgs
 
@@ -66,11 +68,16 @@ struct fgs_ctx {
     // mapping-step buffers
     DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
     DBuf seed_ws, seed_sc;
+    // learned prior: network workspace (rows_cap rows) and per-frame tile buffers for seeding
+    DBuf mlp_ws, prior_feat, prior_valid, prior_y;
+    int64_t mlp_rows = 0;
     int64_t ms_cap = 0;
     uint32_t *host_words = nullptr;  // pinned copy of the status words
     // host-mapped per-view pair counts of mapping steps: [2v] = pairs, [2v+1] = overflow flag
     uint32_t *ms_host = nullptr, *ms_host_dev = nullptr;
     std::vector<bool> ms_seen;
+    std::vector<fgs_camera> ms_cams;  // camera last run at each view index
+    int64_t ms_n = -1;                // gaussian count of the last step
     // profiling: 0 off, 1 rasterizer kernels only, 2 every stage
     int prof = 0;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
@@ -312,12 +319,64 @@ void clear_profile(fgs_ctx *ctx, bool destroy = false)
 
 fgs_status read_words(fgs_ctx *ctx);
 
+// Network workspace for at least `rows` rows (grown on the context's stream, after it drained).
+fgs_status ensure_mlp(fgs_ctx *ctx, int64_t rows)
+{
+    if (rows <= ctx->mlp_rows && ctx->mlp_ws.p) return FGS_OK;
+    const int64_t r = std::max<int64_t>(rows, std::max<int64_t>(ctx->mlp_rows, 64));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, ctx->mlp_ws.ensure(mlp_ws_bytes(r)));
+    ctx->mlp_rows = r;
+    return FGS_OK;
+}
+
+// Unit quaternion (w, x, y, z) of the camera-to-world rotation R_cw^T, so that a gaussian with
+// this rotation has its local axes along the camera's x, y and viewing axes.
+void camera_to_world_quat(const float R_cw[9], float q[4])
+{
+    double m[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) m[i][j] = R_cw[j * 3 + i];  // transpose
+    const double tr = m[0][0] + m[1][1] + m[2][2];
+    double w, x, y, z;
+    if (tr > 0) {
+        const double s = 2.0 * sqrt(tr + 1.0);
+        w = 0.25 * s;
+        x = (m[2][1] - m[1][2]) / s;
+        y = (m[0][2] - m[2][0]) / s;
+        z = (m[1][0] - m[0][1]) / s;
+    } else if (m[0][0] > m[1][1] && m[0][0] > m[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + m[0][0] - m[1][1] - m[2][2]);
+        w = (m[2][1] - m[1][2]) / s;
+        x = 0.25 * s;
+        y = (m[0][1] + m[1][0]) / s;
+        z = (m[0][2] + m[2][0]) / s;
+    } else if (m[1][1] > m[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + m[1][1] - m[0][0] - m[2][2]);
+        w = (m[0][2] - m[2][0]) / s;
+        x = (m[0][1] + m[1][0]) / s;
+        y = 0.25 * s;
+        z = (m[1][2] + m[2][1]) / s;
+    } else {
+        const double s = 2.0 * sqrt(1.0 + m[2][2] - m[0][0] - m[1][1]);
+        w = (m[1][0] - m[0][1]) / s;
+        x = (m[0][2] + m[2][0]) / s;
+        y = (m[1][2] + m[2][1]) / s;
+        z = 0.25 * s;
+    }
+    const double nrm = sqrt(w * w + x * x + y * y + z * z);
+    q[0] = (float)(w / nrm);
+    q[1] = (float)(x / nrm);
+    q[2] = (float)(y / nrm);
+    q[3] = (float)(z / nrm);
+}
+
 // Enqueue the forward pipeline into a state with layout L. With K_check, the call waits for the
 // pair count after the scan and, when it exceeds the state's capacity, returns FGS_ERR_CAPACITY
 // with the count in *K_check before enqueueing the rest.
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
-                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr)
+                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true)
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
@@ -364,7 +423,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
                                            key_bits_for(L.T), sort_ws(ctx, L.cap), s);
         launch_ranges(keys, npairs, L.cap, sp.ranges, L.T, s);
     }
-    {
+    if (raster) {
         Stage st_(ctx, "raster_fwd");
         launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img,
                           prof_counts(ctx), s);
@@ -758,6 +817,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         memset(ctx->ms_host, 0, 2 * 4096 * 4);
         HIP_TRY(ctx, hipHostGetDevicePointer((void **)&ctx->ms_host_dev, ctx->ms_host, 0));
         ctx->ms_seen.assign(4096, false);
+        ctx->ms_cams.assign(4096, fgs_camera{});
     }
     // A step whose pair count outgrew the state while running unchecked is reported here, once:
     // the state is grown and the caller learns that the earlier step used an incomplete gradient.
@@ -768,6 +828,9 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             const int64_t K = hs[0];
             hs[1] = 0;
             if (K + K / 4 + 1024 > ctx->ms_cap) ctx->ms_cap = K + K / 4 + 1024;
+            // the context's overflow word saw the same event; this report replaces it
+            HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, s));
+            HIP_TRY(ctx, hipStreamSynchronize(s));
             return fail(ctx, FGS_ERR_CAPACITY,
                         "%s: an earlier step needed %lld (tile, gaussian) pairs in view %d; the state was grown", w,
                         (long long)K, v);
@@ -799,17 +862,21 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
             // The pair count is data dependent. A view is checked synchronously (the forward waits
             // for the count after the scan and restarts with a larger state when it does not fit)
-            // the first time it is seen and whenever its last observed count came within 10% of the
-            // capacity; otherwise it runs without a host round trip and an overflow is caught by the
-            // flag above on the next call.
-            const bool seen = v < 4096 && ctx->ms_seen[v];
+            // the first time it is seen (a new index, camera or gaussian count) and whenever its last
+            // observed count came within 10% of the capacity; otherwise it runs without a host round
+            // trip and an overflow is caught by the flag above on the next call.
+            const bool seen = v < 4096 && ctx->ms_seen[v] && n == ctx->ms_n &&
+                              memcmp(&ctx->ms_cams[v], &cam, sizeof(fgs_camera)) == 0;
             const int64_t K_obs = v < 4096 ? (int64_t)((volatile uint32_t *)ctx->ms_host)[2 * v] : 0;
             const bool checked = !seen || K_obs * 10 > ctx->ms_cap * 9;
             int64_t K = 0;
             st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, checked ? &K : nullptr,
                                  hs_dev);
             if (st == FGS_OK) {
-                if (v < 4096) ctx->ms_seen[v] = true;
+                if (v < 4096) {
+                    ctx->ms_seen[v] = true;
+                    ctx->ms_cams[v] = cam;
+                }
                 // keep 50% headroom above a count seen within 20% of the capacity (the larger state
                 // is allocated before the next step's forward)
                 if (checked && K * 5 > ctx->ms_cap * 4) ctx->ms_cap = K + K / 2 + 1024;
@@ -830,6 +897,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
                                    grad, v > 0)) != FGS_OK)
             return st;
     }
+    ctx->ms_n = n;
     enqueue_adam(ctx, *params, grad, opt);
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -849,7 +917,9 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     if (!isfinite(o->alpha_h) || !isfinite(o->alpha_l) || !isfinite(o->opacity_logit) ||
         !(o->depth_min <= o->depth_max))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: radius factors, opacity or depth range invalid", w);
-    if (o->use_prior) return fail(ctx, FGS_ERR_UNSUPPORTED, "%s: the learned prior is not built into this call", w);
+    if (o->use_prior && !o->prior) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior without weights", w);
+    if (o->use_prior && !out->params.mean)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior needs out->params (the prior writes gaussians)", w);
     if (!out || out->capacity < 0 || (out->capacity > 0 && (!out->pixel || !out->is_high || !out->mean ||
                                                             !out->radius || !out->rgb)))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: seed output incomplete", w);
@@ -884,6 +954,33 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     launch_seed(rgb, depth, W, H, o->D0, sk, so, ctx->seed_ws.p, sc, status_words(ctx), ctx->stream);
     if (out->threshold)
         HIP_TRY(ctx, hipMemcpyAsync(out->threshold, &sc->thresh, 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (o->use_prior && out->capacity > 0) {
+        const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+        const int64_t T = (int64_t)tx * ty;
+        if ((st = ensure_mlp(ctx, T)) != FGS_OK) return st;
+        HIP_TRY(ctx, ctx->prior_feat.ensure((size_t)T * kMlpIn * 4));
+        HIP_TRY(ctx, ctx->prior_valid.ensure((size_t)T * 4));
+        HIP_TRY(ctx, ctx->prior_y.ensure((size_t)T * kMlpOut * 4));
+        MlpWS ws;
+        mlp_ws_carve(ctx->mlp_ws.p, ctx->mlp_rows, &ws);
+        launch_tile_features(rgb, depth, W, H, o->depth_min, o->depth_max, T, nullptr, ctx->prior_feat.as<float>(),
+                             ctx->prior_valid.as<int32_t>(), ctx->stream);
+        launch_mlp_forward(ws, T, ctx->prior_feat.as<float>(), (const float *)o->prior, ctx->prior_y.as<float>(),
+                           false, ctx->stream);
+        PriorApplyK pk;
+        pk.tiles_x = tx;
+        pk.W = W;
+        pk.fx = cam->fx;
+        pk.alpha_h = o->alpha_h;
+        pk.alpha_l = o->alpha_l;
+        pk.max_dev = (float)log(4.0);
+        pk.min_valid = 4;
+        camera_to_world_quat(cam->R_cw, pk.q);
+        const int64_t S = out->params.stride;
+        launch_prior_apply(pk, seed_count_ptr(ctx->seed_ws.p, W, H), out->capacity, out->pixel, out->is_high, depth,
+                           ctx->prior_y.as<float>(), ctx->prior_valid.as<int32_t>(), out->params.log_scale,
+                           out->params.quat, out->params.opacity_logit, S, out->from_prior, ctx->stream);
+    }
     HIP_TRY(ctx, hipGetLastError());
     if (n_seeds_host) {
         if ((st = read_words(ctx)) != FGS_OK) return st;
@@ -896,6 +993,505 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
                         (long long)out->capacity);
         }
     }
+    return FGS_OK;
+}
+
+/* ------------------------------------ learned prior ------------------------------------ */
+
+fgs_status fgs_tile_features(fgs_ctx *ctx, const float *rgb, const float *depth, int32_t width, int32_t height,
+                             float depth_min, float depth_max, int64_t n_tiles, const int32_t *tile_ids, float *feat,
+                             int32_t *n_valid)
+{
+    const char *w = "fgs_tile_features";
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: image size %dx%d outside [1, 16384]", w, width, height);
+    if (n_tiles < 0 || n_tiles > ((int64_t)1 << 31) - 1) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_tiles", w);
+    if (n_tiles > 0 && (!rgb || !depth || !feat)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: NULL plane", w);
+    if (!tile_ids && n_tiles > (int64_t)((width + 15) / 16) * ((height + 15) / 16))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: more tiles than the frame has", w);
+    if (!(depth_min <= depth_max)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: depth range", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    launch_tile_features(rgb, depth, width, height, depth_min, depth_max, n_tiles, tile_ids, feat, n_valid,
+                         ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status fgs_prior_forward(fgs_ctx *ctx, int64_t rows, const float *x, const float *weights, float *y)
+{
+    const char *w = "fgs_prior_forward";
+    if (rows < 0 || rows > ((int64_t)1 << 24)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: rows outside [0, 2^24]", w);
+    if (rows > 0 && (!x || !weights || !y)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: NULL argument", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    if (rows == 0) return FGS_OK;
+    fgs_status st;
+    if ((st = ensure_mlp(ctx, rows)) != FGS_OK) return st;
+    MlpWS ws;
+    mlp_ws_carve(ctx->mlp_ws.p, ctx->mlp_rows, &ws);
+    launch_mlp_forward(ws, rows, x, weights, y, false, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status fgs_prior_train_step(fgs_ctx *ctx, int64_t rows, const float *x, const float *target, float *weights,
+                                fgs_prior_adam *opt, float *loss_dev, float *grad_out)
+{
+    const char *w = "fgs_prior_train_step";
+    if (rows <= 0 || rows > ((int64_t)1 << 24)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: rows outside [1, 2^24]", w);
+    if (!x || !target || !weights) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: NULL argument", w);
+    if (!opt || !opt->m || !opt->v) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: Adam state incomplete", w);
+    if (opt->step < 0 || !isfinite(opt->lr) || !(opt->beta1 >= 0 && opt->beta1 < 1) ||
+        !(opt->beta2 >= 0 && opt->beta2 < 1) || !(opt->eps >= 0))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: Adam hyper-parameters", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    fgs_status st;
+    if ((st = ensure_mlp(ctx, rows)) != FGS_OK) return st;
+    MlpWS ws;
+    mlp_ws_carve(ctx->mlp_ws.p, ctx->mlp_rows, &ws);
+    const double k = (double)(opt->step + 1);
+    const float bc1 = (float)(1.0 - pow((double)opt->beta1, k));
+    const float bc2 = (float)(1.0 - pow((double)opt->beta2, k));
+    launch_mlp_train_step(ws, rows, x, target, weights, opt->m, opt->v, opt->lr, opt->beta1, opt->beta2, opt->eps,
+                          bc1, bc2, loss_dev, grad_out, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    opt->step += 1;
+    return FGS_OK;
+}
+
+}  // extern "C"
+
+/* ------------------------------------ keyframe window ------------------------------------ */
+
+struct fgs_window {
+    fgs_ctx *ctx = nullptr;
+    int nv = 0;
+    std::vector<fgs_camera> cams;
+    std::vector<int> tw, th;
+    int blocks = 0;
+    int64_t n = -1;
+    std::vector<int64_t> cap;
+    std::vector<StateLayout> L;
+    std::vector<DBuf> state;
+    std::vector<int64_t> pix_off;  // float offset of view v's 4 planes in img and dl
+    std::vector<uint32_t> tile_base;
+    uint32_t total_tiles = 0;
+    DBuf img, dl, grad2d, views, cams_dev, qka, qva, qkb, qvb, queue, words, partials;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> sig;        // what the captured graph baked in
+    std::vector<uintptr_t> table_sig;  // what the device view table was built from
+    ViewK *views_host = nullptr;       // pinned, rewritten only after the window stream drained
+    CamK *cams_host = nullptr;
+    int64_t *step_host = nullptr;      // pinned staging of the device Adam step counter
+    int64_t dev_step = -1;             // value of the device counter once enqueued work is done
+    uint32_t *hs = nullptr, *hs_dev = nullptr;  // host-mapped: [2v] pairs, [2v+1] overflow of view v
+};
+
+namespace {
+
+// device words of a window: queue counter, queue length, Adam step (int64), per-view 1/P_v
+constexpr int WW_COUNTER = 0, WW_TOTAL = 1, WW_STEP = 2, WW_DSCALE = 4;
+
+void window_drop_graph(fgs_window *w)
+{
+    if (w->exec) (void)hipGraphExecDestroy(w->exec);
+    if (w->graph) (void)hipGraphDestroy(w->graph);
+    w->exec = nullptr;
+    w->graph = nullptr;
+    w->sig.clear();
+}
+
+float *view_img(fgs_window *w, int v) { return w->img.as<float>() + w->pix_off[v]; }
+float *view_dl(fgs_window *w, int v) { return w->dl.as<float>() + w->pix_off[v]; }
+
+// Size every view's state from a synchronous pair count (50% headroom) for this n.
+fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_render_opts &o)
+{
+    fgs_ctx *ctx = w->ctx;
+    const int64_t n = params.n;
+    fgs_status st;
+    if ((st = ensure_ws(ctx, std::max<int64_t>(n, w->total_tiles), 0)) != FGS_OK) return st;
+    for (int v = 0; v < w->nv; ++v) {
+        const fgs_camera &cam = w->cams[v];
+        const int64_t P = (int64_t)cam.width * cam.height;
+        int64_t cap = std::max<int64_t>(w->cap[v], std::max<int64_t>(n * 8, (int64_t)1 << 20));
+        for (int attempt = 0;; ++attempt) {
+            state_layout(n, cam.width, cam.height, w->tw[v], w->th[v], cap, &w->L[v]);
+            HIP_TRY(ctx, w->state[v].ensure(w->L[v].bytes));
+            float *im = view_img(w, v);
+            ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
+            int64_t K = 0;
+            st = enqueue_forward(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v], &K, nullptr,
+                                 false);
+            if (st == FGS_OK || st == FGS_ERR_CAPACITY) {
+                if (st == FGS_ERR_CAPACITY && attempt > 0) return fail(ctx, st, "fgs_window_step: sizing failed");
+                w->cap[v] = std::max<int64_t>(w->cap[v], K + K / 2 + 1024);
+                if (st == FGS_OK) break;
+                cap = w->cap[v];
+                continue;
+            }
+            return st;
+        }
+        state_layout(n, cam.width, cam.height, w->tw[v], w->th[v], w->cap[v], &w->L[v]);
+        HIP_TRY(ctx, w->state[v].ensure(w->L[v].bytes));
+    }
+    int64_t capmax = 0;
+    for (int v = 0; v < w->nv; ++v) capmax = std::max(capmax, w->cap[v]);
+    if ((st = ensure_ws(ctx, std::max<int64_t>(n, w->total_tiles), capmax)) != FGS_OK) return st;
+    const size_t g2 = (size_t)w->nv * 10 * (size_t)(n > 0 ? n : 1) * 4;
+    HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+    HIP_TRY(ctx, w->grad2d.ensure(g2));
+    HIP_TRY(ctx, hipMemset(w->grad2d.p, 0, g2));  // the backward keeps it all-zero between steps
+    w->n = n;
+    window_drop_graph(w);
+    w->table_sig.clear();
+    return FGS_OK;
+}
+
+// Build and upload the device table of views (pointers, shapes, options) when it changed.
+fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_render_opts &o)
+{
+    fgs_ctx *ctx = w->ctx;
+    std::vector<uintptr_t> sig = {(uintptr_t)params.n, (uintptr_t)ctx->prof};
+    uint32_t ob[sizeof(fgs_render_opts) / 4];
+    memcpy(ob, &o, sizeof(ob));
+    for (uint32_t x : ob) sig.push_back(x);
+    for (int v = 0; v < w->nv; ++v) sig.push_back((uintptr_t)w->state[v].p);
+    if (sig == w->table_sig) return FGS_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // earlier copies out of the pinned tables are done
+    const int64_t n = params.n;
+    for (int v = 0; v < w->nv; ++v) {
+        const fgs_camera &cam = w->cams[v];
+        const int64_t P = (int64_t)cam.width * cam.height;
+        const StatePtrs sp = state_ptrs(w->state[v].p, w->L[v]);
+        ViewK V = {};
+        V.rk = to_rk(o, w->tw[v], w->th[v], cam.width, cam.height);
+        V.W = cam.width;
+        V.H = cam.height;
+        V.rec = sp.rec;
+        V.vals = sp.vals;
+        V.ids = sp.ids;
+        V.ranges = sp.ranges;
+        V.last = sp.last;
+        V.tfinal = sp.tfinal;
+        V.img = ImageK{view_img(w, v), view_img(w, v) + 3 * P, nullptr, nullptr, nullptr};
+        V.drgb = view_dl(w, v);
+        V.ddepth = view_dl(w, v) + 3 * P;
+        V.ddepth_scale = w->words.as<float>() + WW_DSCALE + v;
+        V.grad2d = w->grad2d.as<float>() + (size_t)v * 10 * (size_t)n;
+        V.n = n;
+        V.counts = prof_counts(ctx);
+        V.tile_base = w->tile_base[v];
+        w->views_host[v] = V;
+        w->cams_host[v] = to_camk(cam);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(w->views.p, w->views_host, sizeof(ViewK) * w->nv, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(w->cams_dev.p, w->cams_host, sizeof(CamK) * w->nv, hipMemcpyHostToDevice, w->stream));
+    w->table_sig = sig;
+    return FGS_OK;
+}
+
+// Enqueue one window step on the context's stream (rebound to the window's stream by the caller).
+// Only kernel launches: the sequence can be captured into a graph.
+fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_adam &opt, const fgs_target *targets,
+                          const fgs_render_opts &o, const fgs_loss_opts &l, float *loss_dev, float *psnr_dev,
+                          const fgs_gaussians *grad_out)
+{
+    fgs_ctx *ctx = w->ctx;
+    hipStream_t s = ctx->stream;
+    fgs_status st;
+    const int64_t n = params.n;
+    for (int v = 0; v < w->nv; ++v) {
+        const fgs_camera &cam = w->cams[v];
+        const int64_t P = (int64_t)cam.width * cam.height;
+        ImageK img{view_img(w, v), view_img(w, v) + 3 * P, nullptr, nullptr, nullptr};
+        if ((st = enqueue_forward(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v], nullptr,
+                                  w->hs_dev + 2 * v, false)) != FGS_OK)
+            return st;
+    }
+    uint32_t *words = w->words.as<uint32_t>();
+    launch_queue_order(w->views.as<ViewK>(), w->nv, w->total_tiles, w->qka.as<uint32_t>(), w->qva.as<uint32_t>(),
+                       w->qkb.as<uint32_t>(), w->qvb.as<uint32_t>(), w->queue.as<uint32_t>(), words + WW_TOTAL,
+                       sort_ws(ctx, w->total_tiles), s);
+    {
+        Stage st_(ctx, "raster_fwd");
+        launch_raster_queue(true, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
+                            words + WW_COUNTER, w->blocks, s);
+        if (ctx->prof) ctx->prof_fwd += w->nv;
+    }
+    for (int v = 0; v < w->nv; ++v) {
+        const int64_t P = (int64_t)w->cams[v].width * w->cams[v].height;
+        Stage st_(ctx, "loss");
+        launch_loss_l1(P, view_img(w, v), view_img(w, v) + 3 * P, targets[v].rgb, targets[v].depth, l.lambda_rgb,
+                       l.lambda_depth, view_dl(w, v), view_dl(w, v) + 3 * P, w->words.as<float>() + WW_DSCALE + v,
+                       w->partials.as<float>(), loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr,
+                       s);
+    }
+    {
+        Stage st_(ctx, "raster_bwd");
+        launch_raster_queue(false, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
+                            words + WW_COUNTER, w->blocks, s);
+    }
+    int64_t *step = (int64_t *)(words + WW_STEP);
+    AdamK ak;
+    ak.m = to_gk(opt.m);
+    ak.v = to_gk(opt.v);
+    ak.step = step;
+    for (int k = 0; k < 5; ++k) ak.lr[k] = opt.lr[k];
+    ak.beta1 = opt.beta1;
+    ak.beta2 = opt.beta2;
+    ak.eps = opt.eps;
+    const GradK gk = grad_out ? to_gk(*grad_out) : GradK{n, n, nullptr, nullptr, nullptr, nullptr, nullptr};
+    {
+        Stage st_(ctx, "project_bwd");
+        launch_project_bwd_window(to_pk(params), w->cams_dev.as<CamK>(), w->nv, o.lowpass, w->grad2d.as<float>(),
+                                  (int64_t)10 * n, gk, ak, s);
+    }
+    launch_step_advance(step, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *cams, const int32_t *tiles,
+                             int32_t blocks_per_cu, fgs_window **out)
+{
+    const char *w_ = "fgs_window_create";
+    if (!out) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: out is NULL", w_);
+    *out = nullptr;
+    if (n_views <= 0 || n_views > 64) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_views outside [1, 64]", w_);
+    if (!cams) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: cams is NULL", w_);
+    if (blocks_per_cu < 0 || blocks_per_cu > 16)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: blocks_per_cu outside [0, 16]", w_);
+    fgs_status st;
+    for (int v = 0; v < n_views; ++v) {
+        if ((st = check_camera(ctx, &cams[v], w_)) != FGS_OK) return st;
+        const int a = tiles ? tiles[2 * v] : 16, b = tiles ? tiles[2 * v + 1] : 16;
+        if (!tile_supported_window(a, b))
+            return fail(ctx, FGS_ERR_INVALID_ARG, "%s: view %d: window tiles are 16x16, 32x8 or 8x32 (got %dx%d)", w_,
+                        v, a, b);
+    }
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w_);
+    fgs_window *w = new (std::nothrow) fgs_window();
+    if (!w) return fail(ctx, FGS_ERR_HIP, "%s: out of host memory", w_);
+    w->ctx = ctx;
+    w->nv = n_views;
+    w->cams.assign(cams, cams + n_views);
+    int64_t pix = 0, pmax = 0;
+    uint64_t tb = 0;
+    for (int v = 0; v < n_views; ++v) {
+        w->tw.push_back(tiles ? tiles[2 * v] : 16);
+        w->th.push_back(tiles ? tiles[2 * v + 1] : 16);
+        w->pix_off.push_back(4 * pix);
+        const int64_t P = (int64_t)cams[v].width * cams[v].height;
+        pix += P;
+        pmax = std::max(pmax, P);
+        w->tile_base.push_back((uint32_t)tb);
+        tb += (uint64_t)((cams[v].width + w->tw[v] - 1) / w->tw[v]) * ((cams[v].height + w->th[v] - 1) / w->th[v]);
+    }
+    if (tb >= ((uint64_t)1 << 31)) {
+        delete w;
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: too many tiles in the window", w_);
+    }
+    w->total_tiles = (uint32_t)tb;
+    w->cap.assign(n_views, 0);
+    w->L.resize(n_views);
+    w->state.resize(n_views);
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    w->blocks = (blocks_per_cu ? blocks_per_cu : 4) * cus;
+    const size_t wbytes = (size_t)(WW_DSCALE + n_views) * 4 + 64;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = w->img.ensure((size_t)pix * 4 * 4);
+    if (e == hipSuccess) e = w->dl.ensure((size_t)pix * 4 * 4);
+    if (e == hipSuccess) e = w->views.ensure(sizeof(ViewK) * n_views);
+    if (e == hipSuccess) e = w->cams_dev.ensure(sizeof(CamK) * n_views);
+    if (e == hipSuccess) e = w->qka.ensure((size_t)tb * 4);
+    if (e == hipSuccess) e = w->qva.ensure((size_t)tb * 4);
+    if (e == hipSuccess) e = w->qkb.ensure((size_t)tb * 4);
+    if (e == hipSuccess) e = w->qvb.ensure((size_t)tb * 4);
+    if (e == hipSuccess) e = w->queue.ensure((size_t)tb * 4);
+    if (e == hipSuccess) e = w->words.ensure(wbytes);
+    if (e == hipSuccess) e = hipMemset(w->words.p, 0, wbytes);
+    if (e == hipSuccess) e = w->partials.ensure((size_t)loss_partials_size(pmax) * 4);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w->step_host, 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w->views_host, sizeof(ViewK) * n_views, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w->cams_host, sizeof(CamK) * n_views, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&w->hs, (size_t)2 * n_views * 4, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        memset(w->hs, 0, (size_t)2 * n_views * 4);
+        e = hipHostGetDevicePointer((void **)&w->hs_dev, w->hs, 0);
+    }
+    if (e != hipSuccess) {
+        fgs_window_destroy(w);
+        return fail(ctx, FGS_ERR_HIP, "%s: %s", w_, hipGetErrorString(e));
+    }
+    *out = w;
+    return FGS_OK;
+}
+
+fgs_status fgs_window_destroy(fgs_window *w)
+{
+    if (!w) return FGS_OK;
+    if (w->stream) (void)hipStreamSynchronize(w->stream);
+    window_drop_graph(w);
+    for (DBuf &b : w->state) b.release();
+    DBuf *bufs[] = {&w->img, &w->dl,  &w->grad2d, &w->views, &w->cams_dev, &w->qka,
+                    &w->qva, &w->qkb, &w->qvb,    &w->queue, &w->words,    &w->partials};
+    for (DBuf *b : bufs) b->release();
+    if (w->ev_in) (void)hipEventDestroy(w->ev_in);
+    if (w->ev_out) (void)hipEventDestroy(w->ev_out);
+    if (w->stream) (void)hipStreamDestroy(w->stream);
+    if (w->step_host) (void)hipHostFree(w->step_host);
+    if (w->views_host) (void)hipHostFree(w->views_host);
+    if (w->cams_host) (void)hipHostFree(w->cams_host);
+    if (w->hs) (void)hipHostFree(w->hs);
+    delete w;
+    return FGS_OK;
+}
+
+fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam *opt, const fgs_target *targets,
+                           const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev, float *psnr_dev,
+                           const fgs_gaussians *grad_out, int32_t use_graph)
+{
+    const char *w_ = "fgs_window_step";
+    if (!w) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: window is NULL", w_);
+    fgs_ctx *ctx = w->ctx;
+    int tw, th;
+    fgs_status st;
+    if ((st = check_gauss(ctx, params, w_, "params")) != FGS_OK) return st;
+    if ((st = check_adam(ctx, opt, params->n, w_)) != FGS_OK) return st;
+    if ((st = check_opts(ctx, o, w_, &tw, &th)) != FGS_OK) return st;
+    if (!targets) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: targets is NULL", w_);
+    for (int v = 0; v < w->nv; ++v)
+        if (!targets[v].rgb || !targets[v].depth)
+            return fail(ctx, FGS_ERR_INVALID_ARG, "%s: target %d has a NULL plane", w_, v);
+    if (!l || !std::isfinite(l->lambda_rgb) || !std::isfinite(l->lambda_depth))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: loss options NULL or not finite", w_);
+    if (grad_out) {
+        if ((st = check_gauss(ctx, grad_out, w_, "grad_out")) != FGS_OK) return st;
+        if (grad_out->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad_out.n != params.n", w_);
+    }
+    // a step already run that outgrew views' states: its result is void; grow them and report once
+    {
+        int64_t worst = 0;
+        int worst_v = -1;
+        bool any = false;
+        for (int v = 0; v < w->nv; ++v) any |= ((volatile uint32_t *)w->hs)[2 * v + 1] != 0;
+        if (any) HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // every view's flag is final now
+        for (int v = 0; v < w->nv; ++v) {
+            volatile uint32_t *hs = w->hs + 2 * v;
+            if (!hs[1]) continue;
+            const int64_t K = hs[0];
+            hs[0] = 0;
+            hs[1] = 0;
+            w->cap[v] = std::max<int64_t>(w->cap[v], K + K / 2 + 1024);
+            if (K > worst) {
+                worst = K;
+                worst_v = v;
+            }
+        }
+        if (worst_v >= 0) {
+            // the context's own overflow word saw the same events; this report replaces it
+            HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, w->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+            w->n = -1;  // the next step resizes
+            return fail(ctx, FGS_ERR_CAPACITY,
+                        "%s: an earlier step needed %lld pairs in view %d; the window has grown, repeat that step", w_,
+                        (long long)worst, worst_v);
+        }
+    }
+    hipStream_t user = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(w->ev_in, user));
+    HIP_TRY(ctx, hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    ctx->stream = w->stream;
+    struct Rebind {
+        fgs_ctx *c;
+        hipStream_t s;
+        ~Rebind() { c->stream = s; }
+    } rebind{ctx, user};
+    if (params->n != w->n && (st = window_size(w, *params, *o)) != FGS_OK) return st;
+    if ((st = window_tables(w, *params, *o)) != FGS_OK) return st;
+    const int64_t dev_step = w->dev_step;
+    w->dev_step = -1;  // unknown until this step is enqueued whole
+    if (opt->step != dev_step) {  // the device counter follows the host's
+        HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+        *w->step_host = opt->step;
+        HIP_TRY(ctx, hipMemcpyAsync(w->words.as<char>() + 4 * WW_STEP, w->step_host, 8, hipMemcpyHostToDevice,
+                                    w->stream));
+    }
+    if (use_graph && ctx->prof) use_graph = 0;  // profiled steps run eagerly
+    if (use_graph) {
+        std::vector<uintptr_t> sig = w->table_sig;
+        const void *ptrs[] = {params->mean, params->log_scale, params->quat, params->opacity_logit, params->rgb,
+                              opt->m.mean, opt->m.log_scale, opt->m.quat, opt->m.opacity_logit, opt->m.rgb,
+                              opt->v.mean, opt->v.log_scale, opt->v.quat, opt->v.opacity_logit, opt->v.rgb,
+                              loss_dev, psnr_dev};
+        for (const void *q : ptrs) sig.push_back((uintptr_t)q);
+        sig.push_back((uintptr_t)params->stride);
+        sig.push_back((uintptr_t)opt->m.stride);
+        sig.push_back((uintptr_t)opt->v.stride);
+        if (grad_out) {
+            const void *gp[] = {grad_out->mean, grad_out->log_scale, grad_out->quat, grad_out->opacity_logit,
+                                grad_out->rgb};
+            for (const void *q : gp) sig.push_back((uintptr_t)q);
+            sig.push_back((uintptr_t)grad_out->stride);
+        } else {
+            sig.push_back(0);
+        }
+        for (int v = 0; v < w->nv; ++v) {
+            sig.push_back((uintptr_t)targets[v].rgb);
+            sig.push_back((uintptr_t)targets[v].depth);
+        }
+        uint32_t fb[10];
+        memcpy(&fb[0], &l->lambda_rgb, 4);
+        memcpy(&fb[1], &l->lambda_depth, 4);
+        memcpy(&fb[2], opt->lr, 20);
+        memcpy(&fb[7], &opt->beta1, 4);
+        memcpy(&fb[8], &opt->beta2, 4);
+        memcpy(&fb[9], &opt->eps, 4);
+        for (uint32_t x : fb) sig.push_back(x);
+        if (!w->exec || sig != w->sig) {
+            window_drop_graph(w);
+            HIP_TRY(ctx, hipStreamBeginCapture(w->stream, hipStreamCaptureModeThreadLocal));
+            st = window_enqueue(w, *params, *opt, targets, *o, *l, loss_dev, psnr_dev, grad_out);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(w->stream, &g);
+            if (st != FGS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(ctx, FGS_ERR_HIP, "%s: capture: %s", w_, hipGetErrorString(e));
+            w->graph = g;
+            const hipError_t e2 = hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0);
+            if (e2 != hipSuccess) {
+                window_drop_graph(w);
+                return fail(ctx, FGS_ERR_HIP, "%s: instantiate: %s", w_, hipGetErrorString(e2));
+            }
+            w->sig = sig;
+        }
+        const hipError_t e = hipGraphLaunch(w->exec, w->stream);
+        if (e != hipSuccess) return fail(ctx, FGS_ERR_HIP, "%s: graph launch: %s", w_, hipGetErrorString(e));
+    } else if ((st = window_enqueue(w, *params, *opt, targets, *o, *l, loss_dev, psnr_dev, grad_out)) != FGS_OK) {
+        return st;
+    }
+    HIP_TRY(ctx, hipEventRecord(w->ev_out, w->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(user, w->ev_out, 0));
+    opt->step += 1;
+    w->dev_step = opt->step;
     return FGS_OK;
 }
 

@@ -123,6 +123,37 @@ struct ImageK {
     int32_t *n_contrib;
 };
 
+// Everything the rasterizer needs for one view (kernel argument, or an entry of a device array
+// for the persistent window kernels).
+struct ViewK {
+    RasterK rk;
+    int32_t W, H;
+    const Rec *rec;
+    const uint32_t *vals, *ids;
+    const uint2 *ranges;
+    uint32_t *last;
+    float *tfinal;
+    ImageK img;
+    const float *drgb, *ddepth, *dalpha, *ddepth_scale;
+    float *grad2d;
+    int64_t n;
+    unsigned long long *counts;
+    uint32_t tile_base;  // index of this view's first tile in the window's item numbering
+};
+
+bool tile_supported(int tw, int th);
+bool tile_supported_window(int tw, int th);
+
+// Order the window's items longest tile list first (stable): queue receives item ids.
+void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t *ka, uint32_t *va, uint32_t *kb,
+                        uint32_t *vb, uint32_t *queue, uint32_t *n_dev, const SortWS &ws, hipStream_t s);
+
+// Persistent window rasterizer: blocks pull items q < total from the queue (item ids g, or q
+// itself when queue is NULL) and process tile g - views[v].tile_base of view v. counter is
+// zeroed first (with a kernel, so the sequence can be captured in a graph).
+void launch_raster_queue(bool fwd, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
+                         uint32_t *counter, int blocks, hipStream_t s);
+
 // counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel
 // stopped, [1] += pairs blended, [2] += list entries staged.
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
@@ -142,6 +173,21 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,
                         bool accumulate, hipStream_t s);
 
+// Adam hyper-parameters for the fused window update; step points to the device count of updates
+// already applied (the kernel applies update *step + 1 and does not change it).
+struct AdamK {
+    GradK m, v;
+    const int64_t *step;
+    float lr[5];
+    float beta1, beta2, eps;
+};
+
+// Window backward: sums every view's 2D gradients through its projection per gaussian (view v's
+// 10 planes at grad2d + v * view_stride, cleared after use), writes grad when grad.mean is set,
+// and applies Adam when adam.m.mean is set.
+void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,
+                               int64_t view_stride, const GradK &grad, const AdamK &adam, hipStream_t s);
+
 // L1 loss of Eq. 16 (colour + depth terms) with its gradient; partials is scratch of
 // loss_partials_size(P) floats; writes loss/psnr device scalars (nullable) and the depth-gradient
 // scale 1/P_v into *ddepth_scale.
@@ -152,5 +198,8 @@ void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float
 
 void launch_adam(const GradK &p, const ParamsK &g, const GradK &m, const GradK &v, const float lr[5],
                  float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+
+// *step += 1 on the device (the Adam step counter a captured window step reads and advances).
+void launch_step_advance(int64_t *step, hipStream_t s);
 
 }  // namespace fgs

@@ -155,42 +155,9 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
     rect[i] = rc;
 }
 
-// Backward of the projection, one thread per gaussian. grad2d holds 10 planes of length n
-// indexed by gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
-// zeroes the slots it read, so grad2d is all-zero again for the next backward. The 14 parameter
-// gradients are added to grad (accumulate) or written to it. Every access is coalesced.
-__global__ void __launch_bounds__(256)
-k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad, int accumulate)
+// Chain rule for one gaussian: 2D gradient g2 -> 14 parameter gradients, added to out[14].
+__device__ inline void chain_rule(const Proj &p, const CamK &cam, const double g2[10], double out[14])
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = g.n;
-    if (i >= n) return;
-    double g2[10];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        g2[k] = grad2d[k * n + i];
-        any |= g2[k] != 0.0;
-    }
-    const int64_t S = grad.stride;
-    Proj p;
-    if (any) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) grad2d[k * n + i] = 0.0f;
-        project_gaussian(g, i, cam, rk.lowpass, p);
-    }
-    if (!any || !p.valid) {
-        if (!accumulate) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) grad.mean[k * S + i] = grad.log_scale[k * S + i] = grad.rgb[k * S + i] = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) grad.quat[k * S + i] = 0.0f;
-            grad.logit[i] = 0.0f;
-        }
-        return;
-    }
-    // accumulate: out += v; otherwise out = v
-    auto put = [accumulate](float *dst, double v) { *dst = accumulate ? *dst + (float)v : (float)v; };
     // conic = Sigma'^-1: dL/dSigma' = -X Gh X with Gh = [[ga, gb/2], [gb/2, gc]], X the conic.
     const double a = p.conic[0], b = p.conic[1], c = p.conic[2];
     const double ga = g2[2], gb = 0.5 * g2[3], gc = g2[4];
@@ -238,7 +205,7 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     dtz += g2[1] * (-fy * ty * iz * iz);
     dtz += g2[9];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) put(&grad.mean[k * S + i], W[k] * dtx + W[3 + k] * dty + W[6 + k] * dtz);
+    for (int k = 0; k < 3; ++k) out[k] += W[k] * dtx + W[3 + k] * dty + W[6 + k] * dtz;
     // Sigma = M M^T, M = R diag(s): dM = 2 dSigma M
     double M[9], dM[9];
 #pragma unroll
@@ -254,7 +221,7 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double ds = p.Rq[k] * dM[k] + p.Rq[3 + k] * dM[3 + k] + p.Rq[6 + k] * dM[6 + k];
-        put(&grad.log_scale[k * S + i], ds * p.s[k]);
+        out[3 + k] += ds * p.s[k];
 #pragma unroll
         for (int u = 0; u < 3; ++u) dR[3 * u + k] = dM[3 * u + k] * p.s[k];
     }
@@ -272,10 +239,106 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
     const double iq = 1.0 / p.qnorm;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) put(&grad.quat[k * S + i], (dq[k] - p.qn[k] * dot) * iq);
-    put(&grad.logit[i], g2[5] * p.opacity * (1.0 - p.opacity));
+    for (int k = 0; k < 4; ++k) out[6 + k] += (dq[k] - p.qn[k] * dot) * iq;
+    out[10] += g2[5] * p.opacity * (1.0 - p.opacity);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) put(&grad.rgb[k * S + i], g2[6 + k]);
+    for (int k = 0; k < 3; ++k) out[11 + k] += g2[6 + k];
+}
+
+__device__ inline float *plane(const GradK &g, int row)
+{
+    const int64_t S = g.stride;
+    return row < 3 ? g.mean + row * S : row < 6 ? g.log_scale + (row - 3) * S : row < 10 ? g.quat + (row - 6) * S
+         : row < 11 ? g.logit : g.rgb + (row - 11) * S;
+}
+
+// Backward of the projection, one thread per gaussian. grad2d holds 10 planes of length n
+// indexed by gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
+// zeroes the slots it read, so grad2d is all-zero again for the next backward. The 14 parameter
+// gradients are added to grad (accumulate) or written to it. Every access is coalesced.
+__global__ void __launch_bounds__(256)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad, int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = g.n;
+    if (i >= n) return;
+    double g2[10];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        g2[k] = grad2d[k * n + i];
+        any |= g2[k] != 0.0;
+    }
+    double out[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) out[k] = 0.0;
+    if (any) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) grad2d[k * n + i] = 0.0f;
+        Proj p;
+        project_gaussian(g, i, cam, rk.lowpass, p);
+        if (p.valid) chain_rule(p, cam, g2, out);
+        else any = false;
+    }
+    if (!any && accumulate) return;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) {
+        float *d = plane(grad, k) + i;
+        *d = accumulate ? *d + (float)out[k] : (float)out[k];
+    }
+}
+
+// Window backward: per gaussian, the 2D gradients of every view (view v at grad2d + v*view_stride)
+// go through that view's projection; the sum is the gaussian's gradient, written to grad (if its
+// pointers are set) and applied by Adam (if adam.m is set). Adam's update number is *step + 1,
+// read from device memory so a captured graph can be replayed unchanged.
+__global__ void __launch_bounds__(256)
+k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float lowpass, float *__restrict__ grad2d,
+                     int64_t view_stride, GradK grad, AdamK adam)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = g.n;
+    if (i >= n) return;
+    double out[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) out[k] = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        float *g2p = grad2d + v * view_stride;
+        double g2[10];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            g2[k] = g2p[k * n + i];
+            any |= g2[k] != 0.0;
+        }
+        if (!any) continue;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) g2p[k * n + i] = 0.0f;
+        const CamK cam = cams[v];
+        Proj p;
+        project_gaussian(g, i, cam, lowpass, p);
+        if (p.valid) chain_rule(p, cam, g2, out);
+    }
+    if (grad.mean)
+#pragma unroll
+        for (int k = 0; k < 14; ++k) plane(grad, k)[i] = (float)out[k];
+    if (adam.m.mean) {
+        const double t = (double)(*adam.step + 1);
+        const float bc1 = (float)(1.0 - pow((double)adam.beta1, t));
+        const float bc2 = (float)(1.0 - pow((double)adam.beta2, t));
+        GradK P{g.n, g.stride, (float *)g.mean, (float *)g.log_scale, (float *)g.quat, (float *)g.logit, (float *)g.rgb};
+#pragma unroll
+        for (int k = 0; k < 14; ++k) {
+            const int group = k < 3 ? 0 : k < 6 ? 1 : k < 10 ? 2 : k < 11 ? 3 : 4;
+            const float gi = (float)out[k];
+            float *mm = plane(adam.m, k) + i, *vv = plane(adam.v, k) + i, *pp = plane(P, k) + i;
+            const float mi = adam.beta1 * *mm + (1.0f - adam.beta1) * gi;
+            const float vi = adam.beta2 * *vv + (1.0f - adam.beta2) * gi * gi;
+            *mm = mi;
+            *vv = vi;
+            *pp -= adam.lr[group] * (mi / bc1) / (sqrtf(vi / bc2) + adam.eps);
+        }
+    }
 }
 
 }  // namespace
@@ -286,6 +349,15 @@ void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *r
     const int64_t blocks = g.n > 0 ? (g.n + 255) / 256 : 1;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec_by_id, rect, count,
                        dkey, ids, n_out);
+}
+
+void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,
+                               int64_t view_stride, const GradK &grad, const AdamK &adam, hipStream_t s)
+{
+    if (g.n <= 0) return;
+    const int64_t blocks = (g.n + 255) / 256;
+    hipLaunchKernelGGL(k_project_bwd_window, dim3((unsigned)blocks), dim3(256), 0, s, g, cams_dev, nv, lowpass, grad2d,
+                       view_stride, grad, adam);
 }
 
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,

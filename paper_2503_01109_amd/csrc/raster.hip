@@ -73,16 +73,19 @@ __device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia,
 // Bit w set when the sigma_cut ellipse of a staged record can reach a pixel centre of wave w's
 // strip (rows [w R, w R + R) of the tile, R = 64 / TW). Conservative by a relative 1e-3 margin:
 // the per-pixel test stays the exact decision.
-template <int TW, int TH>
-__device__ __forceinline__ uint32_t strip_mask(const float4 &a4, const float4 &b4, float cut2)
+// Bit w set when the sigma_cut ellipse of a staged record can reach a pixel centre of wave w's
+// strip (rows [w R, w R + R) of the tile, R = 64 / tw). Conservative by a relative 1e-3 margin:
+// the per-pixel test stays the exact decision.
+template <int NW>
+__device__ __forceinline__ uint32_t strip_mask(const float4 &a4, const float4 &b4, float cut2, int tw)
 {
-    constexpr int R = kWave / TW, NW = TW * TH / kWave;
+    const int R = kWave / tw;
     uint32_t m = 0;
     const float ia = __frcp_rn(a4.z), ic = __frcp_rn(b4.x);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const float q =
-            rect_min_q(a4.z, a4.w, b4.x, ia, ic, a4.x, a4.y, 0.5f, TW - 0.5f, w * R + 0.5f, w * R + R - 0.5f);
+        const float q = rect_min_q(a4.z, a4.w, b4.x, ia, ic, a4.x, a4.y, 0.5f, tw - 0.5f, w * R + 0.5f,
+                                   w * R + R - 0.5f);
         if (q <= cut2 * 1.001f) m |= 1u << w;
     }
     return m;
@@ -127,26 +130,30 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH)
-k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
-             const uint2 *__restrict__ ranges, uint32_t *__restrict__ last_out, float *__restrict__ tfinal_out,
-             ImageK img, unsigned long long *__restrict__ counts)
+// Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
+// tile_w x tile_h = NT pixels).
+template <int NT>
+__device__ void tile_fwd(const ViewK &V, int tile)
 {
-    constexpr int NT = TW * TH, NW = NT / kWave;
+    constexpr int NW = NT / kWave;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint8_t smask[NT];
     __shared__ uint16_t slist[NW][NT];
+    __shared__ unsigned long long red[2];
+    const RasterK &rk = V.rk;
+    const int W = V.W, H = V.H;
+    const Rec *__restrict__ rec = V.rec;
+    const uint32_t *__restrict__ vals = V.vals;
+    const int TW = rk.tile_w, TH = rk.tile_h;
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
-    const int tile = blockIdx.x;
     const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
     const int lx = tid % TW, ly = tid / TW;
     const int x = x0 + lx, y = y0 + ly;
     const bool inside = x < W && y < H;
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint2 range = ranges[tile];
+    const uint2 range = V.ranges[tile];
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
@@ -164,7 +171,7 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
-            smask[tid] = (uint8_t)strip_mask<TW, TH>(a4, b4, cut2);
+            smask[tid] = (uint8_t)strip_mask<NW>(a4, b4, cut2, TW);
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, range.y - b);
@@ -198,9 +205,8 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             last = b + k - range.x + 1;
         }
     }
-    if (counts) {
+    if (V.counts) {
         // work counters (profiling only): block sums, one atomic per block and counter
-        __shared__ unsigned long long red[2];
         if (tid == 0) red[0] = red[1] = 0ull;
         __syncthreads();
         if (inside) {
@@ -209,14 +215,17 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
         }
         __syncthreads();
         if (tid == 0) {
-            atomicAdd(&counts[0], red[0]);
-            atomicAdd(&counts[1], red[1]);
-            atomicAdd(&counts[2], (unsigned long long)staged);
+            atomicAdd(&V.counts[0], red[0]);
+            atomicAdd(&V.counts[1], red[1]);
+            atomicAdd(&V.counts[2], (unsigned long long)staged);
         }
     }
+    // the next tile of a persistent workgroup restages the LDS arrays: wait for every reader
+    __syncthreads();
     if (!inside) return;
     const int64_t P = (int64_t)W * H;
     const int64_t p = (int64_t)y * W + x;
+    const ImageK &img = V.img;
     img.rgb[p] = C0 + T * rk.bg[0];
     img.rgb[P + p] = C1 + T * rk.bg[1];
     img.rgb[2 * P + p] = C2 + T * rk.bg[2];
@@ -224,19 +233,23 @@ k_raster_fwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
     if (img.alpha) img.alpha[p] = A;
     if (img.T_final) img.T_final[p] = T;
     if (img.n_contrib) img.n_contrib[p] = ncon;
-    last_out[p] = last;
-    tfinal_out[p] = T;
+    V.last[p] = last;
+    V.tfinal[p] = T;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW *TH)
-k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, const uint32_t *__restrict__ vals,
-             const uint32_t *__restrict__ ids, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ last_in,
-             const float *__restrict__ tfinal_in, const float *__restrict__ drgb, const float *__restrict__ ddepth,
-             const float *__restrict__ dalpha, const float *__restrict__ ddepth_scale, float *__restrict__ grad2d,
-             int64_t n)
+// Backward of one tile of one view (NT threads, one pixel each).
+template <int NT>
+__device__ void tile_bwd(const ViewK &V, int tile)
 {
-    constexpr int NT = TW * TH, NW = NT / kWave;
+    constexpr int NW = NT / kWave;
+    const RasterK &rk = V.rk;
+    const int W = V.W, H = V.H;
+    const Rec *__restrict__ rec = V.rec;
+    const uint32_t *__restrict__ vals = V.vals;
+    const uint32_t *__restrict__ ids = V.ids;
+    float *__restrict__ grad2d = V.grad2d;
+    const int64_t n = V.n;
+    const int TW = rk.tile_w, TH = rk.tile_h;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint32_t srank[NT];
     __shared__ float sacc[10][NT];
@@ -246,14 +259,13 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wid = tid / kWave;
-    const int tile = blockIdx.x;
     const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
     const int lx = tid % TW, ly = tid / TW;
     const int x = x0 + lx, y = y0 + ly;
     const bool inside = x < W && y < H;
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint2 range = ranges[tile];
+    const uint2 range = V.ranges[tile];
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
     const int64_t P = (int64_t)W * H;
     const int64_t p = (int64_t)y * W + x;
@@ -261,13 +273,13 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
     uint32_t L = 0;
     float T = 1.0f, gC0 = 0, gC1 = 0, gC2 = 0, gD = 0, gA = 0;
     if (inside) {
-        L = last_in[p];
-        T = tfinal_in[p];
-        gC0 = drgb[p];
-        gC1 = drgb[P + p];
-        gC2 = drgb[2 * P + p];
-        gD = ddepth[p] * (ddepth_scale ? *ddepth_scale : 1.0f);
-        gA = dalpha ? dalpha[p] : 0.0f;
+        L = V.last[p];
+        T = V.tfinal[p];
+        gC0 = V.drgb[p];
+        gC1 = V.drgb[P + p];
+        gC2 = V.drgb[2 * P + p];
+        gD = V.ddepth[p] * (V.ddepth_scale ? *V.ddepth_scale : 1.0f);
+        gA = V.dalpha ? V.dalpha[p] : 0.0f;
     }
     const float Tf = T;
     float BC0 = Tf * rk.bg[0], BC1 = Tf * rk.bg[1], BC2 = Tf * rk.bg[2], BD = Tf * rk.bg_depth;
@@ -292,7 +304,7 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             sb[tid] = b4;
             sc[tid] = c4;
             srank[tid] = ids[r];  // gradients are accumulated by gaussian id
-            smask[tid] = (uint8_t)strip_mask<TW, TH>(a4, b4, cut2);
+            smask[tid] = (uint8_t)strip_mask<NW>(a4, b4, cut2, TW);
         }
         __syncthreads();
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
@@ -376,36 +388,46 @@ k_raster_bwd(RasterK rk, int32_t W, int32_t H, const Rec *__restrict__ rec, cons
             }
         }
     }
+    __syncthreads();  // LDS is restaged by the next tile of a persistent workgroup
 }
 
-template <int TW, int TH>
-void fwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint2 *ranges,
-           uint32_t *last, float *tfinal, const ImageK &img, unsigned long long *counts, hipStream_t s)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT>(V, blockIdx.x); }
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT>(V, blockIdx.x); }
+
+__device__ inline int view_of(const ViewK *views, int nv, uint32_t g)
 {
-    const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
-    hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ranges, last,
-                       tfinal, img, counts);
+    int v = 0;
+    while (v + 1 < nv && views[v + 1].tile_base <= g) ++v;
+    return v;
 }
 
-template <int TW, int TH>
-void bwd_t(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals, const uint32_t *ids,
-           const uint2 *ranges, const uint32_t *last, const float *tfinal, const float *drgb, const float *ddepth,
-           const float *dalpha, const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s)
+// Persistent rasterizer over a window of views: workgroups pull (view, tile) items from a queue
+// through an atomic counter until it runs past the last item. 256 threads per workgroup; each
+// view's tile has 256 pixels in its own shape (16x16, 32x8 or 8x32).
+template <bool FWD>
+__global__ void __launch_bounds__(256)
+k_raster_queue(const ViewK *__restrict__ views, int nv, const uint32_t *__restrict__ queue, uint32_t total,
+               uint32_t *__restrict__ counter)
 {
-    const unsigned tiles = (unsigned)(rk.tiles_x * rk.tiles_y);
-    hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(tiles), dim3(TW * TH), 0, s, rk, W, H, rec, vals, ids, ranges,
-                       last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n);
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t q = s_item;
+        __syncthreads();
+        if (q >= total) break;
+        const uint32_t g = queue ? queue[q] : q;
+        const int v = view_of(views, nv, g);
+        const ViewK &V = views[v];
+        if (FWD) tile_fwd<256>(V, (int)(g - V.tile_base));
+        else tile_bwd<256>(V, (int)(g - V.tile_base));
+    }
 }
 
 }  // namespace
-
-#define FGS_TILE_SWITCH(CALL)                                          \
-    if (rk.tile_w == 16 && rk.tile_h == 16) CALL(16, 16);              \
-    else if (rk.tile_w == 32 && rk.tile_h == 8) CALL(32, 8);           \
-    else if (rk.tile_w == 8 && rk.tile_h == 32) CALL(8, 32);           \
-    else if (rk.tile_w == 32 && rk.tile_h == 16) CALL(32, 16);         \
-    else if (rk.tile_w == 16 && rk.tile_h == 32) CALL(16, 32);         \
-    else if (rk.tile_w == 8 && rk.tile_h == 8) CALL(8, 8);
 
 bool tile_supported(int tw, int th)
 {
@@ -413,13 +435,48 @@ bool tile_supported(int tw, int th)
            (tw == 16 && th == 32) || (tw == 8 && th == 8);
 }
 
+bool tile_supported_window(int tw, int th) { return tw * th == 256 && (tw == 16 || tw == 32 || tw == 8); }
+
+static ViewK view_of_args(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals)
+{
+    ViewK V = {};
+    V.rk = rk;
+    V.W = W;
+    V.H = H;
+    V.rec = rec;
+    V.vals = vals;
+    return V;
+}
+
+static void launch_fwd_view(const ViewK &V, hipStream_t s)
+{
+    const unsigned tiles = (unsigned)(V.rk.tiles_x * V.rk.tiles_y);
+    const int nt = V.rk.tile_w * V.rk.tile_h;
+    if (nt == 256) hipLaunchKernelGGL(k_raster_fwd<256>, dim3(tiles), dim3(256), 0, s, V);
+    else if (nt == 512) hipLaunchKernelGGL(k_raster_fwd<512>, dim3(tiles), dim3(512), 0, s, V);
+    else hipLaunchKernelGGL(k_raster_fwd<64>, dim3(tiles), dim3(64), 0, s, V);
+}
+
+static void launch_bwd_view(const ViewK &V, hipStream_t s)
+{
+    const unsigned tiles = (unsigned)(V.rk.tiles_x * V.rk.tiles_y);
+    const int nt = V.rk.tile_w * V.rk.tile_h;
+    if (nt == 256) hipLaunchKernelGGL(k_raster_bwd<256>, dim3(tiles), dim3(256), 0, s, V);
+    else if (nt == 512) hipLaunchKernelGGL(k_raster_bwd<512>, dim3(tiles), dim3(512), 0, s, V);
+    else hipLaunchKernelGGL(k_raster_bwd<64>, dim3(tiles), dim3(64), 0, s, V);
+}
+
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
                        unsigned long long *counts, hipStream_t s)
 {
-#define FGS_CALL_FWD(a, b) fwd_t<a, b>(rk, W, H, rec, vals, ranges, last, tfinal, img, counts, s)
-    FGS_TILE_SWITCH(FGS_CALL_FWD)
-#undef FGS_CALL_FWD
+    ViewK V = view_of_args(rk, W, H, rec, vals);
+    V.ranges = ranges;
+    V.last = last;
+    V.tfinal = tfinal;
+    V.img = img;
+    V.counts = counts;
+    launch_fwd_view(V, s);
 }
 
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
@@ -427,10 +484,26 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        const float *drgb, const float *ddepth, const float *dalpha, const float *ddepth_scale,
                        float *grad2d, int64_t n, hipStream_t s)
 {
-#define FGS_CALL_BWD(a, b) \
-    bwd_t<a, b>(rk, W, H, rec, vals, ids, ranges, last, tfinal, drgb, ddepth, dalpha, ddepth_scale, grad2d, n, s)
-    FGS_TILE_SWITCH(FGS_CALL_BWD)
-#undef FGS_CALL_BWD
+    ViewK V = view_of_args(rk, W, H, rec, vals);
+    V.ids = ids;
+    V.ranges = ranges;
+    V.last = (uint32_t *)last;
+    V.tfinal = (float *)tfinal;
+    V.drgb = drgb;
+    V.ddepth = ddepth;
+    V.dalpha = dalpha;
+    V.ddepth_scale = ddepth_scale;
+    V.grad2d = grad2d;
+    V.n = n;
+    launch_bwd_view(V, s);
+}
+
+void launch_raster_queue(bool fwd, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
+                         uint32_t *counter, int blocks, hipStream_t s)
+{
+    launch_zero_u32(counter, 1, s);
+    if (fwd) hipLaunchKernelGGL(k_raster_queue<true>, dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+    else hipLaunchKernelGGL(k_raster_queue<false>, dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
 }
 
 }  // namespace fgs

@@ -461,6 +461,19 @@ size_t seed_ws_bytes(int W, int H)
     return P * 16 + P * 8 + P + 2 * (size_t)H * 8 + 256 * 4 + ((size_t)H + 1) * 4 * 2 + 4096;
 }
 
+uint32_t *seed_count_ptr(void *ws, int W, int H)
+{
+    const size_t P = (size_t)W * H;
+    char *w = (char *)ws;
+    w += ((P * 16 + 255) / 256) * 256;
+    w += ((P * 8 + 255) / 256) * 256;
+    w += ((P + 255) / 256) * 256;
+    w += ((2 * (size_t)H * 8 + 255) / 256) * 256;
+    w += 256 * 4;
+    uint32_t *row_count = (uint32_t *)w;
+    return row_count + H + H;  // row_off[H]: the total written by the seed scan
+}
+
 void launch_seed(const float *rgb, const float *depth, int W, int H, double D0, const SeedK &sk, const SeedOutK &out,
                  void *ws, SeedScalars *sc, uint32_t *status, hipStream_t s)
 {

@@ -35,6 +35,8 @@ struct SeedOutK {
 
 bool seed_size_supported(int W, int H);
 size_t seed_ws_bytes(int W, int H);
+// Device word holding the number of seeds found by the last launch_seed on this workspace.
+uint32_t *seed_count_ptr(void *ws, int W, int H);
 void launch_seed(const float *rgb, const float *depth, int W, int H, double D0, const SeedK &sk, const SeedOutK &out,
                  void *ws, SeedScalars *sc, uint32_t *status, hipStream_t s);
 

@@ -38,6 +38,7 @@ LAYOUT_PROBE = r"""
 #include <stddef.h>
 #include <stdio.h>
 #include "fgs.h"
+#include "fgs_prior.h"
 #define S(T) printf(#T " %zu\n", sizeof(T));
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
@@ -46,6 +47,7 @@ int main(void) {
   S(fgs_render_opts) O(fgs_render_opts, bg) O(fgs_render_opts, tile_h)
   S(fgs_image) S(fgs_adam) O(fgs_adam, step) O(fgs_adam, lr) O(fgs_adam, eps)
   S(fgs_target) S(fgs_loss_opts)
+  S(fgs_prior_adam) O(fgs_prior_adam, step) O(fgs_prior_adam, eps)
   %EXTRA%
   return 0;
 }
@@ -55,7 +57,8 @@ int main(void) {
 def test_struct_layouts_match_header(tmp_path):
     extra = ""
     if hasattr(F, "CSeedOpts"):
-        extra = "S(fgs_seed_opts) O(fgs_seed_opts, use_prior) S(fgs_seed_out) O(fgs_seed_out, tile_count)"
+        extra = ("S(fgs_seed_opts) O(fgs_seed_opts, use_prior) S(fgs_seed_out) O(fgs_seed_out, tile_count) "
+                 "O(fgs_seed_out, from_prior)")
     src = tmp_path / "probe.c"
     src.write_text(LAYOUT_PROBE.replace("%EXTRA%", extra))
     exe = tmp_path / "probe"
@@ -71,10 +74,13 @@ def test_struct_layouts_match_header(tmp_path):
         "fgs_image": C.sizeof(F.CImage), "fgs_adam": C.sizeof(F.CAdam), "fgs_adam.step": F.CAdam.step.offset,
         "fgs_adam.lr": F.CAdam.lr.offset, "fgs_adam.eps": F.CAdam.eps.offset,
         "fgs_target": C.sizeof(F.CTarget), "fgs_loss_opts": C.sizeof(F.CLossOpts),
+        "fgs_prior_adam": C.sizeof(F.CPriorAdam), "fgs_prior_adam.step": F.CPriorAdam.step.offset,
+        "fgs_prior_adam.eps": F.CPriorAdam.eps.offset,
     }
     if extra:
         mine.update({"fgs_seed_opts": C.sizeof(F.CSeedOpts), "fgs_seed_opts.use_prior": F.CSeedOpts.use_prior.offset,
-                     "fgs_seed_out": C.sizeof(F.CSeedOut), "fgs_seed_out.tile_count": F.CSeedOut.tile_count.offset})
+                     "fgs_seed_out": C.sizeof(F.CSeedOut), "fgs_seed_out.tile_count": F.CSeedOut.tile_count.offset,
+                     "fgs_seed_out.from_prior": F.CSeedOut.from_prior.offset})
     for k, v in mine.items():
         assert int(got[k]) == v, f"{k}: header {got[k]} vs binding {v}"
 
@@ -169,3 +175,49 @@ def test_seed_rejects_bad_arguments_on_host():
     assert st == F.ERR_INVALID_ARG
     st, msg = call(synth.camera_tum(), capacity=-1)
     assert st == F.ERR_INVALID_ARG and "output" in msg
+
+
+def test_window_rejects_bad_arguments_on_host():
+    import synth
+    cams = [synth.camera_small(), synth.camera_tum()]
+
+    def call(cams, tiles=None, blocks=0):
+        V = len(cams)
+        cc = (F.CCamera * max(V, 1))(*[F.camera(c) for c in cams])
+        ct = None if tiles is None else (C.c_int32 * (2 * V))(*[x for t in tiles for x in t])
+        p = C.c_void_p()
+        st = F._lib.fgs_window_create(None, V, cc, ct, blocks, C.byref(p))
+        return st, F.last_error()
+
+    assert call(cams) == (F.ERR_INVALID_ARG, "fgs_window_create: ctx is NULL")
+    st, msg = call([])
+    assert st == F.ERR_INVALID_ARG and "n_views" in msg
+    st, msg = call(cams, tiles=[(16, 16), (12, 12)])
+    assert st == F.ERR_INVALID_ARG and "view 1" in msg and "12x12" in msg
+    st, msg = call(cams, tiles=[(16, 16), (32, 16)])
+    assert st == F.ERR_INVALID_ARG
+    st, msg = call(cams, blocks=17)
+    assert st == F.ERR_INVALID_ARG and "blocks_per_cu" in msg
+    st, msg = call([cams[0], _cam(fx=0.0)])
+    assert st == F.ERR_INVALID_ARG and "focal" in msg
+    st = F._lib.fgs_window_step(None, None, None, None, None, None, None, None, None, 1)
+    assert st == F.ERR_INVALID_ARG and "window is NULL" in F.last_error()
+
+
+def test_prior_rejects_bad_arguments_on_host():
+    d = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    assert F._lib.fgs_prior_forward(None, 10, d, d, d) == F.ERR_INVALID_ARG
+    assert "ctx is NULL" in F.last_error()
+    assert F._lib.fgs_prior_forward(None, -1, d, d, d) == F.ERR_INVALID_ARG
+    assert "rows" in F.last_error()
+    assert F._lib.fgs_prior_forward(None, 5, None, d, d) == F.ERR_INVALID_ARG
+    a = F.CPriorAdam(d, d, 0, 1e-3, 0.9, 0.999, 1e-8)
+    assert F._lib.fgs_prior_train_step(None, 0, d, d, d, C.byref(a), None, None) == F.ERR_INVALID_ARG
+    bad = F.CPriorAdam(d, d, 0, 1e-3, 1.5, 0.999, 1e-8)
+    assert F._lib.fgs_prior_train_step(None, 4, d, d, d, C.byref(bad), None, None) == F.ERR_INVALID_ARG
+    assert "hyper" in F.last_error()
+    assert F._lib.fgs_tile_features(None, d, d, 64, 48, 0.1, 10.0, 13, None, d, None) == F.ERR_INVALID_ARG
+    assert "more tiles" in F.last_error()
+    assert F._lib.fgs_tile_features(None, d, d, 0, 48, 0.1, 10.0, 1, None, d, None) == F.ERR_INVALID_ARG
+    assert F._lib.fgs_tile_features(None, d, d, 64, 48, 0.1, 10.0, 12, None, d, None) == F.ERR_INVALID_ARG
+    assert "ctx is NULL" in F.last_error()

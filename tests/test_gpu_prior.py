@@ -1,0 +1,239 @@
+"""GPU parity of the learned seeding prior against the FP64 oracle.
+
+Tile features are FP64 sums stored as FP32 on the GPU: compared at 1e-6 relative.
+
+The network's products round their operands to bfloat16 on both sides; the GPU accumulates in
+FP32 and the oracle in FP64. A hidden activation computed in the two precisions lands on different
+sides of a bfloat16 rounding boundary about once in 1e4 (FP32 error ~2e-7 against a bfloat16 step
+of 2^-8), which moves that operand by one bfloat16 step and the outputs by up to ~1e-3 of their largest
+entry, whatever their own size; so outputs and gradients are held to 2e-3 of their largest entry
+(elementwise where an entry exceeds half of that), and, to show
+that the GPU rounds at the same points, to a quarter of what the rounding itself does (the
+oracle with rounding against the oracle without). Applying the prior to seeds is pinned with
+networks whose output is exactly their output bias (all weights zero), so every fallback decision
+is known exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import assert_close_rel, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+MLP_TOL, MLP_FLOOR, ROUNDING_SHARE = 2e-3, 0.5, 0.25
+
+
+def check_mlp(gpu, ref_bf16, ref_exact, what):
+    assert_close_rel(gpu, ref_bf16, MLP_TOL, what=what, floor=MLP_FLOOR)
+    dev_ = np.abs(np.asarray(gpu, np.float64) - ref_bf16).max()
+    effect = np.abs(ref_bf16 - ref_exact).max()
+    assert dev_ <= ROUNDING_SHARE * effect, f"{what}: deviation {dev_:.3e} vs bfloat16 effect {effect:.3e}"
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    need_gpu()
+    import paper_2503_01109_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fgs):
+    c = fgs.Context()
+    yield c
+    c.close()
+
+
+def random_weights(seed, scale=1.0):
+    """Packed weights with per-layer N(0, scale / fan_in) entries and small biases."""
+    g = synth.rng(seed)
+    parts = [g.normal(0, np.sqrt(scale / 260), 256 * 260), g.normal(0, 0.1, 256),
+             g.normal(0, np.sqrt(scale / 256), 256 * 256), g.normal(0, 0.1, 256),
+             g.normal(0, np.sqrt(scale / 256), 4 * 256), g.normal(0, 0.1, 4)]
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == oracle.MLP_PARAMS
+    return w
+
+
+def feature_rows(seed, rows):
+    """Rows shaped like tile features: 256 log-magnitudes in [0, 6], depth statistics in metres."""
+    g = synth.rng(seed)
+    x = np.empty((rows, 260), np.float32)
+    x[:, :256] = g.uniform(0, 6, (rows, 256))
+    mean = g.uniform(1, 4, rows)
+    x[:, 256] = mean
+    x[:, 257] = g.uniform(0, 0.3, rows)
+    x[:, 258] = mean - g.uniform(0, 0.5, rows)
+    x[:, 259] = mean + g.uniform(0, 0.5, rows)
+    return x
+
+
+def test_tile_features_match_oracle(fgs, ctx):
+    """Every tile of a ragged 70x50 frame with invalid depth (NaN, zero, beyond the range)."""
+    rgb, depth = synth.rgbd_frame(21, 70, 50, n_rect=6)
+    depth[:, :9] = np.nan
+    depth[30:34] = 0.0
+    depth[40:, 60:] = 50.0
+    feat, valid = fgs.tile_features(ctx, dev(rgb), dev(depth), 0.1, 10.0)
+    f, v = host(feat), host(valid)
+    assert f.shape == (5 * 4, 260)
+    for t in range(20):
+        ref, nv = oracle.tile_features(rgb, depth, t % 5, t // 5, 0.1, 10.0)
+        assert v[t] == nv, f"tile {t}"
+        np.testing.assert_allclose(f[t], ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max(), err_msg=f"tile {t}")
+    assert (v == 0).any() and (v == 256).any()
+
+
+def test_tile_features_by_id(fgs, ctx):
+    import torch
+    rgb, depth = synth.rgbd_frame(22, 64, 48, n_rect=4)
+    ids = torch.tensor([5, 0, 11, -1, 12, 3], dtype=torch.int32, device="cuda")
+    feat, valid = fgs.tile_features(ctx, dev(rgb), dev(depth), tile_ids=ids)
+    f, v = host(feat), host(valid)
+    for k, t in enumerate(host(ids)):
+        if t < 0 or t >= 12:
+            assert v[k] == -1 and not f[k].any()
+            continue
+        ref, nv = oracle.tile_features(rgb, depth, t % 4, t // 4)
+        assert v[k] == nv
+        np.testing.assert_allclose(f[k], ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("rows", [1, 63, 200, 1200])
+def test_forward_matches_oracle(fgs, ctx, rows):
+    x = feature_rows(rows, rows)
+    w = random_weights(3)
+    y = host(fgs.prior_forward(ctx, dev(x), dev(w)))
+    check_mlp(y, oracle.mlp_fwd(x, w, bf16=True), oracle.mlp_fwd(x, w, bf16=False), f"y ({rows} rows)")
+
+
+def test_zero_weights_give_the_bias(fgs, ctx):
+    w = np.zeros(oracle.MLP_PARAMS, np.float32)
+    w[-4:] = [0.25, -1.5, 3.0, 0.125]
+    y = host(fgs.prior_forward(ctx, dev(feature_rows(1, 70)), dev(w)))
+    np.testing.assert_array_equal(y, np.broadcast_to(w[-4:], (70, 4)))
+
+
+@pytest.mark.parametrize("rows", [64, 300, 5000])
+def test_gradient_matches_oracle(fgs, ctx, rows):
+    """One training step with learning rate 0: the loss and every gradient block (W1, b1, W2, b2,
+    W3, b3) against the oracle's backward with the same bfloat16 rounding points."""
+    import torch
+    x = feature_rows(10 + rows, rows)
+    w = random_weights(4)
+    t = synth.rng(5).normal(0, 1, (rows, 4)).astype(np.float32)
+    wd = dev(w)
+    adam = fgs.PriorAdam.like(wd, lr=0.0)
+    grad = torch.zeros_like(wd)
+    loss = torch.zeros(1, device="cuda")
+    fgs.prior_train_step(ctx, dev(x), dev(t), wd, adam, loss=loss, grad_out=grad)
+    gref, L = oracle.mlp_bwd(x, w, t, bf16=True)
+    gexact, _ = oracle.mlp_bwd(x, w, t, bf16=False)
+    assert abs(float(loss) - L) <= MLP_TOL * L
+    np.testing.assert_array_equal(host(wd), w)  # lr = 0
+    gg = host(grad)
+    offs = np.cumsum([0, 256 * 260, 256, 256 * 256, 256, 4 * 256, 4])
+    for k, name in enumerate(("W1", "b1", "W2", "b2", "W3", "b3")):
+        sl = slice(offs[k], offs[k + 1])
+        check_mlp(gg[sl], gref[sl], gexact[sl], name)
+    assert adam.step == 1
+
+
+def test_adam_update_of_the_weights(fgs, ctx):
+    """Two steps: the second update equals Adam (bias corrections for step 2) applied on the host
+    to the moments and gradient of that step."""
+    import torch
+    rows = 256
+    x = feature_rows(30, rows)
+    t = synth.rng(31).normal(0, 1, (rows, 4)).astype(np.float32)
+    wd = dev(random_weights(6))
+    adam = fgs.PriorAdam.like(wd, lr=1e-3)
+    grad = torch.zeros_like(wd)
+    fgs.prior_train_step(ctx, dev(x), dev(t), wd, adam, grad_out=grad)
+    w0, m0, v0 = (host(a).astype(np.float64) for a in (wd, adam.m, adam.v))
+    fgs.prior_train_step(ctx, dev(x), dev(t), wd, adam, grad_out=grad)
+    g = host(grad).astype(np.float64)
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    m1 = b1 * m0 + (1 - b1) * g
+    v1 = b2 * v0 + (1 - b2) * g * g
+    expect = w0 - 1e-3 * (m1 / (1 - b1 ** 2)) / (np.sqrt(v1 / (1 - b2 ** 2)) + 1e-8)
+    big = np.abs(g) > 1e-6 * np.abs(g).max()
+    err = np.abs(host(wd) - expect)
+    assert np.all(err[big] <= 1e-5 * 1e-3 + 2 * np.spacing(np.abs(expect[big]).astype(np.float32)))
+
+
+def test_training_lowers_the_loss(fgs, ctx):
+    """300 full-batch steps on targets that are a smooth function of the features."""
+    import torch
+    rows = 2000
+    x = feature_rows(40, rows)
+    t = np.stack([np.tanh(x[:, :64].mean(1) - 3), x[:, 256] - 2.5, np.sin(x[:, 100]), x[:, 257] * 3], 1)
+    t = t.astype(np.float32)
+    wd = dev(random_weights(7, scale=0.5))
+    adam = fgs.PriorAdam.like(wd, lr=1e-3)
+    losses = torch.zeros(300, device="cuda")
+    xd, td = dev(x), dev(t)
+    for k in range(300):
+        fgs.prior_train_step(ctx, xd, td, wd, adam, loss=losses[k:k + 1])
+    ls = host(losses)
+    assert np.all(np.isfinite(ls)) and ls[-1] < 0.2 * ls[0]
+
+
+def quat_to_rot(q):
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def test_seeding_with_the_prior(fgs, ctx):
+    """A network whose output is its bias b3 = (log 1.5, log 1.2, log 0.5, 1.0): high-frequency seeds
+    (alpha_h = 1) take it in every tile with at least 4 valid-depth pixels; low-frequency seeds
+    (alpha_l = 4) fall back, since log 0.5 lies farther than log 4 from log 4. The seed set and the
+    seed arrays equal plain seeding; prior seeds get log(d / fx) + b3 on the camera axes, the
+    camera-to-world rotation and the logit b3[3]; fallback seeds keep the radius rule."""
+    import torch
+    import test_oracle_render as tor
+    R = tor.rot_of(np.array([0.9, 0.2, -0.3, 0.1]))
+    cam = synth.Camera(640, 480, 525.0, 525.0, 319.5, 239.5, R=R, t=[0.3, -0.2, 1.1])
+    rgb, depth = synth.rgbd_frame(8)
+    depth[:40, :100] = np.nan  # tiles without valid depth
+    w = np.zeros(oracle.MLP_PARAMS, np.float32)
+    b3 = np.array([np.log(1.5), np.log(1.2), np.log(0.5), 1.0], np.float32)
+    w[-4:] = b3
+    cap = 100_000
+    plain_p = torch.zeros((14, cap), device="cuda")
+    prior_p = torch.zeros((14, cap), device="cuda")
+    base = fgs.SeedOpts(opacity_logit=-0.5)
+    a = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, base, capacity=cap, params=plain_p)
+    o = fgs.SeedOpts(opacity_logit=-0.5, use_prior=1, prior=dev(w))
+    b = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, o, capacity=cap, params=prior_p)
+    n = a["n"]
+    assert b["n"] == n
+    for k in ("pixel", "is_high", "radius"):
+        np.testing.assert_array_equal(host(a[k])[:n], host(b[k])[:n], err_msg=k)
+    for k in ("mean", "rgb"):
+        np.testing.assert_array_equal(host(a[k])[:, :n], host(b[k])[:, :n], err_msg=k)
+    np.testing.assert_array_equal(host(a["tile_count"]), host(b["tile_count"]))
+    pa, pb = host(plain_p)[:, :n], host(prior_p)[:, :n]
+    np.testing.assert_array_equal(pb[0:3], pa[0:3])
+    np.testing.assert_array_equal(pb[11:14], pa[11:14])
+    pix = host(a["pixel"])[:n]
+    high = host(a["is_high"])[:n].astype(bool)
+    used = host(b["from_prior"])[:n].astype(bool)
+    # expected decisions: valid-depth count per 16x16 tile, class of the seed
+    W, H = 640, 480
+    dv = np.isfinite(depth) & (depth >= 0.1) & (depth <= 10.0)
+    tiles = dv.reshape(H // 16, 16, W // 16, 16).sum(axis=(1, 3)).ravel()
+    tid = (pix // W // 16) * (W // 16) + (pix % W) // 16
+    expect = high & (tiles[tid] >= 4)
+    np.testing.assert_array_equal(used, expect)
+    assert used.any() and (~used).any()
+    d = depth.ravel()[pix].astype(np.float32)
+    base_ls = np.log(d / np.float32(525.0))
+    np.testing.assert_allclose(pb[3:6, used], (base_ls[None, used] + b3[:3, None]), rtol=0, atol=2e-6)
+    np.testing.assert_array_equal(pb[10, used], b3[3])
+    Rq = quat_to_rot(pb[6:10, np.argmax(used)].astype(np.float64))
+    np.testing.assert_allclose(Rq, np.asarray(R, np.float64).reshape(3, 3).T, atol=1e-6)
+    np.testing.assert_array_equal(pb[3:11, ~used], pa[3:11, ~used])

@@ -90,6 +90,48 @@ def test_small_scene_forward_backward(fgs, ctx, seed):
     check_backward(fgs, ctx, p, cam, opts, out, ref, seed)
 
 
+def test_full_size_workload_sampled(fgs, ctx):
+    """The 300k-gaussian 1200x680 workload (20% of the gaussians in 8 blobs), 16x16 tiles as the
+    benchmark runs it: the forward planes at 4,000 sampled pixels against the oracle rendering those
+    pixels one by one, and all 14 parameter gradients of an upstream gradient that is non-zero at
+    the sampled pixels only, against the oracle's backward over the same pixels."""
+    cam = synth.camera_replica()
+    p = synth.scene_replica(0)
+    n = p.shape[1]
+    p64 = p.astype(np.float64)
+    opts = fgs.RenderOpts()
+    pd = params_dev(p)
+    out = fgs.render(ctx, pd, n, cam, opts)
+    W, H = cam.width, cam.height
+    P = W * H
+    g = synth.rng(77)
+    pix = np.sort(g.choice(P, 4000, replace=False))
+    ref = oracle.render_fwd(p64, cam, oracle_opts(opts), mode=0, pix=pix, amb_rel=1e-5)
+    ok = ~ref["amb"]
+    assert ref["n_amb"] <= 0.01 * pix.size, f"{ref['n_amb']} ambiguous sampled pixels"
+    rgb = host(out["rgb"]).reshape(3, P)[:, pix]
+    assert_close_rel(rgb, ref["rgb"], FWD_TOL, ok, "rgb")
+    for k in ("depth", "alpha", "T_final"):
+        assert_close_rel(host(out[k]).ravel()[pix], ref[k], FWD_TOL, ok, k)
+    np.testing.assert_array_equal(host(out["n_contrib"]).ravel()[pix][ok], ref["n_contrib"][ok])
+    keep = pix[ok]
+    gr = np.zeros((3, P), np.float32)
+    gd = np.zeros(P, np.float32)
+    ga = np.zeros(P, np.float32)
+    gr[:, keep] = g.normal(size=(3, keep.size))
+    gd[keep] = g.normal(size=keep.size)
+    ga[keep] = g.normal(size=keep.size)
+    grad = dev(np.zeros((14, n), np.float32))
+    fgs.render_bwd(ctx, pd, n, cam, opts, out["state"], dev(gr), dev(gd), dev(ga), grad)
+    ctx.check()
+    gref, _ = oracle.render_bwd(p64, cam, gr[:, keep], gd[keep], ga[keep], oracle_opts(opts), mode=0, pix=keep)
+    gg = host(grad)
+    assert np.count_nonzero(gref[10]) > 1000  # the sample reaches many gaussians
+    for name, rows in (("mean", slice(0, 3)), ("log_scale", slice(3, 6)), ("quat", slice(6, 10)),
+                       ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+        assert_close_rel(gg[rows], gref[rows], GRAD_TOL, None, f"d{name}", floor=GRAD_FLOOR)
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (8, 8)])
 def test_tile_shape_independence(fgs, ctx, tile):
     """P6: every rasterizer tile shape gives the oracle's image (ragged 70x50 frame)."""
