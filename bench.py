@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=10, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the keyframe-window, seeding and learned-prior measurements")
+    ap.add_argument("--prior-train-scenes", type=int, default=50)
+    ap.add_argument("--prior-test-scenes", type=int, default=20)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -65,6 +69,112 @@ def cpu_baseline(iters: int) -> dict:
     return {"value": iters / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": f"{iters} full iterations (fwd + L1 loss + bwd + Adam, FP64) of the 300k-gaussian "
                       f"1200x680 workload, {dt:.1f} s"}
+
+
+def raster_roofline(rep, kernel_prefix):
+    """Dominant rasterizer kernel of a profile report against the FP32 vector peak."""
+    cnt = rep["counts"]
+    fwd = max(cnt["forwards"], 1)
+    E_f = cnt["pairs_examined"] / fwd
+    E_c = cnt["pairs_blended"] / fwd
+    ms = {k: rep[k][0] / max(rep[k][1], 1) for k in ("raster_fwd", "raster_bwd")}
+    launches = {k: max(rep[k][1], 1) for k in ("raster_fwd", "raster_bwd")}
+    # flops per launch: one launch covers forwards/launches views
+    per = fwd / launches["raster_fwd"]
+    flops = {"raster_fwd": (F_FWD_EXAMINED * E_f + F_FWD_BLENDED * E_c) * per, "raster_bwd": F_BWD_BLENDED * E_c * per}
+    dom = max(ms, key=lambda k: ms[k])
+    achieved = flops[dom] / (ms[dom] / 1e3) / 1e12
+    return {"bound": "alu", "kernel": f"{kernel_prefix}{dom.split('_')[1]}", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
+            "traffic": None, "avg_ms": round(ms[dom], 4), "flops_per_launch": flops[dom]}
+
+
+def window_extra(F, ctx, steps: int = 20) -> dict:
+    """The 8-view keyframe window (four 640x480, four 1200x680 views of a 500k-gaussian box scene):
+    autotuned tile and grid shapes, graph-replayed steps (fwd + loss + bwd + Adam)."""
+    import torch
+
+    import synth
+    from paper_2503_01109_amd import autotune
+    cams = synth.window_cameras(0)
+    p = synth.scene_window(0)
+    n = p.shape[1]
+    params = torch.as_tensor(p).cuda().contiguous()
+    tscene = torch.as_tensor(synth.scene_window(1)).cuda().contiguous()
+    targets = []
+    for c in cams:
+        t = F.render(ctx, tscene, n, c, F.RenderOpts(), aux=False)
+        targets.append((t["rgb"], t["depth"]))
+    del tscene
+    opts = F.RenderOpts()
+    tune = autotune.tune_window(F, ctx, cams, params, n, targets, opts, steps=3)
+    win = F.Window(ctx, cams, tune["tiles"], tune["blocks_per_cu"])
+    adam = F.Adam.like(params)
+    loss = torch.zeros(len(cams), device="cuda")
+    for _ in range(3):
+        win.step(params, n, adam, targets, opts, loss=loss, graph=True)
+    ctx.check()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        win.step(params, n, adam, targets, opts, loss=loss, graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1) / steps
+    ctx.profile(1)
+    for _ in range(3):
+        win.step(params, n, adam, targets, opts, loss=loss, graph=True)  # profiled steps run eagerly
+    ctx.check()
+    rep = ctx.profile_report()
+    ctx.profile(0)
+    win.close()
+    return {"workload": "8-view keyframe window, 500k gaussians (6x6x4 m box, 20% in 8 blobs), 4x640x480 f=525 + "
+                        "4x1200x680 f=600", "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 3),
+            "views_per_s": round(8e3 / ms, 2), "graph": True,
+            "tiles": [f"{a}x{b}" for a, b in tune["tiles"]], "blocks_per_cu": tune["blocks_per_cu"],
+            "tuning_ms": {k: round(v, 4) for k, v in tune["ms"].items()},
+            "roofline": raster_roofline(rep, "k_raster_queue_")}
+
+
+def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
+    """Fourier seeding of a 640x480 synthetic RGB-D frame and 200 mapping iterations on it."""
+    import numpy as np
+    import torch
+
+    from paper_2503_01109_amd import prior
+    fr = prior.frame_of(0)
+    rgb, depth = torch.as_tensor(fr.rgb).cuda(), torch.as_tensor(fr.depth).cuda()
+    o = F.SeedOpts()
+    cap = 640 * 480 // 4 + 2048
+    params = torch.zeros((14, cap), device="cuda")
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        F.seed_gaussians(ctx, rgb, depth, fr.cam, o, capacity=cap, params=params, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ctx.check()
+    run = prior.seed_and_map(F, ctx, fr, iters, o)
+    return {"workload": "Fourier seeding of a 640x480 RGB-D frame (D0 = 30, m = 2, n = 8) + 200 mapping iterations",
+            "seeding_us_median": round(float(np.median(times)) * 1e3, 2), "seeds": run.n,
+            "map_ms_per_iter": round(float((run.ms[-1] - run.seed_ms) / iters), 4),
+            "total_ms": round(float(run.ms[-1]), 3), "final_psnr_db": round(float(run.psnr[-1]), 3)}
+
+
+def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
+    """Learned prior: trained on 100 tiles of each of n_train converged maps, compared with the
+    plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on n_test held-out frames."""
+    from paper_2503_01109_amd import prior
+    r = prior.run_experiment(F, ctx, range(1000, 1000 + n_train), range(5000, 5000 + n_test), iters=200,
+                             tiles_per_scene=100, train_steps=2000)
+    s = r["summary"]
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
 
 def main():
@@ -142,7 +252,7 @@ def main():
         "raster_bwd": F_BWD_BLENDED * E_c,
     }
     stages = {k: v for k, v in rep2.items() if k != "counts"}
-    kernel_ms = {k: (t / max(l, 1)) for k, (t, l) in rep.items() if k != "counts"}
+    kernel_ms = {k: v[0] / max(v[1], 1) for k, v in rep.items() if k != "counts"}
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: kernel_ms[k])
     achieved = flops[dom] / (kernel_ms[dom] / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": f"k_raster_{dom.split('_')[1]}", "achieved": round(achieved, 3),
@@ -171,6 +281,14 @@ def main():
                   "entries_staged_per_iter": cnt["entries_staged"] / fwd},
         "final_loss": float(loss), "final_psnr": float(psnr),
     }
+    if not args.no_extras:
+        line["window"] = window_extra(F, ctx)
+        line["seeding"] = seeding_extra(F, ctx)
+        pr = prior_extra(F, ctx, args.prior_train_scenes, args.prior_test_scenes)
+        line["learned_prior"] = pr
+        line["ms_to_target_psnr"] = {"learned": pr["prior_ms_mean"], "plain": pr["plain_ms_mean"],
+                                     "target": "plain method's PSNR after 200 iterations - 0.1 dB",
+                                     "held_out_scenes": pr["scenes"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
     print(json.dumps(line), flush=True)

@@ -11,11 +11,11 @@
  *  - network: h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), y = W3 h2 + b3, GELU(a) =
  *    a (1 + erf(a / sqrt 2)) / 2, sizes 260 -> 256 -> 256 -> 4. Every product rounds its operands
  *    to bfloat16 (round to nearest even) and accumulates in FP32 on the matrix cores;
- *  - outputs: y[0..2] are log-scale offsets from log(d / fx) (d: the seed's depth) along the
- *    camera's x, y and viewing axes, y[3] is the opacity logit;
- *  - fallback: a tile with fewer than 4 valid-depth pixels, or a prediction farther than log 4
- *    from log(alpha) on some axis (alpha: the seed's radius factor of Eq. 11), keeps the radius
- *    rule and the constant opacity.
+ *  - outputs: y[0..2] are log-scale offsets from the log of the seed's Eq. 11 radius
+ *    (alpha d / fx, alpha by the seed's frequency class) along the camera's x, y and viewing axes;
+ *    y[3] is the opacity logit;
+ *  - fallback: a tile with fewer than 4 valid-depth pixels, or an offset larger than log 4 in
+ *    magnitude on some axis, keeps the radius rule and the constant opacity.
  *
  * Weights are one packed FP32 vector of FGS_PRIOR_PARAMS floats (device): W1 [256][260] row-major,
  * b1 [256], W2 [256][256], b2 [256], W3 [4][256], b3 [4]. All calls enqueue on the context's

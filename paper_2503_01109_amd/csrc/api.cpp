@@ -970,14 +970,11 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
         PriorApplyK pk;
         pk.tiles_x = tx;
         pk.W = W;
-        pk.fx = cam->fx;
-        pk.alpha_h = o->alpha_h;
-        pk.alpha_l = o->alpha_l;
         pk.max_dev = (float)log(4.0);
         pk.min_valid = 4;
         camera_to_world_quat(cam->R_cw, pk.q);
         const int64_t S = out->params.stride;
-        launch_prior_apply(pk, seed_count_ptr(ctx->seed_ws.p, W, H), out->capacity, out->pixel, out->is_high, depth,
+        launch_prior_apply(pk, seed_count_ptr(ctx->seed_ws.p, W, H), out->capacity, out->pixel,
                            ctx->prior_y.as<float>(), ctx->prior_valid.as<int32_t>(), out->params.log_scale,
                            out->params.quat, out->params.opacity_logit, S, out->from_prior, ctx->stream);
     }

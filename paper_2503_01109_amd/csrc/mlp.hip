@@ -362,8 +362,7 @@ __global__ void k_mlp_adam(float *__restrict__ w, const float *__restrict__ g, f
 /* ------------------------------------- prior on seeds ------------------------------------- */
 
 __global__ void k_prior_apply(PriorApplyK pk, const uint32_t *__restrict__ count, int64_t capacity,
-                              const int32_t *__restrict__ pixel, const uint8_t *__restrict__ is_high,
-                              const float *__restrict__ depth, const float *__restrict__ y,
+                              const int32_t *__restrict__ pixel, const float *__restrict__ y,
                               const int32_t *__restrict__ n_valid, float *__restrict__ log_scale,
                               float *__restrict__ quat, float *__restrict__ logit, int64_t S,
                               uint8_t *__restrict__ from_prior)
@@ -373,16 +372,16 @@ __global__ void k_prior_apply(PriorApplyK pk, const uint32_t *__restrict__ count
         const int32_t p = pixel[i];
         const int px = p % pk.W, py = p / pk.W;
         const int64_t t = (int64_t)(py / 16) * pk.tiles_x + px / 16;
-        const float la = logf(is_high[i] ? pk.alpha_h : pk.alpha_l);
         bool use = n_valid[t] >= pk.min_valid;
         float o[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) o[k] = y[t * 4 + k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) use = use && isfinite(o[k]) && fabsf(o[k] - la) <= pk.max_dev;
+        for (int k = 0; k < 3; ++k) use = use && isfinite(o[k]) && fabsf(o[k]) <= pk.max_dev;
         use = use && isfinite(o[3]);
         if (use) {
-            const float base = logf(depth[p] / pk.fx);
+            // the radius rule's log-radius, written by the seed emission on every axis
+            const float base = log_scale[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k) log_scale[k * S + i] = base + o[k];
 #pragma unroll
@@ -537,13 +536,12 @@ void launch_mlp_train_step(const MlpWS &ws, int64_t rows, const float *x, const 
 }
 
 void launch_prior_apply(const PriorApplyK &pk, const uint32_t *count, int64_t capacity, const int32_t *pixel,
-                        const uint8_t *is_high, const float *depth, const float *y, const int32_t *n_valid,
-                        float *log_scale, float *quat, float *logit, int64_t stride, uint8_t *from_prior,
-                        hipStream_t s)
+                        const float *y, const int32_t *n_valid, float *log_scale, float *quat, float *logit,
+                        int64_t stride, uint8_t *from_prior, hipStream_t s)
 {
     if (capacity <= 0) return;
-    hipLaunchKernelGGL(k_prior_apply, dim3(grid_for(capacity)), dim3(256), 0, s, pk, count, capacity, pixel, is_high,
-                       depth, y, n_valid, log_scale, quat, logit, stride, from_prior);
+    hipLaunchKernelGGL(k_prior_apply, dim3(grid_for(capacity)), dim3(256), 0, s, pk, count, capacity, pixel, y,
+                       n_valid, log_scale, quat, logit, stride, from_prior);
 }
 
 }  // namespace fgs

@@ -57,19 +57,18 @@ void launch_mlp_train_step(const MlpWS &ws, int64_t rows, const float *x, const 
 
 struct PriorApplyK {
     int tiles_x, W;
-    float fx;
-    float alpha_h, alpha_l, max_dev;  // fallback when |y - log alpha| > max_dev on an axis
-    float q[4];                       // camera-to-world rotation (w, x, y, z): local axes = camera axes
-    int32_t min_valid;                // fallback when a tile has fewer valid-depth pixels
+    float max_dev;    // fallback when a predicted offset exceeds this in magnitude
+    float q[4];       // camera-to-world rotation (w, x, y, z): local axes = camera axes
+    int32_t min_valid;  // fallback when a tile has fewer valid-depth pixels
 };
 
 // Rewrites the seeds' log-scales, rotation and opacity logit from per-tile predictions y
-// [tiles][4] (offsets from log(d / fx) on the camera's x, y and viewing axes, opacity logit),
-// keeping the radius rule where the tile or the prediction is rejected. count: number of seeds
-// (device), capped by capacity. from_prior (nullable): 1 where the prior was used.
+// [tiles][4] (offsets from the radius rule's log-radius on the camera's x, y and viewing axes,
+// opacity logit), keeping the radius rule where the tile or the prediction is rejected. The seed
+// emission must have written log(radius) into log_scale. count: number of seeds (device), capped
+// by capacity. from_prior (nullable): 1 where the prior was used.
 void launch_prior_apply(const PriorApplyK &pk, const uint32_t *count, int64_t capacity, const int32_t *pixel,
-                        const uint8_t *is_high, const float *depth, const float *y, const int32_t *n_valid,
-                        float *log_scale, float *quat, float *logit, int64_t stride, uint8_t *from_prior,
-                        hipStream_t s);
+                        const float *y, const int32_t *n_valid, float *log_scale, float *quat, float *logit,
+                        int64_t stride, uint8_t *from_prior, hipStream_t s);
 
 }  // namespace fgs

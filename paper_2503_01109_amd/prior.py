@@ -5,8 +5,9 @@ Eq. 11 radii, one initial opacity) and mapped for a fixed number of iterations a
 (the colour and depth L1 terms of the mapping loss); what the gaussians converged to, per 16x16
 tile, is the network's target:
 
-* log-scale offsets: each seed's converged log-scales sorted in descending order, minus
-  log(d / fx) with d its depth, averaged over the tile's seeds (three values);
+* log-scale offsets: each seed's converged log-scales sorted in descending order, minus the log
+  of its Eq. 11 radius (alpha d / fx with alpha by its frequency class), averaged over the
+  tile's seeds (three values);
 * opacity: the tile's mean converged opacity logit.
 
 The network (fgs_prior.h) is trained on the GPU by the library's own forward, backward and Adam
@@ -83,15 +84,17 @@ def seed_and_map(F, ctx, frame: Frame, iters: int, seed_opts, lr=MAP_LR, opts=No
     return run
 
 
-def tile_targets(run: MapRun, frame: Frame):
-    """Per 16x16 tile: mean over the tile's seeds of (descending converged log-scales - log(d/fx))
-    and of the converged opacity logit. Returns (targets [T, 4], seeds per tile [T])."""
+def tile_targets(run: MapRun, frame: Frame, alpha_h: float = 1.0, alpha_l: float = 4.0):
+    """Per 16x16 tile: mean over the tile's seeds of (descending converged log-scales - the log of
+    the seed's radius-rule radius) and of the converged opacity logit. Returns (targets [T, 4],
+    seeds per tile [T])."""
     H, W = frame.depth.shape
     tx, ty = (W + 15) // 16, (H + 15) // 16
     p = run.params[:, :run.n].cpu().numpy().astype(np.float64)
     pix = run.pixel
     d = frame.depth.ravel()[pix].astype(np.float64)
-    off = -np.sort(-p[3:6], axis=0) - np.log(d / float(frame.cam.fx))[None, :]
+    alpha = np.where(run.is_high, alpha_h, alpha_l)
+    off = -np.sort(-p[3:6], axis=0) - np.log(alpha * d / float(frame.cam.fx))[None, :]
     tile = (pix // W // 16) * tx + (pix % W) // 16
     T = tx * ty
     cnt = np.bincount(tile, minlength=T).astype(np.float64)
@@ -113,7 +116,7 @@ def build_dataset(F, ctx, scenes, iters: int = 200, tiles_per_scene: int = 100, 
     for s in scenes:
         fr = frame_of(s)
         run = seed_and_map(F, ctx, fr, iters, seed_opts)
-        tgt, cnt = tile_targets(run, fr)
+        tgt, cnt = tile_targets(run, fr, seed_opts.alpha_h, seed_opts.alpha_l)
         ok = np.flatnonzero(cnt > 0)
         pick = np.sort(g.choice(ok, size=min(tiles_per_scene, ok.size), replace=False))
         ids = torch.as_tensor(pick.astype(np.int32)).cuda()
