@@ -176,33 +176,35 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         __syncthreads();
         const int cnt = min((uint32_t)NT, range.y - b);
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
+        // Branch-free per pair: every lane evaluates the entry and the decisions select what is
+        // kept (the arithmetic of a kept pair is the same as with branches); the wave leaves the
+        // list once all of its pixels are done.
         for (int i = 0; i < len; ++i) {
-            if (done) continue;
+            if (__ballot(!done) == 0) break;
             const int k = slist[wid][i];
             const float4 a4 = sa[k];
             const float dx = px - a4.x, dy = py - a4.y;
             const float4 b4 = sb[k];
             const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
-            if (Q > cut2) continue;
-            ++ntest;
+            const bool near = !done && !(Q > cut2);
             const float G = __expf(-0.5f * Q);
             const float alpha = fminf(rk.alpha_max, b4.y * G);
-            if (alpha < rk.alpha_min) continue;
             const float Tn = T * (1.0f - alpha);
-            if (Tn < rk.T_min) {
-                done = true;
-                continue;
-            }
-            const float w = alpha * T;
+            const bool take = near && !(alpha < rk.alpha_min);
+            const bool stop = take && Tn < rk.T_min;
+            const bool blend = take && !stop;
+            const float w = blend ? alpha * T : 0.0f;
             const float4 c4 = sc[k];
             C0 += w * c4.x;
             C1 += w * c4.y;
             C2 += w * c4.z;
             D += w * b4.z;
             A += w;
-            T = Tn;
-            ++ncon;
-            last = b + k - range.x + 1;
+            T = blend ? Tn : T;
+            done = done || stop;
+            ntest += near ? 1u : 0u;
+            ncon += blend ? 1 : 0;
+            last = blend ? b + k - range.x + 1 : last;
         }
     }
     if (V.counts) {
@@ -325,7 +327,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
                     if (!(alpha < rk.alpha_min)) {
                         contrib = true;
                         const float4 c4 = sc[k];
-                        const float inv = 1.0f / (1.0f - alpha);
+                        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
                         const float Ti = T * inv;
                         const float w = alpha * Ti;
                         const float dal = Ti * (gC0 * c4.x + gC1 * c4.y + gC2 * c4.z + gD * b4.z) -
