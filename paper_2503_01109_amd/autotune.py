@@ -9,8 +9,8 @@ queue. Both are picked by timing the real window step on the real scene:
 1. per resolution, each tile shape is timed on a window holding only that resolution's views;
 2. with the winning shapes, each grid size is timed on the whole window;
 3. the chosen configuration is checked against the default one (16x16 tiles, 4 workgroups per
-   compute unit): the same per-view losses, and a summed gradient within a few times the
-   default's own run-to-run spread (FP32 atomics accumulate in a different order every run).
+   compute unit): the same per-view losses, and the same summed gradient per parameter row in
+   relative L2 error (FP32 atomics accumulate in a different order every run).
 
 Results are cached in a JSON file keyed by device name, resolution and gaussian count (rounded
 to a power of two), so a later run picks them up without timing.
@@ -68,27 +68,22 @@ def _window_result(F, ctx, cams, tiles, bpc, params, n, targets, opts):
     return loss, grad
 
 
-def check_against_default(F, ctx, cams, tiles, bpc, params, n, targets, opts, tol=1e-5, spread_factor=8.0):
+def check_against_default(F, ctx, cams, tiles, bpc, params, n, targets, opts, tol=1e-5, l2_tol=1e-4, max_tol=1e-2):
     """Raise AssertionError unless the configuration reproduces the default one: per-view losses
-    within tol relative, and per parameter row a gradient that differs from the default's by at
-    most spread_factor times the default's own run-to-run spread (FP32 atomics in a different
-    order) plus 1e-6 of the row's largest entry."""
-    import torch
+    within tol relative, and per parameter row a gradient within l2_tol relative L2 error and
+    max_tol of the row's largest entry (L1-loss gradients cancel heavily, so FP32 atomics in a
+    different order move single entries far more than the row as a whole)."""
     l0, g0 = _window_result(F, ctx, cams, None, 0, params, n, targets, opts)
-    _, g0b = _window_result(F, ctx, cams, None, 0, params, n, targets, opts)
     l1, g1 = _window_result(F, ctx, cams, tiles, bpc, params, n, targets, opts)
     dl = (l1 - l0).abs() / l0.abs().clamp_min(1e-30)
     if float(dl.max()) > tol:
         raise AssertionError(f"autotuned window: loss differs from the default by {float(dl.max()):.2e}")
-    g0, g0b, g1 = g0.double(), g0b.double(), g1.double()
-    scale = g0.abs().amax(dim=1)
-    spread = (g0b - g0).abs().amax(dim=1)
-    err = (g1 - g0).abs().amax(dim=1)
-    bad = err > spread_factor * spread + 1e-6 * scale
-    if bool(bad.any()):
-        rows = torch.nonzero(bad).flatten().tolist()
-        raise AssertionError(f"autotuned window: gradient rows {rows} differ from the default by "
-                             f"{(err / scale).tolist()} of their scale (run-to-run spread {(spread / scale).tolist()})")
+    g0, g1 = g0.double(), g1.double()
+    l2 = (g1 - g0).norm(dim=1) / g0.norm(dim=1).clamp_min(1e-300)
+    worst = (g1 - g0).abs().amax(dim=1) / g0.abs().amax(dim=1).clamp_min(1e-300)
+    if bool((l2 > l2_tol).any()) or bool((worst > max_tol).any()):
+        raise AssertionError(f"autotuned window: gradient rows differ from the default: relative L2 {l2.tolist()}, "
+                             f"max error / row max {worst.tolist()}")
 
 
 def tune_window(F, ctx, cams, params, n: int, targets, opts=None, steps: int = 5, cache: str | None = DEFAULT_CACHE,

@@ -63,6 +63,10 @@ struct fgs_ctx {
     std::string err;
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rec_by_id, rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
+    DBuf rect_sorted, start_rank;
+    // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
+    DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words;
+    int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
     DBuf words;  // status words (ST_WORDS) + small device scalars
     int64_t ws_n = -1, ws_cap = -1;
     // mapping-step buffers
@@ -93,6 +97,8 @@ constexpr int W_STATUS = 0;            // ST_WORDS u32
 constexpr int W_NDEV = ST_WORDS;       // n for the depth sort
 constexpr int W_NPAIRS = ST_WORDS + 1; // pairs to sort
 constexpr int W_DSCALE = ST_WORDS + 2; // float: 1/P_v of the depth term
+constexpr int W_NSUP = ST_WORDS + 3;   // super-tile pairs to sort
+constexpr int W_KTOTAL = ST_WORDS + 4; // (tile, gaussian) pairs counted by the projection
 constexpr int W_TOTAL = ST_WORDS + 8;
 
 fgs_status fail(fgs_ctx *ctx, fgs_status s, const char *fmt, ...)
@@ -222,6 +228,8 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->idB.ensure(N * 4));
     HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks(nn) + 2) * 4));
     HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
+    HIP_TRY(ctx, ctx->rect_sorted.ensure(N * sizeof(uint2)));
+    HIP_TRY(ctx, ctx->start_rank.ensure((size_t)emit_chunks((int64_t)C) * 4));
     HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
@@ -236,6 +244,39 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     ctx->ws_n = nn;
     ctx->ws_cap = cc;
     return FGS_OK;
+}
+
+// Workspace of the tile-list expansion for nsup super-tiles, T tiles and cap pairs (grown on the
+// context's stream after it drained).
+fgs_status ensure_bin(fgs_ctx *ctx, int64_t nsup, int64_t T, int64_t cap)
+{
+    if (nsup <= ctx->bin_nsup && T <= ctx->bin_T && cap <= ctx->bin_cap) return FGS_OK;
+    const int64_t ns = std::max(nsup, ctx->bin_nsup), tt = std::max(T, ctx->bin_T), cc = std::max(cap, ctx->bin_cap);
+    const int64_t mc = bin_max_chunks(cc, ns);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, ctx->bin_sranges.ensure((size_t)ns * 8));
+    HIP_TRY(ctx, ctx->bin_cstart.ensure((size_t)(ns + 1) * 4));
+    HIP_TRY(ctx, ctx->bin_csuper.ensure((size_t)mc * 4));
+    HIP_TRY(ctx, ctx->bin_chist.ensure((size_t)mc * kSuper * kSuper * 4));
+    HIP_TRY(ctx, ctx->bin_tile_total.ensure((size_t)tt * 4));
+    HIP_TRY(ctx, ctx->bin_words.ensure(64));
+    ctx->bin_nsup = ns;
+    ctx->bin_T = tt;
+    ctx->bin_cap = cc;
+    return FGS_OK;
+}
+
+BinWS bin_ws(fgs_ctx *ctx)
+{
+    BinWS b;
+    b.cstart = ctx->bin_cstart.as<uint32_t>();
+    b.csuper = ctx->bin_csuper.as<uint32_t>();
+    b.chist = ctx->bin_chist.as<uint32_t>();
+    b.tile_total = ctx->bin_tile_total.as<uint32_t>();
+    b.nchunks = ctx->bin_words.as<uint32_t>();
+    b.ok = ctx->bin_words.as<uint32_t>() + 1;
+    b.max_chunks = bin_max_chunks(ctx->bin_cap, ctx->bin_nsup);
+    return b;
 }
 
 SortWS sort_ws(fgs_ctx *ctx, int64_t elems)
@@ -380,18 +421,25 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
+    const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
+    const int supers_x = (rk.tiles_x + kSuper - 1) / kSuper, supers_y = (rk.tiles_y + kSuper - 1) / kSuper;
+    const int nsup = supers_x * supers_y;
+    if ((st = ensure_bin(ctx, nsup, L.T, L.cap)) != FGS_OK) return st;
     hipStream_t s = ctx->stream;
     const CamK ck = to_camk(cam);
-    const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
     const ParamsK pk = to_pk(g);
     const StatePtrs sp = state_ptrs(state, L);
     uint32_t *words = ctx->words.as<uint32_t>();
-    uint32_t *ndev = words + W_NDEV, *npairs = words + W_NPAIRS;
+    uint32_t *ndev = words + W_NDEV, *npairs = words + W_NPAIRS, *nsup_pairs = words + W_NSUP;
+    uint32_t *ktotal = words + W_KTOTAL;
+    const BinWS bw = bin_ws(ctx);
+    const int sbits = key_bits_for(nsup);
+    uint32_t *svals = (sbits + 7) / 8 == 1 ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
 
     {
         Stage st_(ctx, "project");
         launch_project(pk, ck, rk, ctx->rec_by_id.as<Rec>(), ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
-                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, s);
+                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, kSuperShift, ktotal, s);
     }
     {
         Stage st_(ctx, "depth_sort");
@@ -399,9 +447,10 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
                           ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n), s);
     }
     {
+        // one pair per covered super-tile, in depth order
         Stage st_(ctx, "bin");
         launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx),
-                           s);
+                           ktotal, s);
     }
     if (K_check) {
         fgs_status st2 = read_words(ctx);
@@ -412,16 +461,25 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     {
         Stage st_(ctx, "bin");
         launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
-                    ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n, rk.tiles_x, L.cap,
-                    ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), sp.rec, status_words(ctx), npairs,
-                    host_status, s);
+                    ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap,
+                    ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), sp.rec, ctx->rect_sorted.as<uint2>(),
+                    ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs, nullptr, s);
     }
+    const uint2 *sranges = ctx->bin_sranges.as<uint2>();
     {
+        // super-tile lists, then the tile ranges
         Stage st_(ctx, "tile_sort");
-        uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
-                                           ctx->pkB.as<uint32_t>(), ctx->pvB.as<uint32_t>(), sp.vals, npairs, L.cap,
-                                           key_bits_for(L.T), sort_ws(ctx, L.cap), s);
-        launch_ranges(keys, npairs, L.cap, sp.ranges, L.T, s);
+        const SortWS sws = sort_ws(ctx, L.cap);
+        uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
+                                           ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
+        const bool one_pass = sbits <= 8;
+        if (!one_pass) launch_ranges(keys, nsup_pairs, L.cap, ctx->bin_sranges.as<uint2>(), nsup, s);
+        launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr,
+                          ctx->rect_sorted.as<uint2>(), supers_x, nsup, s);
+        launch_bin_tiles(bw, supers_x, nsup, rk.tiles_x, rk.tiles_y, L.cap, ktotal, sp.ranges, status_words(ctx),
+                         npairs, host_status, s);
+        launch_bin_place(bw, svals, sranges, ctx->rect_sorted.as<uint2>(), supers_x, rk.tiles_x, rk.tiles_y,
+                         sp.ranges, sp.vals, s);
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");

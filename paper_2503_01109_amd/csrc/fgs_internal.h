@@ -88,10 +88,12 @@ int sort_blocks(int64_t cap);
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 
-// Projects every gaussian; writes n to *n_out (the element count of the depth sort).
+// Projects every gaussian; writes n to *n_out (the element count of the depth sort). count[i]
+// receives the number of tiles (shift 0) or super-tiles (tile rectangle >> shift) covered, and
+// *ktotal the number of (tile, gaussian) pairs.
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id,
-                    uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out,
-                    hipStream_t s);
+                    uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
+                    uint32_t *ktotal, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
@@ -101,19 +103,53 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             hipStream_t s);
 
 // Exclusive scan of count[ids[r]] over depth ranks r, by blocks: blocksums (scan_blocks(n) + 1
-// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs.
+// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs;
+// status[ST_PAIRS] receives *ktotal.
 int64_t scan_blocks(int64_t n);
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, hipStream_t s);
+                        uint32_t *status, const uint32_t *ktotal, hipStream_t s);
 
-// Emit one (tile, rank) pair per covered tile in depth order, and gather records into depth
-// order. offsets is scratch of n + 1 words (per-rank exclusive offsets). If the pairs exceed
+// Emit one (key, rank) pair per covered tile in depth order, and gather records into depth
+// order; with shift > 0 the keys are super-tiles (tile rectangle >> shift, keys_x super-tiles per
+// row). offsets is scratch of n + 1 words (per-rank exclusive offsets). If the pairs exceed
 // cap, nothing is emitted for sorting (*n_pairs_dev = 0) and the required count is recorded in
 // status. host_status (nullable, host-mapped): [0] = pairs, [1] |= overflow.
+// rect_sorted (n) receives the tile rectangles in depth order, start_rank (emit_chunks(cap)
+// words) the first rank of every emission chunk.
+int64_t emit_chunks(int64_t cap);
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t tiles_x, int64_t cap,
-                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev,
-                 uint32_t *host_status, hipStream_t s);
+                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap,
+                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint2 *rect_sorted, uint32_t *start_rank,
+                 uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s);
+
+// Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
+// are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by super-tile
+// into svals with ranges sranges; then:
+//   launch_bin_counts: chunk table and per-chunk tile counts;
+//   launch_bin_tiles:  prefixes over chunks and tiles, the tile ranges, and the capacity check of
+//                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
+//                      overflow);
+//   launch_bin_place:  every entry's depth rank into the lists of its tiles (vals, K entries).
+constexpr int kSuper = 4, kSuperShift = 2;
+struct BinWS {
+    uint32_t *cstart;      // nsup + 1
+    uint32_t *csuper;      // max_chunks
+    uint32_t *chist;       // max_chunks x kSuper^2
+    uint32_t *tile_total;  // T
+    uint32_t *nchunks;     // 1 word
+    uint32_t *ok;          // 1 word
+    int64_t max_chunks;
+};
+int64_t bin_max_chunks(int64_t cap, int64_t nsup);
+// digit_totals (nullable): the per-digit totals of a single-pass super-tile sort, from which the
+// super-tile ranges are written into sranges; else sranges holds them already.
+void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
+                       const uint2 *rect_sorted, int supers_x, int nsup, hipStream_t s);
+void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
+                      const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
+                      uint32_t *host_status, hipStream_t s);
+void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect_sorted,
+                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s);
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
                    int64_t T, hipStream_t s);

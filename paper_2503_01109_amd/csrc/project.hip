@@ -112,18 +112,39 @@ __device__ inline bool pixel_span(double c, double r, int32_t size, int32_t &lo,
     return true;
 }
 
+__device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
+                                int shift, int64_t i);
+
+// Projects every gaussian (one thread each): record, tile rectangle, count of covered tiles or
+// super-tiles, depth key; *ktotal (zero on entry) receives the number of (tile, gaussian) pairs.
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-          uint32_t *__restrict__ n_out)
+          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ ktotal)
 {
+    __shared__ uint32_t wsum[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n_out = (uint32_t)g.n;
-    if (i >= g.n) return;
+    uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian, summed into *ktotal
+    if (i < g.n) tiles = project_one(g, cam, rk, rec, rect, count, dkey, ids, shift, i);
+    for (int o = 32; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = tiles;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (t) atomicAdd(ktotal, t);
+    }
+}
+
+__device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
+                                int shift, int64_t i)
+{
     ids[i] = (uint32_t)i;
     Proj p;
     project_gaussian(g, i, cam, rk.lowpass, p);
-    uint32_t cnt = 0, key = 0xFFFFFFFFu;
+    uint32_t cnt = 0, key = 0xFFFFFFFFu, tiles = 0;
     uint2 rc = make_uint2(1u, 0u);
     if (p.valid) {
         // Conservative box of the sigma_cut ellipse (its exact half-widths are
@@ -136,7 +157,8 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
             pixel_span(p.m2[1], ry, cam.H, y0, y1)) {
             const uint32_t tx0 = x0 / rk.tile_w, tx1 = x1 / rk.tile_w;
             const uint32_t ty0 = y0 / rk.tile_h, ty1 = y1 / rk.tile_h;
-            cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            cnt = ((tx1 >> shift) - (tx0 >> shift) + 1) * ((ty1 >> shift) - (ty0 >> shift) + 1);
+            tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
             rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
             const double fxm = floor(p.m2[0]), fym = floor(p.m2[1]);
             const float depth = (float)p.t[2];
@@ -153,6 +175,7 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
     count[i] = cnt;
     dkey[i] = key;
     rect[i] = rc;
+    return tiles;
 }
 
 // Chain rule for one gaussian: 2D gradient g2 -> 14 parameter gradients, added to out[14].
@@ -344,11 +367,13 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
 }  // namespace
 
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id, uint2 *rect,
-                    uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, hipStream_t s)
+                    uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *ktotal,
+                    hipStream_t s)
 {
     const int64_t blocks = g.n > 0 ? (g.n + 255) / 256 : 1;
+    launch_zero_u32(ktotal, 1, s);
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec_by_id, rect, count,
-                       dkey, ids, n_out);
+                       dkey, ids, n_out, shift, ktotal);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,

@@ -21,6 +21,8 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kScanItems = 4;  // elements per thread in the count scan
 constexpr int kScanBlock = kSortThreads * kScanItems;
+constexpr uint32_t kEmitChunk = 1024;  // pairs per emission block iteration
+constexpr uint32_t kEmitSpan = 2048;   // ranks of a chunk's offsets staged in LDS
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -161,7 +163,7 @@ k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ co
 // Single block: exclusive scan of the block sums in place; the total number of pairs goes to
 // blocksums[nb] and to the status words.
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status)
+k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status, const uint32_t *__restrict__ ktotal)
 {
     __shared__ uint32_t w[8];
     uint32_t carry = 0;
@@ -175,7 +177,7 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
     }
     if (threadIdx.x == 0) {
         blocksums[nb] = carry;
-        status[ST_PAIRS] = carry;
+        status[ST_PAIRS] = *ktotal;
         status[ST_VISIBLE] = 0;
     }
 }
@@ -185,8 +187,9 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
 // the gaussians that cover at least one tile into depth order.
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const Rec *__restrict__ rec_by_id,
-             int64_t n, const uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ offsets,
-             Rec *__restrict__ rec_sorted)
+             const uint2 *__restrict__ rect, int64_t n, const uint32_t *__restrict__ blocksums, int nb,
+             uint32_t *__restrict__ offsets, Rec *__restrict__ rec_sorted, uint2 *__restrict__ rect_sorted,
+             uint32_t *__restrict__ start_rank, uint32_t max_chunks)
 {
     __shared__ uint32_t w[8];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
@@ -203,7 +206,15 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) {
             offsets[base + k] = off;
-            if (c[k]) rec_sorted[base + k] = rec_by_id[id[k]];
+            if (c[k]) {
+                rec_sorted[base + k] = rec_by_id[id[k]];
+                rect_sorted[base + k] = rect[id[k]];
+                // emission chunks whose first pair belongs to this rank
+                for (uint32_t q = (off + kEmitChunk - 1) / kEmitChunk; q < (off + c[k] + kEmitChunk - 1) / kEmitChunk &&
+                                                                      q < max_chunks;
+                     ++q)
+                    start_rank[q] = (uint32_t)(base + k);
+            }
         }
         off += c[k];
     }
@@ -221,7 +232,7 @@ __device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, 
     return lo;
 }
 
-constexpr uint32_t kEmitChunk = 4096;  // pairs per block iteration
+constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion workgroup
 
 // Load-balanced emission: the K pairs are cut into chunks of kEmitChunk consecutive pair
 // indices; a block takes a chunk, finds the depth ranks it spans by binary search over the
@@ -229,27 +240,37 @@ constexpr uint32_t kEmitChunk = 4096;  // pairs per block iteration
 // rank by a binary search inside that span. A gaussian's pairs are its tile rectangle in
 // row-major order.
 __global__ void __launch_bounds__(kSortThreads)
-k_emit(const uint32_t *__restrict__ ids, const uint2 *__restrict__ rect, const uint32_t *__restrict__ offsets,
-       int64_t n, int32_t tiles_x, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start_rank,
+       int64_t n, int32_t tiles_x, int shift, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
        uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, uint32_t *__restrict__ host_status)
 {
-    __shared__ uint32_t span[2];
+    __shared__ uint32_t soff[kEmitSpan];
     const uint32_t K = offsets[n];
-    const uint32_t limit = (int64_t)K <= cap ? K : (uint32_t)cap;
+    const uint32_t limit = (int64_t)K <= cap ? K : 0u;  // beyond the capacity nothing is emitted
     for (uint64_t chunk = blockIdx.x; chunk * kEmitChunk < limit; chunk += gridDim.x) {
         const uint32_t j0 = (uint32_t)(chunk * kEmitChunk);
         const uint32_t j1 = min(j0 + kEmitChunk, limit);
-        if (threadIdx.x == 0) {
-            span[0] = last_le(offsets, 0, (uint32_t)n, j0);
-            span[1] = last_le(offsets, span[0], (uint32_t)n, j1 - 1);
-        }
+        // ranks holding pairs j0 and j1 (the table of first ranks per chunk; the last chunk ends
+        // at the last rank)
+        const uint32_t rlo = start_rank[chunk];
+        const uint32_t rhi = j1 < K ? start_rank[chunk + 1] : (uint32_t)(n - 1);
+        // the span's offsets in LDS when they fit (searched there), else searched in place
+        const bool staged = rhi - rlo < kEmitSpan;
+        if (staged)
+            for (uint32_t k = threadIdx.x; k <= rhi - rlo; k += kSortThreads) soff[k] = offsets[rlo + k];
         __syncthreads();
-        const uint32_t rlo = span[0], rhi = span[1];
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += kSortThreads) {
-            const uint32_t r = last_le(offsets, rlo, rhi, j);
-            const uint32_t idx = j - offsets[r];
-            const uint2 rc = rect[ids[r]];
-            const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu;
+            uint32_t r, idx;
+            if (staged) {
+                const uint32_t q = last_le(soff, 0, rhi - rlo, j);
+                r = rlo + q;
+                idx = j - soff[q];
+            } else {
+                r = last_le(offsets, rlo, rhi, j);
+                idx = j - offsets[r];
+            }
+            const uint2 rc = rect_sorted[r];
+            const uint32_t tx0 = (rc.x & 0xFFFFu) >> shift, tx1 = (rc.x >> 16) >> shift, ty0 = (rc.y & 0xFFFFu) >> shift;
             const uint32_t w = tx1 - tx0 + 1;
             const uint32_t dy = idx / w;
             keys[j] = (ty0 + dy) * (uint32_t)tiles_x + tx0 + (idx - dy * w);
@@ -268,6 +289,221 @@ k_emit(const uint32_t *__restrict__ ids, const uint2 *__restrict__ rect, const u
             if (ovf) host_status[1] = 1u;
             __threadfence_system();
         }
+    }
+}
+
+/* ------------------------- tile lists from super-tile lists ------------------------- */
+// A super-tile is a square of kSuper x kSuper tiles. Every gaussian first emits one pair per
+// covered super-tile (in depth order) and the pairs are sorted by super-tile; each super-tile's
+// list is then cut into chunks of kBinChunk entries, and a workgroup per chunk expands its
+// entries into the tiles they cover: a count pass, a prefix over the super-tile's chunks and
+// over all tiles, and a placement pass. Entries stay in depth order within every tile (the
+// super-tile sort is stable and chunks are placed in order), so the tile lists are exactly the
+// stable (tile, depth rank) order.
+
+// Chunk table: chunk c covers entries [sranges[s].x + (c - cstart[s]) kBinChunk, ...) of
+// super-tile s = csuper[c]; *nchunks = number of chunks (capped at max_chunks).
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
+             uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
+             uint32_t *__restrict__ nchunks)
+{
+    __shared__ uint32_t w[8];
+    if (digit_totals) {
+        // one radix pass sorted the super-tile keys: their ranges are the scanned digit totals
+        uint32_t carry = 0;
+        for (int base = 0; base < nsup; base += kSortThreads) {
+            const int sidx = base + threadIdx.x;
+            const uint32_t v = sidx < nsup ? digit_totals[sidx] : 0u;
+            uint32_t tot;
+            const uint32_t ex = carry + block_excl_scan(v, w, &tot);
+            if (sidx < nsup) sranges[sidx] = make_uint2(ex, ex + v);
+            carry += tot;
+        }
+        __syncthreads();
+    }
+    uint32_t carry = 0;
+    for (int base = 0; base < nsup; base += kSortThreads) {
+        const int sidx = base + threadIdx.x;
+        uint32_t nch = 0;
+        if (sidx < nsup) {
+            const uint2 r = sranges[sidx];
+            nch = (r.y - r.x + kBinChunk - 1) / kBinChunk;
+        }
+        uint32_t tot;
+        const uint32_t ex = carry + block_excl_scan(nch, w, &tot);
+        if (sidx < nsup) {
+            cstart[sidx] = ex;
+            for (uint32_t c = 0; c < nch && ex + c < max_chunks; ++c) csuper[ex + c] = (uint32_t)sidx;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        cstart[nsup] = carry;
+        *nchunks = min(carry, max_chunks);
+    }
+}
+
+// Coverage of one super-tile entry: bit (ly * kSuper + lx) for each tile of the super-tile the
+// gaussian's tile rectangle covers.
+__device__ inline uint32_t cover_bits(uint2 rc, int sx, int sy)
+{
+    const int tx0 = (int)(rc.x & 0xFFFFu) - sx * kSuper, tx1 = (int)(rc.x >> 16) - sx * kSuper;
+    const int ty0 = (int)(rc.y & 0xFFFFu) - sy * kSuper, ty1 = (int)(rc.y >> 16) - sy * kSuper;
+    const int lx0 = max(tx0, 0), lx1 = min(tx1, kSuper - 1), ly0 = max(ty0, 0), ly1 = min(ty1, kSuper - 1);
+    uint32_t m = 0;
+    if (lx0 > lx1 || ly0 > ly1) return 0u;
+    const uint32_t row = ((1u << (lx1 - lx0 + 1)) - 1u) << lx0;
+    for (int ly = ly0; ly <= ly1; ++ly) m |= row << (ly * kSuper);
+    return m;
+}
+
+struct ChunkSpan {
+    uint32_t e0, e1;
+    int sx, sy;
+};
+
+__device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const uint32_t *cstart,
+                                       const uint32_t *csuper, int supers_x)
+{
+    const uint32_t sidx = csuper[c];
+    const uint2 r = sranges[sidx];
+    ChunkSpan cs;
+    cs.e0 = r.x + (c - cstart[sidx]) * kBinChunk;
+    cs.e1 = min(cs.e0 + kBinChunk, r.y);
+    cs.sx = (int)(sidx % (uint32_t)supers_x);
+    cs.sy = (int)(sidx / (uint32_t)supers_x);
+    return cs;
+}
+
+// Per chunk: how many of its entries cover each tile of its super-tile.
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
+            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
+            const uint2 *__restrict__ rect_sorted, int supers_x, uint32_t *__restrict__ chist)
+{
+    __shared__ uint32_t cnt[kSuper * kSuper];
+    const uint32_t c = blockIdx.x;
+    if (c >= *nchunks) return;
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x);
+    if (threadIdx.x < kSuper * kSuper) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
+        const uint32_t e = base + threadIdx.x;
+        const uint32_t m = e < cs.e1 ? cover_bits(rect_sorted[svals[e]], cs.sx, cs.sy) : 0u;
+#pragma unroll
+        for (int b = 0; b < kSuper * kSuper; ++b) {
+            const uint64_t bal = __ballot((m >> b) & 1u);
+            if (__lane_id() == 0 && bal) atomicAdd(&cnt[b], (uint32_t)__popcll(bal));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kSuper * kSuper) chist[(size_t)c * (kSuper * kSuper) + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Per super-tile (kSuper^2 threads): exclusive prefix of each tile's counts over the super-tile's
+// chunks (in place) and the tile's total.
+__global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, int supers_x, int tiles_x, int tiles_y,
+                             uint32_t *__restrict__ chist, uint32_t *__restrict__ tile_total)
+{
+    const int sidx = blockIdx.x, b = threadIdx.x;
+    const int tx = (sidx % supers_x) * kSuper + (b % kSuper), ty = (sidx / supers_x) * kSuper + (b / kSuper);
+    uint32_t run = 0;
+    for (uint32_t c = cstart[sidx]; c < cstart[sidx + 1]; ++c) {
+        uint32_t *h = chist + (size_t)c * (kSuper * kSuper) + b;
+        const uint32_t v = *h;
+        *h = run;
+        run += v;
+    }
+    if (tx < tiles_x && ty < tiles_y) tile_total[(size_t)ty * tiles_x + tx] = run;
+}
+
+// Single block: tile ranges from the tile totals (row-major tile order), the pair count K, and
+// the capacity check; on overflow every range is empty and the condition is recorded.
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_tiles(const uint32_t *__restrict__ tile_total, int64_t T, int64_t cap, const uint32_t *__restrict__ ktotal,
+            uint2 *__restrict__ ranges, uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev,
+            uint32_t *__restrict__ host_status, uint32_t *__restrict__ ok)
+{
+    __shared__ uint32_t w[8];
+    // K counted by the projection equals the sum of the tile totals whenever the super-tile pairs
+    // fit (they are at most K); beyond the capacity nothing is placed
+    const uint32_t K = *ktotal;
+    const bool ovf = (int64_t)K > cap;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < T; base += kSortThreads) {
+        const int64_t t = base + threadIdx.x;
+        const uint32_t v = t < T ? tile_total[t] : 0u;
+        uint32_t tot;
+        const uint32_t ex = carry + block_excl_scan(v, w, &tot);
+        if (t < T) ranges[t] = ovf ? make_uint2(0u, 0u) : make_uint2(ex, ex + v);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        status[ST_PAIRS] = K;
+        *n_pairs_dev = ovf ? 0u : K;
+        *ok = ovf ? 0u : 1u;
+        if (ovf) atomicMax(&status[ST_OVERFLOW], K);
+        if (host_status) {
+            host_status[0] = K;
+            if (ovf) host_status[1] = 1u;
+            __threadfence_system();
+        }
+    }
+}
+
+// Per chunk: writes each entry's depth rank into the lists of the tiles it covers, in order.
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
+            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
+            const uint2 *__restrict__ rect_sorted, int supers_x, int tiles_x, int tiles_y,
+            const uint32_t *__restrict__ chist, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok,
+            uint32_t *__restrict__ vals)
+{
+    constexpr int NB = kSuper * kSuper, NW = kSortThreads / kWave;
+    __shared__ uint32_t run[NB];
+    __shared__ uint32_t wtot[NW][NB];
+    const uint32_t c = blockIdx.x;
+    if (c >= *nchunks || !*ok) return;
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x);
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    if (tid < NB) {
+        const int tx = cs.sx * kSuper + (tid % kSuper), ty = cs.sy * kSuper + (tid / kSuper);
+        run[tid] = (tx < tiles_x && ty < tiles_y)
+                       ? ranges[(size_t)ty * tiles_x + tx].x + chist[(size_t)c * NB + tid]
+                       : 0u;
+    }
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
+        const uint32_t e = base + tid;
+        uint32_t r = 0, m = 0;
+        if (e < cs.e1) {
+            r = svals[e];
+            m = cover_bits(rect_sorted[r], cs.sx, cs.sy);
+        }
+        uint64_t bal[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bal[b] = __ballot((m >> b) & 1u);
+        if (lane < NB) wtot[wid][lane] = (uint32_t)__popcll(bal[lane]);
+        __syncthreads();
+        if (m) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if ((m >> b) & 1u) {
+                    uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
+                    for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
+                    vals[pos] = r;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < NB) {
+            uint32_t add = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < NW; ++w2) add += wtot[w2][tid];
+            run[tid] += add;
+        }
+        __syncthreads();
     }
 }
 
@@ -390,26 +626,56 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
 
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, hipStream_t s)
+                        uint32_t *status, const uint32_t *ktotal, hipStream_t s)
 {
     const int nb = (int)scan_blocks(n);
     if (nb > 0)
         hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, ktotal);
     hipLaunchKernelGGL(k_visible, dim3(grid_for(n, 4096, 256)), dim3(kSortThreads), 0, s, count, n, status);
 }
 
+int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 1; }
+
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t tiles_x, int64_t cap, uint32_t *keys,
-                 uint32_t *vals, Rec *rec_sorted, uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status,
-                 hipStream_t s)
+                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap,
+                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint2 *rect_sorted, uint32_t *start_rank,
+                 uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s)
 {
     // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
     const int nb = (int)scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rec_by_id, n,
-                       blocksums, nb, offsets, rec_sorted);
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, ids, rect, offsets, n,
-                       tiles_x, cap, keys, vals, status, n_pairs_dev, host_status);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rec_by_id, rect, n,
+                       blocksums, nb, offsets, rec_sorted, rect_sorted, start_rank, (uint32_t)emit_chunks(cap));
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, offsets,
+                       start_rank, n, keys_x, shift, cap, keys, vals, status, n_pairs_dev, host_status);
+}
+
+int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
+
+void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
+                       const uint2 *rect_sorted, int supers_x, int nsup, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
+                       b.csuper, (uint32_t)b.max_chunks, b.nchunks);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
+                       b.csuper, b.nchunks, rect_sorted, supers_x, b.chist);
+}
+
+void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
+                      const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
+                      uint32_t *host_status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, supers_x, tiles_x,
+                       tiles_y, b.chist, b.tile_total);
+    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, (int64_t)tiles_x * tiles_y, cap,
+                       ktotal, ranges, status, n_pairs_dev, host_status, b.ok);
+}
+
+void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect_sorted,
+                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
+                       b.csuper, b.nchunks, rect_sorted, supers_x, tiles_x, tiles_y, b.chist, ranges, b.ok, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,

@@ -253,13 +253,16 @@ def test_full_window_workload(fgs, ctx):
     launch configuration the benchmark times.
 
     The window's losses equal single-view renders (1e-5). Its gradient is compared with the plain
-    mapping step's over the same views. At this size the FP32 atomic order alone moves the
-    geometric gradients (mean, log-scale, rotation) of many gaussians by up to a few 1e-3 of
-    themselves: two runs of the same plain step differ that much, since cameras inside the box see
-    gaussians a few cm past the near plane whose gradients are sums of very large cancelling terms.
-    Those rows are held to eight times the plain step's own run-to-run spread (row maxima); the
-    opacity and colour gradients are well conditioned and held to the gradient bar (1e-4). A graph
-    replay is compared with an eager step the same way."""
+    mapping step's over the same views, per parameter row. Opacity and colour gradients are well
+    conditioned: relative L2 error 1e-5 and largest difference 1e-4 of the row's largest entry.
+    The geometric rows (mean, log-scale, rotation) are not reproducible to that level by any FP32
+    path at this size: L1-loss gradients are sums of +-1-weighted pixel terms that cancel heavily,
+    and cameras inside the box see gaussians just past the near plane whose gradients cancel over
+    most of a view, so the FP32 atomic order alone moves these rows by up to 5e-4 in relative L2
+    (measured between two runs of the same plain step); they are held to 2e-3 in relative L2 and
+    1e-2 of the row's largest entry, which any missing view, tile or term would exceed by orders
+    of magnitude. Elementwise parity with the oracle is asserted on the small windows above. A
+    graph replay is compared with an eager step the same way."""
     import torch
     cams = synth.window_cameras(0)
     p = synth.scene_window(0)
@@ -274,14 +277,10 @@ def test_full_window_workload(fgs, ctx):
     lopts = fgs.LossOpts()
     ref_loss = per_view_losses(fgs, ctx, pd, n, cams, targets, lopts)
     zero = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
-
-    def plain():
-        g = torch.zeros_like(pd)
-        fgs.map_step(ctx, pd, n, zero, cams, targets, fgs.RenderOpts(), lopts, grad_out=g)
-        ctx.check()
-        return host(g).astype(np.float64)
-
-    ref, ref2 = plain(), plain()
+    ref = torch.zeros_like(pd)
+    fgs.map_step(ctx, pd, n, zero, cams, targets, fgs.RenderOpts(), lopts, grad_out=ref)
+    ctx.check()
+    ref = host(ref).astype(np.float64)
     win = fgs.Window(ctx, cams)
     loss = torch.zeros(8, device="cuda")
     ga, gb = torch.zeros_like(pd), torch.zeros_like(pd)
@@ -293,15 +292,11 @@ def test_full_window_workload(fgs, ctx):
     ctx.check()
     np.testing.assert_allclose(host(loss), ref_loss, rtol=1e-5)
     g_a, g_b = host(ga).astype(np.float64), host(gb).astype(np.float64)
-    for rows in (slice(10, 11), slice(11, 14)):
-        assert_close_rel(g_a[rows], ref[rows], 1e-4, what=f"window vs map_step {rows}", floor=1e-2)
-        assert_close_rel(g_b[rows], g_a[rows], 1e-4, what=f"replay vs eager {rows}", floor=1e-2)
-    scale = np.abs(ref).max(axis=1)
-    spread = np.abs(ref2 - ref).max(axis=1)
-    assert np.all(spread[:10] <= 1e-2 * scale[:10]), spread / scale
-    for what, x in (("window vs map_step", g_a), ("replay vs eager", g_b)):
-        y = ref if x is g_a else g_a
-        err = np.abs(x - y).max(axis=1)
-        bad = err[:10] > 8 * spread[:10] + 1e-6 * scale[:10]
-        assert not bad.any(), (what, err / scale, spread / scale)
+    l2_tol = np.array([2e-3] * 10 + [1e-5] * 4)
+    max_tol = np.array([1e-2] * 10 + [1e-4] * 4)
+    for what, x, y in (("window vs map_step", g_a, ref), ("replay vs eager", g_b, g_a)):
+        l2 = np.linalg.norm(x - y, axis=1) / np.linalg.norm(y, axis=1)
+        worst = np.abs(x - y).max(axis=1) / np.abs(y).max(axis=1)
+        assert np.all(l2 <= l2_tol), (what, "relative L2 per row", l2)
+        assert np.all(worst <= max_tol), (what, "max error / row max", worst)
     win.close()
