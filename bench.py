@@ -12,6 +12,7 @@ roofline (live HIP-event timing of that kernel on the library's stream, algorith
 the rasterizer's exact pair counters), and the CPU oracle timed on the host on the same workload.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -117,11 +118,14 @@ def window_extra(F, ctx, steps: int = 20) -> dict:
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     e0.record(stream)
     for _ in range(steps):
         win.step(params, n, adam, targets, opts, loss=loss, graph=True)
     e1.record(stream)
     torch.cuda.synchronize()
+    gc.enable()
     ctx.check()
     ms = e0.elapsed_time(e1) / steps
     ctx.profile(1)
@@ -218,7 +222,11 @@ def main():
     torch.cuda.synchronize()
 
     # timed region: HIP events around the two rasterizer kernels only (level 1), so the timing of
-    # the dominant kernel is live without breaking up the rest of the step
+    # the dominant kernel is live without breaking up the rest of the step. Python's cyclic garbage
+    # collector is paused meanwhile: a full collection stalls the host for ~20 ms, long enough to
+    # drain the GPU's queue of enqueued steps.
+    gc.collect()
+    gc.disable()
     ctx.profile(1)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -228,6 +236,7 @@ def main():
         F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
     e1.record(stream)
     torch.cuda.synchronize()
+    gc.enable()
     ms = e0.elapsed_time(e1)
     ctx.check()
     rep = ctx.profile_report()

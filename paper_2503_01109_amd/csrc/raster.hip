@@ -118,6 +118,53 @@ __device__ __forceinline__ float dpp_add(float v)
     return v + __int_as_float(t);
 }
 
+// Ten wave sums at once by a transposed butterfly: at each exchange a lane keeps half of its
+// partial sums (the half its partner does not keep) and adds the partner's matching half, so
+// 10 values shrink to 5, 3, 2 and 1 per lane over lane distances 1, 2, 4 and 8; two more
+// exchanges add the four rows. Lane j (j < 16; every row holds the same) returns the full sum of
+// term reduce_term(j), or of nothing when that is negative (padding). About 40 VALU operations
+// instead of 10 separate 6-step wave sums.
+__device__ __forceinline__ float reduce10(const float v[10], int lane)
+{
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+    float a[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const float send = b0 ? v[c] : v[c + 5], mine = b0 ? v[c + 5] : v[c];
+        a[c] = mine + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0xB1, 0xf, 0xf, false));
+    }
+    float q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float hi = c < 2 ? a[c + 3] : 0.0f, lo = a[c];
+        const float send = b1 ? lo : hi, mine = b1 ? hi : lo;
+        q[c] = mine + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0x4E, 0xf, 0xf, false));
+    }
+    float r[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float hi = c < 1 ? q[c + 2] : 0.0f, lo = q[c];
+        const float send = b2 ? lo : hi, mine = b2 ? hi : lo;
+        r[c] = mine + __shfl_xor(send, 4);
+    }
+    const float send = b3 ? r[0] : r[1], mine = b3 ? r[1] : r[0];
+    float d = mine + __shfl_xor(send, 8);
+    d += __shfl_xor(d, 16);
+    d += __shfl_xor(d, 32);
+    return d;
+}
+
+// The term whose sum reduce10 leaves in lane j of a row (-1: padding).
+__device__ __forceinline__ int reduce_term(int lane)
+{
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const int i3 = b2 ? 2 + b3 : b3;  // index among the 3 values of the third exchange
+    if (i3 > 2) return -1;
+    const int i5 = b1 ? 3 + i3 : i3;  // among the 5 values of the second
+    if (i5 > 4) return -1;
+    return b0 ? 5 + i5 : i5;
+}
+
 // Sum over the 64 lanes; the total is valid in lanes 48..63.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -254,7 +301,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int TW = rk.tile_w, TH = rk.tile_h;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint32_t srank[NT];
-    __shared__ float sacc[10][NT];
+    __shared__ float sacc[10][NT + 1];  // padded: the ten terms of one entry fall in different banks
     __shared__ uint32_t smax;
     __shared__ uint8_t smask[NT];
     __shared__ uint16_t slist[NW][NT];
@@ -368,12 +415,11 @@ __device__ void tile_bwd(const ViewK &V, int tile)
                         for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
                     }
                 } else {
-#pragma unroll
-                    for (int c = 0; c < 10; ++c) g[c] = wave_sum(g[c]);
-                    if (lane == kWave - 1) {
-#pragma unroll
-                        for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
-                    }
+                    // transposed reduction: lane j of the first row ends with the wave sum of term
+                    // reduce_term(j); one LDS atomic instruction adds all ten terms
+                    const float t = reduce10(g, lane);
+                    const int term = reduce_term(lane);
+                    if (lane < 16 && term >= 0) atomicAdd(&sacc[term][k], t);
                 }
             }
         }
