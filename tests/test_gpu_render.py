@@ -171,6 +171,48 @@ def test_termination_stack(fgs, ctx):
     assert host(out["T_final"])[8, 8] == np.float32(2.0 ** -13)
 
 
+def test_many_super_tiles_and_huge_gaussians(fgs, ctx):
+    """8x8 tiles on a 640x480 frame: 80x60 tiles in 20x15 = 300 super-tiles, more than one radix
+    digit, so the super-tile order takes two passes. The scene mixes ordinary gaussians with a
+    few that cover most of the frame (lists of every tile, many chunks per super-tile) and
+    gaussians straddling the frame border. Forward at 3,000 sampled pixels and the full gradient
+    against the oracle."""
+    cam = synth.camera_tum()
+    p = synth.frustum_scene(31, 3000, cam, 1.0, 6.0)
+    p[3:6, :6] = np.log(0.8)  # six gaussians about a metre wide
+    p[0, 6:20] = np.linspace(-3.0, 3.0, 14)  # a row across the frame border at x = 0 and x = W
+    p[1, 6:20] = 0.0
+    p[2, 6:20] = 2.0
+    n = p.shape[1]
+    opts = fgs.RenderOpts(tile_w=8, tile_h=8)
+    pd = params_dev(p)
+    out = fgs.render(ctx, pd, n, cam, opts)
+    P = cam.width * cam.height
+    g = synth.rng(78)
+    pix = np.sort(g.choice(P, 3000, replace=False))
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(opts), mode=0, pix=pix, amb_rel=1e-5)
+    ok = ~ref["amb"]
+    assert ref["n_amb"] <= 0.01 * pix.size
+    assert_close_rel(host(out["rgb"]).reshape(3, P)[:, pix], ref["rgb"], FWD_TOL, ok, "rgb")
+    for k in ("depth", "alpha", "T_final"):
+        assert_close_rel(host(out[k]).ravel()[pix], ref[k], FWD_TOL, ok, k)
+    np.testing.assert_array_equal(host(out["n_contrib"]).ravel()[pix][ok], ref["n_contrib"][ok])
+    keep = pix[ok]
+    gr = np.zeros((3, P), np.float32)
+    gd = np.zeros(P, np.float32)
+    gr[:, keep] = g.normal(size=(3, keep.size))
+    gd[keep] = g.normal(size=keep.size)
+    grad = dev(np.zeros((14, n), np.float32))
+    fgs.render_bwd(ctx, pd, n, cam, opts, out["state"], dev(gr), dev(gd), None, grad)
+    ctx.check()
+    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr[:, keep], gd[keep], None, oracle_opts(opts), mode=0,
+                                pix=keep)
+    gg = host(grad)
+    for name, rows in (("mean", slice(0, 3)), ("log_scale", slice(3, 6)), ("quat", slice(6, 10)),
+                       ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+        assert_close_rel(gg[rows], gref[rows], GRAD_TOL, None, f"d{name}", floor=GRAD_FLOOR)
+
+
 def test_empty_and_culled(fgs, ctx):
     """n = 0 and an all-culled scene render the background."""
     cam = synth.camera_small()
@@ -216,6 +258,18 @@ def test_capacity_overflow_is_reported(fgs, ctx):
     need = fgs.ctx_required_pairs(e.value)
     assert K <= need <= K + K // 50 + 16  # GPU machines are padded by 1e-5 relative + 1e-3 px
     ctx.check()  # the condition is cleared once reported
+    # one pair short: the super-tile pairs still fit, the tile lists do not
+    nb = fgs.state_bytes(n, cam.width, cam.height, need - 1, opts)
+    state = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    fgs.render_fwd(ctx, pd, n, cam, opts, rgb, depth, state)
+    with pytest.raises(fgs.FgsError) as e:
+        ctx.check()
+    assert e.value.status == fgs.ERR_CAPACITY and fgs.ctx_required_pairs(e.value) == need
+    # exactly enough
+    nb = fgs.state_bytes(n, cam.width, cam.height, need, opts)
+    state = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    fgs.render_fwd(ctx, pd, n, cam, opts, rgb, depth, state)
+    ctx.check()
 
 
 def test_deterministic_forward(fgs, ctx):
