@@ -143,16 +143,18 @@ const char *fgs_status_str(fgs_status s);
 fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len);
 
 /* [host] Profiling. While enabled, the context records HIP events around pipeline stages it
- * enqueues and the forward rasterizer counts its work. level 1: the rasterizer kernels only
- * ("raster_fwd", "raster_bwd"); level 2: every stage: "project", "depth_sort", "bin" (scan +
- * pair emission), "tile_sort" (with tile ranges), "raster_fwd", "loss", "raster_bwd",
- * "project_bwd", "adam". 0 disables. Every call clears previous records. */
+ * enqueues. level 1: the rasterizer kernels only ("raster_fwd", "raster_bwd"), which then run
+ * exactly as unprofiled; level 2: every stage: "project", "depth_sort", "bin" (scan + pair
+ * emission), "tile_sort" (with tile ranges), "raster_fwd", "loss", "raster_bwd", "project_bwd",
+ * "adam", and the forward rasterizer counts its work (fgs_ctx_profile_counts). 0 disables.
+ * Every call clears previous records. */
 fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t level);
 /* Waits for the stream; total milliseconds and number of launches of one stage since enabling. */
 fgs_status fgs_ctx_profile_stage(fgs_ctx *ctx, const char *stage, double *total_ms, int64_t *launches);
-/* Waits for the stream; work counters since enabling: counts[0] = (pixel, gaussian) pairs within
- * the sigma_cut ellipse that each pixel examined before it stopped, counts[1] = pairs blended,
- * counts[2] = list entries staged by the forward rasterizer, counts[3] = forward launches. */
+/* Waits for the stream; work counters since enabling level 2 (zero at level 1): counts[0] =
+ * (pixel, gaussian) pairs within the sigma_cut ellipse that each pixel examined before it
+ * stopped, counts[1] = pairs blended, counts[2] = list entries staged by the forward rasterizer,
+ * counts[3] = forward launches counted. */
 fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4]);
 
 /* ---------------------------- rendering (Eq. 1) and its gradient ---------------------------- */

@@ -68,11 +68,23 @@ def _window_result(F, ctx, cams, tiles, bpc, params, n, targets, opts):
     return loss, grad
 
 
-def check_against_default(F, ctx, cams, tiles, bpc, params, n, targets, opts, tol=1e-5, l2_tol=1e-4, max_tol=1e-2):
-    """Raise AssertionError unless the configuration reproduces the default one: per-view losses
-    within tol relative, and per parameter row a gradient within l2_tol relative L2 error and
-    max_tol of the row's largest entry (L1-loss gradients cancel heavily, so FP32 atomics in a
-    different order move single entries far more than the row as a whole)."""
+# Parameter rows of the packed layout: mean 0-2, log-scale 3-5, quaternion 6-9 (geometric, whose
+# gradients are sums of large terms of both signs), logit 10 and rgb 11-13 (appearance).
+GEOMETRIC_ROWS = slice(0, 10)
+APPEARANCE_ROWS = slice(10, 14)
+
+
+def check_against_default(F, ctx, cams, tiles, bpc, params, n, targets, opts, tol=1e-5, app_l2_tol=1e-5,
+                          app_max_tol=1e-4, geo_l2_tol=2e-3, geo_max_tol=1e-2):
+    """Raise AssertionError unless the configuration reproduces the default one.
+
+    The per-pixel blend does not depend on the tile shape, so the per-view losses must agree to
+    tol relative. Gradients are sums over pixels in an order that the tile shape and the FP32
+    atomics change: the appearance rows (opacity, colour) are well conditioned and are held to
+    app_l2_tol relative L2 error and app_max_tol of the row's largest entry; the geometric rows
+    cancel heavily (at 500k gaussians two summation orders differ by up to ~6e-4 relative L2 on a
+    row), so they are held to geo_l2_tol and geo_max_tol, bounds that any real fault (a missed
+    pair, a wrong pixel offset) exceeds by orders of magnitude."""
     l0, g0 = _window_result(F, ctx, cams, None, 0, params, n, targets, opts)
     l1, g1 = _window_result(F, ctx, cams, tiles, bpc, params, n, targets, opts)
     dl = (l1 - l0).abs() / l0.abs().clamp_min(1e-30)
@@ -81,7 +93,9 @@ def check_against_default(F, ctx, cams, tiles, bpc, params, n, targets, opts, to
     g0, g1 = g0.double(), g1.double()
     l2 = (g1 - g0).norm(dim=1) / g0.norm(dim=1).clamp_min(1e-300)
     worst = (g1 - g0).abs().amax(dim=1) / g0.abs().amax(dim=1).clamp_min(1e-300)
-    if bool((l2 > l2_tol).any()) or bool((worst > max_tol).any()):
+    bad = bool((l2[APPEARANCE_ROWS] > app_l2_tol).any()) or bool((worst[APPEARANCE_ROWS] > app_max_tol).any())
+    bad = bad or bool((l2[GEOMETRIC_ROWS] > geo_l2_tol).any()) or bool((worst[GEOMETRIC_ROWS] > geo_max_tol).any())
+    if bad:
         raise AssertionError(f"autotuned window: gradient rows differ from the default: relative L2 {l2.tolist()}, "
                              f"max error / row max {worst.tolist()}")
 

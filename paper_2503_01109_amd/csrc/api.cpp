@@ -338,9 +338,11 @@ struct Stage {
     }
 };
 
+// Work counters of the forward rasterizer: collected at profiling level 2 only, so the kernels
+// timed at level 1 are the ones that run unprofiled.
 unsigned long long *prof_counts(fgs_ctx *ctx)
 {
-    return ctx->prof ? ctx->prof_counts.as<unsigned long long>() : nullptr;
+    return ctx->prof >= 2 ? ctx->prof_counts.as<unsigned long long>() : nullptr;
 }
 
 void clear_profile(fgs_ctx *ctx, bool destroy = false)
@@ -485,7 +487,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
         Stage st_(ctx, "raster_fwd");
         launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img,
                           prof_counts(ctx), s);
-        if (ctx->prof) ctx->prof_fwd++;
+        if (prof_counts(ctx)) ctx->prof_fwd++;
     }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -1272,9 +1274,9 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                        sort_ws(ctx, w->total_tiles), s);
     {
         Stage st_(ctx, "raster_fwd");
-        launch_raster_queue(true, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
-                            words + WW_COUNTER, w->blocks, s);
-        if (ctx->prof) ctx->prof_fwd += w->nv;
+        launch_raster_queue(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(),
+                            w->total_tiles, words + WW_COUNTER, w->blocks, s);
+        if (prof_counts(ctx)) ctx->prof_fwd += w->nv;
     }
     for (int v = 0; v < w->nv; ++v) {
         const int64_t P = (int64_t)w->cams[v].width * w->cams[v].height;
@@ -1286,7 +1288,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     }
     {
         Stage st_(ctx, "raster_bwd");
-        launch_raster_queue(false, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
+        launch_raster_queue(false, false, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
                             words + WW_COUNTER, w->blocks, s);
     }
     int64_t *step = (int64_t *)(words + WW_STEP);

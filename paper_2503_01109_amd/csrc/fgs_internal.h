@@ -186,8 +186,9 @@ void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t
 
 // Persistent window rasterizer: blocks pull items q < total from the queue (item ids g, or q
 // itself when queue is NULL) and process tile g - views[v].tile_base of view v. counter is
-// zeroed first (with a kernel, so the sequence can be captured in a graph).
-void launch_raster_queue(bool fwd, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
+// zeroed first (with a kernel, so the sequence can be captured in a graph). count: the forward
+// adds its work counters to views[v].counts (which must then be non-null).
+void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
                          uint32_t *counter, int blocks, hipStream_t s);
 
 // counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel

@@ -8,10 +8,17 @@
 // per-pixel cutoffs (Mahalanobis distance <= sigma_cut, alpha >= alpha_min, stop before T drops
 // below T_min); the workgroup leaves the list as soon as a barrier count shows every pixel done.
 //
+// The staged conic is pre-multiplied by -log2(e)/2, so a pair costs one exp2 of the scaled
+// quadratic form: G = 2^(s Q) = exp(-Q/2), and the cutoff Q <= sigma_cut^2 becomes
+// s Q >= s sigma_cut^2.
+//
 // The backward walks the same list in reverse from the last blended position of the tile,
-// recovering T_i = T_{i+1}/(1 - alpha_i). Each pair yields 10 gradient terms; they are summed
-// over the wave with DPP row operations, over the workgroup's waves with LDS float atomics, and
-// reach HBM as one FP32 atomic per (tile, gaussian, term).
+// recovering T_i = T_{i+1}/(1 - alpha_i). The colour, depth and opacity terms behind a pair enter
+// its opacity gradient only through one running sum per pixel, S = sum over later pairs of
+// w_j (dL/dC . c_j + dL/dD d_j) plus the background's and the opacity output's share. Each pair
+// yields 10 gradient terms; they are summed over the wave by a transposed butterfly, over the
+// workgroup's waves with LDS float atomics, and reach HBM as one FP32 atomic per (tile, gaussian,
+// term).
 //
 // The forward and the backward evaluate the cutoff decisions with the same inline functions in
 // this translation unit, compiled without floating-point contraction, so both take identical
@@ -22,27 +29,43 @@ namespace fgs {
 
 namespace {
 
-struct Pair {
-    float dx, dy, Q;
-};
+// s = -log2(e)/2 scales the staged conic; -2/s = 4 ln 2 turns the scaled form's derivative back
+// into the gradient of the 2D mean.
+constexpr float kConicScale = -0.721347520444481703680f;
+constexpr float kMeanGradScale = 2.772588722239781237669f;
 
-__device__ __forceinline__ float quad_form(float ca, float cb, float cc, float dx, float dy)
-{
-    // Q = ca dx^2 + 2 cb dx dy + cc dy^2, fixed operation order
-    const float t0 = ca * dx * dx;
-    const float t1 = 2.0f * cb * dx * dy;
-    const float t2 = cc * dy * dy;
-    return (t0 + t1) + t2;
-}
-
-__device__ __forceinline__ void stage(const Rec &R, int x0, int y0, float4 &a, float4 &b, float4 &c)
+// Record of a list entry in tile-local coordinates: a = {mean x, mean y, s a, s b}, b = {s c,
+// opacity, depth, 0}, c = {r, g, b, 0} with (a, b, c) the conic. mean and conic (unscaled) are
+// returned for the strip test.
+__device__ __forceinline__ void stage(const Rec &R, int x0, int y0, float4 &a, float4 &b, float4 &c, float &mx,
+                                      float &my)
 {
     // projected mean in tile-local coordinates: integer part is exact, one rounding for the sum
-    const float mx = (float)(__float_as_int(R.r0.x) - x0) + R.r0.z;
-    const float my = (float)(__float_as_int(R.r0.y) - y0) + R.r0.w;
-    a = make_float4(mx, my, R.r1.x, R.r1.y);          // mean2 (local), conic a, conic b
-    b = make_float4(R.r1.z, R.r1.w, R.r2.w, 0.0f);    // conic c, opacity, depth
-    c = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.0f);    // rgb
+    mx = (float)(__float_as_int(R.r0.x) - x0) + R.r0.z;
+    my = (float)(__float_as_int(R.r0.y) - y0) + R.r0.w;
+    a = make_float4(mx, my, kConicScale * R.r1.x, kConicScale * R.r1.y);
+    b = make_float4(kConicScale * R.r1.z, R.r1.w, R.r2.w, 0.0f);
+    c = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.0f);
+}
+
+// One (pixel, staged record) pair: offsets from the mean, the products of the scaled conic with
+// them (reused by the backward), q = s Q in a fixed operation order and G = 2^q = exp(-Q/2).
+struct PairEval {
+    float dx, dy, Adx, Bdx, Cdy, q, G;
+};
+
+__device__ __forceinline__ PairEval eval_pair(const float4 &a4, const float4 &b4, float px, float py)
+{
+    PairEval e;
+    e.dx = px - a4.x;
+    e.dy = py - a4.y;
+    e.Adx = a4.z * e.dx;
+    e.Bdx = a4.w * e.dx;
+    e.Cdy = b4.x * e.dy;
+    const float t0 = e.Adx * e.dx, t1 = e.Bdx * e.dy, t2 = e.Cdy * e.dy;
+    e.q = __builtin_fmaf(2.0f, t1, t0) + t2;  // (t0 + 2 t1) + t2; 2 t1 is exact
+    e.G = __builtin_amdgcn_exp2f(e.q);        // q <= 0 up to rounding, >= s sigma_cut^2 when used
+    return e;
 }
 
 // Minimum of the quadratic form Q(p - m) = a dx^2 + 2 b dx dy + c dy^2 over the rectangle
@@ -71,21 +94,17 @@ __device__ __forceinline__ float rect_min_q(float a, float b, float c, float ia,
 }
 
 // Bit w set when the sigma_cut ellipse of a staged record can reach a pixel centre of wave w's
-// strip (rows [w R, w R + R) of the tile, R = 64 / TW). Conservative by a relative 1e-3 margin:
-// the per-pixel test stays the exact decision.
-// Bit w set when the sigma_cut ellipse of a staged record can reach a pixel centre of wave w's
 // strip (rows [w R, w R + R) of the tile, R = 64 / tw). Conservative by a relative 1e-3 margin:
-// the per-pixel test stays the exact decision.
+// the per-pixel test stays the exact decision. (mx, my): tile-local mean; (ca, cb, cc): conic.
 template <int NW>
-__device__ __forceinline__ uint32_t strip_mask(const float4 &a4, const float4 &b4, float cut2, int tw)
+__device__ __forceinline__ uint32_t strip_mask(float mx, float my, float ca, float cb, float cc, float cut2, int tw)
 {
     const int R = kWave / tw;
     uint32_t m = 0;
-    const float ia = __frcp_rn(a4.z), ic = __frcp_rn(b4.x);
+    const float ia = __frcp_rn(ca), ic = __frcp_rn(cc);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const float q = rect_min_q(a4.z, a4.w, b4.x, ia, ic, a4.x, a4.y, 0.5f, tw - 0.5f, w * R + 0.5f,
-                                   w * R + R - 0.5f);
+        const float q = rect_min_q(ca, cb, cc, ia, ic, mx, my, 0.5f, tw - 0.5f, w * R + 0.5f, w * R + R - 0.5f);
         if (q <= cut2 * 1.001f) m |= 1u << w;
     }
     return m;
@@ -178,8 +197,8 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 // Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
-// tile_w x tile_h = NT pixels).
-template <int NT>
+// tile_w x tile_h = NT pixels). COUNT: accumulate the profiling work counters.
+template <int NT, bool COUNT>
 __device__ void tile_fwd(const ViewK &V, int tile)
 {
     constexpr int NW = NT / kWave;
@@ -202,6 +221,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
     const uint2 range = V.ranges[tile];
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
+    const float qcut = kConicScale * cut2;
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
     uint32_t last = 0, ntest = 0, staged = 0;
@@ -213,48 +233,47 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         staged += min((uint32_t)NT, range.y - b);
         const uint32_t j = b + tid;
         if (j < range.y) {
+            const Rec R = rec[vals[j]];
             float4 a4, b4, c4;
-            stage(rec[vals[j]], x0, y0, a4, b4, c4);
+            float mx, my;
+            stage(R, x0, y0, a4, b4, c4, mx, my);
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
-            smask[tid] = (uint8_t)strip_mask<NW>(a4, b4, cut2, TW);
+            smask[tid] = (uint8_t)strip_mask<NW>(mx, my, R.r1.x, R.r1.y, R.r1.z, cut2, TW);
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, range.y - b);
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
+        const uint32_t base = b - range.x + 1;
         // Branch-free per pair: every lane evaluates the entry and the decisions select what is
-        // kept (the arithmetic of a kept pair is the same as with branches); the wave leaves the
-        // list once all of its pixels are done.
+        // kept; the wave leaves the list once all of its pixels are done.
         for (int i = 0; i < len; ++i) {
             if (__ballot(!done) == 0) break;
             const int k = slist[wid][i];
-            const float4 a4 = sa[k];
-            const float dx = px - a4.x, dy = py - a4.y;
-            const float4 b4 = sb[k];
-            const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
-            const bool near = !done && !(Q > cut2);
-            const float G = __expf(-0.5f * Q);
-            const float alpha = fminf(rk.alpha_max, b4.y * G);
+            const float4 a4 = sa[k], b4 = sb[k];
+            const PairEval e = eval_pair(a4, b4, px, py);
+            const bool near = !done && !(e.q < qcut);
+            const float alpha = fminf(rk.alpha_max, b4.y * e.G);
             const float Tn = T * (1.0f - alpha);
             const bool take = near && !(alpha < rk.alpha_min);
             const bool stop = take && Tn < rk.T_min;
             const bool blend = take && !stop;
             const float w = blend ? alpha * T : 0.0f;
             const float4 c4 = sc[k];
-            C0 += w * c4.x;
-            C1 += w * c4.y;
-            C2 += w * c4.z;
-            D += w * b4.z;
+            C0 = __builtin_fmaf(w, c4.x, C0);
+            C1 = __builtin_fmaf(w, c4.y, C1);
+            C2 = __builtin_fmaf(w, c4.z, C2);
+            D = __builtin_fmaf(w, b4.z, D);
             A += w;
             T = blend ? Tn : T;
             done = done || stop;
-            ntest += near ? 1u : 0u;
+            if (COUNT) ntest += near ? 1u : 0u;
             ncon += blend ? 1 : 0;
-            last = blend ? b + k - range.x + 1 : last;
+            last = blend ? base + k : last;
         }
     }
-    if (V.counts) {
+    if (COUNT) {
         // work counters (profiling only): block sums, one atomic per block and counter
         if (tid == 0) red[0] = red[1] = 0ull;
         __syncthreads();
@@ -316,6 +335,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
     const uint2 range = V.ranges[tile];
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
+    const float qcut = kConicScale * cut2;
     const int64_t P = (int64_t)W * H;
     const int64_t p = (int64_t)y * W + x;
 
@@ -330,8 +350,11 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         gD = V.ddepth[p] * (V.ddepth_scale ? *V.ddepth_scale : 1.0f);
         gA = V.dalpha ? V.dalpha[p] : 0.0f;
     }
+    // S: what the pairs behind the current one (and the background) pass back through its
+    // transmittance: dL/dC . C_behind + dL/dD D_behind - dL/dA T_final, with C_behind, D_behind
+    // the colour and depth blended behind it including the background's T_final share.
     const float Tf = T;
-    float BC0 = Tf * rk.bg[0], BC1 = Tf * rk.bg[1], BC2 = Tf * rk.bg[2], BD = Tf * rk.bg_depth;
+    float S = Tf * (gC0 * rk.bg[0] + gC1 * rk.bg[1] + gC2 * rk.bg[2] + gD * rk.bg_depth - gA);
 
     if (tid == 0) smax = 0;
 #pragma unroll
@@ -347,70 +370,61 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         __syncthreads();
         if (tid < cnt) {
             const uint32_t r = vals[bstart + tid];
+            const Rec R = rec[r];
             float4 a4, b4, c4;
-            stage(rec[r], x0, y0, a4, b4, c4);
+            float mx, my;
+            stage(R, x0, y0, a4, b4, c4, mx, my);
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
             srank[tid] = ids[r];  // gradients are accumulated by gaussian id
-            smask[tid] = (uint8_t)strip_mask<NW>(a4, b4, cut2, TW);
+            smask[tid] = (uint8_t)strip_mask<NW>(mx, my, R.r1.x, R.r1.y, R.r1.z, cut2, TW);
         }
         __syncthreads();
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
+        const uint32_t base = bstart - range.x;
+        // Branch-free per pair, like the forward: the decisions select what is kept, and a lane
+        // that does not take the pair contributes exact zeros.
         for (int i = len - 1; i >= 0; --i) {
             const int k = slist[wid][i];
-            const uint32_t pos = bstart + k - range.x;  // list position of entry k
+            const float4 a4 = sa[k], b4 = sb[k], c4 = sc[k];
+            const PairEval e = eval_pair(a4, b4, px, py);
+            const float ar = b4.y * e.G;
+            const float alpha = fminf(rk.alpha_max, ar);
+            // blended in the forward: before the pixel's last blended position, inside the
+            // cutoff and above alpha_min
+            const bool take = base + k < L && !(e.q < qcut) && !(alpha < rk.alpha_min);
+            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
+            const float Ti = T * inv;
+            const float w = take ? alpha * Ti : 0.0f;
+            // dL/dalpha_i = T_i X_i - S / (1 - alpha_i), X_i = dL/dC . c_i + dL/dD d_i
+            const float X = __builtin_fmaf(gC0, c4.x, __builtin_fmaf(gC1, c4.y, __builtin_fmaf(gC2, c4.z, gD * b4.z)));
+            const float dal = __builtin_fmaf(-S, inv, Ti * X);
+            // a clamped alpha (o G > alpha_max) passes nothing to opacity, mean or conic
+            const float dalg = take && !(ar > rk.alpha_max) ? dal : 0.0f;
+            S = __builtin_fmaf(w, X, S);
+            T = take ? Ti : T;
             float g[10];
-            bool contrib = false;
-            if (pos < L) {
-                const float4 a4 = sa[k];
-                const float dx = px - a4.x, dy = py - a4.y;
-                const float4 b4 = sb[k];
-                const float Q = quad_form(a4.z, a4.w, b4.x, dx, dy);
-                if (!(Q > cut2)) {
-                    const float G = __expf(-0.5f * Q);
-                    const float ar = b4.y * G;
-                    const float alpha = fminf(rk.alpha_max, ar);
-                    if (!(alpha < rk.alpha_min)) {
-                        contrib = true;
-                        const float4 c4 = sc[k];
-                        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
-                        const float Ti = T * inv;
-                        const float w = alpha * Ti;
-                        const float dal = Ti * (gC0 * c4.x + gC1 * c4.y + gC2 * c4.z + gD * b4.z) -
-                                          (gC0 * BC0 + gC1 * BC1 + gC2 * BC2 + gD * BD - gA * Tf) * inv;
-                        g[6] = gC0 * w;
-                        g[7] = gC1 * w;
-                        g[8] = gC2 * w;
-                        g[9] = gD * w;
-                        if (ar > rk.alpha_max) {
-                            g[0] = g[1] = g[2] = g[3] = g[4] = g[5] = 0.0f;
-                        } else {
-                            g[5] = dal * G;
-                            const float dQ = -0.5f * alpha * dal;
-                            g[0] = -2.0f * dQ * (a4.z * dx + a4.w * dy);
-                            g[1] = -2.0f * dQ * (a4.w * dx + b4.x * dy);
-                            g[2] = dQ * dx * dx;
-                            g[3] = 2.0f * dQ * dx * dy;
-                            g[4] = dQ * dy * dy;
-                        }
-                        BC0 += w * c4.x;
-                        BC1 += w * c4.y;
-                        BC2 += w * c4.z;
-                        BD += w * b4.z;
-                        T = Ti;
-                    }
-                }
-            }
-            if (!contrib) {
-#pragma unroll
-                for (int c = 0; c < 10; ++c) g[c] = 0.0f;
-            }
-            const uint64_t any = __ballot(contrib);
+            g[6] = gC0 * w;
+            g[7] = gC1 * w;
+            g[8] = gC2 * w;
+            g[9] = gD * w;
+            g[5] = dalg * e.G;  // d alpha / d opacity = G
+            // dL/dQ = -alpha dL/dalpha / 2; the mean gradient is -2 dL/dQ (a dx + b dy, b dx + c dy)
+            // = dL/dQ (-2/s) (s a dx + s b dy, ...), from the scaled products of the forward form
+            const float dQ = -0.5f * (alpha * dalg);
+            const float km = kMeanGradScale * dQ;
+            g[0] = km * __builtin_fmaf(a4.w, e.dy, e.Adx);
+            g[1] = km * (e.Bdx + e.Cdy);
+            const float dQdx = dQ * e.dx;
+            g[2] = dQdx * e.dx;
+            g[3] = 2.0f * (dQdx * e.dy);
+            g[4] = (dQ * e.dy) * e.dy;
+            const uint64_t any = __ballot(take);
             if (any) {
                 if ((any & (any - 1)) == 0) {
                     // a single contributing lane: no reduction needed
-                    if (contrib) {
+                    if (take) {
 #pragma unroll
                         for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
                     }
@@ -439,8 +453,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     __syncthreads();  // LDS is restaged by the next tile of a persistent workgroup
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT>(V, blockIdx.x); }
+template <int NT, bool COUNT>
+__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT>(V, blockIdx.x); }
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT>(V, blockIdx.x); }
@@ -455,7 +469,7 @@ __device__ inline int view_of(const ViewK *views, int nv, uint32_t g)
 // Persistent rasterizer over a window of views: workgroups pull (view, tile) items from a queue
 // through an atomic counter until it runs past the last item. 256 threads per workgroup; each
 // view's tile has 256 pixels in its own shape (16x16, 32x8 or 8x32).
-template <bool FWD>
+template <bool FWD, bool COUNT>
 __global__ void __launch_bounds__(256)
 k_raster_queue(const ViewK *__restrict__ views, int nv, const uint32_t *__restrict__ queue, uint32_t total,
                uint32_t *__restrict__ counter)
@@ -470,7 +484,7 @@ k_raster_queue(const ViewK *__restrict__ views, int nv, const uint32_t *__restri
         const uint32_t g = queue ? queue[q] : q;
         const int v = view_of(views, nv, g);
         const ViewK &V = views[v];
-        if (FWD) tile_fwd<256>(V, (int)(g - V.tile_base));
+        if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
         else tile_bwd<256>(V, (int)(g - V.tile_base));
     }
 }
@@ -500,9 +514,15 @@ static void launch_fwd_view(const ViewK &V, hipStream_t s)
 {
     const unsigned tiles = (unsigned)(V.rk.tiles_x * V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
-    if (nt == 256) hipLaunchKernelGGL(k_raster_fwd<256>, dim3(tiles), dim3(256), 0, s, V);
-    else if (nt == 512) hipLaunchKernelGGL(k_raster_fwd<512>, dim3(tiles), dim3(512), 0, s, V);
-    else hipLaunchKernelGGL(k_raster_fwd<64>, dim3(tiles), dim3(64), 0, s, V);
+    if (V.counts) {
+        if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, true>), dim3(tiles), dim3(256), 0, s, V);
+        else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, true>), dim3(tiles), dim3(512), 0, s, V);
+        else hipLaunchKernelGGL((k_raster_fwd<64, true>), dim3(tiles), dim3(64), 0, s, V);
+    } else {
+        if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, false>), dim3(tiles), dim3(256), 0, s, V);
+        else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, false>), dim3(tiles), dim3(512), 0, s, V);
+        else hipLaunchKernelGGL((k_raster_fwd<64, false>), dim3(tiles), dim3(64), 0, s, V);
+    }
 }
 
 static void launch_bwd_view(const ViewK &V, hipStream_t s)
@@ -546,12 +566,16 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
     launch_bwd_view(V, s);
 }
 
-void launch_raster_queue(bool fwd, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
+void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
                          uint32_t *counter, int blocks, hipStream_t s)
 {
     launch_zero_u32(counter, 1, s);
-    if (fwd) hipLaunchKernelGGL(k_raster_queue<true>, dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
-    else hipLaunchKernelGGL(k_raster_queue<false>, dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+    if (fwd && count)
+        hipLaunchKernelGGL((k_raster_queue<true, true>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+    else if (fwd)
+        hipLaunchKernelGGL((k_raster_queue<true, false>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+    else
+        hipLaunchKernelGGL((k_raster_queue<false, false>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
 }
 
 }  // namespace fgs

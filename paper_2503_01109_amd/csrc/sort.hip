@@ -3,9 +3,12 @@
 //
 // Ordering scheme: the n gaussians are first sorted by depth (32-bit keys, the bits of the
 // positive FP32 depth; ids emitted in ascending order and a stable sort, so equal depths keep
-// ascending index). Every gaussian then emits one (tile, depth rank) pair per covered tile, in
-// depth order. A stable sort of the pairs by tile alone leaves each tile's list ordered by
-// (depth, index) - the pairs never need a depth key of their own.
+// ascending index). Every gaussian then emits one (super-tile, depth rank) pair per covered
+// square of kSuper x kSuper tiles, in depth order; a stable sort of those pairs by super-tile
+// alone leaves each super-tile's list in (depth, index) order, and an in-order expansion of each
+// super-tile list into the lists of its tiles keeps that order. The result is exactly the stable
+// (tile, depth rank) order of one pair per covered tile, while the sort only moves one pair per
+// covered super-tile; no pair ever carries a depth key of its own.
 //
 // The radix sort is an LSD sort with 8-bit digits and a fixed grid: block b handles the b-th
 // contiguous chunk of the input, whose length is read from device memory, so no host round

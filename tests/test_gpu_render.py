@@ -280,3 +280,26 @@ def test_deterministic_forward(fgs, ctx):
     b = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
     for k in ("rgb", "depth", "alpha", "T_final", "n_contrib"):
         assert np.array_equal(host(a[k]), host(b[k]))
+
+
+def test_profiling_levels_and_work_counters(fgs, ctx):
+    """Level 1 times the rasterizer without counting; level 2 counts exactly: the pairs blended
+    are the sum of the per-pixel contributor counts, and profiling changes no output bit."""
+    p = synth.scene_small(8)
+    cam = synth.camera_small()
+    pd = params_dev(p)
+    plain = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    ctx.profile(1)
+    a = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    rep1 = ctx.profile_report()
+    ctx.profile(2)
+    b = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    rep2 = ctx.profile_report()
+    ctx.profile(0)
+    assert rep1["raster_fwd"][1] == 1 and rep1["counts"]["forwards"] == 0
+    assert rep1["counts"]["pairs_blended"] == 0 and rep1["counts"]["pairs_examined"] == 0
+    assert rep2["counts"]["forwards"] == 1
+    assert rep2["counts"]["pairs_blended"] == int(host(b["n_contrib"]).sum()) > 0
+    assert rep2["counts"]["pairs_examined"] >= rep2["counts"]["pairs_blended"]
+    for k in ("rgb", "depth", "alpha", "T_final", "n_contrib"):
+        assert np.array_equal(host(a[k]), host(plain[k])) and np.array_equal(host(b[k]), host(plain[k])), k
