@@ -22,7 +22,7 @@ import os
 import time
 
 TILE_SHAPES = ((16, 16), (32, 8), (8, 32))
-BLOCKS_PER_CU = (2, 4, 8)
+BLOCKS_PER_CU = (0, 2, 4, 8)  # 0: one workgroup per (view, tile) item
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fgs_autotune.json")
 
 

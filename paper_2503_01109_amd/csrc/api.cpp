@@ -62,13 +62,14 @@ struct fgs_ctx {
     int device = 0;
     std::string err;
     // workspace of one forward (sized for the largest n / pair capacity seen)
-    DBuf rec_by_id, rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
+    DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
     DBuf rect_sorted, start_rank;
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
     DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words;
     int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
     DBuf words;  // status words (ST_WORDS) + small device scalars
     int64_t ws_n = -1, ws_cap = -1;
+    int hist_G = 0;  // radix-sort workgroups the hist buffer holds
     // mapping-step buffers
     DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
     DBuf seed_ws, seed_sc;
@@ -219,7 +220,6 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     const int64_t cc = cap > ctx->ws_cap ? cap : ctx->ws_cap;
     const size_t N = (size_t)(nn > 0 ? nn : 1), C = (size_t)(cc > 0 ? cc : 1);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(ctx, ctx->rec_by_id.ensure(N * sizeof(Rec)));
     HIP_TRY(ctx, ctx->rect.ensure(N * sizeof(uint2)));
     HIP_TRY(ctx, ctx->count.ensure(N * 4));
     HIP_TRY(ctx, ctx->dkA.ensure(N * 4));
@@ -234,8 +234,9 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvB.ensure(C * 4));
-    const int64_t G = sort_blocks(cc > nn ? cc : nn);
+    const int G = std::max(sort_blocks(nn, kDepthSortPerBlock), sort_blocks(cc > nn ? cc : nn, kPairSortPerBlock));
     HIP_TRY(ctx, ctx->hist.ensure(((size_t)G * 256 + 256) * 4));
+    ctx->hist_G = G;
     if (nn > ctx->ws_n) {
         // the backward keeps grad2d all-zero between calls (project_bwd clears what it reads)
         HIP_TRY(ctx, ctx->grad2d.ensure(N * 10 * 4));
@@ -279,12 +280,14 @@ BinWS bin_ws(fgs_ctx *ctx)
     return b;
 }
 
-SortWS sort_ws(fgs_ctx *ctx, int64_t elems)
+// Scratch of one radix sort of up to elems elements; the grid is capped by what the workspace
+// holds (a smaller grid only gives each workgroup a larger share).
+SortWS sort_ws(fgs_ctx *ctx, int64_t elems, int per_block = kPairSortPerBlock)
 {
     SortWS s;
-    s.G = sort_blocks(elems);
+    s.G = std::min(sort_blocks(elems, per_block), ctx->hist_G);
     s.hist = ctx->hist.as<uint32_t>();
-    s.totals = ctx->hist.as<uint32_t>() + (size_t)sort_blocks(ctx->ws_cap > ctx->ws_n ? ctx->ws_cap : ctx->ws_n) * 256;
+    s.totals = ctx->hist.as<uint32_t>() + (size_t)ctx->hist_G * 256;
     return s;
 }
 
@@ -440,13 +443,13 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
 
     {
         Stage st_(ctx, "project");
-        launch_project(pk, ck, rk, ctx->rec_by_id.as<Rec>(), ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
+        launch_project(pk, ck, rk, sp.rec, ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
                        ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, kSuperShift, ktotal, s);
     }
     {
         Stage st_(ctx, "depth_sort");
         launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n), s);
+                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n, kDepthSortPerBlock), s);
     }
     {
         // one pair per covered super-tile, in depth order
@@ -462,10 +465,10 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     }
     {
         Stage st_(ctx, "bin");
-        launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->rec_by_id.as<Rec>(),
-                    ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap,
-                    ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), sp.rec, ctx->rect_sorted.as<uint2>(),
-                    ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs, nullptr, s);
+        launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->blocksums.as<uint32_t>(),
+                    ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(),
+                    ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(),
+                    status_words(ctx), nsup_pairs, nullptr, s);
     }
     const uint2 *sranges = ctx->bin_sranges.as<uint2>();
     {
@@ -477,10 +480,10 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
         const bool one_pass = sbits <= 8;
         if (!one_pass) launch_ranges(keys, nsup_pairs, L.cap, ctx->bin_sranges.as<uint2>(), nsup, s);
         launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr,
-                          ctx->rect_sorted.as<uint2>(), supers_x, nsup, s);
+                          ctx->rect.as<uint2>(), supers_x, nsup, s);
         launch_bin_tiles(bw, supers_x, nsup, rk.tiles_x, rk.tiles_y, L.cap, ktotal, sp.ranges, status_words(ctx),
                          npairs, host_status, s);
-        launch_bin_place(bw, svals, sranges, ctx->rect_sorted.as<uint2>(), supers_x, rk.tiles_x, rk.tiles_y,
+        launch_bin_place(bw, svals, sranges, ctx->rect.as<uint2>(), supers_x, rk.tiles_x, rk.tiles_y,
                          sp.ranges, sp.vals, s);
     }
     if (raster) {
@@ -507,7 +510,7 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     float *g2 = ctx->grad2d.as<float>();
     {
         Stage st_(ctx, "raster_bwd");
-        launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ids, sp.ranges, sp.last, sp.tfinal, drgb,
+        launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb,
                           ddepth, dalpha, dscale, g2, g.n, s);
     }
     {
@@ -612,7 +615,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (!ctx) return FGS_OK;
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
     clear_profile(ctx, true);
-    DBuf *bufs[] = {&ctx->prof_counts, &ctx->rec_by_id, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
+    DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets};
@@ -1229,7 +1232,6 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         V.H = cam.height;
         V.rec = sp.rec;
         V.vals = sp.vals;
-        V.ids = sp.ids;
         V.ranges = sp.ranges;
         V.last = sp.last;
         V.tfinal = sp.tfinal;
@@ -1365,7 +1367,7 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
         if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    w->blocks = (blocks_per_cu ? blocks_per_cu : 4) * cus;
+    w->blocks = blocks_per_cu * cus;  // 0: one workgroup per (view, tile) item
     const size_t wbytes = (size_t)(WW_DSCALE + n_views) * 4 + 64;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = w->img.ensure((size_t)pix * 4 * 4);

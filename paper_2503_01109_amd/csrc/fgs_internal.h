@@ -59,12 +59,12 @@ enum : int {
 struct StateLayout {
     int64_t n = 0, P = 0, T = 0;
     int32_t W = 0, H = 0, tw = 0, th = 0, tiles_x = 0, tiles_y = 0;
-    size_t off_rec = 0;    // Rec x n, depth order
-    size_t off_ids = 0;    // u32 x n: gaussian id of depth rank r
+    size_t off_rec = 0;    // Rec x n, by gaussian id
+    size_t off_ids = 0;    // u32 x n: gaussian id of depth rank r (used by the binning)
     size_t off_ranges = 0; // uint2 x T: [start, end) into vals per tile
     size_t off_last = 0;   // u32 x P: list position after a pixel's last blended gaussian
     size_t off_tfinal = 0; // f32 x P: final transmittance
-    size_t off_vals = 0;   // u32 x cap: depth ranks, per tile in (depth, index) order
+    size_t off_vals = 0;   // u32 x cap: gaussian ids, per tile in (depth, index) order
     int64_t cap = 0;
     size_t fixed = 0, bytes = 0;
 };
@@ -83,15 +83,21 @@ struct SortWS {  // radix-sort scratch of one sort
     uint32_t *totals;  // 256
     int G;
 };
-int sort_blocks(int64_t cap);
+// Radix-sort grid for up to cap elements at about per_block elements per workgroup (1..4096
+// workgroups). Any grid sorts correctly: each workgroup takes a contiguous share of the actual
+// element count. The depth sort (n known on the host) uses small shares so that every compute
+// unit takes part; pair sorts are sized from their capacity and use larger ones.
+constexpr int kDepthSortPerBlock = 512, kPairSortPerBlock = 2048;
+int sort_blocks(int64_t cap, int per_block);
 
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 
-// Projects every gaussian; writes n to *n_out (the element count of the depth sort). count[i]
-// receives the number of tiles (shift 0) or super-tiles (tile rectangle >> shift) covered, and
-// *ktotal the number of (tile, gaussian) pairs.
-void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id,
+// Projects every gaussian into rec (by id: the forward state's records); writes n to *n_out (the
+// element count of the depth sort). count[i] receives the number of tiles (shift 0) or
+// super-tiles (tile rectangle >> shift) covered, rect[i] the tile rectangle, and *ktotal the
+// number of (tile, gaussian) pairs.
+void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
                     uint32_t *ktotal, hipStream_t s);
 
@@ -109,18 +115,17 @@ int64_t scan_blocks(int64_t n);
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
                         uint32_t *status, const uint32_t *ktotal, hipStream_t s);
 
-// Emit one (key, rank) pair per covered tile in depth order, and gather records into depth
-// order; with shift > 0 the keys are super-tiles (tile rectangle >> shift, keys_x super-tiles per
-// row). offsets is scratch of n + 1 words (per-rank exclusive offsets). If the pairs exceed
-// cap, nothing is emitted for sorting (*n_pairs_dev = 0) and the required count is recorded in
-// status. host_status (nullable, host-mapped): [0] = pairs, [1] |= overflow.
-// rect_sorted (n) receives the tile rectangles in depth order, start_rank (emit_chunks(cap)
-// words) the first rank of every emission chunk.
+// Emit one (key, gaussian id) pair per covered tile in depth order; with shift > 0 the keys are
+// super-tiles (tile rectangle >> shift, keys_x super-tiles per row). offsets is scratch of n + 1
+// words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
+// (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
+// host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
+// depth order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk.
 int64_t emit_chunks(int64_t cap);
-void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap,
-                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint2 *rect_sorted, uint32_t *start_rank,
-                 uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s);
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
+                 uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
+                 uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
+                 uint32_t *host_status, hipStream_t s);
 
 // Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
 // are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by super-tile
@@ -129,7 +134,7 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 //   launch_bin_tiles:  prefixes over chunks and tiles, the tile ranges, and the capacity check of
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
 //                      overflow);
-//   launch_bin_place:  every entry's depth rank into the lists of its tiles (vals, K entries).
+//   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
 constexpr int kSuper = 4, kSuperShift = 2;
 struct BinWS {
     uint32_t *cstart;      // nsup + 1
@@ -144,11 +149,11 @@ int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 // digit_totals (nullable): the per-digit totals of a single-pass super-tile sort, from which the
 // super-tile ranges are written into sranges; else sranges holds them already.
 void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect_sorted, int supers_x, int nsup, hipStream_t s);
+                       const uint2 *rect, int supers_x, int nsup, hipStream_t s);
 void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
                       const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
                       uint32_t *host_status, hipStream_t s);
-void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect_sorted,
+void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect,
                       int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s);
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
@@ -165,7 +170,7 @@ struct ViewK {
     RasterK rk;
     int32_t W, H;
     const Rec *rec;
-    const uint32_t *vals, *ids;
+    const uint32_t *vals;  // tile lists of gaussian ids
     const uint2 *ranges;
     uint32_t *last;
     float *tfinal;
@@ -184,9 +189,10 @@ bool tile_supported_window(int tw, int th);
 void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t *ka, uint32_t *va, uint32_t *kb,
                         uint32_t *vb, uint32_t *queue, uint32_t *n_dev, const SortWS &ws, hipStream_t s);
 
-// Persistent window rasterizer: blocks pull items q < total from the queue (item ids g, or q
-// itself when queue is NULL) and process tile g - views[v].tile_base of view v. counter is
-// zeroed first (with a kernel, so the sequence can be captured in a graph). count: the forward
+// Window rasterizer over items q < total (item ids g = queue[q], or q itself when queue is NULL;
+// item g is tile g - views[v].tile_base of view v). blocks > 0: a persistent grid of that many
+// workgroups pulls items through counter, zeroed first with a kernel so the sequence can be
+// captured in a graph; blocks <= 0: one workgroup per item in queue order. count: the forward
 // adds its work counters to views[v].counts (which must then be non-null).
 void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
                          uint32_t *counter, int blocks, hipStream_t s);
@@ -199,9 +205,9 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
 // to a device float multiplying ddepth (the 1/P_v of the mean depth term). grad2d: 10 planes of n,
-// indexed by gaussian id (ids maps depth rank -> id).
+// indexed by gaussian id (the tile lists hold ids).
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint32_t *ids, const uint2 *ranges, const uint32_t *last, const float *tfinal,
+                       const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha,
                        const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s);
 

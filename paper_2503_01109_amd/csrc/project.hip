@@ -366,13 +366,13 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
 
 }  // namespace
 
-void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec_by_id, uint2 *rect,
+void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
                     uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *ktotal,
                     hipStream_t s)
 {
     const int64_t blocks = g.n > 0 ? (g.n + 255) / 256 : 1;
     launch_zero_u32(ktotal, 1, s);
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec_by_id, rect, count,
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec, rect, count,
                        dkey, ids, n_out, shift, ktotal);
 }
 

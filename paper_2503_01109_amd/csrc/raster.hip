@@ -1,8 +1,8 @@
 // Tile rasterizer: front-to-back alpha blending of Eq. 1 (colour, depth and opacity) and its
 // backward.
 //
-// One workgroup per screen tile, one pixel per thread. The tile's list (depth-ordered ranks of
-// the gaussians whose 3-sigma box touches the tile) is walked in batches; each batch of records
+// One workgroup per screen tile, one pixel per thread. The tile's list (ids of the gaussians whose
+// 3-sigma box touches the tile, in (depth, index) order) is walked in batches; each batch of records
 // is gathered from HBM once by the whole workgroup, converted to tile-local coordinates and
 // staged in LDS, then every pixel reads the records as LDS broadcasts. A pixel applies the exact
 // per-pixel cutoffs (Mahalanobis distance <= sigma_cut, alpha >= alpha_min, stop before T drops
@@ -314,12 +314,11 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int W = V.W, H = V.H;
     const Rec *__restrict__ rec = V.rec;
     const uint32_t *__restrict__ vals = V.vals;
-    const uint32_t *__restrict__ ids = V.ids;
     float *__restrict__ grad2d = V.grad2d;
     const int64_t n = V.n;
     const int TW = rk.tile_w, TH = rk.tile_h;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
-    __shared__ uint32_t srank[NT];
+    __shared__ uint32_t sid[NT];
     __shared__ float sacc[10][NT + 1];  // padded: the ten terms of one entry fall in different banks
     __shared__ uint32_t smax;
     __shared__ uint8_t smask[NT];
@@ -369,15 +368,15 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         const int cnt = (int)(bend - bstart);
         __syncthreads();
         if (tid < cnt) {
-            const uint32_t r = vals[bstart + tid];
-            const Rec R = rec[r];
+            const uint32_t id = vals[bstart + tid];
+            const Rec R = rec[id];
             float4 a4, b4, c4;
             float mx, my;
             stage(R, x0, y0, a4, b4, c4, mx, my);
             sa[tid] = a4;
             sb[tid] = b4;
             sc[tid] = c4;
-            srank[tid] = ids[r];  // gradients are accumulated by gaussian id
+            sid[tid] = id;  // gradients are accumulated by gaussian id
             smask[tid] = (uint8_t)strip_mask<NW>(mx, my, R.r1.x, R.r1.y, R.r1.z, cut2, TW);
         }
         __syncthreads();
@@ -439,12 +438,12 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         }
         __syncthreads();
         if (tid < cnt) {
-            const uint32_t r = srank[tid];
+            const uint32_t id = sid[tid];
 #pragma unroll
             for (int c = 0; c < 10; ++c) {
                 const float v = sacc[c][tid];
                 if (v != 0.0f) {
-                    unsafeAtomicAdd(&grad2d[c * n + r], v);
+                    unsafeAtomicAdd(&grad2d[c * n + id], v);
                     sacc[c][tid] = 0.0f;
                 }
             }
@@ -487,6 +486,19 @@ k_raster_queue(const ViewK *__restrict__ views, int nv, const uint32_t *__restri
         if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
         else tile_bwd<256>(V, (int)(g - V.tile_base));
     }
+}
+
+// The same items with one workgroup each (grid = total): the hardware dispatches workgroups in
+// index order, so the queue's order (longest list first) is kept without a counter.
+template <bool FWD, bool COUNT>
+__global__ void __launch_bounds__(256)
+k_raster_items(const ViewK *__restrict__ views, int nv, const uint32_t *__restrict__ queue)
+{
+    const uint32_t g = queue ? queue[blockIdx.x] : blockIdx.x;
+    const int v = view_of(views, nv, g);
+    const ViewK &V = views[v];
+    if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
+    else tile_bwd<256>(V, (int)(g - V.tile_base));
 }
 
 }  // namespace
@@ -548,12 +560,11 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 }
 
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint32_t *ids, const uint2 *ranges, const uint32_t *last, const float *tfinal,
+                       const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha, const float *ddepth_scale,
                        float *grad2d, int64_t n, hipStream_t s)
 {
     ViewK V = view_of_args(rk, W, H, rec, vals);
-    V.ids = ids;
     V.ranges = ranges;
     V.last = (uint32_t *)last;
     V.tfinal = (float *)tfinal;
@@ -569,6 +580,14 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
                          uint32_t *counter, int blocks, hipStream_t s)
 {
+    if (total == 0) return;
+    if (blocks <= 0) {
+        const dim3 grid(total);
+        if (fwd && count) hipLaunchKernelGGL((k_raster_items<true, true>), grid, dim3(256), 0, s, views_dev, nv, queue);
+        else if (fwd) hipLaunchKernelGGL((k_raster_items<true, false>), grid, dim3(256), 0, s, views_dev, nv, queue);
+        else hipLaunchKernelGGL((k_raster_items<false, false>), grid, dim3(256), 0, s, views_dev, nv, queue);
+        return;
+    }
     launch_zero_u32(counter, 1, s);
     if (fwd && count)
         hipLaunchKernelGGL((k_raster_queue<true, true>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);

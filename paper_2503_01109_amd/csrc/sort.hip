@@ -186,13 +186,13 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
 }
 
 // Per-rank exclusive offsets: offsets[r] = block offset + prefix of count[ids[.]] inside the
-// block (same partition as k_count_reduce); offsets[n] = total. Also gathers the records of
-// the gaussians that cover at least one tile into depth order.
+// block (same partition as k_count_reduce); offsets[n] = total. Also gathers the tile rectangles
+// of the gaussians that cover at least one tile into depth order, and the first rank of every
+// emission chunk.
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const Rec *__restrict__ rec_by_id,
-             const uint2 *__restrict__ rect, int64_t n, const uint32_t *__restrict__ blocksums, int nb,
-             uint32_t *__restrict__ offsets, Rec *__restrict__ rec_sorted, uint2 *__restrict__ rect_sorted,
-             uint32_t *__restrict__ start_rank, uint32_t max_chunks)
+k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
+             int64_t n, const uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ offsets,
+             uint2 *__restrict__ rect_sorted, uint32_t *__restrict__ start_rank, uint32_t max_chunks)
 {
     __shared__ uint32_t w[8];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
@@ -210,7 +210,6 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
         if (base + k < n) {
             offsets[base + k] = off;
             if (c[k]) {
-                rec_sorted[base + k] = rec_by_id[id[k]];
                 rect_sorted[base + k] = rect[id[k]];
                 // emission chunks whose first pair belongs to this rank
                 for (uint32_t q = (off + kEmitChunk - 1) / kEmitChunk; q < (off + c[k] + kEmitChunk - 1) / kEmitChunk &&
@@ -241,10 +240,10 @@ constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion 
 // indices; a block takes a chunk, finds the depth ranks it spans by binary search over the
 // per-rank offsets, and its threads write consecutive pair indices (coalesced), each finding its
 // rank by a binary search inside that span. A gaussian's pairs are its tile rectangle in
-// row-major order.
+// row-major order; each pair carries the gaussian's id.
 __global__ void __launch_bounds__(kSortThreads)
-k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start_rank,
-       int64_t n, int32_t tiles_x, int shift, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, const uint32_t *__restrict__ offsets,
+       const uint32_t *__restrict__ start_rank, int64_t n, int32_t tiles_x, int shift, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
        uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, uint32_t *__restrict__ host_status)
 {
     __shared__ uint32_t soff[kEmitSpan];
@@ -277,7 +276,7 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ offse
             const uint32_t w = tx1 - tx0 + 1;
             const uint32_t dy = idx / w;
             keys[j] = (ty0 + dy) * (uint32_t)tiles_x + tx0 + (idx - dy * w);
-            vals[j] = r;
+            vals[j] = ids[r];
         }
         __syncthreads();
     }
@@ -383,7 +382,7 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect_sorted, int supers_x, uint32_t *__restrict__ chist)
+            const uint2 *__restrict__ rect, int supers_x, uint32_t *__restrict__ chist)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
     const uint32_t c = blockIdx.x;
@@ -393,7 +392,7 @@ k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     __syncthreads();
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
         const uint32_t e = base + threadIdx.x;
-        const uint32_t m = e < cs.e1 ? cover_bits(rect_sorted[svals[e]], cs.sx, cs.sy) : 0u;
+        const uint32_t m = e < cs.e1 ? cover_bits(rect[svals[e]], cs.sx, cs.sy) : 0u;
 #pragma unroll
         for (int b = 0; b < kSuper * kSuper; ++b) {
             const uint64_t bal = __ballot((m >> b) & 1u);
@@ -455,11 +454,11 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int64_t T, int64_t cap, con
     }
 }
 
-// Per chunk: writes each entry's depth rank into the lists of the tiles it covers, in order.
+// Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order.
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect_sorted, int supers_x, int tiles_x, int tiles_y,
+            const uint2 *__restrict__ rect, int supers_x, int tiles_x, int tiles_y,
             const uint32_t *__restrict__ chist, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok,
             uint32_t *__restrict__ vals)
 {
@@ -479,10 +478,10 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
         const uint32_t e = base + tid;
-        uint32_t r = 0, m = 0;
+        uint32_t id = 0, m = 0;
         if (e < cs.e1) {
-            r = svals[e];
-            m = cover_bits(rect_sorted[r], cs.sx, cs.sy);
+            id = svals[e];
+            m = cover_bits(rect[id], cs.sx, cs.sy);
         }
         uint64_t bal[NB];
 #pragma unroll
@@ -495,7 +494,7 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
                 if ((m >> b) & 1u) {
                     uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
                     for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
-                    vals[pos] = r;
+                    vals[pos] = id;
                 }
             }
         }
@@ -576,9 +575,9 @@ void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t
     launch_radix_sort(ka, va, kb, vb, queue, n_dev, total, 24, ws, s);
 }
 
-int sort_blocks(int64_t cap)
+int sort_blocks(int64_t cap, int per_block)
 {
-    int64_t G = (cap + 2047) / 2048;
+    int64_t G = (cap + per_block - 1) / per_block;
     if (G < 1) G = 1;
     if (G > 4096) G = 4096;
     return (int)G;
@@ -640,28 +639,28 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 
 int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 1; }
 
-void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const Rec *rec_by_id,
-                 const uint32_t *blocksums, uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap,
-                 uint32_t *keys, uint32_t *vals, Rec *rec_sorted, uint2 *rect_sorted, uint32_t *start_rank,
-                 uint32_t *status, uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s)
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
+                 uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
+                 uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
+                 uint32_t *host_status, hipStream_t s)
 {
     // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
     const int nb = (int)scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rec_by_id, rect, n,
-                       blocksums, nb, offsets, rec_sorted, rect_sorted, start_rank, (uint32_t)emit_chunks(cap));
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, offsets,
-                       start_rank, n, keys_x, shift, cap, keys, vals, status, n_pairs_dev, host_status);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums,
+                       nb, offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap));
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, ids,
+                       offsets, start_rank, n, keys_x, shift, cap, keys, vals, status, n_pairs_dev, host_status);
 }
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
 void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect_sorted, int supers_x, int nsup, hipStream_t s)
+                       const uint2 *rect, int supers_x, int nsup, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
                        b.csuper, (uint32_t)b.max_chunks, b.nchunks);
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect_sorted, supers_x, b.chist);
+                       b.csuper, b.nchunks, rect, supers_x, b.chist);
 }
 
 void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
@@ -674,11 +673,11 @@ void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int t
                        ktotal, ranges, status, n_pairs_dev, host_status, b.ok);
 }
 
-void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect_sorted,
-                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s)
+void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect, int supers_x,
+                      int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect_sorted, supers_x, tiles_x, tiles_y, b.chist, ranges, b.ok, vals);
+                       b.csuper, b.nchunks, rect, supers_x, tiles_x, tiles_y, b.chist, ranges, b.ok, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,
