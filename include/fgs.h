@@ -209,22 +209,21 @@ fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_ga
 
 /* ------------------------------------ keyframe window ------------------------------------ */
 
-typedef struct fgs_window fgs_window; /* opaque: per-view states, work queue, captured graph */
+typedef struct fgs_window fgs_window; /* opaque: per-view states, item counter, captured graph */
 
 /* A keyframe window (Sec. III-D, III-E: the co-visible and random keyframes optimised together)
  * of n_views cameras ([host] array, copied) that may differ in size. tiles ([host], 2 ints per
  * view: tile_w, tile_h; NULL = 16x16) picks each view's rasterizer tile among 16x16, 32x8 and
  * 8x32. blocks_per_cu > 0 makes the rasterizer launches persistent grids of that many workgroups
- * per compute unit pulling (view, tile) items from a counter; 0 launches one workgroup per item,
- * dispatched in the queue's order. The window keeps its own stream for graph capture and orders it
- * against the context's stream. */
+ * per compute unit pulling (view, tile) items from a counter; 0 launches one workgroup per item.
+ * The window keeps its own stream for graph capture and orders it against the context's stream. */
 fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *cams, const int32_t *tiles,
                              int32_t blocks_per_cu, fgs_window **out);
 fgs_status fgs_window_destroy(fgs_window *w);
 
 /* One mapping iteration over the window, with the semantics of fgs_map_step: every view is
  * binned and ordered, all views' tiles are rendered (Eq. 1) by ONE launch over the (view, tile)
- * items ordered longest list first, the L1 terms of Eq. 15 are taken per view, ONE launch runs
+ * items, the L1 terms of Eq. 15 are taken per view, ONE launch runs
  * every view's backward over the same items, and one pass per gaussian sums the views' gradients
  * through their projections and applies Adam. targets: [host] array of n_views. use_graph != 0 captures
  * the step in a hipGraph on its first call and replays it afterwards (re-captured when a pointer,

@@ -239,8 +239,8 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     ctx->hist_G = G;
     if (nn > ctx->ws_n) {
         // the backward keeps grad2d all-zero between calls (project_bwd clears what it reads)
-        HIP_TRY(ctx, ctx->grad2d.ensure(N * 10 * 4));
-        HIP_TRY(ctx, hipMemset(ctx->grad2d.p, 0, N * 10 * 4));
+        HIP_TRY(ctx, ctx->grad2d.ensure(N * kG2Stride * 4));
+        HIP_TRY(ctx, hipMemset(ctx->grad2d.p, 0, N * kG2Stride * 4));
     }
     ctx->ws_n = nn;
     ctx->ws_cap = cc;
@@ -511,7 +511,7 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     {
         Stage st_(ctx, "raster_bwd");
         launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb,
-                          ddepth, dalpha, dscale, g2, g.n, s);
+                          ddepth, dalpha, dscale, g2, s);
     }
     {
         Stage st_(ctx, "project_bwd");
@@ -1135,7 +1135,7 @@ struct fgs_window {
     std::vector<int64_t> pix_off;  // float offset of view v's 4 planes in img and dl
     std::vector<uint32_t> tile_base;
     uint32_t total_tiles = 0;
-    DBuf img, dl, grad2d, views, cams_dev, qka, qva, qkb, qvb, queue, words, partials;
+    DBuf img, dl, grad2d, views, cams_dev, words, partials;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -1151,8 +1151,9 @@ struct fgs_window {
 
 namespace {
 
-// device words of a window: queue counter, queue length, Adam step (int64), per-view 1/P_v
-constexpr int WW_COUNTER = 0, WW_TOTAL = 1, WW_STEP = 2, WW_DSCALE = 4;
+// device words of a window: item counter of the persistent rasterizer, Adam step (int64, 8-byte
+// aligned), per-view 1/P_v
+constexpr int WW_COUNTER = 0, WW_STEP = 2, WW_DSCALE = 4;
 
 void window_drop_graph(fgs_window *w)
 {
@@ -1200,7 +1201,7 @@ fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_ren
     int64_t capmax = 0;
     for (int v = 0; v < w->nv; ++v) capmax = std::max(capmax, w->cap[v]);
     if ((st = ensure_ws(ctx, std::max<int64_t>(n, w->total_tiles), capmax)) != FGS_OK) return st;
-    const size_t g2 = (size_t)w->nv * 10 * (size_t)(n > 0 ? n : 1) * 4;
+    const size_t g2 = (size_t)w->nv * kG2Stride * (size_t)(n > 0 ? n : 1) * 4;
     HIP_TRY(ctx, hipStreamSynchronize(w->stream));
     HIP_TRY(ctx, w->grad2d.ensure(g2));
     HIP_TRY(ctx, hipMemset(w->grad2d.p, 0, g2));  // the backward keeps it all-zero between steps
@@ -1239,8 +1240,7 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         V.drgb = view_dl(w, v);
         V.ddepth = view_dl(w, v) + 3 * P;
         V.ddepth_scale = w->words.as<float>() + WW_DSCALE + v;
-        V.grad2d = w->grad2d.as<float>() + (size_t)v * 10 * (size_t)n;
-        V.n = n;
+        V.grad2d = w->grad2d.as<float>() + (size_t)v * kG2Stride * (size_t)n;
         V.counts = prof_counts(ctx);
         V.tile_base = w->tile_base[v];
         w->views_host[v] = V;
@@ -1271,13 +1271,10 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
             return st;
     }
     uint32_t *words = w->words.as<uint32_t>();
-    launch_queue_order(w->views.as<ViewK>(), w->nv, w->total_tiles, w->qka.as<uint32_t>(), w->qva.as<uint32_t>(),
-                       w->qkb.as<uint32_t>(), w->qvb.as<uint32_t>(), w->queue.as<uint32_t>(), words + WW_TOTAL,
-                       sort_ws(ctx, w->total_tiles), s);
     {
         Stage st_(ctx, "raster_fwd");
-        launch_raster_queue(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(),
-                            w->total_tiles, words + WW_COUNTER, w->blocks, s);
+        launch_raster_window(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->total_tiles,
+                             words + WW_COUNTER, w->blocks, s);
         if (prof_counts(ctx)) ctx->prof_fwd += w->nv;
     }
     for (int v = 0; v < w->nv; ++v) {
@@ -1290,8 +1287,8 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     }
     {
         Stage st_(ctx, "raster_bwd");
-        launch_raster_queue(false, false, w->views.as<ViewK>(), w->nv, w->queue.as<uint32_t>(), w->total_tiles,
-                            words + WW_COUNTER, w->blocks, s);
+        launch_raster_window(false, false, w->views.as<ViewK>(), w->nv, w->total_tiles, words + WW_COUNTER,
+                             w->blocks, s);
     }
     int64_t *step = (int64_t *)(words + WW_STEP);
     AdamK ak;
@@ -1306,7 +1303,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     {
         Stage st_(ctx, "project_bwd");
         launch_project_bwd_window(to_pk(params), w->cams_dev.as<CamK>(), w->nv, o.lowpass, w->grad2d.as<float>(),
-                                  (int64_t)10 * n, gk, ak, s);
+                                  (int64_t)kG2Stride * n, gk, ak, s);
     }
     launch_step_advance(step, s);
     HIP_TRY(ctx, hipGetLastError());
@@ -1374,11 +1371,6 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
     if (e == hipSuccess) e = w->dl.ensure((size_t)pix * 4 * 4);
     if (e == hipSuccess) e = w->views.ensure(sizeof(ViewK) * n_views);
     if (e == hipSuccess) e = w->cams_dev.ensure(sizeof(CamK) * n_views);
-    if (e == hipSuccess) e = w->qka.ensure((size_t)tb * 4);
-    if (e == hipSuccess) e = w->qva.ensure((size_t)tb * 4);
-    if (e == hipSuccess) e = w->qkb.ensure((size_t)tb * 4);
-    if (e == hipSuccess) e = w->qvb.ensure((size_t)tb * 4);
-    if (e == hipSuccess) e = w->queue.ensure((size_t)tb * 4);
     if (e == hipSuccess) e = w->words.ensure(wbytes);
     if (e == hipSuccess) e = hipMemset(w->words.p, 0, wbytes);
     if (e == hipSuccess) e = w->partials.ensure((size_t)loss_partials_size(pmax) * 4);
@@ -1408,8 +1400,7 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     window_drop_graph(w);
     for (DBuf &b : w->state) b.release();
-    DBuf *bufs[] = {&w->img, &w->dl,  &w->grad2d, &w->views, &w->cams_dev, &w->qka,
-                    &w->qva, &w->qkb, &w->qvb,    &w->queue, &w->words,    &w->partials};
+    DBuf *bufs[] = {&w->img, &w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials};
     for (DBuf *b : bufs) b->release();
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);

@@ -26,6 +26,11 @@ struct RasterK {
     int32_t tile_w, tile_h, tiles_x, tiles_y;
 };
 
+// 2D gradients of one view: one record of kG2Stride floats per gaussian id, terms d/d(mean2 x, y;
+// conic a, b, c; opacity; r, g, b; depth) in slots 0..9, the rest padding (a record is one 64-byte
+// line, so the rasterizer's atomics for one gaussian land in one line).
+constexpr int kG2Stride = 16;
+
 // Gaussian parameter planes (device).
 struct ParamsK {
     int64_t n, stride;
@@ -177,7 +182,6 @@ struct ViewK {
     ImageK img;
     const float *drgb, *ddepth, *dalpha, *ddepth_scale;
     float *grad2d;
-    int64_t n;
     unsigned long long *counts;
     uint32_t tile_base;  // index of this view's first tile in the window's item numbering
 };
@@ -185,17 +189,13 @@ struct ViewK {
 bool tile_supported(int tw, int th);
 bool tile_supported_window(int tw, int th);
 
-// Order the window's items longest tile list first (stable): queue receives item ids.
-void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t *ka, uint32_t *va, uint32_t *kb,
-                        uint32_t *vb, uint32_t *queue, uint32_t *n_dev, const SortWS &ws, hipStream_t s);
-
-// Window rasterizer over items q < total (item ids g = queue[q], or q itself when queue is NULL;
-// item g is tile g - views[v].tile_base of view v). blocks > 0: a persistent grid of that many
-// workgroups pulls items through counter, zeroed first with a kernel so the sequence can be
-// captured in a graph; blocks <= 0: one workgroup per item in queue order. count: the forward
-// adds its work counters to views[v].counts (which must then be non-null).
-void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
-                         uint32_t *counter, int blocks, hipStream_t s);
+// Window rasterizer over the items g < total of all views (item g is tile g - views[v].tile_base
+// of view v, views in order). blocks > 0: a persistent grid of that many workgroups pulls items
+// through counter, zeroed first with a kernel so the sequence can be captured in a graph;
+// blocks <= 0: one workgroup per item. count: the forward adds its work counters to
+// views[v].counts (which must then be non-null).
+void launch_raster_window(bool fwd, bool count, const ViewK *views_dev, int nv, uint32_t total, uint32_t *counter,
+                          int blocks, hipStream_t s);
 
 // counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel
 // stopped, [1] += pairs blended, [2] += list entries staged.
@@ -204,12 +204,12 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        unsigned long long *counts, hipStream_t s);
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
-// to a device float multiplying ddepth (the 1/P_v of the mean depth term). grad2d: 10 planes of n,
-// indexed by gaussian id (the tile lists hold ids).
+// to a device float multiplying ddepth (the 1/P_v of the mean depth term). grad2d: records of
+// kG2Stride floats by gaussian id (the tile lists hold ids).
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha,
-                       const float *ddepth_scale, float *grad2d, int64_t n, hipStream_t s);
+                       const float *ddepth_scale, float *grad2d, hipStream_t s);
 
 // Chain rule from the 2D gradients (10 planes by gaussian id) to the 14 parameter gradients of
 // every gaussian. accumulate: grad += (else grad =, for every gaussian). grad2d is left zeroed.
@@ -226,7 +226,7 @@ struct AdamK {
 };
 
 // Window backward: sums every view's 2D gradients through its projection per gaussian (view v's
-// 10 planes at grad2d + v * view_stride, cleared after use), writes grad when grad.mean is set,
+// records at grad2d + v * view_stride, cleared after use), writes grad when grad.mean is set,
 // and applies Adam when adam.m.mean is set.
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,
                                int64_t view_stride, const GradK &grad, const AdamK &adam, hipStream_t s);

@@ -275,9 +275,32 @@ __device__ inline float *plane(const GradK &g, int row)
          : row < 11 ? g.logit : g.rgb + (row - 11) * S;
 }
 
-// Backward of the projection, one thread per gaussian. grad2d holds 10 planes of length n
-// indexed by gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
-// zeroes the slots it read, so grad2d is all-zero again for the next backward. The 14 parameter
+// The 2D gradient record of gaussian i (slots 0..9 of kG2Stride floats) into g2; returns
+// whether any term is nonzero, and then clears the record (the rasterizer's next backward
+// accumulates into zeros).
+__device__ __forceinline__ bool take_g2(float *__restrict__ rec, double g2[10])
+{
+    const float4 a = reinterpret_cast<const float4 *>(rec)[0], b = reinterpret_cast<const float4 *>(rec)[1];
+    const float2 c = reinterpret_cast<const float2 *>(rec)[4];
+    const float v[10] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y};
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        g2[k] = v[k];
+        any |= v[k] != 0.0f;
+    }
+    if (any) {
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        reinterpret_cast<float4 *>(rec)[0] = z;
+        reinterpret_cast<float4 *>(rec)[1] = z;
+        reinterpret_cast<float2 *>(rec)[4] = make_float2(0.0f, 0.0f);
+    }
+    return any;
+}
+
+// Backward of the projection, one thread per gaussian. grad2d holds one record of kG2Stride
+// floats per gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
+// zeroes the record it read, so grad2d is all-zero again for the next backward. The 14 parameter
 // gradients are added to grad (accumulate) or written to it. Every access is coalesced.
 __global__ void __launch_bounds__(256)
 k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad, int accumulate)
@@ -286,18 +309,11 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     const int64_t n = g.n;
     if (i >= n) return;
     double g2[10];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        g2[k] = grad2d[k * n + i];
-        any |= g2[k] != 0.0;
-    }
+    bool any = take_g2(grad2d + i * kG2Stride, g2);
     double out[14];
 #pragma unroll
     for (int k = 0; k < 14; ++k) out[k] = 0.0;
     if (any) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) grad2d[k * n + i] = 0.0f;
         Proj p;
         project_gaussian(g, i, cam, rk.lowpass, p);
         if (p.valid) chain_rule(p, cam, g2, out);
@@ -311,7 +327,8 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     }
 }
 
-// Window backward: per gaussian, the 2D gradients of every view (view v at grad2d + v*view_stride)
+// Window backward: per gaussian, the 2D gradient records of every view (view v's at grad2d +
+// v * view_stride)
 // go through that view's projection; the sum is the gaussian's gradient, written to grad (if its
 // pointers are set) and applied by Adam (if adam.m is set). Adam's update number is *step + 1,
 // read from device memory so a captured graph can be replayed unchanged.
@@ -326,17 +343,8 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
 #pragma unroll
     for (int k = 0; k < 14; ++k) out[k] = 0.0;
     for (int v = 0; v < nv; ++v) {
-        float *g2p = grad2d + v * view_stride;
         double g2[10];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            g2[k] = g2p[k * n + i];
-            any |= g2[k] != 0.0;
-        }
-        if (!any) continue;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) g2p[k * n + i] = 0.0f;
+        if (!take_g2(grad2d + v * view_stride + i * kG2Stride, g2)) continue;
         const CamK cam = cams[v];
         Proj p;
         project_gaussian(g, i, cam, lowpass, p);

@@ -17,8 +17,8 @@
 // its opacity gradient only through one running sum per pixel, S = sum over later pairs of
 // w_j (dL/dC . c_j + dL/dD d_j) plus the background's and the opacity output's share. Each pair
 // yields 10 gradient terms; they are summed over the wave by a transposed butterfly, over the
-// workgroup's waves with LDS float atomics, and reach HBM as one FP32 atomic per (tile, gaussian,
-// term).
+// workgroup's waves with LDS float atomics, and reach HBM as FP32 atomics into the gaussian's
+// 64-byte gradient record, one wave instruction covering four (tile, gaussian) entries.
 //
 // The forward and the backward evaluate the cutoff decisions with the same inline functions in
 // this translation unit, compiled without floating-point contraction, so both take identical
@@ -305,6 +305,46 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     V.tfinal[p] = T;
 }
 
+// Backward of one (pixel, entry) pair, walking the list from the back: decides whether the
+// forward blended it (before the pixel's last blended position, inside the cutoff, above
+// alpha_min), recovers T_i from T_{i+1}, writes the pair's 10 gradient terms (exact zeros when
+// not taken) and advances the pixel's T and S. Returns whether the pair was taken.
+__device__ __forceinline__ bool bwd_pair(const float4 &a4, const float4 &b4, const float4 &c4, bool before_last,
+                                         float px, float py, float qcut, const RasterK &rk, float gC0, float gC1,
+                                         float gC2, float gD, float &T, float &S, float g[10])
+{
+    const PairEval e = eval_pair(a4, b4, px, py);
+    const float ar = b4.y * e.G;
+    const float alpha = fminf(rk.alpha_max, ar);
+    const bool take = before_last && !(e.q < qcut) && !(alpha < rk.alpha_min);
+    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
+    const float Ti = T * inv;
+    const float w = take ? alpha * Ti : 0.0f;
+    // dL/dalpha_i = T_i X_i - S / (1 - alpha_i), X_i = dL/dC . c_i + dL/dD d_i
+    const float X = __builtin_fmaf(gC0, c4.x, __builtin_fmaf(gC1, c4.y, __builtin_fmaf(gC2, c4.z, gD * b4.z)));
+    const float dal = __builtin_fmaf(-S, inv, Ti * X);
+    // a clamped alpha (o G > alpha_max) passes nothing to opacity, mean or conic
+    const float dalg = take && !(ar > rk.alpha_max) ? dal : 0.0f;
+    S = __builtin_fmaf(w, X, S);
+    T = take ? Ti : T;
+    g[6] = gC0 * w;
+    g[7] = gC1 * w;
+    g[8] = gC2 * w;
+    g[9] = gD * w;
+    g[5] = dalg * e.G;  // d alpha / d opacity = G
+    // dL/dQ = -alpha dL/dalpha / 2; the mean gradient is -2 dL/dQ (a dx + b dy, b dx + c dy)
+    // = dL/dQ (-2/s) (s a dx + s b dy, ...), from the scaled products of the forward form
+    const float dQ = -0.5f * (alpha * dalg);
+    const float km = kMeanGradScale * dQ;
+    g[0] = km * __builtin_fmaf(a4.w, e.dy, e.Adx);
+    g[1] = km * (e.Bdx + e.Cdy);
+    const float dQdx = dQ * e.dx;
+    g[2] = dQdx * e.dx;
+    g[3] = 2.0f * (dQdx * e.dy);
+    g[4] = (dQ * e.dy) * e.dy;
+    return take;
+}
+
 // Backward of one tile of one view (NT threads, one pixel each).
 template <int NT>
 __device__ void tile_bwd(const ViewK &V, int tile)
@@ -315,16 +355,17 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const Rec *__restrict__ rec = V.rec;
     const uint32_t *__restrict__ vals = V.vals;
     float *__restrict__ grad2d = V.grad2d;
-    const int64_t n = V.n;
     const int TW = rk.tile_w, TH = rk.tile_h;
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint32_t sid[NT];
-    __shared__ float sacc[10][NT + 1];  // padded: the ten terms of one entry fall in different banks
+    __shared__ float sacc[NT][10];  // per staged entry: the ten terms summed over the workgroup
     __shared__ uint32_t smax;
     __shared__ uint8_t smask[NT];
     __shared__ uint16_t slist[NW][NT];
     const int tid = threadIdx.x;
     const int lane = __lane_id();
+    const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
+    const bool red_lane = lane < 16 && term >= 0;
     const int wid = tid / kWave;
     const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
     const int x0 = tx * TW, y0 = ty * TH;
@@ -357,7 +398,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
 
     if (tid == 0) smax = 0;
 #pragma unroll
-    for (int c = 0; c < 10; ++c) sacc[c][tid] = 0.0f;
+    for (int c = 0; c < 10; ++c) sacc[tid][c] = 0.0f;
     __syncthreads();
     if (L) atomicMax(&smax, L);
     __syncthreads();
@@ -383,68 +424,43 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
         const uint32_t base = bstart - range.x;
         // Branch-free per pair, like the forward: the decisions select what is kept, and a lane
-        // that does not take the pair contributes exact zeros.
-        for (int i = len - 1; i >= 0; --i) {
-            const int k = slist[wid][i];
-            const float4 a4 = sa[k], b4 = sb[k], c4 = sc[k];
-            const PairEval e = eval_pair(a4, b4, px, py);
-            const float ar = b4.y * e.G;
-            const float alpha = fminf(rk.alpha_max, ar);
-            // blended in the forward: before the pixel's last blended position, inside the
-            // cutoff and above alpha_min
-            const bool take = base + k < L && !(e.q < qcut) && !(alpha < rk.alpha_min);
-            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
-            const float Ti = T * inv;
-            const float w = take ? alpha * Ti : 0.0f;
-            // dL/dalpha_i = T_i X_i - S / (1 - alpha_i), X_i = dL/dC . c_i + dL/dD d_i
-            const float X = __builtin_fmaf(gC0, c4.x, __builtin_fmaf(gC1, c4.y, __builtin_fmaf(gC2, c4.z, gD * b4.z)));
-            const float dal = __builtin_fmaf(-S, inv, Ti * X);
-            // a clamped alpha (o G > alpha_max) passes nothing to opacity, mean or conic
-            const float dalg = take && !(ar > rk.alpha_max) ? dal : 0.0f;
-            S = __builtin_fmaf(w, X, S);
-            T = take ? Ti : T;
-            float g[10];
-            g[6] = gC0 * w;
-            g[7] = gC1 * w;
-            g[8] = gC2 * w;
-            g[9] = gD * w;
-            g[5] = dalg * e.G;  // d alpha / d opacity = G
-            // dL/dQ = -alpha dL/dalpha / 2; the mean gradient is -2 dL/dQ (a dx + b dy, b dx + c dy)
-            // = dL/dQ (-2/s) (s a dx + s b dy, ...), from the scaled products of the forward form
-            const float dQ = -0.5f * (alpha * dalg);
-            const float km = kMeanGradScale * dQ;
-            g[0] = km * __builtin_fmaf(a4.w, e.dy, e.Adx);
-            g[1] = km * (e.Bdx + e.Cdy);
-            const float dQdx = dQ * e.dx;
-            g[2] = dQdx * e.dx;
-            g[3] = 2.0f * (dQdx * e.dy);
-            g[4] = (dQ * e.dy) * e.dy;
-            const uint64_t any = __ballot(take);
-            if (any) {
-                if ((any & (any - 1)) == 0) {
-                    // a single contributing lane: no reduction needed
-                    if (take) {
-#pragma unroll
-                        for (int c = 0; c < 10; ++c) atomicAdd(&sacc[c][k], g[c]);
-                    }
-                } else {
-                    // transposed reduction: lane j of the first row ends with the wave sum of term
-                    // reduce_term(j); one LDS atomic instruction adds all ten terms
-                    const float t = reduce10(g, lane);
-                    const int term = reduce_term(lane);
-                    if (lane < 16 && term >= 0) atomicAdd(&sacc[term][k], t);
+        // that does not take the pair contributes exact zeros. Two entries per iteration: their
+        // evaluations and wave reductions are independent, only T and S pass from one to the next.
+        int i = len - 1;
+        for (; i >= 1; i -= 2) {
+            const int k0 = slist[wid][i], k1 = slist[wid][i - 1];
+            float g0[10], g1[10];
+            const bool take0 = bwd_pair(sa[k0], sb[k0], sc[k0], base + k0 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g0);
+            const bool take1 = bwd_pair(sa[k1], sb[k1], sc[k1], base + k1 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g1);
+            const uint64_t any0 = __ballot(take0), any1 = __ballot(take1);
+            if (any0 | any1) {
+                const float t0 = reduce10(g0, lane), t1 = reduce10(g1, lane);
+                if (red_lane) {
+                    if (any0) atomicAdd(&sacc[k0][term], t0);
+                    if (any1) atomicAdd(&sacc[k1][term], t1);
                 }
             }
         }
+        if (i == 0) {
+            const int k0 = slist[wid][0];
+            float g0[10];
+            const bool take0 = bwd_pair(sa[k0], sb[k0], sc[k0], base + k0 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g0);
+            if (__ballot(take0)) {
+                const float t0 = reduce10(g0, lane);
+                if (red_lane) atomicAdd(&sacc[k0][term], t0);
+            }
+        }
         __syncthreads();
-        if (tid < cnt) {
-            const uint32_t id = sid[tid];
-#pragma unroll
-            for (int c = 0; c < 10; ++c) {
-                const float v = sacc[c][tid];
+        // Each gaussian's ten terms form one 64-byte record of grad2d: 16 lanes per entry, lane c
+        // (< 10) adds term c, so one wave instruction updates the records of four gaussians, one
+        // cache line each.
+        for (int e = tid >> 4; e < cnt; e += NT >> 4) {
+            const int c = tid & 15;
+            if (c < 10) {
+                const float v = sacc[e][c];
                 if (v != 0.0f) {
-                    unsafeAtomicAdd(&grad2d[c * n + id], v);
-                    sacc[c][tid] = 0.0f;
+                    unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + c], v);
+                    sacc[e][c] = 0.0f;
                 }
             }
         }
@@ -465,38 +481,34 @@ __device__ inline int view_of(const ViewK *views, int nv, uint32_t g)
     return v;
 }
 
-// Persistent rasterizer over a window of views: workgroups pull (view, tile) items from a queue
-// through an atomic counter until it runs past the last item. 256 threads per workgroup; each
-// view's tile has 256 pixels in its own shape (16x16, 32x8 or 8x32).
+// Persistent rasterizer over a window of views: workgroups pull (view, tile) items through an
+// atomic counter until it runs past the last item. 256 threads per workgroup; each view's tile
+// has 256 pixels in its own shape (16x16, 32x8 or 8x32). The item's view descriptor is copied
+// out of device memory once, so the tile code reads it from registers.
 template <bool FWD, bool COUNT>
 __global__ void __launch_bounds__(256)
-k_raster_queue(const ViewK *__restrict__ views, int nv, const uint32_t *__restrict__ queue, uint32_t total,
-               uint32_t *__restrict__ counter)
+k_raster_queue(const ViewK *__restrict__ views, int nv, uint32_t total, uint32_t *__restrict__ counter)
 {
     __shared__ uint32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t q = s_item;
+        const uint32_t g = s_item;
         __syncthreads();
-        if (q >= total) break;
-        const uint32_t g = queue ? queue[q] : q;
-        const int v = view_of(views, nv, g);
-        const ViewK &V = views[v];
+        if (g >= total) break;
+        const ViewK V = views[view_of(views, nv, g)];
         if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
         else tile_bwd<256>(V, (int)(g - V.tile_base));
     }
 }
 
-// The same items with one workgroup each (grid = total): the hardware dispatches workgroups in
-// index order, so the queue's order (longest list first) is kept without a counter.
+// The same items with one workgroup each (grid = total).
 template <bool FWD, bool COUNT>
 __global__ void __launch_bounds__(256)
-k_raster_items(const ViewK *__restrict__ views, int nv, const uint32_t *__restrict__ queue)
+k_raster_items(const ViewK *__restrict__ views, int nv)
 {
-    const uint32_t g = queue ? queue[blockIdx.x] : blockIdx.x;
-    const int v = view_of(views, nv, g);
-    const ViewK &V = views[v];
+    const uint32_t g = blockIdx.x;
+    const ViewK V = views[view_of(views, nv, g)];
     if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
     else tile_bwd<256>(V, (int)(g - V.tile_base));
 }
@@ -562,7 +574,7 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha, const float *ddepth_scale,
-                       float *grad2d, int64_t n, hipStream_t s)
+                       float *grad2d, hipStream_t s)
 {
     ViewK V = view_of_args(rk, W, H, rec, vals);
     V.ranges = ranges;
@@ -573,28 +585,28 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
     V.dalpha = dalpha;
     V.ddepth_scale = ddepth_scale;
     V.grad2d = grad2d;
-    V.n = n;
     launch_bwd_view(V, s);
 }
 
-void launch_raster_queue(bool fwd, bool count, const ViewK *views_dev, int nv, const uint32_t *queue, uint32_t total,
-                         uint32_t *counter, int blocks, hipStream_t s)
+void launch_raster_window(bool fwd, bool count, const ViewK *views_dev, int nv, uint32_t total, uint32_t *counter,
+                          int blocks, hipStream_t s)
 {
     if (total == 0) return;
     if (blocks <= 0) {
         const dim3 grid(total);
-        if (fwd && count) hipLaunchKernelGGL((k_raster_items<true, true>), grid, dim3(256), 0, s, views_dev, nv, queue);
-        else if (fwd) hipLaunchKernelGGL((k_raster_items<true, false>), grid, dim3(256), 0, s, views_dev, nv, queue);
-        else hipLaunchKernelGGL((k_raster_items<false, false>), grid, dim3(256), 0, s, views_dev, nv, queue);
+        if (fwd && count) hipLaunchKernelGGL((k_raster_items<true, true>), grid, dim3(256), 0, s, views_dev, nv);
+        else if (fwd) hipLaunchKernelGGL((k_raster_items<true, false>), grid, dim3(256), 0, s, views_dev, nv);
+        else hipLaunchKernelGGL((k_raster_items<false, false>), grid, dim3(256), 0, s, views_dev, nv);
         return;
     }
     launch_zero_u32(counter, 1, s);
+    const dim3 grid(blocks);
     if (fwd && count)
-        hipLaunchKernelGGL((k_raster_queue<true, true>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+        hipLaunchKernelGGL((k_raster_queue<true, true>), grid, dim3(256), 0, s, views_dev, nv, total, counter);
     else if (fwd)
-        hipLaunchKernelGGL((k_raster_queue<true, false>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+        hipLaunchKernelGGL((k_raster_queue<true, false>), grid, dim3(256), 0, s, views_dev, nv, total, counter);
     else
-        hipLaunchKernelGGL((k_raster_queue<false, false>), dim3(blocks), dim3(256), 0, s, views_dev, nv, queue, total, counter);
+        hipLaunchKernelGGL((k_raster_queue<false, false>), grid, dim3(256), 0, s, views_dev, nv, total, counter);
 }
 
 }  // namespace fgs

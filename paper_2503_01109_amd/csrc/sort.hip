@@ -542,23 +542,6 @@ k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, 
     ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t), lower_bound_u32(keys, K, (uint32_t)t + 1));
 }
 
-// Queue keys of a window: item g (tile g - tile_base of its view) gets the key 2^24 - 1 - (its list
-// length, clamped), so a stable ascending sort puts the longest lists first; *n_out = total.
-__global__ void __launch_bounds__(kSortThreads)
-k_queue_keys(const ViewK *__restrict__ views, int nv, uint32_t total, uint32_t *__restrict__ keys,
-             uint32_t *__restrict__ vals, uint32_t *__restrict__ n_out)
-{
-    const uint32_t g = blockIdx.x * kSortThreads + threadIdx.x;
-    if (g == 0) *n_out = total;
-    if (g >= total) return;
-    int v = 0;
-    while (v + 1 < nv && views[v + 1].tile_base <= g) ++v;
-    const uint2 r = views[v].ranges[g - views[v].tile_base];
-    const uint32_t len = min(r.y - r.x, 0xFFFFFFu);
-    keys[g] = 0xFFFFFFu - len;
-    vals[g] = g;
-}
-
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -566,14 +549,6 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n)
 }
 
 }  // namespace
-
-void launch_queue_order(const ViewK *views_dev, int nv, uint32_t total, uint32_t *ka, uint32_t *va, uint32_t *kb,
-                        uint32_t *vb, uint32_t *queue, uint32_t *n_dev, const SortWS &ws, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_queue_keys, dim3((total + kSortThreads - 1) / kSortThreads), dim3(kSortThreads), 0, s, views_dev,
-                       nv, total, ka, va, n_dev);
-    launch_radix_sort(ka, va, kb, vb, queue, n_dev, total, 24, ws, s);
-}
 
 int sort_blocks(int64_t cap, int per_block)
 {
