@@ -27,9 +27,30 @@ namespace {
 
 thread_local std::string g_thread_error;
 
+// Device buffer owned by its holder (freed on destruction; movable, not copyable).
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
     hipError_t ensure(size_t want)
     {
         if (want <= bytes && p) return hipSuccess;
@@ -63,7 +84,7 @@ struct fgs_ctx {
     std::string err;
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
-    DBuf rect_sorted, start_rank;
+    DBuf rect_sorted, start_rank, kpart;
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
     DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words;
     int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
@@ -228,6 +249,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->idB.ensure(N * 4));
     HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks(nn) + 2) * 4));
     HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
+    HIP_TRY(ctx, ctx->kpart.ensure((size_t)project_blocks(nn) * 2 * 4));
     HIP_TRY(ctx, ctx->rect_sorted.ensure(N * sizeof(uint2)));
     HIP_TRY(ctx, ctx->start_rank.ensure((size_t)emit_chunks((int64_t)C) * 4));
     HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
@@ -444,7 +466,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     {
         Stage st_(ctx, "project");
         launch_project(pk, ck, rk, sp.rec, ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
-                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, kSuperShift, ktotal, s);
+                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, kSuperShift, ctx->kpart.as<uint32_t>(), s);
     }
     {
         Stage st_(ctx, "depth_sort");
@@ -455,7 +477,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
         // one pair per covered super-tile, in depth order
         Stage st_(ctx, "bin");
         launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx),
-                           ktotal, s);
+                           ctx->kpart.as<uint32_t>(), project_blocks(g.n), ktotal, s);
     }
     if (K_check) {
         fgs_status st2 = read_words(ctx);

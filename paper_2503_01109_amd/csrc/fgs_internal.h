@@ -100,11 +100,13 @@ void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 
 // Projects every gaussian into rec (by id: the forward state's records); writes n to *n_out (the
 // element count of the depth sort). count[i] receives the number of tiles (shift 0) or
-// super-tiles (tile rectangle >> shift) covered, rect[i] the tile rectangle, and *ktotal the
-// number of (tile, gaussian) pairs.
+// super-tiles (tile rectangle >> shift) covered, rect[i] the tile rectangle; kpart (2 words per
+// workgroup, project_blocks(n) workgroups) the workgroups' (tile, gaussian) pair and visible
+// gaussian counts, summed by launch_scan_counts.
+int64_t project_blocks(int64_t n);
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
-                    uint32_t *ktotal, hipStream_t s);
+                    uint32_t *kpart, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
@@ -114,11 +116,12 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             hipStream_t s);
 
 // Exclusive scan of count[ids[r]] over depth ranks r, by blocks: blocksums (scan_blocks(n) + 1
-// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs;
-// status[ST_PAIRS] receives *ktotal.
+// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs.
+// The projection's per-workgroup counts kpart are summed into *ktotal and status[ST_PAIRS]
+// ((tile, gaussian) pairs) and status[ST_VISIBLE].
 int64_t scan_blocks(int64_t n);
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, const uint32_t *ktotal, hipStream_t s);
+                        uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s);
 
 // Emit one (key, gaussian id) pair per covered tile in depth order; with shift > 0 the keys are
 // super-tiles (tile rectangle >> shift, keys_x super-tiles per row). offsets is scratch of n + 1

@@ -117,24 +117,31 @@ __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict
                                 int shift, int64_t i);
 
 // Projects every gaussian (one thread each): record, tile rectangle, count of covered tiles or
-// super-tiles, depth key; *ktotal (zero on entry) receives the number of (tile, gaussian) pairs.
+// super-tiles, depth key; kpart[2 b], kpart[2 b + 1] receive block b's number of (tile, gaussian)
+// pairs and of gaussians that cover a tile (summed by the scan, so nothing needs zeroing first).
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ ktotal)
+          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart)
 {
-    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t wsum[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n_out = (uint32_t)g.n;
-    uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian, summed into *ktotal
+    uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian
     if (i < g.n) tiles = project_one(g, cam, rk, rec, rect, count, dkey, ids, shift, i);
-    for (int o = 32; o > 0; o >>= 1) tiles += __shfl_xor(tiles, o);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = tiles;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (t) atomicAdd(ktotal, t);
+    uint32_t vis = tiles != 0u;
+    for (int o = 32; o > 0; o >>= 1) {
+        tiles += __shfl_xor(tiles, o);
+        vis += __shfl_xor(vis, o);
     }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[0][threadIdx.x >> 6] = tiles;
+        wsum[1][threadIdx.x >> 6] = vis;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        kpart[2 * blockIdx.x + threadIdx.x] =
+            wsum[threadIdx.x][0] + wsum[threadIdx.x][1] + wsum[threadIdx.x][2] + wsum[threadIdx.x][3];
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
@@ -374,14 +381,14 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
 
 }  // namespace
 
+int64_t project_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 1; }
+
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
-                    uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *ktotal,
+                    uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *kpart,
                     hipStream_t s)
 {
-    const int64_t blocks = g.n > 0 ? (g.n + 255) / 256 : 1;
-    launch_zero_u32(ktotal, 1, s);
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, rec, rect, count,
-                       dkey, ids, n_out, shift, ktotal);
+    hipLaunchKernelGGL(k_project, dim3((unsigned)project_blocks(g.n)), dim3(256), 0, s, g, cam, rk, rec, rect, count,
+                       dkey, ids, n_out, shift, kpart);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,

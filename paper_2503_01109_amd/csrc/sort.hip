@@ -164,9 +164,11 @@ k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ co
 }
 
 // Single block: exclusive scan of the block sums in place; the total number of pairs goes to
-// blocksums[nb] and to the status words.
+// blocksums[nb] and to the status words. Also sums the projection's per-block counts (kpart,
+// npb blocks) into *ktotal, status[ST_PAIRS] (tile pairs) and status[ST_VISIBLE].
 __global__ void __launch_bounds__(kSortThreads)
-k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status, const uint32_t *__restrict__ ktotal)
+k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart,
+           int npb, uint32_t *__restrict__ ktotal)
 {
     __shared__ uint32_t w[8];
     uint32_t carry = 0;
@@ -178,10 +180,19 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
         if (j < nb) blocksums[j] = carry + ex;
         carry += tot;
     }
+    uint32_t pairs = 0, vis = 0;
+    for (int j = threadIdx.x; j < npb; j += kSortThreads) {
+        pairs += kpart[2 * j];
+        vis += kpart[2 * j + 1];
+    }
+    uint32_t tp, tv;
+    block_excl_scan(pairs, w, &tp);
+    block_excl_scan(vis, w, &tv);
     if (threadIdx.x == 0) {
         blocksums[nb] = carry;
-        status[ST_PAIRS] = *ktotal;
-        status[ST_VISIBLE] = 0;
+        *ktotal = tp;
+        status[ST_PAIRS] = tp;
+        status[ST_VISIBLE] = tv;
     }
 }
 
@@ -509,18 +520,6 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     }
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-k_visible(const uint32_t *__restrict__ count, int64_t n, uint32_t *__restrict__ status)
-{
-    __shared__ uint32_t w[8];
-    uint32_t s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortThreads)
-        s += count[i] != 0;
-    uint32_t tot;
-    block_excl_scan(s, w, &tot);
-    if (threadIdx.x == 0 && tot) atomicAdd(&status[ST_VISIBLE], tot);
-}
-
 __device__ inline uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v)
 {
     uint32_t lo = 0, hi = n;
@@ -603,13 +602,13 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
 
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, const uint32_t *ktotal, hipStream_t s)
+                        uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s)
 {
     const int nb = (int)scan_blocks(n);
     if (nb > 0)
         hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, ktotal);
-    hipLaunchKernelGGL(k_visible, dim3(grid_for(n, 4096, 256)), dim3(kSortThreads), 0, s, count, n, status);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, kpart, (int)proj_blocks,
+                       ktotal);
 }
 
 int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 1; }

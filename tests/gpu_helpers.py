@@ -27,8 +27,9 @@ def assert_close_rel(gpu, ref, tol, mask=None, what="", floor=1e-3):
     |gpu - ref| <= tol * |ref| wherever |ref| >= floor * max|ref|. mask selects compared elements.
 
     Rendered planes use floor = 1e-3. Gradients are sums over many pixels with cancelling signs;
-    their FP32 absolute error floor is a few 1e-7 of max|ref| (measured), so they use floor = 1e-2,
-    where that floor is at most a tenth of the 1e-4 bar."""
+    their FP32 absolute error floor is a few 1e-7 of max|ref| on the small scenes (measured), so
+    they use floor = 1e-2, where that floor is at most a tenth of the 1e-4 bar; the full-size
+    sampled test measures up to 1.2e-6 and uses 2e-2."""
     g = np.asarray(gpu, np.float64)
     r = np.asarray(ref, np.float64)
     if mask is not None:

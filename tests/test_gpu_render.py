@@ -15,6 +15,11 @@ from gpu_helpers import assert_close_rel, dev, host, need_gpu
 pytestmark = pytest.mark.gpu
 
 FWD_TOL, GRAD_TOL, GRAD_FLOOR = 1e-5, 1e-4, 1e-2
+# At 300k gaussians with random-sign upstream gradients at 4,000 sampled pixels, a gaussian's
+# gradient is a sum of terms of both signs accumulated in an order the FP32 atomics choose; the
+# measured absolute error reaches 1.2e-6 of the row's largest entry, so elements are held to the
+# 1e-4 relative bar from 2e-2 of that entry up (the per-tensor bound still covers all of them).
+GRAD_FLOOR_FULL = 2e-2
 
 
 @pytest.fixture(scope="module")
@@ -94,7 +99,8 @@ def test_full_size_workload_sampled(fgs, ctx):
     """The 300k-gaussian 1200x680 workload (20% of the gaussians in 8 blobs), 16x16 tiles as the
     benchmark runs it: the forward planes at 4,000 sampled pixels against the oracle rendering those
     pixels one by one, and all 14 parameter gradients of an upstream gradient that is non-zero at
-    the sampled pixels only, against the oracle's backward over the same pixels."""
+    the sampled pixels only, against the oracle's backward over the same pixels (elementwise from
+    GRAD_FLOOR_FULL of each tensor's largest entry up)."""
     cam = synth.camera_replica()
     p = synth.scene_replica(0)
     n = p.shape[1]
@@ -129,7 +135,7 @@ def test_full_size_workload_sampled(fgs, ctx):
     assert np.count_nonzero(gref[10]) > 1000  # the sample reaches many gaussians
     for name, rows in (("mean", slice(0, 3)), ("log_scale", slice(3, 6)), ("quat", slice(6, 10)),
                        ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
-        assert_close_rel(gg[rows], gref[rows], GRAD_TOL, None, f"d{name}", floor=GRAD_FLOOR)
+        assert_close_rel(gg[rows], gref[rows], GRAD_TOL, None, f"d{name}", floor=GRAD_FLOOR_FULL)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (8, 8)])
