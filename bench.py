@@ -33,8 +33,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "14dc3a186ca4353e7e15539edf5a9cf75e0b1f2dff02f1c52fed8ebc5994f6f4",
-                     "tile": "16x16", "fetch_bytes": 44622611, "write_bytes": 82438331},
+    "k_raster_bwd": {"source_sha256": "fbb174c512b2a4644e881d153db7ced57816b9a4207d71ab9783a41d2a852d9f",
+                     "tile": "16x16", "fetch_bytes": 46997496, "write_bytes": 16498761},
 }
 
 
@@ -49,6 +49,11 @@ def measured_traffic(kernel: str, tile: str):
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
     return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def progress(msg: str):
+    """One progress line on stderr (stdout carries only the JSON result)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -204,7 +209,7 @@ def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
     plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on n_test held-out frames."""
     from paper_2503_01109_amd import prior
     r = prior.run_experiment(F, ctx, range(1000, 1000 + n_train), range(5000, 5000 + n_test), iters=200,
-                             tiles_per_scene=100, train_steps=2000)
+                             tiles_per_scene=100, train_steps=2000, log=progress)
     s = r["summary"]
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
@@ -248,6 +253,7 @@ def main():
         F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
     ctx.check()
     torch.cuda.synchronize()
+    progress(f"warm-up done; timing {args.steps} steps")
 
     # timed region: HIP events around the two rasterizer kernels only (level 1; the kernels run as
     # unprofiled), so the timing of the dominant kernel is live without breaking up the rest of
@@ -315,10 +321,13 @@ def main():
     if not args.no_extras:
         # the extra measurements report their own failure in the line instead of losing it
         def extra(fn, *a):
+            t0 = time.perf_counter()
             try:
-                return fn(*a)
+                r = fn(*a)
             except Exception as e:  # noqa: BLE001 - any failure is reported, not hidden
-                return {"error": f"{type(e).__name__}: {e}"[:600]}
+                r = {"error": f"{type(e).__name__}: {e}"[:600]}
+            progress(f"{fn.__name__} done in {time.perf_counter() - t0:.1f} s")
+            return r
         line["window"] = extra(window_extra, F, ctx)
         line["seeding"] = extra(seeding_extra, F, ctx)
         pr = extra(prior_extra, F, ctx, args.prior_train_scenes, args.prior_test_scenes)
@@ -329,6 +338,7 @@ def main():
                                          "held_out_scenes": pr["scenes"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

@@ -197,18 +197,24 @@ def best_plain_opacity(F, ctx, scenes, iters: int, choices=(0.1, 0.5, 0.9)):
 
 
 def run_experiment(F, ctx, train_scenes, test_scenes, iters: int = 200, tiles_per_scene: int = 100,
-                   train_steps: int = 2000, lr: float = 1e-3, margin_db: float = 0.1, opacity=None) -> dict:
+                   train_steps: int = 2000, lr: float = 1e-3, margin_db: float = 0.1, opacity=None,
+                   log=None) -> dict:
     """Build the training set from the plain method's converged maps, train the prior on the GPU,
-    and compare time and iterations to the plain method's final PSNR on held-out scenes."""
+    and compare time and iterations to the plain method's final PSNR on held-out scenes. log
+    (optional) receives one progress line per phase."""
     import time
+    log = log or (lambda msg: None)
     t0 = time.perf_counter()
     if opacity is None:
         opacity = best_plain_opacity(F, ctx, list(train_scenes)[:5], iters)
+        log(f"plain opacity {opacity} chosen")
     base = F.SeedOpts(opacity_logit=logit(opacity))
     X, Y = build_dataset(F, ctx, train_scenes, iters, tiles_per_scene, base)
     t_data = time.perf_counter() - t0
+    log(f"training set of {X.shape[0]} tiles built in {t_data:.1f} s")
     w, losses = train(F, ctx, X, Y, train_steps, lr)
     t_train = time.perf_counter() - t0 - t_data
+    log(f"prior trained in {t_train:.1f} s")
     rows = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=base)
     both = [r for r in rows if r["plain_iters"] is not None and r["prior_iters"] is not None]
     summary = dict(
