@@ -518,10 +518,12 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     return FGS_OK;
 }
 
+// Enqueue the backward of one view: grad_out (nullable) = grad_in (nullable) + this view's
+// gradient; adam (nullable) applies that sum to g.
 fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                             int tw, int th, const void *state, const StateLayout &L, const float *drgb,
-                            const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians &grad,
-                            bool accumulate)
+                            const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians *grad_in,
+                            const fgs_gaussians *grad_out, const AdamK *adam)
 {
     fgs_status st = ensure_ws(ctx, g.n, 0);
     if (st != FGS_OK) return st;
@@ -537,7 +539,10 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     }
     {
         Stage st_(ctx, "project_bwd");
-        launch_project_bwd(to_pk(g), ck, rk, g2, to_gk(grad), accumulate, s);
+        const GradK none{g.n, g.n, nullptr, nullptr, nullptr, nullptr, nullptr};
+        AdamK no_adam{};
+        launch_project_bwd(to_pk(g), ck, rk, g2, grad_in ? to_gk(*grad_in) : none, grad_out ? to_gk(*grad_out) : none,
+                           adam ? *adam : no_adam, s);
     }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -806,8 +811,8 @@ fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state of %lld bytes does not match n and the image size", w,
                     (long long)state_bytes);
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
-    return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, *grad,
-                            true);
+    return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, grad, grad,
+                            nullptr);
 }
 
 fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth, const fgs_target *target,
@@ -978,12 +983,29 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
                            dl + 3 * P, dscale, ctx->ms_partials.as<float>(), loss_dev ? loss_dev + v : nullptr,
                            psnr_dev ? psnr_dev + v : nullptr, s);
         }
+        // views before the last sum their gradients into grad; the last one adds its own and
+        // applies Adam in the same kernel (writing the sum only when the caller asked for it)
+        const bool last = v == n_views - 1;
+        AdamK ak{};
+        if (last) {
+            ak.m = to_gk(opt->m);
+            ak.v = to_gk(opt->v);
+            ak.step = nullptr;
+            for (int k = 0; k < 5; ++k) ak.lr[k] = opt->lr[k];
+            ak.beta1 = opt->beta1;
+            ak.beta2 = opt->beta2;
+            ak.eps = opt->eps;
+            const double t = (double)(opt->step + 1);
+            ak.bc1 = (float)(1.0 - pow((double)opt->beta1, t));
+            ak.bc2 = (float)(1.0 - pow((double)opt->beta2, t));
+        }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
-                                   grad, v > 0)) != FGS_OK)
+                                   v > 0 ? &grad : nullptr, !last || grad_out ? &grad : nullptr,
+                                   last ? &ak : nullptr)) != FGS_OK)
             return st;
     }
     ctx->ms_n = n;
-    enqueue_adam(ctx, *params, grad, opt);
+    opt->step += 1;
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
@@ -1313,7 +1335,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                              w->blocks, s);
     }
     int64_t *step = (int64_t *)(words + WW_STEP);
-    AdamK ak;
+    AdamK ak{};
     ak.m = to_gk(opt.m);
     ak.v = to_gk(opt.v);
     ak.step = step;

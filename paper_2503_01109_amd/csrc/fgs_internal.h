@@ -214,19 +214,25 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        const float *drgb, const float *ddepth, const float *dalpha,
                        const float *ddepth_scale, float *grad2d, hipStream_t s);
 
-// Chain rule from the 2D gradients (10 planes by gaussian id) to the 14 parameter gradients of
-// every gaussian. accumulate: grad += (else grad =, for every gaussian). grad2d is left zeroed.
-void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,
-                        bool accumulate, hipStream_t s);
-
-// Adam hyper-parameters for the fused window update; step points to the device count of updates
-// already applied (the kernel applies update *step + 1 and does not change it).
+// Adam hyper-parameters of an update fused into a projection backward. step (nullable) points
+// to the device count of updates already applied (the kernel applies update *step + 1 and does
+// not change it, so a captured graph can be replayed); without it, bc1 and bc2 are the bias
+// corrections of this update.
 struct AdamK {
     GradK m, v;
     const int64_t *step;
     float lr[5];
     float beta1, beta2, eps;
+    float bc1, bc2;
 };
+
+// Chain rule from the 2D gradient records (by gaussian id) to the 14 parameter gradients of every
+// gaussian: grad_out (nullable) = grad_in (nullable: an earlier views' sum) + this view's, and
+// Adam (when adam.m.mean is set) applies that sum. grad2d is left zeroed. grad_in may equal
+// grad_out (accumulation in place).
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad_in,
+                        const GradK &grad_out, const AdamK &adam, hipStream_t s);
+
 
 // Window backward: sums every view's 2D gradients through its projection per gaussian (view v's
 // records at grad2d + v * view_stride, cleared after use), writes grad when grad.mean is set,

@@ -305,12 +305,36 @@ __device__ __forceinline__ bool take_g2(float *__restrict__ rec, double g2[10])
     return any;
 }
 
+// Adam on the 14 parameters of gaussian i with gradient gi: update number *adam.step + 1 (device
+// counter) when adam.step is set, else bias corrections adam.bc1, adam.bc2.
+__device__ inline void adam_update(const AdamK &adam, const ParamsK &g, int64_t i, const float gi[14])
+{
+    float bc1 = adam.bc1, bc2 = adam.bc2;
+    if (adam.step) {
+        const double t = (double)(*adam.step + 1);
+        bc1 = (float)(1.0 - pow((double)adam.beta1, t));
+        bc2 = (float)(1.0 - pow((double)adam.beta2, t));
+    }
+    GradK P{g.n, g.stride, (float *)g.mean, (float *)g.log_scale, (float *)g.quat, (float *)g.logit, (float *)g.rgb};
+#pragma unroll
+    for (int k = 0; k < 14; ++k) {
+        const int group = k < 3 ? 0 : k < 6 ? 1 : k < 10 ? 2 : k < 11 ? 3 : 4;
+        float *mm = plane(adam.m, k) + i, *vv = plane(adam.v, k) + i, *pp = plane(P, k) + i;
+        const float mi = adam.beta1 * *mm + (1.0f - adam.beta1) * gi[k];
+        const float vi = adam.beta2 * *vv + (1.0f - adam.beta2) * gi[k] * gi[k];
+        *mm = mi;
+        *vv = vi;
+        *pp -= adam.lr[group] * (mi / bc1) / (sqrtf(vi / bc2) + adam.eps);
+    }
+}
+
 // Backward of the projection, one thread per gaussian. grad2d holds one record of kG2Stride
 // floats per gaussian id: d/d(mean2 x, y; conic a, b, c; opacity; r, g, b; depth); each thread
-// zeroes the record it read, so grad2d is all-zero again for the next backward. The 14 parameter
-// gradients are added to grad (accumulate) or written to it. Every access is coalesced.
+// zeroes the record it read, so grad2d is all-zero again for the next backward. The gaussian's
+// 14 parameter gradients plus grad_in (nullable: gradients of earlier views) are written to
+// grad_out (nullable) and, when adam.m.mean is set, applied by Adam. Every access is coalesced.
 __global__ void __launch_bounds__(256)
-k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad, int accumulate)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad_in, GradK grad_out, AdamK adam)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
@@ -326,12 +350,15 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
         if (p.valid) chain_rule(p, cam, g2, out);
         else any = false;
     }
-    if (!any && accumulate) return;
+    // accumulating in place with nothing to add and no update: the gradient stays as it is
+    if (!any && !adam.m.mean && grad_in.mean && grad_in.mean == grad_out.mean) return;
+    float gi[14];
 #pragma unroll
-    for (int k = 0; k < 14; ++k) {
-        float *d = plane(grad, k) + i;
-        *d = accumulate ? *d + (float)out[k] : (float)out[k];
-    }
+    for (int k = 0; k < 14; ++k) gi[k] = grad_in.mean ? plane(grad_in, k)[i] + (float)out[k] : (float)out[k];
+    if (grad_out.mean)
+#pragma unroll
+        for (int k = 0; k < 14; ++k) plane(grad_out, k)[i] = gi[k];
+    if (adam.m.mean) adam_update(adam, g, i, gi);
 }
 
 // Window backward: per gaussian, the 2D gradient records of every view (view v's at grad2d +
@@ -357,26 +384,13 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
         project_gaussian(g, i, cam, lowpass, p);
         if (p.valid) chain_rule(p, cam, g2, out);
     }
+    float gi[14];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) gi[k] = (float)out[k];
     if (grad.mean)
 #pragma unroll
-        for (int k = 0; k < 14; ++k) plane(grad, k)[i] = (float)out[k];
-    if (adam.m.mean) {
-        const double t = (double)(*adam.step + 1);
-        const float bc1 = (float)(1.0 - pow((double)adam.beta1, t));
-        const float bc2 = (float)(1.0 - pow((double)adam.beta2, t));
-        GradK P{g.n, g.stride, (float *)g.mean, (float *)g.log_scale, (float *)g.quat, (float *)g.logit, (float *)g.rgb};
-#pragma unroll
-        for (int k = 0; k < 14; ++k) {
-            const int group = k < 3 ? 0 : k < 6 ? 1 : k < 10 ? 2 : k < 11 ? 3 : 4;
-            const float gi = (float)out[k];
-            float *mm = plane(adam.m, k) + i, *vv = plane(adam.v, k) + i, *pp = plane(P, k) + i;
-            const float mi = adam.beta1 * *mm + (1.0f - adam.beta1) * gi;
-            const float vi = adam.beta2 * *vv + (1.0f - adam.beta2) * gi * gi;
-            *mm = mi;
-            *vv = vi;
-            *pp -= adam.lr[group] * (mi / bc1) / (sqrtf(vi / bc2) + adam.eps);
-        }
-    }
+        for (int k = 0; k < 14; ++k) plane(grad, k)[i] = gi[k];
+    if (adam.m.mean) adam_update(adam, g, i, gi);
 }
 
 }  // namespace
@@ -400,13 +414,13 @@ void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, f
                        view_stride, grad, adam);
 }
 
-void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad,
-                        bool accumulate, hipStream_t s)
+void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad_in,
+                        const GradK &grad_out, const AdamK &adam, hipStream_t s)
 {
     if (g.n <= 0) return;
     const int64_t blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, grad2d, grad,
-                       (int)accumulate);
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, grad2d, grad_in, grad_out,
+                       adam);
 }
 
 }  // namespace fgs

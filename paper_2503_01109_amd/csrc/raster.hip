@@ -305,18 +305,35 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     V.tfinal[p] = T;
 }
 
-// Backward of one (pixel, entry) pair, walking the list from the back: decides whether the
-// forward blended it (before the pixel's last blended position, inside the cutoff, above
-// alpha_min), recovers T_i from T_{i+1}, writes the pair's 10 gradient terms (exact zeros when
-// not taken) and advances the pixel's T and S. Returns whether the pair was taken.
-__device__ __forceinline__ bool bwd_pair(const float4 &a4, const float4 &b4, const float4 &c4, bool before_last,
-                                         float px, float py, float qcut, const RasterK &rk, float gC0, float gC1,
-                                         float gC2, float gD, float &T, float &S, float g[10])
+// Backward of one (pixel, entry) pair, walking the list from the back, in two parts. bwd_decide:
+// whether the forward blended it (before the pixel's last blended position, inside the cutoff,
+// above alpha_min). bwd_grad: recovers T_i from T_{i+1}, writes the pair's 10 gradient terms (exact
+// zeros when not taken) and advances the pixel's T and S; a lane that does not take the pair
+// leaves T and S unchanged, so a wave in which no lane takes it can skip bwd_grad altogether.
+struct BwdPair {
+    PairEval e;
+    float ar, alpha;
+    bool take;
+};
+
+__device__ __forceinline__ BwdPair bwd_decide(const float4 &a4, const float4 &b4, bool before_last, float px,
+                                              float py, float qcut, const RasterK &rk)
 {
-    const PairEval e = eval_pair(a4, b4, px, py);
-    const float ar = b4.y * e.G;
-    const float alpha = fminf(rk.alpha_max, ar);
-    const bool take = before_last && !(e.q < qcut) && !(alpha < rk.alpha_min);
+    BwdPair p;
+    p.e = eval_pair(a4, b4, px, py);
+    p.ar = b4.y * p.e.G;
+    p.alpha = fminf(rk.alpha_max, p.ar);
+    p.take = before_last && !(p.e.q < qcut) && !(p.alpha < rk.alpha_min);
+    return p;
+}
+
+__device__ __forceinline__ void bwd_grad(const BwdPair &p, const float4 &a4, const float4 &b4, const float4 &c4,
+                                         const RasterK &rk, float gC0, float gC1, float gC2, float gD, float &T,
+                                         float &S, float g[10])
+{
+    const PairEval &e = p.e;
+    const float alpha = p.alpha;
+    const bool take = p.take;
     const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; alpha <= alpha_max < 1
     const float Ti = T * inv;
     const float w = take ? alpha * Ti : 0.0f;
@@ -324,7 +341,7 @@ __device__ __forceinline__ bool bwd_pair(const float4 &a4, const float4 &b4, con
     const float X = __builtin_fmaf(gC0, c4.x, __builtin_fmaf(gC1, c4.y, __builtin_fmaf(gC2, c4.z, gD * b4.z)));
     const float dal = __builtin_fmaf(-S, inv, Ti * X);
     // a clamped alpha (o G > alpha_max) passes nothing to opacity, mean or conic
-    const float dalg = take && !(ar > rk.alpha_max) ? dal : 0.0f;
+    const float dalg = take && !(p.ar > rk.alpha_max) ? dal : 0.0f;
     S = __builtin_fmaf(w, X, S);
     T = take ? Ti : T;
     g[6] = gC0 * w;
@@ -342,7 +359,6 @@ __device__ __forceinline__ bool bwd_pair(const float4 &a4, const float4 &b4, con
     g[2] = dQdx * e.dx;
     g[3] = 2.0f * (dQdx * e.dy);
     g[4] = (dQ * e.dy) * e.dy;
-    return take;
 }
 
 // Backward of one tile of one view (NT threads, one pixel each).
@@ -429,23 +445,27 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         int i = len - 1;
         for (; i >= 1; i -= 2) {
             const int k0 = slist[wid][i], k1 = slist[wid][i - 1];
+            const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
+            const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
+            const BwdPair p1 = bwd_decide(a1, b1, base + k1 < L, px, py, qcut, rk);
+            const uint64_t any0 = __ballot(p0.take), any1 = __ballot(p1.take);
+            if (!(any0 | any1)) continue;  // no lane blended either entry: nothing to add or update
             float g0[10], g1[10];
-            const bool take0 = bwd_pair(sa[k0], sb[k0], sc[k0], base + k0 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g0);
-            const bool take1 = bwd_pair(sa[k1], sb[k1], sc[k1], base + k1 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g1);
-            const uint64_t any0 = __ballot(take0), any1 = __ballot(take1);
-            if (any0 | any1) {
-                const float t0 = reduce10(g0, lane), t1 = reduce10(g1, lane);
-                if (red_lane) {
-                    if (any0) atomicAdd(&sacc[k0][term], t0);
-                    if (any1) atomicAdd(&sacc[k1][term], t1);
-                }
+            bwd_grad(p0, a0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
+            bwd_grad(p1, a1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
+            const float t0 = reduce10(g0, lane), t1 = reduce10(g1, lane);
+            if (red_lane) {
+                if (any0) atomicAdd(&sacc[k0][term], t0);
+                if (any1) atomicAdd(&sacc[k1][term], t1);
             }
         }
         if (i == 0) {
             const int k0 = slist[wid][0];
-            float g0[10];
-            const bool take0 = bwd_pair(sa[k0], sb[k0], sc[k0], base + k0 < L, px, py, qcut, rk, gC0, gC1, gC2, gD, T, S, g0);
-            if (__ballot(take0)) {
+            const float4 a0 = sa[k0], b0 = sb[k0];
+            const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
+            if (__ballot(p0.take)) {
+                float g0[10];
+                bwd_grad(p0, a0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
                 const float t0 = reduce10(g0, lane);
                 if (red_lane) atomicAdd(&sacc[k0][term], t0);
             }
