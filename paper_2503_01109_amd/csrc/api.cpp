@@ -92,7 +92,7 @@ struct fgs_ctx {
     int64_t ws_n = -1, ws_cap = -1;
     int hist_G = 0;  // radix-sort workgroups the hist buffer holds
     // mapping-step buffers
-    DBuf ms_state, ms_img, ms_dl, ms_grad, ms_partials;
+    DBuf ms_state, ms_dl, ms_grad, ms_partials;
     DBuf seed_ws, seed_sc;
     // learned prior: network workspace (rows_cap rows) and per-frame tile buffers for seeding
     DBuf mlp_ws, prior_feat, prior_valid, prior_y;
@@ -444,7 +444,8 @@ void camera_to_world_quat(const float R_cw[9], float q[4])
 // with the count in *K_check before enqueueing the rest.
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
-                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true)
+                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
+                           const LossK *loss = nullptr)
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
@@ -510,8 +511,9 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");
+        const LossK no_loss{};
         launch_raster_fwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, img,
-                          prof_counts(ctx), s);
+                          loss ? *loss : no_loss, prof_counts(ctx), s);
         if (prof_counts(ctx)) ctx->prof_fwd++;
     }
     HIP_TRY(ctx, hipGetLastError());
@@ -644,7 +646,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
-                    &ctx->words, &ctx->ms_state, &ctx->ms_img, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
+                    &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets};
     for (DBuf *b : bufs) b->release();
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
@@ -935,9 +937,13 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         float *b = ctx->ms_grad.as<float>();
         grad = fgs_gaussians{n, n, b, b + 3 * n, b + 6 * n, b + 10 * n, b + 11 * n};
     }
-    HIP_TRY(ctx, ctx->ms_img.ensure((size_t)Pmax * 4 * 4));
+    // the loss is fused into each view's forward: per-pixel gradients into ms_dl, one partial
+    // quadruple per tile into ms_partials
+    int64_t Tmax = 0;
+    for (int v = 0; v < n_views; ++v)
+        Tmax = std::max<int64_t>(Tmax, (int64_t)((cams[v].width + tw - 1) / tw) * ((cams[v].height + th - 1) / th));
     HIP_TRY(ctx, ctx->ms_dl.ensure((size_t)Pmax * 4 * 4));
-    HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)loss_partials_size(Pmax) * 4));
+    HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)Tmax * 4 * 4));
     if (ctx->ms_cap == 0) ctx->ms_cap = n * 16 > ((int64_t)1 << 22) ? n * 16 : ((int64_t)1 << 22);
     float *dscale = ctx->words.as<float>() + W_DSCALE;
     for (int v = 0; v < n_views; ++v) {
@@ -948,8 +954,17 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         for (int attempt = 0;; ++attempt) {
             state_layout(n, cam.width, cam.height, tw, th, ctx->ms_cap, &L);
             HIP_TRY(ctx, ctx->ms_state.ensure(L.bytes));
-            float *im = ctx->ms_img.as<float>();
-            ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
+            const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // only the loss reads the image
+            float *dl = ctx->ms_dl.as<float>();
+            LossK lk{};
+            lk.trgb = targets[v].rgb;
+            lk.tdepth = targets[v].depth;
+            lk.drgb = dl;
+            lk.ddepth = dl + 3 * P;
+            lk.partials = ctx->ms_partials.as<float>();
+            lk.lrgb = l->lambda_rgb;
+            lk.ldepth = l->lambda_depth;
+            lk.inv3P = (float)(1.0 / (3.0 * (double)P));
             // The pair count is data dependent. A view is checked synchronously (the forward waits
             // for the count after the scan and restarts with a larger state when it does not fit)
             // the first time it is seen (a new index, camera or gaussian count) and whenever its last
@@ -961,7 +976,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             const bool checked = !seen || K_obs * 10 > ctx->ms_cap * 9;
             int64_t K = 0;
             st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, checked ? &K : nullptr,
-                                 hs_dev);
+                                 hs_dev, true, &lk);
             if (st == FGS_OK) {
                 if (v < 4096) {
                     ctx->ms_seen[v] = true;
@@ -975,13 +990,11 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             if (st != FGS_ERR_CAPACITY || attempt > 0) return st;
             ctx->ms_cap = K + K / 4 + 1024;
         }
-        float *im = ctx->ms_img.as<float>();
         float *dl = ctx->ms_dl.as<float>();
         {
             Stage st_(ctx, "loss");
-            launch_loss_l1(P, im, im + 3 * P, targets[v].rgb, targets[v].depth, l->lambda_rgb, l->lambda_depth, dl,
-                           dl + 3 * P, dscale, ctx->ms_partials.as<float>(), loss_dev ? loss_dev + v : nullptr,
-                           psnr_dev ? psnr_dev + v : nullptr, s);
+            launch_loss_final(ctx->ms_partials.as<float>(), (int)L.T, P, l->lambda_rgb, l->lambda_depth, dscale,
+                              loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr, s);
         }
         // views before the last sum their gradients into grad; the last one adds its own and
         // applies Adam in the same kernel (writing the sum only when the caller asked for it)

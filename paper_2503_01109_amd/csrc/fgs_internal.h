@@ -168,8 +168,19 @@ void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t ca
                    int64_t T, hipStream_t s);
 
 struct ImageK {
-    float *rgb, *depth, *alpha, *T_final;
+    float *rgb, *depth, *alpha, *T_final;  // rgb, depth: nullable when the loss below is fused
     int32_t *n_contrib;
+};
+
+// The L1 terms of the mapping loss fused into the forward's per-pixel epilogue (partials ==
+// nullptr: none). For each pixel: drgb = lrgb sgn(C - C*) inv3P per channel, ddepth = ldepth
+// sgn(D - D*) where D* > 0 (else 0; the 1/P_v factor is applied by the backward); each tile's
+// workgroup writes partials[4 tile + q] = its sums of |C - C*|, (C - C*)^2, |D - D*| over valid
+// depth, and the valid-depth count, which launch_loss_final reduces.
+struct LossK {
+    const float *trgb, *tdepth;
+    float *drgb, *ddepth, *partials;
+    float lrgb, ldepth, inv3P;
 };
 
 // Everything the rasterizer needs for one view (kernel argument, or an entry of a device array
@@ -186,6 +197,7 @@ struct ViewK {
     const float *drgb, *ddepth, *dalpha, *ddepth_scale;
     float *grad2d;
     unsigned long long *counts;
+    LossK loss;
     uint32_t tile_base;  // index of this view's first tile in the window's item numbering
 };
 
@@ -203,7 +215,7 @@ void launch_raster_window(bool fwd, bool count, const ViewK *views_dev, int nv, 
 // counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel
 // stopped, [1] += pairs blended, [2] += list entries staged.
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
+                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img, const LossK &loss,
                        unsigned long long *counts, hipStream_t s);
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
@@ -244,6 +256,10 @@ void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, f
 // loss_partials_size(P) floats; writes loss/psnr device scalars (nullable) and the depth-gradient
 // scale 1/P_v into *ddepth_scale.
 int64_t loss_partials_size(int64_t P);
+// Reduction of nb partial quadruples (as written by the fused forward loss) into loss, psnr and
+// the depth term's 1/P_v (all device scalars, nullable).
+void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
+                       float *loss, float *psnr, hipStream_t s);
 void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float *trgb,
                     const float *tdepth, float lrgb, float ldepth, float *drgb, float *ddepth,
                     float *ddepth_scale, float *partials, float *loss, float *psnr, hipStream_t s);

@@ -164,6 +164,13 @@ void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float
                        loss, psnr);
 }
 
+void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
+                       float *loss, float *psnr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
+                       loss, psnr);
+}
+
 void launch_scale(float *x, int64_t n, const float *s, hipStream_t st)
 {
     if (n <= 0) return;

@@ -34,6 +34,8 @@ namespace {
 constexpr float kConicScale = -0.721347520444481703680f;
 constexpr float kMeanGradScale = 2.772588722239781237669f;
 
+__device__ __forceinline__ float sgn(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
+
 // Record of a list entry in tile-local coordinates: a = {mean x, mean y, s a, s b}, b = {s c,
 // opacity, depth, 0}, c = {r, g, b, 0} with (a, b, c) the conic. mean and conic (unscaled) are
 // returned for the strip test.
@@ -290,19 +292,60 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     }
     // the next tile of a persistent workgroup restages the LDS arrays: wait for every reader
     __syncthreads();
-    if (!inside) return;
     const int64_t P = (int64_t)W * H;
     const int64_t p = (int64_t)y * W + x;
-    const ImageK &img = V.img;
-    img.rgb[p] = C0 + T * rk.bg[0];
-    img.rgb[P + p] = C1 + T * rk.bg[1];
-    img.rgb[2 * P + p] = C2 + T * rk.bg[2];
-    img.depth[p] = D + T * rk.bg_depth;
-    if (img.alpha) img.alpha[p] = A;
-    if (img.T_final) img.T_final[p] = T;
-    if (img.n_contrib) img.n_contrib[p] = ncon;
-    V.last[p] = last;
-    V.tfinal[p] = T;
+    const float col[3] = {C0 + T * rk.bg[0], C1 + T * rk.bg[1], C2 + T * rk.bg[2]};
+    const float dep = D + T * rk.bg_depth;
+    if (inside) {
+        const ImageK &img = V.img;
+        if (img.rgb) {
+            img.rgb[p] = col[0];
+            img.rgb[P + p] = col[1];
+            img.rgb[2 * P + p] = col[2];
+        }
+        if (img.depth) img.depth[p] = dep;
+        if (img.alpha) img.alpha[p] = A;
+        if (img.T_final) img.T_final[p] = T;
+        if (img.n_contrib) img.n_contrib[p] = ncon;
+        V.last[p] = last;
+        V.tfinal[p] = T;
+    }
+    const LossK &lk = V.loss;
+    if (lk.partials) {
+        // the L1 terms of the mapping loss and their gradients, summed over the tile
+        float q[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // |C - C*|, (C - C*)^2, |D - D*| (valid), valid
+        if (inside) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float r = col[c] - lk.trgb[c * P + p];
+                q[0] += fabsf(r);
+                q[1] += r * r;
+                lk.drgb[c * P + p] = lk.lrgb * sgn(r) * lk.inv3P;
+            }
+            const float td = lk.tdepth[p];
+            const bool valid = td > 0.0f;
+            const float rd = dep - td;
+            q[2] = valid ? fabsf(rd) : 0.0f;
+            q[3] = valid ? 1.0f : 0.0f;
+            lk.ddepth[p] = valid ? lk.ldepth * sgn(rd) : 0.0f;
+        }
+        __shared__ float sred[NW][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float v = q[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (__lane_id() == 0) sred[wid][k] = v;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            float t = 0.0f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += sred[w][tid];
+            lk.partials[4 * (int64_t)tile + tid] = t;
+        }
+        __syncthreads();  // sred is reused by the next tile of a persistent workgroup
+    }
 }
 
 // Backward of one (pixel, entry) pair, walking the list from the back, in two parts. bwd_decide:
@@ -579,7 +622,7 @@ static void launch_bwd_view(const ViewK &V, hipStream_t s)
 }
 
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
-                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img,
+                       const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img, const LossK &loss,
                        unsigned long long *counts, hipStream_t s)
 {
     ViewK V = view_of_args(rk, W, H, rec, vals);
@@ -587,6 +630,7 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
     V.last = last;
     V.tfinal = tfinal;
     V.img = img;
+    V.loss = loss;
     V.counts = counts;
     launch_fwd_view(V, s);
 }
