@@ -1192,7 +1192,7 @@ struct fgs_window {
     std::vector<int64_t> pix_off;  // float offset of view v's 4 planes in img and dl
     std::vector<uint32_t> tile_base;
     uint32_t total_tiles = 0;
-    DBuf img, dl, grad2d, views, cams_dev, words, partials;
+    DBuf dl, grad2d, views, cams_dev, words, partials;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -1221,7 +1221,6 @@ void window_drop_graph(fgs_window *w)
     w->sig.clear();
 }
 
-float *view_img(fgs_window *w, int v) { return w->img.as<float>() + w->pix_off[v]; }
 float *view_dl(fgs_window *w, int v) { return w->dl.as<float>() + w->pix_off[v]; }
 
 // Size every view's state from a synchronous pair count (50% headroom) for this n.
@@ -1233,13 +1232,11 @@ fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_ren
     if ((st = ensure_ws(ctx, std::max<int64_t>(n, w->total_tiles), 0)) != FGS_OK) return st;
     for (int v = 0; v < w->nv; ++v) {
         const fgs_camera &cam = w->cams[v];
-        const int64_t P = (int64_t)cam.width * cam.height;
         int64_t cap = std::max<int64_t>(w->cap[v], std::max<int64_t>(n * 8, (int64_t)1 << 20));
         for (int attempt = 0;; ++attempt) {
             state_layout(n, cam.width, cam.height, w->tw[v], w->th[v], cap, &w->L[v]);
             HIP_TRY(ctx, w->state[v].ensure(w->L[v].bytes));
-            float *im = view_img(w, v);
-            ImageK img{im, im + 3 * P, nullptr, nullptr, nullptr};
+            const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // binning only: no image
             int64_t K = 0;
             st = enqueue_forward(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v], &K, nullptr,
                                  false);
@@ -1268,15 +1265,25 @@ fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_ren
     return FGS_OK;
 }
 
-// Build and upload the device table of views (pointers, shapes, options) when it changed.
-fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_render_opts &o)
+// Build and upload the device table of views (pointers, shapes, options, the fused loss's
+// targets) when it changed.
+fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_render_opts &o,
+                         const fgs_target *targets, const fgs_loss_opts &l)
 {
     fgs_ctx *ctx = w->ctx;
     std::vector<uintptr_t> sig = {(uintptr_t)params.n, (uintptr_t)ctx->prof};
     uint32_t ob[sizeof(fgs_render_opts) / 4];
     memcpy(ob, &o, sizeof(ob));
     for (uint32_t x : ob) sig.push_back(x);
-    for (int v = 0; v < w->nv; ++v) sig.push_back((uintptr_t)w->state[v].p);
+    uint32_t lb[2];
+    memcpy(&lb[0], &l.lambda_rgb, 4);
+    memcpy(&lb[1], &l.lambda_depth, 4);
+    for (uint32_t x : lb) sig.push_back(x);
+    for (int v = 0; v < w->nv; ++v) {
+        sig.push_back((uintptr_t)w->state[v].p);
+        sig.push_back((uintptr_t)targets[v].rgb);
+        sig.push_back((uintptr_t)targets[v].depth);
+    }
     if (sig == w->table_sig) return FGS_OK;
     HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // earlier copies out of the pinned tables are done
     const int64_t n = params.n;
@@ -1293,7 +1300,15 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         V.ranges = sp.ranges;
         V.last = sp.last;
         V.tfinal = sp.tfinal;
-        V.img = ImageK{view_img(w, v), view_img(w, v) + 3 * P, nullptr, nullptr, nullptr};
+        V.img = ImageK{nullptr, nullptr, nullptr, nullptr, nullptr};  // only the fused loss reads the image
+        V.loss.trgb = targets[v].rgb;
+        V.loss.tdepth = targets[v].depth;
+        V.loss.drgb = view_dl(w, v);
+        V.loss.ddepth = view_dl(w, v) + 3 * P;
+        V.loss.partials = w->partials.as<float>() + 4 * (size_t)w->tile_base[v];
+        V.loss.lrgb = l.lambda_rgb;
+        V.loss.ldepth = l.lambda_depth;
+        V.loss.inv3P = (float)(1.0 / (3.0 * (double)P));
         V.drgb = view_dl(w, v);
         V.ddepth = view_dl(w, v) + 3 * P;
         V.ddepth_scale = w->words.as<float>() + WW_DSCALE + v;
@@ -1321,8 +1336,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     const int64_t n = params.n;
     for (int v = 0; v < w->nv; ++v) {
         const fgs_camera &cam = w->cams[v];
-        const int64_t P = (int64_t)cam.width * cam.height;
-        ImageK img{view_img(w, v), view_img(w, v) + 3 * P, nullptr, nullptr, nullptr};
+        const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // binning only: no image
         if ((st = enqueue_forward(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v], nullptr,
                                   w->hs_dev + 2 * v, false)) != FGS_OK)
             return st;
@@ -1335,12 +1349,12 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
         if (prof_counts(ctx)) ctx->prof_fwd += w->nv;
     }
     for (int v = 0; v < w->nv; ++v) {
+        // the forward wrote the L1 terms' gradients and one partial quadruple per tile
         const int64_t P = (int64_t)w->cams[v].width * w->cams[v].height;
         Stage st_(ctx, "loss");
-        launch_loss_l1(P, view_img(w, v), view_img(w, v) + 3 * P, targets[v].rgb, targets[v].depth, l.lambda_rgb,
-                       l.lambda_depth, view_dl(w, v), view_dl(w, v) + 3 * P, w->words.as<float>() + WW_DSCALE + v,
-                       w->partials.as<float>(), loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr,
-                       s);
+        launch_loss_final(w->partials.as<float>() + 4 * (size_t)w->tile_base[v], (int)w->L[v].T, P, l.lambda_rgb,
+                          l.lambda_depth, w->words.as<float>() + WW_DSCALE + v, loss_dev ? loss_dev + v : nullptr,
+                          psnr_dev ? psnr_dev + v : nullptr, s);
     }
     {
         Stage st_(ctx, "raster_bwd");
@@ -1395,7 +1409,7 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
     w->ctx = ctx;
     w->nv = n_views;
     w->cams.assign(cams, cams + n_views);
-    int64_t pix = 0, pmax = 0;
+    int64_t pix = 0;
     uint64_t tb = 0;
     for (int v = 0; v < n_views; ++v) {
         w->tw.push_back(tiles ? tiles[2 * v] : 16);
@@ -1403,7 +1417,6 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
         w->pix_off.push_back(4 * pix);
         const int64_t P = (int64_t)cams[v].width * cams[v].height;
         pix += P;
-        pmax = std::max(pmax, P);
         w->tile_base.push_back((uint32_t)tb);
         tb += (uint64_t)((cams[v].width + w->tw[v] - 1) / w->tw[v]) * ((cams[v].height + w->th[v] - 1) / w->th[v]);
     }
@@ -1424,13 +1437,12 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
     w->blocks = blocks_per_cu * cus;  // 0: one workgroup per (view, tile) item
     const size_t wbytes = (size_t)(WW_DSCALE + n_views) * 4 + 64;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = w->img.ensure((size_t)pix * 4 * 4);
     if (e == hipSuccess) e = w->dl.ensure((size_t)pix * 4 * 4);
     if (e == hipSuccess) e = w->views.ensure(sizeof(ViewK) * n_views);
     if (e == hipSuccess) e = w->cams_dev.ensure(sizeof(CamK) * n_views);
     if (e == hipSuccess) e = w->words.ensure(wbytes);
     if (e == hipSuccess) e = hipMemset(w->words.p, 0, wbytes);
-    if (e == hipSuccess) e = w->partials.ensure((size_t)loss_partials_size(pmax) * 4);
+    if (e == hipSuccess) e = w->partials.ensure((size_t)w->total_tiles * 4 * 4);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming);
@@ -1457,7 +1469,7 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     window_drop_graph(w);
     for (DBuf &b : w->state) b.release();
-    DBuf *bufs[] = {&w->img, &w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials};
+    DBuf *bufs[] = {&w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials};
     for (DBuf *b : bufs) b->release();
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
@@ -1531,7 +1543,7 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
         ~Rebind() { c->stream = s; }
     } rebind{ctx, user};
     if (params->n != w->n && (st = window_size(w, *params, *o)) != FGS_OK) return st;
-    if ((st = window_tables(w, *params, *o)) != FGS_OK) return st;
+    if ((st = window_tables(w, *params, *o, targets, *l)) != FGS_OK) return st;
     const int64_t dev_step = w->dev_step;
     w->dev_step = -1;  // unknown until this step is enqueued whole
     if (opt->step != dev_step) {  // the device counter follows the host's
