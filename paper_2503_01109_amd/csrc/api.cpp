@@ -221,6 +221,7 @@ RasterK to_rk(const fgs_render_opts &o, int tw, int th, int W, int H)
     r.tile_w = tw; r.tile_h = th;
     r.tiles_x = (W + tw - 1) / tw;
     r.tiles_y = (H + th - 1) / th;
+    r.supers_x = supers_for(r.tiles_x);
     return r;
 }
 
@@ -561,7 +562,7 @@ bool state_layout(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64
     l.n = n; l.W = W; l.H = H; l.tw = tw; l.th = th;
     l.tiles_x = (W + tw - 1) / tw;
     l.tiles_y = (H + th - 1) / th;
-    l.T = (int64_t)l.tiles_x * l.tiles_y;
+    l.T = tile_items(l.tiles_x, l.tiles_y);
     l.P = (int64_t)W * H;
     size_t o = 0;
     l.off_rec = o; o = align256(o + (size_t)n * sizeof(Rec));
@@ -941,7 +942,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     // quadruple per tile into ms_partials
     int64_t Tmax = 0;
     for (int v = 0; v < n_views; ++v)
-        Tmax = std::max<int64_t>(Tmax, (int64_t)((cams[v].width + tw - 1) / tw) * ((cams[v].height + th - 1) / th));
+        Tmax = std::max<int64_t>(Tmax, tile_items((cams[v].width + tw - 1) / tw, (cams[v].height + th - 1) / th));
     HIP_TRY(ctx, ctx->ms_dl.ensure((size_t)Pmax * 4 * 4));
     HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)Tmax * 4 * 4));
     if (ctx->ms_cap == 0) ctx->ms_cap = n * 16 > ((int64_t)1 << 22) ? n * 16 : ((int64_t)1 << 22);
@@ -1418,7 +1419,7 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
         const int64_t P = (int64_t)cams[v].width * cams[v].height;
         pix += P;
         w->tile_base.push_back((uint32_t)tb);
-        tb += (uint64_t)((cams[v].width + w->tw[v] - 1) / w->tw[v]) * ((cams[v].height + w->th[v] - 1) / w->th[v]);
+        tb += (uint64_t)tile_items((cams[v].width + w->tw[v] - 1) / w->tw[v], (cams[v].height + w->th[v] - 1) / w->th[v]);
     }
     if (tb >= ((uint64_t)1 << 31)) {
         delete w;

@@ -23,8 +23,19 @@ struct RasterK {
     float sigma_cut, alpha_min, alpha_max, T_min, lowpass;
     float bg[3];
     float bg_depth;
-    int32_t tile_w, tile_h, tiles_x, tiles_y;
+    int32_t tile_w, tile_h, tiles_x, tiles_y, supers_x;
 };
+
+// Tiles are grouped in super-tiles of kSuper x kSuper and numbered super-tile-major: item
+// g = kSuper^2 s + kSuper ly + lx is tile (kSuper (s % supers_x) + lx, kSuper (s / supers_x) + ly);
+// items beyond the image's tiles have empty lists. Tile ranges, rasterizer grids and window items
+// all use this numbering.
+constexpr int kSuper = 4, kSuperShift = 2;
+inline int32_t supers_for(int32_t tiles) { return (tiles + kSuper - 1) / kSuper; }
+inline int64_t tile_items(int32_t tiles_x, int32_t tiles_y)
+{
+    return (int64_t)supers_for(tiles_x) * supers_for(tiles_y) * kSuper * kSuper;
+}
 
 // 2D gradients of one view: one record of kG2Stride floats per gaussian id, terms d/d(mean2 x, y;
 // conic a, b, c; opacity; r, g, b; depth) in slots 0..9, the rest padding (a record is one 64-byte
@@ -66,7 +77,7 @@ struct StateLayout {
     int32_t W = 0, H = 0, tw = 0, th = 0, tiles_x = 0, tiles_y = 0;
     size_t off_rec = 0;    // Rec x n, by gaussian id
     size_t off_ids = 0;    // u32 x n: gaussian id of depth rank r (used by the binning)
-    size_t off_ranges = 0; // uint2 x T: [start, end) into vals per tile
+    size_t off_ranges = 0; // uint2 x T: [start, end) into vals per tile item (super-tile-major)
     size_t off_last = 0;   // u32 x P: list position after a pixel's last blended gaussian
     size_t off_tfinal = 0; // f32 x P: final transmittance
     size_t off_vals = 0;   // u32 x cap: gaussian ids, per tile in (depth, index) order
@@ -143,7 +154,6 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
 //                      overflow);
 //   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
-constexpr int kSuper = 4, kSuperShift = 2;
 struct BinWS {
     uint32_t *cstart;      // nsup + 1
     uint32_t *csuper;      // max_chunks

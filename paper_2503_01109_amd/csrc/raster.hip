@@ -215,7 +215,8 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     const int TW = rk.tile_w, TH = rk.tile_h;
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
-    const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
+    const int sidx = tile / (kSuper * kSuper), sl = tile % (kSuper * kSuper);
+    const int tx = (sidx % rk.supers_x) * kSuper + sl % kSuper, ty = (sidx / rk.supers_x) * kSuper + sl / kSuper;
     const int x0 = tx * TW, y0 = ty * TH;
     const int lx = tid % TW, ly = tid / TW;
     const int x = x0 + lx, y = y0 + ly;
@@ -426,7 +427,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
     const bool red_lane = lane < 16 && term >= 0;
     const int wid = tid / kWave;
-    const int tx = tile % rk.tiles_x, ty = tile / rk.tiles_x;
+    const int sidx = tile / (kSuper * kSuper), sl = tile % (kSuper * kSuper);
+    const int tx = (sidx % rk.supers_x) * kSuper + sl % kSuper, ty = (sidx / rk.supers_x) * kSuper + sl / kSuper;
     const int x0 = tx * TW, y0 = ty * TH;
     const int lx = tid % TW, ly = tid / TW;
     const int x = x0 + lx, y = y0 + ly;
@@ -599,7 +601,7 @@ static ViewK view_of_args(const RasterK &rk, int32_t W, int32_t H, const Rec *re
 
 static void launch_fwd_view(const ViewK &V, hipStream_t s)
 {
-    const unsigned tiles = (unsigned)(V.rk.tiles_x * V.rk.tiles_y);
+    const unsigned tiles = (unsigned)tile_items(V.rk.tiles_x, V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
     if (V.counts) {
         if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, true>), dim3(tiles), dim3(256), 0, s, V);
@@ -614,7 +616,7 @@ static void launch_fwd_view(const ViewK &V, hipStream_t s)
 
 static void launch_bwd_view(const ViewK &V, hipStream_t s)
 {
-    const unsigned tiles = (unsigned)(V.rk.tiles_x * V.rk.tiles_y);
+    const unsigned tiles = (unsigned)tile_items(V.rk.tiles_x, V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
     if (nt == 256) hipLaunchKernelGGL(k_raster_bwd<256>, dim3(tiles), dim3(256), 0, s, V);
     else if (nt == 512) hipLaunchKernelGGL(k_raster_bwd<512>, dim3(tiles), dim3(512), 0, s, V);

@@ -420,7 +420,7 @@ __global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, int supers_x, 
                              uint32_t *__restrict__ chist, uint32_t *__restrict__ tile_total)
 {
     const int sidx = blockIdx.x, b = threadIdx.x;
-    const int tx = (sidx % supers_x) * kSuper + (b % kSuper), ty = (sidx / supers_x) * kSuper + (b / kSuper);
+    (void)supers_x, (void)tiles_x, (void)tiles_y;
     uint32_t run = 0;
     for (uint32_t c = cstart[sidx]; c < cstart[sidx + 1]; ++c) {
         uint32_t *h = chist + (size_t)c * (kSuper * kSuper) + b;
@@ -428,28 +428,40 @@ __global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, int supers_x, 
         *h = run;
         run += v;
     }
-    if (tx < tiles_x && ty < tiles_y) tile_total[(size_t)ty * tiles_x + tx] = run;
+    tile_total[(size_t)sidx * (kSuper * kSuper) + b] = run;  // zero for tiles beyond the image
 }
 
-// Single block: tile ranges from the tile totals (row-major tile order), the pair count K, and
-// the capacity check; on overflow every range is empty and the condition is recorded.
+// Single block: tile ranges from the tile totals (super-tile-major items: each thread takes one
+// super-tile's 16 tiles, the block scans the super-tile sums), the pair count K, and the capacity
+// check; on overflow every range is empty and the condition is recorded.
 __global__ void __launch_bounds__(kSortThreads)
-k_bin_tiles(const uint32_t *__restrict__ tile_total, int64_t T, int64_t cap, const uint32_t *__restrict__ ktotal,
+k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, const uint32_t *__restrict__ ktotal,
             uint2 *__restrict__ ranges, uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev,
             uint32_t *__restrict__ host_status, uint32_t *__restrict__ ok)
 {
+    constexpr int NB = kSuper * kSuper;
     __shared__ uint32_t w[8];
     // K counted by the projection equals the sum of the tile totals whenever the super-tile pairs
     // fit (they are at most K); beyond the capacity nothing is placed
     const uint32_t K = *ktotal;
     const bool ovf = (int64_t)K > cap;
     uint32_t carry = 0;
-    for (int64_t base = 0; base < T; base += kSortThreads) {
-        const int64_t t = base + threadIdx.x;
-        const uint32_t v = t < T ? tile_total[t] : 0u;
+    for (int base = 0; base < nsup; base += kSortThreads) {
+        const int sidx = base + threadIdx.x;
+        uint32_t v[NB], sum = 0;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            v[l] = sidx < nsup ? tile_total[(size_t)sidx * NB + l] : 0u;
+            sum += v[l];
+        }
         uint32_t tot;
-        const uint32_t ex = carry + block_excl_scan(v, w, &tot);
-        if (t < T) ranges[t] = ovf ? make_uint2(0u, 0u) : make_uint2(ex, ex + v);
+        uint32_t at = carry + block_excl_scan(sum, w, &tot);
+        if (sidx < nsup)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                ranges[(size_t)sidx * NB + l] = ovf ? make_uint2(0u, 0u) : make_uint2(at, at + v[l]);
+                at += v[l];
+            }
         carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -480,12 +492,7 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     if (c >= *nchunks || !*ok) return;
     const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x);
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
-    if (tid < NB) {
-        const int tx = cs.sx * kSuper + (tid % kSuper), ty = cs.sy * kSuper + (tid / kSuper);
-        run[tid] = (tx < tiles_x && ty < tiles_y)
-                       ? ranges[(size_t)ty * tiles_x + tx].x + chist[(size_t)c * NB + tid]
-                       : 0u;
-    }
+    if (tid < NB) run[tid] = ranges[(size_t)(cs.sy * supers_x + cs.sx) * NB + tid].x + chist[(size_t)c * NB + tid];
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
         const uint32_t e = base + tid;
@@ -643,8 +650,8 @@ void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int t
 {
     hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, supers_x, tiles_x,
                        tiles_y, b.chist, b.tile_total);
-    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, (int64_t)tiles_x * tiles_y, cap,
-                       ktotal, ranges, status, n_pairs_dev, host_status, b.ok);
+    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, nsup, cap, ktotal, ranges, status,
+                       n_pairs_dev, host_status, b.ok);
 }
 
 void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect, int supers_x,
