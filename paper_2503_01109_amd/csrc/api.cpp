@@ -440,46 +440,39 @@ void camera_to_world_quat(const float R_cw[9], float q[4])
     q[3] = (float)(z / nrm);
 }
 
-// Enqueue the forward pipeline into a state with layout L. With K_check, the call waits for the
-// pair count after the scan and, when it exceeds the state's capacity, returns FGS_ERR_CAPACITY
-// with the count in *K_check before enqueueing the rest.
-fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
-                           int tw, int th, const ImageK &img, void *state, const StateLayout &L,
-                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
-                           const LossK *loss = nullptr)
+// Where the projection of a view left its per-gaussian tile rectangles and super-tile counts and
+// its per-workgroup pair counts (read by the binning).
+struct ProjOut {
+    uint2 *rect;
+    uint32_t *count, *kpart;
+};
+
+// Enqueue the binning of a projected, depth-sorted view (the state's ids hold its depth order)
+// and, with raster, its forward rasterization. With K_check, the call waits for the pair count
+// after the scan and, when it exceeds the state's capacity, returns FGS_ERR_CAPACITY with the
+// count in *K_check before enqueueing the rest.
+fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
+                              int tw, int th, const ImageK &img, void *state, const StateLayout &L, const ProjOut &po,
+                              int64_t *K_check, uint32_t *host_status, bool raster, const LossK *loss)
 {
-    fgs_status st = ensure_ws(ctx, g.n, L.cap);
-    if (st != FGS_OK) return st;
     const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
     const int supers_x = (rk.tiles_x + kSuper - 1) / kSuper, supers_y = (rk.tiles_y + kSuper - 1) / kSuper;
     const int nsup = supers_x * supers_y;
+    fgs_status st;
     if ((st = ensure_bin(ctx, nsup, L.T, L.cap)) != FGS_OK) return st;
     hipStream_t s = ctx->stream;
-    const CamK ck = to_camk(cam);
-    const ParamsK pk = to_pk(g);
     const StatePtrs sp = state_ptrs(state, L);
     uint32_t *words = ctx->words.as<uint32_t>();
-    uint32_t *ndev = words + W_NDEV, *npairs = words + W_NPAIRS, *nsup_pairs = words + W_NSUP;
+    uint32_t *npairs = words + W_NPAIRS, *nsup_pairs = words + W_NSUP;
     uint32_t *ktotal = words + W_KTOTAL;
     const BinWS bw = bin_ws(ctx);
     const int sbits = key_bits_for(nsup);
     uint32_t *svals = (sbits + 7) / 8 == 1 ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
-
-    {
-        Stage st_(ctx, "project");
-        launch_project(pk, ck, rk, sp.rec, ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(),
-                       ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, kSuperShift, ctx->kpart.as<uint32_t>(), s);
-    }
-    {
-        Stage st_(ctx, "depth_sort");
-        launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n, kDepthSortPerBlock), s);
-    }
     {
         // one pair per covered super-tile, in depth order
         Stage st_(ctx, "bin");
-        launch_scan_counts(sp.ids, ctx->count.as<uint32_t>(), g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx),
-                           ctx->kpart.as<uint32_t>(), project_blocks(g.n), ktotal, s);
+        launch_scan_counts(sp.ids, po.count, g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx), po.kpart,
+                           project_blocks(g.n), ktotal, s);
     }
     if (K_check) {
         fgs_status st2 = read_words(ctx);
@@ -489,10 +482,10 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     }
     {
         Stage st_(ctx, "bin");
-        launch_emit(sp.ids, ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(), ctx->blocksums.as<uint32_t>(),
-                    ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(),
-                    ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(),
-                    status_words(ctx), nsup_pairs, nullptr, s);
+        launch_emit(sp.ids, po.count, po.rect, ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n,
+                    supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
+                    ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs,
+                    nullptr, s);
     }
     const uint2 *sranges = ctx->bin_sranges.as<uint2>();
     {
@@ -503,12 +496,11 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
                                            ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
         const bool one_pass = sbits <= 8;
         if (!one_pass) launch_ranges(keys, nsup_pairs, L.cap, ctx->bin_sranges.as<uint2>(), nsup, s);
-        launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr,
-                          ctx->rect.as<uint2>(), supers_x, nsup, s);
+        launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, po.rect, supers_x,
+                          nsup, s);
         launch_bin_tiles(bw, supers_x, nsup, rk.tiles_x, rk.tiles_y, L.cap, ktotal, sp.ranges, status_words(ctx),
                          npairs, host_status, s);
-        launch_bin_place(bw, svals, sranges, ctx->rect.as<uint2>(), supers_x, rk.tiles_x, rk.tiles_y,
-                         sp.ranges, sp.vals, s);
+        launch_bin_place(bw, svals, sranges, po.rect, supers_x, rk.tiles_x, rk.tiles_y, sp.ranges, sp.vals, s);
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");
@@ -520,6 +512,34 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
+
+// Enqueue the forward pipeline of one view into a state with layout L: projection, depth sort,
+// binning (enqueue_bin_raster, with its K_check) and, with raster, the rasterization.
+fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
+                           int tw, int th, const ImageK &img, void *state, const StateLayout &L,
+                           int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
+                           const LossK *loss = nullptr)
+{
+    fgs_status st = ensure_ws(ctx, g.n, L.cap);
+    if (st != FGS_OK) return st;
+    const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
+    hipStream_t s = ctx->stream;
+    const StatePtrs sp = state_ptrs(state, L);
+    uint32_t *ndev = ctx->words.as<uint32_t>() + W_NDEV;
+    const ProjOut po{ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(), ctx->kpart.as<uint32_t>()};
+    {
+        Stage st_(ctx, "project");
+        launch_project(to_pk(g), to_camk(cam), rk, sp.rec, po.rect, po.count, ctx->dkA.as<uint32_t>(),
+                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s);
+    }
+    {
+        Stage st_(ctx, "depth_sort");
+        launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
+                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n, kDepthSortPerBlock), s);
+    }
+    return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss);
+}
+
 
 // Enqueue the backward of one view: grad_out (nullable) = grad_in (nullable) + this view's
 // gradient; adam (nullable) applies that sum to g.
@@ -1194,6 +1214,10 @@ struct fgs_window {
     std::vector<uint32_t> tile_base;
     uint32_t total_tiles = 0;
     DBuf dl, grad2d, views, cams_dev, words, partials;
+    // all views' depth orders in one sort: per-view pair counts of the projection, the view keys
+    // and sorted values of the last pass, and the device table of the views' id arrays
+    DBuf kpart, bk, bv, ids_dev;
+    uint32_t **ids_host = nullptr;  // pinned staging of ids_dev
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -1255,9 +1279,16 @@ fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_ren
     }
     int64_t capmax = 0;
     for (int v = 0; v < w->nv; ++v) capmax = std::max(capmax, w->cap[v]);
-    if ((st = ensure_ws(ctx, std::max<int64_t>(n, w->total_tiles), capmax)) != FGS_OK) return st;
+    // the context's depth-sort buffers hold every view's keys at once
+    const int64_t all = (int64_t)w->nv * n;
+    if (all >= ((int64_t)1 << 31))
+        return fail(ctx, FGS_ERR_UNSUPPORTED, "fgs_window_step: views x gaussians = %lld exceeds 2^31", (long long)all);
+    if ((st = ensure_ws(ctx, std::max<int64_t>(all, w->total_tiles), capmax)) != FGS_OK) return st;
     const size_t g2 = (size_t)w->nv * kG2Stride * (size_t)(n > 0 ? n : 1) * 4;
     HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+    HIP_TRY(ctx, w->kpart.ensure((size_t)w->nv * 2 * project_blocks(n) * 4));
+    HIP_TRY(ctx, w->bk.ensure((size_t)std::max<int64_t>(all, 1) * 4));
+    HIP_TRY(ctx, w->bv.ensure((size_t)std::max<int64_t>(all, 1) * 4));
     HIP_TRY(ctx, w->grad2d.ensure(g2));
     HIP_TRY(ctx, hipMemset(w->grad2d.p, 0, g2));  // the backward keeps it all-zero between steps
     w->n = n;
@@ -1319,6 +1350,9 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         w->views_host[v] = V;
         w->cams_host[v] = to_camk(cam);
     }
+    for (int v = 0; v < w->nv; ++v) w->ids_host[v] = state_ptrs(w->state[v].p, w->L[v]).ids;
+    HIP_TRY(ctx, hipMemcpyAsync(w->ids_dev.p, w->ids_host, sizeof(uint32_t *) * w->nv, hipMemcpyHostToDevice,
+                                w->stream));
     HIP_TRY(ctx, hipMemcpyAsync(w->views.p, w->views_host, sizeof(ViewK) * w->nv, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(ctx, hipMemcpyAsync(w->cams_dev.p, w->cams_host, sizeof(CamK) * w->nv, hipMemcpyHostToDevice, w->stream));
     w->table_sig = sig;
@@ -1335,14 +1369,40 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     hipStream_t s = ctx->stream;
     fgs_status st;
     const int64_t n = params.n;
+    // every view's projection into consecutive ranges of the depth-sort buffers
+    const int64_t pb = project_blocks(n), all = (int64_t)w->nv * n;
+    uint32_t *ndev = ctx->words.as<uint32_t>() + W_NDEV;
+    auto proj_out = [&](int v) {
+        return ProjOut{ctx->rect.as<uint2>() + (size_t)v * n, ctx->count.as<uint32_t>() + (size_t)v * n,
+                       w->kpart.as<uint32_t>() + (size_t)v * 2 * pb};
+    };
+    for (int v = 0; v < w->nv; ++v) {
+        const fgs_camera &cam = w->cams[v];
+        const ProjOut po = proj_out(v);
+        Stage st_(ctx, "project");
+        launch_project(to_pk(params), to_camk(cam), to_rk(o, w->tw[v], w->th[v], cam.width, cam.height),
+                       state_ptrs(w->state[v].p, w->L[v]).rec, po.rect, po.count, ctx->dkA.as<uint32_t>() + (size_t)v * n,
+                       ctx->idA.as<uint32_t>() + (size_t)v * n, ndev, kSuperShift, po.kpart, s, (uint32_t)((size_t)v * n));
+    }
+    {
+        // one stable sort of all views' values v n + i by depth, then one pass by view
+        Stage st_(ctx, "depth_sort");
+        launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
+                          ctx->idB.as<uint32_t>(), w->bv.as<uint32_t>(), ndev, all, 32,
+                          sort_ws(ctx, all, kDepthSortPerBlock), s);
+        launch_view_keys(w->bv.as<uint32_t>(), all, n, w->bk.as<uint32_t>(), s);
+        launch_radix_sort(w->bk.as<uint32_t>(), w->bv.as<uint32_t>(), ctx->dkA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
+                          ctx->idB.as<uint32_t>(), ndev, all, key_bits_for(w->nv), sort_ws(ctx, all, kDepthSortPerBlock),
+                          s);
+        launch_split_ids(ctx->idB.as<uint32_t>(), w->nv, n, w->ids_dev.as<uint32_t *>(), s);
+    }
     for (int v = 0; v < w->nv; ++v) {
         const fgs_camera &cam = w->cams[v];
         const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // binning only: no image
-        if ((st = enqueue_forward(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v], nullptr,
-                                  w->hs_dev + 2 * v, false)) != FGS_OK)
+        if ((st = enqueue_bin_raster(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v],
+                                     proj_out(v), nullptr, w->hs_dev + 2 * v, false, nullptr)) != FGS_OK)
             return st;
-    }
-    uint32_t *words = w->words.as<uint32_t>();
+    }    uint32_t *words = w->words.as<uint32_t>();
     {
         Stage st_(ctx, "raster_fwd");
         launch_raster_window(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->total_tiles,
@@ -1450,6 +1510,8 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->step_host, 8, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->views_host, sizeof(ViewK) * n_views, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->cams_host, sizeof(CamK) * n_views, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w->ids_host, sizeof(uint32_t *) * n_views, hipHostMallocDefault);
+    if (e == hipSuccess) e = w->ids_dev.ensure(sizeof(uint32_t *) * n_views);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&w->hs, (size_t)2 * n_views * 4, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
@@ -1470,7 +1532,8 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     window_drop_graph(w);
     for (DBuf &b : w->state) b.release();
-    DBuf *bufs[] = {&w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials};
+    DBuf *bufs[] = {&w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials, &w->kpart, &w->bk, &w->bv,
+                    &w->ids_dev};
     for (DBuf *b : bufs) b->release();
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
@@ -1478,6 +1541,7 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->step_host) (void)hipHostFree(w->step_host);
     if (w->views_host) (void)hipHostFree(w->views_host);
     if (w->cams_host) (void)hipHostFree(w->cams_host);
+    if (w->ids_host) (void)hipHostFree(w->ids_host);
     if (w->hs) (void)hipHostFree(w->hs);
     delete w;
     return FGS_OK;

@@ -109,15 +109,22 @@ int sort_blocks(int64_t cap, int per_block);
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 
-// Projects every gaussian into rec (by id: the forward state's records); writes n to *n_out (the
-// element count of the depth sort). count[i] receives the number of tiles (shift 0) or
-// super-tiles (tile rectangle >> shift) covered, rect[i] the tile rectangle; kpart (2 words per
-// workgroup, project_blocks(n) workgroups) the workgroups' (tile, gaussian) pair and visible
-// gaussian counts, summed by launch_scan_counts.
+// Projects every gaussian into rec (by id: the forward state's records); writes the depth key
+// dkey[i] and ids[i] = id_base + i, and id_base + n to *n_out (the element count of the depth
+// sort: views sorted together are projected into consecutive ranges). count[i] receives the
+// number of tiles (shift 0) or super-tiles (tile rectangle >> shift) covered, rect[i] the tile
+// rectangle; kpart (2 words per workgroup, project_blocks(n) workgroups) the workgroups'
+// (tile, gaussian) pair and visible gaussian counts, summed by launch_scan_counts.
 int64_t project_blocks(int64_t n);
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
-                    uint32_t *kpart, hipStream_t s);
+                    uint32_t *kpart, hipStream_t s, uint32_t id_base = 0);
+
+// Depth order of several views at once: after a stable sort of the nv n values v n + i by depth,
+// keys[j] = vals[j] / n (the view) for one more stable pass; launch_split_ids then hands view v
+// its n ids in depth order: outs[v][r] = vals[v n + r] - v n (outs: device array of nv pointers).
+void launch_view_keys(const uint32_t *vals, int64_t total, int64_t n, uint32_t *keys, hipStream_t s);
+void launch_split_ids(const uint32_t *vals, int nv, int64_t n, uint32_t *const *outs, hipStream_t s);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and

@@ -113,8 +113,7 @@ __device__ inline bool pixel_span(double c, double r, int32_t size, int32_t &lo,
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
-                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-                                int shift, int64_t i);
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i);
 
 // Projects every gaussian (one thread each): record, tile rectangle, count of covered tiles or
 // super-tiles, depth key; kpart[2 b], kpart[2 b + 1] receive block b's number of (tile, gaussian)
@@ -122,13 +121,16 @@ __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart)
+          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart, uint32_t id_base)
 {
     __shared__ uint32_t wsum[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *n_out = (uint32_t)g.n;
+    if (i == 0) *n_out = id_base + (uint32_t)g.n;
     uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian
-    if (i < g.n) tiles = project_one(g, cam, rk, rec, rect, count, dkey, ids, shift, i);
+    if (i < g.n) {
+        tiles = project_one(g, cam, rk, rec, rect, count, dkey, shift, i);
+        ids[i] = id_base + (uint32_t)i;
+    }
     uint32_t vis = tiles != 0u;
     for (int o = 32; o > 0; o >>= 1) {
         tiles += __shfl_xor(tiles, o);
@@ -145,10 +147,8 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
-                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-                                int shift, int64_t i)
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i)
 {
-    ids[i] = (uint32_t)i;
     Proj p;
     project_gaussian(g, i, cam, rk.lowpass, p);
     uint32_t cnt = 0, key = 0xFFFFFFFFu, tiles = 0;
@@ -399,10 +399,10 @@ int64_t project_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
                     uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *kpart,
-                    hipStream_t s)
+                    hipStream_t s, uint32_t id_base)
 {
     hipLaunchKernelGGL(k_project, dim3((unsigned)project_blocks(g.n)), dim3(256), 0, s, g, cam, rk, rec, rect, count,
-                       dkey, ids, n_out, shift, kpart);
+                       dkey, ids, n_out, shift, kpart, id_base);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,

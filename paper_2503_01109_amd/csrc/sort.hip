@@ -548,6 +548,21 @@ k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, 
     ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t), lower_bound_u32(keys, K, (uint32_t)t + 1));
 }
 
+__global__ void k_view_keys(const uint32_t *__restrict__ vals, int64_t total, uint32_t n, uint32_t *__restrict__ keys)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x)
+        keys[j] = vals[j] / n;
+}
+
+__global__ void k_split_ids(const uint32_t *__restrict__ vals, int nv, uint32_t n, uint32_t *const *__restrict__ outs)
+{
+    const int v = blockIdx.y;
+    uint32_t *out = outs[v];
+    const uint32_t base = (uint32_t)v * n;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        out[r] = vals[base + r] - base;
+}
+
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -570,6 +585,19 @@ static unsigned grid_for(int64_t n, int per_block, unsigned max_blocks)
     if (b < 1) b = 1;
     if (b > max_blocks) b = max_blocks;
     return (unsigned)b;
+}
+
+void launch_view_keys(const uint32_t *vals, int64_t total, int64_t n, uint32_t *keys, hipStream_t s)
+{
+    if (total <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_view_keys, dim3(grid_for(total, 1024, 4096)), dim3(256), 0, s, vals, total, (uint32_t)n, keys);
+}
+
+void launch_split_ids(const uint32_t *vals, int nv, int64_t n, uint32_t *const *outs, hipStream_t s)
+{
+    if (nv <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_split_ids, dim3(grid_for(n, 1024, 1024), (unsigned)nv), dim3(256), 0, s, vals, nv, (uint32_t)n,
+                       outs);
 }
 
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
