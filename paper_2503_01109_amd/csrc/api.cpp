@@ -1385,14 +1385,15 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                        ctx->idA.as<uint32_t>() + (size_t)v * n, ndev, kSuperShift, po.kpart, s, (uint32_t)((size_t)v * n));
     }
     {
-        // one stable sort of all views' values v n + i by depth, then one pass by view
+        // one stable sort of all views' values v n + i by depth, then one pass by view (2,048 keys
+        // per workgroup: measured faster than 512 or 1,024 at 4M keys)
         Stage st_(ctx, "depth_sort");
         launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
                           ctx->idB.as<uint32_t>(), w->bv.as<uint32_t>(), ndev, all, 32,
-                          sort_ws(ctx, all, kDepthSortPerBlock), s);
+                          sort_ws(ctx, all, kPairSortPerBlock), s);
         launch_view_keys(w->bv.as<uint32_t>(), all, n, w->bk.as<uint32_t>(), s);
         launch_radix_sort(w->bk.as<uint32_t>(), w->bv.as<uint32_t>(), ctx->dkA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), ndev, all, key_bits_for(w->nv), sort_ws(ctx, all, kDepthSortPerBlock),
+                          ctx->idB.as<uint32_t>(), ndev, all, key_bits_for(w->nv), sort_ws(ctx, all, kPairSortPerBlock),
                           s);
         launch_split_ids(ctx->idB.as<uint32_t>(), w->nv, n, w->ids_dev.as<uint32_t *>(), s);
     }
