@@ -16,7 +16,8 @@
 // recovering T_i = T_{i+1}/(1 - alpha_i). The colour, depth and opacity terms behind a pair enter
 // its opacity gradient only through one running sum per pixel, S = sum over later pairs of
 // w_j (dL/dC . c_j + dL/dD d_j) plus the background's and the opacity output's share. Each pair
-// yields 10 gradient terms; they are summed over the wave by a transposed butterfly, over the
+// yields 10 terms (the colour, depth and opacity gradients and five moments from which the mean
+// and conic gradients follow); they are summed over the wave by a transposed butterfly, over the
 // workgroup's waves with LDS float atomics, and reach HBM as FP32 atomics into the gaussian's
 // 64-byte gradient record, one wave instruction covering four (tile, gaussian) entries.
 //
@@ -29,10 +30,9 @@ namespace fgs {
 
 namespace {
 
-// s = -log2(e)/2 scales the staged conic; -2/s = 4 ln 2 turns the scaled form's derivative back
-// into the gradient of the 2D mean.
+// s = -log2(e)/2 scales the staged conic; 1/s = -2 ln 2 recovers the conic from it.
 constexpr float kConicScale = -0.721347520444481703680f;
-constexpr float kMeanGradScale = 2.772588722239781237669f;
+constexpr float kInvConicScale = -1.386294361119890618834f;
 
 __device__ __forceinline__ float sgn(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
 
@@ -371,9 +371,8 @@ __device__ __forceinline__ BwdPair bwd_decide(const float4 &a4, const float4 &b4
     return p;
 }
 
-__device__ __forceinline__ void bwd_grad(const BwdPair &p, const float4 &a4, const float4 &b4, const float4 &c4,
-                                         const RasterK &rk, float gC0, float gC1, float gC2, float gD, float &T,
-                                         float &S, float g[10])
+__device__ __forceinline__ void bwd_grad(const BwdPair &p, const float4 &b4, const float4 &c4, const RasterK &rk,
+                                         float gC0, float gC1, float gC2, float gD, float &T, float &S, float g[10])
 {
     const PairEval &e = p.e;
     const float alpha = p.alpha;
@@ -393,16 +392,18 @@ __device__ __forceinline__ void bwd_grad(const BwdPair &p, const float4 &a4, con
     g[8] = gC2 * w;
     g[9] = gD * w;
     g[5] = dalg * e.G;  // d alpha / d opacity = G
-    // dL/dQ = -alpha dL/dalpha / 2; the mean gradient is -2 dL/dQ (a dx + b dy, b dx + c dy)
-    // = dL/dQ (-2/s) (s a dx + s b dy, ...), from the scaled products of the forward form
-    const float dQ = -0.5f * (alpha * dalg);
-    const float km = kMeanGradScale * dQ;
-    g[0] = km * __builtin_fmaf(a4.w, e.dy, e.Adx);
-    g[1] = km * (e.Bdx + e.Cdy);
-    const float dQdx = dQ * e.dx;
-    g[2] = dQdx * e.dx;
-    g[3] = 2.0f * (dQdx * e.dy);
-    g[4] = (dQ * e.dy) * e.dy;
+    // With e = alpha dL/dalpha, dL/dQ = -e/2, so the conic gradient is -(1/2) (e dx^2, 2 e dx dy,
+    // e dy^2) and the mean gradient -2 dL/dQ (a dx + b dy, b dx + c dy) = (a e dx + b e dy, ...):
+    // both are linear in the moments e dx, e dy, e dx^2, e dx dy, e dy^2 with coefficients of the
+    // gaussian alone. The pairs leave those moments (slots 0-4), summed over the pixels; the
+    // flush applies the coefficients once per (tile, gaussian).
+    const float ea = alpha * dalg;
+    const float edx = ea * e.dx, edy = ea * e.dy;
+    g[0] = edx;
+    g[1] = edy;
+    g[2] = edx * e.dx;
+    g[3] = edx * e.dy;
+    g[4] = edy * e.dy;
 }
 
 // Backward of one tile of one view (NT threads, one pixel each).
@@ -496,8 +497,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             const uint64_t any0 = __ballot(p0.take), any1 = __ballot(p1.take);
             if (!(any0 | any1)) continue;  // no lane blended either entry: nothing to add or update
             float g0[10], g1[10];
-            bwd_grad(p0, a0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
-            bwd_grad(p1, a1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
+            bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
+            bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
             const float t0 = reduce10(g0, lane), t1 = reduce10(g1, lane);
             if (red_lane) {
                 if (any0) atomicAdd(&sacc[k0][term], t0);
@@ -510,7 +511,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
             if (__ballot(p0.take)) {
                 float g0[10];
-                bwd_grad(p0, a0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
+                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
                 const float t0 = reduce10(g0, lane);
                 if (red_lane) atomicAdd(&sacc[k0][term], t0);
             }
@@ -522,11 +523,15 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         for (int e = tid >> 4; e < cnt; e += NT >> 4) {
             const int c = tid & 15;
             if (c < 10) {
-                const float v = sacc[e][c];
-                if (v != 0.0f) {
-                    unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + c], v);
-                    sacc[e][c] = 0.0f;
-                }
+                // moments to gradients (see bwd_grad): the staged conic is s (a, b, c)
+                const float raw = sacc[e][c], m0 = sacc[e][0], m1 = sacc[e][1];
+                float v = raw;
+                if (c == 0) v = (sa[e].z * m0 + sa[e].w * m1) * kInvConicScale;
+                else if (c == 1) v = (sa[e].w * m0 + sb[e].x * m1) * kInvConicScale;
+                else if (c == 3) v = -raw;
+                else if (c == 2 || c == 4) v = -0.5f * raw;
+                if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + c], v);
+                if (raw != 0.0f) sacc[e][c] = 0.0f;
             }
         }
     }
