@@ -199,8 +199,9 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 // Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
-// tile_w x tile_h = NT pixels). COUNT: accumulate the profiling work counters.
-template <int NT, bool COUNT>
+// tile_w x tile_h = NT pixels). COUNT: accumulate the profiling work counters; NCON: count each
+// pixel's blended pairs (for the n_contrib output; implied by COUNT).
+template <int NT, bool COUNT, bool NCON = COUNT>
 __device__ void tile_fwd(const ViewK &V, int tile)
 {
     constexpr int NW = NT / kWave;
@@ -272,7 +273,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             T = blend ? Tn : T;
             done = done || stop;
             if (COUNT) ntest += near ? 1u : 0u;
-            ncon += blend ? 1 : 0;
+            if (COUNT || NCON) ncon += blend ? 1 : 0;
             last = blend ? base + k : last;
         }
     }
@@ -538,8 +539,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     __syncthreads();  // LDS is restaged by the next tile of a persistent workgroup
 }
 
-template <int NT, bool COUNT>
-__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT>(V, blockIdx.x); }
+template <int NT, bool COUNT, bool NCON>
+__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT, NCON>(V, blockIdx.x); }
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT>(V, blockIdx.x); }
@@ -604,19 +605,21 @@ static ViewK view_of_args(const RasterK &rk, int32_t W, int32_t H, const Rec *re
     return V;
 }
 
+template <bool COUNT, bool NCON>
+static void launch_fwd_variant(const ViewK &V, unsigned tiles, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, COUNT, NCON>), dim3(tiles), dim3(256), 0, s, V);
+    else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, COUNT, NCON>), dim3(tiles), dim3(512), 0, s, V);
+    else hipLaunchKernelGGL((k_raster_fwd<64, COUNT, NCON>), dim3(tiles), dim3(64), 0, s, V);
+}
+
 static void launch_fwd_view(const ViewK &V, hipStream_t s)
 {
     const unsigned tiles = (unsigned)tile_items(V.rk.tiles_x, V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
-    if (V.counts) {
-        if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, true>), dim3(tiles), dim3(256), 0, s, V);
-        else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, true>), dim3(tiles), dim3(512), 0, s, V);
-        else hipLaunchKernelGGL((k_raster_fwd<64, true>), dim3(tiles), dim3(64), 0, s, V);
-    } else {
-        if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, false>), dim3(tiles), dim3(256), 0, s, V);
-        else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, false>), dim3(tiles), dim3(512), 0, s, V);
-        else hipLaunchKernelGGL((k_raster_fwd<64, false>), dim3(tiles), dim3(64), 0, s, V);
-    }
+    if (V.counts) launch_fwd_variant<true, true>(V, tiles, nt, s);
+    else if (V.img.n_contrib) launch_fwd_variant<false, true>(V, tiles, nt, s);
+    else launch_fwd_variant<false, false>(V, tiles, nt, s);
 }
 
 static void launch_bwd_view(const ViewK &V, hipStream_t s)
