@@ -574,15 +574,23 @@ k_raster_queue(const ViewK *__restrict__ views, int nv, uint32_t total, uint32_t
     }
 }
 
-// The same items with one workgroup each (grid = total).
-template <bool FWD, bool COUNT>
-__global__ void __launch_bounds__(256)
-k_raster_items(const ViewK *__restrict__ views, int nv)
+// The same items with one workgroup each (grid = total). The forward is held to 64 VGPRs (eight
+// waves per SIMD), as the single-view forward compiles to by itself.
+template <bool COUNT>
+__global__ void __launch_bounds__(256, 8)
+k_raster_items_fwd(const ViewK *__restrict__ views, int nv)
 {
     const uint32_t g = blockIdx.x;
     const ViewK V = views[view_of(views, nv, g)];
-    if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
-    else tile_bwd<256>(V, (int)(g - V.tile_base));
+    tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
+}
+
+__global__ void __launch_bounds__(256)
+k_raster_items_bwd(const ViewK *__restrict__ views, int nv)
+{
+    const uint32_t g = blockIdx.x;
+    const ViewK V = views[view_of(views, nv, g)];
+    tile_bwd<256>(V, (int)(g - V.tile_base));
 }
 
 }  // namespace
@@ -669,9 +677,9 @@ void launch_raster_window(bool fwd, bool count, const ViewK *views_dev, int nv, 
     if (total == 0) return;
     if (blocks <= 0) {
         const dim3 grid(total);
-        if (fwd && count) hipLaunchKernelGGL((k_raster_items<true, true>), grid, dim3(256), 0, s, views_dev, nv);
-        else if (fwd) hipLaunchKernelGGL((k_raster_items<true, false>), grid, dim3(256), 0, s, views_dev, nv);
-        else hipLaunchKernelGGL((k_raster_items<false, false>), grid, dim3(256), 0, s, views_dev, nv);
+        if (fwd && count) hipLaunchKernelGGL((k_raster_items_fwd<true>), grid, dim3(256), 0, s, views_dev, nv);
+        else if (fwd) hipLaunchKernelGGL((k_raster_items_fwd<false>), grid, dim3(256), 0, s, views_dev, nv);
+        else hipLaunchKernelGGL(k_raster_items_bwd, grid, dim3(256), 0, s, views_dev, nv);
         return;
     }
     launch_zero_u32(counter, 1, s);
