@@ -33,8 +33,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "fbb174c512b2a4644e881d153db7ced57816b9a4207d71ab9783a41d2a852d9f",
-                     "tile": "16x16", "fetch_bytes": 46997496, "write_bytes": 16498761},
+    "k_raster_bwd": {"source_sha256": "e934b11e2982b06ce2e5c8aff104741ef7acc1a2e5d92192e5d262a2caa98fa9",
+                     "tile": "16x16", "fetch_bytes": 46723300, "write_bytes": 16498761},
 }
 
 
@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--window-only", action="store_true",
+                    help="only run the 8-view keyframe window measurement (tuning, timed graph replays, "
+                         "profiled steps), print its JSON object and exit")
     return ap.parse_args()
 
 
@@ -173,7 +176,7 @@ def window_extra(F, ctx, steps: int = 20) -> dict:
             "views_per_s": round(8e3 / ms, 2), "graph": True,
             "tiles": [f"{a}x{b}" for a, b in tune["tiles"]], "blocks_per_cu": tune["blocks_per_cu"],
             "tuning_ms": {k: round(v, 4) for k, v in tune["ms"].items()},
-            "roofline": raster_roofline(rep, counts, "k_raster_queue_")}
+            "roofline": raster_roofline(rep, counts, "k_raster_items_" if tune["blocks_per_cu"] == 0 else "k_raster_queue_")}
 
 
 def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
@@ -228,6 +231,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.window_only:
+        print(json.dumps(window_extra(F, F.Context())), flush=True)
+        return
     if args.copy_calib:
         x = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
