@@ -1214,10 +1214,11 @@ struct fgs_window {
     std::vector<uint32_t> tile_base;
     uint32_t total_tiles = 0;
     DBuf dl, grad2d, views, cams_dev, words, partials;
-    // all views' depth orders in one sort: per-view pair counts of the projection, the view keys
-    // and sorted values of the last pass, and the device table of the views' id arrays
-    DBuf kpart, bk, bv, ids_dev;
-    uint32_t **ids_host = nullptr;  // pinned staging of ids_dev
+    // all views binned at once: the projection's per-workgroup pair counts of every view, the
+    // views' key tables (x: super-tiles per row, y: first super-tile), every super-tile's
+    // coordinates in its view, and the tile ranges (by window item) and tile lists of all views
+    DBuf kpart, bintab, wranges, wvals;
+    int64_t nsup_all = 0, cap_all = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -1228,7 +1229,7 @@ struct fgs_window {
     CamK *cams_host = nullptr;
     int64_t *step_host = nullptr;      // pinned staging of the device Adam step counter
     int64_t dev_step = -1;             // value of the device counter once enqueued work is done
-    uint32_t *hs = nullptr, *hs_dev = nullptr;  // host-mapped: [2v] pairs, [2v+1] overflow of view v
+    uint32_t *hs = nullptr, *hs_dev = nullptr;  // host-mapped: [0] pairs of all views, [1] overflow
 };
 
 namespace {
@@ -1277,18 +1278,20 @@ fgs_status window_size(fgs_window *w, const fgs_gaussians &params, const fgs_ren
         state_layout(n, cam.width, cam.height, w->tw[v], w->th[v], w->cap[v], &w->L[v]);
         HIP_TRY(ctx, w->state[v].ensure(w->L[v].bytes));
     }
-    int64_t capmax = 0;
-    for (int v = 0; v < w->nv; ++v) capmax = std::max(capmax, w->cap[v]);
-    // the context's depth-sort buffers hold every view's keys at once
+    // the context's sort and binning buffers hold every view's gaussians and pairs at once
+    int64_t capsum = 0;
+    for (int v = 0; v < w->nv; ++v) capsum += w->cap[v];
+    w->cap_all = std::max(w->cap_all, capsum);
     const int64_t all = (int64_t)w->nv * n;
-    if (all >= ((int64_t)1 << 31))
-        return fail(ctx, FGS_ERR_UNSUPPORTED, "fgs_window_step: views x gaussians = %lld exceeds 2^31", (long long)all);
-    if ((st = ensure_ws(ctx, std::max<int64_t>(all, w->total_tiles), capmax)) != FGS_OK) return st;
+    if (all >= ((int64_t)1 << 31) || w->cap_all >= ((int64_t)1 << 32) - 1)
+        return fail(ctx, FGS_ERR_UNSUPPORTED, "fgs_window_step: views x gaussians = %lld or pairs = %lld too many",
+                    (long long)all, (long long)w->cap_all);
+    if ((st = ensure_ws(ctx, std::max<int64_t>(all, w->total_tiles), w->cap_all)) != FGS_OK) return st;
+    if ((st = ensure_bin(ctx, w->nsup_all, w->total_tiles, w->cap_all)) != FGS_OK) return st;
     const size_t g2 = (size_t)w->nv * kG2Stride * (size_t)(n > 0 ? n : 1) * 4;
     HIP_TRY(ctx, hipStreamSynchronize(w->stream));
     HIP_TRY(ctx, w->kpart.ensure((size_t)w->nv * 2 * project_blocks(n) * 4));
-    HIP_TRY(ctx, w->bk.ensure((size_t)std::max<int64_t>(all, 1) * 4));
-    HIP_TRY(ctx, w->bv.ensure((size_t)std::max<int64_t>(all, 1) * 4));
+    HIP_TRY(ctx, w->wvals.ensure((size_t)std::max<int64_t>(w->cap_all, 1) * 4));
     HIP_TRY(ctx, w->grad2d.ensure(g2));
     HIP_TRY(ctx, hipMemset(w->grad2d.p, 0, g2));  // the backward keeps it all-zero between steps
     w->n = n;
@@ -1328,8 +1331,8 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         V.W = cam.width;
         V.H = cam.height;
         V.rec = sp.rec;
-        V.vals = sp.vals;
-        V.ranges = sp.ranges;
+        V.vals = w->wvals.as<uint32_t>();
+        V.ranges = w->wranges.as<uint2>() + w->tile_base[v];
         V.last = sp.last;
         V.tfinal = sp.tfinal;
         V.img = ImageK{nullptr, nullptr, nullptr, nullptr, nullptr};  // only the fused loss reads the image
@@ -1350,9 +1353,6 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         w->views_host[v] = V;
         w->cams_host[v] = to_camk(cam);
     }
-    for (int v = 0; v < w->nv; ++v) w->ids_host[v] = state_ptrs(w->state[v].p, w->L[v]).ids;
-    HIP_TRY(ctx, hipMemcpyAsync(w->ids_dev.p, w->ids_host, sizeof(uint32_t *) * w->nv, hipMemcpyHostToDevice,
-                                w->stream));
     HIP_TRY(ctx, hipMemcpyAsync(w->views.p, w->views_host, sizeof(ViewK) * w->nv, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(ctx, hipMemcpyAsync(w->cams_dev.p, w->cams_host, sizeof(CamK) * w->nv, hipMemcpyHostToDevice, w->stream));
     w->table_sig = sig;
@@ -1385,25 +1385,50 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                        ctx->idA.as<uint32_t>() + (size_t)v * n, ndev, kSuperShift, po.kpart, s, (uint32_t)((size_t)v * n));
     }
     {
-        // one stable sort of all views' values v n + i by depth, then one pass by view (2,048 keys
-        // per workgroup: measured faster than 512 or 1,024 at 4M keys)
+        // one stable sort of all views' values v n + i by depth (2,048 keys per workgroup: measured
+        // faster than 512 or 1,024 at 4M keys)
         Stage st_(ctx, "depth_sort");
+        // (four passes: the last one writes its values to idA, as it would without v_final)
         launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), w->bv.as<uint32_t>(), ndev, all, 32,
+                          ctx->idB.as<uint32_t>(), ctx->idA.as<uint32_t>(), ndev, all, 32,
                           sort_ws(ctx, all, kPairSortPerBlock), s);
-        launch_view_keys(w->bv.as<uint32_t>(), all, n, w->bk.as<uint32_t>(), s);
-        launch_radix_sort(w->bk.as<uint32_t>(), w->bv.as<uint32_t>(), ctx->dkA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), ndev, all, key_bits_for(w->nv), sort_ws(ctx, all, kPairSortPerBlock),
-                          s);
-        launch_split_ids(ctx->idB.as<uint32_t>(), w->nv, n, w->ids_dev.as<uint32_t *>(), s);
     }
-    for (int v = 0; v < w->nv; ++v) {
-        const fgs_camera &cam = w->cams[v];
-        const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // binning only: no image
-        if ((st = enqueue_bin_raster(ctx, params, cam, o, w->tw[v], w->th[v], img, w->state[v].p, w->L[v],
-                                     proj_out(v), nullptr, w->hs_dev + 2 * v, false, nullptr)) != FGS_OK)
-            return st;
-    }    uint32_t *words = w->words.as<uint32_t>();
+    {
+        // All views binned at once: the pairs of one super-tile come from one view, so the depth
+        // order of all views' values, kept by the stable super-tile sort, is each view's depth order.
+        uint32_t *cw = ctx->words.as<uint32_t>();
+        const uint2 *view_tab = w->bintab.as<uint2>();
+        const uint32_t *super_xy = (const uint32_t *)(view_tab + w->nv);
+        const int nsup = (int)w->nsup_all, sbits = key_bits_for(nsup);
+        uint32_t *svals = (sbits + 7) / 8 == 1 ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
+        const BinWS bw = bin_ws(ctx);
+        {
+            Stage st_(ctx, "bin");
+            launch_scan_counts(ctx->idA.as<uint32_t>(), ctx->count.as<uint32_t>(), all, ctx->blocksums.as<uint32_t>(),
+                               status_words(ctx), w->kpart.as<uint32_t>(), (int64_t)w->nv * pb, cw + W_KTOTAL, s);
+            launch_emit(ctx->idA.as<uint32_t>(), ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(),
+                        ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), all, 0, kSuperShift, w->cap_all,
+                        ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(),
+                        ctx->start_rank.as<uint32_t>(), status_words(ctx), cw + W_NSUP, nullptr, s, view_tab,
+                        (uint32_t)n);
+        }
+        {
+            Stage st_(ctx, "tile_sort");
+            const SortWS sws = sort_ws(ctx, w->cap_all);
+            uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
+                                               ctx->pkB.as<uint32_t>(), ctx->pvB.as<uint32_t>(), svals, cw + W_NSUP,
+                                               w->cap_all, sbits, sws, s);
+            const bool one_pass = sbits <= 8;
+            if (!one_pass) launch_ranges(keys, cw + W_NSUP, w->cap_all, ctx->bin_sranges.as<uint2>(), nsup, s);
+            launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr,
+                              ctx->rect.as<uint2>(), 0, nsup, s, super_xy);
+            launch_bin_tiles(bw, 0, nsup, 0, 0, w->cap_all, cw + W_KTOTAL, w->wranges.as<uint2>(), status_words(ctx),
+                             cw + W_NPAIRS, w->hs_dev, s);
+            launch_bin_place(bw, svals, ctx->bin_sranges.as<uint2>(), ctx->rect.as<uint2>(), 0, 0, 0,
+                             w->wranges.as<uint2>(), w->wvals.as<uint32_t>(), s, super_xy, (uint32_t)n);
+        }
+    }
+    uint32_t *words = w->words.as<uint32_t>();
     {
         Stage st_(ctx, "raster_fwd");
         launch_raster_window(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->total_tiles,
@@ -1487,6 +1512,17 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: too many tiles in the window", w_);
     }
     w->total_tiles = (uint32_t)tb;
+    // key table of the joint binning: view v's super-tiles follow those of the views before it
+    std::vector<uint32_t> bintab(2 * (size_t)n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const int sx = supers_for((cams[v].width + w->tw[v] - 1) / w->tw[v]);
+        const int sy = supers_for((cams[v].height + w->th[v] - 1) / w->th[v]);
+        bintab[2 * v] = (uint32_t)sx;
+        bintab[2 * v + 1] = (uint32_t)w->nsup_all;
+        for (int y = 0; y < sy; ++y)
+            for (int x = 0; x < sx; ++x) bintab.push_back((uint32_t)x | (uint32_t)y << 16);
+        w->nsup_all += (int64_t)sx * sy;
+    }
     w->cap.assign(n_views, 0);
     w->L.resize(n_views);
     w->state.resize(n_views);
@@ -1511,12 +1547,13 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->step_host, 8, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->views_host, sizeof(ViewK) * n_views, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w->cams_host, sizeof(CamK) * n_views, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&w->ids_host, sizeof(uint32_t *) * n_views, hipHostMallocDefault);
-    if (e == hipSuccess) e = w->ids_dev.ensure(sizeof(uint32_t *) * n_views);
+    if (e == hipSuccess) e = w->bintab.ensure(bintab.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(w->bintab.p, bintab.data(), bintab.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = w->wranges.ensure((size_t)w->total_tiles * 8);
     if (e == hipSuccess)
-        e = hipHostMalloc((void **)&w->hs, (size_t)2 * n_views * 4, hipHostMallocMapped | hipHostMallocCoherent);
+        e = hipHostMalloc((void **)&w->hs, 2 * 4, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
-        memset(w->hs, 0, (size_t)2 * n_views * 4);
+        memset(w->hs, 0, 2 * 4);
         e = hipHostGetDevicePointer((void **)&w->hs_dev, w->hs, 0);
     }
     if (e != hipSuccess) {
@@ -1533,8 +1570,8 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     window_drop_graph(w);
     for (DBuf &b : w->state) b.release();
-    DBuf *bufs[] = {&w->dl, &w->grad2d, &w->views, &w->cams_dev, &w->words, &w->partials, &w->kpart, &w->bk, &w->bv,
-                    &w->ids_dev};
+    DBuf *bufs[] = {&w->dl,       &w->grad2d, &w->views,   &w->cams_dev, &w->words,
+                    &w->partials, &w->kpart,  &w->bintab, &w->wranges,  &w->wvals};
     for (DBuf *b : bufs) b->release();
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
@@ -1542,7 +1579,6 @@ fgs_status fgs_window_destroy(fgs_window *w)
     if (w->step_host) (void)hipHostFree(w->step_host);
     if (w->views_host) (void)hipHostFree(w->views_host);
     if (w->cams_host) (void)hipHostFree(w->cams_host);
-    if (w->ids_host) (void)hipHostFree(w->ids_host);
     if (w->hs) (void)hipHostFree(w->hs);
     delete w;
     return FGS_OK;
@@ -1570,34 +1606,22 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
         if ((st = check_gauss(ctx, grad_out, w_, "grad_out")) != FGS_OK) return st;
         if (grad_out->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad_out.n != params.n", w_);
     }
-    // a step already run that outgrew views' states: its result is void; grow them and report once
-    {
-        int64_t worst = 0;
-        int worst_v = -1;
-        bool any = false;
-        for (int v = 0; v < w->nv; ++v) any |= ((volatile uint32_t *)w->hs)[2 * v + 1] != 0;
-        if (any) HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // every view's flag is final now
-        for (int v = 0; v < w->nv; ++v) {
-            volatile uint32_t *hs = w->hs + 2 * v;
-            if (!hs[1]) continue;
-            const int64_t K = hs[0];
-            hs[0] = 0;
-            hs[1] = 0;
-            w->cap[v] = std::max<int64_t>(w->cap[v], K + K / 2 + 1024);
-            if (K > worst) {
-                worst = K;
-                worst_v = v;
-            }
-        }
-        if (worst_v >= 0) {
-            // the context's own overflow word saw the same events; this report replaces it
-            HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, w->stream));
-            HIP_TRY(ctx, hipStreamSynchronize(w->stream));
-            w->n = -1;  // the next step resizes
-            return fail(ctx, FGS_ERR_CAPACITY,
-                        "%s: an earlier step needed %lld pairs in view %d; the window has grown, repeat that step", w_,
-                        (long long)worst, worst_v);
-        }
+    // a step already run that outgrew the window's pair capacity: its result is void; grow it and
+    // report once
+    if (((volatile uint32_t *)w->hs)[1]) {
+        HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // the flag and count are final now
+        volatile uint32_t *hs = w->hs;
+        const int64_t K = hs[0];
+        hs[0] = 0;
+        hs[1] = 0;
+        w->cap_all = std::max<int64_t>(w->cap_all, K + K / 2 + 1024);
+        // the context's own overflow word saw the same event; this report replaces it
+        HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, w->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+        w->n = -1;  // the next step resizes
+        return fail(ctx, FGS_ERR_CAPACITY,
+                    "%s: an earlier step needed %lld pairs over its views; the window has grown, repeat that step", w_,
+                    (long long)K);
     }
     hipStream_t user = ctx->stream;
     HIP_TRY(ctx, hipEventRecord(w->ev_in, user));

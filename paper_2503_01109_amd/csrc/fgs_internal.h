@@ -120,12 +120,6 @@ void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *r
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
                     uint32_t *kpart, hipStream_t s, uint32_t id_base = 0);
 
-// Depth order of several views at once: after a stable sort of the nv n values v n + i by depth,
-// keys[j] = vals[j] / n (the view) for one more stable pass; launch_split_ids then hands view v
-// its n ids in depth order: outs[v][r] = vals[v n + r] - v n (outs: device array of nv pointers).
-void launch_view_keys(const uint32_t *vals, int64_t total, int64_t n, uint32_t *keys, hipStream_t s);
-void launch_split_ids(const uint32_t *vals, int nv, int64_t n, uint32_t *const *outs, hipStream_t s);
-
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
 // (kb, vb); the last pass writes the values to v_final and the keys to the returned buffer.
@@ -142,7 +136,9 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
                         uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s);
 
 // Emit one (key, gaussian id) pair per covered tile in depth order; with shift > 0 the keys are
-// super-tiles (tile rectangle >> shift, keys_x super-tiles per row). offsets is scratch of n + 1
+// super-tiles (tile rectangle >> shift, keys_x super-tiles per row). Several views binned at once
+// (view_tab non-null): ids are values v view_n + i, and view v's keys are view_tab[v].y + its own
+// key with view_tab[v].x keys per row (keys_x unused). offsets is scratch of n + 1
 // words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
 // (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
@@ -151,7 +147,7 @@ int64_t emit_chunks(int64_t cap);
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
-                 uint32_t *host_status, hipStream_t s);
+                 uint32_t *host_status, hipStream_t s, const uint2 *view_tab = nullptr, uint32_t view_n = 0);
 
 // Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
 // are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by super-tile
@@ -161,6 +157,9 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
 //                      overflow);
 //   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
+// Super-tile s lies at (s % supers_x, s / supers_x), or with super_xy non-null at
+// (super_xy[s] & 0xFFFF, super_xy[s] >> 16): the super-tiles of several views numbered one after
+// another, whose entries are view-offset values (view_n > 0) that the lists receive as id % view_n.
 struct BinWS {
     uint32_t *cstart;      // nsup + 1
     uint32_t *csuper;      // max_chunks
@@ -174,12 +173,14 @@ int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 // digit_totals (nullable): the per-digit totals of a single-pass super-tile sort, from which the
 // super-tile ranges are written into sranges; else sranges holds them already.
 void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect, int supers_x, int nsup, hipStream_t s);
+                       const uint2 *rect, int supers_x, int nsup, hipStream_t s,
+                       const uint32_t *super_xy = nullptr);
 void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
                       const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
                       uint32_t *host_status, hipStream_t s);
 void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect,
-                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s);
+                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s,
+                      const uint32_t *super_xy = nullptr, uint32_t view_n = 0);
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
                    int64_t T, hipStream_t s);

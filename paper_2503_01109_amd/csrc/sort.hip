@@ -254,7 +254,8 @@ constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion 
 // row-major order; each pair carries the gaussian's id.
 __global__ void __launch_bounds__(kSortThreads)
 k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, const uint32_t *__restrict__ offsets,
-       const uint32_t *__restrict__ start_rank, int64_t n, int32_t tiles_x, int shift, int64_t cap, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+       const uint32_t *__restrict__ start_rank, int64_t n, int32_t tiles_x, int shift, int64_t cap,
+       const uint2 *__restrict__ view_tab, uint32_t view_n, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
        uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev, uint32_t *__restrict__ host_status)
 {
     __shared__ uint32_t soff[kEmitSpan];
@@ -286,8 +287,11 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
             const uint32_t tx0 = (rc.x & 0xFFFFu) >> shift, tx1 = (rc.x >> 16) >> shift, ty0 = (rc.y & 0xFFFFu) >> shift;
             const uint32_t w = tx1 - tx0 + 1;
             const uint32_t dy = idx / w;
-            keys[j] = (ty0 + dy) * (uint32_t)tiles_x + tx0 + (idx - dy * w);
-            vals[j] = ids[r];
+            const uint32_t id = ids[r];
+            // several views: the value is v view_n + id, keys count on from the view's first key
+            const uint2 vt = view_tab ? view_tab[id / view_n] : make_uint2((uint32_t)tiles_x, 0u);
+            keys[j] = vt.y + (ty0 + dy) * vt.x + tx0 + (idx - dy * w);
+            vals[j] = id;
         }
         __syncthreads();
     }
@@ -372,20 +376,30 @@ __device__ inline uint32_t cover_bits(uint2 rc, int sx, int sy)
 }
 
 struct ChunkSpan {
-    uint32_t e0, e1;
+    uint32_t e0, e1, s;
     int sx, sy;
 };
 
+// Chunk c's entries [e0, e1) of super-tile s at super-tile coordinates (sx, sy): from s and
+// supers_x for one view, or from super_xy[s] (x | y << 16) when the super-tiles of several views
+// are numbered one after another.
 __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const uint32_t *cstart,
-                                       const uint32_t *csuper, int supers_x)
+                                       const uint32_t *csuper, int supers_x, const uint32_t *super_xy)
 {
     const uint32_t sidx = csuper[c];
     const uint2 r = sranges[sidx];
     ChunkSpan cs;
+    cs.s = sidx;
     cs.e0 = r.x + (c - cstart[sidx]) * kBinChunk;
     cs.e1 = min(cs.e0 + kBinChunk, r.y);
-    cs.sx = (int)(sidx % (uint32_t)supers_x);
-    cs.sy = (int)(sidx / (uint32_t)supers_x);
+    if (super_xy) {
+        const uint32_t xy = super_xy[sidx];
+        cs.sx = (int)(xy & 0xFFFFu);
+        cs.sy = (int)(xy >> 16);
+    } else {
+        cs.sx = (int)(sidx % (uint32_t)supers_x);
+        cs.sy = (int)(sidx / (uint32_t)supers_x);
+    }
     return cs;
 }
 
@@ -393,12 +407,13 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect, int supers_x, uint32_t *__restrict__ chist)
+            const uint2 *__restrict__ rect, int supers_x, const uint32_t *__restrict__ super_xy,
+            uint32_t *__restrict__ chist)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
     const uint32_t c = blockIdx.x;
     if (c >= *nchunks) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x);
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x, super_xy);
     if (threadIdx.x < kSuper * kSuper) cnt[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
@@ -477,11 +492,12 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, cons
     }
 }
 
-// Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order.
+// Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order
+// (view_n > 0: entries are view-offset values v view_n + id; the lists get id).
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect, int supers_x, int tiles_x, int tiles_y,
+            const uint2 *__restrict__ rect, int supers_x, const uint32_t *__restrict__ super_xy, uint32_t view_n,
             const uint32_t *__restrict__ chist, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok,
             uint32_t *__restrict__ vals)
 {
@@ -490,9 +506,9 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     __shared__ uint32_t wtot[NW][NB];
     const uint32_t c = blockIdx.x;
     if (c >= *nchunks || !*ok) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x);
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x, super_xy);
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
-    if (tid < NB) run[tid] = ranges[(size_t)(cs.sy * supers_x + cs.sx) * NB + tid].x + chist[(size_t)c * NB + tid];
+    if (tid < NB) run[tid] = ranges[(size_t)cs.s * NB + tid].x + chist[(size_t)c * NB + tid];
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
         const uint32_t e = base + tid;
@@ -512,7 +528,7 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
                 if ((m >> b) & 1u) {
                     uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
                     for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
-                    vals[pos] = id;
+                    vals[pos] = view_n ? id % view_n : id;  // the id within its view
                 }
             }
         }
@@ -548,21 +564,6 @@ k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, 
     ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t), lower_bound_u32(keys, K, (uint32_t)t + 1));
 }
 
-__global__ void k_view_keys(const uint32_t *__restrict__ vals, int64_t total, uint32_t n, uint32_t *__restrict__ keys)
-{
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x)
-        keys[j] = vals[j] / n;
-}
-
-__global__ void k_split_ids(const uint32_t *__restrict__ vals, int nv, uint32_t n, uint32_t *const *__restrict__ outs)
-{
-    const int v = blockIdx.y;
-    uint32_t *out = outs[v];
-    const uint32_t base = (uint32_t)v * n;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-        out[r] = vals[base + r] - base;
-}
-
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -585,19 +586,6 @@ static unsigned grid_for(int64_t n, int per_block, unsigned max_blocks)
     if (b < 1) b = 1;
     if (b > max_blocks) b = max_blocks;
     return (unsigned)b;
-}
-
-void launch_view_keys(const uint32_t *vals, int64_t total, int64_t n, uint32_t *keys, hipStream_t s)
-{
-    if (total <= 0 || n <= 0) return;
-    hipLaunchKernelGGL(k_view_keys, dim3(grid_for(total, 1024, 4096)), dim3(256), 0, s, vals, total, (uint32_t)n, keys);
-}
-
-void launch_split_ids(const uint32_t *vals, int nv, int64_t n, uint32_t *const *outs, hipStream_t s)
-{
-    if (nv <= 0 || n <= 0) return;
-    hipLaunchKernelGGL(k_split_ids, dim3(grid_for(n, 1024, 1024), (unsigned)nv), dim3(256), 0, s, vals, nv, (uint32_t)n,
-                       outs);
 }
 
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
@@ -651,25 +639,26 @@ int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
-                 uint32_t *host_status, hipStream_t s)
+                 uint32_t *host_status, hipStream_t s, const uint2 *view_tab, uint32_t view_n)
 {
     // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
     const int nb = (int)scan_blocks(n);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums,
                        nb, offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap));
     hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, ids,
-                       offsets, start_rank, n, keys_x, shift, cap, keys, vals, status, n_pairs_dev, host_status);
+                       offsets, start_rank, n, keys_x, shift, cap, view_tab, view_n, keys, vals, status, n_pairs_dev,
+                       host_status);
 }
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
 void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect, int supers_x, int nsup, hipStream_t s)
+                       const uint2 *rect, int supers_x, int nsup, hipStream_t s, const uint32_t *super_xy)
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
                        b.csuper, (uint32_t)b.max_chunks, b.nchunks);
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect, supers_x, b.chist);
+                       b.csuper, b.nchunks, rect, supers_x, super_xy, b.chist);
 }
 
 void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
@@ -683,10 +672,11 @@ void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int t
 }
 
 void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect, int supers_x,
-                      int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s)
+                      int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s,
+                      const uint32_t *super_xy, uint32_t view_n)
 {
     hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect, supers_x, tiles_x, tiles_y, b.chist, ranges, b.ok, vals);
+                       b.csuper, b.nchunks, rect, supers_x, super_xy, view_n, b.chist, ranges, b.ok, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,
