@@ -495,12 +495,10 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
                                            ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
         const bool one_pass = sbits <= 8;
-        if (!one_pass) launch_ranges(keys, nsup_pairs, L.cap, ctx->bin_sranges.as<uint2>(), nsup, s);
-        launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, po.rect, supers_x,
-                          nsup, s);
-        launch_bin_tiles(bw, supers_x, nsup, rk.tiles_x, rk.tiles_y, L.cap, ktotal, sp.ranges, status_words(ctx),
-                         npairs, host_status, s);
-        launch_bin_place(bw, svals, sranges, po.rect, supers_x, rk.tiles_x, rk.tiles_y, sp.ranges, sp.vals, s);
+        if (!one_pass) launch_ranges(keys, nsup_pairs, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
+        launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
+        launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, s);
+        launch_bin_place(bw, keys, svals, sranges, sp.ranges, sp.vals, 0, s);
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");
@@ -1215,8 +1213,8 @@ struct fgs_window {
     uint32_t total_tiles = 0;
     DBuf dl, grad2d, views, cams_dev, words, partials;
     // all views binned at once: the projection's per-workgroup pair counts of every view, the
-    // views' key tables (x: super-tiles per row, y: first super-tile), every super-tile's
-    // coordinates in its view, and the tile ranges (by window item) and tile lists of all views
+    // views' key tables (x: super-tiles per row, y: first super-tile), and the tile ranges (by
+    // window item) and tile lists of all views
     DBuf kpart, bintab, wranges, wvals;
     int64_t nsup_all = 0, cap_all = 0;
     hipStream_t stream = nullptr;
@@ -1398,7 +1396,6 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
         // order of all views' values, kept by the stable super-tile sort, is each view's depth order.
         uint32_t *cw = ctx->words.as<uint32_t>();
         const uint2 *view_tab = w->bintab.as<uint2>();
-        const uint32_t *super_xy = (const uint32_t *)(view_tab + w->nv);
         const int nsup = (int)w->nsup_all, sbits = key_bits_for(nsup);
         uint32_t *svals = (sbits + 7) / 8 == 1 ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
         const BinWS bw = bin_ws(ctx);
@@ -1419,13 +1416,12 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                                                ctx->pkB.as<uint32_t>(), ctx->pvB.as<uint32_t>(), svals, cw + W_NSUP,
                                                w->cap_all, sbits, sws, s);
             const bool one_pass = sbits <= 8;
-            if (!one_pass) launch_ranges(keys, cw + W_NSUP, w->cap_all, ctx->bin_sranges.as<uint2>(), nsup, s);
-            launch_bin_counts(bw, svals, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr,
-                              ctx->rect.as<uint2>(), 0, nsup, s, super_xy);
-            launch_bin_tiles(bw, 0, nsup, 0, 0, w->cap_all, cw + W_KTOTAL, w->wranges.as<uint2>(), status_words(ctx),
+            if (!one_pass) launch_ranges(keys, cw + W_NSUP, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
+            launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
+            launch_bin_tiles(bw, nsup, w->cap_all, cw + W_KTOTAL, w->wranges.as<uint2>(), status_words(ctx),
                              cw + W_NPAIRS, w->hs_dev, s);
-            launch_bin_place(bw, svals, ctx->bin_sranges.as<uint2>(), ctx->rect.as<uint2>(), 0, 0, 0,
-                             w->wranges.as<uint2>(), w->wvals.as<uint32_t>(), s, super_xy, (uint32_t)n);
+            launch_bin_place(bw, keys, svals, ctx->bin_sranges.as<uint2>(), w->wranges.as<uint2>(),
+                             w->wvals.as<uint32_t>(), (uint32_t)n, s);
         }
     }
     uint32_t *words = w->words.as<uint32_t>();
@@ -1519,9 +1515,11 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
         const int sy = supers_for((cams[v].height + w->th[v] - 1) / w->th[v]);
         bintab[2 * v] = (uint32_t)sx;
         bintab[2 * v + 1] = (uint32_t)w->nsup_all;
-        for (int y = 0; y < sy; ++y)
-            for (int x = 0; x < sx; ++x) bintab.push_back((uint32_t)x | (uint32_t)y << 16);
         w->nsup_all += (int64_t)sx * sy;
+    }
+    if (w->nsup_all > ((int64_t)1 << kBoxShift)) {  // not reached with 64 views of at most 16384^2 pixels
+        delete w;
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: too many super-tiles in the window", w_);
     }
     w->cap.assign(n_views, 0);
     w->L.resize(n_views);

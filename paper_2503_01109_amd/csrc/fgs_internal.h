@@ -31,6 +31,10 @@ struct RasterK {
 // items beyond the image's tiles have empty lists. Tile ranges, rasterizer grids and window items
 // all use this numbering.
 constexpr int kSuper = 4, kSuperShift = 2;
+// super-tile keys carry the entry's coverage box (4 x 2 bits) above bit kBoxShift; the super-tile
+// index itself stays below 2^kBoxShift (at most 64 views of at most 2^18 super-tiles)
+constexpr int kBoxShift = 24;
+constexpr uint32_t kSuperKeyMask = (1u << kBoxShift) - 1u;
 inline int32_t supers_for(int32_t tiles) { return (tiles + kSuper - 1) / kSuper; }
 inline int64_t tile_items(int32_t tiles_x, int32_t tiles_y)
 {
@@ -136,9 +140,10 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
                         uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s);
 
 // Emit one (key, gaussian id) pair per covered tile in depth order; with shift > 0 the keys are
-// super-tiles (tile rectangle >> shift, keys_x super-tiles per row). Several views binned at once
-// (view_tab non-null): ids are values v view_n + i, and view v's keys are view_tab[v].y + its own
-// key with view_tab[v].x keys per row (keys_x unused). offsets is scratch of n + 1
+// super-tiles (tile rectangle >> shift, keys_x super-tiles per row) and carry, above bit
+// kBoxShift, the box of the super-tile's tiles that the gaussian covers. Several views binned at
+// once (view_tab non-null): ids are values v view_n + i, and view v's keys are view_tab[v].y + its
+// own key with view_tab[v].x keys per row (keys_x unused). offsets is scratch of n + 1
 // words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
 // (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
@@ -150,16 +155,16 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
                  uint32_t *host_status, hipStream_t s, const uint2 *view_tab = nullptr, uint32_t view_n = 0);
 
 // Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
-// are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by super-tile
-// into svals with ranges sranges; then:
+// are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by the key bits
+// below kBoxShift into (skeys, svals) with ranges sranges; then:
 //   launch_bin_counts: chunk table and per-chunk tile counts;
 //   launch_bin_tiles:  prefixes over chunks and tiles, the tile ranges, and the capacity check of
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
 //                      overflow);
-//   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
-// Super-tile s lies at (s % supers_x, s / supers_x), or with super_xy non-null at
-// (super_xy[s] & 0xFFFF, super_xy[s] >> 16): the super-tiles of several views numbered one after
-// another, whose entries are view-offset values (view_n > 0) that the lists receive as id % view_n.
+//   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries);
+//                      with view_n > 0 the entries are view-offset values v view_n + id and the
+//                      lists receive id.
+// The tiles an entry covers come from the box in its key.
 struct BinWS {
     uint32_t *cstart;      // nsup + 1
     uint32_t *csuper;      // max_chunks
@@ -172,18 +177,16 @@ struct BinWS {
 int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 // digit_totals (nullable): the per-digit totals of a single-pass super-tile sort, from which the
 // super-tile ranges are written into sranges; else sranges holds them already.
-void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect, int supers_x, int nsup, hipStream_t s,
-                       const uint32_t *super_xy = nullptr);
-void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
-                      const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
-                      uint32_t *host_status, hipStream_t s);
-void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect,
-                      int supers_x, int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s,
-                      const uint32_t *super_xy = nullptr, uint32_t view_n = 0);
+void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
+                       hipStream_t s);
+void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
+                      uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s);
+void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
+                      const uint2 *ranges, uint32_t *vals, uint32_t view_n, hipStream_t s);
 
-void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges,
-                   int64_t T, hipStream_t s);
+// [start, end) of the runs of keys 0..T-1 in the sorted keys (n_dev of them), comparing key & mask.
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, uint2 *ranges, int64_t T, uint32_t mask,
+                   hipStream_t s);
 
 struct ImageK {
     float *rgb, *depth, *alpha, *T_final;  // rgb, depth: nullable when the loss below is fused

@@ -247,6 +247,17 @@ __device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, 
 
 constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion workgroup
 
+// The tiles of super-tile (sx, sy) that a gaussian's tile rectangle rc covers, as a box of
+// super-tile-local tile coordinates: lx0 | lx1 << 2 | ly0 << 4 | ly1 << 6 (never empty when the
+// super-tile lies in the rectangle's super-tile range).
+__device__ inline uint32_t cover_box(uint2 rc, uint32_t sx, uint32_t sy)
+{
+    const int x0 = (int)(sx * kSuper), y0 = (int)(sy * kSuper);
+    const int lx0 = max((int)(rc.x & 0xFFFFu) - x0, 0), lx1 = min((int)(rc.x >> 16) - x0, kSuper - 1);
+    const int ly0 = max((int)(rc.y & 0xFFFFu) - y0, 0), ly1 = min((int)(rc.y >> 16) - y0, kSuper - 1);
+    return (uint32_t)lx0 | (uint32_t)lx1 << 2 | (uint32_t)ly0 << 4 | (uint32_t)ly1 << 6;
+}
+
 // Load-balanced emission: the K pairs are cut into chunks of kEmitChunk consecutive pair
 // indices; a block takes a chunk, finds the depth ranks it spans by binary search over the
 // per-rank offsets, and its threads write consecutive pair indices (coalesced), each finding its
@@ -287,10 +298,13 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
             const uint32_t tx0 = (rc.x & 0xFFFFu) >> shift, tx1 = (rc.x >> 16) >> shift, ty0 = (rc.y & 0xFFFFu) >> shift;
             const uint32_t w = tx1 - tx0 + 1;
             const uint32_t dy = idx / w;
+            const uint32_t kx = tx0 + (idx - dy * w), ky = ty0 + dy;
             const uint32_t id = ids[r];
             // several views: the value is v view_n + id, keys count on from the view's first key
             const uint2 vt = view_tab ? view_tab[id / view_n] : make_uint2((uint32_t)tiles_x, 0u);
-            keys[j] = vt.y + (ty0 + dy) * vt.x + tx0 + (idx - dy * w);
+            uint32_t key = vt.y + ky * vt.x + kx;
+            if (shift > 0) key |= cover_box(rc, kx, ky) << kBoxShift;
+            keys[j] = key;
             vals[j] = id;
         }
         __syncthreads();
@@ -361,30 +375,24 @@ k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_tot
     }
 }
 
-// Coverage of one super-tile entry: bit (ly * kSuper + lx) for each tile of the super-tile the
-// gaussian's tile rectangle covers.
-__device__ inline uint32_t cover_bits(uint2 rc, int sx, int sy)
+// Coverage of one super-tile entry from the box in its key's top byte: bit (ly * kSuper + lx)
+// for each tile of the super-tile inside the box (never empty).
+__device__ inline uint32_t box_bits(uint32_t key)
 {
-    const int tx0 = (int)(rc.x & 0xFFFFu) - sx * kSuper, tx1 = (int)(rc.x >> 16) - sx * kSuper;
-    const int ty0 = (int)(rc.y & 0xFFFFu) - sy * kSuper, ty1 = (int)(rc.y >> 16) - sy * kSuper;
-    const int lx0 = max(tx0, 0), lx1 = min(tx1, kSuper - 1), ly0 = max(ty0, 0), ly1 = min(ty1, kSuper - 1);
-    uint32_t m = 0;
-    if (lx0 > lx1 || ly0 > ly1) return 0u;
-    const uint32_t row = ((1u << (lx1 - lx0 + 1)) - 1u) << lx0;
-    for (int ly = ly0; ly <= ly1; ++ly) m |= row << (ly * kSuper);
-    return m;
+    const uint32_t b = key >> kBoxShift;
+    const uint32_t lx0 = b & 3u, lx1 = (b >> 2) & 3u, ly0 = (b >> 4) & 3u, ly1 = (b >> 6) & 3u;
+    const uint32_t row = ((1u << (lx1 - lx0 + 1u)) - 1u) << lx0;
+    const uint32_t rows = 0x1111u & (0xFFFFu << (4u * ly0)) & (0xFFFFu >> (4u * (3u - ly1)));
+    return row * rows;  // row < 16: the product places one copy of row per selected row
 }
 
 struct ChunkSpan {
     uint32_t e0, e1, s;
-    int sx, sy;
 };
 
-// Chunk c's entries [e0, e1) of super-tile s at super-tile coordinates (sx, sy): from s and
-// supers_x for one view, or from super_xy[s] (x | y << 16) when the super-tiles of several views
-// are numbered one after another.
+// Chunk c's entries [e0, e1) of super-tile s.
 __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const uint32_t *cstart,
-                                       const uint32_t *csuper, int supers_x, const uint32_t *super_xy)
+                                       const uint32_t *csuper)
 {
     const uint32_t sidx = csuper[c];
     const uint2 r = sranges[sidx];
@@ -392,33 +400,23 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
     cs.s = sidx;
     cs.e0 = r.x + (c - cstart[sidx]) * kBinChunk;
     cs.e1 = min(cs.e0 + kBinChunk, r.y);
-    if (super_xy) {
-        const uint32_t xy = super_xy[sidx];
-        cs.sx = (int)(xy & 0xFFFFu);
-        cs.sy = (int)(xy >> 16);
-    } else {
-        cs.sx = (int)(sidx % (uint32_t)supers_x);
-        cs.sy = (int)(sidx / (uint32_t)supers_x);
-    }
     return cs;
 }
 
 // Per chunk: how many of its entries cover each tile of its super-tile.
 __global__ void __launch_bounds__(kSortThreads)
-k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
-            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect, int supers_x, const uint32_t *__restrict__ super_xy,
-            uint32_t *__restrict__ chist)
+k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
+            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
     const uint32_t c = blockIdx.x;
     if (c >= *nchunks) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x, super_xy);
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
     if (threadIdx.x < kSuper * kSuper) cnt[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
         const uint32_t e = base + threadIdx.x;
-        const uint32_t m = e < cs.e1 ? cover_bits(rect[svals[e]], cs.sx, cs.sy) : 0u;
+        const uint32_t m = e < cs.e1 ? box_bits(skeys[e]) : 0u;
 #pragma unroll
         for (int b = 0; b < kSuper * kSuper; ++b) {
             const uint64_t bal = __ballot((m >> b) & 1u);
@@ -431,11 +429,10 @@ k_bin_count(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
 
 // Per super-tile (kSuper^2 threads): exclusive prefix of each tile's counts over the super-tile's
 // chunks (in place) and the tile's total.
-__global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, int supers_x, int tiles_x, int tiles_y,
-                             uint32_t *__restrict__ chist, uint32_t *__restrict__ tile_total)
+__global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, uint32_t *__restrict__ chist,
+                             uint32_t *__restrict__ tile_total)
 {
     const int sidx = blockIdx.x, b = threadIdx.x;
-    (void)supers_x, (void)tiles_x, (void)tiles_y;
     uint32_t run = 0;
     for (uint32_t c = cstart[sidx]; c < cstart[sidx + 1]; ++c) {
         uint32_t *h = chist + (size_t)c * (kSuper * kSuper) + b;
@@ -495,18 +492,17 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, cons
 // Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order
 // (view_n > 0: entries are view-offset values v view_n + id; the lists get id).
 __global__ void __launch_bounds__(kSortThreads)
-k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
-            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks,
-            const uint2 *__restrict__ rect, int supers_x, const uint32_t *__restrict__ super_xy, uint32_t view_n,
-            const uint32_t *__restrict__ chist, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok,
-            uint32_t *__restrict__ vals)
+k_bin_place(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges,
+            const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ csuper,
+            const uint32_t *__restrict__ nchunks, uint32_t view_n, const uint32_t *__restrict__ chist,
+            const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok, uint32_t *__restrict__ vals)
 {
     constexpr int NB = kSuper * kSuper, NW = kSortThreads / kWave;
     __shared__ uint32_t run[NB];
     __shared__ uint32_t wtot[NW][NB];
     const uint32_t c = blockIdx.x;
     if (c >= *nchunks || !*ok) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper, supers_x, super_xy);
+    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
     if (tid < NB) run[tid] = ranges[(size_t)cs.s * NB + tid].x + chist[(size_t)c * NB + tid];
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -515,7 +511,7 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
         uint32_t id = 0, m = 0;
         if (e < cs.e1) {
             id = svals[e];
-            m = cover_bits(rect[id], cs.sx, cs.sy);
+            m = box_bits(skeys[e]);
         }
         uint64_t bal[NB];
 #pragma unroll
@@ -543,25 +539,27 @@ k_bin_place(const uint32_t *__restrict__ svals, const uint2 *__restrict__ srange
     }
 }
 
-__device__ inline uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v)
+__device__ inline uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v, uint32_t mask)
 {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1;
+        if ((a[mid] & mask) < v) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-// [start, end) of every tile's run in the sorted keys, by two binary searches per tile.
+// [start, end) of every key's run in the sorted keys (compared under mask), by two binary
+// searches per key.
 __global__ void __launch_bounds__(kSortThreads)
-k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges, int64_t T)
+k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges, int64_t T,
+         uint32_t mask)
 {
     const int64_t t = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
     if (t >= T) return;
     const uint32_t K = *n_dev;
-    ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t), lower_bound_u32(keys, K, (uint32_t)t + 1));
+    ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t, mask), lower_bound_u32(keys, K, (uint32_t)t + 1, mask));
 }
 
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
@@ -652,39 +650,36 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
-void launch_bin_counts(const BinWS &b, const uint32_t *svals, uint2 *sranges, const uint32_t *digit_totals,
-                       const uint2 *rect, int supers_x, int nsup, hipStream_t s, const uint32_t *super_xy)
+void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
+                       hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
                        b.csuper, (uint32_t)b.max_chunks, b.nchunks);
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect, supers_x, super_xy, b.chist);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, skeys, sranges, b.cstart,
+                       b.csuper, b.nchunks, b.chist);
 }
 
-void launch_bin_tiles(const BinWS &b, int supers_x, int nsup, int tiles_x, int tiles_y, int64_t cap,
-                      const uint32_t *ktotal, uint2 *ranges, uint32_t *status, uint32_t *n_pairs_dev,
-                      uint32_t *host_status, hipStream_t s)
+void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
+                      uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, supers_x, tiles_x,
-                       tiles_y, b.chist, b.tile_total);
+    hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, b.chist,
+                       b.tile_total);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, nsup, cap, ktotal, ranges, status,
                        n_pairs_dev, host_status, b.ok);
 }
 
-void launch_bin_place(const BinWS &b, const uint32_t *svals, const uint2 *sranges, const uint2 *rect, int supers_x,
-                      int tiles_x, int tiles_y, const uint2 *ranges, uint32_t *vals, hipStream_t s,
-                      const uint32_t *super_xy, uint32_t view_n)
+void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
+                      const uint2 *ranges, uint32_t *vals, uint32_t view_n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, svals, sranges, b.cstart,
-                       b.csuper, b.nchunks, rect, supers_x, super_xy, view_n, b.chist, ranges, b.ok, vals);
+    hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, skeys, svals, sranges,
+                       b.cstart, b.csuper, b.nchunks, view_n, b.chist, ranges, b.ok, vals);
 }
 
-void launch_ranges(const uint32_t *keys, const uint32_t *n_pairs_dev, int64_t cap, uint2 *ranges, int64_t T,
+void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, uint2 *ranges, int64_t T, uint32_t mask,
                    hipStream_t s)
 {
-    (void)cap;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((T + kSortThreads - 1) / kSortThreads)), dim3(kSortThreads), 0, s,
-                       keys, n_pairs_dev, ranges, T);
+                       keys, n_dev, ranges, T, mask);
 }
 
 }  // namespace fgs
