@@ -147,51 +147,58 @@ __device__ __forceinline__ int wave_compact(const uint8_t *smask, int cnt, int w
     return len;
 }
 
-// Ten wave sums at once by a transposed butterfly: at each exchange a lane keeps half of its
-// partial sums (the half its partner does not keep) and adds the partner's matching half, so
-// 10 values shrink to 5, 3, 2 and 1 per lane over lane distances 1, 2, 4 and 8; two more
-// exchanges add the four rows. Lane j (j < 16; every row holds the same) returns the full sum of
-// term reduce_term(j), or of nothing when that is negative (padding). About 40 VALU operations
-// instead of 10 separate 6-step wave sums.
+// Exchange across lane distance 32 (D = 32) or 16 (D = 16) without selects: lanes whose bit D is
+// clear return lo summed with the partner's lo, the others hi summed with the partner's hi
+// (gfx950's row swaps: permlane32 trades the upper half of lo for the lower half of hi, permlane16
+// the odd rows of lo for the even rows of hi).
+template <int D>
+__device__ __forceinline__ float swap_add(float lo, float hi)
+{
+    const auto r = D == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                           : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Exchange across lane distance 1 (PAT = quad_perm 0xB1) or 2 (0x4E): lanes with that bit clear
+// return lo summed with the partner's lo, the others hi summed with the partner's hi.
+template <int PAT, int BIT>
+__device__ __forceinline__ float dpp_add(float lo, float hi, int lane)
+{
+    const bool b = lane & BIT;
+    const float send = b ? lo : hi, mine = b ? hi : lo;
+    return mine + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), PAT, 0xf, 0xf, false));
+}
+
+// Ten wave sums at once by a transposed butterfly: at each exchange a lane keeps the half of its
+// partial sums that its partner gives away and adds the partner's matching half, so 10 values
+// shrink to 5, 3, 2 and 1 per lane over lane distances 32, 16, 1 and 2 (an odd value out is summed
+// by both partners); two rotations within each row of 16 add its four quads. Every lane ends with
+// the full sum of one term; reduce_term names, for one lane per term, which (-1 elsewhere). The
+// two widest exchanges use the row swaps, the rest DPP: about 25 VALU operations and no LDS
+// traffic for ten sums.
 __device__ __forceinline__ float reduce10(const float v[10], int lane)
 {
-    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
     float a[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        const float send = b0 ? v[c] : v[c + 5], mine = b0 ? v[c + 5] : v[c];
-        a[c] = mine + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0xB1, 0xf, 0xf, false));
-    }
-    float q[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float hi = c < 2 ? a[c + 3] : 0.0f, lo = a[c];
-        const float send = b1 ? lo : hi, mine = b1 ? hi : lo;
-        q[c] = mine + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0x4E, 0xf, 0xf, false));
-    }
-    float r[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const float hi = c < 1 ? q[c + 2] : 0.0f, lo = q[c];
-        const float send = b2 ? lo : hi, mine = b2 ? hi : lo;
-        r[c] = mine + __shfl_xor(send, 4);
-    }
-    const float send = b3 ? r[0] : r[1], mine = b3 ? r[1] : r[0];
-    float d = mine + __shfl_xor(send, 8);
-    d += __shfl_xor(d, 16);
-    d += __shfl_xor(d, 32);
+    for (int c = 0; c < 5; ++c) a[c] = swap_add<32>(v[c], v[c + 5]);  // term c + 5 (lane >> 5)
+    const float q0 = swap_add<16>(a[0], a[3]), q1 = swap_add<16>(a[1], a[4]), q2 = swap_add<16>(a[2], a[2]);
+    const float r0 = dpp_add<0xB1, 1>(q0, q2, lane);
+    const float r1 = q1 + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(q1), 0xB1, 0xf, 0xf, false));
+    float d = dpp_add<0x4E, 2>(r0, r1, lane);
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x124, 0xf, 0xf, false));  // row_ror:4
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, false));  // row_ror:8
     return d;
 }
 
-// The term whose sum reduce10 leaves in lane j of a row (-1: padding).
+// The term whose sum reduce10 leaves in this lane, for one lane per term (-1: a copy or padding).
+// Row r of 16 lanes holds terms 5 (r >> 1) + {0, 2, 1} (r even) or + {3, -, 4} (r odd) in its
+// lanes 0, 1, 2.
 __device__ __forceinline__ int reduce_term(int lane)
 {
-    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
-    const int i3 = b2 ? 2 + b3 : b3;  // index among the 3 values of the third exchange
-    if (i3 > 2) return -1;
-    const int i5 = b1 ? 3 + i3 : i3;  // among the 5 values of the second
-    if (i5 > 4) return -1;
-    return b0 ? 5 + i5 : i5;
+    const int row = lane >> 4, i = lane & 15, base = 5 * (row >> 1);
+    if (i > 2) return -1;
+    if ((row & 1) == 0) return base + (i == 0 ? 0 : (i == 1 ? 2 : 1));
+    return i == 1 ? -1 : base + (i == 0 ? 3 : 4);
 }
 
 // Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
@@ -423,7 +430,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
-    const bool red_lane = lane < 16 && term >= 0;
+    const bool red_lane = term >= 0;
     const int wid = tid / kWave;
     const int sidx = tile / (kSuper * kSuper), sl = tile % (kSuper * kSuper);
     const int tx = (sidx % rk.supers_x) * kSuper + sl % kSuper, ty = (sidx / rk.supers_x) * kSuper + sl / kSuper;
