@@ -45,15 +45,16 @@ __device__ __forceinline__ void stage(const Rec &R, int x0, int y0, float4 &a, f
     // projected mean in tile-local coordinates: integer part is exact, one rounding for the sum
     mx = (float)(__float_as_int(R.r0.x) - x0) + R.r0.z;
     my = (float)(__float_as_int(R.r0.y) - y0) + R.r0.w;
-    a = make_float4(mx, my, kConicScale * R.r1.x, kConicScale * R.r1.y);
+    a = make_float4(mx, my, kConicScale * R.r1.x, (2.0f * kConicScale) * R.r1.y);  // s a, 2 s b
     b = make_float4(kConicScale * R.r1.z, R.r1.w, R.r2.w, 0.0f);
     c = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.0f);
 }
 
-// One (pixel, staged record) pair: offsets from the mean, the products of the scaled conic with
-// them (reused by the backward), q = s Q in a fixed operation order and G = 2^q = exp(-Q/2).
+// One (pixel, staged record) pair: offsets from the mean, q = s Q in a fixed operation order,
+// (s a dx + 2 s b dy) dx + (s c dy) dy with two FMAs, and G = 2^q = exp(-Q/2). The forward and the
+// backward evaluate it identically, so they take the same decisions.
 struct PairEval {
-    float dx, dy, Adx, Bdx, Cdy, q, G;
+    float dx, dy, q, G;
 };
 
 __device__ __forceinline__ PairEval eval_pair(const float4 &a4, const float4 &b4, float px, float py)
@@ -61,12 +62,9 @@ __device__ __forceinline__ PairEval eval_pair(const float4 &a4, const float4 &b4
     PairEval e;
     e.dx = px - a4.x;
     e.dy = py - a4.y;
-    e.Adx = a4.z * e.dx;
-    e.Bdx = a4.w * e.dx;
-    e.Cdy = b4.x * e.dy;
-    const float t0 = e.Adx * e.dx, t1 = e.Bdx * e.dy, t2 = e.Cdy * e.dy;
-    e.q = __builtin_fmaf(2.0f, t1, t0) + t2;  // (t0 + 2 t1) + t2; 2 t1 is exact
-    e.G = __builtin_amdgcn_exp2f(e.q);        // q <= 0 up to rounding, >= s sigma_cut^2 when used
+    const float u = __builtin_fmaf(a4.w, e.dy, a4.z * e.dx);
+    e.q = __builtin_fmaf(u, e.dx, (b4.x * e.dy) * e.dy);
+    e.G = __builtin_amdgcn_exp2f(e.q);  // q <= 0 up to rounding, >= s sigma_cut^2 when used
     return e;
 }
 
@@ -532,11 +530,11 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         for (int e = tid >> 4; e < cnt; e += NT >> 4) {
             const int c = tid & 15;
             if (c < 10) {
-                // moments to gradients (see bwd_grad): the staged conic is s (a, b, c)
-                const float raw = sacc[e][c], m0 = sacc[e][0], m1 = sacc[e][1];
+                // moments to gradients (see bwd_grad): the staged conic is s (a, 2 b, c)
+                const float raw = sacc[e][c], m0 = sacc[e][0], m1 = sacc[e][1], sbv = 0.5f * sa[e].w;
                 float v = raw;
-                if (c == 0) v = (sa[e].z * m0 + sa[e].w * m1) * kInvConicScale;
-                else if (c == 1) v = (sa[e].w * m0 + sb[e].x * m1) * kInvConicScale;
+                if (c == 0) v = (sa[e].z * m0 + sbv * m1) * kInvConicScale;
+                else if (c == 1) v = (sbv * m0 + sb[e].x * m1) * kInvConicScale;
                 else if (c == 3) v = -raw;
                 else if (c == 2 || c == 4) v = -0.5f * raw;
                 if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + c], v);
