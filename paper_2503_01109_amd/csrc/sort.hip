@@ -245,7 +245,8 @@ __device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, 
     return lo;
 }
 
-constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion workgroup
+constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion chunk
+constexpr int kBinGrid = 4096;         // workgroups of the expansion kernels (each loops over chunks)
 
 // The tiles of super-tile (sx, sy) that a gaussian's tile rectangle rc covers, as a box of
 // super-tile-local tile coordinates: lx0 | lx1 << 2 | ly0 << 4 | ly1 << 6 (never empty when the
@@ -409,22 +410,24 @@ k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ srange
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
-    const uint32_t c = blockIdx.x;
-    if (c >= *nchunks) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
-    if (threadIdx.x < kSuper * kSuper) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
-        const uint32_t e = base + threadIdx.x;
-        const uint32_t m = e < cs.e1 ? box_bits(skeys[e]) : 0u;
+    const uint32_t nc = *nchunks;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
+        if (threadIdx.x < kSuper * kSuper) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
+            const uint32_t e = base + threadIdx.x;
+            const uint32_t m = e < cs.e1 ? box_bits(skeys[e]) : 0u;
 #pragma unroll
-        for (int b = 0; b < kSuper * kSuper; ++b) {
-            const uint64_t bal = __ballot((m >> b) & 1u);
-            if (__lane_id() == 0 && bal) atomicAdd(&cnt[b], (uint32_t)__popcll(bal));
+            for (int b = 0; b < kSuper * kSuper; ++b) {
+                const uint64_t bal = __ballot((m >> b) & 1u);
+                if (__lane_id() == 0 && bal) atomicAdd(&cnt[b], (uint32_t)__popcll(bal));
+            }
         }
+        __syncthreads();
+        if (threadIdx.x < kSuper * kSuper) chist[(size_t)c * (kSuper * kSuper) + threadIdx.x] = cnt[threadIdx.x];
+        __syncthreads();  // cnt is cleared for the next chunk
     }
-    __syncthreads();
-    if (threadIdx.x < kSuper * kSuper) chist[(size_t)c * (kSuper * kSuper) + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Per super-tile (kSuper^2 threads): exclusive prefix of each tile's counts over the super-tile's
@@ -500,42 +503,43 @@ k_bin_place(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ sva
     constexpr int NB = kSuper * kSuper, NW = kSortThreads / kWave;
     __shared__ uint32_t run[NB];
     __shared__ uint32_t wtot[NW][NB];
-    const uint32_t c = blockIdx.x;
-    if (c >= *nchunks || !*ok) return;
-    const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
+    const uint32_t nc = *ok ? *nchunks : 0u;
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
-    if (tid < NB) run[tid] = ranges[(size_t)cs.s * NB + tid].x + chist[(size_t)c * NB + tid];
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
-        const uint32_t e = base + tid;
-        uint32_t id = 0, m = 0;
-        if (e < cs.e1) {
-            id = svals[e];
-            m = box_bits(skeys[e]);
-        }
-        uint64_t bal[NB];
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
+        if (tid < NB) run[tid] = ranges[(size_t)cs.s * NB + tid].x + chist[(size_t)c * NB + tid];
+        for (uint32_t base = cs.e0; base < cs.e1; base += kSortThreads) {
+            const uint32_t e = base + tid;
+            uint32_t id = 0, m = 0;
+            if (e < cs.e1) {
+                id = svals[e];
+                m = box_bits(skeys[e]);
+            }
+            uint64_t bal[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bal[b] = __ballot((m >> b) & 1u);
-        if (lane < NB) wtot[wid][lane] = (uint32_t)__popcll(bal[lane]);
-        __syncthreads();
-        if (m) {
+            for (int b = 0; b < NB; ++b) bal[b] = __ballot((m >> b) & 1u);
+            if (lane < NB) wtot[wid][lane] = (uint32_t)__popcll(bal[lane]);
+            __syncthreads();
+            if (m) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if ((m >> b) & 1u) {
-                    uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
-                    for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
-                    vals[pos] = view_n ? id % view_n : id;  // the id within its view
+                for (int b = 0; b < NB; ++b) {
+                    if ((m >> b) & 1u) {
+                        uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
+                        for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
+                        vals[pos] = view_n ? id % view_n : id;  // the id within its view
+                    }
                 }
             }
-        }
-        __syncthreads();
-        if (tid < NB) {
-            uint32_t add = 0;
+            __syncthreads();
+            if (tid < NB) {
+                uint32_t add = 0;
 #pragma unroll
-            for (int w2 = 0; w2 < NW; ++w2) add += wtot[w2][tid];
-            run[tid] += add;
+                for (int w2 = 0; w2 < NW; ++w2) add += wtot[w2][tid];
+                run[tid] += add;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -655,8 +659,8 @@ void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, co
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
                        b.csuper, (uint32_t)b.max_chunks, b.nchunks);
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, skeys, sranges, b.cstart,
-                       b.csuper, b.nchunks, b.chist);
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, sranges,
+                       b.cstart, b.csuper, b.nchunks, b.chist);
 }
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
@@ -671,8 +675,8 @@ void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *kto
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
                       const uint2 *ranges, uint32_t *vals, uint32_t view_n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_place, dim3((unsigned)b.max_chunks), dim3(kSortThreads), 0, s, skeys, svals, sranges,
-                       b.cstart, b.csuper, b.nchunks, view_n, b.chist, ranges, b.ok, vals);
+    hipLaunchKernelGGL(k_bin_place, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, svals,
+                       sranges, b.cstart, b.csuper, b.nchunks, view_n, b.chist, ranges, b.ok, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, uint2 *ranges, int64_t T, uint32_t mask,
