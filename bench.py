@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-iters", type=int, default=10, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--cpu-iters", type=int, default=40, help="oracle iterations timed for the CPU baseline (about 15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-extras", action="store_true",
