@@ -202,7 +202,7 @@ __device__ __forceinline__ int reduce_term(int lane)
 // Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
 // tile_w x tile_h = NT pixels). COUNT: accumulate the profiling work counters; NCON: count each
 // pixel's blended pairs (for the n_contrib output; implied by COUNT).
-template <int NT, bool COUNT, bool NCON = COUNT>
+template <int NT, bool COUNT, bool NCON = COUNT, bool ALPHA = true>
 __device__ void tile_fwd(const ViewK &V, int tile)
 {
     constexpr int NW = NT / kWave;
@@ -231,10 +231,12 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
     uint32_t last = 0, ntest = 0, staged = 0;
     int32_t ncon = 0;
-    bool done = !inside;
+    // the lane's cutoff on q: qcut while the pixel blends, +inf once it is done (outside the
+    // image, or stopped before a pair that would take T below T_min), so that no pair is near
+    float qc = inside ? qcut : INFINITY;
 
     for (uint32_t b = range.x; b < range.y; b += NT) {
-        if (__syncthreads_count(!done) == 0) break;
+        if (__syncthreads_count(qc < INFINITY) == 0) break;
         staged += min((uint32_t)NT, range.y - b);
         const uint32_t j = b + tid;
         if (j < range.y) {
@@ -252,31 +254,38 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
         const uint32_t base = b - range.x + 1;
         // Branch-free per pair: every lane evaluates the entry and the decisions select what is
-        // kept; the wave leaves the list once all of its pixels are done.
-        for (int i = 0; i < len; ++i) {
-            if (__ballot(!done) == 0) break;
-            const int k = slist[wid][i];
+        // kept; T - alpha T is the new transmittance (T (1 - alpha) up to rounding). The last
+        // blended entry of this chunk is kept as its list index and folded into `last` after it.
+        int lastk = -1;
+        auto pair = [&](int k) {
             const float4 a4 = sa[k], b4 = sb[k];
             const PairEval e = eval_pair(a4, b4, px, py);
-            const bool near = !done && !(e.q < qcut);
+            const bool near = !(e.q < qc);
             const float alpha = fminf(rk.alpha_max, b4.y * e.G);
-            const float Tn = T * (1.0f - alpha);
             const bool take = near && !(alpha < rk.alpha_min);
-            const bool stop = take && Tn < rk.T_min;
-            const bool blend = take && !stop;
-            const float w = blend ? alpha * T : 0.0f;
+            const float u = alpha * T, Tn = T - u;
+            const bool low = Tn < rk.T_min;
+            const bool blend = take && !low;
+            const float w = blend ? u : 0.0f;
             const float4 c4 = sc[k];
             C0 = __builtin_fmaf(w, c4.x, C0);
             C1 = __builtin_fmaf(w, c4.y, C1);
             C2 = __builtin_fmaf(w, c4.z, C2);
             D = __builtin_fmaf(w, b4.z, D);
-            A += w;
+            if (ALPHA) A += w;
             T = blend ? Tn : T;
-            done = done || stop;
+            qc = take && low ? INFINITY : qc;
             if (COUNT) ntest += near ? 1u : 0u;
             if (COUNT || NCON) ncon += blend ? 1 : 0;
-            last = blend ? base + k : last;
+            lastk = blend ? k : lastk;
+        };
+        // two entries per round: the wave leaves the list once all of its pixels are done
+        for (int i = 0; i < len; i += 2) {
+            if (__ballot(qc < INFINITY) == 0) break;
+            pair(slist[wid][i]);
+            if (i + 1 < len) pair(slist[wid][i + 1]);
         }
+        if (lastk >= 0) last = base + (uint32_t)lastk;
     }
     if (COUNT) {
         // work counters (profiling only): block sums, one atomic per block and counter
@@ -307,7 +316,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             img.rgb[2 * P + p] = col[2];
         }
         if (img.depth) img.depth[p] = dep;
-        if (img.alpha) img.alpha[p] = A;
+        if (ALPHA && img.alpha) img.alpha[p] = A;
         if (img.T_final) img.T_final[p] = T;
         if (img.n_contrib) img.n_contrib[p] = ncon;
         V.last[p] = last;
@@ -545,8 +554,9 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     __syncthreads();  // LDS is restaged by the next tile of a persistent workgroup
 }
 
-template <int NT, bool COUNT, bool NCON>
-__global__ void __launch_bounds__(NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT, NCON>(V, blockIdx.x); }
+// eight waves per SIMD (64 VGPRs), as the window's forward
+template <int NT, bool COUNT, bool NCON, bool ALPHA>
+__global__ void __launch_bounds__(NT, 2048 / NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT, NCON, ALPHA>(V, blockIdx.x); }
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT>(V, blockIdx.x); }
@@ -574,7 +584,7 @@ k_raster_queue(const ViewK *__restrict__ views, int nv, uint32_t total, uint32_t
         __syncthreads();
         if (g >= total) break;
         const ViewK V = views[view_of(views, nv, g)];
-        if (FWD) tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
+        if (FWD) tile_fwd<256, COUNT, COUNT, false>(V, (int)(g - V.tile_base));  // loss only: no image
         else tile_bwd<256>(V, (int)(g - V.tile_base));
     }
 }
@@ -587,7 +597,7 @@ k_raster_items_fwd(const ViewK *__restrict__ views, int nv)
 {
     const uint32_t g = blockIdx.x;
     const ViewK V = views[view_of(views, nv, g)];
-    tile_fwd<256, COUNT>(V, (int)(g - V.tile_base));
+    tile_fwd<256, COUNT, COUNT, false>(V, (int)(g - V.tile_base));  // loss only: no image
 }
 
 __global__ void __launch_bounds__(256)
@@ -619,21 +629,23 @@ static ViewK view_of_args(const RasterK &rk, int32_t W, int32_t H, const Rec *re
     return V;
 }
 
-template <bool COUNT, bool NCON>
+template <bool COUNT, bool NCON, bool ALPHA>
 static void launch_fwd_variant(const ViewK &V, unsigned tiles, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, COUNT, NCON>), dim3(tiles), dim3(256), 0, s, V);
-    else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, COUNT, NCON>), dim3(tiles), dim3(512), 0, s, V);
-    else hipLaunchKernelGGL((k_raster_fwd<64, COUNT, NCON>), dim3(tiles), dim3(64), 0, s, V);
+    if (nt == 256) hipLaunchKernelGGL((k_raster_fwd<256, COUNT, NCON, ALPHA>), dim3(tiles), dim3(256), 0, s, V);
+    else if (nt == 512) hipLaunchKernelGGL((k_raster_fwd<512, COUNT, NCON, ALPHA>), dim3(tiles), dim3(512), 0, s, V);
+    else hipLaunchKernelGGL((k_raster_fwd<64, COUNT, NCON, ALPHA>), dim3(tiles), dim3(64), 0, s, V);
 }
 
 static void launch_fwd_view(const ViewK &V, hipStream_t s)
 {
     const unsigned tiles = (unsigned)tile_items(V.rk.tiles_x, V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
-    if (V.counts) launch_fwd_variant<true, true>(V, tiles, nt, s);
-    else if (V.img.n_contrib) launch_fwd_variant<false, true>(V, tiles, nt, s);
-    else launch_fwd_variant<false, false>(V, tiles, nt, s);
+    // the opacity plane's running sum only when that plane is written (not by the mapping step)
+    if (V.counts) launch_fwd_variant<true, true, true>(V, tiles, nt, s);
+    else if (V.img.n_contrib) launch_fwd_variant<false, true, true>(V, tiles, nt, s);
+    else if (V.img.alpha) launch_fwd_variant<false, false, true>(V, tiles, nt, s);
+    else launch_fwd_variant<false, false, false>(V, tiles, nt, s);
 }
 
 static void launch_bwd_view(const ViewK &V, hipStream_t s)
