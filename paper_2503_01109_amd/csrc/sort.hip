@@ -95,6 +95,109 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ total
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// Stable scatter of the workgroup's chunk by one digit, through LDS (for digits spread over many
+// values, where k_radix_scatter's stores would each hit a different line): each tile of up to
+// kScatterTile keys is first ordered by digit in LDS (rounds of 256 keys in order; within a round
+// each lane is ranked among the lanes of its wave holding the same digit, one ballot per digit
+// bit, and the waves before it are counted through wcnt), then written out in that order, so
+// that the consecutive lanes of a store land in a few runs of consecutive slots instead of one
+// slot per digit.
+constexpr int kScatterItems = 8, kScatterTile = kSortThreads * kScatterItems;
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter_lds(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                    uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, uint32_t n_cap, int shift,
+                    uint32_t mask, int bits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals)
+{
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t gbase[256];  // next global slot of each digit
+    __shared__ uint32_t tstart[256];  // first tile slot of each digit
+    __shared__ uint32_t run[256];     // digit counts of the tile, then its next tile slots
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t skey[kScatterTile], sval[kScatterTile];
+    __shared__ uint32_t w8[8];
+    const int tid = threadIdx.x, wid = tid / kWave;
+    {
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(totals[tid], w8, &tot);
+        gbase[tid] = ex + hist[(size_t)tid * gridDim.x + blockIdx.x];
+        run[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    }
+    __syncthreads();
+    const uint32_t n = min(*n_dev, n_cap);
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
+    for (uint32_t t0 = lo; t0 < hi; t0 += kScatterTile) {
+        const uint32_t nt = min((uint32_t)kScatterTile, hi - t0);
+        const int rounds = (int)((nt + kSortThreads - 1) / kSortThreads);
+        uint32_t key[kScatterItems], val[kScatterItems], rank[kScatterItems], cnt[kScatterItems];
+        // the tile's digit counts (one add per wave and digit)
+#pragma unroll
+        for (int r = 0; r < kScatterItems; ++r) {
+            if (r >= rounds) break;
+            const uint32_t i = t0 + (uint32_t)(r * kSortThreads + tid);
+            const bool valid = i < hi;
+            key[r] = valid ? kin[i] : 0u;
+            val[r] = valid ? vin[i] : 0u;
+            const uint32_t d = (key[r] >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < bits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            rank[r] = valid ? __popcll(peers & lanemask_lt()) : kSortThreads;  // invalid: no leader
+            cnt[r] = __popcll(peers);
+            if (rank[r] == 0) atomicAdd(&run[d], cnt[r]);
+        }
+        __syncthreads();
+        {
+            uint32_t tot;
+            const uint32_t c = run[tid];
+            tstart[tid] = block_excl_scan(c, w8, &tot);  // (synchronizes the block)
+            run[tid] = tstart[tid];
+        }
+        // local slots, round by round: the leaders publish their wave's count of their digit,
+        // every lane adds the waves before it, then the leaders advance their digit's slot
+#pragma unroll
+        for (int r = 0; r < kScatterItems; ++r) {
+            if (r >= rounds) break;
+            const uint32_t d = (key[r] >> shift) & mask;
+            if (rank[r] == 0) wcnt[wid][d] = cnt[r];
+            __syncthreads();
+            if (rank[r] < (uint32_t)kSortThreads) {
+                uint32_t pos = run[d] + rank[r];
+                for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+                skey[pos] = key[r];
+                sval[pos] = val[r];
+            }
+            __syncthreads();
+            if (rank[r] == 0) {
+                atomicAdd(&run[d], cnt[r]);
+                wcnt[wid][d] = 0;
+            }
+        }
+        __syncthreads();
+        // out in tile order: slot j of digit d goes to gbase[d] + (j - tstart[d])
+        for (uint32_t j = tid; j < nt; j += kSortThreads) {
+            const uint32_t k = skey[j], d = (k >> shift) & mask;
+            const uint32_t g = gbase[d] + (j - tstart[d]);
+            kout[g] = k;
+            vout[g] = sval[j];
+        }
+        __syncthreads();
+        gbase[tid] += run[tid] - tstart[tid];
+        run[tid] = 0;
+        __syncthreads();
+    }
+}
+
+// Stable scatter of the workgroup's chunk by one digit, straight to memory: 256 keys per round,
+// each lane ranked among the lanes of its wave holding the same digit (one ballot per digit bit),
+// the waves before it counted through wcnt. Right for a digit with few distinct values (the
+// keys' top bits), whose rounds already land in long runs.
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                 uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, uint32_t n_cap, int shift,
@@ -614,8 +717,13 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
         hipLaunchKernelGGL(k_radix_hist, dim3(ws.G), dim3(kSortThreads), 0, s, sk, n_dev, (uint32_t)n_cap, shift,
                            mask, ws.hist);
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, s, ws.hist, ws.G, ws.totals);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(ws.G), dim3(kSortThreads), 0, s, sk, sv, ok, ov, n_dev,
-                           (uint32_t)n_cap, shift, mask, bits, ws.hist, ws.totals);
+        // the last pass of several sorts the top bits, whose few values already give long runs
+        if (p == passes - 1 && passes > 1)
+            hipLaunchKernelGGL(k_radix_scatter, dim3(ws.G), dim3(kSortThreads), 0, s, sk, sv, ok, ov, n_dev,
+                               (uint32_t)n_cap, shift, mask, bits, ws.hist, ws.totals);
+        else
+            hipLaunchKernelGGL(k_radix_scatter_lds, dim3(ws.G), dim3(kSortThreads), 0, s, sk, sv, ok, ov, n_dev,
+                               (uint32_t)n_cap, shift, mask, bits, ws.hist, ws.totals);
         if (p == passes - 1) return ok;
         sk = dk; sv = dv;
         dk = (dk == kb) ? ka : kb;
