@@ -1345,6 +1345,7 @@ fgs_status window_tables(fgs_window *w, const fgs_gaussians &params, const fgs_r
         V.drgb = view_dl(w, v);
         V.ddepth = view_dl(w, v) + 3 * P;
         V.ddepth_scale = w->words.as<float>() + WW_DSCALE + v;
+        V.loss.ddepth_scale = w->words.as<float>() + WW_DSCALE + v;
         V.grad2d = w->grad2d.as<float>() + (size_t)v * kG2Stride * (size_t)n;
         V.counts = prof_counts(ctx);
         V.tile_base = w->tile_base[v];
@@ -1431,13 +1432,10 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
                              words + WW_COUNTER, w->blocks, s);
         if (prof_counts(ctx)) ctx->prof_fwd += w->nv;
     }
-    for (int v = 0; v < w->nv; ++v) {
+    {
         // the forward wrote the L1 terms' gradients and one partial quadruple per tile
-        const int64_t P = (int64_t)w->cams[v].width * w->cams[v].height;
         Stage st_(ctx, "loss");
-        launch_loss_final(w->partials.as<float>() + 4 * (size_t)w->tile_base[v], (int)w->L[v].T, P, l.lambda_rgb,
-                          l.lambda_depth, w->words.as<float>() + WW_DSCALE + v, loss_dev ? loss_dev + v : nullptr,
-                          psnr_dev ? psnr_dev + v : nullptr, s);
+        launch_loss_final_views(w->views.as<ViewK>(), w->nv, w->total_tiles, loss_dev, psnr_dev, s);
     }
     {
         Stage st_(ctx, "raster_bwd");

@@ -201,6 +201,7 @@ struct ImageK {
 struct LossK {
     const float *trgb, *tdepth;
     float *drgb, *ddepth, *partials;
+    float *ddepth_scale;  // where the loss reduction of a window view writes its 1/P_v
     float lrgb, ldepth, inv3P;
 };
 
@@ -281,6 +282,10 @@ int64_t loss_partials_size(int64_t P);
 // the depth term's 1/P_v (all device scalars, nullable).
 void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
                        float *loss, float *psnr, hipStream_t s);
+// The same for every view of a window at once (view v: its partials, tile count, pixel count,
+// loss weights and 1/P_v slot from views_dev[v]; loss[v], psnr[v], nullable).
+void launch_loss_final_views(const ViewK *views_dev, int nv, uint32_t total_items, float *loss, float *psnr,
+                             hipStream_t s);
 void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float *trgb,
                     const float *tdepth, float lrgb, float ldepth, float *drgb, float *ddepth,
                     float *ddepth_scale, float *partials, float *loss, float *psnr, hipStream_t s);

@@ -57,9 +57,10 @@ k_loss_partial(int64_t P, const float *__restrict__ rgb, const float *__restrict
     if (threadIdx.x < 4) partials[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(kLossThreads)
-k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
-             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
+// Loss and PSNR from nb per-tile partial quadruples (one workgroup of kLossThreads), in FP64 and
+// a fixed order.
+__device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
+                            float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
 {
     __shared__ double red[4][kLossThreads];
     double acc[4] = {0, 0, 0, 0};
@@ -83,6 +84,25 @@ k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, 
         const double mse = se / (3.0 * (double)P);
         if (psnr) *psnr = (float)(mse > 0 ? 10.0 * log10(1.0 / mse) : INFINITY);
     }
+}
+
+__global__ void __launch_bounds__(kLossThreads)
+k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
+             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
+{
+    loss_reduce(partials, nb, P, lrgb, ldepth, ddepth_scale, loss, psnr);
+}
+
+// One workgroup per view of a window: view v's tiles are window items [tile_base_v, tile_base_v+1).
+__global__ void __launch_bounds__(kLossThreads)
+k_loss_final_views(const ViewK *__restrict__ views, int nv, uint32_t total_items, float *__restrict__ loss,
+                   float *__restrict__ psnr)
+{
+    const int v = blockIdx.x;
+    const ViewK &V = views[v];
+    const uint32_t end = v + 1 < nv ? views[v + 1].tile_base : total_items;
+    loss_reduce(V.loss.partials, (int)(end - V.tile_base), (int64_t)V.W * V.H, V.loss.lrgb, V.loss.ldepth,
+                V.loss.ddepth_scale, loss ? loss + v : nullptr, psnr ? psnr + v : nullptr);
 }
 
 __device__ inline float *plane_ptr(const GradK &g, int row)
@@ -168,6 +188,14 @@ void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, flo
                        float *loss, float *psnr, hipStream_t s)
 {
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
+                       loss, psnr);
+}
+
+void launch_loss_final_views(const ViewK *views_dev, int nv, uint32_t total_items, float *loss, float *psnr,
+                             hipStream_t s)
+{
+    if (nv <= 0) return;
+    hipLaunchKernelGGL(k_loss_final_views, dim3((unsigned)nv), dim3(kLossThreads), 0, s, views_dev, nv, total_items,
                        loss, psnr);
 }
 
