@@ -199,6 +199,40 @@ __device__ __forceinline__ int reduce_term(int lane)
     return i == 1 ? -1 : base + (i == 0 ? 3 : 4);
 }
 
+// Twenty wave sums at once, the ten terms of two list entries (u: the first, v: the second), by
+// the same transposed butterfly: 20 values shrink to 10, 5, 3, 2 and 1 per lane over lane
+// distances 32 (row swaps), 16 (row swaps), 1 and 2 (DPP) and 4 (an LDS swizzle, outside the VALU),
+// and one rotation by 8 within each row adds its two halves. Every lane ends with the full sum of
+// one term of one entry; reduce20_slot names, for one lane per term, which.
+__device__ __forceinline__ float reduce20(const float u[10], const float v[10], int lane)
+{
+    float a[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) a[c] = swap_add<32>(u[c], v[c]);  // entry lane >> 5, term c
+    float q[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) q[c] = swap_add<16>(a[c], a[c + 5]);
+    const float r0 = dpp_add<0xB1, 1>(q[0], q[3], lane), r1 = dpp_add<0xB1, 1>(q[1], q[4], lane);
+    const float r2 = q[2] + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(q[2]), 0xB1, 0xf, 0xf, false));
+    const float t0 = dpp_add<0x4E, 2>(r0, r2, lane);
+    const float t1 = r1 + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(r1), 0x4E, 0xf, 0xf, false));
+    const bool b2 = lane & 4;
+    const float send = b2 ? t0 : t1, mine = b2 ? t1 : t0;
+    // ds_swizzle bitmask mode: and 0x1f, or 0, xor 4 (the partner across lane distance 4)
+    float d = mine + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x101F));
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, false));  // row_ror:8
+    return d;
+}
+
+// Which sum reduce20 leaves in this lane, for one lane per sum: 10 e + term for entry e (u: 0,
+// v: 1), or -1 (a copy). Row r of 16 lanes holds sums 5 r + {0, 3, 2, -, 1, 4} in its lanes 0-5.
+__device__ __forceinline__ int reduce20_slot(int lane)
+{
+    const int r = lane >> 4, i = lane & 15;
+    const int off = i == 0 ? 0 : i == 1 ? 3 : i == 2 ? 2 : i == 4 ? 1 : i == 5 ? 4 : -1;
+    return off < 0 ? -1 : 5 * r + off;
+}
+
 // Forward of one tile of one view by a workgroup of NT threads (one pixel each; the tile is
 // tile_w x tile_h = NT pixels). COUNT: accumulate the profiling work counters; NCON: count each
 // pixel's blended pairs (for the n_contrib output; implied by COUNT).
@@ -438,6 +472,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int lane = __lane_id();
     const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
     const bool red_lane = term >= 0;
+    const int slot20 = reduce20_slot(lane);  // the same after reduce20
     const int wid = tid / kWave;
     const int sidx = tile / (kSuper * kSuper), sl = tile % (kSuper * kSuper);
     const int tx = (sidx % rk.supers_x) * kSuper + sl % kSuper, ty = (sidx / rk.supers_x) * kSuper + sl / kSuper;
@@ -510,16 +545,12 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
             const BwdPair p1 = bwd_decide(a1, b1, base + k1 < L, px, py, qcut, rk);
-            const uint64_t any0 = __ballot(p0.take), any1 = __ballot(p1.take);
-            if (!(any0 | any1)) continue;  // no lane blended either entry: nothing to add or update
+            if (!__ballot(p0.take || p1.take)) continue;  // no lane blended either entry: nothing to do
             float g0[10], g1[10];
             bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
             bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
-            const float t0 = reduce10(g0, lane), t1 = reduce10(g1, lane);
-            if (red_lane) {
-                if (any0) atomicAdd(&sacc[k0][term], t0);
-                if (any1) atomicAdd(&sacc[k1][term], t1);
-            }
+            const float t = reduce20(g0, g1, lane);
+            if (slot20 >= 0) atomicAdd(&sacc[slot20 < 10 ? k0 : k1][slot20 % 10], t);
         }
         if (i == 0) {
             const int k0 = slist[wid][0];
