@@ -33,8 +33,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "22693412e8090e841e46d6b63123279815585200f30020478b5c58dcb5c17af5",
-                     "tile": "16x16", "fetch_bytes": 46714803, "write_bytes": 16498757},
+    "k_raster_bwd": {"source_sha256": "7450c8ad8200e52caf297c70651bade868f3687dd0ce5a6e0197f46f85970d96",
+                     "tile": "16x16", "fetch_bytes": 46715730, "write_bytes": 16498766},
 }
 
 
