@@ -40,7 +40,7 @@ typedef enum {
     FGS_ERR_INVALID_ARG = -1, /* bad size, stride, null pointer or option; nothing enqueued */
     FGS_ERR_CAPACITY = -2,    /* a device buffer was too small; fgs_last_error gives the size */
     FGS_ERR_HIP = -3,         /* a HIP runtime call failed; fgs_last_error gives its message */
-    FGS_ERR_UNSUPPORTED = -5  /* no gfx950 device, or an option this build does not provide */
+    FGS_ERR_UNSUPPORTED = -5  /* no gfx950 device, or an option the library does not provide */
 } fgs_status;
 
 typedef struct fgs_ctx fgs_ctx; /* opaque: stream, workspace, device status words */
