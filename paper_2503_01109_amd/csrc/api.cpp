@@ -471,21 +471,19 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     {
         // one pair per covered super-tile, in depth order
         Stage st_(ctx, "bin");
-        launch_scan_counts(sp.ids, po.count, g.n, ctx->blocksums.as<uint32_t>(), status_words(ctx), po.kpart,
-                           project_blocks(g.n), ktotal, s);
+        launch_scan_counts(sp.ids, po.count, g.n, ctx->blocksums.as<uint32_t>(), s);
+        launch_emit(sp.ids, po.count, po.rect, ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n,
+                    supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
+                    ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs,
+                    nullptr, po.kpart, project_blocks(g.n), ktotal, s);
     }
     if (K_check) {
+        // the pair count is known once the scan is complete (the emission of an oversized set
+        // stops at the capacity; the caller grows the state and starts over)
         fgs_status st2 = read_words(ctx);
         if (st2 != FGS_OK) return st2;
         *K_check = ctx->host_words[ST_PAIRS];
         if (*K_check > L.cap) return FGS_ERR_CAPACITY;
-    }
-    {
-        Stage st_(ctx, "bin");
-        launch_emit(sp.ids, po.count, po.rect, ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n,
-                    supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
-                    ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs,
-                    nullptr, s);
     }
     const uint2 *sranges = ctx->bin_sranges.as<uint2>();
     {
@@ -1403,12 +1401,12 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
         {
             Stage st_(ctx, "bin");
             launch_scan_counts(ctx->idA.as<uint32_t>(), ctx->count.as<uint32_t>(), all, ctx->blocksums.as<uint32_t>(),
-                               status_words(ctx), w->kpart.as<uint32_t>(), (int64_t)w->nv * pb, cw + W_KTOTAL, s);
+                               s);
             launch_emit(ctx->idA.as<uint32_t>(), ctx->count.as<uint32_t>(), ctx->rect.as<uint2>(),
                         ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), all, 0, kSuperShift, w->cap_all,
                         ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(),
-                        ctx->start_rank.as<uint32_t>(), status_words(ctx), cw + W_NSUP, nullptr, s, view_tab,
-                        (uint32_t)n);
+                        ctx->start_rank.as<uint32_t>(), status_words(ctx), cw + W_NSUP, nullptr,
+                        w->kpart.as<uint32_t>(), (int64_t)w->nv * pb, cw + W_KTOTAL, s, view_tab, (uint32_t)n);
         }
         {
             Stage st_(ctx, "tile_sort");

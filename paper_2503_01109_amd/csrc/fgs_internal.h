@@ -131,15 +131,13 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             const uint32_t *n_dev, int64_t n_cap, int key_bits, const SortWS &ws,
                             hipStream_t s);
 
-// Exclusive scan of count[ids[r]] over depth ranks r, by blocks: blocksums (scan_blocks(n) + 1
-// words) receives the scanned block sums and, at [scan_blocks(n)], the total number of pairs.
-// The projection's per-workgroup counts kpart are summed into *ktotal and status[ST_PAIRS]
-// ((tile, gaussian) pairs) and status[ST_VISIBLE].
+// Per-block sums of count[ids[r]] over depth ranks r (scan_blocks(n) words of blocksums), the
+// first half of the scan that launch_emit completes.
 int64_t scan_blocks(int64_t n);
-void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s);
+void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums, hipStream_t s);
 
-// Emit one (key, gaussian id) pair per covered tile in depth order; with shift > 0 the keys are
+// Completes the scan (each block adds the block sums before it) and emits one (key, gaussian id)
+// pair per covered tile in depth order; with shift > 0 the keys are
 // super-tiles (tile rectangle >> shift, keys_x super-tiles per row) and carry, above bit
 // kBoxShift, the box of the super-tile's tiles that the gaussian covers. Several views binned at
 // once (view_tab non-null): ids are values v view_n + i, and view v's keys are view_tab[v].y + its
@@ -147,12 +145,15 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 // words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
 // (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
-// depth order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk.
+// depth order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk. The
+// projection's per-workgroup counts kpart (proj_blocks workgroups) are summed into *ktotal and
+// status[ST_PAIRS] ((tile, gaussian) pairs) and status[ST_VISIBLE].
 int64_t emit_chunks(int64_t cap);
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
-                 uint32_t *host_status, hipStream_t s, const uint2 *view_tab = nullptr, uint32_t view_n = 0);
+                 uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,
+                 const uint2 *view_tab = nullptr, uint32_t view_n = 0);
 
 // Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
 // are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by the key bits

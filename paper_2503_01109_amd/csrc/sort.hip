@@ -266,38 +266,6 @@ k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ co
     if (threadIdx.x == 0) blocksums[blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the block sums in place; the total number of pairs goes to
-// blocksums[nb] and to the status words. Also sums the projection's per-block counts (kpart,
-// npb blocks) into *ktotal, status[ST_PAIRS] (tile pairs) and status[ST_VISIBLE].
-__global__ void __launch_bounds__(kSortThreads)
-k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart,
-           int npb, uint32_t *__restrict__ ktotal)
-{
-    __shared__ uint32_t w[8];
-    uint32_t carry = 0;
-    for (int base = 0; base < nb; base += kSortThreads) {
-        const int j = base + threadIdx.x;
-        const uint32_t v = j < nb ? blocksums[j] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, w, &tot);
-        if (j < nb) blocksums[j] = carry + ex;
-        carry += tot;
-    }
-    uint32_t pairs = 0, vis = 0;
-    for (int j = threadIdx.x; j < npb; j += kSortThreads) {
-        pairs += kpart[2 * j];
-        vis += kpart[2 * j + 1];
-    }
-    uint32_t tp, tv;
-    block_excl_scan(pairs, w, &tp);
-    block_excl_scan(vis, w, &tv);
-    if (threadIdx.x == 0) {
-        blocksums[nb] = carry;
-        *ktotal = tp;
-        status[ST_PAIRS] = tp;
-        status[ST_VISIBLE] = tv;
-    }
-}
 
 // Per-rank exclusive offsets: offsets[r] = block offset + prefix of count[ids[.]] inside the
 // block (same partition as k_count_reduce); offsets[n] = total. Also gathers the tile rectangles
@@ -305,10 +273,35 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
 // emission chunk.
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-             int64_t n, const uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ offsets,
-             uint2 *__restrict__ rect_sorted, uint32_t *__restrict__ start_rank, uint32_t max_chunks)
+             int64_t n, const uint32_t *__restrict__ blocksums, uint32_t *__restrict__ offsets,
+             uint2 *__restrict__ rect_sorted, uint32_t *__restrict__ start_rank, uint32_t max_chunks,
+             uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart, int npb,
+             uint32_t *__restrict__ ktotal)
 {
     __shared__ uint32_t w[8];
+    // this block's first offset: the sum of the block sums before it
+    uint32_t boff;
+    {
+        uint32_t pre = 0;
+        for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kSortThreads) pre += blocksums[j];
+        block_excl_scan(pre, w, &boff);
+    }
+    if (blockIdx.x == 0) {
+        // the projection's per-workgroup counts: (tile, gaussian) pairs and visible gaussians
+        uint32_t pairs = 0, vis = 0;
+        for (int j = threadIdx.x; j < npb; j += kSortThreads) {
+            pairs += kpart[2 * j];
+            vis += kpart[2 * j + 1];
+        }
+        uint32_t tp, tv;
+        block_excl_scan(pairs, w, &tp);
+        block_excl_scan(vis, w, &tv);
+        if (threadIdx.x == 0) {
+            *ktotal = tp;
+            status[ST_PAIRS] = tp;
+            status[ST_VISIBLE] = tv;
+        }
+    }
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
     uint32_t c[kScanItems], id[kScanItems], s = 0;
 #pragma unroll
@@ -318,7 +311,7 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
         s += c[k];
     }
     uint32_t tot;
-    uint32_t off = blocksums[blockIdx.x] + block_excl_scan(s, w, &tot);
+    uint32_t off = boff + block_excl_scan(s, w, &tot);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) {
@@ -334,7 +327,7 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
         }
         off += c[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = blocksums[nb];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[n] = boff + tot;  // the last block: the total
 }
 
 // Largest r in [lo, hi] with a[r] <= v (a non-decreasing, a[lo] <= v).
@@ -734,14 +727,11 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 
 int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
 
-void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums,
-                        uint32_t *status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s)
+void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums, hipStream_t s)
 {
     const int nb = (int)scan_blocks(n);
     if (nb > 0)
         hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, kpart, (int)proj_blocks,
-                       ktotal);
 }
 
 int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 1; }
@@ -749,12 +739,14 @@ int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
-                 uint32_t *host_status, hipStream_t s, const uint2 *view_tab, uint32_t view_n)
+                 uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,
+                 const uint2 *view_tab, uint32_t view_n)
 {
-    // blocksums holds the scanned per-block sums in [0, nb) and the total at [nb]
+    // blocksums holds the per-block sums of the counts in [0, nb)
     const int nb = (int)scan_blocks(n);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums,
-                       nb, offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap));
+                       offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart, (int)proj_blocks,
+                       ktotal);
     hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, ids,
                        offsets, start_rank, n, keys_x, shift, cap, view_tab, view_n, keys, vals, status, n_pairs_dev,
                        host_status);
