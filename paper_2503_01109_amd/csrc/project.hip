@@ -333,7 +333,9 @@ __device__ inline void adam_update(const AdamK &adam, const ParamsK &g, int64_t 
 // zeroes the record it read, so grad2d is all-zero again for the next backward. The gaussian's
 // 14 parameter gradients plus grad_in (nullable: gradients of earlier views) are written to
 // grad_out (nullable) and, when adam.m.mean is set, applied by Adam. Every access is coalesced.
-__global__ void __launch_bounds__(256)
+// Four waves per SIMD (at most 128 VGPRs, no spills) hide more of the memory latency than the
+// three its FP64 chain rule would otherwise leave room for.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad_in, GradK grad_out, AdamK adam)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
