@@ -77,19 +77,33 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
     hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One block per digit: exclusive scan of the digit's row over blocks, row total to totals.
+// One block per digit: exclusive scan of the digit's row over blocks, row total to totals. Each
+// thread scans a contiguous run of the row serially, so one block-wide scan covers rows of up to
+// 256 x kRowRun blocks (longer rows take several rounds).
+constexpr int kRowRun = 16;
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ totals)
 {
     __shared__ uint32_t w[8];
     uint32_t *row = hist + (size_t)blockIdx.x * G;
+    const int per = min((G + kSortThreads - 1) / kSortThreads, kRowRun);
     uint32_t carry = 0;
-    for (int base = 0; base < G; base += kSortThreads) {
-        const int j = base + threadIdx.x;
-        const uint32_t v = j < G ? row[j] : 0u;
+    for (int base = 0; base < G; base += per * kSortThreads) {
+        const int j0 = base + threadIdx.x * per;
+        uint32_t v[kRowRun], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kRowRun; ++k) {
+            v[k] = k < per && j0 + k < G ? row[j0 + k] : 0u;
+            sum += v[k];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, w, &tot);
-        if (j < G) row[j] = carry + ex;
+        uint32_t ex = carry + block_excl_scan(sum, w, &tot);
+#pragma unroll
+        for (int k = 0; k < kRowRun; ++k)
+            if (k < per && j0 + k < G) {
+                row[j0 + k] = ex;
+                ex += v[k];
+            }
         carry += tot;
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
