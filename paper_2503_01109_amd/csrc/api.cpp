@@ -496,7 +496,7 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         if (!one_pass) launch_ranges(keys, nsup_pairs, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
         launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
         launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, s);
-        launch_bin_place(bw, keys, svals, sranges, sp.ranges, sp.vals, 0, s);
+        launch_bin_place(bw, keys, svals, sranges, sp.ranges, sp.vals, s);
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");
@@ -1420,7 +1420,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
             launch_bin_tiles(bw, nsup, w->cap_all, cw + W_KTOTAL, w->wranges.as<uint2>(), status_words(ctx),
                              cw + W_NPAIRS, w->hs_dev, s);
             launch_bin_place(bw, keys, svals, ctx->bin_sranges.as<uint2>(), w->wranges.as<uint2>(),
-                             w->wvals.as<uint32_t>(), (uint32_t)n, s);
+                             w->wvals.as<uint32_t>(), s);
         }
     }
     uint32_t *words = w->words.as<uint32_t>();

@@ -140,8 +140,8 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 // pair per covered tile in depth order; with shift > 0 the keys are
 // super-tiles (tile rectangle >> shift, keys_x super-tiles per row) and carry, above bit
 // kBoxShift, the box of the super-tile's tiles that the gaussian covers. Several views binned at
-// once (view_tab non-null): ids are values v view_n + i, and view v's keys are view_tab[v].y + its
-// own key with view_tab[v].x keys per row (keys_x unused). offsets is scratch of n + 1
+// once (view_tab non-null): ids are values v view_n + i, view v's keys are view_tab[v].y + its
+// own key with view_tab[v].x keys per row (keys_x unused), and the value emitted is i. offsets is scratch of n + 1
 // words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
 // (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
@@ -162,9 +162,7 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 //   launch_bin_tiles:  prefixes over chunks and tiles, the tile ranges, and the capacity check of
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
 //                      overflow);
-//   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries);
-//                      with view_n > 0 the entries are view-offset values v view_n + id and the
-//                      lists receive id.
+//   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
 // The tiles an entry covers come from the box in its key.
 struct BinWS {
     uint32_t *cstart;      // nsup + 1
@@ -183,7 +181,7 @@ void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, co
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
                       uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s);
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
-                      const uint2 *ranges, uint32_t *vals, uint32_t view_n, hipStream_t s);
+                      const uint2 *ranges, uint32_t *vals, hipStream_t s);
 
 // [start, end) of the runs of keys 0..T-1 in the sorted keys (n_dev of them), comparing key & mask.
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, uint2 *ranges, int64_t T, uint32_t mask,

@@ -411,12 +411,14 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
             const uint32_t dy = idx / w;
             const uint32_t kx = tx0 + (idx - dy * w), ky = ty0 + dy;
             const uint32_t id = ids[r];
-            // several views: the value is v view_n + id, keys count on from the view's first key
-            const uint2 vt = view_tab ? view_tab[id / view_n] : make_uint2((uint32_t)tiles_x, 0u);
+            // several views: the value is v view_n + i; keys count on from view v's first key and
+            // the value emitted is i, the id within its view
+            const uint32_t v = view_tab ? id / view_n : 0u;
+            const uint2 vt = view_tab ? view_tab[v] : make_uint2((uint32_t)tiles_x, 0u);
             uint32_t key = vt.y + ky * vt.x + kx;
             if (shift > 0) key |= cover_box(rc, kx, ky) << kBoxShift;
             keys[j] = key;
-            vals[j] = id;
+            vals[j] = id - v * view_n;
         }
         __syncthreads();
     }
@@ -602,12 +604,11 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, cons
     }
 }
 
-// Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order
-// (view_n > 0: entries are view-offset values v view_n + id; the lists get id).
+// Per chunk: writes each entry's gaussian id into the lists of the tiles it covers, in order.
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_place(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals, const uint2 *__restrict__ sranges,
             const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ csuper,
-            const uint32_t *__restrict__ nchunks, uint32_t view_n, const uint32_t *__restrict__ chist,
+            const uint32_t *__restrict__ nchunks, const uint32_t *__restrict__ chist,
             const uint2 *__restrict__ ranges, const uint32_t *__restrict__ ok, uint32_t *__restrict__ vals)
 {
     constexpr int NB = kSuper * kSuper, NW = kSortThreads / kWave;
@@ -637,7 +638,7 @@ k_bin_place(const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ sva
                     if ((m >> b) & 1u) {
                         uint32_t pos = run[b] + (uint32_t)__popcll(bal[b] & lt);
                         for (int w2 = 0; w2 < wid; ++w2) pos += wtot[w2][b];
-                        vals[pos] = view_n ? id % view_n : id;  // the id within its view
+                        vals[pos] = id;
                     }
                 }
             }
@@ -787,10 +788,10 @@ void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *kto
 }
 
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
-                      const uint2 *ranges, uint32_t *vals, uint32_t view_n, hipStream_t s)
+                      const uint2 *ranges, uint32_t *vals, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_place, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, svals,
-                       sranges, b.cstart, b.csuper, b.nchunks, view_n, b.chist, ranges, b.ok, vals);
+                       sranges, b.cstart, b.csuper, b.nchunks, b.chist, ranges, b.ok, vals);
 }
 
 void launch_ranges(const uint32_t *keys, const uint32_t *n_dev, uint2 *ranges, int64_t T, uint32_t mask,
