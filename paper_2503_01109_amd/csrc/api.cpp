@@ -489,7 +489,7 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     {
         // super-tile lists, then the tile ranges
         Stage st_(ctx, "tile_sort");
-        const SortWS sws = sort_ws(ctx, L.cap);
+        const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
         uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
                                            ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
         const bool one_pass = sbits <= 8;
