@@ -248,7 +248,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->dkB.ensure(N * 4));
     HIP_TRY(ctx, ctx->idA.ensure(N * 4));
     HIP_TRY(ctx, ctx->idB.ensure(N * 4));
-    HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks(nn) + 2) * 4));
+    HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks_cap(nn) + 2) * 4));
     HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
     HIP_TRY(ctx, ctx->kpart.ensure((size_t)project_blocks(nn) * 2 * 4));
     HIP_TRY(ctx, ctx->rect_sorted.ensure(N * sizeof(uint2)));

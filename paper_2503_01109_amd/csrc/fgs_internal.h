@@ -134,9 +134,10 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             const uint32_t *n_dev, int64_t n_cap, int key_bits, const SortWS &ws,
                             hipStream_t s);
 
-// Per-block sums of count[ids[r]] over depth ranks r (scan_blocks(n) words of blocksums), the
-// first half of the scan that launch_emit completes.
+// Per-block sums of count[ids[r]] over depth ranks r (scan_blocks(n) words of blocksums, at most
+// scan_blocks_cap(n) for any count up to n), the first half of the scan that launch_emit completes.
 int64_t scan_blocks(int64_t n);
+int64_t scan_blocks_cap(int64_t n);
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums, hipStream_t s);
 
 // Completes the scan (each block adds the block sums before it) and emits one (key, gaussian id)
@@ -152,7 +153,7 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 // projection's per-workgroup counts kpart (proj_blocks workgroups) are summed into *ktotal and
 // status[ST_PAIRS] ((tile, gaussian) pairs) and status[ST_VISIBLE].
 int64_t emit_chunks(int64_t cap);
-void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
                  uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,

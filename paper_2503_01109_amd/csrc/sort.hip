@@ -22,8 +22,11 @@ namespace fgs {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kScanItems = 4;  // elements per thread in the count scan
-constexpr int kScanBlock = kSortThreads * kScanItems;
+// The count scan takes 2 ranks per thread up to 2^20 ranks (more workgroups to hide the gathers'
+// latency), else 4. Each apply workgroup adds the block sums before it itself while there are at
+// most kScanFold workgroups; beyond that a single-workgroup pass scans them first.
+constexpr int kScanFold = 4096;
+__host__ __device__ inline int scan_items(int64_t n) { return n <= ((int64_t)1 << 20) ? 2 : 4; }
 constexpr uint32_t kEmitChunk = 1024;  // pairs per emission block iteration
 constexpr uint32_t kEmitSpan = 2048;   // ranks of a chunk's offsets staged in LDS
 
@@ -264,16 +267,17 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     }
 }
 
-// Per block: sum of count[ids[r]] over the block's kScanBlock ranks.
+// Per block: sum of count[ids[r]] over the block's 256 ITEMS ranks.
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, int64_t n,
                uint32_t *__restrict__ blocksums)
 {
     __shared__ uint32_t w[8];
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = ((int64_t)blockIdx.x * kSortThreads + threadIdx.x) * ITEMS;
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
+    for (int k = 0; k < ITEMS; ++k)
         if (base + k < n) s += count[ids[base + k]];
     uint32_t tot;
     block_excl_scan(s, w, &tot);
@@ -281,13 +285,54 @@ k_count_reduce(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ co
 }
 
 
+// Single block: exclusive scan of the block sums in place (the pass before k_scan_apply when there
+// are more than kScanFold of them). Also sums the projection's per-block counts (kpart, npb
+// blocks) into *ktotal, status[ST_PAIRS] (tile pairs) and status[ST_VISIBLE].
+__device__ inline void sum_kpart(const uint32_t *__restrict__ kpart, int npb, uint32_t *__restrict__ status,
+                                 uint32_t *__restrict__ ktotal, uint32_t *w)
+{
+    uint32_t pairs = 0, vis = 0;
+    for (int j = threadIdx.x; j < npb; j += kSortThreads) {
+        pairs += kpart[2 * j];
+        vis += kpart[2 * j + 1];
+    }
+    uint32_t tp, tv;
+    block_excl_scan(pairs, w, &tp);
+    block_excl_scan(vis, w, &tv);
+    if (threadIdx.x == 0) {
+        *ktotal = tp;
+        status[ST_PAIRS] = tp;
+        status[ST_VISIBLE] = tv;
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart,
+           int npb, uint32_t *__restrict__ ktotal)
+{
+    __shared__ uint32_t w[8];
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kSortThreads) {
+        const int j = base + threadIdx.x;
+        const uint32_t v = j < nb ? blocksums[j] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, w, &tot);
+        if (j < nb) blocksums[j] = carry + ex;
+        carry += tot;
+    }
+    sum_kpart(kpart, npb, status, ktotal, w);
+}
+
 // Per-rank exclusive offsets: offsets[r] = block offset + prefix of count[ids[.]] inside the
 // block (same partition as k_count_reduce); offsets[n] = total. Also gathers the tile rectangles
 // of the gaussians that cover at least one tile into depth order, and the first rank of every
 // emission chunk.
+// scanned: blocksums already hold exclusive prefixes (k_scan_top ran); otherwise each block adds
+// the block sums before it and block 0 sums the projection's counts.
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads)
 k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ count, const uint2 *__restrict__ rect,
-             int64_t n, const uint32_t *__restrict__ blocksums, uint32_t *__restrict__ offsets,
+             int64_t n, const uint32_t *__restrict__ blocksums, bool scanned, uint32_t *__restrict__ offsets,
              uint2 *__restrict__ rect_sorted, uint32_t *__restrict__ start_rank, uint32_t max_chunks,
              uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart, int npb,
              uint32_t *__restrict__ ktotal)
@@ -295,31 +340,18 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
     __shared__ uint32_t w[8];
     // this block's first offset: the sum of the block sums before it
     uint32_t boff;
-    {
+    if (scanned) {
+        boff = blocksums[blockIdx.x];
+    } else {
         uint32_t pre = 0;
         for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kSortThreads) pre += blocksums[j];
         block_excl_scan(pre, w, &boff);
+        if (blockIdx.x == 0) sum_kpart(kpart, npb, status, ktotal, w);
     }
-    if (blockIdx.x == 0) {
-        // the projection's per-workgroup counts: (tile, gaussian) pairs and visible gaussians
-        uint32_t pairs = 0, vis = 0;
-        for (int j = threadIdx.x; j < npb; j += kSortThreads) {
-            pairs += kpart[2 * j];
-            vis += kpart[2 * j + 1];
-        }
-        uint32_t tp, tv;
-        block_excl_scan(pairs, w, &tp);
-        block_excl_scan(vis, w, &tv);
-        if (threadIdx.x == 0) {
-            *ktotal = tp;
-            status[ST_PAIRS] = tp;
-            status[ST_VISIBLE] = tv;
-        }
-    }
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-    uint32_t c[kScanItems], id[kScanItems], s = 0;
+    const int64_t base = ((int64_t)blockIdx.x * kSortThreads + threadIdx.x) * ITEMS;
+    uint32_t c[ITEMS], id[ITEMS], s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         id[k] = base + k < n ? ids[base + k] : 0u;
         c[k] = base + k < n ? count[id[k]] : 0u;
         s += c[k];
@@ -327,7 +359,7 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
     uint32_t tot;
     uint32_t off = boff + block_excl_scan(s, w, &tot);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         if (base + k < n) {
             offsets[base + k] = off;
             if (c[k]) {
@@ -740,18 +772,27 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
     return nullptr;
 }
 
-int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+int64_t scan_blocks(int64_t n)
+{
+    const int64_t per = (int64_t)kSortThreads * scan_items(n);
+    return (n + per - 1) / per;
+}
+
+int64_t scan_blocks_cap(int64_t n) { return (n + 2 * kSortThreads - 1) / (2 * kSortThreads) + 1; }
 
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums, hipStream_t s)
 {
     const int nb = (int)scan_blocks(n);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
+    if (nb <= 0) return;
+    if (scan_items(n) == 2)
+        hipLaunchKernelGGL(k_count_reduce<2>, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
+    else
+        hipLaunchKernelGGL(k_count_reduce<4>, dim3(nb), dim3(kSortThreads), 0, s, ids, count, n, blocksums);
 }
 
 int64_t emit_chunks(int64_t cap) { return (cap + kEmitChunk - 1) / kEmitChunk + 1; }
 
-void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, const uint32_t *blocksums,
+void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
                  uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,
@@ -759,9 +800,19 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 {
     // blocksums holds the per-block sums of the counts in [0, nb)
     const int nb = (int)scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb > 0 ? nb : 1), dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums,
-                       offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart, (int)proj_blocks,
-                       ktotal);
+    const bool scanned = nb > kScanFold;
+    if (scanned)
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, kpart,
+                           (int)proj_blocks, ktotal);
+    const dim3 grid(nb > 0 ? nb : 1);
+    if (scan_items(n) == 2)
+        hipLaunchKernelGGL(k_scan_apply<2>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums, scanned,
+                           offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart,
+                           (int)proj_blocks, ktotal);
+    else
+        hipLaunchKernelGGL(k_scan_apply<4>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums, scanned,
+                           offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart,
+                           (int)proj_blocks, ktotal);
     hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, ids,
                        offsets, start_rank, n, keys_x, shift, cap, view_tab, view_n, keys, vals, status, n_pairs_dev,
                        host_status);

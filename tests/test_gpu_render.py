@@ -236,6 +236,27 @@ def test_empty_and_culled(fgs, ctx):
         assert np.all(host(out["n_contrib"]) == 0)
 
 
+def test_many_gaussians_take_the_two_level_scan(fgs, ctx):
+    """4.5M gaussians, all but 2,000 behind the camera: the scan of the covered super-tiles then has
+    more block sums than one apply workgroup adds up itself (a separate pass scans them first),
+    and the result must equal the render of the 2,000 alone, bit for bit (their order by depth,
+    then by index, does not change)."""
+    small = synth.scene_small(5)
+    cam = synth.camera_small()
+    n = 4_500_000
+    big = np.zeros((14, n), np.float32)
+    big[2] = -1.0  # behind the camera
+    big[6] = 1.0
+    idx = np.sort(synth.rng(11).choice(n, small.shape[1], replace=False))
+    big[:, idx] = small
+    opts = fgs.RenderOpts()
+    a = fgs.render(ctx, params_dev(small), small.shape[1], cam, opts)
+    b = fgs.render(ctx, dev(big), n, cam, opts, max_pairs=1 << 20)
+    for k in ("rgb", "depth", "alpha", "T_final", "n_contrib"):
+        assert np.array_equal(host(a[k]), host(b[k])), k
+    del b, big
+
+
 def test_invariant_weights_sum_to_one(fgs, ctx):
     """P4 on the GPU: alpha + T_final = 1 within FP32 rounding, at every pixel."""
     p = synth.scene_small(4)
