@@ -62,22 +62,28 @@ k_loss_partial(int64_t P, const float *__restrict__ rgb, const float *__restrict
 __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
                             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
 {
-    __shared__ double red[4][kLossThreads];
+    constexpr int NW = kLossThreads / kWave;
+    __shared__ double red[NW][4];
     double acc[4] = {0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += kLossThreads)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] += (double)partials[4 * b + q];
+    // wave sums (butterfly over the 64 lanes), then the waves' sums in order
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+    const int wid = threadIdx.x / kWave;
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wid][q] = acc[q];
     __syncthreads();
-    for (int s = kLossThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        const double l1c = red[0][0], se = red[1][0], l1d = red[2][0], nv = red[3][0];
+        double t[4] = {0, 0, 0, 0};
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] += red[w][q];
+        const double l1c = t[0], se = t[1], l1d = t[2], nv = t[3];
         const double scale = nv > 0 ? 1.0 / nv : 0.0;
         if (ddepth_scale) *ddepth_scale = (float)scale;
         if (loss) *loss = (float)((double)lrgb * l1c / (3.0 * (double)P) + (double)ldepth * l1d * scale);
