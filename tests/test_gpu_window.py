@@ -248,6 +248,24 @@ def test_profiled_window_step_runs_eagerly(fgs, ctx):
     win.close()
 
 
+def test_empty_window(fgs, ctx):
+    """No gaussians: every view renders the background, so each view's loss is the L1 loss of the
+    background against its target, as the plain mapping step reports it, and nothing faults."""
+    import torch
+    cams, tiles = small_views()
+    targets = random_targets(cams, 40)
+    pd = dev(np.zeros((14, 1), np.float32))
+    lw = torch.zeros(len(cams), device="cuda")
+    lm = torch.zeros(len(cams), device="cuda")
+    win = fgs.Window(ctx, cams, tiles, 0)
+    win.step(pd, 0, fgs.Adam.like(pd), targets, fgs.RenderOpts(), loss=lw, graph=False)
+    win.close()
+    fgs.map_step(ctx, pd, 0, fgs.Adam.like(pd), cams, targets, fgs.RenderOpts(), loss=lm)
+    ctx.check()
+    assert np.all(np.isfinite(host(lw)))
+    np.testing.assert_allclose(host(lw), host(lm), rtol=1e-6)
+
+
 def test_full_window_workload(fgs, ctx):
     """The 8-view window over the 500k-gaussian box scene (four 640x480, four 1200x680 views) in the
     launch configuration the benchmark times.
