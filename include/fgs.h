@@ -221,15 +221,15 @@ fgs_status fgs_window_create(fgs_ctx *ctx, int32_t n_views, const fgs_camera *ca
                              int32_t blocks_per_cu, fgs_window **out);
 fgs_status fgs_window_destroy(fgs_window *w);
 
-/* One mapping iteration over the window, with the semantics of fgs_map_step: every view is
- * binned and ordered, all views' tiles are rendered (Eq. 1) by ONE launch over the (view, tile)
- * items, the L1 terms of Eq. 15 are taken per view, ONE launch runs
- * every view's backward over the same items, and one pass per gaussian sums the views' gradients
- * through their projections and applies Adam. targets: [host] array of n_views. use_graph != 0 captures
+/* One mapping iteration over the window, with the semantics of fgs_map_step: all views' gaussians
+ * are ordered by depth in one sort and binned together, all views' tiles are rendered (Eq. 1) by
+ * ONE launch over the (view, tile) items, the L1 terms of Eq. 16 are taken per view, ONE launch
+ * runs every view's backward over the same items, and one pass per gaussian sums the views'
+ * gradients through their projections and applies Adam. targets: [host] array of n_views. use_graph != 0 captures
  * the step in a hipGraph on its first call and replays it afterwards (re-captured when a pointer,
- * n, an option or the profiling level changes). The first call for a given n sizes the per-view
- * states from a synchronous pair count (50% headroom); a later step that outgrows a state is
- * reported by the next call with FGS_ERR_CAPACITY after the window has grown. */
+ * n, an option or the profiling level changes). The first call for a given n sizes the window's
+ * pair capacity from a synchronous count per view (50% headroom); a later step that outgrows it
+ * is reported by the next call with FGS_ERR_CAPACITY after the window has grown. */
 fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam *opt, const fgs_target *targets,
                            const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev, float *psnr_dev,
                            const fgs_gaussians *grad_out, int32_t use_graph);
