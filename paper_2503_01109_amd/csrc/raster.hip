@@ -473,6 +473,9 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
     const bool red_lane = term >= 0;
     const int slot20 = reduce20_slot(lane);  // the same after reduce20
+    // the flush: 16 lanes per entry, lane fc adds slot fc, scaled by fscale (slots 2-9)
+    const int fc = tid & 15;
+    const float fscale = fc == 3 ? -1.0f : (fc == 2 || fc == 4) ? -0.5f : 1.0f;
     const int wid = tid / kWave;
     const int sidx = tile / (kSuper * kSuper), sl = tile % (kSuper * kSuper);
     const int tx = (sidx % rk.supers_x) * kSuper + sl % kSuper, ty = (sidx / rk.supers_x) * kSuper + sl / kSuper;
@@ -568,17 +571,14 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         // (< 10) adds term c, so one wave instruction updates the records of four gaussians, one
         // cache line each.
         for (int e = tid >> 4; e < cnt; e += NT >> 4) {
-            const int c = tid & 15;
-            if (c < 10) {
-                // moments to gradients (see bwd_grad): the staged conic is s (a, 2 b, c)
-                const float raw = sacc[e][c], m0 = sacc[e][0], m1 = sacc[e][1], sbv = 0.5f * sa[e].w;
-                float v = raw;
-                if (c == 0) v = (sa[e].z * m0 + sbv * m1) * kInvConicScale;
-                else if (c == 1) v = (sbv * m0 + sb[e].x * m1) * kInvConicScale;
-                else if (c == 3) v = -raw;
-                else if (c == 2 || c == 4) v = -0.5f * raw;
-                if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + c], v);
-                if (raw != 0.0f) sacc[e][c] = 0.0f;
+            if (fc < 10) {
+                // moments to gradients (see bwd_grad): the staged conic is s (a, 2 b, c); slots 0
+                // and 1 mix the first two moments with the gaussian's conic, the rest scale theirs
+                const float raw = sacc[e][fc], m0 = sacc[e][0], m1 = sacc[e][1], sbv = 0.5f * sa[e].w;
+                const float P = fc == 0 ? sa[e].z : sbv, Q = fc == 0 ? sbv : sb[e].x;
+                const float v = fc < 2 ? (P * m0 + Q * m1) * kInvConicScale : raw * fscale;
+                if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)sid[e] * kG2Stride + fc], v);
+                if (raw != 0.0f) sacc[e][fc] = 0.0f;
             }
         }
     }
