@@ -33,8 +33,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "7450c8ad8200e52caf297c70651bade868f3687dd0ce5a6e0197f46f85970d96",
-                     "tile": "16x16", "fetch_bytes": 46715730, "write_bytes": 16498766},
+    "k_raster_bwd": {"source_sha256": "a84c0bf75d48f486d8d8792b01eb023c430275d23efb84518e0bbcd11d76aaa1",
+                     "tile": "16x16", "fetch_bytes": 46714745, "write_bytes": 16498766},
 }
 
 
