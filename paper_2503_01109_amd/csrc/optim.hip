@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kLossThreads = 256;
 constexpr int kLossItems = 4;
+constexpr int kFinalThreads = 1024;  // the one-workgroup reductions of the partials
 
 __device__ inline float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
 
@@ -57,17 +58,31 @@ k_loss_partial(int64_t P, const float *__restrict__ rgb, const float *__restrict
     if (threadIdx.x < 4) partials[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Loss and PSNR from nb per-tile partial quadruples (one workgroup of kLossThreads), in FP64 and
-// a fixed order.
+// Loss and PSNR from nb per-tile partial quadruples (one workgroup of kFinalThreads), in FP64 and
+// a fixed order. A quadruple is one 16-byte load (partials is 16-byte aligned); each thread puts
+// up to four of them in flight before adding, so the kernel waits on memory about once.
 __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
                             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
 {
-    constexpr int NW = kLossThreads / kWave;
+    constexpr int NW = kFinalThreads / kWave, U = 4;
     __shared__ double red[NW][4];
+    const float4 *__restrict__ p4 = reinterpret_cast<const float4 *>(partials);
     double acc[4] = {0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += kLossThreads)
+    for (int b0 = 0; b0 < nb; b0 += U * kFinalThreads) {
+        float4 v[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += (double)partials[4 * b + q];
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * kFinalThreads + (int)threadIdx.x;
+            v[u] = b < nb ? p4[b] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[0] += (double)v[u].x;
+            acc[1] += (double)v[u].y;
+            acc[2] += (double)v[u].z;
+            acc[3] += (double)v[u].w;
+        }
+    }
     // wave sums (butterfly over the 64 lanes), then the waves' sums in order
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -92,7 +107,7 @@ __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t 
     }
 }
 
-__global__ void __launch_bounds__(kLossThreads)
+__global__ void __launch_bounds__(kFinalThreads)
 k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
              float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
 {
@@ -100,7 +115,7 @@ k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, 
 }
 
 // One workgroup per view of a window: view v's tiles are window items [tile_base_v, tile_base_v+1).
-__global__ void __launch_bounds__(kLossThreads)
+__global__ void __launch_bounds__(kFinalThreads)
 k_loss_final_views(const ViewK *__restrict__ views, int nv, uint32_t total_items, float *__restrict__ loss,
                    float *__restrict__ psnr)
 {
@@ -186,14 +201,14 @@ void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float
     const int nb = (int)((P + kLossThreads * kLossItems - 1) / (kLossThreads * kLossItems));
     hipLaunchKernelGGL(k_loss_partial, dim3(nb), dim3(kLossThreads), 0, s, P, rgb, depth, trgb, tdepth, lrgb,
                        ldepth, drgb, ddepth, partials);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kFinalThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
                        loss, psnr);
 }
 
 void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
                        float *loss, float *psnr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kFinalThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
                        loss, psnr);
 }
 
@@ -201,7 +216,7 @@ void launch_loss_final_views(const ViewK *views_dev, int nv, uint32_t total_item
                              hipStream_t s)
 {
     if (nv <= 0) return;
-    hipLaunchKernelGGL(k_loss_final_views, dim3((unsigned)nv), dim3(kLossThreads), 0, s, views_dev, nv, total_items,
+    hipLaunchKernelGGL(k_loss_final_views, dim3((unsigned)nv), dim3(kFinalThreads), 0, s, views_dev, nv, total_items,
                        loss, psnr);
 }
 
