@@ -183,6 +183,21 @@ fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera
                           const float *dL_drgb, const float *dL_ddepth, const float *dL_dalpha,
                           const fgs_gaussians *grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the computation, arguments and result of
+ * fgs_render_bwd, with no allocation inside the call. Its one scratch buffer, the 2D gradient
+ * records (64 bytes per gaussian), is a static device array of FGS_NOALLOC_MAX_GAUSSIANS records
+ * that each GPU holds until the process ends (32 MiB); the call clears the first g->n records
+ * with a fill kernel before using them. Every call on one GPU shares that array: calls that
+ * overlap on one GPU (two streams or two threads) race and produce wrong gradients. g->n above
+ * FGS_NOALLOC_MAX_GAUSSIANS returns FGS_ERR_CAPACITY and enqueues nothing. ctx must have been
+ * created on the GPU the call runs on (fgs_ctx_create looks up that GPU's copy of the array). */
+#define FGS_NOALLOC_MAX_GAUSSIANS (1 << 19)
+fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam,
+                                  const fgs_render_opts *o, const void *state, int64_t state_bytes,
+                                  const float *dL_drgb, const float *dL_ddepth, const float *dL_dalpha,
+                                  const fgs_gaussians *grad);
+
 /* ------------------------------------ mapping step ------------------------------------ */
 
 /* One mapping iteration over a window of n_views keyframes (Sec. III-E, map optimisation):

@@ -105,6 +105,8 @@ _sigs = {
     "fgs_render_fwd": [_vp, _P(CGaussians), _P(CCamera), _P(CRenderOpts), _P(CImage), _vp, C.c_int64],
     "fgs_render_bwd": [_vp, _P(CGaussians), _P(CCamera), _P(CRenderOpts), _vp, C.c_int64, _fp, _fp, _fp,
                        _P(CGaussians)],
+    "fgs_render_bwd_noalloc": [_vp, _P(CGaussians), _P(CCamera), _P(CRenderOpts), _vp, C.c_int64, _fp, _fp, _fp,
+                               _P(CGaussians)],
     "fgs_map_step": [_vp, _P(CGaussians), _P(CAdam), C.c_int32, _P(CCamera), _P(CTarget), _P(CRenderOpts),
                      _P(CLossOpts), _fp, _fp, _P(CGaussians)],
     "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
@@ -284,6 +286,19 @@ def render_bwd(ctx: Context, params, n: int, cam, opts: RenderOpts, state, dL_dr
                                C.byref(opts.c()), C.c_void_p(state.data_ptr()),
                                state.numel() * state.element_size(), _f32(dL_drgb), _f32(dL_ddepth),
                                _f32(dL_dalpha), C.byref(gaussians(grad, n))), ctx.handle)
+
+
+NOALLOC_MAX_GAUSSIANS = 1 << 19
+
+
+def render_bwd_noalloc(ctx: Context, params, n: int, cam, opts: RenderOpts, state, dL_drgb, dL_ddepth, dL_dalpha,
+                       grad):
+    """render_bwd through the entry point that allocates nothing (a static per-GPU scratch of
+    NOALLOC_MAX_GAUSSIANS gradient records; calls that overlap on one GPU race)."""
+    _check(_lib.fgs_render_bwd_noalloc(ctx.handle, C.byref(gaussians(params, n)), C.byref(camera(cam)),
+                                       C.byref(opts.c()), C.c_void_p(state.data_ptr()),
+                                       state.numel() * state.element_size(), _f32(dL_drgb), _f32(dL_ddepth),
+                                       _f32(dL_dalpha), C.byref(gaussians(grad, n))), ctx.handle)
 
 
 @dataclass

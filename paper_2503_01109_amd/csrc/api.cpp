@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -75,6 +76,37 @@ struct DBuf {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Scratch of fgs_render_bwd_noalloc: the 2D gradient records of FGS_NOALLOC_MAX_GAUSSIANS
+// gaussians (kG2Stride floats each, 32 MiB), one copy per GPU for the life of the process. Host
+// code never passes `scratch` itself to a kernel: that name is a host-side stand-in. Its device
+// address is looked up once per device (noalloc_scratch_init, from fgs_ctx_create) and kept in
+// g_scratch_dev.
+constexpr int64_t kNoallocMax = FGS_NOALLOC_MAX_GAUSSIANS;
+static __device__ __align__(256) float scratch[kNoallocMax * kG2Stride];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
+// With device `dev` current: the address of that device's copy of `scratch`.
+hipError_t noalloc_scratch_init(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = (float *)ptr;
+    return hipSuccess;
+}
+
+float *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[dev];
+}
 
 }  // namespace
 
@@ -645,7 +677,8 @@ fgs_status fgs_ctx_create(fgs_ctx **out, void *hip_stream)
     if (!c) return fail(nullptr, FGS_ERR_HIP, "fgs_ctx_create: out of host memory");
     c->device = dev;
     c->stream = (hipStream_t)hip_stream;
-    e = c->words.ensure(W_TOTAL * 4);
+    e = noalloc_scratch_init(dev);
+    if (e == hipSuccess) e = c->words.ensure(W_TOTAL * 4);
     if (e == hipSuccess) e = hipMemset(c->words.p, 0, W_TOTAL * 4);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_words, W_TOTAL * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -832,6 +865,45 @@ fgs_status fgs_render_bwd(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
     return enqueue_backward(ctx, *g, *cam, *o, tw, th, state, L, dL_drgb, dL_ddepth, dL_dalpha, nullptr, grad, grad,
                             nullptr);
+}
+
+fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fgs_camera *cam,
+                                  const fgs_render_opts *o, const void *state, int64_t state_bytes,
+                                  const float *dL_drgb, const float *dL_ddepth, const float *dL_dalpha,
+                                  const fgs_gaussians *grad)
+{
+    const char *w = "fgs_render_bwd_noalloc";
+    int tw, th;
+    fgs_status st;
+    if ((st = check_gauss(ctx, g, w, "g")) != FGS_OK) return st;
+    if ((st = check_gauss(ctx, grad, w, "grad")) != FGS_OK) return st;
+    if (grad->n != g->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad.n != g.n", w);
+    if (g->n > kNoallocMax)
+        return fail(ctx, FGS_ERR_CAPACITY, "%s: %lld gaussians exceed the static scratch of %lld", w,
+                    (long long)g->n, (long long)kNoallocMax);
+    if ((st = check_camera(ctx, cam, w)) != FGS_OK) return st;
+    if ((st = check_opts(ctx, o, w, &tw, &th)) != FGS_OK) return st;
+    if (!dL_drgb || !dL_ddepth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: dL_drgb/dL_ddepth is NULL", w);
+    if (!state) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state is NULL", w);
+    StateLayout L;
+    if (state_capacity(g->n, cam->width, cam->height, tw, th, state_bytes, &L) < 0)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: state of %lld bytes does not match n and the image size", w,
+                    (long long)state_bytes);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    float *g2 = noalloc_scratch(ctx->device);
+    if (!g2) return fail(ctx, FGS_ERR_HIP, "%s: no scratch address for device %d", w, ctx->device);
+    if (g->n == 0) return FGS_OK;
+    hipStream_t s = ctx->stream;
+    const RasterK rk = to_rk(*o, tw, th, cam->width, cam->height);
+    const StatePtrs sp = state_ptrs((void *)state, L);
+    // the records of this call's gaussians start at zero (a fill kernel, so the call can be captured)
+    launch_zero_f32(g2, g->n * kG2Stride, s);
+    launch_raster_bwd(rk, cam->width, cam->height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, dL_drgb,
+                      dL_ddepth, dL_dalpha, nullptr, g2, s);
+    const GradK gk = to_gk(*grad);
+    launch_project_bwd(to_pk(*g), to_camk(*cam), rk, g2, gk, gk, AdamK{}, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
 }
 
 fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth, const fgs_target *target,

@@ -221,3 +221,17 @@ def test_prior_rejects_bad_arguments_on_host():
     assert F._lib.fgs_tile_features(None, d, d, 0, 48, 0.1, 10.0, 1, None, d, None) == F.ERR_INVALID_ARG
     assert F._lib.fgs_tile_features(None, d, d, 64, 48, 0.1, 10.0, 12, None, d, None) == F.ERR_INVALID_ARG
     assert "ctx is NULL" in F.last_error()
+
+
+def test_noalloc_backward_rejects_more_gaussians_than_its_scratch_on_host():
+    g = F.CGaussians()
+    g.n = g.stride = F.NOALLOC_MAX_GAUSSIANS + 1
+    d = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    g.mean = g.log_scale = g.quat = g.opacity_logit = g.rgb = d
+    st = F._lib.fgs_render_bwd_noalloc(None, C.byref(g), C.byref(F.camera(_cam())), C.byref(F.RenderOpts().c()),
+                                      C.c_void_p(0x2000), 1 << 30, d, d, None, C.byref(g))
+    assert st == F.ERR_CAPACITY and "static scratch" in F.last_error()
+    g.n = g.stride = 10
+    st = F._lib.fgs_render_bwd_noalloc(None, C.byref(g), C.byref(F.camera(_cam())), C.byref(F.RenderOpts().c()),
+                                      C.c_void_p(0x2000), 1 << 30, d, d, None, C.byref(g))
+    assert st == F.ERR_INVALID_ARG and "ctx is NULL" in F.last_error()
