@@ -206,7 +206,13 @@ fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fg
  * incremented on the host). cams and targets are [host] arrays of n_views. loss_dev and
  * psnr_dev (device, n_views floats each, may be NULL) receive each view's loss and PSNR.
  * grad_out (may be NULL) receives the summed gradient (overwritten). The context keeps the
- * per-view states; it grows them when a scene needs more pairs than before. */
+ * per-view states; it grows them when a scene needs more pairs than before. Adam's step count is
+ * kept on the device too (the update applied is that count + 1; a caller that changes opt->step
+ * between calls is followed). A view seen before (same index, camera and gaussian count) runs
+ * without waiting for its pair count; if its pairs outgrow the state, that step applies nothing:
+ * parameters, moments and the device count stay as they were. The next call then returns
+ * FGS_ERR_CAPACITY without running, with opt->step set back to the device's count and the state
+ * grown; the caller repeats the step. */
 fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt,
                         int32_t n_views, const fgs_camera *cams, const fgs_target *targets,
                         const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev,
@@ -242,9 +248,11 @@ fgs_status fgs_window_destroy(fgs_window *w);
  * runs every view's backward over the same items, and one pass per gaussian sums the views'
  * gradients through their projections and applies Adam. targets: [host] array of n_views. use_graph != 0 captures
  * the step in a hipGraph on its first call and replays it afterwards (re-captured when a pointer,
- * n, an option or the profiling level changes). The first call for a given n sizes the window's
- * pair capacity from a synchronous count per view (50% headroom); a later step that outgrows it
- * is reported by the next call with FGS_ERR_CAPACITY after the window has grown. */
+ * n, an option, the profiling level or the context's own sort and binning buffers change). The
+ * first call for a given n sizes the window's pair capacity from a synchronous count per view (50%
+ * headroom). A later step that outgrows it applies nothing (parameters, moments and the device
+ * step count stay as they were); the next call returns FGS_ERR_CAPACITY without running, with
+ * opt->step set back to the device's count and the window grown, and the caller repeats the step. */
 fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam *opt, const fgs_target *targets,
                            const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev, float *psnr_dev,
                            const fgs_gaussians *grad_out, int32_t use_graph);

@@ -342,10 +342,11 @@ def map_step(ctx: Context, params, n: int, adam: Adam, cams, targets, opts: Rend
     ccams = (CCamera * V)(*[camera(c) for c in cams])
     ctg = (CTarget * V)(*[CTarget(_f32(r), _f32(d)) for r, d in targets])
     ca = adam.c(n)
-    _check(_lib.fgs_map_step(ctx.handle, C.byref(gaussians(params, n)), C.byref(ca), V, ccams, ctg,
-                             C.byref(opts.c()), C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
-                             None if grad_out is None else C.byref(gaussians(grad_out, n))), ctx.handle)
-    adam.step = ca.step
+    st = _lib.fgs_map_step(ctx.handle, C.byref(gaussians(params, n)), C.byref(ca), V, ccams, ctg,
+                           C.byref(opts.c()), C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
+                           None if grad_out is None else C.byref(gaussians(grad_out, n)))
+    adam.step = ca.step  # also on an overflow report, which sets the count back
+    _check(st, ctx.handle)
 
 
 class Window:
@@ -386,11 +387,11 @@ class Window:
                 raise ValueError("loss / psnr need one entry per view")
         ctg = (CTarget * self.n_views)(*[CTarget(_f32(r), _f32(d)) for r, d in targets])
         ca = adam.c(n)
-        _check(_lib.fgs_window_step(self._p, C.byref(gaussians(params, n)), C.byref(ca), ctg, C.byref(opts.c()),
-                                    C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
-                                    None if grad_out is None else C.byref(gaussians(grad_out, n)), int(bool(graph))),
-               self.ctx.handle)
-        adam.step = ca.step
+        st = _lib.fgs_window_step(self._p, C.byref(gaussians(params, n)), C.byref(ca), ctg, C.byref(opts.c()),
+                                  C.byref((loss_opts or LossOpts()).c()), _f32(loss), _f32(psnr),
+                                  None if grad_out is None else C.byref(gaussians(grad_out, n)), int(bool(graph)))
+        adam.step = ca.step  # also on an overflow report, which sets the count back
+        _check(st, self.ctx.handle)
 
 
 def loss_l1(ctx: Context, rgb, depth, target_rgb, target_depth, loss_opts: LossOpts | None, dL_drgb, dL_ddepth,

@@ -122,6 +122,9 @@ struct fgs_ctx {
     int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
     DBuf words;  // status words (ST_WORDS) + small device scalars
     int64_t ws_n = -1, ws_cap = -1;
+    // bumped whenever ensure_ws or ensure_bin may have moved a workspace buffer (a captured window
+    // graph that baked in the old addresses is then re-captured)
+    uint64_t ws_gen = 0;
     int hist_G = 0;  // radix-sort workgroups the hist buffer holds
     // mapping-step buffers
     DBuf ms_state, ms_dl, ms_grad, ms_partials;
@@ -136,6 +139,13 @@ struct fgs_ctx {
     std::vector<bool> ms_seen;
     std::vector<fgs_camera> ms_cams;  // camera last run at each view index
     int64_t ms_n = -1;                // gaussian count of the last step
+    int ms_nv_max = 0;                // most views of any step (host-mapped flags in use)
+    // Adam step count of mapping steps on the device, in two slots (a step reads one and writes
+    // the other, so its kernel never reads what it writes); ms_dev_step is the count the device
+    // will hold once the enqueued steps are done, if none of them overflowed (-1: unknown)
+    int ms_slot = 0;
+    int64_t ms_dev_step = -1;
+    int64_t *step_host = nullptr;     // pinned staging of that count
     // profiling: 0 off, 1 rasterizer kernels only, 2 every stage
     int prof = 0;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
@@ -153,7 +163,9 @@ constexpr int W_NPAIRS = ST_WORDS + 1; // pairs to sort
 constexpr int W_DSCALE = ST_WORDS + 2; // float: 1/P_v of the depth term
 constexpr int W_NSUP = ST_WORDS + 3;   // super-tile pairs to sort
 constexpr int W_KTOTAL = ST_WORDS + 4; // (tile, gaussian) pairs counted by the projection
-constexpr int W_TOTAL = ST_WORDS + 8;
+constexpr int W_STEPOVF = ST_WORDS + 5; // a mapping step's overflow word (any view's pairs did not fit)
+constexpr int W_STEP = ST_WORDS + 6;   // two int64 slots (8-byte aligned): the mapping step's Adam count
+constexpr int W_TOTAL = ST_WORDS + 16;
 
 fgs_status fail(fgs_ctx *ctx, fgs_status s, const char *fmt, ...)
 {
@@ -274,6 +286,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     const int64_t cc = cap > ctx->ws_cap ? cap : ctx->ws_cap;
     const size_t N = (size_t)(nn > 0 ? nn : 1), C = (size_t)(cc > 0 ? cc : 1);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->ws_gen++;
     HIP_TRY(ctx, ctx->rect.ensure(N * sizeof(uint2)));
     HIP_TRY(ctx, ctx->count.ensure(N * 4));
     HIP_TRY(ctx, ctx->dkA.ensure(N * 4));
@@ -310,6 +323,7 @@ fgs_status ensure_bin(fgs_ctx *ctx, int64_t nsup, int64_t T, int64_t cap)
     const int64_t ns = std::max(nsup, ctx->bin_nsup), tt = std::max(T, ctx->bin_T), cc = std::max(cap, ctx->bin_cap);
     const int64_t mc = bin_max_chunks(cc, ns);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->ws_gen++;
     HIP_TRY(ctx, ctx->bin_sranges.ensure((size_t)ns * 8));
     HIP_TRY(ctx, ctx->bin_cstart.ensure((size_t)(ns + 1) * 4));
     HIP_TRY(ctx, ctx->bin_csuper.ensure((size_t)mc * 4));
@@ -485,7 +499,8 @@ struct ProjOut {
 // count in *K_check before enqueueing the rest.
 fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                               int tw, int th, const ImageK &img, void *state, const StateLayout &L, const ProjOut &po,
-                              int64_t *K_check, uint32_t *host_status, bool raster, const LossK *loss)
+                              int64_t *K_check, uint32_t *host_status, bool raster, const LossK *loss,
+                              uint32_t *step_ovf, bool first_of_step)
 {
     const RasterK rk = to_rk(o, tw, th, cam.width, cam.height);
     const int supers_x = (rk.tiles_x + kSuper - 1) / kSuper, supers_y = (rk.tiles_y + kSuper - 1) / kSuper;
@@ -527,7 +542,8 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         const bool one_pass = sbits <= 8;
         if (!one_pass) launch_ranges(keys, nsup_pairs, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
         launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
-        launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, s);
+        launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, step_ovf,
+                         first_of_step, s);
         launch_bin_place(bw, keys, svals, sranges, sp.ranges, sp.vals, s);
     }
     if (raster) {
@@ -546,7 +562,7 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
                            int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
-                           const LossK *loss = nullptr)
+                           const LossK *loss = nullptr, uint32_t *step_ovf = nullptr, bool first_of_step = false)
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
@@ -565,7 +581,8 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
         launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
                           ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n, kDepthSortPerBlock), s);
     }
-    return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss);
+    return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss, step_ovf,
+                              first_of_step);
 }
 
 
@@ -701,6 +718,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     for (DBuf *b : bufs) b->release();
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
     if (ctx->ms_host) (void)hipHostFree(ctx->ms_host);
+    if (ctx->step_host) (void)hipHostFree(ctx->step_host);
     delete ctx;
     return FGS_OK;
 }
@@ -997,25 +1015,57 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         HIP_TRY(ctx, hipHostMalloc((void **)&ctx->ms_host, 2 * 4096 * 4, hipHostMallocMapped | hipHostMallocCoherent));
         memset(ctx->ms_host, 0, 2 * 4096 * 4);
         HIP_TRY(ctx, hipHostGetDevicePointer((void **)&ctx->ms_host_dev, ctx->ms_host, 0));
+        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->step_host, 8, hipHostMallocDefault));
         ctx->ms_seen.assign(4096, false);
         ctx->ms_cams.assign(4096, fgs_camera{});
     }
-    // A step whose pair count outgrew the state while running unchecked is reported here, once:
-    // the state is grown and the caller learns that the earlier step used an incomplete gradient.
-    for (int v = 0; v < n_views; ++v) {
-        volatile uint32_t *hs = ctx->ms_host + 2 * v;
-        if (hs[1]) {
-            HIP_TRY(ctx, hipStreamSynchronize(s));
-            const int64_t K = hs[0];
-            hs[1] = 0;
+    int64_t *dstep = (int64_t *)(ctx->words.as<uint32_t>() + W_STEP);
+    uint32_t *step_ovf = ctx->words.as<uint32_t>() + W_STEPOVF;
+    // A step whose pair count outgrew a view's state while running unchecked is reported here,
+    // once. Such a step (and any step enqueued after it that overflowed as well) left the
+    // parameters, the Adam moments and the device step count as they were: opt->step is set back
+    // to the device's count, the state is grown, and the caller repeats the step.
+    {
+        volatile uint32_t *hs = ctx->ms_host;
+        bool any = false;
+        for (int v = 0; v < ctx->ms_nv_max; ++v) any |= hs[2 * v + 1] != 0;
+        if (any) {
+            HIP_TRY(ctx, hipStreamSynchronize(s));  // the flags and counts are final now
+            int64_t K = 0;
+            int vk = 0;
+            for (int v = 0; v < ctx->ms_nv_max; ++v)
+                if (hs[2 * v + 1]) {
+                    if ((int64_t)hs[2 * v] >= K) {
+                        K = hs[2 * v];
+                        vk = v;
+                    }
+                    hs[2 * v + 1] = 0;
+                }
             if (K + K / 4 + 1024 > ctx->ms_cap) ctx->ms_cap = K + K / 4 + 1024;
             // the context's overflow word saw the same event; this report replaces it
             HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, s));
-            HIP_TRY(ctx, hipStreamSynchronize(s));
+            fgs_status st2 = read_words(ctx);
+            if (st2 != FGS_OK) return st2;
+            if (ctx->ms_dev_step >= 0) {
+                int64_t dev;
+                memcpy(&dev, ctx->host_words + W_STEP + 2 * ctx->ms_slot, 8);
+                opt->step = dev;
+                ctx->ms_dev_step = dev;
+            }
             return fail(ctx, FGS_ERR_CAPACITY,
-                        "%s: an earlier step needed %lld (tile, gaussian) pairs in view %d; the state was grown", w,
-                        (long long)K, v);
+                        "%s: an earlier step needed %lld (tile, gaussian) pairs in view %d and was not applied "
+                        "(parameters, moments and step count unchanged); the state was grown, repeat that step",
+                        w, (long long)K, vk);
         }
+    }
+    if (n_views > ctx->ms_nv_max) ctx->ms_nv_max = std::min(n_views, 4096);
+    // the device's step count follows the host's (a new context, or a caller that reset opt->step)
+    if (opt->step != ctx->ms_dev_step) {
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        *ctx->step_host = opt->step;
+        HIP_TRY(ctx, hipMemcpyAsync(dstep + ctx->ms_slot, ctx->step_host, 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        ctx->ms_dev_step = opt->step;
     }
     // summed gradient: the caller's buffer, or the context's (the first view overwrites it)
     fgs_gaussians grad;
@@ -1065,7 +1115,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             const bool checked = !seen || K_obs * 10 > ctx->ms_cap * 9;
             int64_t K = 0;
             st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, checked ? &K : nullptr,
-                                 hs_dev, true, &lk);
+                                 hs_dev, true, &lk, step_ovf, v == 0);
             if (st == FGS_OK) {
                 if (v < 4096) {
                     ctx->ms_seen[v] = true;
@@ -1090,16 +1140,17 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         const bool last = v == n_views - 1;
         AdamK ak{};
         if (last) {
+            // update number = the device's count + 1; skipped (and the count kept) when any view
+            // of this step overflowed its state
             ak.m = to_gk(opt->m);
             ak.v = to_gk(opt->v);
-            ak.step = nullptr;
+            ak.step = dstep + ctx->ms_slot;
+            ak.step_out = dstep + (1 - ctx->ms_slot);
+            ak.skip = step_ovf;
             for (int k = 0; k < 5; ++k) ak.lr[k] = opt->lr[k];
             ak.beta1 = opt->beta1;
             ak.beta2 = opt->beta2;
             ak.eps = opt->eps;
-            const double t = (double)(opt->step + 1);
-            ak.bc1 = (float)(1.0 - pow((double)opt->beta1, t));
-            ak.bc2 = (float)(1.0 - pow((double)opt->beta2, t));
         }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
                                    v > 0 ? &grad : nullptr, !last || grad_out ? &grad : nullptr,
@@ -1108,6 +1159,12 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     }
     ctx->ms_n = n;
     opt->step += 1;
+    if (n > 0) {
+        ctx->ms_slot ^= 1;  // the projection backward wrote the new count into the other slot
+        ctx->ms_dev_step = opt->step;
+    } else {
+        ctx->ms_dev_step = -1;  // no projection backward ran: the next step uploads the count
+    }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
@@ -1302,9 +1359,9 @@ struct fgs_window {
 
 namespace {
 
-// device words of a window: item counter of the persistent rasterizer, Adam step (int64, 8-byte
-// aligned), per-view 1/P_v
-constexpr int WW_COUNTER = 0, WW_STEP = 2, WW_DSCALE = 4;
+// device words of a window: item counter of the persistent rasterizer, the step's overflow word,
+// Adam step (int64, 8-byte aligned), per-view 1/P_v
+constexpr int WW_COUNTER = 0, WW_OVF = 1, WW_STEP = 2, WW_DSCALE = 4;
 
 void window_drop_graph(fgs_window *w)
 {
@@ -1436,8 +1493,8 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
 {
     fgs_ctx *ctx = w->ctx;
     hipStream_t s = ctx->stream;
-    fgs_status st;
     const int64_t n = params.n;
+    uint32_t *words = w->words.as<uint32_t>();
     // every view's projection into consecutive ranges of the depth-sort buffers
     const int64_t pb = project_blocks(n), all = (int64_t)w->nv * n;
     uint32_t *ndev = ctx->words.as<uint32_t>() + W_NDEV;
@@ -1490,12 +1547,11 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
             if (!one_pass) launch_ranges(keys, cw + W_NSUP, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
             launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
             launch_bin_tiles(bw, nsup, w->cap_all, cw + W_KTOTAL, w->wranges.as<uint2>(), status_words(ctx),
-                             cw + W_NPAIRS, w->hs_dev, s);
+                             cw + W_NPAIRS, w->hs_dev, words + WW_OVF, true, s);
             launch_bin_place(bw, keys, svals, ctx->bin_sranges.as<uint2>(), w->wranges.as<uint2>(),
                              w->wvals.as<uint32_t>(), s);
         }
     }
-    uint32_t *words = w->words.as<uint32_t>();
     {
         Stage st_(ctx, "raster_fwd");
         launch_raster_window(true, prof_counts(ctx) != nullptr, w->views.as<ViewK>(), w->nv, w->total_tiles,
@@ -1517,6 +1573,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     ak.m = to_gk(opt.m);
     ak.v = to_gk(opt.v);
     ak.step = step;
+    ak.skip = words + WW_OVF;  // an overflowed step changes no parameter, moment or step count
     for (int k = 0; k < 5; ++k) ak.lr[k] = opt.lr[k];
     ak.beta1 = opt.beta1;
     ak.beta2 = opt.beta2;
@@ -1527,7 +1584,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
         launch_project_bwd_window(to_pk(params), w->cams_dev.as<CamK>(), w->nv, o.lowpass, w->grad2d.as<float>(),
                                   (int64_t)kG2Stride * n, gk, ak, s);
     }
-    launch_step_advance(step, s);
+    launch_step_advance(step, words + WW_OVF, s);
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
 }
@@ -1672,8 +1729,9 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
         if ((st = check_gauss(ctx, grad_out, w_, "grad_out")) != FGS_OK) return st;
         if (grad_out->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad_out.n != params.n", w_);
     }
-    // a step already run that outgrew the window's pair capacity: its result is void; grow it and
-    // report once
+    // a step already run that outgrew the window's pair capacity changed no parameter, moment or
+    // device step count: opt->step is set back to that count, the window grows, and the caller
+    // hears of it once
     if (((volatile uint32_t *)w->hs)[1]) {
         HIP_TRY(ctx, hipStreamSynchronize(w->stream));  // the flag and count are final now
         volatile uint32_t *hs = w->hs;
@@ -1683,11 +1741,15 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
         w->cap_all = std::max<int64_t>(w->cap_all, K + K / 2 + 1024);
         // the context's own overflow word saw the same event; this report replaces it
         HIP_TRY(ctx, hipMemsetAsync(ctx->words.as<uint32_t>() + ST_OVERFLOW, 0, 4, w->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(w->step_host, w->words.as<char>() + 4 * WW_STEP, 8, hipMemcpyDeviceToHost,
+                                    w->stream));
         HIP_TRY(ctx, hipStreamSynchronize(w->stream));
+        if (w->dev_step >= 0) opt->step = *w->step_host;
+        w->dev_step = opt->step;
         w->n = -1;  // the next step resizes
         return fail(ctx, FGS_ERR_CAPACITY,
-                    "%s: an earlier step needed %lld pairs over its views; the window has grown, repeat that step", w_,
-                    (long long)K);
+                    "%s: an earlier step needed %lld pairs over its views and was not applied (parameters, moments "
+                    "and step count unchanged); the window has grown, repeat that step", w_, (long long)K);
     }
     hipStream_t user = ctx->stream;
     HIP_TRY(ctx, hipEventRecord(w->ev_in, user));
@@ -1711,6 +1773,7 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
     if (use_graph && ctx->prof) use_graph = 0;  // profiled steps run eagerly
     if (use_graph) {
         std::vector<uintptr_t> sig = w->table_sig;
+        sig.push_back((uintptr_t)ctx->ws_gen);  // the context's sort and binning buffers are baked in
         const void *ptrs[] = {params->mean, params->log_scale, params->quat, params->opacity_logit, params->rgb,
                               opt->m.mean, opt->m.log_scale, opt->m.quat, opt->m.opacity_logit, opt->m.rgb,
                               opt->v.mean, opt->v.log_scale, opt->v.quat, opt->v.opacity_logit, opt->v.rgb,

@@ -165,7 +165,9 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 //   launch_bin_counts: chunk table and per-chunk tile counts;
 //   launch_bin_tiles:  prefixes over chunks and tiles, the tile ranges, and the capacity check of
 //                      K = *ktotal pairs (status, n_pairs_dev, host_status; empty ranges on
-//                      overflow);
+//                      overflow). step_ovf (nullable) is the overflow word of a mapping step
+//                      whose views are binned one after another: the step's first binning
+//                      writes 0 or 1 to it, later ones set it to 1 on overflow;
 //   launch_bin_place:  every entry's gaussian id into the lists of its tiles (vals, K entries).
 // The tiles an entry covers come from the box in its key.
 struct BinWS {
@@ -183,7 +185,8 @@ int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
                        hipStream_t s);
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
-                      uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s);
+                      uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
+                      hipStream_t s);
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
                       const uint2 *ranges, uint32_t *vals, hipStream_t s);
 
@@ -252,12 +255,16 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        const float *ddepth_scale, float *grad2d, hipStream_t s);
 
 // Adam hyper-parameters of an update fused into a projection backward. step (nullable) points
-// to the device count of updates already applied (the kernel applies update *step + 1 and does
-// not change it, so a captured graph can be replayed); without it, bc1 and bc2 are the bias
-// corrections of this update.
+// to the device count of updates already applied (the kernel applies update *step + 1); without
+// it, bc1 and bc2 are the bias corrections of this update. skip (nullable) points to a step's
+// overflow word: when it is non-zero the step's gradient is incomplete and no parameter or moment
+// changes. step_out (nullable, not aliasing step) receives the count after this step: *step + 1,
+// or *step when skipped (a captured window step advances its counter in a launch of its own).
 struct AdamK {
     GradK m, v;
     const int64_t *step;
+    int64_t *step_out;
+    const uint32_t *skip;
     float lr[5];
     float beta1, beta2, eps;
     float bc1, bc2;
@@ -296,7 +303,8 @@ void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float
 void launch_adam(const GradK &p, const ParamsK &g, const GradK &m, const GradK &v, const float lr[5],
                  float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
 
-// *step += 1 on the device (the Adam step counter a captured window step reads and advances).
-void launch_step_advance(int64_t *step, hipStream_t s);
+// *step += 1 on the device unless *skip (nullable) is non-zero (the Adam step counter a captured
+// window step reads and advances; an overflowed step leaves it unchanged).
+void launch_step_advance(int64_t *step, const uint32_t *skip, hipStream_t s);
 
 }  // namespace fgs

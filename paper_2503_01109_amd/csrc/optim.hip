@@ -177,16 +177,16 @@ __global__ void k_scale(float *__restrict__ x, int64_t n, const float *__restric
         x[i] *= f;
 }
 
-__global__ void k_step_advance(int64_t *step)
+__global__ void k_step_advance(int64_t *step, const uint32_t *skip)
 {
-    if (threadIdx.x == 0) *step += 1;
+    if (threadIdx.x == 0 && !(skip && *skip)) *step += 1;
 }
 
 }  // namespace
 
-void launch_step_advance(int64_t *step, hipStream_t s)
+void launch_step_advance(int64_t *step, const uint32_t *skip, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step, skip);
 }
 
 int64_t loss_partials_size(int64_t P)

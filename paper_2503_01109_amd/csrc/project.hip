@@ -341,6 +341,9 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
     if (i >= n) return;
+    // an overflowed step (incomplete gradient) changes no parameter, moment or step count
+    const bool skip = adam.skip && *adam.skip;
+    if (i == 0 && adam.step_out) *adam.step_out = *adam.step + (skip ? 0 : 1);
     double g2[10];
     bool any = take_g2(grad2d + i * kG2Stride, g2);
     double out[14];
@@ -360,7 +363,7 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     if (grad_out.mean)
 #pragma unroll
         for (int k = 0; k < 14; ++k) plane(grad_out, k)[i] = gi[k];
-    if (adam.m.mean) adam_update(adam, g, i, gi);
+    if (adam.m.mean && !skip) adam_update(adam, g, i, gi);
 }
 
 // Window backward: per gaussian, the 2D gradient records of every view (view v's at grad2d +
@@ -392,7 +395,7 @@ k_project_bwd_window(ParamsK g, const CamK *__restrict__ cams, int nv, float low
     if (grad.mean)
 #pragma unroll
         for (int k = 0; k < 14; ++k) plane(grad, k)[i] = gi[k];
-    if (adam.m.mean) adam_update(adam, g, i, gi);
+    if (adam.m.mean && !(adam.skip && *adam.skip)) adam_update(adam, g, i, gi);
 }
 
 }  // namespace

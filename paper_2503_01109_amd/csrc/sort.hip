@@ -596,7 +596,8 @@ __global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, uint32_t *__re
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, const uint32_t *__restrict__ ktotal,
             uint2 *__restrict__ ranges, uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev,
-            uint32_t *__restrict__ host_status, uint32_t *__restrict__ ok)
+            uint32_t *__restrict__ host_status, uint32_t *__restrict__ ok, uint32_t *__restrict__ step_ovf,
+            int first_of_step)
 {
     constexpr int NB = kSuper * kSuper;
     __shared__ uint32_t w[8];
@@ -627,6 +628,8 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, cons
         status[ST_PAIRS] = K;
         *n_pairs_dev = ovf ? 0u : K;
         *ok = ovf ? 0u : 1u;
+        // the step's overflow word: set by the first binning of a step, or-ed by the others
+        if (step_ovf && (first_of_step || ovf)) *step_ovf = ovf ? 1u : 0u;
         if (ovf) atomicMax(&status[ST_OVERFLOW], K);
         if (host_status) {
             host_status[0] = K;
@@ -830,12 +833,13 @@ void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, co
 }
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
-                      uint32_t *n_pairs_dev, uint32_t *host_status, hipStream_t s)
+                      uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
+                      hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, b.chist,
                        b.tile_total);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, nsup, cap, ktotal, ranges, status,
-                       n_pairs_dev, host_status, b.ok);
+                       n_pairs_dev, host_status, b.ok, step_ovf, first_of_step ? 1 : 0);
 }
 
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,

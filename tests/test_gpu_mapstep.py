@@ -178,3 +178,89 @@ def test_map_step_trains(fgs, ctx):
     ctx.check()
     ls = host(losses)
     assert ls[-1] < 0.8 * ls[0]
+
+
+GROUP = np.array([0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4])
+
+
+def adam_expect(p0, m0, v0, g, t):
+    """Update number t of Adam (Kingma and Ba) from the state (p0, m0, v0) with gradient g."""
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    m1 = b1 * m0 + (1 - b1) * g
+    v1 = b2 * v0 + (1 - b2) * g * g
+    lr = np.array(LR)[GROUP][:, None]
+    return p0 - lr * (m1 / (1 - b1 ** t)) / (np.sqrt(v1 / (1 - b2 ** t)) + 1e-15), lr
+
+
+def test_map_step_adam_reads_the_device_step(fgs):
+    """The mapping step keeps Adam's step count on the device: each of six steps applies update
+    number step + 1 (checked against the host formula from the snapshot before it and its own
+    gradient), and a count reset on the host between steps is followed by the device."""
+    import torch
+    c = fgs.Context()
+    cam = synth.camera_small()
+    p = synth.frustum_scene(12, 1500, cam, 1.0, 5.0)
+    n = p.shape[1]
+    pd = dev(p)
+    g0 = synth.rng(160)
+    targets = [(dev(g0.uniform(size=(3, cam.height, cam.width))), dev(g0.uniform(1, 4, (cam.height, cam.width))))]
+    adam = fgs.Adam.like(pd, lr=LR)
+    grad = torch.zeros_like(pd)
+    for k in range(6):
+        if k == 4:
+            adam.step = 10
+        snap = [host(t).astype(np.float64) for t in (pd, adam.m, adam.v)]
+        t = adam.step + 1
+        fgs.map_step(c, pd, n, adam, [cam], targets, fgs.RenderOpts(), grad_out=grad)
+        c.check()
+        g = host(grad).astype(np.float64)
+        expect, lr = adam_expect(*snap, g, t)
+        big = np.abs(g) >= 1e-3 * np.abs(g).max(axis=1, keepdims=True)
+        err = np.abs(host(pd).astype(np.float64) - expect)
+        ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
+        assert np.all((err <= 1e-4 * np.abs(expect - snap[0]) + 2 * ulp + 1e-5 * lr)[big]), f"step {k} (t = {t})"
+    assert adam.step == 12
+    c.close()
+
+
+def test_map_step_overflow_leaves_parameters_moments_and_step(fgs):
+    """A view seen before runs without a host round trip; when its gaussians grow in place past the
+    state's pair capacity (2,000 gaussians covering all 3,225 tiles of a 1200x680 view: 6.45M pairs
+    against 4M), that step applies nothing: parameters, Adam moments and the device step count stay
+    as they were (nonzero learning rates). The next call reports FGS_ERR_CAPACITY once and sets the
+    host's count back; the one after it applies update number 2."""
+    import torch
+    c = fgs.Context()  # fresh: its state capacity starts at 4M pairs
+    cam = synth.camera_replica()
+    p = synth.frustum_scene(13, 2000, cam, 1.0, 5.0)
+    p[3:6] = -6.0  # tiny: about one tile each
+    n = p.shape[1]
+    pd = dev(p)
+    g0 = synth.rng(170)
+    targets = [(dev(g0.uniform(size=(3, cam.height, cam.width))), dev(g0.uniform(1, 4, (cam.height, cam.width))))]
+    adam = fgs.Adam.like(pd, lr=LR)
+    grad = torch.zeros_like(pd)
+    fgs.map_step(c, pd, n, adam, [cam], targets, fgs.RenderOpts(), grad_out=grad)
+    c.check()
+    pd[3:6] = 0.5  # 1.6 m scales at 1-5 m: every gaussian covers the whole view
+    snap = [host(t).copy() for t in (pd, adam.m, adam.v)]
+    fgs.map_step(c, pd, n, adam, [cam], targets, fgs.RenderOpts(), grad_out=grad)  # overflows, not yet known
+    torch.cuda.synchronize()
+    assert adam.step == 2
+    for name, t, s in zip(("params", "m", "v"), (pd, adam.m, adam.v), snap):
+        np.testing.assert_array_equal(host(t), s, err_msg=f"{name} changed by the overflowed step")
+    with pytest.raises(fgs.FgsError) as e:
+        fgs.map_step(c, pd, n, adam, [cam], targets, fgs.RenderOpts(), grad_out=grad)
+    assert e.value.status == fgs.ERR_CAPACITY and "not applied" in str(e.value)
+    assert adam.step == 1, "the overflowed step is not counted"
+    c.check()  # the context's overflow word was cleared by the report
+    fgs.map_step(c, pd, n, adam, [cam], targets, fgs.RenderOpts(), grad_out=grad)
+    c.check()
+    assert adam.step == 2
+    g = host(grad).astype(np.float64)
+    expect, lr = adam_expect(*(s.astype(np.float64) for s in snap), g, 2)
+    big = np.abs(g) >= 1e-3 * np.abs(g).max(axis=1, keepdims=True)
+    err = np.abs(host(pd).astype(np.float64) - expect)
+    ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
+    assert np.all((err <= 1e-4 * np.abs(expect - snap[0].astype(np.float64)) + 2 * ulp + 1e-5 * lr)[big])
+    c.close()

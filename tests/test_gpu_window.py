@@ -198,9 +198,11 @@ def test_graph_adam_reads_the_device_step(fgs, ctx):
 
 
 def test_overflow_in_a_replay_is_reported_and_recovered(fgs, ctx):
-    """Gaussians grown in place after the window was sized: the replay overflows a view's state,
-    the next call reports FGS_ERR_CAPACITY once, and the call after it resizes and equals the
-    plain mapping step again."""
+    """Gaussians grown in place after the window was sized: the replay overflows a view's state and
+    leaves the parameters, the Adam moments and the device step count as they were (nonzero
+    learning rates); the next call reports FGS_ERR_CAPACITY once and sets the host's step count
+    back; the call after it resizes, equals the plain mapping step again and applies update
+    number 2."""
     import torch
     cams, tiles = small_views()
     p = synth.frustum_scene(6, 2000, cams[0], 1.0, 5.0)
@@ -208,24 +210,82 @@ def test_overflow_in_a_replay_is_reported_and_recovered(fgs, ctx):
     n = p.shape[1]
     pd = dev(p)
     targets = random_targets(cams, 110)
-    zero = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
+    adam = fgs.Adam.like(pd, lr=LR)
     grad = torch.zeros_like(pd)
     win = fgs.Window(ctx, cams, tiles)
-    win.step(pd, n, zero, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
+    win.step(pd, n, adam, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
     ctx.check()
+    assert adam.step == 1
     pd[3:6] = -1.5  # large footprints: many more (tile, gaussian) pairs
-    win.step(pd, n, zero, targets, fgs.RenderOpts(), grad_out=grad, graph=True)  # overflows, not yet known
+    snap = [host(t).copy() for t in (pd, adam.m, adam.v)]
+    win.step(pd, n, adam, targets, fgs.RenderOpts(), grad_out=grad, graph=True)  # overflows, not yet known
     torch.cuda.synchronize()
+    for name, t, s in zip(("params", "m", "v"), (pd, adam.m, adam.v), snap):
+        np.testing.assert_array_equal(host(t), s, err_msg=f"{name} changed by the overflowed step")
     with pytest.raises(fgs.FgsError) as e:
-        win.step(pd, n, zero, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
-    assert e.value.status == fgs.ERR_CAPACITY and "grown" in str(e.value)
+        win.step(pd, n, adam, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
+    assert e.value.status == fgs.ERR_CAPACITY and "grown" in str(e.value) and "not applied" in str(e.value)
+    assert adam.step == 1, "the overflowed step is not counted"
     ctx.check()  # the context's own overflow word was cleared by the window's report
-    win.step(pd, n, zero, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
     ref = torch.zeros_like(pd)
     fgs.map_step(ctx, pd, n, fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0)), cams, targets, fgs.RenderOpts(), grad_out=ref)
     ctx.check()
+    p0, m0, v0 = (s.astype(np.float64) for s in snap)
+    win.step(pd, n, adam, targets, fgs.RenderOpts(), grad_out=grad, graph=True)
+    ctx.check()
+    assert adam.step == 2
     assert_close_rel(host(grad), host(ref), 1e-5, what="after recovery", floor=1e-2)
+    # update number 2 from the state the overflowed step left
+    g = host(grad).astype(np.float64)
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    m1 = b1 * m0 + (1 - b1) * g
+    v1 = b2 * v0 + (1 - b2) * g * g
+    lr = np.array(LR)[GROUP][:, None]
+    expect = p0 - lr * (m1 / (1 - b1 ** 2)) / (np.sqrt(v1 / (1 - b2 ** 2)) + 1e-15)
+    err = np.abs(host(pd).astype(np.float64) - expect)
+    ulp = np.spacing(np.abs(expect).astype(np.float32)).astype(np.float64)
+    assert np.all(err <= 1e-4 * np.abs(expect - p0) + 2 * ulp + 1e-5 * lr), "update 2 after recovery"
     win.close()
+
+
+def test_graph_recaptured_after_the_context_workspace_grows(fgs):
+    """A captured window step bakes in the context's sort and binning buffers. A larger mapping step
+    on the same context grows (reallocates) them; the next graphed window step must be captured
+    again, not replay the old addresses. Each graphed step equals an eager step on the same
+    inputs."""
+    import torch
+    c = fgs.Context()  # fresh: its workspace is sized by the small window first
+    cams, tiles = small_views()
+    p = synth.frustum_scene(7, 1500, cams[0], 1.0, 5.0)
+    n = p.shape[1]
+    pd = dev(p)
+    targets = random_targets(cams, 130)
+    zero = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
+    wg, we = fgs.Window(c, cams, tiles), fgs.Window(c, cams, tiles)
+    gg, ge = torch.zeros_like(pd), torch.zeros_like(pd)
+    lg, le = torch.zeros(len(cams), device="cuda"), torch.zeros(len(cams), device="cuda")
+
+    def compare(what):
+        wg.step(pd, n, zero, targets, fgs.RenderOpts(), loss=lg, grad_out=gg, graph=True)
+        we.step(pd, n, zero, targets, fgs.RenderOpts(), loss=le, grad_out=ge, graph=False)
+        c.check()
+        np.testing.assert_allclose(host(lg), host(le), rtol=1e-6, err_msg=what)
+        assert_close_rel(host(gg), host(ge), 1e-5, what=f"{what} gradient", floor=1e-2)
+
+    compare("before")
+    compare("replay")
+    big_cam = synth.camera_replica()
+    big = dev(synth.frustum_scene(8, 200_000, big_cam, 0.5, 8.0))
+    bt = [(dev(synth.rng(140).uniform(size=(3, big_cam.height, big_cam.width))),
+           dev(synth.rng(141).uniform(1, 4, (big_cam.height, big_cam.width))))]
+    fgs.map_step(c, big, 200_000, fgs.Adam.like(big, lr=(0, 0, 0, 0, 0)), [big_cam], bt, fgs.RenderOpts())
+    c.check()
+    del big, bt
+    compare("after the workspace grew")
+    compare("replay after the workspace grew")
+    wg.close()
+    we.close()
+    c.close()
 
 
 def test_profiled_window_step_runs_eagerly(fgs, ctx):
