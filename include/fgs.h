@@ -200,7 +200,7 @@ fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fg
 
 /* ------------------------------------ mapping step ------------------------------------ */
 
-/* One mapping iteration over a window of n_views keyframes (Sec. III-E, map optimisation):
+/* One mapping iteration over a window of n_views keyframes (Sec. III-D, map optimization):
  * for every view, render (Eq. 1), take the L1 colour and depth terms of Eq. 16 against the
  * view's target, and accumulate the gradient; then one Adam update of `params` (opt->step is
  * incremented on the host). cams and targets are [host] arrays of n_views. loss_dev and
@@ -232,7 +232,7 @@ fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_ga
 
 typedef struct fgs_window fgs_window; /* opaque: per-view states, item counter, captured graph */
 
-/* A keyframe window (Sec. III-D, III-E: the co-visible and random keyframes optimised together)
+/* A keyframe window (Sec. III-C, III-D: the co-visible and random keyframes optimised together)
  * of n_views cameras ([host] array, copied) that may differ in size. tiles ([host], 2 ints per
  * view: tile_w, tile_h; NULL = 16x16) picks each view's rasterizer tile among 16x16, 32x8 and
  * 8x32. blocks_per_cu > 0 makes the rasterizer launches persistent grids of that many workgroups

@@ -96,7 +96,7 @@ def lib():
         L.fgso_render_fwd.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), C.c_int,
                                       C.c_int64, _i64p, _dp, _dp, _dp, _dp, _i32p, _u8p, C.c_double, _dp]
         L.fgso_render_bwd.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), C.c_int,
-                                      C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp]
+                                      C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp, _dp]
         L.fgso_count_duplicates.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts),
                                             C.c_int32, C.c_int32]
         L.fgso_count_duplicates.restype = C.c_int64
@@ -165,19 +165,24 @@ def render_fwd(params, cam, opts: RenderOpts | None = None, mode: int = 0, pix=N
                                _ptr(alpha, _dp), _ptr(T, _dp), _ptr(nc, _i32p), _ptr(amb, _u8p),
                                float(amb_rel), _ptr(stats, _dp))
     _check(rc, "render_fwd")
-    out = dict(rgb=rgb, depth=depth, alpha=alpha, T_final=T, n_contrib=nc, amb=amb.astype(bool),
+    # amb: a cutoff decision within amb_rel of its threshold (the pixel's result may legitimately
+    # differ in FP32); amb_tie: equal binary32 depths blended in index order (unambiguous)
+    out = dict(rgb=rgb, depth=depth, alpha=alpha, T_final=T, n_contrib=nc, amb=(amb & 1).astype(bool),
+               amb_cut=(amb & 1).astype(bool), amb_tie=(amb & 2).astype(bool),
                E_f=stats[0], E_c=stats[1], n_amb=int(stats[2]))
     if pixa is None:
         H, W = cam.height, cam.width
-        for k in ("depth", "alpha", "T_final", "n_contrib", "amb"):
+        for k in ("depth", "alpha", "T_final", "n_contrib", "amb", "amb_cut", "amb_tie"):
             out[k] = out[k].reshape(H, W)
         out["rgb"] = rgb.reshape(3, H, W)
     return out
 
 
 def render_bwd(params, cam, g_rgb, g_depth, g_alpha=None, opts: RenderOpts | None = None,
-               mode: int = 0, pix=None):
-    """Analytic backward: returns (dL/dparams (14, N), dL/d2D (10, N))."""
+               mode: int = 0, pix=None, mass: bool = False):
+    """Analytic backward: returns (dL/dparams (14, N), dL/d2D (10, N)), and with mass=True also
+    the absolute mass (14, N) of every gradient entry (the bound on its rounding error, see
+    fgso.h)."""
     p = _d(params)
     n = p.shape[1]
     pixa = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
@@ -185,11 +190,12 @@ def render_bwd(params, cam, g_rgb, g_depth, g_alpha=None, opts: RenderOpts | Non
     gr = _d(np.reshape(g_rgb, (3, m))); gd = _d(np.reshape(g_depth, (m,)))
     ga = None if g_alpha is None else _d(np.reshape(g_alpha, (m,)))
     grad = np.zeros((14, n)); grad2d = np.zeros((10, n))
+    ms = np.zeros((14, n)) if mass else None
     rc = lib().fgso_render_bwd(n, _ptr(p, _dp), C.byref(_cam(cam)), C.byref((opts or RenderOpts()).c()),
                                mode, m, _ptr(pixa, _i64p), _ptr(gr, _dp), _ptr(gd, _dp), _ptr(ga, _dp),
-                               _ptr(grad, _dp), _ptr(grad2d, _dp))
+                               _ptr(grad, _dp), _ptr(grad2d, _dp), _ptr(ms, _dp))
     _check(rc, "render_bwd")
-    return grad, grad2d
+    return (grad, grad2d, ms) if mass else (grad, grad2d)
 
 
 def count_duplicates(params, cam, tile_w=16, tile_h=16, opts: RenderOpts | None = None) -> int:

@@ -50,10 +50,13 @@ int fgso_project(int64_t n, const double *params, const fgso_camera *cam,
  * mode 0: tile-bucketed candidate lists (a conservative pre-cull); mode 1: brute force.
  * pix: optional list of n_pix pixel indices to render (NULL = all pixels); outputs are
  * then indexed by list position. Outputs: rgb (3 planes), depth, alpha, T_final, n_contrib.
- * amb (nullable): per-pixel flag set when any decision at this pixel lies within a
- * relative amb_rel of its cutoff, or two contributors' depths tie within 1e-6 relative.
+ * Candidates are ordered by (depth rounded to binary32, index).
+ * amb (nullable): per-pixel flags: bit 0 (ambiguous) when a cutoff decision at this pixel (Q
+ * against sigma_cut^2, alpha against alpha_min or alpha_max, T against T_min) lies within a
+ * relative amb_rel of its threshold; bit 1 (information only) when two consecutive contributors
+ * have equal binary32 depths and so blend in index order.
  * stats (nullable, 4 doubles): pairs tested until termination (E_f), contributing pairs
- * (E_c), flagged pixels, candidates (Q <= cut^2) before termination. */
+ * (E_c), pixels with bit 0 set, pixels rendered. */
 int fgso_render_fwd(int64_t n, const double *params, const fgso_camera *cam,
                     const fgso_render_opts *o, int mode, int64_t n_pix, const int64_t *pix,
                     double *rgb, double *depth, double *alpha, double *T_final,
@@ -62,11 +65,19 @@ int fgso_render_fwd(int64_t n, const double *params, const fgso_camera *cam,
 /* Analytic backward of fgso_render_fwd. g_rgb (3 planes), g_depth, g_alpha (nullable) are the
  * upstream gradients of the rendered planes (indexed like the forward's outputs when pix is
  * given). grad (14 planes) receives dL/dparams (overwritten). grad2d (nullable, 10 planes of n):
- * dL/d(mean2_x, mean2_y, conic_a, conic_b, conic_c, opacity, r, g, b, depth). */
+ * dL/d(mean2_x, mean2_y, conic_a, conic_b, conic_c, opacity, r, g, b, depth).
+ * mass (nullable, 14 planes of n, a diagnostic): the absolute mass of every gradient entry, which
+ * bounds the rounding error of an evaluation of that sum in a precision of unit roundoff u as
+ * c u mass for a modest c: per 2D entry the sum over pixels of the absolute value of each term, with
+ * dL/dalpha replaced by the sum of the absolute values of its parts (the pair's own share and
+ * everything blended behind it) and the mean terms a dx + b dy split as |a dx| + |b dy|; then
+ * mass_k = sum_j |d grad_k / d grad2d_j| mass2d_j through the per-gaussian chain rule. It does not
+ * model the sensitivity of the terms to rounded inputs, which dominates for splats just past the
+ * near plane (very elongated, far off-centre projections). */
 int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
                     const fgso_render_opts *o, int mode, int64_t n_pix, const int64_t *pix,
                     const double *g_rgb, const double *g_depth, const double *g_alpha,
-                    double *grad, double *grad2d);
+                    double *grad, double *grad2d, double *mass);
 
 /* Number of (tile, gaussian) duplicates under axis-aligned 3-sigma-box binning. */
 int64_t fgso_count_duplicates(int64_t n, const double *params, const fgso_camera *cam,

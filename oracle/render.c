@@ -11,7 +11,9 @@
  *    Sigma' = A Sigma A^T + lowpass * I; conic = Sigma'^-1; culled when det Sigma' <= 0.
  *  - mean2 = (fx tx/tz + cx, fy ty/tz + cy); pixel (x, y) samples (x + 0.5, y + 0.5).
  *  - Per pixel, the candidates are the gaussians with Q = d^T conic d <= sigma_cut^2,
- *    ordered by (depth, index). Eq. 1 is evaluated front to back with
+ *    ordered by (depth, index). The order is a decision that floating point takes; it is taken
+ *    on the depth rounded to binary32, the precision of the rasterizer's sort key (the depth
+ *    itself, as blended, stays FP64), so that equal binary32 depths blend in index order. Eq. 1 is evaluated front to back with
  *    alpha = min(alpha_max, o exp(-Q/2)), skipping alpha < alpha_min, and stopping
  *    (without compositing) at the first gaussian that would take T below T_min.
  *  - Colour = sum w_i c_i + T bg, depth = sum w_i d_i + T bg_depth, opacity = sum w_i,
@@ -178,10 +180,13 @@ static int cmp_key(const void *a, const void *b)
     return (x->i > y->i) - (x->i < y->i);
 }
 
-/* Order idx[0..cnt) by (depth, index) ascending; tmp holds cnt keys. */
+/* The depth that orders the blending: the camera-space depth rounded to binary32. */
+static double order_key(double depth) { return (double)(float)depth; }
+
+/* Order idx[0..cnt) by (binary32 depth, index) ascending; tmp holds cnt keys. */
 static void sort_by_depth(const proj_t *P, int32_t *idx, int64_t cnt, dkey_t *tmp)
 {
-    for (int64_t k = 0; k < cnt; ++k) { tmp[k].d = P[idx[k]].depth; tmp[k].i = idx[k]; }
+    for (int64_t k = 0; k < cnt; ++k) { tmp[k].d = order_key(P[idx[k]].depth); tmp[k].i = idx[k]; }
     qsort(tmp, (size_t)cnt, sizeof(dkey_t), cmp_key);
     for (int64_t k = 0; k < cnt; ++k) idx[k] = tmp[k].i;
 }
@@ -282,21 +287,21 @@ static void composite(const proj_t *P, const double *col, int64_t n, const int32
         if (!g->valid) continue;
         double dx = px - g->m2[0], dy = py - g->m2[1];
         double Q = g->conic[0] * dx * dx + 2 * g->conic[1] * dx * dy + g->conic[2] * dy * dy;
-        if (amb_rel > 0 && fabs(Q - cut2) <= amb_rel * cut2) amb = 1;
+        if (amb_rel > 0 && fabs(Q - cut2) <= amb_rel * cut2) amb |= 1;
         if (!(Q <= cut2)) continue;
         ef += 1;
         double G = exp(-0.5 * Q);
         double ar = g->opacity * G;
         if (amb_rel > 0 && (fabs(ar - o->alpha_min) <= amb_rel * o->alpha_min ||
-                            fabs(ar - o->alpha_max) <= amb_rel * o->alpha_max)) amb = 1;
+                            fabs(ar - o->alpha_max) <= amb_rel * o->alpha_max)) amb |= 1;
         int clamped = ar > o->alpha_max;
         double alpha = clamped ? o->alpha_max : ar;
         if (alpha < o->alpha_min) continue;
         double Tn = T * (1 - alpha);
-        if (amb_rel > 0 && fabs(Tn - o->T_min) <= amb_rel * o->T_min) amb = 1;
+        if (amb_rel > 0 && fabs(Tn - o->T_min) <= amb_rel * o->T_min) amb |= 1;
         if (Tn < o->T_min) break;
-        if (amb_rel > 0 && prev_d >= 0 && fabs(g->depth - prev_d) <= 1e-6 * g->depth) amb = 1;
-        prev_d = g->depth;
+        if (amb_rel > 0 && prev_d >= 0 && order_key(g->depth) == prev_d) amb |= 2;
+        prev_d = order_key(g->depth);
         double w = alpha * T;
         for (int ch = 0; ch < 3; ++ch) C[ch] += w * col[ch * n + i];
         D += w * g->depth;
@@ -422,7 +427,7 @@ int fgso_render_fwd(int64_t n, const double *params, const fgso_camera *cam,
             if (amb) amb[k] = (uint8_t)po.amb;
             ef_tot += po.ef;
             ec_tot += po.nc;
-            amb_tot += po.amb;
+            amb_tot += (po.amb & 1) != 0;
         }
         free(buf);
         free(tmp);
@@ -529,7 +534,7 @@ static void chain_one(const proj_t *p, const fgso_camera *cam, const double *g2,
 int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
                     const fgso_render_opts *o, int mode, int64_t n_pix, const int64_t *pix,
                     const double *g_rgb, const double *g_depth, const double *g_alpha,
-                    double *grad, double *grad2d)
+                    double *grad, double *grad2d, double *mass)
 {
     if (n < 0 || (n > 0 && (!params || !grad)) || !opts_ok(cam, o) || (mode != 0 && mode != 1))
         return -1;
@@ -549,6 +554,9 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
 #endif
     double *acc = (double *)calloc((size_t)nthr * 10 * (size_t)(n > 0 ? n : 1), sizeof(double));
     if (!acc) { teardown(&s); return -2; }
+    /* with mass: the same sums over the absolute values of every term (see fgso.h) */
+    double *macc = mass ? (double *)calloc((size_t)nthr * 10 * (size_t)(n > 0 ? n : 1), sizeof(double)) : NULL;
+    if (mass && !macc) { free(acc); teardown(&s); return -2; }
     int64_t seq_cap = max_contrib(o);
 #pragma omp parallel
     {
@@ -557,6 +565,7 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
         tid = omp_get_thread_num();
 #endif
         double *g2 = acc + (size_t)tid * 10 * (size_t)n;
+        double *m2 = macc ? macc + (size_t)tid * 10 * (size_t)n : NULL;
         int32_t *buf = mode == 1 ? (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) : NULL;
         dkey_t *tmp = mode == 1 ? (dkey_t *)malloc(sizeof(dkey_t) * (size_t)(n > 0 ? n : 1)) : NULL;
         contrib_t *seq = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)seq_cap);
@@ -578,6 +587,9 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
             /* suffix sums of what lies behind contributor j */
             double BC[3] = {Tf * o->bg[0], Tf * o->bg[1], Tf * o->bg[2]};
             double BD = Tf * o->bg_depth;
+            /* absolute mass of what lies behind (for the mass diagnostic) */
+            double Babs = Tf * (fabs(gC[0] * o->bg[0]) + fabs(gC[1] * o->bg[1]) + fabs(gC[2] * o->bg[2]) +
+                                fabs(gD * o->bg_depth) + fabs(gA));
             for (int32_t j = m - 1; j >= 0; --j) {
                 const contrib_t *e = &seq[j];
                 const proj_t *g = &s.P[e->i];
@@ -599,6 +611,25 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
                     d[2 * n + e->i] += dQ * e->dx * e->dx;
                     d[3 * n + e->i] += dQ * 2 * e->dx * e->dy;
                     d[4 * n + e->i] += dQ * e->dy * e->dy;
+                }
+                if (m2) {
+                    double Xabs = fabs(gC[0] * c3[0]) + fabs(gC[1] * c3[1]) + fabs(gC[2] * c3[2]) +
+                                  fabs(gD * g->depth);
+                    for (int ch = 0; ch < 3; ++ch) m2[(6 + ch) * n + e->i] += fabs(gC[ch] * w);
+                    m2[9 * n + e->i] += fabs(gD * w);
+                    if (!e->clamped) {
+                        double dam = Tj * Xabs + Babs / (1 - a); /* mass of dL/dalpha */
+                        double dQm = 0.5 * a * dam;
+                        double ca = fabs(g->conic[0]), cb = fabs(g->conic[1]), cc = fabs(g->conic[2]);
+                        double adx = fabs(e->dx), ady = fabs(e->dy);
+                        m2[5 * n + e->i] += dam * e->G;
+                        m2[0 * n + e->i] += dQm * 2 * (ca * adx + cb * ady);
+                        m2[1 * n + e->i] += dQm * 2 * (cb * adx + cc * ady);
+                        m2[2 * n + e->i] += dQm * adx * adx;
+                        m2[3 * n + e->i] += dQm * 2 * adx * ady;
+                        m2[4 * n + e->i] += dQm * ady * ady;
+                    }
+                    Babs += w * Xabs;
                 }
                 for (int ch = 0; ch < 3; ++ch) BC[ch] += w * c3[ch];
                 BD += w * g->depth;
@@ -623,8 +654,23 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
         double out[14];
         chain_one(&s.P[i], cam, g2, out);
         for (int k = 0; k < 14; ++k) grad[k * n + i] = out[k];
+        if (mass) {
+            /* parameter mass: sum_j |d grad_k / d g2_j| * mass of g2_j (the chain rule is linear) */
+            double mk[14] = {0};
+            for (int j = 0; j < 10; ++j) {
+                double mj = 0;
+                for (int th = 0; th < nthr; ++th) mj += macc[(size_t)th * 10 * (size_t)n + (size_t)j * n + i];
+                if (mj == 0) continue;
+                double unit[10] = {0}, col_j[14];
+                unit[j] = 1;
+                chain_one(&s.P[i], cam, unit, col_j);
+                for (int k = 0; k < 14; ++k) mk[k] += fabs(col_j[k]) * mj;
+            }
+            for (int k = 0; k < 14; ++k) mass[k * n + i] = mk[k];
+        }
     }
     free(acc);
+    free(macc);
     teardown(&s);
     return 0;
 }

@@ -1,6 +1,6 @@
 /*
- * FGS oracle: Fourier seeding of new gaussians (Sec. III-A, "Adaptive Gaussian
- * Densification", Eq. 2-8 and Eq. 11), in FP64 with a naive separable DFT.
+ * FGS oracle: Fourier seeding of new gaussians (Sec. III-A, "Mapping": Eq. 2-8, the triangle
+ * threshold and Eq. 11), in FP64 with a naive separable DFT.
  *
  * TEST INFRASTRUCTURE ONLY (see fgso.h).
  *

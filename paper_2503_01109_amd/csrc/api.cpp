@@ -1151,6 +1151,12 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             ak.beta1 = opt->beta1;
             ak.beta2 = opt->beta2;
             ak.eps = opt->eps;
+            // the bias corrections of the update the host expects (the kernel recomputes them if
+            // the device count differs, after an overflowed step not yet reported)
+            ak.step_expect = opt->step;
+            const double t = (double)(opt->step + 1);
+            ak.bc1 = (float)(1.0 - pow((double)opt->beta1, t));
+            ak.bc2 = (float)(1.0 - pow((double)opt->beta2, t));
         }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
                                    v > 0 ? &grad : nullptr, !last || grad_out ? &grad : nullptr,
@@ -1573,6 +1579,7 @@ fgs_status window_enqueue(fgs_window *w, const fgs_gaussians &params, const fgs_
     ak.m = to_gk(opt.m);
     ak.v = to_gk(opt.v);
     ak.step = step;
+    ak.step_expect = -1;       // a replayed graph meets a new count every time: always recomputed
     ak.skip = words + WW_OVF;  // an overflowed step changes no parameter, moment or step count
     for (int k = 0; k < 5; ++k) ak.lr[k] = opt.lr[k];
     ak.beta1 = opt.beta1;

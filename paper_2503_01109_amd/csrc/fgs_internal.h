@@ -255,14 +255,16 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
                        const float *ddepth_scale, float *grad2d, hipStream_t s);
 
 // Adam hyper-parameters of an update fused into a projection backward. step (nullable) points
-// to the device count of updates already applied (the kernel applies update *step + 1); without
-// it, bc1 and bc2 are the bias corrections of this update. skip (nullable) points to a step's
+// to the device count of updates already applied (the kernel applies update *step + 1): bc1 and
+// bc2 are the bias corrections of update step_expect + 1, used when *step == step_expect (the
+// count the host expects) and recomputed otherwise; without step, bc1 and bc2 are used as given. skip (nullable) points to a step's
 // overflow word: when it is non-zero the step's gradient is incomplete and no parameter or moment
 // changes. step_out (nullable, not aliasing step) receives the count after this step: *step + 1,
 // or *step when skipped (a captured window step advances its counter in a launch of its own).
 struct AdamK {
     GradK m, v;
     const int64_t *step;
+    int64_t step_expect;
     int64_t *step_out;
     const uint32_t *skip;
     float lr[5];

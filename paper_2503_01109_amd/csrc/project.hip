@@ -311,9 +311,12 @@ __device__ inline void adam_update(const AdamK &adam, const ParamsK &g, int64_t 
 {
     float bc1 = adam.bc1, bc2 = adam.bc2;
     if (adam.step) {
-        const double t = (double)(*adam.step + 1);
-        bc1 = (float)(1.0 - pow((double)adam.beta1, t));
-        bc2 = (float)(1.0 - pow((double)adam.beta2, t));
+        const int64_t s = *adam.step;
+        if (s != adam.step_expect) {
+            const double t = (double)(s + 1);
+            bc1 = (float)(1.0 - pow((double)adam.beta1, t));
+            bc2 = (float)(1.0 - pow((double)adam.beta2, t));
+        }
     }
     GradK P{g.n, g.stride, (float *)g.mean, (float *)g.log_scale, (float *)g.quat, (float *)g.logit, (float *)g.rgb};
 #pragma unroll

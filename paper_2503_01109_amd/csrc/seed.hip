@@ -1,4 +1,4 @@
-// Fourier seeding of new gaussians (Sec. III-A, "Adaptive Gaussian Densification").
+// Fourier seeding of new gaussians (Sec. III-A, "Mapping": Eq. 2-8, the triangle threshold, Eq. 11).
 //
 //  1. luma of the frame (BT.601, FP64) and the 2D DFT of Eq. 2, as row transforms followed by
 //     column transforms;

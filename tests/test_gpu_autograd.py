@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import assert_close_rel, need_gpu
+from gpu_helpers import assert_close_rel, need_gpu, oracle_opts, assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def test_autograd_matches_oracle(mods):
     F, A, torch = mods
     p = synth.scene_small(3)
     cam = synth.camera_small()
-    ref = oracle.render_fwd(p.astype(np.float64), cam, amb_rel=1e-5)
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(), amb_rel=1e-5)
     ok = ~ref["amb"]
     g = synth.rng(77)
     gr = g.normal(size=(3, cam.height, cam.width)) * ok
@@ -41,11 +41,10 @@ def test_autograd_matches_oracle(mods):
         (depth * torch.tensor(gd, dtype=torch.float32, device="cuda")).sum() + \
         (alpha * torch.tensor(ga, dtype=torch.float32, device="cuda")).sum()
     loss.backward()
-    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, ga)
+    gref, _, mass = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, ga, oracle_opts(), mass=True)
     got = np.concatenate([tens[0].grad.cpu().numpy(), tens[1].grad.cpu().numpy(), tens[2].grad.cpu().numpy(),
                           tens[3].grad.cpu().numpy()[None], tens[4].grad.cpu().numpy()])
-    for rows in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11), slice(11, 14)):
-        assert_close_rel(got[rows], gref[rows], 1e-4, what=f"rows {rows}", floor=1e-2)
+    assert_grad_close(got, gref, mass, "autograd")
     assert_close_rel(rgb.detach().cpu().numpy(), ref["rgb"], 1e-5, ok, "rgb")
 
 

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import assert_close_rel, dev, host, need_gpu
+from gpu_helpers import assert_close_rel, dev, host, need_gpu, oracle_opts, assert_grad_close, near_plane_splats
 
 pytestmark = pytest.mark.gpu
 LR = (1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3)
@@ -107,13 +107,13 @@ def test_window_first_view_matches_oracle(fgs, ctx):
     from test_gpu_mapstep import zero_ambiguity_scene
     p, cam, seed = zero_ambiguity_scene()
     n = p.shape[1]
-    ref = oracle.render_fwd(p.astype(np.float64), cam, amb_rel=0)
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(), amb_rel=0)
     tgt = oracle.render_fwd(synth.frustum_scene(seed + 1000, n, cam, 1.0, 5.0).astype(np.float64), cam, amb_rel=0)
     trgb, td = tgt["rgb"].astype(np.float32), tgt["depth"].astype(np.float32)
     trgb[np.abs(ref["rgb"] - trgb) < 1e-3] += 0.01
     td[np.abs(ref["depth"] - td) < 1e-3] += 0.01
     L, ps, gr, gd = oracle.loss_l1(ref["rgb"], ref["depth"], trgb, td, 1.0, 0.1)
-    gref, _ = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, None)
+    gref, _, mass = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, None, oracle_opts(), mass=True)
     pd = dev(p)
     adam = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
     grad = torch.zeros_like(pd)
@@ -124,10 +124,85 @@ def test_window_first_view_matches_oracle(fgs, ctx):
     assert abs(float(loss) - L) <= 1e-5 * L
     assert abs(float(psnr) - ps) <= 1e-5 * ps
     gg = host(grad)
-    for rows in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11), slice(11, 14)):
-        assert_close_rel(gg[rows], gref[rows], 1e-4, what=f"grad rows {rows}", floor=1e-2)
+    assert_grad_close(gg, gref, mass, "one-view window")
     np.testing.assert_array_equal(host(pd), p)  # lr = 0
     win.close()
+
+
+@pytest.mark.parametrize("blocks_per_cu,graph", [(0, False), (0, True), (2, False), (2, True)])
+def test_uneven_window_matches_oracle(fgs, ctx, blocks_per_cu, graph):
+    """Four views of different sizes and poses with 16x16, 32x8, 8x32 and 16x16 tiles, one
+    workgroup per item or a persistent grid, eager or graph-replayed: each view's loss against the
+    oracle's forward and L1 terms of Eq. 16, and the gradient summed over the views and the first
+    Adam update against the oracle's per-view backward (ambiguous pixels masked out of the targets
+    on both sides)."""
+    import torch
+    from oracle_ref import mapping_reference
+    cams, tiles = small_views()
+    p = synth.frustum_scene(14, 1500, cams[0], 1.0, 5.0)
+    n = p.shape[1]
+    targets = [(host(a), host(b)) for a, b in random_targets(cams, 150)]
+    R = mapping_reference(p, cams, targets)
+    win = fgs.Window(ctx, cams, tiles, blocks_per_cu)
+    pd = dev(p)
+    loss, psnr = torch.zeros(len(cams), device="cuda"), torch.zeros(len(cams), device="cuda")
+    win.step(pd, n, fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0)), [(dev(a), dev(b)) for a, b in R["targets"]],
+             fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1), loss, psnr, graph=graph)
+    ctx.check()
+    np.testing.assert_allclose(host(loss), R["loss"], rtol=1e-5)
+    np.testing.assert_allclose(host(psnr), R["psnr"], rtol=1e-5)
+    adam = fgs.Adam.like(pd, lr=LR)
+    grad = torch.zeros_like(pd)
+    win.step(pd, n, adam, [(dev(a), dev(b)) for a, b in R["masked"]], fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1),
+             grad_out=grad, graph=graph)
+    ctx.check()
+    gg, gref = host(grad), R["grad"]
+    assert_grad_close(gg, gref, R["mass"], "uneven window")
+    lr = np.array(LR)[GROUP][:, None]
+    expect = p - lr * gref / (np.abs(gref) + 1e-15)
+    big = np.abs(gref) >= 1e-2 * np.abs(gref).max(axis=1, keepdims=True)
+    np.testing.assert_allclose(host(pd)[big], expect[big], rtol=1e-6, atol=1e-6)
+    win.close()
+
+
+def test_full_window_matches_oracle(fgs):
+    """The 8-view window at its real shapes (500k gaussians in a 6x6x4 m box, four 640x480 views
+    with 32x8 tiles and four 1200x680 views with 16x16 tiles, graph replay) against the oracle's
+    per-view forward, L1 terms of Eq. 16 and backward, summed over the views (random targets;
+    ambiguous pixels masked out on both sides). Losses at 1e-5; gradients at the parity bar
+    (assert_grad_close). The cameras stand inside the scene, so some 8% of the gaussians lie within
+    25% of the near plane in some view; their projections are huge (radius up to ~27,000 px), very
+    elongated and far off-centre, and the binary32 rounding of those projections, not the sums,
+    decides their gradients to about 1e-3 (measured: up to 0.72% of the absolute mass): they are
+    held to the near-plane allowance."""
+    import torch
+    from oracle_ref import mapping_reference
+    c = fgs.Context()
+    cams = synth.window_cameras(0)
+    p = synth.scene_window(0)
+    n = p.shape[1]
+    targets = []
+    for k, cam in enumerate(cams):
+        g = synth.rng(900 + k)
+        targets.append((g.uniform(size=(3, cam.height, cam.width)).astype(np.float32),
+                        g.uniform(1, 4, (cam.height, cam.width)).astype(np.float32)))
+    R = mapping_reference(p, cams, targets, log=lambda s: print(s, flush=True))
+    near = near_plane_splats(p, cams)
+    win = fgs.Window(c, cams, [(32, 8)] * 4 + [(16, 16)] * 4, 0)
+    pd = dev(p)
+    loss = torch.zeros(len(cams), device="cuda")
+    win.step(pd, n, fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0)), [(dev(a), dev(b)) for a, b in R["targets"]],
+             fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1), loss, graph=True)
+    grad = torch.zeros_like(pd)
+    win.step(pd, n, fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0)), [(dev(a), dev(b)) for a, b in R["masked"]],
+             fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1), grad_out=grad, graph=True)
+    c.check()
+    np.testing.assert_allclose(host(loss), R["loss"], rtol=1e-5)
+    gg, gref = host(grad).astype(np.float64), R["grad"]
+    print(f"{int(near.sum())} near-plane splats of {n}", flush=True)
+    assert_grad_close(gg, gref, R["mass"], "8-view window", near=near)
+    win.close()
+    c.close()
 
 
 def test_graph_replays_match_eager_steps(fgs, ctx):

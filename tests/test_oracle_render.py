@@ -100,6 +100,30 @@ def test_two_gaussian_ordering_and_ties():
         np.testing.assert_allclose(out["rgb"][:, 0], expect, rtol=1e-13)
 
 
+def test_order_takes_the_binary32_depth():
+    """The blending order is decided on the depth rounded to binary32 (the precision of the
+    rasterizer's sort key), ties in index order: depths 2 + 2^-30 and 2 round to the same binary32
+    value, so index 0 (the deeper one in FP64) blends first; 2 + 2^-20 is four binary32 steps
+    above 2, so index 1 (at 2) blends first. The blended depth value stays FP64."""
+    cam = Camera(16, 16, 40.0, 40.0, 8.5, 8.5)
+    c1, c2 = (1.0, 0.0, 0.0), (0.0, 0.0, 1.0)
+    l1, l2 = 0.4, -0.2
+    o1, o2 = 1 / (1 + np.exp(-l1)), 1 / (1 + np.exp(-l2))
+    pix = [8 * 16 + 8]
+    for dz, first in ((2.0 ** -30, 1), (2.0 ** -20, 2)):
+        z1 = 2.0 + dz
+        p = stack(one_gaussian((0, 0, z1), [np.log(0.05)] * 3, logit=l1, rgb=c1),
+                  one_gaussian((0, 0, 2.0), [np.log(0.05)] * 3, logit=l2, rgb=c2))
+        out = oracle.render_fwd(p, cam, O, mode=1, pix=pix, amb_rel=1e-5)
+        if first == 1:
+            w1, w2 = o1, o2 * (1 - o1)
+        else:
+            w1, w2 = o1 * (1 - o2), o2
+        np.testing.assert_allclose(out["rgb"][:, 0], w1 * np.array(c1) + w2 * np.array(c2), rtol=1e-13)
+        np.testing.assert_allclose(out["depth"][0], w1 * z1 + w2 * 2.0, rtol=1e-15)
+        assert bool(out["amb_tie"][0]) == (first == 1) and not out["amb"][0]
+
+
 def test_termination_semantics():
     """P3: identical alpha = 0.5 contributors: 2^-14 < 1e-4 <= 2^-13, so 13 composite and the
     14th is dropped (not composited) when the pixel stops."""
