@@ -45,6 +45,23 @@ class _SeedOpts(C.Structure):
                 ("depth_min", C.c_double), ("depth_max", C.c_double)]
 
 
+class _Missing(C.Structure):
+    _fields_ = [("alpha", _fp), ("depth", _fp), ("rgb", _fp), ("tau_alpha", C.c_float), ("tau_depth", C.c_float),
+                ("tau_rgb", C.c_float)]
+
+
+@dataclass
+class MissingCheck:
+    """The current map rendered at the frame's pose (binary32 planes: opacity (H, W), depth (H, W),
+    rgb (3, H, W)) and the thresholds of the missing-region check (Sec. III-A, Eq. 9, 10)."""
+    alpha: object
+    depth: object
+    rgb: object
+    tau_alpha: float = 0.5
+    tau_depth: float = 0.1
+    tau_rgb: float = 0.3
+
+
 @dataclass
 class RenderOpts:
     """Cutoffs of the compositing (3-sigma, alpha >= 1/255, alpha <= 0.99, stop before T < 1e-4)."""
@@ -108,7 +125,7 @@ def lib():
         L.fgso_triangle.restype = C.c_int32
         L.fgso_seed.argtypes = [C.c_int32, C.c_int32, _fp, _fp, _fp, _fp, C.c_float, C.c_float, C.c_float,
                                 C.c_float, C.POINTER(_SeedOpts), C.c_int64, _i32p, _u8p, _fp, _fp, _fp,
-                                _i32p, _i32p, _dp]
+                                _i32p, _i32p, _dp, C.POINTER(_Missing), _u8p]
         L.fgso_seed.restype = C.c_int64
         L.fgso_tile_features.argtypes = [C.c_int32, C.c_int32, _fp, _fp, C.c_int32, C.c_int32, C.c_double,
                                          C.c_double, _dp]
@@ -240,8 +257,10 @@ def triangle(hist) -> int:
     return int(lib().fgso_triangle(_ptr(h, _i64p)))
 
 
-def seed(rgb, depth, cam, opts: SeedOpts | None = None, capacity: int | None = None) -> dict:
-    """Fourier seeding of one RGB-D frame; float outputs are binary32."""
+def seed(rgb, depth, cam, opts: SeedOpts | None = None, capacity: int | None = None,
+         miss: MissingCheck | None = None) -> dict:
+    """Fourier seeding of one RGB-D frame; float outputs are binary32. miss: the missing-region
+    check against the current map (None: no map yet); the result's "missing" is M_m."""
     o = opts or SeedOpts()
     r = np.ascontiguousarray(rgb, dtype=np.float32)
     d = np.ascontiguousarray(depth, dtype=np.float32)
@@ -255,13 +274,22 @@ def seed(rgb, depth, cam, opts: SeedOpts | None = None, capacity: int | None = N
     t = C.c_int32(); mg = C.c_double()
     R = np.ascontiguousarray(cam.R, np.float32).reshape(9)
     tt = np.ascontiguousarray(cam.t, np.float32).reshape(3)
+    missing = np.zeros(H * W, np.uint8)
+    cm = None
+    if miss is not None:
+        ma = np.ascontiguousarray(miss.alpha, np.float32).reshape(H * W)
+        md = np.ascontiguousarray(miss.depth, np.float32).reshape(H * W)
+        mr = np.ascontiguousarray(miss.rgb, np.float32).reshape(3 * H * W)
+        cm = _Missing(_ptr(ma, _fp), _ptr(md, _fp), _ptr(mr, _fp), miss.tau_alpha, miss.tau_depth, miss.tau_rgb)
     n = lib().fgso_seed(W, H, _ptr(r, _fp), _ptr(d, _fp), _ptr(R, _fp), _ptr(tt, _fp), cam.fx, cam.fy, cam.cx,
                         cam.cy, C.byref(o.c()), cap, _ptr(pixel, _i32p), _ptr(hi, _u8p), _ptr(mean, _fp),
-                        _ptr(rad, _fp), _ptr(srgb, _fp), _ptr(tc, _i32p), C.byref(t), C.byref(mg))
+                        _ptr(rad, _fp), _ptr(srgb, _fp), _ptr(tc, _i32p), C.byref(t), C.byref(mg),
+                        None if cm is None else C.byref(cm), _ptr(missing, _u8p))
     _check(n, "seed")
     k = min(n, cap)
     return dict(n=int(n), pixel=pixel[:k], is_high=hi[:k].astype(bool), mean=mean[:, :k], radius=rad[:k],
-                rgb=srgb[:, :k], tile_count=tc.reshape(ty, tx), threshold=t.value, margin=mg.value)
+                rgb=srgb[:, :k], tile_count=tc.reshape(ty, tx), threshold=t.value, margin=mg.value,
+                missing=missing.reshape(H, W).astype(bool))
 
 
 def tile_features(rgb, depth, tx, ty, depth_min=0.1, depth_max=10.0):

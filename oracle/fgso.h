@@ -116,15 +116,30 @@ int fgso_highpass(int32_t W, int32_t H, const float *rgb, double D0, double *E,
 /* Triangle threshold over a 256-bin histogram. */
 int32_t fgso_triangle(const int64_t *hist);
 
+/* Missing-region check (Sec. III-A, Eq. 9 and 10) against the current map rendered at the
+ * frame's pose: binary32 planes of W*H, the rendered opacity (Eq. 1 with gamma = 1), depth (gamma
+ * = d) and 3 colour planes. A pixel is missing (M_m = M_i | M_d | M_c, Eq. 9) when
+ *   M_i: rendered opacity < tau_alpha (too little gaussian there);
+ *   M_d: its frame depth is valid and |rendered depth - frame depth| > tau_depth (foreground that
+ *        the map lacks);
+ *   M_c: (|dr| + |dg|) + |db| > tau_rgb over the rendered minus the frame colour;
+ * each difference, absolute value and sum a binary32 operation, the comparisons strict. */
+typedef struct {
+    const float *alpha, *depth, *rgb;
+    float tau_alpha, tau_depth, tau_rgb;
+} fgso_missing;
+
 /* Full seeding: returns the number of seeds (or < 0 on error). Seeds are written in
  * ascending pixel order, at most `capacity`: pixel id, class (1 = high frequency),
  * mean (3 planes of capacity), radius, rgb (3 planes of capacity). tile_count has
- * ceil(W/tile)*ceil(H/tile) entries. Float outputs are binary32 values. */
+ * ceil(W/tile)*ceil(H/tile) entries. Float outputs are binary32 values. miss (nullable: no map
+ * yet, every pixel missing) restricts the high- and low-frequency masks to the missing region
+ * (Eq. 10); missing_out (nullable, W*H) receives M_m. */
 int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
                   const float cam_R[9], const float cam_t[3], float fx, float fy, float cx, float cy,
                   const fgso_seed_opts *o, int64_t capacity, int32_t *pixel, uint8_t *is_high,
                   float *mean, float *radius, float *seed_rgb, int32_t *tile_count,
-                  int32_t *thresh_out, double *margin_out);
+                  int32_t *thresh_out, double *margin_out, const fgso_missing *miss, uint8_t *missing_out);
 
 /* ------------------------------- Learned prior MLP ------------------------------- */
 /* Tile features: 256 values log(1 + |F_c|) of the tile's 16x16 luma DFT (Eq. 2-4, centred),

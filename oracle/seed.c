@@ -165,8 +165,9 @@ int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
                   const float cam_R[9], const float cam_t[3], float fx, float fy, float cx, float cy,
                   const fgso_seed_opts *o, int64_t capacity, int32_t *pixel, uint8_t *is_high,
                   float *mean, float *radius, float *seed_rgb, int32_t *tile_count,
-                  int32_t *thresh_out, double *margin_out)
+                  int32_t *thresh_out, double *margin_out, const fgso_missing *miss, uint8_t *missing_out)
 {
+    if (miss && (!miss->alpha || !miss->depth || !miss->rgb)) return -1;
     if (W <= 0 || H <= 0 || !rgb || !depth || !o || !cam_R || !cam_t) return -1;
     if (o->m <= 0 || o->n <= 0 || o->tile <= 0 || capacity < 0) return -1;
     if (!(fx > 0) || !(fy > 0)) return -1;
@@ -187,7 +188,21 @@ int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
         for (int32_t x = 0; x < W; ++x) {
             int64_t p = (int64_t)y * W + x;
             float d = depth[p];
-            if (!isfinite(d) || !(d >= o->depth_min) || !(d <= o->depth_max)) continue;
+            int valid = isfinite(d) && d >= o->depth_min && d <= o->depth_max;
+            /* Eq. 9: the missing region; without a map every pixel is missing */
+            int missing = 1;
+            if (miss) {
+                int Mi = miss->alpha[p] < miss->tau_alpha;
+                int Md = valid && fabsf(f_sub(miss->depth[p], d)) > miss->tau_depth;
+                float dc = 0;
+                for (int c = 0; c < 3; ++c) dc = f_add(dc, fabsf(f_sub(miss->rgb[c * P + p], rgb[c * P + p])));
+                int Mc = dc > miss->tau_rgb;
+                missing = Mi || Md || Mc;
+            }
+            if (missing_out) missing_out[p] = (uint8_t)missing;
+            if (!valid) continue;
+            /* Eq. 10: both frequency masks are restricted to the missing region */
+            if (!missing) continue;
             int high = 0;
             if (Emax > 0) {
                 int32_t q = (int32_t)floor(255.0 * (E[p] / Emax));

@@ -237,3 +237,85 @@ def test_seed_set_from_numpy_mask():
     np.testing.assert_array_equal(s["pixel"], expect)
     np.testing.assert_array_equal(s["is_high"], hi.ravel()[expect])
     assert 0 < s["is_high"].sum() < len(expect)
+
+
+# ------------------------------------------------ missing-region check (Eq. 9, 10)
+
+def missing_frame():
+    rgb, depth = synth.rgbd_frame(11, W, H, n_rect=8)
+    depth[:4, :] = 0.0  # a band without depth measurements
+    return rgb, depth, Camera(W, H, 60.0, 60.0, W / 2, H / 2)
+
+
+def rendered_like(rgb, depth, alpha=1.0):
+    """A map that explains the frame exactly: opacity `alpha`, the frame's own colour and depth."""
+    return oracle.MissingCheck(np.full(depth.shape, alpha, np.float32), depth.copy(), rgb.copy())
+
+
+def test_missing_check_first_frame_is_the_identity():
+    """No map yet, or a map whose rendered opacity is 0 everywhere (M_i is the whole frame): the
+    seeds are those of the plain seeding, and M_m is every pixel."""
+    rgb, depth, cam = missing_frame()
+    plain = oracle.seed(rgb, depth, cam)
+    assert plain["missing"].all()
+    empty = oracle.seed(rgb, depth, cam, miss=oracle.MissingCheck(np.zeros_like(depth), np.zeros_like(depth),
+                                                                   np.zeros_like(rgb)))
+    assert empty["missing"].all()
+    for k in ("pixel", "is_high", "mean", "radius", "rgb", "tile_count"):
+        np.testing.assert_array_equal(empty[k], plain[k], err_msg=k)
+
+
+def test_missing_check_fully_explained_frame_seeds_nothing():
+    rgb, depth, cam = missing_frame()
+    s = oracle.seed(rgb, depth, cam, miss=rendered_like(rgb, depth))
+    assert s["n"] == 0 and not s["missing"].any() and s["tile_count"].sum() == 0
+
+
+def test_missing_check_masks_and_the_seeds_they_keep():
+    """Three disjoint rectangles, each missing for one reason: low rendered opacity (M_i), a
+    rendered depth 0.3 m off the frame's (M_d), a rendered colour 0.2 off per channel (M_c). M_m is
+    exactly their union (Eq. 9), and the seeds are exactly the plain seeds inside it (Eq. 10: both
+    frequency masks restricted to M_m, the lattices and radii unchanged)."""
+    rgb, depth, cam = missing_frame()
+    plain = oracle.seed(rgb, depth, cam)
+    m = rendered_like(rgb, depth)
+    A, B, Cr = (slice(8, 20), slice(5, 30)), (slice(24, 40), slice(10, 50)), (slice(2, 12), slice(40, 70))
+    m.alpha[A] = 0.2
+    m.depth[B] += 0.3
+    m.rgb[(slice(None),) + Cr] = np.clip(m.rgb[(slice(None),) + Cr] + 0.2, 0.0, 1.2)
+    s = oracle.seed(rgb, depth, cam, miss=m)
+    expect_mask = np.zeros(depth.shape, bool)
+    expect_mask[A] = True
+    valid = (depth >= 0.1) & (depth <= 10.0)
+    expect_mask[B] |= valid[B]  # the depth mask needs a depth measurement
+    expect_mask[Cr] = True
+    np.testing.assert_array_equal(s["missing"], expect_mask)
+    keep = expect_mask.ravel()[plain["pixel"]]
+    assert keep.sum() > 20 and (~keep).sum() > 50
+    np.testing.assert_array_equal(s["pixel"], plain["pixel"][keep])
+    np.testing.assert_array_equal(s["is_high"], plain["is_high"][keep])
+    np.testing.assert_array_equal(s["mean"], plain["mean"][:, keep])
+    np.testing.assert_array_equal(s["radius"], plain["radius"][keep])
+    assert s["tile_count"].sum() == s["n"]
+
+
+def test_missing_check_thresholds_are_strict():
+    """An opacity equal to tau_alpha is not missing; a depth difference equal to tau_depth is not;
+    a colour difference summing to exactly tau_rgb is not (values exact in binary32); just past each
+    threshold is; a huge depth difference at a pixel without a depth measurement is not."""
+    rgb, depth, cam = missing_frame()
+    rgb = np.full_like(rgb, 0.5)
+    depth = np.where(depth > 0, 2.0, 0.0).astype(np.float32)
+    m = rendered_like(rgb, depth)
+    m.alpha[10, 10], m.alpha[10, 11] = 0.5, np.nextafter(np.float32(0.5), np.float32(0))
+    m.depth[12, 10], m.depth[12, 11] = 2.125, np.nextafter(np.float32(2.125), np.float32(3))
+    m.rgb[:, 14, 10] = 0.5 + np.float32(0.125)           # (0.125 + 0.125) + 0.125 = 0.375 exactly
+    m.rgb[:, 14, 11] = [0.625, 0.625, np.nextafter(np.float32(0.625), np.float32(1))]
+    m.depth[1, 20] = 50.0                                 # row 1 has no depth measurement
+    s = oracle.seed(rgb, depth, cam, miss=oracle.MissingCheck(m.alpha, m.depth, m.rgb, 0.5, 0.125, 0.375))
+    mm = s["missing"]
+    assert not mm[10, 10] and mm[10, 11]
+    assert not mm[12, 10] and mm[12, 11]
+    assert not mm[14, 10] and mm[14, 11]
+    assert not mm[1, 20]
+    assert mm.sum() == 3
