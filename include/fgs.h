@@ -7,7 +7,8 @@
  * back alpha blending (Eq. 1, with gamma = colour, depth and 1), differentiates that
  * rendering, optimises the map against an RGB-D frame with the L1 colour and depth terms of
  * the mapping loss (Eq. 16) and Adam, and seeds new gaussians from a frame by the Fourier
- * high-pass analysis of Sec. III-A (Eq. 2-8, the triangle threshold, Eq. 11).
+ * high-pass analysis of Sec. III-A (Eq. 2-8, the triangle threshold, the missing-region check of
+ * Eq. 9-10, Eq. 11).
  *
  * Conventions shared by every call:
  *  - Pointers are DEVICE pointers unless a parameter is marked [host].
@@ -266,7 +267,15 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
  * Seeds need a finite depth in [depth_min, depth_max]. use_prior = 1 replaces the radius rule and
  * the constant opacity of the gaussians written into out->params (required then) by the learned
  * prior of fgs_prior.h, evaluated on the frame's 16x16 tiles, whose packed FP32 weights `prior`
- * points to (device); the seed set and the seed arrays are unchanged. */
+ * points to (device); the seed set and the seed arrays are unchanged.
+ * Missing-region check (Sec. III-A, Eq. 9, 10): render_alpha, render_depth (width*height) and
+ * render_rgb (3 planes) are the current map rendered at cam with a black background and background
+ * depth 0 (fgs_render_fwd's opacity A, depth and colour planes; device). A pixel is missing when
+ * A < miss_alpha (M_i), or A > 0 and either its depth is valid and |rendered depth / A - depth| >
+ * miss_depth (M_d) or (|dr| + |dg|) + |db| > miss_rgb for the rendered colour / A minus the frame
+ * colour (M_c), each a binary32 operation; only missing pixels seed (both frequency masks are
+ * intersected with M_m). render_alpha NULL: no map yet, every pixel is missing (the other two
+ * pointers are then ignored). */
 typedef struct {
     double D0;
     int32_t m, n, tile;
@@ -274,6 +283,8 @@ typedef struct {
     float depth_min, depth_max;
     int32_t use_prior;
     const void *prior;
+    const float *render_alpha, *render_depth, *render_rgb;
+    float miss_alpha, miss_depth, miss_rgb;
 } fgs_seed_opts;
 
 /* Seed output (device). Seeds are written in ascending pixel order (y * width + x), at most
@@ -285,7 +296,8 @@ typedef struct {
  * logit and the pixel colour (params.stride >= capacity). E (width*height doubles: |I_h|), hist
  * (256 uint32: histogram of q = floor(255 E / E_max)) and threshold (one int32: the triangle
  * threshold, -1 for a flat frame) are optional diagnostics. With the learned prior, from_prior
- * (capacity bytes, nullable) marks the seeds whose shape and opacity came from the prior. */
+ * (capacity bytes, nullable) marks the seeds whose shape and opacity came from the prior. missing
+ * (width*height bytes, nullable) receives the missing-region mask M_m (1 = missing). */
 typedef struct {
     int64_t capacity;
     int32_t *pixel;
@@ -300,12 +312,14 @@ typedef struct {
     uint32_t *hist;
     int32_t *threshold;
     uint8_t *from_prior;
+    uint8_t *missing;
 } fgs_seed_out;
 
 /* Seeds gaussians from one RGB-D frame (rgb: 3 planes, depth: 1 plane, width*height of cam) by the
  * frequency analysis of Sec. III-A: luma DFT (Eq. 2), Gaussian high-pass centred on DC (Eq. 3, 5,
- * 7), inverse DFT (Eq. 8), the triangle threshold of the magnitude histogram, lattice sampling
- * with strides m and n, and back-projection through cam with the radius rule of Eq. 11. Frame
+ * 7), inverse DFT (Eq. 8), the triangle threshold of the magnitude histogram, the missing-region
+ * check against the current map (Eq. 9, 10; see fgs_seed_opts), lattice sampling with strides m
+ * and n, and back-projection through cam with the radius rule of Eq. 11. Frame
  * lines must be at most 1920 pixels with prime factors up to 31. n_seeds_host [host] (may be NULL)
  * waits for the stream and receives the number of seeds; more seeds than capacity then returns
  * FGS_ERR_CAPACITY (otherwise the next fgs_ctx_check reports it). */

@@ -117,13 +117,14 @@ int fgso_highpass(int32_t W, int32_t H, const float *rgb, double D0, double *E,
 int32_t fgso_triangle(const int64_t *hist);
 
 /* Missing-region check (Sec. III-A, Eq. 9 and 10) against the current map rendered at the
- * frame's pose: binary32 planes of W*H, the rendered opacity (Eq. 1 with gamma = 1), depth (gamma
- * = d) and 3 colour planes. A pixel is missing (M_m = M_i | M_d | M_c, Eq. 9) when
- *   M_i: rendered opacity < tau_alpha (too little gaussian there);
- *   M_d: its frame depth is valid and |rendered depth - frame depth| > tau_depth (foreground that
- *        the map lacks);
- *   M_c: (|dr| + |dg|) + |db| > tau_rgb over the rendered minus the frame colour;
- * each difference, absolute value and sum a binary32 operation, the comparisons strict. */
+ * frame's pose (black background, background depth 0): binary32 planes of W*H, the rendered
+ * opacity A (Eq. 1 with gamma = 1), depth (gamma = d) and 3 colour planes. A pixel is missing
+ * (M_m = M_i | M_d | M_c, Eq. 9) when
+ *   M_i: A < tau_alpha (too little gaussian there);
+ *   M_d: A > 0, its frame depth is valid and |rendered depth / A - frame depth| > tau_depth
+ *        (foreground that the map lacks);
+ *   M_c: A > 0 and (|dr| + |dg|) + |db| > tau_rgb over the rendered colour / A minus the frame's;
+ * each division, difference, absolute value and sum a binary32 operation, comparisons strict. */
 typedef struct {
     const float *alpha, *depth, *rgb;
     float tau_alpha, tau_depth, tau_rgb;

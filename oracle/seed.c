@@ -192,11 +192,17 @@ int64_t fgso_seed(int32_t W, int32_t H, const float *rgb, const float *depth,
             /* Eq. 9: the missing region; without a map every pixel is missing */
             int missing = 1;
             if (miss) {
-                int Mi = miss->alpha[p] < miss->tau_alpha;
-                int Md = valid && fabsf(f_sub(miss->depth[p], d)) > miss->tau_depth;
-                float dc = 0;
-                for (int c = 0; c < 3; ++c) dc = f_add(dc, fabsf(f_sub(miss->rgb[c * P + p], rgb[c * P + p])));
-                int Mc = dc > miss->tau_rgb;
+                /* M_d and M_c compare the surface the map shows: the rendered depth and colour over
+                   the rendered opacity (Eq. 1 with gamma = d, c divided by gamma = 1) */
+                float A = miss->alpha[p];
+                int Mi = A < miss->tau_alpha, Md = 0, Mc = 0;
+                if (A > 0) {
+                    Md = valid && fabsf(f_sub(f_div(miss->depth[p], A), d)) > miss->tau_depth;
+                    float dc = 0;
+                    for (int c = 0; c < 3; ++c)
+                        dc = f_add(dc, fabsf(f_sub(f_div(miss->rgb[c * P + p], A), rgb[c * P + p])));
+                    Mc = dc > miss->tau_rgb;
+                }
                 missing = Mi || Md || Mc;
             }
             if (missing_out) missing_out[p] = (uint8_t)missing;

@@ -77,14 +77,16 @@ class CLossOpts(C.Structure):
 class CSeedOpts(C.Structure):
     _fields_ = [("D0", C.c_double), ("m", C.c_int32), ("n", C.c_int32), ("tile", C.c_int32),
                 ("alpha_h", C.c_float), ("alpha_l", C.c_float), ("opacity_logit", C.c_float),
-                ("depth_min", C.c_float), ("depth_max", C.c_float), ("use_prior", C.c_int32), ("prior", C.c_void_p)]
+                ("depth_min", C.c_float), ("depth_max", C.c_float), ("use_prior", C.c_int32), ("prior", C.c_void_p),
+                ("render_alpha", _fp), ("render_depth", _fp), ("render_rgb", _fp), ("miss_alpha", C.c_float),
+                ("miss_depth", C.c_float), ("miss_rgb", C.c_float)]
 
 
 class CSeedOut(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("pixel", _i32p), ("is_high", C.POINTER(C.c_uint8)), ("mean", _fp),
                 ("radius", _fp), ("rgb", _fp), ("tile_count", _i32p), ("n_dev", C.POINTER(C.c_int64)),
                 ("params", CGaussians), ("E", C.POINTER(C.c_double)), ("hist", C.POINTER(C.c_uint32)),
-                ("threshold", _i32p), ("from_prior", C.POINTER(C.c_uint8))]
+                ("threshold", _i32p), ("from_prior", C.POINTER(C.c_uint8)), ("missing", C.POINTER(C.c_uint8))]
 
 
 class CPriorAdam(C.Structure):
@@ -464,6 +466,14 @@ class SeedOpts:
     depth_max: float = 10.0
     use_prior: int = 0
     prior: object = None
+    # missing-region check (Sec. III-A, Eq. 9, 10): the current map rendered at the frame's pose
+    # (float32 device tensors: opacity (H, W), depth (H, W), rgb (3, H, W)); None: no map yet
+    render_alpha: object = None
+    render_depth: object = None
+    render_rgb: object = None
+    miss_alpha: float = 0.5
+    miss_depth: float = 0.1
+    miss_rgb: float = 0.3
 
     def c(self) -> CSeedOpts:
         o = CSeedOpts()
@@ -471,6 +481,9 @@ class SeedOpts:
         o.alpha_h, o.alpha_l, o.opacity_logit = self.alpha_h, self.alpha_l, self.opacity_logit
         o.depth_min, o.depth_max, o.use_prior = self.depth_min, self.depth_max, self.use_prior
         o.prior = None if self.prior is None else C.c_void_p(self.prior.data_ptr())
+        o.render_alpha, o.render_depth, o.render_rgb = (_f32(self.render_alpha), _f32(self.render_depth),
+                                                        _f32(self.render_rgb))
+        o.miss_alpha, o.miss_depth, o.miss_rgb = self.miss_alpha, self.miss_depth, self.miss_rgb
         return o
 
 
@@ -510,6 +523,9 @@ def seed_gaussians(ctx: Context, rgb, depth, cam, opts: SeedOpts | None = None, 
     if o.use_prior:
         r["from_prior"] = torch.zeros(cap, dtype=torch.uint8, device=dev)
         out.from_prior = _ptr(r["from_prior"], C.POINTER(C.c_uint8))
+    if diagnostics:
+        r["missing"] = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        out.missing = _ptr(r["missing"], C.POINTER(C.c_uint8))
     n = C.c_int64(-1)
     _check(_lib.fgs_seed_gaussians(ctx.handle, _f32(rgb), _f32(depth), C.byref(camera(cam)), C.byref(o.c()),
                                    C.byref(out), C.byref(n) if sync else None), ctx.handle)

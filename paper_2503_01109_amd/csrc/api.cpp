@@ -1190,6 +1190,10 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
         !(o->depth_min <= o->depth_max))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: radius factors, opacity or depth range invalid", w);
     if (o->use_prior && !o->prior) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior without weights", w);
+    if (o->render_alpha && (!o->render_depth || !o->render_rgb))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: missing-region check needs the rendered depth and colour", w);
+    if (o->render_alpha && (std::isnan(o->miss_alpha) || std::isnan(o->miss_depth) || std::isnan(o->miss_rgb)))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: missing-region thresholds are NaN", w);
     if (o->use_prior && !out->params.mean)
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior needs out->params (the prior writes gaussians)", w);
     if (!out || out->capacity < 0 || (out->capacity > 0 && (!out->pixel || !out->is_high || !out->mean ||
@@ -1214,6 +1218,12 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     sk.fx = cam->fx; sk.fy = cam->fy; sk.cx = cam->cx; sk.cy = cam->cy;
     for (int k = 0; k < 9; ++k) sk.R[k] = cam->R_cw[k];
     for (int k = 0; k < 3; ++k) sk.t[k] = cam->t_cw[k];
+    sk.ra = o->render_alpha;
+    sk.rd = o->render_alpha ? o->render_depth : nullptr;
+    sk.rc = o->render_alpha ? o->render_rgb : nullptr;
+    sk.tau_a = o->miss_alpha;
+    sk.tau_d = o->miss_depth;
+    sk.tau_c = o->miss_rgb;
     SeedOutK so;
     so.capacity = out->capacity;
     so.pixel = out->pixel; so.is_high = out->is_high; so.mean = out->mean; so.radius = out->radius; so.rgb = out->rgb;
@@ -1222,6 +1232,7 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     so.params = out->params.mean ? to_gk(out->params) : GradK{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
     so.E = out->E;
     so.hist = out->hist;
+    so.missing = out->missing;
     SeedScalars *sc = ctx->seed_sc.as<SeedScalars>();
     launch_seed(rgb, depth, W, H, o->D0, sk, so, ctx->seed_ws.p, sc, status_words(ctx), ctx->stream);
     if (out->threshold)

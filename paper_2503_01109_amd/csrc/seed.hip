@@ -295,31 +295,57 @@ __global__ void __launch_bounds__(256) k_triangle(const uint32_t *__restrict__ h
     }
 }
 
-__device__ inline bool is_seed(int x, int y, const uint8_t *q, const float *depth, int W, int thresh, int m, int n,
-                               float dmin, float dmax, bool &high)
+// Missing-region mask M_m (Eq. 9) at pixel p: too little rendered opacity A (M_i), or, where A > 0,
+// a rendered surface depth (depth / A) far from a valid frame depth (M_d) or a rendered surface
+// colour (colour / A) far from the frame's (M_c), decided in binary32 in this order of operations
+// (IEEE division, no contraction).
+__device__ inline bool missing_at(const SeedK &sk, int64_t p, int64_t P, const float *__restrict__ rgb, float d,
+                                  bool valid)
+{
+    if (!sk.ra) return true;  // no map yet
+    const float A = sk.ra[p];
+    if (A < sk.tau_a) return true;
+    if (!(A > 0.0f)) return false;
+    if (valid && fabsf(sk.rd[p] / A - d) > sk.tau_d) return true;
+    const float dc = (fabsf(sk.rc[p] / A - rgb[p]) + fabsf(sk.rc[P + p] / A - rgb[P + p])) +
+                     fabsf(sk.rc[2 * P + p] / A - rgb[2 * P + p]);
+    return dc > sk.tau_c;
+}
+
+// Whether pixel (x, y) seeds: valid depth, inside the missing region (Eq. 10 intersects both
+// frequency masks with it), and on its class's lattice. miss receives M_m at the pixel.
+__device__ inline bool is_seed(int x, int y, const uint8_t *q, const float *rgb, const float *depth, int W, int64_t P,
+                               int thresh, const SeedK &sk, bool &high, bool &miss)
 {
     const int64_t p = (int64_t)y * W + x;
     const float d = depth[p];
     high = thresh >= 0 && (int)q[p] > thresh;
-    if (!isfinite(d) || !(d >= dmin) || !(d <= dmax)) return false;
-    const int s = high ? m : n;
+    const bool valid = isfinite(d) && d >= sk.dmin && d <= sk.dmax;
+    miss = missing_at(sk, p, P, rgb, d, valid);
+    if (!valid || !miss) return false;
+    const int s = high ? sk.m : sk.n;
     return (x % s) == 0 && (y % s) == 0;
 }
 
-// Seeds per image row, and per tile (integer atomics: the sums do not depend on their order).
+// Seeds per image row, and per tile (integer atomics: the sums do not depend on their order); the
+// missing-region mask when asked for.
 __global__ void __launch_bounds__(kT)
-k_seed_count(const uint8_t *__restrict__ q, const float *__restrict__ depth, int W, int H, const SeedScalars *sc,
-             int m, int n, int tile, float dmin, float dmax, uint32_t *__restrict__ row_count,
-             int32_t *__restrict__ tile_count)
+k_seed_count(const uint8_t *__restrict__ q, const float *__restrict__ rgb, const float *__restrict__ depth, int W,
+             int H, const SeedScalars *sc, SeedK sk, uint32_t *__restrict__ row_count, int32_t *__restrict__ tile_count,
+             uint8_t *__restrict__ missing)
 {
     __shared__ uint32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int y = blockIdx.x, thresh = sc->thresh;
+    const int tile = sk.tile;
     const int tiles_x = (W + tile - 1) / tile;
+    const int64_t P = (int64_t)W * H;
     for (int x = threadIdx.x; x < W; x += kT) {
-        bool high;
-        if (is_seed(x, y, q, depth, W, thresh, m, n, dmin, dmax, high)) {
+        bool high, miss;
+        const bool seed = is_seed(x, y, q, rgb, depth, W, P, thresh, sk, high, miss);
+        if (missing) missing[(int64_t)y * W + x] = miss ? 1 : 0;
+        if (seed) {
             atomicAdd(&cnt, 1u);
             if (tile_count) atomicAdd(&tile_count[(y / tile) * tiles_x + x / tile], 1);
         }
@@ -375,8 +401,8 @@ k_seed_emit(const uint8_t *__restrict__ q, const float *__restrict__ rgb, const 
     __syncthreads();
     for (int x0 = 0; x0 < W; x0 += kT) {
         const int x = x0 + threadIdx.x;
-        bool high = false;
-        const bool s = x < W && is_seed(x, y, q, depth, W, thresh, sk.m, sk.n, sk.dmin, sk.dmax, high);
+        bool high = false, miss;
+        const bool s = x < W && is_seed(x, y, q, rgb, depth, W, P, thresh, sk, high, miss);
         const uint64_t bal = __ballot(s);
         if (lane == 0) wsum[wid] = __popcll(bal);
         __syncthreads();
@@ -506,8 +532,8 @@ void launch_seed(const float *rgb, const float *depth, int W, int H, double D0, 
     hipLaunchKernelGGL(k_triangle, dim3(1), dim3(256), 0, s, hist, sc);
     const int tiles = ((W + sk.tile - 1) / sk.tile) * ((H + sk.tile - 1) / sk.tile);
     if (out.tile_count) hipLaunchKernelGGL(k_fill_i32, dim3((tiles + 255) / 256), dim3(256), 0, s, out.tile_count, (int64_t)tiles);
-    hipLaunchKernelGGL(k_seed_count, dim3(H), dim3(kT), 0, s, q, depth, W, H, sc, sk.m, sk.n, sk.tile, sk.dmin, sk.dmax,
-                       row_count, out.tile_count);
+    hipLaunchKernelGGL(k_seed_count, dim3(H), dim3(kT), 0, s, q, rgb, depth, W, H, sc, sk, row_count,
+                       out.tile_count, out.missing);
     hipLaunchKernelGGL(k_seed_scan, dim3(1), dim3(kT), 0, s, row_count, H, row_off, out.capacity, out.n_dev, status);
     hipLaunchKernelGGL(k_seed_emit, dim3(H), dim3(kT), 0, s, q, rgb, depth, W, H, sc, sk, row_off, out);
     // diagnostics

@@ -19,6 +19,10 @@ struct SeedK {
     float dmin, dmax, alpha_h, alpha_l, opacity_logit;
     float fx, fy, cx, cy;
     float R[9], t[3];  // world -> camera pose; seeds go back to world coordinates
+    // missing-region check: the map rendered at the frame's pose (ra == nullptr: every pixel
+    // missing) and the thresholds on opacity, depth difference and summed colour difference
+    const float *ra, *rd, *rc;
+    float tau_a, tau_d, tau_c;
 };
 
 struct SeedOutK {
@@ -31,6 +35,7 @@ struct SeedOutK {
     GradK params;  // params.mean == nullptr: not written
     double *E;
     uint32_t *hist;
+    uint8_t *missing;  // nullable: the missing-region mask, one byte per pixel
 };
 
 bool seed_size_supported(int W, int H);

@@ -57,8 +57,8 @@ int main(void) {
 def test_struct_layouts_match_header(tmp_path):
     extra = ""
     if hasattr(F, "CSeedOpts"):
-        extra = ("S(fgs_seed_opts) O(fgs_seed_opts, use_prior) S(fgs_seed_out) O(fgs_seed_out, tile_count) "
-                 "O(fgs_seed_out, from_prior)")
+        extra = ("S(fgs_seed_opts) O(fgs_seed_opts, use_prior) O(fgs_seed_opts, render_rgb) O(fgs_seed_opts, miss_rgb) "
+                 "S(fgs_seed_out) O(fgs_seed_out, tile_count) O(fgs_seed_out, from_prior) O(fgs_seed_out, missing)")
     src = tmp_path / "probe.c"
     src.write_text(LAYOUT_PROBE.replace("%EXTRA%", extra))
     exe = tmp_path / "probe"
@@ -79,8 +79,11 @@ def test_struct_layouts_match_header(tmp_path):
     }
     if extra:
         mine.update({"fgs_seed_opts": C.sizeof(F.CSeedOpts), "fgs_seed_opts.use_prior": F.CSeedOpts.use_prior.offset,
+                     "fgs_seed_opts.render_rgb": F.CSeedOpts.render_rgb.offset,
+                     "fgs_seed_opts.miss_rgb": F.CSeedOpts.miss_rgb.offset,
                      "fgs_seed_out": C.sizeof(F.CSeedOut), "fgs_seed_out.tile_count": F.CSeedOut.tile_count.offset,
-                     "fgs_seed_out.from_prior": F.CSeedOut.from_prior.offset})
+                     "fgs_seed_out.from_prior": F.CSeedOut.from_prior.offset,
+                     "fgs_seed_out.missing": F.CSeedOut.missing.offset})
     for k, v in mine.items():
         assert int(got[k]) == v, f"{k}: header {got[k]} vs binding {v}"
 

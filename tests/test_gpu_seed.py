@@ -130,3 +130,77 @@ def test_seeds_as_gaussians(fgs, ctx):
     np.testing.assert_array_equal(p[11:14, :n], host(g["rgb"])[:, :n])
     out = fgs.render(ctx, params, n, cam, fgs.RenderOpts(), aux=True)
     assert host(out["alpha"]).mean() > 0.5
+
+
+# ------------------------------------------------ missing-region check (Eq. 9, 10)
+
+def compare_missing(fgs, ctx, rgb, depth, cam, alpha_r, depth_r, rgb_r, taus=(0.5, 0.1, 0.3)):
+    """Seeding of a frame against a rendered map (float32 planes, the same on both sides): the
+    missing-region mask and the whole seeded set bit-exact."""
+    o = fgs.SeedOpts(render_alpha=dev(alpha_r), render_depth=dev(depth_r), render_rgb=dev(rgb_r),
+                     miss_alpha=taus[0], miss_depth=taus[1], miss_rgb=taus[2])
+    g = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, o, diagnostics=True)
+    ref = oracle.seed(rgb, depth, cam, oracle_opts(o), miss=oracle.MissingCheck(alpha_r, depth_r, rgb_r, *taus))
+    if ref["threshold"] >= 0:
+        assert ref["margin"] > 1e-9, f"ambiguous frame: quantisation margin {ref['margin']:.2e}"
+    np.testing.assert_array_equal(host(g["missing"]).astype(bool), ref["missing"])
+    n = g["n"]
+    assert n == ref["n"]
+    np.testing.assert_array_equal(host(g["pixel"])[:n], ref["pixel"])
+    np.testing.assert_array_equal(host(g["is_high"])[:n].astype(bool), ref["is_high"])
+    np.testing.assert_array_equal(host(g["mean"])[:, :n], ref["mean"])
+    np.testing.assert_array_equal(host(g["radius"])[:n], ref["radius"])
+    np.testing.assert_array_equal(host(g["rgb"])[:, :n], ref["rgb"])
+    np.testing.assert_array_equal(host(g["tile_count"]), ref["tile_count"])
+    return g, ref
+
+
+def test_missing_check_first_frame_is_the_identity(fgs, ctx):
+    """A rendered opacity of 0 everywhere (nothing mapped yet) seeds exactly what no check seeds."""
+    rgb, depth = synth.rgbd_frame(4)
+    cam = synth.camera_tum()
+    g, ref = compare_missing(fgs, ctx, rgb, depth, cam, np.zeros_like(depth), np.zeros_like(depth),
+                             np.zeros_like(rgb))
+    plain = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam, fgs.SeedOpts(), diagnostics=True)
+    assert ref["missing"].all() and host(plain["missing"]).all()
+    assert plain["n"] == g["n"]
+    np.testing.assert_array_equal(host(plain["pixel"])[:g["n"]], host(g["pixel"])[:g["n"]])
+
+
+def test_missing_check_rectangles_and_noise(fgs, ctx):
+    """A map that explains the frame up to noise, except in rectangles of low opacity, wrong depth
+    and wrong colour (values near every threshold occur): mask and seeds bit-exact."""
+    rgb, depth = synth.rgbd_frame(5)
+    cam = synth.camera_tum()
+    g0 = synth.rng(55)
+    alpha_r = np.clip(g0.normal(0.8, 0.2, depth.shape), 0, 1).astype(np.float32)
+    depth_r = (depth + g0.normal(0, 0.06, depth.shape)).astype(np.float32)
+    rgb_r = np.clip(rgb + g0.normal(0, 0.06, rgb.shape), 0, 1).astype(np.float32)
+    alpha_r[100:180, 50:200] = 0.1
+    depth_r[250:330, 300:500] -= 0.8
+    rgb_r[:, 380:460, 100:260] = 1.0 - rgb_r[:, 380:460, 100:260]
+    g, ref = compare_missing(fgs, ctx, rgb, depth, cam, alpha_r, depth_r, rgb_r)
+    frac = ref["missing"].mean()
+    assert 0.1 < frac < 0.9, frac
+    plain = oracle.seed(rgb, depth, cam)
+    assert 0 < ref["n"] < plain["n"]
+
+
+def test_missing_check_against_a_rendered_map(fgs, ctx):
+    """The incremental loop: the seeds of a frame as gaussians, rendered at its camera by the oracle
+    (binary32 planes), then the frame checked against that map: only what the map fails to explain
+    (about 9% of the pixels here) seeds again, bit-exact."""
+    cam = synth.camera_tum()
+    rgb0, depth0 = synth.rgbd_frame(0)
+    s0 = oracle.seed(rgb0, depth0, cam)
+    k = s0["n"]
+    p = np.zeros((14, k))
+    p[0:3] = s0["mean"]
+    p[3:6] = np.log(s0["radius"])[None, :]
+    p[6] = 1.0
+    p[11:14] = s0["rgb"]
+    ren = oracle.render_fwd(p, cam, amb_rel=0)
+    g, ref = compare_missing(fgs, ctx, rgb0, depth0, cam, ren["alpha"].astype(np.float32),
+                             ren["depth"].astype(np.float32), ren["rgb"].astype(np.float32))
+    assert 0.01 < ref["missing"].mean() < 0.5
+    assert 0 < ref["n"] < k // 4

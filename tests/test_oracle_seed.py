@@ -271,6 +271,21 @@ def test_missing_check_fully_explained_frame_seeds_nothing():
     assert s["n"] == 0 and not s["missing"].any() and s["tile_count"].sum() == 0
 
 
+def test_missing_check_compares_the_surface_over_its_opacity():
+    """A translucent map (opacity 0.75 everywhere, above tau_alpha) whose depth and colour
+    renderings are 0.75 times the frame's explains the frame: nothing is missing. The same planes
+    taken as surface values (opacity 1) would put every pixel in M_d."""
+    rgb, depth, cam = missing_frame()
+    a = np.float32(0.75)
+    m = oracle.MissingCheck(np.full(depth.shape, a, np.float32), depth * a, rgb * a)
+    s = oracle.seed(rgb, depth, cam, miss=m)
+    # 0.75 x rounds; the quotient is within one binary32 step of the frame's value
+    assert not s["missing"].any() and s["n"] == 0
+    opaque = oracle.seed(rgb, depth, cam, miss=oracle.MissingCheck(np.ones_like(depth), depth * a, rgb * a))
+    valid = (depth >= 0.1) & (depth <= 10.0)
+    assert opaque["missing"][valid].all()
+
+
 def test_missing_check_masks_and_the_seeds_they_keep():
     """Three disjoint rectangles, each missing for one reason: low rendered opacity (M_i), a
     rendered depth 0.3 m off the frame's (M_d), a rendered colour 0.2 off per channel (M_c). M_m is
@@ -302,12 +317,16 @@ def test_missing_check_masks_and_the_seeds_they_keep():
 def test_missing_check_thresholds_are_strict():
     """An opacity equal to tau_alpha is not missing; a depth difference equal to tau_depth is not;
     a colour difference summing to exactly tau_rgb is not (values exact in binary32); just past each
-    threshold is; a huge depth difference at a pixel without a depth measurement is not."""
+    threshold is; a huge depth difference at a pixel without a depth measurement is not. Depth and
+    colour are compared as the surface the map shows (rendered value over rendered opacity: at
+    opacity 0.5 a render of half the frame's depth and colour matches the frame)."""
     rgb, depth, cam = missing_frame()
     rgb = np.full_like(rgb, 0.5)
     depth = np.where(depth > 0, 2.0, 0.0).astype(np.float32)
     m = rendered_like(rgb, depth)
     m.alpha[10, 10], m.alpha[10, 11] = 0.5, np.nextafter(np.float32(0.5), np.float32(0))
+    m.depth[10, 10:12] *= m.alpha[10, 10:12]  # the surface the map shows: depth and colour / opacity
+    m.rgb[:, 10, 10] *= 0.5
     m.depth[12, 10], m.depth[12, 11] = 2.125, np.nextafter(np.float32(2.125), np.float32(3))
     m.rgb[:, 14, 10] = 0.5 + np.float32(0.125)           # (0.125 + 0.125) + 0.125 = 0.375 exactly
     m.rgb[:, 14, 11] = [0.625, 0.625, np.nextafter(np.float32(0.625), np.float32(1))]
