@@ -9,7 +9,9 @@ the L1 colour + depth loss, the backward pass, and one Adam update of all parame
 
 Prints one JSON line: iterations/s over the timed steps, the dominant kernel against its
 roofline (live HIP-event timing of that kernel on the library's stream, algorithmic FLOPs from
-the rasterizer's exact pair counters), and the CPU oracle timed on the host on the same workload.
+the rasterizer's exact pair counters), the whole step against the HBM roofline (algorithmic bytes
+per iteration from the exact work counts) and against the composite roofline of its kernels, and
+the CPU oracle timed on the host on the same workload and on the other configurations.
 """
 import argparse
 import gc
@@ -22,8 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published (counts packed FP32: two FMAs per lane and cycle)
+PEAK_FP32_UNPACKED = 78.65  # the same without packed FP32, which this library does not use
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, published
+# Algorithmic bytes of one mapping iteration (what the method must move, not what a given
+# implementation moves): per gaussian 768 (projection 108, scan 8, emission 12, projection
+# backward 152, Adam 392, gradient zeroing 96); per (tile, gaussian) pair 44 (key and value write
+# 12, one sort pass read and write 24, range read 8); per list entry consumed before a tile
+# terminates 44 (index 4, record 40), forward and backward; per (tile, gaussian) pair with a blended
+# pixel 40 (its reduced gradient); per pixel 96 (forward outputs 24, loss 48, backward inputs 24);
+# per tile 24 (ranges).
+B_PER_G, B_PER_PAIR, B_PER_ENTRY, B_PER_KC, B_PER_PIX, B_PER_TILE = 768, 44, 44, 40, 96, 24
 # Algorithmic FLOPs per pair: forward 14 per pair examined within the cutoff plus
 # 12 per pair blended; backward 80 per pair blended.
 F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
@@ -71,53 +82,262 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--oracle-job", default=None, help=argparse.SUPPRESS)  # child process of cpu_baseline
     ap.add_argument("--window-only", action="store_true",
                     help="only run the 8-view keyframe window measurement (tuning, timed graph replays, "
                          "profiled steps), print its JSON object and exit")
     return ap.parse_args()
 
 
-def cpu_baseline(iters: int) -> dict:
-    """The FP64 oracle (fwd + L1 loss + bwd + Adam) on the same workload, all host threads."""
+def _oracle_step(oracle, p, m, v, cam, tgt, k, lr):
+    """One oracle mapping iteration (fwd + L1 terms + bwd + Adam, FP64) over one view."""
+    out = oracle.render_fwd(p, cam, mode=0, amb_rel=0)
+    _, _, gr, gd = oracle.loss_l1(out["rgb"], out["depth"], tgt[0], tgt[1])
+    grad, _ = oracle.render_bwd(p, cam, gr, gd, None, mode=0)
+    return oracle.adam(p, m, v, grad, k, lr)
+
+
+def oracle_job(job: str) -> dict:
+    """Time the FP64 oracle on one configuration (run in a child process, so that OMP_NUM_THREADS
+    decides its threads). job: "c0:K" (K iterations of the 2,000-gaussian 64x48 step), "c1:K" (the
+    300k 1200x680 step), "c2" (seeding of a 640x480 frame + 10 mapping iterations of its seeds),
+    "c3" (one 8-view window step over 500k gaussians: per view fwd + L1 + bwd, summed, one Adam),
+    "c4" (prior features and network over 5,000 tiles)."""
     import numpy as np
 
     import oracle
     import synth
-    cam = synth.camera_replica()
-    p = synth.scene_replica(0).astype(np.float64)
-    tgt = oracle.render_fwd(synth.scene_replica(1).astype(np.float64), cam, mode=0, amb_rel=0)
-    m = np.zeros_like(p)
-    v = np.zeros_like(p)
     lr = [1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3]
-    t0 = time.perf_counter()
-    for k in range(iters):
-        out = oracle.render_fwd(p, cam, mode=0, amb_rel=0)
-        _, _, gr, gd = oracle.loss_l1(out["rgb"], out["depth"], tgt["rgb"], tgt["depth"])
-        grad, _ = oracle.render_bwd(p, cam, gr, gd, None, mode=0)
-        p, m, v = oracle.adam(p, m, v, grad, k, lr)
-    dt = time.perf_counter() - t0
+    name, _, arg = job.partition(":")
+    iters = int(arg) if arg else 1
+    if name in ("c0", "c1"):
+        cam = synth.camera_small() if name == "c0" else synth.camera_replica()
+        scene = synth.scene_small if name == "c0" else synth.scene_replica
+        p = scene(0).astype(np.float64)
+        t = oracle.render_fwd(scene(1).astype(np.float64), cam, mode=0, amb_rel=0)
+        tgt = (t["rgb"], t["depth"])
+        m, v = np.zeros_like(p), np.zeros_like(p)
+        t0 = time.perf_counter()
+        for k in range(iters):
+            p, m, v = _oracle_step(oracle, p, m, v, cam, tgt, k, lr)
+        dt = time.perf_counter() - t0
+        return {"iters": iters, "s": dt, "iters_per_s": iters / dt}
+    if name == "c2":
+        rgb, depth = synth.rgbd_frame(0)
+        cam = synth.camera_tum()
+        t0 = time.perf_counter()
+        sd = oracle.seed(rgb, depth, cam)
+        t_seed = time.perf_counter() - t0
+        k = sd["n"]
+        p = np.zeros((14, k))
+        p[0:3], p[3:6], p[6], p[11:14] = sd["mean"], np.log(sd["radius"])[None, :], 1.0, sd["rgb"]
+        m, v = np.zeros_like(p), np.zeros_like(p)
+        for it in range(10):
+            p, m, v = _oracle_step(oracle, p, m, v, cam, (rgb, depth), it, lr)
+        dt = time.perf_counter() - t0
+        return {"seeds": k, "seed_s": t_seed, "s": dt, "map_iters": 10}
+    if name == "c3":
+        cams = synth.window_cameras(0)
+        p = synth.scene_window(0).astype(np.float64)
+        p1 = synth.scene_window(1).astype(np.float64)
+        tg = [oracle.render_fwd(p1, c, mode=0, amb_rel=0) for c in cams]
+        t0 = time.perf_counter()
+        grad = np.zeros_like(p)
+        for c, t in zip(cams, tg):
+            out = oracle.render_fwd(p, c, mode=0, amb_rel=0)
+            _, _, gr, gd = oracle.loss_l1(out["rgb"], out["depth"], t["rgb"], t["depth"])
+            grad += oracle.render_bwd(p, c, gr, gd, None, mode=0)[0]
+        oracle.adam(p, np.zeros_like(p), np.zeros_like(p), grad, 0, lr)
+        dt = time.perf_counter() - t0
+        return {"views": len(cams), "s": dt, "views_per_s": len(cams) / dt}
+    if name == "c4":
+        g = np.random.default_rng(0)
+        w = np.concatenate([g.normal(0, 260 ** -0.5, 256 * 260), np.zeros(256), g.normal(0, 1 / 16, 256 * 256),
+                            np.zeros(256), g.normal(0, 0.1 / 16, 4 * 256), np.zeros(4)])
+        frames = [synth.rgbd_frame(k) for k in range(50)]
+        target = g.normal(size=(5000, 4))
+        t0 = time.perf_counter()
+        # 100 tiles of each training frame (every 12th of its 40 x 30 tiles)
+        x = np.asarray([oracle.tile_features(rgb, depth, t % 40, t // 40)[0] for rgb, depth in frames
+                        for t in range(0, 1200, 12)])
+        t_feat = time.perf_counter() - t0
+        oracle.mlp_fwd(x, w, bf16=True)
+        oracle.mlp_bwd(x, w, target, bf16=True)
+        dt = time.perf_counter() - t0
+        return {"tiles": int(x.shape[0]), "features_s": t_feat, "s": dt}
+    raise ValueError(job)
+
+
+def run_oracle_job(job: str, threads: int | None = None, timeout: int = 300) -> dict:
+    """oracle_job in a child process (threads: its OMP_NUM_THREADS; None keeps the environment's)."""
+    import subprocess
+    env = dict(os.environ)
+    if threads is not None:
+        env["OMP_NUM_THREADS"] = str(threads)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-job", job], env=env, timeout=timeout,
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle job {job}: {r.stderr.strip()[-400:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(iters: int) -> dict:
+    """The FP64 oracle timed on the host: the benchmark's workload (fwd + L1 loss + bwd + Adam at
+    300k gaussians, 1200x680) on all threads and on one, and the other configurations on all
+    threads. Each runs in a child process (no GPU there)."""
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": iters / dt, "unit": "iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters} full iterations (fwd + L1 loss + bwd + Adam, FP64) of the 300k-gaussian "
-                      f"1200x680 workload, {dt:.1f} s"}
+    main = run_oracle_job(f"c1:{iters}")
+    progress("cpu baseline: c1 timed")
+    line = {"value": main["iters_per_s"], "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters} full iterations (fwd + L1 loss + bwd + Adam, FP64) of the 300k-gaussian 1200x680 "
+                      f"workload, {main['s']:.1f} s", "cpu": host_cpu()}
+    extra = {}
+    for key, job, threads in (("c1_single_thread", "c1:1", 1), ("c0", "c0:100", None), ("c2", "c2", None),
+                              ("c3", "c3", None), ("c4", "c4", None)):
+        try:
+            extra[key] = run_oracle_job(job, threads)
+        except Exception as e:  # noqa: BLE001 - reported in the line
+            extra[key] = {"error": f"{type(e).__name__}: {e}"[:300]}
+        progress(f"cpu baseline: {key} timed")
+    line["single_thread"] = dict(extra.pop("c1_single_thread"), cores=1)
+    line["configs"] = extra
+    return line
 
 
-def raster_roofline(rep, counts, kernel_prefix):
-    """Dominant rasterizer kernel against the FP32 vector peak: kernel times from a level-1
-    profile (kernels as unprofiled), work per forward from the counters of a level-2 run."""
-    fwd = max(counts["forwards"], 1)
-    E_f = counts["pairs_examined"] / fwd
-    E_c = counts["pairs_blended"] / fwd
-    ms = {k: rep[k][0] / max(rep[k][1], 1) for k in ("raster_fwd", "raster_bwd")}
-    # one launch covers views_per_launch views
-    views_per_launch = counts["forwards"] / max(counts["launches"], 1)
-    flops = {"raster_fwd": (F_FWD_EXAMINED * E_f + F_FWD_BLENDED * E_c) * views_per_launch,
-             "raster_bwd": F_BWD_BLENDED * E_c * views_per_launch}
-    dom = max(ms, key=lambda k: ms[k])
-    achieved = flops[dom] / (ms[dom] / 1e3) / 1e12
-    return {"bound": "alu", "kernel": f"{kernel_prefix}{dom.split('_')[1]}", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
-            "traffic": None, "avg_ms": round(ms[dom], 4), "flops_per_launch": flops[dom]}
+def work_counts(rep3) -> dict:
+    """Per-forward work counts from a level-3 profile: E_f, E_c, K_c, L_f, L_b and entries staged."""
+    c = rep3["counts"]
+    fwd = max(c["forwards"], 1)
+    out = {k: c[src] / fwd for k, src in (("E_f", "pairs_examined"), ("E_c", "pairs_blended"), ("K_c", "K_c"),
+                                          ("L_f", "L_f"), ("L_b", "L_b"), ("staged", "entries_staged"))}
+    out["forwards"] = c["forwards"]
+    out["views_per_launch"] = c["forwards"] / max(rep3["raster_fwd"][1], 1)
+    return out
+
+
+def stage_work(w: dict, N: int, K: float, P: int, T: int) -> dict:
+    """Algorithmic bytes and FP32 FLOPs of every stage group of one mapping iteration (one view):
+    {group: (bytes, flops, stages)}. The per-unit figures are the ones in the header constants;
+    their sum over the groups is B_alg = 768 N + 44 K + 44 (L_f + L_b) + 40 K_c + 96 P + 24 T."""
+    return {
+        "project": (108.0 * N, 0.0, ("project",)),
+        "binning": (20.0 * N + B_PER_PAIR * K + B_PER_TILE * T, 0.0, ("depth_sort", "bin", "tile_sort")),
+        "raster_fwd": (B_PER_ENTRY * w["L_f"] + 72.0 * P, F_FWD_EXAMINED * w["E_f"] + F_FWD_BLENDED * w["E_c"],
+                       ("raster_fwd", "loss")),
+        "raster_bwd": (B_PER_ENTRY * w["L_b"] + B_PER_KC * w["K_c"] + 24.0 * P, F_BWD_BLENDED * w["E_c"],
+                       ("raster_bwd",)),
+        "project_bwd_adam": (640.0 * N, 0.0, ("project_bwd", "adam")),
+    }
+
+
+def roofline_report(ms_iter: float, stage_ms: dict, kernel_ms: dict, w: dict, N: int, K: float, P: int,
+                    T: int, traffic=None) -> tuple:
+    """(dominant-kernel roofline object, whole-step roofline object).
+
+    kernel_ms: average launch time of the two rasterizer kernels over the timed region (level 1);
+    stage_ms: per-iteration time of every stage of the timed kernel variants (level 2)."""
+    sw = stage_work(w, N, K, P, T)
+    B_alg = sum(b for b, _, _ in sw.values())
+    per = {}
+    floor_ms = 0.0
+    for g, (byt, fl, stages) in sw.items():
+        t = sum(stage_ms.get(x, 0.0) for x in stages)
+        t_hbm = byt / (PEAK_HBM_GBS * 1e9) * 1e3
+        t_alu = fl / (PEAK_FP32_TFLOPS * 1e12) * 1e3
+        floor_ms += max(t_hbm, t_alu)
+        per[g] = {"ms": round(t, 4), "bytes": int(byt), "flops": int(fl),
+                  "hbm_frac": round(t_hbm / t, 4) if t > 0 else None,
+                  "alu_frac": round(t_alu / t, 4) if t > 0 else None,
+                  "frac": round(max(t_hbm, t_alu) / t, 4) if t > 0 else None}
+    step = {"bound": "hbm", "achieved": round(B_alg / (ms_iter * 1e-3) / 1e9, 2), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(B_alg / (ms_iter * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "bytes_alg_per_iter": int(B_alg), "ms_per_iter": round(ms_iter, 4),
+            "composite_floor_ms": round(floor_ms, 4), "composite_frac": round(floor_ms / ms_iter, 4),
+            "stages": per}
+    # dominant kernel: the slower of the two rasterizer kernels, per launch
+    vpl = w["views_per_launch"]
+    flops = {"raster_fwd": sw["raster_fwd"][1] * vpl, "raster_bwd": sw["raster_bwd"][1] * vpl}
+    byts = {"raster_fwd": (B_PER_ENTRY * w["L_f"] + 40.0 * P) * vpl,  # without the loss's target reads
+            "raster_bwd": sw["raster_bwd"][0] * vpl}
+    dom = max(kernel_ms, key=lambda k: kernel_ms[k])
+    t = kernel_ms[dom] * 1e-3
+    achieved = flops[dom] / t / 1e12
+    kern = {"bound": "alu", "kernel": f"k_{dom}", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
+            "frac_unpacked_fp32": round(achieved / PEAK_FP32_UNPACKED, 5),
+            "traffic": traffic, "avg_ms": round(kernel_ms[dom], 4), "flops_per_launch": int(flops[dom]),
+            "bytes_alg_per_launch": int(byts[dom]), "hbm_frac": round(byts[dom] / t / 1e9 / PEAK_HBM_GBS, 4)}
+    return kern, step
+
+
+def kernel_ms(rep1, prefix="") -> dict:
+    return {k: rep1[k][0] / max(rep1[k][1], 1) for k in ("raster_fwd", "raster_bwd")}
+
+
+def pct(xs) -> dict:
+    import numpy as np
+    a = np.asarray(xs, np.float64)
+    return {"p10": round(float(np.percentile(a, 10)), 4), "p50": round(float(np.percentile(a, 50)), 4),
+            "p90": round(float(np.percentile(a, 90)), 4)}
+
+
+def timed_steps(step, steps: int, stream):
+    """Run step() `steps` times with one event between steps; returns (total ms, per-step ms)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    ev[0].record(stream)
+    for k in range(steps):
+        step()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    gc.enable()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return ev[0].elapsed_time(ev[steps]), per
+
+
+def c0_latency(F, iters: int = 100) -> dict:
+    """Mapping iterations on the 2,000-gaussian 64x48 scene: a latency figure (too small for a
+    roofline), median and p10/p90 over `iters` iterations after warm-up."""
+    import torch
+
+    import synth
+    cam = synth.camera_small()
+    p = synth.scene_small(0)
+    n = p.shape[1]
+    ctx = F.Context()
+    params = torch.as_tensor(p).cuda().contiguous()
+    tgt = F.render(ctx, torch.as_tensor(synth.scene_small(1)).cuda().contiguous(), n, cam, F.RenderOpts(), aux=False)
+    targets = [(tgt["rgb"], tgt["depth"])]
+    adam = F.Adam.like(params)
+    loss = torch.zeros(1, device="cuda")
+    step = lambda: F.map_step(ctx, params, n, adam, [cam], targets, F.RenderOpts(), loss=loss)
+    for _ in range(10):
+        step()
+    ctx.check()
+    total, per = timed_steps(step, iters, torch.cuda.current_stream())
+    ctx.check()
+    return dict({"workload": f"{n} gaussians, {cam.width}x{cam.height}, fwd+L1+bwd+Adam", "iters": iters,
+                 "ms_per_iter_mean": round(total / iters, 4)}, **{f"ms_{k}": v for k, v in pct(per).items()})
 
 
 def window_extra(F, ctx, steps: int = 20) -> dict:
@@ -163,20 +383,33 @@ def window_extra(F, ctx, steps: int = 20) -> dict:
         win.step(params, n, adam, targets, opts, loss=loss, graph=True)  # profiled steps run eagerly
     ctx.check()
     rep = ctx.profile_report()
-    ctx.profile(2)
+    ctx.profile(3)
     for _ in range(3):
         win.step(params, n, adam, targets, opts, loss=loss, graph=True)
     ctx.check()
     rep2 = ctx.profile_report()
     ctx.profile(0)
     win.close()
-    counts = dict(rep2["counts"], launches=rep2["raster_fwd"][1])
     return {"workload": "8-view keyframe window, 500k gaussians (6x6x4 m box, 20% in 8 blobs), 4x640x480 f=525 + "
                         "4x1200x680 f=600", "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 3),
             "views_per_s": round(8e3 / ms, 2), "graph": True,
             "tiles": [f"{a}x{b}" for a, b in tune["tiles"]], "blocks_per_cu": tune["blocks_per_cu"],
             "tuning_ms": {k: round(v, 4) for k, v in tune["ms"].items()},
-            "roofline": raster_roofline(rep, counts, "k_raster_items_" if tune["blocks_per_cu"] == 0 else "k_raster_queue_")}
+            "roofline": window_roofline(rep, rep2, "k_raster_items_" if tune["blocks_per_cu"] == 0 else "k_raster_queue_")}
+
+
+def window_roofline(rep1, rep3, kernel_prefix) -> dict:
+    """The window's dominant rasterizer kernel against the FP32 vector peak (one launch covers all
+    views)."""
+    w = work_counts(rep3)
+    ms = kernel_ms(rep1)
+    flops = {"raster_fwd": (F_FWD_EXAMINED * w["E_f"] + F_FWD_BLENDED * w["E_c"]) * w["views_per_launch"],
+             "raster_bwd": F_BWD_BLENDED * w["E_c"] * w["views_per_launch"]}
+    dom = max(ms, key=lambda k: ms[k])
+    achieved = flops[dom] / (ms[dom] / 1e3) / 1e12
+    return {"bound": "alu", "kernel": f"{kernel_prefix}{dom.split('_')[1]}", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
+            "traffic": None, "avg_ms": round(ms[dom], 4), "flops_per_launch": int(flops[dom])}
 
 
 def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
@@ -201,24 +434,51 @@ def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
         times.append(e0.elapsed_time(e1))
     ctx.check()
     run = prior.seed_and_map(F, ctx, fr, iters, o)
+    # the missing-region check (Sec. III-A, Eq. 9, 10): the mapped scene rendered at the frame's pose
+    # and the frame seeded again against it; only the seeding call is timed
+    r = F.render(ctx, run.params, run.n, fr.cam, F.RenderOpts())
+    om = F.SeedOpts(render_alpha=r["alpha"], render_depth=r["depth"], render_rgb=r["rgb"])
+    params2 = torch.zeros((14, cap), device="cuda")
+    times_m = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        F.seed_gaussians(ctx, rgb, depth, fr.cam, om, capacity=cap, params=params2, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times_m.append(e0.elapsed_time(e1))
+    ctx.check()
+    again = F.seed_gaussians(ctx, rgb, depth, fr.cam, om, capacity=cap, params=params2, diagnostics=True)
     return {"workload": "Fourier seeding of a 640x480 RGB-D frame (D0 = 30, m = 2, n = 8) + 200 mapping iterations",
             "seeding_us_median": round(float(np.median(times)) * 1e3, 2), "seeds": run.n,
             "map_ms_per_iter": round(float((run.ms[-1] - run.seed_ms) / iters), 4),
-            "total_ms": round(float(run.ms[-1]), 3), "final_psnr_db": round(float(run.psnr[-1]), 3)}
+            "total_ms": round(float(run.ms[-1]), 3), "final_psnr_db": round(float(run.psnr[-1]), 3),
+            "missing_check": {"seeding_us_median": round(float(np.median(times_m)) * 1e3, 2),
+                              "seeds_after_mapping": int(again["n"]),
+                              "missing_pixels": int(again["missing"].sum().item())}}
 
 
 def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
-    """Learned prior: trained on 100 tiles of each of n_train converged maps, compared with the
-    plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on n_test held-out frames."""
+    """Learned prior: trained on 100 tiles of each of the converged maps of frames 0..n_train-1,
+    compared with the plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on the held-out frames
+    1000..1000+n_test-1; the headline and one record per held-out frame."""
     from paper_2503_01109_amd import prior
-    r = prior.run_experiment(F, ctx, range(1000, 1000 + n_train), range(5000, 5000 + n_test), iters=200,
+    r = prior.run_experiment(F, ctx, range(0, n_train), range(1000, 1000 + n_test), iters=200,
                              tiles_per_scene=100, train_steps=2000, log=progress)
-    s = r["summary"]
-    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+    rnd = lambda v: round(v, 4) if isinstance(v, float) else v
+    out = {k: rnd(v) for k, v in r["summary"].items()}
+    keys = ("ms", "iters", "seed_ms", "ms_per_iter", "seeds", "final_db")
+    out["per_scene"] = [dict(scene=row["scene"], **{f"{run}_{k}": rnd(row[run][k]) for run in
+                                                    ("plain", "prior", "plain_repeat") for k in keys})
+                        for row in r["rows"]]
+    return out
 
 
 def main():
     args = parse()
+    if args.oracle_job:
+        print(json.dumps(oracle_job(args.oracle_job)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
               f"described in DESIGN.md and is not run", file=sys.stderr)
@@ -255,53 +515,49 @@ def main():
     loss = torch.zeros(1, device="cuda")
     psnr = torch.zeros(1, device="cuda")
 
+    step = lambda: F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
     for _ in range(args.warmup):
-        F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
+        step()
     ctx.check()
     torch.cuda.synchronize()
     progress(f"warm-up done; timing {args.steps} steps")
 
-    # timed region: HIP events around the two rasterizer kernels only (level 1; the kernels run as
-    # unprofiled), so the timing of the dominant kernel is live without breaking up the rest of
-    # the step. Python's cyclic garbage
-    # collector is paused meanwhile: a full collection stalls the host for ~20 ms, long enough to
-    # drain the GPU's queue of enqueued steps.
-    gc.collect()
-    gc.disable()
-    ctx.profile(1)
+    # timed region: one event between steps on the library's stream, and the two rasterizer kernels
+    # bracketed by events (level 1: those kernels run as unprofiled), so the dominant kernel's time is
+    # live without breaking up the rest of the step. Python's cyclic garbage collector is paused
+    # meanwhile: a full collection stalls the host long enough to drain the queue of enqueued steps.
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    gc.enable()
-    ms = e0.elapsed_time(e1)
+    ctx.profile(1)
+    ms, per_step = timed_steps(step, args.steps, stream)
     ctx.check()
-    rep = ctx.profile_report()
+    rep1 = ctx.profile_report()
     stats = ctx.stats()
-    # per-stage breakdown (events around every stage), from a short untimed continuation
-    ctx.profile(2)
+    # untimed continuations: level 2 times every stage of the same kernel variants, level 3 counts
+    # the forward's work (a slower counting variant; the scene drifts slowly under Adam, so these are
+    # the timed steps' counts to well under 1%)
     brk = 10
+    ctx.profile(2)
     for _ in range(brk):
-        F.map_step(ctx, params, n, adam, [cam], targets, opts, loss=loss, psnr=psnr)
+        step()
     ctx.check()
     rep2 = ctx.profile_report()
+    ctx.profile(3)
+    for _ in range(3):
+        step()
+    ctx.check()
+    rep3 = ctx.profile_report()
     ctx.profile(0)
+    progress("timed steps and profiles done")
 
     steps = args.steps
     value = steps / (ms / 1e3)
-    # work per forward from the level-2 counters of the continuation (the scene drifts slowly
-    # under Adam, so these are the timed steps' counts to well under 1%)
-    cnt = dict(rep2["counts"], launches=rep2["raster_fwd"][1])
-    fwd = max(cnt["forwards"], 1)
-    E_f = cnt["pairs_examined"] / fwd
-    E_c = cnt["pairs_blended"] / fwd
-    stages = {k: v for k, v in rep2.items() if k != "counts"}
-    roofline = raster_roofline(rep, cnt, "k_raster_")
-    roofline["traffic"] = measured_traffic(roofline["kernel"], args.tile)
+    w = work_counts(rep3)
+    stage_ms = {k: v[0] / brk for k, v in rep2.items() if k != "counts"}
+    T = ((cam.width + tw - 1) // tw) * ((cam.height + th - 1) // th)
+    P = cam.width * cam.height
+    K = float(stats["pairs"])
+    kern, step_roof = roofline_report(ms / steps, stage_ms, kernel_ms(rep1), w, n, K, P, T)
+    kern["traffic"] = measured_traffic(kern["kernel"], args.tile)
     line = {
         "metric": "splat fwd+bwd iters/s (300k G, 1200x680)",
         "value": round(value, 3),
@@ -310,6 +566,7 @@ def main():
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms / steps, 4),
+        "ms_per_step_pct": pct(per_step),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -318,12 +575,17 @@ def main():
         "config": {"workload": "splat fwd+L1 loss+bwd+Adam, 300k gaussians (20% in 8 blobs), 1200x680, "
                                "fx=fy=600, depth 0.5-8 m", "n_gaussians": n, "width": cam.width,
                    "height": cam.height, "tile": args.tile, "parallelism": "single GPU"},
-        "roofline": roofline,
-        "stages_ms_per_step": {k: round(t / brk, 4) for k, (t, l) in stages.items()},
-        "pairs": {"tile_pairs": stats["pairs"], "examined_per_iter": E_f, "blended_per_iter": E_c,
-                  "entries_staged_per_iter": cnt["entries_staged"] / fwd},
+        "roofline": kern,
+        "step_roofline": step_roof,
+        "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "work_per_iter": {"N": n, "K": int(K), "K_c": round(w["K_c"]), "E_f": round(w["E_f"]),
+                          "E_c": round(w["E_c"]), "L_f": round(w["L_f"]), "L_b": round(w["L_b"]),
+                          "entries_staged": round(w["staged"]), "P": P, "T": T},
         "final_loss": float(loss), "final_psnr": float(psnr),
     }
+    del params, adam, targets, tgt
+    line["c0_latency"] = c0_latency(F)
+    progress("c0 latency done")
     if not args.no_extras:
         # the extra measurements report their own failure in the line instead of losing it
         def extra(fn, *a):
@@ -341,7 +603,8 @@ def main():
         if "error" not in pr:
             line["ms_to_target_psnr"] = {"learned": pr["prior_ms_mean"], "plain": pr["plain_ms_mean"],
                                          "target": "plain method's PSNR after 200 iterations - 0.1 dB",
-                                         "held_out_scenes": pr["scenes"]}
+                                         "held_out_scenes": pr["scenes"], "wins": pr["wins"],
+                                         "prior_never_reached": pr["prior_never_reached"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         progress("cpu baseline done")

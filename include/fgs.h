@@ -147,16 +147,25 @@ fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len);
  * enqueues. level 1: the rasterizer kernels only ("raster_fwd", "raster_bwd"), which then run
  * exactly as unprofiled; level 2: every stage: "project", "depth_sort", "bin" (scan + pair
  * emission), "tile_sort" (with tile ranges), "raster_fwd", "loss", "raster_bwd", "project_bwd",
- * "adam", and the forward rasterizer counts its work (fgs_ctx_profile_counts). 0 disables.
- * Every call clears previous records. */
+ * "adam", every kernel still the unprofiled one; level 3: as level 2, and the forward rasterizer
+ * counts its work (fgs_ctx_profile_counts, fgs_ctx_profile_work) in a variant that runs longer.
+ * 0 disables. Every call clears previous records. */
 fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t level);
 /* Waits for the stream; total milliseconds and number of launches of one stage since enabling. */
 fgs_status fgs_ctx_profile_stage(fgs_ctx *ctx, const char *stage, double *total_ms, int64_t *launches);
-/* Waits for the stream; work counters since enabling level 2 (zero at level 1): counts[0] =
+/* Waits for the stream; work counters since enabling level 3 (zero below): counts[0] =
  * (pixel, gaussian) pairs within the sigma_cut ellipse that each pixel examined before it
  * stopped, counts[1] = pairs blended, counts[2] = list entries staged by the forward rasterizer,
  * counts[3] = forward launches counted. */
 fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4]);
+/* Waits for the stream; the full work counters since enabling level 3 (zero below), summed
+ * over forwards: counts[0] = E_f, (pixel, gaussian) pairs within the sigma_cut ellipse examined
+ * before each pixel stopped; counts[1] = E_c, pairs blended; counts[2] = list entries staged (read
+ * from HBM) by the forward rasterizer; counts[3] = K_c, (tile, gaussian) list entries that some pixel
+ * of the tile blended; counts[4] = L_f, per tile the list entries up to the last one any pixel
+ * examined (all, for a pixel that never stops), summed; counts[5] = L_b, per tile the list entries
+ * up to the last blended one, summed; counts[6] = forwards counted; counts[7] = 0. */
+fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[8]);
 
 /* ---------------------------- rendering (Eq. 1) and its gradient ---------------------------- */
 

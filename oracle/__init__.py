@@ -114,6 +114,7 @@ def lib():
                                       C.c_int64, _i64p, _dp, _dp, _dp, _dp, _i32p, _u8p, C.c_double, _dp]
         L.fgso_render_bwd.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), C.c_int,
                                       C.c_int64, _i64p, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.fgso_tile_counts.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts), _i64p]
         L.fgso_count_duplicates.argtypes = [C.c_int64, _dp, C.POINTER(_Camera), C.POINTER(_RenderOpts),
                                             C.c_int32, C.c_int32]
         L.fgso_count_duplicates.restype = C.c_int64
@@ -213,6 +214,17 @@ def render_bwd(params, cam, g_rgb, g_depth, g_alpha=None, opts: RenderOpts | Non
                                _ptr(grad, _dp), _ptr(grad2d, _dp), _ptr(ms, _dp))
     _check(rc, "render_bwd")
     return (grad, grad2d, ms) if mass else (grad, grad2d)
+
+
+def tile_counts(params, cam, opts: RenderOpts | None = None) -> dict:
+    """Work of the 16x16-tile formulation: K_c (tile, gaussian) pairs with a blended pixel, L_f and
+    L_b list entries consumed by the forward and the backward before each tile terminates, K the
+    list entries (the oracle's own box binning)."""
+    p = _d(params)
+    c = np.zeros(4, np.int64)
+    _check(lib().fgso_tile_counts(p.shape[1], _ptr(p, _dp), C.byref(_cam(cam)), C.byref((opts or RenderOpts()).c()),
+                                  _ptr(c, _i64p)), "tile_counts")
+    return dict(K_c=int(c[0]), L_f=int(c[1]), L_b=int(c[2]), K=int(c[3]))
 
 
 def count_duplicates(params, cam, tile_w=16, tile_h=16, opts: RenderOpts | None = None) -> int:

@@ -79,6 +79,15 @@ int fgso_render_bwd(int64_t n, const double *params, const fgso_camera *cam,
                     const double *g_rgb, const double *g_depth, const double *g_alpha,
                     double *grad, double *grad2d, double *mass);
 
+/* Work counts of the tile formulation (16x16 tiles, lists of the gaussians whose sigma_cut box
+ * reaches the tile, in (binary32 depth, index) order): counts[0] = K_c, the (tile, gaussian) pairs
+ * with at least one blended pixel; counts[1] = L_f, per tile the list entries up to the last one
+ * any pixel examined (a pixel examines up to the entry at which it stops, the whole list when it
+ * never stops), summed; counts[2] = L_b, per tile the list entries up to the last blended one,
+ * summed; counts[3] = the list entries of all tiles. A diagnostic of the work the method implies. */
+int fgso_tile_counts(int64_t n, const double *params, const fgso_camera *cam, const fgso_render_opts *o,
+                     int64_t counts[4]);
+
 /* Number of (tile, gaussian) duplicates under axis-aligned 3-sigma-box binning. */
 int64_t fgso_count_duplicates(int64_t n, const double *params, const fgso_camera *cam,
                               const fgso_render_opts *o, int32_t tile_w, int32_t tile_h);

@@ -257,6 +257,8 @@ typedef struct {
     int32_t nc;
     int amb;
     double ef;
+    int64_t consumed; /* list entries up to the one at which the pixel stopped (all when it never did) */
+    int64_t last_pos; /* 1 + list position of the last contributor (0: none) */
 } pixel_out_t;
 
 /* Upper bound on contributors per pixel: every contributor has alpha >= alpha_min, so T
@@ -281,6 +283,7 @@ static void composite(const proj_t *P, const double *col, int64_t n, const int32
     int32_t nc = 0;
     int amb = 0;
     double ef = 0;
+    int64_t consumed = cnt, last_pos = 0;
     for (int64_t k = 0; k < cnt; ++k) {
         int32_t i = list[k];
         const proj_t *g = &P[i];
@@ -299,7 +302,7 @@ static void composite(const proj_t *P, const double *col, int64_t n, const int32
         if (alpha < o->alpha_min) continue;
         double Tn = T * (1 - alpha);
         if (amb_rel > 0 && fabs(Tn - o->T_min) <= amb_rel * o->T_min) amb |= 1;
-        if (Tn < o->T_min) break;
+        if (Tn < o->T_min) { consumed = k + 1; break; }
         if (amb_rel > 0 && prev_d >= 0 && order_key(g->depth) == prev_d) amb |= 2;
         prev_d = order_key(g->depth);
         double w = alpha * T;
@@ -312,9 +315,11 @@ static void composite(const proj_t *P, const double *col, int64_t n, const int32
         }
         T = Tn;
         nc++;
+        last_pos = k + 1;
     }
     for (int ch = 0; ch < 3; ++ch) out->C[ch] = C[ch];
     out->T = T; out->A = A; out->D = D; out->nc = nc; out->amb = amb; out->ef = ef;
+    out->consumed = consumed; out->last_pos = last_pos;
 }
 
 /* Candidate list for a brute-force pixel: all valid gaussians with Q <= cut2_ext, ordered
@@ -691,4 +696,64 @@ int64_t fgso_count_duplicates(int64_t n, const double *params, const fgso_camera
         K += (int64_t)(x1 / tile_w - x0 / tile_w + 1) * (y1 / tile_h - y0 / tile_h + 1);
     }
     return K;
+}
+
+/* Work counts of the tile formulation (16x16 tiles, lists of the gaussians whose sigma_cut box
+ * reaches the tile, in (binary32 depth, index) order): counts[0] = K_c, the (tile, gaussian) pairs
+ * with at least one blended pixel; counts[1] = L_f, per tile the list entries up to the last one
+ * any pixel examined (a pixel examines up to the entry at which it stops, the whole list when it
+ * never stops), summed; counts[2] = L_b, per tile the list entries up to the last blended one,
+ * summed; counts[3] = K, the list entries of all tiles. */
+int fgso_tile_counts(int64_t n, const double *params, const fgso_camera *cam, const fgso_render_opts *o,
+                     int64_t counts[4])
+{
+    if (n < 0 || (n > 0 && !params) || !opts_ok(cam, o) || !counts) return -1;
+    setup_t s;
+    if (setup(n, params, cam, o, 0, 0, NULL, 0, &s)) { teardown(&s); return -2; }
+    const double *col = params + 11 * n;
+    int64_t T = (int64_t)s.b.tiles_x * s.b.tiles_y;
+    int64_t kc = 0, lf = 0, lb = 0;
+    int64_t cap = max_contrib(o);
+#pragma omp parallel reduction(+ : kc, lf, lb)
+    {
+        contrib_t *seq = (contrib_t *)malloc(sizeof(contrib_t) * (size_t)cap);
+        uint8_t *seen = NULL;
+        int64_t seen_cap = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < T; ++t) {
+            int64_t cnt = s.b.start[t + 1] - s.b.start[t];
+            const int32_t *L = s.b.idx + s.b.start[t];
+            if (cnt > seen_cap) {
+                free(seen);
+                seen = (uint8_t *)malloc((size_t)cnt);
+                seen_cap = cnt;
+            }
+            if (cnt) memset(seen, 0, (size_t)cnt);
+            int32_t tx = (int32_t)(t % s.b.tiles_x), ty = (int32_t)(t / s.b.tiles_x);
+            int64_t tf = 0, tb = 0;
+            for (int32_t y = ty * BUCKET; y < (ty + 1) * BUCKET && y < cam->height; ++y)
+                for (int32_t x = tx * BUCKET; x < (tx + 1) * BUCKET && x < cam->width; ++x) {
+                    pixel_out_t po;
+                    composite(s.P, col, n, L, cnt, x + 0.5, y + 0.5, o, 0, &po, seq, cap);
+                    if (po.consumed > tf) tf = po.consumed;
+                    if (po.last_pos > tb) tb = po.last_pos;
+                    /* mark the contributors' list positions (the list holds each gaussian once) */
+                    for (int32_t j = 0, k = 0; j < po.nc && j < cap; ++j) {
+                        while (k < cnt && L[k] != seq[j].i) ++k;
+                        if (k < cnt) seen[k] = 1;
+                    }
+                }
+            for (int64_t k = 0; k < cnt; ++k) kc += seen[k];
+            lf += tf;
+            lb += tb;
+        }
+        free(seq);
+        free(seen);
+    }
+    counts[0] = kc;
+    counts[1] = lf;
+    counts[2] = lb;
+    counts[3] = s.b.start[T];
+    teardown(&s);
+    return 0;
 }

@@ -116,6 +116,7 @@ _sigs = {
     "fgs_ctx_profile": [_vp, C.c_int32],
     "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
     "fgs_ctx_profile_counts": [_vp, _P(C.c_int64)],
+    "fgs_ctx_profile_work": [_vp, _P(C.c_int64)],
     "fgs_seed_gaussians": [_vp, _fp, _fp, _P(CCamera), _P(CSeedOpts), _P(CSeedOut), _P(C.c_int64)],
     "fgs_tile_features": [_vp, _fp, _fp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_int64, _P(C.c_int32), _fp,
                           _P(C.c_int32)],
@@ -245,7 +246,8 @@ class Context:
 
     def profile(self, level: int = 2):
         """Start (clearing earlier records) or stop (0) HIP-event timing and work counters:
-        level 1 times the rasterizer kernels only, level 2 every pipeline stage."""
+        level 1 times the rasterizer kernels only, level 2 every pipeline stage, level 3 every
+        stage with the forward rasterizer's work counters (a slower counting variant)."""
         _check(_lib.fgs_ctx_profile(self._p, int(level)), self._p)
 
     def profile_report(self) -> dict:
@@ -257,9 +259,10 @@ class Context:
             k = C.c_int64()
             _check(_lib.fgs_ctx_profile_stage(self._p, s.encode(), C.byref(t), C.byref(k)), self._p)
             rep[s] = (t.value, k.value)
-        c = (C.c_int64 * 4)()
-        _check(_lib.fgs_ctx_profile_counts(self._p, c), self._p)
-        rep["counts"] = dict(pairs_examined=c[0], pairs_blended=c[1], entries_staged=c[2], forwards=c[3])
+        c = (C.c_int64 * 8)()
+        _check(_lib.fgs_ctx_profile_work(self._p, c), self._p)
+        rep["counts"] = dict(pairs_examined=c[0], pairs_blended=c[1], entries_staged=c[2], K_c=c[3], L_f=c[4],
+                             L_b=c[5], forwards=c[6])
         return rep
 
     def stats(self) -> dict:

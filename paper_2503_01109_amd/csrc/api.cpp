@@ -150,7 +150,7 @@ struct fgs_ctx {
     int prof = 0;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
     std::vector<hipEvent_t> event_pool;  // reused by Stage
-    DBuf prof_counts;  // 4 x u64
+    DBuf prof_counts;  // 8 x u64 (see fgs_ctx_profile_work)
     int64_t prof_fwd = 0;
 };
 
@@ -410,11 +410,11 @@ struct Stage {
     }
 };
 
-// Work counters of the forward rasterizer: collected at profiling level 2 only, so the kernels
-// timed at level 1 are the ones that run unprofiled.
+// Work counters of the forward rasterizer: collected at profiling level 3 only, so the kernels
+// timed at levels 1 and 2 are the ones that run unprofiled.
 unsigned long long *prof_counts(fgs_ctx *ctx)
 {
-    return ctx->prof >= 2 ? ctx->prof_counts.as<unsigned long long>() : nullptr;
+    return ctx->prof >= 3 ? ctx->prof_counts.as<unsigned long long>() : nullptr;
 }
 
 void clear_profile(fgs_ctx *ctx, bool destroy = false)
@@ -777,7 +777,7 @@ fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "fgs_ctx_profile: ctx is NULL");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     clear_profile(ctx);
-    ctx->prof = enable < 0 ? 0 : enable > 2 ? 2 : enable;
+    ctx->prof = enable < 0 ? 0 : enable > 3 ? 3 : enable;
     if (ctx->prof && ctx->event_pool.size() < 4096) {
         // events for a few hundred steps up front, so the timed loop does not create any
         while (ctx->event_pool.size() < 4096) {
@@ -787,8 +787,8 @@ fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
         }
     }
     if (ctx->prof) {
-        HIP_TRY(ctx, ctx->prof_counts.ensure(4 * 8));
-        HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 4 * 8));
+        HIP_TRY(ctx, ctx->prof_counts.ensure(8 * 8));
+        HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 8 * 8));
     }
     return FGS_OK;
 }
@@ -823,6 +823,20 @@ fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4])
     }
     for (int k = 0; k < 3; ++k) counts[k] = (int64_t)c[k];
     counts[3] = ctx->prof_fwd;
+    return FGS_OK;
+}
+
+fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[8])
+{
+    if (!ctx || !counts) return fail(ctx, FGS_ERR_INVALID_ARG, "fgs_ctx_profile_work: NULL argument");
+    unsigned long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (ctx->prof_counts.p) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpy(c, ctx->prof_counts.p, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    }
+    for (int k = 0; k < 6; ++k) counts[k] = (int64_t)c[k];
+    counts[6] = ctx->prof_fwd;
+    counts[7] = 0;
     return FGS_OK;
 }
 

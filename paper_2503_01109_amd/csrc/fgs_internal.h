@@ -241,7 +241,9 @@ void launch_raster_window(bool fwd, bool count, const ViewK *views_dev, int nv, 
                           int blocks, hipStream_t s);
 
 // counts (nullable, profiling): [0] += pairs within the cutoff examined before each pixel
-// stopped, [1] += pairs blended, [2] += list entries staged.
+// stopped, [1] += pairs blended, [2] += list entries staged, [3] += (tile, gaussian) entries that
+// some pixel blended (K_c), [4] += per tile the list entries up to the last one a pixel examined
+// (L_f), [5] += per tile the list entries up to the last blended one (L_b).
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, uint32_t *last, float *tfinal, const ImageK &img, const LossK &loss,
                        unsigned long long *counts, hipStream_t s);

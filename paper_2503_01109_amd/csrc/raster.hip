@@ -243,7 +243,9 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     __shared__ float4 sa[NT], sb[NT], sc[NT];
     __shared__ uint8_t smask[NT];
     __shared__ uint16_t slist[NW][NT];
-    __shared__ unsigned long long red[2];
+    __shared__ unsigned long long red[3];
+    __shared__ uint32_t smx[2];
+    __shared__ uint8_t sblend[NT];  // COUNT: entries of the staged batch that some pixel blended
     const RasterK &rk = V.rk;
     const int W = V.W, H = V.H;
     const Rec *__restrict__ rec = V.rec;
@@ -268,9 +270,19 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     // the lane's cutoff on q: qcut while the pixel blends, +inf once it is done (outside the
     // image, or stopped before a pair that would take T below T_min), so that no pair is near
     float qc = inside ? qcut : INFINITY;
+    // COUNT: list entries this pixel examines (up to the one it stops at; all if it never stops),
+    // and (tile, gaussian) entries some pixel blended
+    uint32_t cons = inside ? range.y - range.x : 0u, kc = 0;
+    int prev_cnt = 0;
+    if (COUNT) sblend[tid] = 0;  // ordered before its first use by the loop's first barrier
 
     for (uint32_t b = range.x; b < range.y; b += NT) {
-        if (__syncthreads_count(qc < INFINITY) == 0) break;
+        const int alive = __syncthreads_count(qc < INFINITY);
+        if (COUNT && tid < prev_cnt) {
+            kc += sblend[tid];
+            sblend[tid] = 0;
+        }
+        if (alive == 0) break;
         staged += min((uint32_t)NT, range.y - b);
         const uint32_t j = b + tid;
         if (j < range.y) {
@@ -285,6 +297,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         }
         __syncthreads();
         const int cnt = min((uint32_t)NT, range.y - b);
+        if (COUNT) prev_cnt = cnt;
         const int len = wave_compact(smask, cnt, wid, slist[wid]);
         const uint32_t base = b - range.x + 1;
         // Branch-free per pair: every lane evaluates the entry and the decisions select what is
@@ -309,7 +322,11 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             if (ALPHA) A += w;
             T = blend ? Tn : T;
             qc = take && low ? INFINITY : qc;
-            if (COUNT) ntest += near ? 1u : 0u;
+            if (COUNT) {
+                ntest += near ? 1u : 0u;
+                if (blend) sblend[k] = 1;
+                if (take && low) cons = base + (uint32_t)k;
+            }
             if (COUNT || NCON) ncon += blend ? 1 : 0;
             lastk = blend ? k : lastk;
         };
@@ -322,18 +339,32 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         if (lastk >= 0) last = base + (uint32_t)lastk;
     }
     if (COUNT) {
-        // work counters (profiling only): block sums, one atomic per block and counter
-        if (tid == 0) red[0] = red[1] = 0ull;
+        // work counters (profiling only): block sums and maxima, one atomic per block and counter
+        __syncthreads();
+        if (tid < prev_cnt) {
+            kc += sblend[tid];
+            sblend[tid] = 0;
+        }
+        if (tid == 0) {
+            red[0] = red[1] = red[2] = 0ull;
+            smx[0] = smx[1] = 0u;
+        }
         __syncthreads();
         if (inside) {
             atomicAdd(&red[0], (unsigned long long)ntest);
             atomicAdd(&red[1], (unsigned long long)ncon);
+            atomicMax(&smx[0], cons);
+            atomicMax(&smx[1], last);
         }
+        if (kc) atomicAdd(&red[2], (unsigned long long)kc);
         __syncthreads();
         if (tid == 0) {
             atomicAdd(&V.counts[0], red[0]);
             atomicAdd(&V.counts[1], red[1]);
             atomicAdd(&V.counts[2], (unsigned long long)staged);
+            atomicAdd(&V.counts[3], red[2]);
+            atomicAdd(&V.counts[4], (unsigned long long)smx[0]);
+            atomicAdd(&V.counts[5], (unsigned long long)smx[1]);
         }
     }
     // the next tile of a persistent workgroup restages the LDS arrays: wait for every reader

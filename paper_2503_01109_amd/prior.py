@@ -154,9 +154,21 @@ def first_reaching(psnr: np.ndarray, target: float):
     return int(hit[0]) if hit.size else None
 
 
+def _reach(run: MapRun, target: float) -> dict:
+    """Iterations and device ms until `run` first reaches `target` dB (None when it never does),
+    with the run's seeding (and prior inference) time, seeds and mean ms per mapping iteration."""
+    i = first_reaching(run.psnr, target)
+    iters = run.psnr.size
+    return dict(iters=None if i is None else i + 1, ms=None if i is None else float(run.ms[i]),
+                seed_ms=float(run.seed_ms), seeds=int(run.n), final_db=float(run.psnr[-1]),
+                ms_per_iter=float((run.ms[-1] - run.seed_ms) / iters))
+
+
 def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, plain_opts=None, prior_opts=None):
-    """Per held-out scene: the plain run's final PSNR is the target; report iterations and ms for
-    each run to reach target - margin_db (None if never within iters)."""
+    """Per held-out scene: the plain run's final PSNR less margin_db is the target; iterations and
+    device ms until each run reaches it (None: never within iters), their seeding times, seeds and
+    ms per iteration. The plain run is repeated; the repeat's distance from the first is the
+    scene's run-to-run spread."""
     plain_opts = plain_opts or F.SeedOpts()
     if prior_opts is None:
         prior_opts = F.SeedOpts(**{k: getattr(plain_opts, k) for k in ("D0", "m", "n", "tile", "alpha_h", "alpha_l",
@@ -167,16 +179,56 @@ def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, 
         fr = frame_of(s)
         a = seed_and_map(F, ctx, fr, iters, plain_opts)
         b = seed_and_map(F, ctx, fr, iters, prior_opts)
+        a2 = seed_and_map(F, ctx, fr, iters, plain_opts)
         target = a.psnr[-1] - margin_db
-        ia, ib = first_reaching(a.psnr, target), first_reaching(b.psnr, target)
-        rows.append(dict(scene=s, target_db=float(a.psnr[-1]), plain_final_db=float(a.psnr[-1]),
-                         prior_final_db=float(b.psnr[-1]), plain_iters=None if ia is None else ia + 1,
-                         prior_iters=None if ib is None else ib + 1,
-                         plain_ms=None if ia is None else float(a.ms[ia]), prior_ms=None if ib is None else float(b.ms[ib]),
-                         plain_seed_ms=a.seed_ms, prior_seed_ms=b.seed_ms,
+        ra, rb, r2 = _reach(a, target), _reach(b, target), _reach(a2, target)
+        rows.append(dict(scene=s, target_db=float(target), plain=ra, prior=rb, plain_repeat=r2,
                          prior_fraction=float(b.from_prior.mean()) if b.from_prior is not None else 0.0))
-        del a, b
+        del a, b, a2
     return rows
+
+
+def summarize(rows) -> dict:
+    """Headline of evaluate(): a scene is a win when the prior reaches the target sooner than both
+    plain runs by more than their spread; a scene the prior never reaches counts as a loss."""
+    wins = losses = failed = 0
+    ratios = []
+    spread = []
+    for r in rows:
+        a, b, a2 = r["plain"], r["prior"], r["plain_repeat"]
+        if b["ms"] is None:
+            failed += 1
+            losses += 1
+            continue
+        if a["ms"] is None or a2["ms"] is None:
+            continue
+        sp = abs(a["ms"] - a2["ms"])
+        spread.append(sp)
+        ratios.append(b["ms"] / min(a["ms"], a2["ms"]))
+        if b["ms"] < min(a["ms"], a2["ms"]) - sp:
+            wins += 1
+        else:
+            losses += 1
+
+    def mean(key, run):
+        v = [r[run][key] for r in rows if r[run][key] is not None]
+        return float(np.mean(v)) if v else None
+
+    return dict(
+        scenes=len(rows), wins=wins, losses=losses, prior_never_reached=failed,
+        plain_never_reached=sum(r["plain"]["ms"] is None for r in rows),
+        ms_ratio_median=float(np.median(ratios)) if ratios else None,
+        ms_ratio_p10=float(np.percentile(ratios, 10)) if ratios else None,
+        ms_ratio_p90=float(np.percentile(ratios, 90)) if ratios else None,
+        spread_ms_median=float(np.median(spread)) if spread else None,
+        plain_ms_mean=mean("ms", "plain"), prior_ms_mean=mean("ms", "prior"),
+        plain_iters_mean=mean("iters", "plain"), prior_iters_mean=mean("iters", "prior"),
+        plain_seed_ms_mean=mean("seed_ms", "plain"), prior_seed_ms_mean=mean("seed_ms", "prior"),
+        plain_ms_per_iter_mean=mean("ms_per_iter", "plain"), prior_ms_per_iter_mean=mean("ms_per_iter", "prior"),
+        plain_seeds_mean=mean("seeds", "plain"), prior_seeds_mean=mean("seeds", "prior"),
+        plain_final_db=mean("final_db", "plain"), prior_final_db=mean("final_db", "prior"),
+        prior_fraction=float(np.mean([r["prior_fraction"] for r in rows])) if rows else None,
+    )
 
 
 def logit(p: float) -> float:
@@ -216,18 +268,6 @@ def run_experiment(F, ctx, train_scenes, test_scenes, iters: int = 200, tiles_pe
     t_train = time.perf_counter() - t0 - t_data
     log(f"prior trained in {t_train:.1f} s")
     rows = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=base)
-    both = [r for r in rows if r["plain_iters"] is not None and r["prior_iters"] is not None]
-    summary = dict(
-        opacity=opacity, train_rows=int(X.shape[0]), train_loss_first=float(losses[0]),
-        train_loss_last=float(losses[-1]), data_s=t_data, train_s=t_train,
-        scenes=len(rows), reached=len(both),
-        prior_reached=sum(r["prior_iters"] is not None for r in rows),
-        plain_ms_mean=float(np.mean([r["plain_ms"] for r in both])) if both else None,
-        prior_ms_mean=float(np.mean([r["prior_ms"] for r in both])) if both else None,
-        plain_iters_mean=float(np.mean([r["plain_iters"] for r in both])) if both else None,
-        prior_iters_mean=float(np.mean([r["prior_iters"] for r in both])) if both else None,
-        plain_final_db=float(np.mean([r["plain_final_db"] for r in rows])),
-        prior_final_db=float(np.mean([r["prior_final_db"] for r in rows])),
-        prior_fraction=float(np.mean([r["prior_fraction"] for r in rows])),
-    )
+    summary = dict(opacity=opacity, train_rows=int(X.shape[0]), train_loss_first=float(losses[0]),
+                   train_loss_last=float(losses[-1]), data_s=t_data, train_s=t_train, **summarize(rows))
     return dict(summary=summary, rows=rows, weights=w, losses=losses)

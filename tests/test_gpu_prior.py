@@ -253,8 +253,8 @@ def test_learned_prior_reaches_the_plain_psnr_sooner(fgs, ctx):
                              train_steps=1000, opacity=0.5)
     s = r["summary"]
     assert s["train_loss_last"] < 0.5 * s["train_loss_first"]
-    assert s["reached"] == 3, r["rows"]
+    assert s["prior_never_reached"] == 0 and s["plain_never_reached"] == 0, r["rows"]
     for row in r["rows"]:
-        assert row["prior_iters"] < row["plain_iters"], row
-        assert row["prior_ms"] < row["plain_ms"], row
+        assert row["prior"]["iters"] < row["plain"]["iters"], row
+        assert row["prior"]["ms"] < row["plain"]["ms"], row
     assert s["prior_fraction"] > 0.5

@@ -298,8 +298,8 @@ def test_deterministic_forward(fgs, ctx):
 
 
 def test_profiling_levels_and_work_counters(fgs, ctx):
-    """Level 1 times the rasterizer without counting; level 2 counts exactly: the pairs blended
-    are the sum of the per-pixel contributor counts, and profiling changes no output bit."""
+    """Levels 1 and 2 time without counting; level 3 counts exactly: the pairs blended are the sum
+    of the per-pixel contributor counts, and profiling changes no output bit."""
     p = synth.scene_small(8)
     cam = synth.camera_small()
     pd = params_dev(p)
@@ -308,13 +308,48 @@ def test_profiling_levels_and_work_counters(fgs, ctx):
     a = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
     rep1 = ctx.profile_report()
     ctx.profile(2)
+    c2 = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
+    rep_2 = ctx.profile_report()
+    ctx.profile(3)
     b = fgs.render(ctx, pd, p.shape[1], cam, fgs.RenderOpts())
     rep2 = ctx.profile_report()
     ctx.profile(0)
     assert rep1["raster_fwd"][1] == 1 and rep1["counts"]["forwards"] == 0
     assert rep1["counts"]["pairs_blended"] == 0 and rep1["counts"]["pairs_examined"] == 0
+    assert rep_2["project"][1] == 1 and rep_2["raster_fwd"][1] == 1 and rep_2["counts"]["forwards"] == 0
     assert rep2["counts"]["forwards"] == 1
     assert rep2["counts"]["pairs_blended"] == int(host(b["n_contrib"]).sum()) > 0
     assert rep2["counts"]["pairs_examined"] >= rep2["counts"]["pairs_blended"]
     for k in ("rgb", "depth", "alpha", "T_final", "n_contrib"):
-        assert np.array_equal(host(a[k]), host(plain[k])) and np.array_equal(host(b[k]), host(plain[k])), k
+        for r in (a, b, c2):
+            assert np.array_equal(host(r[k]), host(plain[k])), k
+
+
+def test_work_counts_match_oracle(fgs):
+    """The forward's work counters at profiling level 3 against the oracle's on a scene with no
+    ambiguous pixel, 16x16 tiles: E_f (pairs examined within the cutoff before each pixel stops),
+    E_c (pairs blended) and K_c ((tile, gaussian) entries some pixel blended) exactly; L_f and L_b
+    (list entries consumed before each tile terminates, forward and backward) within 0.5% plus two
+    per tile at most (the HIP tile boxes are padded by 1e-3 px so that FP32 cannot reach outside them,
+    which can put an extra boundary entry in a list)."""
+    from test_gpu_mapstep import zero_ambiguity_scene
+    p, cam, _ = zero_ambiguity_scene(n=2000)
+    n = p.shape[1]
+    c = fgs.Context()
+    c.profile(3)
+    fgs.render(c, params_dev(p), n, cam, fgs.RenderOpts(), aux=False)
+    rep = c.profile_report()
+    c.profile(0)
+    cnt = rep["counts"]
+    assert cnt["forwards"] == 1
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(), amb_rel=1e-5)
+    assert ref["n_amb"] == 0
+    tc = oracle.tile_counts(p.astype(np.float64), cam, oracle_opts())
+    assert cnt["pairs_examined"] == ref["E_f"]
+    assert cnt["pairs_blended"] == ref["E_c"]
+    assert cnt["K_c"] == tc["K_c"]
+    tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    for k in ("L_f", "L_b"):
+        assert abs(cnt[k] - tc[k]) <= 0.005 * tc[k] + 2 * tiles, (k, cnt[k], tc[k])
+    assert tc["K_c"] <= tc["L_b"] <= tc["L_f"] <= tc["K"]
+    c.close()

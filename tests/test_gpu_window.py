@@ -370,7 +370,7 @@ def test_profiled_window_step_runs_eagerly(fgs, ctx):
     pd = dev(p)
     targets = random_targets(cams, 130)
     win = fgs.Window(ctx, cams, tiles)
-    ctx.profile(2)
+    ctx.profile(3)
     adam = fgs.Adam.like(pd)
     for _ in range(3):
         win.step(pd, p.shape[1], adam, targets, fgs.RenderOpts(), graph=True)

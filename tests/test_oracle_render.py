@@ -348,3 +348,26 @@ def test_duplicate_count_matches_buckets():
             continue
         k2 += (int(x1) // 16 - int(x0) // 16 + 1) * (int(y1) // 16 - int(y0) // 16 + 1)
     assert K == k2 and K > 0
+
+
+def test_tile_counts_invariants_and_limits():
+    """Work counts of the 16x16-tile formulation: K_c <= L_b <= L_f <= K (a contributing pair lies
+    before the last blended entry, which lies before the last examined one); with no termination
+    (T_min = 0) every pixel examines the whole list, L_f = K; with nothing above alpha_min nothing
+    blends, K_c = L_b = 0 and L_f = K; one small gaussian inside one tile gives 1 everywhere."""
+    cam = Camera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    import synth
+    p = synth.scene_small(4).astype(np.float64)
+    c = oracle.tile_counts(p, cam)
+    K = oracle.count_duplicates(p, cam, 16, 16)
+    assert c["K"] == K
+    assert 0 < c["K_c"] <= c["L_b"] <= c["L_f"] <= K
+    c0 = oracle.tile_counts(p, cam, O.__class__(T_min=0.0))
+    assert c0["L_f"] == K
+    q = p.copy()
+    q[10] = -12.0  # opacity 6e-6 < 1/255
+    cn = oracle.tile_counts(q, cam)
+    assert cn["K_c"] == 0 and cn["L_b"] == 0 and cn["L_f"] == K
+    one = one_gaussian(((24.5 - 32.0) * 2 / 60.0, (8.5 - 24.0) * 2 / 60.0, 2.0), [np.log(0.02)] * 3, logit=2.0)
+    c1 = oracle.tile_counts(stack(one), cam)
+    assert c1 == {"K_c": 1, "L_f": 1, "L_b": 1, "K": 1}
