@@ -229,6 +229,9 @@ def work_counts(rep3) -> dict:
                                           ("L_f", "L_f"), ("L_b", "L_b"), ("staged", "entries_staged"))}
     out["forwards"] = c["forwards"]
     out["views_per_launch"] = c["forwards"] / max(rep3["raster_fwd"][1], 1)
+    bwd = max(c.get("backwards", 0), 1)
+    for k in ("bwd_wave_evals", "bwd_wave_takes", "bwd_wave_few", "bwd_pairs_blended"):
+        out[k] = c.get(k, 0) / bwd
     return out
 
 
@@ -580,7 +583,10 @@ def main():
         "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "work_per_iter": {"N": n, "K": int(K), "K_c": round(w["K_c"]), "E_f": round(w["E_f"]),
                           "E_c": round(w["E_c"]), "L_f": round(w["L_f"]), "L_b": round(w["L_b"]),
-                          "entries_staged": round(w["staged"]), "P": P, "T": T},
+                          "entries_staged": round(w["staged"]), "P": P, "T": T,
+                          "bwd_lane_evals_per_blend": round(64 * w["bwd_wave_evals"] / max(w["bwd_pairs_blended"], 1), 3),
+                          "bwd_wave_evals_blending": round(w["bwd_wave_takes"] / max(w["bwd_wave_evals"], 1), 4),
+                          "bwd_wave_evals_1_to_8_blending": round(w["bwd_wave_few"] / max(w["bwd_wave_evals"], 1), 4)},
         "final_loss": float(loss), "final_psnr": float(psnr),
     }
     del params, adam, targets, tgt

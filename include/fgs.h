@@ -147,8 +147,8 @@ fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len);
  * enqueues. level 1: the rasterizer kernels only ("raster_fwd", "raster_bwd"), which then run
  * exactly as unprofiled; level 2: every stage: "project", "depth_sort", "bin" (scan + pair
  * emission), "tile_sort" (with tile ranges), "raster_fwd", "loss", "raster_bwd", "project_bwd",
- * "adam", every kernel still the unprofiled one; level 3: as level 2, and the forward rasterizer
- * counts its work (fgs_ctx_profile_counts, fgs_ctx_profile_work) in a variant that runs longer.
+ * "adam", every kernel still the unprofiled one; level 3: as level 2, and the rasterizers count
+ * their work (fgs_ctx_profile_counts, fgs_ctx_profile_work) in variants that run longer.
  * 0 disables. Every call clears previous records. */
 fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t level);
 /* Waits for the stream; total milliseconds and number of launches of one stage since enabling. */
@@ -159,13 +159,16 @@ fgs_status fgs_ctx_profile_stage(fgs_ctx *ctx, const char *stage, double *total_
  * counts[3] = forward launches counted. */
 fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4]);
 /* Waits for the stream; the full work counters since enabling level 3 (zero below), summed
- * over forwards: counts[0] = E_f, (pixel, gaussian) pairs within the sigma_cut ellipse examined
- * before each pixel stopped; counts[1] = E_c, pairs blended; counts[2] = list entries staged (read
- * from HBM) by the forward rasterizer; counts[3] = K_c, (tile, gaussian) list entries that some pixel
- * of the tile blended; counts[4] = L_f, per tile the list entries up to the last one any pixel
- * examined (all, for a pixel that never stops), summed; counts[5] = L_b, per tile the list entries
- * up to the last blended one, summed; counts[6] = forwards counted; counts[7] = 0. */
-fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[8]);
+ * over the single-view forwards and backwards: counts[0] = E_f, (pixel, gaussian) pairs within the
+ * sigma_cut ellipse examined before each pixel stopped; counts[1] = E_c, pairs blended; counts[2] =
+ * list entries staged (read from HBM) by the forward rasterizer; counts[3] = K_c, (tile, gaussian)
+ * list entries that some pixel of the tile blended; counts[4] = L_f, per tile the list entries up to
+ * the last one any pixel examined (all, for a pixel that never stops), summed; counts[5] = L_b, per
+ * tile the list entries up to the last blended one, summed; counts[6] = forwards counted;
+ * counts[7] = backward wave-entry evaluations (a wave of 64 pixels evaluating one list entry);
+ * counts[8] = those in which some pixel blended; counts[9] = those in which 1 to 8 pixels blended;
+ * counts[10] = pairs the backward found blended (E_c again); counts[11] = backwards counted. */
+fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[12]);
 
 /* ---------------------------- rendering (Eq. 1) and its gradient ---------------------------- */
 

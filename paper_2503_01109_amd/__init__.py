@@ -259,10 +259,11 @@ class Context:
             k = C.c_int64()
             _check(_lib.fgs_ctx_profile_stage(self._p, s.encode(), C.byref(t), C.byref(k)), self._p)
             rep[s] = (t.value, k.value)
-        c = (C.c_int64 * 8)()
+        c = (C.c_int64 * 12)()
         _check(_lib.fgs_ctx_profile_work(self._p, c), self._p)
         rep["counts"] = dict(pairs_examined=c[0], pairs_blended=c[1], entries_staged=c[2], K_c=c[3], L_f=c[4],
-                             L_b=c[5], forwards=c[6])
+                             L_b=c[5], forwards=c[6], bwd_wave_evals=c[7], bwd_wave_takes=c[8],
+                             bwd_wave_few=c[9], bwd_pairs_blended=c[10], backwards=c[11])
         return rep
 
     def stats(self) -> dict:

@@ -151,7 +151,7 @@ struct fgs_ctx {
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
     std::vector<hipEvent_t> event_pool;  // reused by Stage
     DBuf prof_counts;  // 8 x u64 (see fgs_ctx_profile_work)
-    int64_t prof_fwd = 0;
+    int64_t prof_fwd = 0, prof_bwd = 0;
 };
 
 namespace {
@@ -426,6 +426,7 @@ void clear_profile(fgs_ctx *ctx, bool destroy = false)
         }
     ctx->prof_events.clear();
     ctx->prof_fwd = 0;
+    ctx->prof_bwd = 0;
     if (destroy) {
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
         ctx->event_pool.clear();
@@ -603,7 +604,8 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
     {
         Stage st_(ctx, "raster_bwd");
         launch_raster_bwd(rk, cam.width, cam.height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, drgb,
-                          ddepth, dalpha, dscale, g2, s);
+                          ddepth, dalpha, dscale, g2, prof_counts(ctx), s);
+        if (prof_counts(ctx)) ctx->prof_bwd++;
     }
     {
         Stage st_(ctx, "project_bwd");
@@ -787,8 +789,8 @@ fgs_status fgs_ctx_profile(fgs_ctx *ctx, int32_t enable)
         }
     }
     if (ctx->prof) {
-        HIP_TRY(ctx, ctx->prof_counts.ensure(8 * 8));
-        HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 8 * 8));
+        HIP_TRY(ctx, ctx->prof_counts.ensure(16 * 8));
+        HIP_TRY(ctx, hipMemset(ctx->prof_counts.p, 0, 16 * 8));
     }
     return FGS_OK;
 }
@@ -826,17 +828,18 @@ fgs_status fgs_ctx_profile_counts(fgs_ctx *ctx, int64_t counts[4])
     return FGS_OK;
 }
 
-fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[8])
+fgs_status fgs_ctx_profile_work(fgs_ctx *ctx, int64_t counts[12])
 {
     if (!ctx || !counts) return fail(ctx, FGS_ERR_INVALID_ARG, "fgs_ctx_profile_work: NULL argument");
-    unsigned long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long c[10] = {};
     if (ctx->prof_counts.p) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        HIP_TRY(ctx, hipMemcpy(c, ctx->prof_counts.p, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpy(c, ctx->prof_counts.p, sizeof(c), hipMemcpyDeviceToHost));
     }
     for (int k = 0; k < 6; ++k) counts[k] = (int64_t)c[k];
     counts[6] = ctx->prof_fwd;
-    counts[7] = 0;
+    for (int k = 6; k < 10; ++k) counts[k + 1] = (int64_t)c[k];
+    counts[11] = ctx->prof_bwd;
     return FGS_OK;
 }
 
@@ -931,7 +934,7 @@ fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fg
     // the records of this call's gaussians start at zero (a fill kernel, so the call can be captured)
     launch_zero_f32(g2, g->n * kG2Stride, s);
     launch_raster_bwd(rk, cam->width, cam->height, sp.rec, sp.vals, sp.ranges, sp.last, sp.tfinal, dL_drgb,
-                      dL_ddepth, dL_dalpha, nullptr, g2, s);
+                      dL_ddepth, dL_dalpha, nullptr, g2, nullptr, s);
     const GradK gk = to_gk(*grad);
     launch_project_bwd(to_pk(*g), to_camk(*cam), rk, g2, gk, gk, AdamK{}, s);
     HIP_TRY(ctx, hipGetLastError());

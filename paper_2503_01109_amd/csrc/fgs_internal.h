@@ -250,11 +250,13 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 
 // dL planes: drgb 3 planes of P, ddepth P, dalpha P (nullable). ddepth_scale (nullable) points
 // to a device float multiplying ddepth (the 1/P_v of the mean depth term). grad2d: records of
-// kG2Stride floats by gaussian id (the tile lists hold ids).
+// kG2Stride floats by gaussian id (the tile lists hold ids). counts (nullable, profiling): [6] +=
+// wave-entry evaluations (a wave evaluating one list entry for its 64 pixels), [7] += those in
+// which some pixel blended, [8] += those in which 1 to 8 pixels blended, [9] += pairs blended.
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha,
-                       const float *ddepth_scale, float *grad2d, hipStream_t s);
+                       const float *ddepth_scale, float *grad2d, unsigned long long *counts, hipStream_t s);
 
 // Adam hyper-parameters of an update fused into a projection backward. step (nullable) points
 // to the device count of updates already applied (the kernel applies update *step + 1): bc1 and

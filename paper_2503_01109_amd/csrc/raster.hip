@@ -482,8 +482,11 @@ __device__ __forceinline__ void bwd_grad(const BwdPair &p, const float4 &b4, con
     g[4] = edy * e.dy;
 }
 
-// Backward of one tile of one view (NT threads, one pixel each).
-template <int NT>
+// Backward of one tile of one view (NT threads, one pixel each). COUNT: add the backward's work
+// counters to V.counts[6..9]: wave-entry evaluations (a wave evaluating one staged entry for its
+// 64 pixels), those in which some pixel blended, those in which 1 to 8 pixels blended, and the
+// (pixel, entry) pairs blended.
+template <int NT, bool COUNT = false>
 __device__ void tile_bwd(const ViewK &V, int tile)
 {
     constexpr int NW = NT / kWave;
@@ -499,8 +502,19 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     __shared__ uint32_t smax;
     __shared__ uint8_t smask[NT];
     __shared__ uint16_t slist[NW][NT];
+    __shared__ unsigned long long swork[NW][4];
     const int tid = threadIdx.x;
     const int lane = __lane_id();
+    // COUNT: this wave's wave-entry evaluations, of them with a blend, with 1-8 blending pixels,
+    // and its blended pairs (wave-uniform)
+    unsigned long long n_eval = 0, n_take = 0, n_few = 0, n_pairs = 0;
+    auto count_entry = [&](uint64_t bal) {
+        const uint32_t c = (uint32_t)__popcll(bal);
+        n_eval += 1;
+        n_take += c ? 1 : 0;
+        n_few += (c && c <= 8) ? 1 : 0;
+        n_pairs += c;
+    };
     const int term = reduce_term(lane);  // the term whose wave sum this lane holds after reduce10
     const bool red_lane = term >= 0;
     const int slot20 = reduce20_slot(lane);  // the same after reduce20
@@ -547,6 +561,11 @@ __device__ void tile_bwd(const ViewK &V, int tile)
     for (int c = 0; c < 10; ++c) sacc[tid][c] = 0.0f;
     __syncthreads();
     if (L) atomicMax(&smax, L);
+    // the wave's own last blended position: entries at or beyond it are blended by none of its
+    // pixels and are left out of its lists before any evaluation
+    uint32_t wL = L;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wL = max(wL, (uint32_t)__shfl_xor((int)wL, o));
     __syncthreads();
     const uint32_t hi = min(range.x + smax, range.y);
 
@@ -568,8 +587,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
                                              : strip_mask<NW>(mx, my, R.r1.x, R.r1.y, R.r1.z, cut2, TW));
         }
         __syncthreads();
-        const int len = wave_compact(smask, cnt, wid, slist[wid]);
         const uint32_t base = bstart - range.x;
+        const int len = wave_compact(smask, (int)min((uint32_t)cnt, wL > base ? wL - base : 0u), wid, slist[wid]);
         // Branch-free per pair, like the forward: the decisions select what is kept, and a lane
         // that does not take the pair contributes exact zeros. Two entries per iteration: their
         // evaluations and wave reductions are independent, only T and S pass from one to the next.
@@ -579,17 +598,31 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
             const BwdPair p1 = bwd_decide(a1, b1, base + k1 < L, px, py, qcut, rk);
-            if (!__ballot(p0.take || p1.take)) continue;  // no lane blended either entry: nothing to do
-            float g0[10], g1[10];
-            bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
-            bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
-            const float t = reduce20(g0, g1, lane);
-            if (slot20 >= 0) atomicAdd(&sacc[slot20 < 10 ? k0 : k1][slot20 % 10], t);
+            const uint64_t t0 = __ballot(p0.take), t1 = __ballot(p1.take);
+            if (COUNT) {
+                count_entry(t0);
+                count_entry(t1);
+            }
+            if (t0 && t1) {
+                float g0[10], g1[10];
+                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
+                bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
+                const float t = reduce20(g0, g1, lane);
+                if (slot20 >= 0) atomicAdd(&sacc[slot20 < 10 ? k0 : k1][slot20 % 10], t);
+            } else if (t0 || t1) {
+                // one entry blended by some lane: the other leaves every lane's T and S as they are
+                const int k = t0 ? k0 : k1;
+                float g[10];
+                bwd_grad(t0 ? p0 : p1, t0 ? b0 : b1, sc[k], rk, gC0, gC1, gC2, gD, T, S, g);
+                const float t = reduce10(g, lane);
+                if (red_lane) atomicAdd(&sacc[k][term], t);
+            }
         }
         if (i == 0) {
             const int k0 = slist[wid][0];
             const float4 a0 = sa[k0], b0 = sb[k0];
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
+            if (COUNT) count_entry(__ballot(p0.take));
             if (__ballot(p0.take)) {
                 float g0[10];
                 bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
@@ -613,6 +646,21 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             }
         }
     }
+    if (COUNT) {
+        if (lane == 0) {
+            swork[wid][0] = n_eval;
+            swork[wid][1] = n_take;
+            swork[wid][2] = n_few;
+            swork[wid][3] = n_pairs;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            unsigned long long t = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += swork[w][tid];
+            if (t) atomicAdd(&V.counts[6 + tid], t);
+        }
+    }
     __syncthreads();  // LDS is restaged by the next tile of a persistent workgroup
 }
 
@@ -620,8 +668,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
 template <int NT, bool COUNT, bool NCON, bool ALPHA>
 __global__ void __launch_bounds__(NT, 2048 / NT) k_raster_fwd(ViewK V) { tile_fwd<NT, COUNT, NCON, ALPHA>(V, blockIdx.x); }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT>(V, blockIdx.x); }
+template <int NT, bool COUNT>
+__global__ void __launch_bounds__(NT) k_raster_bwd(ViewK V) { tile_bwd<NT, COUNT>(V, blockIdx.x); }
 
 __device__ inline int view_of(const ViewK *views, int nv, uint32_t g)
 {
@@ -714,9 +762,15 @@ static void launch_bwd_view(const ViewK &V, hipStream_t s)
 {
     const unsigned tiles = (unsigned)tile_items(V.rk.tiles_x, V.rk.tiles_y);
     const int nt = V.rk.tile_w * V.rk.tile_h;
-    if (nt == 256) hipLaunchKernelGGL(k_raster_bwd<256>, dim3(tiles), dim3(256), 0, s, V);
-    else if (nt == 512) hipLaunchKernelGGL(k_raster_bwd<512>, dim3(tiles), dim3(512), 0, s, V);
-    else hipLaunchKernelGGL(k_raster_bwd<64>, dim3(tiles), dim3(64), 0, s, V);
+    if (V.counts) {
+        if (nt == 256) hipLaunchKernelGGL((k_raster_bwd<256, true>), dim3(tiles), dim3(256), 0, s, V);
+        else if (nt == 512) hipLaunchKernelGGL((k_raster_bwd<512, true>), dim3(tiles), dim3(512), 0, s, V);
+        else hipLaunchKernelGGL((k_raster_bwd<64, true>), dim3(tiles), dim3(64), 0, s, V);
+    } else {
+        if (nt == 256) hipLaunchKernelGGL((k_raster_bwd<256, false>), dim3(tiles), dim3(256), 0, s, V);
+        else if (nt == 512) hipLaunchKernelGGL((k_raster_bwd<512, false>), dim3(tiles), dim3(512), 0, s, V);
+        else hipLaunchKernelGGL((k_raster_bwd<64, false>), dim3(tiles), dim3(64), 0, s, V);
+    }
 }
 
 void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
@@ -736,7 +790,7 @@ void launch_raster_fwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
 void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, const uint32_t *vals,
                        const uint2 *ranges, const uint32_t *last, const float *tfinal,
                        const float *drgb, const float *ddepth, const float *dalpha, const float *ddepth_scale,
-                       float *grad2d, hipStream_t s)
+                       float *grad2d, unsigned long long *counts, hipStream_t s)
 {
     ViewK V = view_of_args(rk, W, H, rec, vals);
     V.ranges = ranges;
@@ -747,6 +801,7 @@ void launch_raster_bwd(const RasterK &rk, int32_t W, int32_t H, const Rec *rec, 
     V.dalpha = dalpha;
     V.ddepth_scale = ddepth_scale;
     V.grad2d = grad2d;
+    V.counts = counts;
     launch_bwd_view(V, s);
 }
 

@@ -325,6 +325,32 @@ def test_profiling_levels_and_work_counters(fgs, ctx):
             assert np.array_equal(host(r[k]), host(plain[k])), k
 
 
+def test_backward_finds_the_forward_blends(fgs):
+    """At profiling level 3 the mapping step's backward counts the (pixel, entry) pairs it finds
+    blended by replaying the forward's decisions in reverse: exactly the forward's count, on a
+    clamp-heavy scene of 3,000 gaussians over several tiles and a ragged edge."""
+    import torch
+    cam = synth.Camera(72, 52, 70.0, 70.0, 36.0, 26.0)
+    p = synth.frustum_scene(21, 3000, cam, 1.0, 5.0)
+    p[10] = np.abs(p[10]) + 2.0  # opacities near 1: many clamped alphas
+    pd = params_dev(p)
+    n = p.shape[1]
+    ctx = fgs.Context()
+    tgt = fgs.render(ctx, params_dev(synth.frustum_scene(22, 3000, cam, 1.0, 5.0)), n, cam, fgs.RenderOpts(), aux=False)
+    adam = fgs.Adam.like(pd)
+    ctx.profile(3)
+    for _ in range(2):
+        fgs.map_step(ctx, pd, n, adam, [cam], [(tgt["rgb"], tgt["depth"])], fgs.RenderOpts())
+    ctx.check()
+    c = ctx.profile_report()["counts"]
+    ctx.profile(0)
+    torch.cuda.synchronize()
+    assert c["forwards"] == 2 and c["backwards"] == 2
+    assert c["bwd_pairs_blended"] == c["pairs_blended"] > 0
+    assert c["bwd_wave_takes"] <= c["bwd_wave_evals"] and c["bwd_wave_few"] <= c["bwd_wave_takes"]
+    assert 64 * c["bwd_wave_takes"] >= c["bwd_pairs_blended"]
+
+
 def test_work_counts_match_oracle(fgs):
     """The forward's work counters at profiling level 3 against the oracle's on a scene with no
     ambiguous pixel, 16x16 tiles: E_f (pairs examined within the cutoff before each pixel stops),
