@@ -121,6 +121,8 @@ def lib():
         L.fgso_loss_l1.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
         L.fgso_adam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _dp, C.c_double, C.c_double,
                                 C.c_double]
+        L.fgso_ssim.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp]
+        L.fgso_scale_reg.argtypes = [C.c_int64, _dp, _dp, _dp]
         L.fgso_highpass.argtypes = [C.c_int32, C.c_int32, _fp, C.c_double, _dp, _i64p, _i32p, _dp]
         L.fgso_triangle.argtypes = [_i64p]
         L.fgso_triangle.restype = C.c_int32
@@ -242,6 +244,27 @@ def loss_l1(rgb, depth, rgb_t, depth_t, lambda_rgb=1.0, lambda_depth=0.1):
     _check(lib().fgso_loss_l1(P, _ptr(r, _dp), _ptr(d, _dp), _ptr(rt, _dp), _ptr(dt, _dp), lambda_rgb,
                               lambda_depth, _ptr(gr, _dp), _ptr(gd, _dp), C.byref(L), C.byref(ps)), "loss")
     return L.value, ps.value, gr.reshape(np.shape(rgb)), gd.reshape(np.shape(depth))
+
+
+def ssim(img, tgt):
+    """Structural similarity of img to tgt ((3, H, W) each) as in Eq. 16's SSIM term: returns
+    (ssim, d ssim / d img (3, H, W), per-pixel index map (3, H, W))."""
+    x, y = _d(img), _d(tgt)
+    _, H, W = x.shape
+    s = C.c_double()
+    g = np.zeros_like(x)
+    m = np.zeros_like(x)
+    _check(lib().fgso_ssim(W, H, _ptr(x, _dp), _ptr(y, _dp), C.byref(s), _ptr(g, _dp), _ptr(m, _dp)), "ssim")
+    return s.value, g, m
+
+
+def scale_reg(log_scale):
+    """Scale regulariser of Eq. 15 over the (3, n) log-scales: returns (value, d value / d log-scale)."""
+    ls = _d(log_scale)
+    v = C.c_double()
+    g = np.zeros_like(ls)
+    _check(lib().fgso_scale_reg(ls.shape[1], _ptr(ls, _dp), C.byref(v), _ptr(g, _dp)), "scale_reg")
+    return v.value, g
 
 
 def adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):

@@ -98,6 +98,17 @@ int fgso_loss_l1(int64_t P, const double *rgb, const double *depth, const double
                  const double *depth_t, double lambda_rgb, double lambda_depth,
                  double *g_rgb, double *g_depth, double *loss, double *psnr);
 
+/* Structural similarity of img to tgt (3 planes each), Sec. III-D, Eq. 16: the mean over the
+ * 3 P (channel, pixel) values of the windowed index (11x11 gaussian window, sigma 1.5, zero
+ * outside the image, C1 = 0.01^2, C2 = 0.03^2). grad (nullable, 3 planes): d ssim / d img;
+ * smap (nullable, 3 planes): the per-pixel index. */
+int fgso_ssim(int32_t W, int32_t H, const double *img, const double *tgt, double *ssim, double *grad,
+              double *smap);
+
+/* Scale regulariser of Eq. 15 over n gaussians (log_scale: 3 planes of n): value = 1/n sum_i
+ * (|s_i1 - s_i2| + s_i3) with s = exp(log-scale); grad (nullable, 3 planes): d value / d log-scale. */
+int fgso_scale_reg(int64_t n, const double *log_scale, double *value, double *grad);
+
 /* Adam (Kingma and Ba) over 14 parameter planes; lr per group (mean, log-scale, quat,
  * opacity, rgb). step = number of updates already done; this update is step+1. */
 int fgso_adam(int64_t n, double *params, double *m, double *v, const double *grad,
