@@ -415,6 +415,47 @@ def window_roofline(rep1, rep3, kernel_prefix) -> dict:
             "traffic": None, "avg_ms": round(ms[dom], 4), "flops_per_launch": int(flops[dom])}
 
 
+def full_loss_extra(F, steps: int = 50) -> dict:
+    """The mapping step with the whole loss of Eq. 16 on the 300k-gaussian 1200x680 workload:
+    lambda_i = 0.8 (SSIM weight 0.2), lambda_d = 0.1, lambda_r = 0.01 (scale regulariser), against
+    the L1-only step timed the same way."""
+    import torch
+
+    import synth
+    cam = synth.camera_replica()
+    p = synth.scene_replica(0)
+    n = p.shape[1]
+    ctx = F.Context()
+    tgt = F.render(ctx, torch.as_tensor(synth.scene_replica(1)).cuda().contiguous(), n, cam, F.RenderOpts(), aux=False)
+    targets = [(tgt["rgb"], tgt["depth"])]
+    stream = torch.cuda.current_stream()
+    out = {"workload": "splat fwd + Eq. 16 loss (L1 colour 0.8, SSIM 0.2, L1 depth 0.1, scale regulariser 0.01) "
+                       "+ bwd + Adam, 300k gaussians, 1200x680"}
+    reg = torch.zeros(1, device="cuda")
+    for name, lo in (("l1_only", F.LossOpts(1.0, 0.1)), ("full", F.LossOpts(0.8, 0.1, 0.01, reg))):
+        params = torch.as_tensor(p).cuda().contiguous()
+        adam = F.Adam.like(params)
+        loss = torch.zeros(1, device="cuda")
+        step = lambda: F.map_step(ctx, params, n, adam, [cam], targets, F.RenderOpts(), lo, loss=loss)
+        for _ in range(5):
+            step()
+        ctx.check()
+        total, per = timed_steps(step, steps, stream)
+        ctx.profile(2)
+        for _ in range(10):
+            step()
+        ctx.check()
+        rep = ctx.profile_report()
+        ctx.profile(0)
+        out[name] = dict({"ms_per_step": round(total / steps, 4), "loss": float(loss)},
+                         **{f"ms_{k}": v for k, v in pct(per).items()})
+        if name == "full":
+            out[name]["ssim_ms_per_step"] = round(rep["ssim"][0] / 10, 4)
+            out[name]["loss_ms_per_step"] = round(rep["loss"][0] / 10, 4)
+            out[name]["scale_regulariser"] = float(reg)
+    return out
+
+
 def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
     """Fourier seeding of a 640x480 synthetic RGB-D frame and 200 mapping iterations on it."""
     import numpy as np
@@ -603,6 +644,7 @@ def main():
             progress(f"{fn.__name__} done in {time.perf_counter() - t0:.1f} s")
             return r
         line["window"] = extra(window_extra, F, ctx)
+        line["full_loss"] = extra(full_loss_extra, F)
         line["seeding"] = extra(seeding_extra, F, ctx)
         pr = extra(prior_extra, F, ctx, args.prior_train_scenes, args.prior_test_scenes)
         line["learned_prior"] = pr

@@ -114,10 +114,21 @@ typedef struct {
     const float *depth;
 } fgs_target;
 
-/* [host] Loss weights of the L1 colour and depth terms of Eq. 16 (mean over pixels; the depth
- * mean runs over pixels with target depth > 0). */
+/* [host] Weights of the mapping loss of Eq. 16 (Sec. III-D):
+ *   lambda_rgb ||C - C*||_1 + lambda_depth ||D - D*||_1 + (1 - lambda_rgb)(1 - ssim(C, C*))
+ *   + lambda_reg L_reg,
+ * the L1 terms as means over pixels (the depth mean over pixels with target depth > 0). ssim is
+ * the windowed structural-similarity index averaged over pixels and channels (11x11 gaussian
+ * window, sigma 1.5, zero outside the image, C1 = 0.01^2, C2 = 0.03^2); its weight 1 - lambda_rgb
+ * follows Eq. 16, so lambda_rgb = 1 leaves only the L1 terms. L_reg is the scale regulariser of
+ * Eq. 15, 1/n sum_i (|s_i1 - s_i2| + s_i3) over the n gaussians with s = exp(log-scale) (the
+ * in-plane mean taken per gaussian, epsilon = 0), counted once per step. reg_dev (device float,
+ * may be NULL) receives L_reg of the parameters a mapping step started from (unweighted).
+ * The SSIM and L_reg terms are taken by fgs_map_step only; fgs_loss_l1 takes the L1 terms. */
 typedef struct {
     float lambda_rgb, lambda_depth;
+    float lambda_reg;
+    float *reg_dev;
 } fgs_loss_opts;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -146,7 +157,8 @@ fgs_status fgs_last_error(fgs_ctx *ctx, char *buf, size_t len);
 /* [host] Profiling. While enabled, the context records HIP events around pipeline stages it
  * enqueues. level 1: the rasterizer kernels only ("raster_fwd", "raster_bwd"), which then run
  * exactly as unprofiled; level 2: every stage: "project", "depth_sort", "bin" (scan + pair
- * emission), "tile_sort" (with tile ranges), "raster_fwd", "loss", "raster_bwd", "project_bwd",
+ * emission), "tile_sort" (with tile ranges), "raster_fwd", "ssim" (the SSIM term of a mapping
+ * step), "loss", "raster_bwd", "project_bwd",
  * "adam", every kernel still the unprofiled one; level 3: as level 2, and the rasterizers count
  * their work (fgs_ctx_profile_counts, fgs_ctx_profile_work) in variants that run longer.
  * 0 disables. Every call clears previous records. */
@@ -214,10 +226,12 @@ fgs_status fgs_render_bwd_noalloc(fgs_ctx *ctx, const fgs_gaussians *g, const fg
 /* ------------------------------------ mapping step ------------------------------------ */
 
 /* One mapping iteration over a window of n_views keyframes (Sec. III-D, map optimization):
- * for every view, render (Eq. 1), take the L1 colour and depth terms of Eq. 16 against the
- * view's target, and accumulate the gradient; then one Adam update of `params` (opt->step is
- * incremented on the host). cams and targets are [host] arrays of n_views. loss_dev and
- * psnr_dev (device, n_views floats each, may be NULL) receive each view's loss and PSNR.
+ * for every view, render (Eq. 1), take the image terms of Eq. 16 (L1 colour and depth, and the
+ * SSIM term when l->lambda_rgb < 1) against the view's target, and accumulate the gradient; add
+ * the scale regulariser's (l->lambda_reg > 0) once; then one Adam update of `params`
+ * (opt->step is incremented on the host). cams and targets are [host] arrays of n_views.
+ * l->lambda_rgb must lie in [0, 1] and l->lambda_reg be >= 0. loss_dev and psnr_dev (device,
+ * n_views floats each, may be NULL) receive each view's image terms and PSNR.
  * grad_out (may be NULL) receives the summed gradient (overwritten). The context keeps the
  * per-view states; it grows them when a scene needs more pairs than before. Adam's step count is
  * kept on the device too (the update applied is that count + 1; a caller that changes opt->step
@@ -236,6 +250,14 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
 fgs_status fgs_loss_l1(fgs_ctx *ctx, int64_t n_pixels, const float *rgb, const float *depth,
                        const fgs_target *target, const fgs_loss_opts *l, float *dL_drgb,
                        float *dL_ddepth, float *loss_dev, float *psnr_dev);
+
+/* Structural similarity of a rendered image to a target (Sec. III-D, the SSIM term of Eq. 16),
+ * device planes of width*height: img and tgt 3 planes each. ssim_dev (device float, may be NULL)
+ * receives the index averaged over pixels and channels (11x11 gaussian window, sigma 1.5, zero
+ * outside the image, C1 = 0.01^2, C2 = 0.03^2); dssim_dimg (device, 3 planes, may be NULL) its
+ * gradient with respect to img (overwritten). */
+fgs_status fgs_ssim(fgs_ctx *ctx, int32_t width, int32_t height, const float *img, const float *tgt,
+                    float *ssim_dev, float *dssim_dimg);
 
 /* One Adam update of params with gradient grad (opt->step is incremented on the host). */
 fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad,
@@ -265,7 +287,9 @@ fgs_status fgs_window_destroy(fgs_window *w);
  * first call for a given n sizes the window's pair capacity from a synchronous count per view (50%
  * headroom). A later step that outgrows it applies nothing (parameters, moments and the device
  * step count stay as they were); the next call returns FGS_ERR_CAPACITY without running, with
- * opt->step set back to the device's count and the window grown, and the caller repeats the step. */
+ * opt->step set back to the device's count and the window grown, and the caller repeats the step.
+ * The window takes the L1 terms only: l->lambda_rgb other than 1 or l->lambda_reg other than 0
+ * returns FGS_ERR_UNSUPPORTED and enqueues nothing. */
 fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam *opt, const fgs_target *targets,
                            const fgs_render_opts *o, const fgs_loss_opts *l, float *loss_dev, float *psnr_dev,
                            const fgs_gaussians *grad_out, int32_t use_graph);

@@ -71,7 +71,8 @@ class CTarget(C.Structure):
 
 
 class CLossOpts(C.Structure):
-    _fields_ = [("lambda_rgb", C.c_float), ("lambda_depth", C.c_float)]
+    _fields_ = [("lambda_rgb", C.c_float), ("lambda_depth", C.c_float), ("lambda_reg", C.c_float),
+                ("reg_dev", _fp)]
 
 
 class CSeedOpts(C.Structure):
@@ -112,6 +113,7 @@ _sigs = {
     "fgs_map_step": [_vp, _P(CGaussians), _P(CAdam), C.c_int32, _P(CCamera), _P(CTarget), _P(CRenderOpts),
                      _P(CLossOpts), _fp, _fp, _P(CGaussians)],
     "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
+    "fgs_ssim": [_vp, C.c_int32, C.c_int32, _fp, _fp, _fp, _fp],
     "fgs_adam_step": [_vp, _P(CGaussians), _P(CGaussians), _P(CAdam)],
     "fgs_ctx_profile": [_vp, C.c_int32],
     "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
@@ -241,8 +243,8 @@ class Context:
         """Waits for the stream and raises FgsError(ERR_CAPACITY) on a recorded overflow."""
         _check(_lib.fgs_ctx_check(self._p), self._p)
 
-    STAGES = ("project", "depth_sort", "bin", "tile_sort", "raster_fwd", "loss", "raster_bwd", "project_bwd",
-              "adam")
+    STAGES = ("project", "depth_sort", "bin", "tile_sort", "raster_fwd", "ssim", "loss", "raster_bwd",
+              "project_bwd", "adam")
 
     def profile(self, level: int = 2):
         """Start (clearing earlier records) or stop (0) HIP-event timing and work counters:
@@ -334,11 +336,16 @@ class Adam:
 
 @dataclass
 class LossOpts:
+    """Weights of the mapping loss (Eq. 16): lambda_rgb on the L1 colour term, 1 - lambda_rgb on
+    the SSIM term, lambda_depth on the L1 depth term, lambda_reg on the scale regulariser (Eq. 15).
+    reg (optional float32 device tensor of one element) receives the regulariser's value."""
     lambda_rgb: float = 1.0
     lambda_depth: float = 0.1
+    lambda_reg: float = 0.0
+    reg: object = None
 
     def c(self) -> CLossOpts:
-        return CLossOpts(self.lambda_rgb, self.lambda_depth)
+        return CLossOpts(self.lambda_rgb, self.lambda_depth, self.lambda_reg, _f32(self.reg))
 
 
 def map_step(ctx: Context, params, n: int, adam: Adam, cams, targets, opts: RenderOpts,
@@ -406,6 +413,13 @@ def loss_l1(ctx: Context, rgb, depth, target_rgb, target_depth, loss_opts: LossO
     _check(_lib.fgs_loss_l1(ctx.handle, depth.numel(), _f32(rgb), _f32(depth), C.byref(tg),
                             C.byref((loss_opts or LossOpts()).c()), _f32(dL_drgb), _f32(dL_ddepth), _f32(loss),
                             _f32(psnr)), ctx.handle)
+
+
+def ssim(ctx: Context, img, tgt, value=None, grad=None):
+    """Structural similarity of img to tgt ((3, H, W) float32 device tensors; the SSIM term of
+    Eq. 16): value (one-element tensor) receives the mean index, grad ((3, H, W)) its gradient."""
+    _, H, W = img.shape
+    _check(_lib.fgs_ssim(ctx.handle, W, H, _f32(img), _f32(tgt), _f32(value), _f32(grad)), ctx.handle)
 
 
 def adam_step(ctx: Context, params, grad, n: int, adam: Adam):

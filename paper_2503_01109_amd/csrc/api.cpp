@@ -128,6 +128,8 @@ struct fgs_ctx {
     int hist_G = 0;  // radix-sort workgroups the hist buffer holds
     // mapping-step buffers
     DBuf ms_state, ms_dl, ms_grad, ms_partials;
+    DBuf ms_img, ms_ssim, ms_reg;  // rendered colour, per-tile SSIM sums, regulariser partials
+    DBuf ssim_part, ssim_ws;       // SSIM: fgs_ssim's per-tile sums; the partials' workspace
     DBuf seed_ws, seed_sc;
     // learned prior: network workspace (rows_cap rows) and per-frame tile buffers for seeding
     DBuf mlp_ws, prior_feat, prior_valid, prior_y;
@@ -563,7 +565,8 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
                            int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
-                           const LossK *loss = nullptr, uint32_t *step_ovf = nullptr, bool first_of_step = false)
+                           const LossK *loss = nullptr, uint32_t *step_ovf = nullptr, bool first_of_step = false,
+                           float *reg_part = nullptr)
 {
     fgs_status st = ensure_ws(ctx, g.n, L.cap);
     if (st != FGS_OK) return st;
@@ -575,7 +578,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     {
         Stage st_(ctx, "project");
         launch_project(to_pk(g), to_camk(cam), rk, sp.rec, po.rect, po.count, ctx->dkA.as<uint32_t>(),
-                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s);
+                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part);
     }
     {
         Stage st_(ctx, "depth_sort");
@@ -716,7 +719,8 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
                     &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
-                    &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets};
+                    &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets, &ctx->ms_img, &ctx->ms_ssim, &ctx->ms_reg,
+                    &ctx->ssim_part, &ctx->ssim_ws};
     for (DBuf *b : bufs) b->release();
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
     if (ctx->ms_host) (void)hipHostFree(ctx->ms_host);
@@ -986,6 +990,27 @@ static void enqueue_adam(fgs_ctx *ctx, const fgs_gaussians &p, const fgs_gaussia
     opt->step += 1;
 }
 
+fgs_status fgs_ssim(fgs_ctx *ctx, int32_t width, int32_t height, const float *img, const float *tgt,
+                    float *ssim_dev, float *dssim_dimg)
+{
+    const char *w = "fgs_ssim";
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    if (width <= 0 || height <= 0 || (int64_t)width * height > ((int64_t)1 << 29))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: image size %d x %d outside (0, 2^29] pixels", w, width, height);
+    if (!img || !tgt) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: img or tgt is NULL", w);
+    if (!ssim_dev && !dssim_dimg) return FGS_OK;
+    const int64_t T = ssim_partials(width, height);
+    HIP_TRY(ctx, ctx->ssim_part.ensure((size_t)T * 4));
+    HIP_TRY(ctx, ctx->ssim_ws.ensure((size_t)ssim_ws_floats(width, height) * 4));
+    launch_ssim(width, height, img, tgt, 1.0f, false, dssim_dimg, ssim_dev ? ctx->ssim_part.as<float>() : nullptr,
+                ctx->ssim_ws.as<float>(), ctx->stream);
+    if (ssim_dev)
+        launch_sum_scaled(ctx->ssim_part.as<float>(), (int)T, 1.0 / (3.0 * (double)width * (double)height), ssim_dev,
+                          ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
 fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_gaussians *grad, fgs_adam *opt)
 {
     const char *w = "fgs_adam_step";
@@ -1012,8 +1037,12 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
     if (n_views <= 0 || n_views > 4096) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_views outside [1, 4096]", w);
     if (!cams || !targets) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: cams/targets is NULL", w);
     if ((st = check_opts(ctx, o, w, &tw, &th)) != FGS_OK) return st;
-    if (!l || !isfinite(l->lambda_rgb) || !isfinite(l->lambda_depth))
+    if (!l || !isfinite(l->lambda_rgb) || !isfinite(l->lambda_depth) || !isfinite(l->lambda_reg))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: loss options NULL or not finite", w);
+    if (!(l->lambda_rgb >= 0.0f && l->lambda_rgb <= 1.0f) || l->lambda_reg < 0.0f)
+        return fail(ctx, FGS_ERR_INVALID_ARG,
+                    "%s: lambda_rgb must lie in [0, 1] (Eq. 16 weights the SSIM term by 1 - lambda_rgb) and "
+                    "lambda_reg be >= 0", w);
     int64_t Pmax = 0;
     for (int v = 0; v < n_views; ++v) {
         if ((st = check_camera(ctx, &cams[v], w)) != FGS_OK) return st;
@@ -1100,6 +1129,18 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         Tmax = std::max<int64_t>(Tmax, tile_items((cams[v].width + tw - 1) / tw, (cams[v].height + th - 1) / th));
     HIP_TRY(ctx, ctx->ms_dl.ensure((size_t)Pmax * 4 * 4));
     HIP_TRY(ctx, ctx->ms_partials.ensure((size_t)Tmax * 4 * 4));
+    // the SSIM term needs the rendered colour and one sum per 16x16 tile; the regulariser one
+    // partial sum per projection workgroup
+    const float ssim_w = 1.0f - l->lambda_rgb;
+    const bool use_ssim = ssim_w > 0.0f, use_reg = l->lambda_reg > 0.0f || l->reg_dev;
+    if (use_ssim) {
+        int64_t St = 0;
+        for (int v = 0; v < n_views; ++v) St = std::max<int64_t>(St, ssim_partials(cams[v].width, cams[v].height));
+        HIP_TRY(ctx, ctx->ms_img.ensure((size_t)Pmax * 3 * 4));
+        HIP_TRY(ctx, ctx->ms_ssim.ensure((size_t)St * 4));
+        HIP_TRY(ctx, ctx->ssim_ws.ensure((size_t)9 * Pmax * 4));
+    }
+    if (use_reg) HIP_TRY(ctx, ctx->ms_reg.ensure((size_t)project_blocks(n) * 4));
     if (ctx->ms_cap == 0) ctx->ms_cap = n * 16 > ((int64_t)1 << 22) ? n * 16 : ((int64_t)1 << 22);
     float *dscale = ctx->words.as<float>() + W_DSCALE;
     for (int v = 0; v < n_views; ++v) {
@@ -1110,7 +1151,8 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         for (int attempt = 0;; ++attempt) {
             state_layout(n, cam.width, cam.height, tw, th, ctx->ms_cap, &L);
             HIP_TRY(ctx, ctx->ms_state.ensure(L.bytes));
-            const ImageK img{nullptr, nullptr, nullptr, nullptr, nullptr};  // only the loss reads the image
+            // only the loss reads the image (and the SSIM term the rendered colour)
+            const ImageK img{use_ssim ? ctx->ms_img.as<float>() : nullptr, nullptr, nullptr, nullptr, nullptr};
             float *dl = ctx->ms_dl.as<float>();
             LossK lk{};
             lk.trgb = targets[v].rgb;
@@ -1132,7 +1174,8 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             const bool checked = !seen || K_obs * 10 > ctx->ms_cap * 9;
             int64_t K = 0;
             st = enqueue_forward(ctx, *params, cam, *o, tw, th, img, ctx->ms_state.p, L, checked ? &K : nullptr,
-                                 hs_dev, true, &lk, step_ovf, v == 0);
+                                 hs_dev, true, &lk, step_ovf, v == 0,
+                                 use_reg && v == 0 ? ctx->ms_reg.as<float>() : nullptr);
             if (st == FGS_OK) {
                 if (v < 4096) {
                     ctx->ms_seen[v] = true;
@@ -1147,14 +1190,31 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             ctx->ms_cap = K + K / 4 + 1024;
         }
         float *dl = ctx->ms_dl.as<float>();
+        const bool last = v == n_views - 1;
+        LossExtraK ex{};
+        if (use_ssim) {
+            // (1 - lambda_rgb)(1 - ssim): its gradient added to the L1 terms' colour gradient
+            Stage st_(ctx, "ssim");
+            launch_ssim(cam.width, cam.height, ctx->ms_img.as<float>(), targets[v].rgb, -ssim_w, true, dl,
+                        ctx->ms_ssim.as<float>(), ctx->ssim_ws.as<float>(), s);
+            ex.ssim_part = ctx->ms_ssim.as<float>();
+            ex.ssim_nb = (int)ssim_partials(cam.width, cam.height);
+            ex.ssim_w = ssim_w;
+        }
+        if (use_reg && last) {
+            ex.reg_part = ctx->ms_reg.as<float>();
+            ex.reg_nb = (int)project_blocks(n);
+            ex.reg_scale = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
+            ex.reg_out = l->reg_dev;
+        }
         {
             Stage st_(ctx, "loss");
             launch_loss_final(ctx->ms_partials.as<float>(), (int)L.T, P, l->lambda_rgb, l->lambda_depth, dscale,
-                              loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr, s);
+                              loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr, s, ex);
         }
-        // views before the last sum their gradients into grad; the last one adds its own and
-        // applies Adam in the same kernel (writing the sum only when the caller asked for it)
-        const bool last = v == n_views - 1;
+        // views before the last sum their gradients into grad; the last one adds its own (and the
+        // regulariser's) and applies Adam in the same kernel (writing the sum only when the caller
+        // asked for it)
         AdamK ak{};
         if (last) {
             // update number = the device's count + 1; skipped (and the count kept) when any view
@@ -1174,6 +1234,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             const double t = (double)(opt->step + 1);
             ak.bc1 = (float)(1.0 - pow((double)opt->beta1, t));
             ak.bc2 = (float)(1.0 - pow((double)opt->beta2, t));
+            ak.reg_w = l->lambda_reg > 0.0f && n > 0 ? (float)((double)l->lambda_reg / (double)n) : 0.0f;
         }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
                                    v > 0 ? &grad : nullptr, !last || grad_out ? &grad : nullptr,
@@ -1760,6 +1821,10 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
             return fail(ctx, FGS_ERR_INVALID_ARG, "%s: target %d has a NULL plane", w_, v);
     if (!l || !std::isfinite(l->lambda_rgb) || !std::isfinite(l->lambda_depth))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: loss options NULL or not finite", w_);
+    if (l->lambda_rgb != 1.0f || l->lambda_reg != 0.0f || l->reg_dev)
+        return fail(ctx, FGS_ERR_UNSUPPORTED,
+                    "%s: the window takes the L1 terms only (lambda_rgb = 1, lambda_reg = 0, no reg_dev); use "
+                    "fgs_map_step for the SSIM term and the scale regulariser", w_);
     if (grad_out) {
         if ((st = check_gauss(ctx, grad_out, w_, "grad_out")) != FGS_OK) return st;
         if (grad_out->n != params->n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: grad_out.n != params.n", w_);

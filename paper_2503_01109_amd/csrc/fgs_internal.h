@@ -121,11 +121,13 @@ void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // sort: views sorted together are projected into consecutive ranges). count[i] receives the
 // number of tiles (shift 0) or super-tiles (tile rectangle >> shift) covered, rect[i] the tile
 // rectangle; kpart (2 words per workgroup, project_blocks(n) workgroups) the workgroups'
-// (tile, gaussian) pair and visible gaussian counts, summed by launch_scan_counts.
+// (tile, gaussian) pair and visible gaussian counts, summed by launch_scan_counts. reg_part
+// (nullable, project_blocks(n) floats): each workgroup's sum of the scale regulariser's terms
+// |s1 - s2| + s3 (s = exp(log-scale); Eq. 15).
 int64_t project_blocks(int64_t n);
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
-                    uint32_t *kpart, hipStream_t s, uint32_t id_base = 0);
+                    uint32_t *kpart, hipStream_t s, uint32_t id_base = 0, float *reg_part = nullptr);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
@@ -274,6 +276,8 @@ struct AdamK {
     float lr[5];
     float beta1, beta2, eps;
     float bc1, bc2;
+    // scale regulariser of Eq. 15 applied with the update: reg_w = lambda_r / n (0: none)
+    float reg_w;
 };
 
 // Chain rule from the 2D gradient records (by gaussian id) to the 14 parameter gradients of every
@@ -296,8 +300,32 @@ void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, f
 int64_t loss_partials_size(int64_t P);
 // Reduction of nb partial quadruples (as written by the fused forward loss) into loss, psnr and
 // the depth term's 1/P_v (all device scalars, nullable).
+// The structural-similarity term and the scale regulariser (Sec. III-D, Eq. 15 and 16) as reduced
+// by launch_loss_final: ssim_part (ssim_nb per-tile sums of the index, nullable) adds
+// ssim_w (1 - sum / (3 P)) to the loss; reg_part (reg_nb per-workgroup sums of |s1 - s2| + s3,
+// nullable) gives reg_out = reg_scale sum (nullable).
+struct LossExtraK {
+    const float *ssim_part;
+    int ssim_nb;
+    float ssim_w;
+    const float *reg_part;
+    int reg_nb;
+    float reg_scale;
+    float *reg_out;
+};
 void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
-                       float *loss, float *psnr, hipStream_t s);
+                       float *loss, float *psnr, hipStream_t s, const LossExtraK &extra = LossExtraK{});
+
+// Structural similarity of img to tgt (3 planes of W x H each; Sec. III-D, Eq. 16): grad (3
+// planes, nullable) = (accumulate ? grad : 0) + gscale d ssim / d img; partials (nullable,
+// ssim_partials(W, H) floats): per channel and 32x32 tile the sum of the index over the tile's
+// pixels; ws: ssim_ws_floats(W, H) floats of scratch.
+int64_t ssim_partials(int32_t W, int32_t H);
+int64_t ssim_ws_floats(int32_t W, int32_t H);
+// *out = scale * the sum of n floats (one workgroup, FP64, fixed order)
+void launch_sum_scaled(const float *a, int n, double scale, float *out, hipStream_t s);
+void launch_ssim(int32_t W, int32_t H, const float *img, const float *tgt, float gscale, bool accumulate, float *grad,
+                 float *partials, float *ws, hipStream_t s);
 // The same for every view of a window at once (view v: its partials, tile count, pixel count,
 // loss weights and 1/P_v slot from views_dev[v]; loss[v], psnr[v], nullable).
 void launch_loss_final_views(const ViewK *views_dev, int nv, uint32_t total_items, float *loss, float *psnr,

@@ -58,12 +58,34 @@ k_loss_partial(int64_t P, const float *__restrict__ rgb, const float *__restrict
     if (threadIdx.x < 4) partials[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Sum of n floats by one workgroup of kFinalThreads in FP64 and a fixed order (every thread gets
+// the sum).
+__device__ double block_sum(const float *__restrict__ a, int n)
+{
+    constexpr int NW = kFinalThreads / kWave;
+    __shared__ double wred[NW];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFinalThreads) s += (double)a[k];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __syncthreads();  // wred may still be read by an earlier call
+    if (__lane_id() == 0) wred[threadIdx.x / kWave] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += wred[w];
+    return t;
+}
+
 // Loss and PSNR from nb per-tile partial quadruples (one workgroup of kFinalThreads), in FP64 and
 // a fixed order. A quadruple is one 16-byte load (partials is 16-byte aligned); each thread puts
-// up to four of them in flight before adding, so the kernel waits on memory about once.
+// up to four of them in flight before adding, so the kernel waits on memory about once. The
+// structural-similarity and regulariser terms (extra) are reduced the same way.
 __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
-                            float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
+                            float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr,
+                            const LossExtraK &extra = LossExtraK{})
 {
+    const double ssim_sum = extra.ssim_part ? block_sum(extra.ssim_part, extra.ssim_nb) : 0.0;
+    const double reg_sum = extra.reg_part ? block_sum(extra.reg_part, extra.reg_nb) : 0.0;
     constexpr int NW = kFinalThreads / kWave, U = 4;
     __shared__ double red[NW][4];
     const float4 *__restrict__ p4 = reinterpret_cast<const float4 *>(partials);
@@ -101,7 +123,10 @@ __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t 
         const double l1c = t[0], se = t[1], l1d = t[2], nv = t[3];
         const double scale = nv > 0 ? 1.0 / nv : 0.0;
         if (ddepth_scale) *ddepth_scale = (float)scale;
-        if (loss) *loss = (float)((double)lrgb * l1c / (3.0 * (double)P) + (double)ldepth * l1d * scale);
+        double L = (double)lrgb * l1c / (3.0 * (double)P) + (double)ldepth * l1d * scale;
+        if (extra.ssim_part) L += (double)extra.ssim_w * (1.0 - ssim_sum / (3.0 * (double)P));
+        if (loss) *loss = (float)L;
+        if (extra.reg_out) *extra.reg_out = (float)(reg_sum * (double)extra.reg_scale);
         const double mse = se / (3.0 * (double)P);
         if (psnr) *psnr = (float)(mse > 0 ? 10.0 * log10(1.0 / mse) : INFINITY);
     }
@@ -109,9 +134,16 @@ __device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t 
 
 __global__ void __launch_bounds__(kFinalThreads)
 k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
-             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr)
+             float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr, LossExtraK extra)
 {
-    loss_reduce(partials, nb, P, lrgb, ldepth, ddepth_scale, loss, psnr);
+    loss_reduce(partials, nb, P, lrgb, ldepth, ddepth_scale, loss, psnr, extra);
+}
+
+__global__ void __launch_bounds__(kFinalThreads)
+k_sum_scaled(const float *__restrict__ a, int n, double scale, float *__restrict__ out)
+{
+    const double t = block_sum(a, n);
+    if (threadIdx.x == 0) *out = (float)(t * scale);
 }
 
 // One workgroup per view of a window: view v's tiles are window items [tile_base_v, tile_base_v+1).
@@ -202,14 +234,19 @@ void launch_loss_l1(int64_t P, const float *rgb, const float *depth, const float
     hipLaunchKernelGGL(k_loss_partial, dim3(nb), dim3(kLossThreads), 0, s, P, rgb, depth, trgb, tdepth, lrgb,
                        ldepth, drgb, ddepth, partials);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kFinalThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
-                       loss, psnr);
+                       loss, psnr, LossExtraK{});
 }
 
 void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
-                       float *loss, float *psnr, hipStream_t s)
+                       float *loss, float *psnr, hipStream_t s, const LossExtraK &extra)
 {
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kFinalThreads), 0, s, partials, nb, P, lrgb, ldepth, ddepth_scale,
-                       loss, psnr);
+                       loss, psnr, extra);
+}
+
+void launch_sum_scaled(const float *a, int n, double scale, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_scaled, dim3(1), dim3(kFinalThreads), 0, s, a, n, scale, out);
 }
 
 void launch_loss_final_views(const ViewK *views_dev, int nv, uint32_t total_items, float *loss, float *psnr,

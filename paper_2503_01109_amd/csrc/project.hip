@@ -121,9 +121,11 @@ __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
-          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart, uint32_t id_base)
+          uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart, uint32_t id_base,
+          float *__restrict__ reg_part)
 {
     __shared__ uint32_t wsum[2][4];
+    __shared__ float wreg[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n_out = id_base + (uint32_t)g.n;
     uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian
@@ -144,6 +146,18 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
     if (threadIdx.x < 2)
         kpart[2 * blockIdx.x + threadIdx.x] =
             wsum[threadIdx.x][0] + wsum[threadIdx.x][1] + wsum[threadIdx.x][2] + wsum[threadIdx.x][3];
+    if (reg_part) {
+        // the scale regulariser's terms (Eq. 15): |s1 - s2| + s3 with s = exp(log-scale)
+        float r = 0.0f;
+        if (i < g.n) {
+            const float s1 = expf(g.log_scale[i]), s2 = expf(g.log_scale[g.stride + i]);
+            r = fabsf(s1 - s2) + expf(g.log_scale[2 * g.stride + i]);
+        }
+        for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+        if ((threadIdx.x & 63) == 0) wreg[threadIdx.x >> 6] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) reg_part[blockIdx.x] = (wreg[0] + wreg[1]) + (wreg[2] + wreg[3]);
+    }
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
@@ -363,6 +377,15 @@ k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK
     float gi[14];
 #pragma unroll
     for (int k = 0; k < 14; ++k) gi[k] = grad_in.mean ? plane(grad_in, k)[i] + (float)out[k] : (float)out[k];
+    if (adam.reg_w != 0.0f) {
+        // scale regulariser (Eq. 15), lambda_r / n (|s1 - s2| + s3): d/d log s_k = s_k d/d s_k
+        const float s1 = expf(g.log_scale[i]), s2 = expf(g.log_scale[g.stride + i]);
+        const float s3 = expf(g.log_scale[2 * g.stride + i]);
+        const float d = (float)((s1 > s2) - (s1 < s2));
+        gi[3] += adam.reg_w * d * s1;
+        gi[4] -= adam.reg_w * d * s2;
+        gi[5] += adam.reg_w * s3;
+    }
     if (grad_out.mean)
 #pragma unroll
         for (int k = 0; k < 14; ++k) plane(grad_out, k)[i] = gi[k];
@@ -407,10 +430,10 @@ int64_t project_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
                     uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *kpart,
-                    hipStream_t s, uint32_t id_base)
+                    hipStream_t s, uint32_t id_base, float *reg_part)
 {
     hipLaunchKernelGGL(k_project, dim3((unsigned)project_blocks(g.n)), dim3(256), 0, s, g, cam, rk, rec, rect, count,
-                       dkey, ids, n_out, shift, kpart, id_base);
+                       dkey, ids, n_out, shift, kpart, id_base, reg_part);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,
