@@ -505,16 +505,26 @@ def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
 def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
     """Learned prior: trained on 100 tiles of each of the converged maps of frames 0..n_train-1,
     compared with the plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on the held-out frames
-    1000..1000+n_test-1; the headline and one record per held-out frame."""
+    1000..1000+n_test-1. Headline: the prior's opacity alone (use_prior 3), with one record per
+    held-out frame; also its shape and opacity together (use_prior 1) and the control that gives
+    the plain rule the prior's mean predicted opacity as its constant."""
     from paper_2503_01109_amd import prior
     r = prior.run_experiment(F, ctx, range(0, n_train), range(1000, 1000 + n_test), iters=200,
-                             tiles_per_scene=100, train_steps=2000, log=progress)
+                             tiles_per_scene=100, train_steps=2000, log=progress, mode=3, other_modes=(1,),
+                             constant_control=True)
     rnd = lambda v: round(v, 4) if isinstance(v, float) else v
     out = {k: rnd(v) for k, v in r["summary"].items()}
     keys = ("ms", "iters", "seed_ms", "ms_per_iter", "seeds", "final_db")
     out["per_scene"] = [dict(scene=row["scene"], **{f"{run}_{k}": rnd(row[run][k]) for run in
                                                     ("plain", "prior", "plain_repeat") for k in keys})
                         for row in r["rows"]]
+    brief = ("wins", "losses", "prior_never_reached", "ms_ratio_median", "ms_ratio_p10", "ms_ratio_p90",
+             "plain_ms_mean", "prior_ms_mean", "plain_iters_mean", "prior_iters_mean", "plain_ms_per_iter_mean",
+             "prior_ms_per_iter_mean", "plain_final_db", "prior_final_db")
+    out["shape_and_opacity"] = {k: rnd(r["modes"][1]["summary"][k]) for k in brief}
+    cc = r["constant_control"]
+    out["constant_opacity_control"] = dict(plain_opacity=rnd(cc["opacity"]),
+                                           **{k: rnd(cc["summary"][k]) for k in brief})
     return out
 
 
@@ -651,8 +661,11 @@ def main():
         if "error" not in pr:
             line["ms_to_target_psnr"] = {"learned": pr["prior_ms_mean"], "plain": pr["plain_ms_mean"],
                                          "target": "plain method's PSNR after 200 iterations - 0.1 dB",
+                                         "learned_applies": "the prior's opacity (its shape prediction costs "
+                                                            "more per iteration than it saves; see shape_and_opacity)",
                                          "held_out_scenes": pr["scenes"], "wins": pr["wins"],
-                                         "prior_never_reached": pr["prior_never_reached"]}
+                                         "prior_never_reached": pr["prior_never_reached"],
+                                         "median_ratio": pr["ms_ratio_median"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_iters)
         progress("cpu baseline done")

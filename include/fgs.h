@@ -303,7 +303,8 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
  * Seeds need a finite depth in [depth_min, depth_max]. use_prior = 1 replaces the radius rule and
  * the constant opacity of the gaussians written into out->params (required then) by the learned
  * prior of fgs_prior.h, evaluated on the frame's 16x16 tiles, whose packed FP32 weights `prior`
- * points to (device); the seed set and the seed arrays are unchanged.
+ * points to (device); 2 takes only its shape (log-scales and the camera-aligned rotation), 3 only
+ * its opacity; the seed set and the seed arrays are unchanged.
  * Missing-region check (Sec. III-A, Eq. 9, 10): render_alpha, render_depth (width*height) and
  * render_rgb (3 planes) are the current map rendered at cam with a black background and background
  * depth 0 (fgs_render_fwd's opacity A, depth and colour planes; device). A pixel is missing when

@@ -1267,6 +1267,8 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
     if (!isfinite(o->alpha_h) || !isfinite(o->alpha_l) || !isfinite(o->opacity_logit) ||
         !(o->depth_min <= o->depth_max))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: radius factors, opacity or depth range invalid", w);
+    if (o->use_prior < 0 || o->use_prior > 3)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior outside 0..3", w);
     if (o->use_prior && !o->prior) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: use_prior without weights", w);
     if (o->render_alpha && (!o->render_depth || !o->render_rgb))
         return fail(ctx, FGS_ERR_INVALID_ARG, "%s: missing-region check needs the rendered depth and colour", w);
@@ -1333,6 +1335,7 @@ fgs_status fgs_seed_gaussians(fgs_ctx *ctx, const float *rgb, const float *depth
         pk.W = W;
         pk.max_dev = (float)log(4.0);
         pk.min_valid = 4;
+        pk.mode = o->use_prior;
         camera_to_world_quat(cam->R_cw, pk.q);
         const int64_t S = out->params.stride;
         launch_prior_apply(pk, seed_count_ptr(ctx->seed_ws.p, W, H), out->capacity, out->pixel,

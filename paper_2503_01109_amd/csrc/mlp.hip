@@ -379,15 +379,15 @@ __global__ void k_prior_apply(PriorApplyK pk, const uint32_t *__restrict__ count
 #pragma unroll
         for (int k = 0; k < 3; ++k) use = use && isfinite(o[k]) && fabsf(o[k]) <= pk.max_dev;
         use = use && isfinite(o[3]);
-        if (use) {
+        if (use && pk.mode != 3) {
             // the radius rule's log-radius, written by the seed emission on every axis
             const float base = log_scale[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k) log_scale[k * S + i] = base + o[k];
 #pragma unroll
             for (int k = 0; k < 4; ++k) quat[k * S + i] = pk.q[k];
-            logit[i] = o[3];
         }
+        if (use && pk.mode != 2) logit[i] = o[3];
         if (from_prior) from_prior[i] = use ? 1 : 0;
     }
 }

@@ -60,6 +60,7 @@ struct PriorApplyK {
     float max_dev;    // fallback when a predicted offset exceeds this in magnitude
     float q[4];       // camera-to-world rotation (w, x, y, z): local axes = camera axes
     int32_t min_valid;  // fallback when a tile has fewer valid-depth pixels
+    int32_t mode;       // 1: shape (log-scales, rotation) and opacity; 2: shape only; 3: opacity only
 };
 
 // Rewrites the seeds' log-scales, rotation and opacity logit from per-tile predictions y

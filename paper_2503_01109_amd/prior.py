@@ -164,7 +164,8 @@ def _reach(run: MapRun, target: float) -> dict:
                 ms_per_iter=float((run.ms[-1] - run.seed_ms) / iters))
 
 
-def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, plain_opts=None, prior_opts=None):
+def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, plain_opts=None, prior_opts=None,
+             mode: int = 3):
     """Per held-out scene: the plain run's final PSNR less margin_db is the target; iterations and
     device ms until each run reaches it (None: never within iters), their seeding times, seeds and
     ms per iteration. The plain run is repeated; the repeat's distance from the first is the
@@ -173,7 +174,7 @@ def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, 
     if prior_opts is None:
         prior_opts = F.SeedOpts(**{k: getattr(plain_opts, k) for k in ("D0", "m", "n", "tile", "alpha_h", "alpha_l",
                                                                        "opacity_logit", "depth_min", "depth_max")})
-        prior_opts.use_prior, prior_opts.prior = 1, weights
+        prior_opts.use_prior, prior_opts.prior = mode, weights
     rows = []
     for s in scenes:
         fr = frame_of(s)
@@ -189,23 +190,29 @@ def evaluate(F, ctx, weights, scenes, iters: int = 200, margin_db: float = 0.1, 
 
 
 def summarize(rows) -> dict:
-    """Headline of evaluate(): a scene is a win when the prior reaches the target sooner than both
-    plain runs by more than their spread; a scene the prior never reaches counts as a loss."""
+    """Headline of evaluate(): a scene is a win when the prior reaches the target sooner than the
+    plain runs by more than their spread (|first - repeat|; where the repeat falls short of the
+    target, the median spread of the other scenes, against the first run); a scene the prior never
+    reaches counts as a loss."""
     wins = losses = failed = 0
     ratios = []
-    spread = []
+    spread = [abs(r["plain"]["ms"] - r["plain_repeat"]["ms"]) for r in rows
+              if r["plain"]["ms"] is not None and r["plain_repeat"]["ms"] is not None]
+    med_spread = float(np.median(spread)) if spread else 0.0
     for r in rows:
         a, b, a2 = r["plain"], r["prior"], r["plain_repeat"]
         if b["ms"] is None:
             failed += 1
             losses += 1
             continue
-        if a["ms"] is None or a2["ms"] is None:
+        if a["ms"] is None:
             continue
-        sp = abs(a["ms"] - a2["ms"])
-        spread.append(sp)
-        ratios.append(b["ms"] / min(a["ms"], a2["ms"]))
-        if b["ms"] < min(a["ms"], a2["ms"]) - sp:
+        if a2["ms"] is not None:
+            best, sp = min(a["ms"], a2["ms"]), abs(a["ms"] - a2["ms"])
+        else:
+            best, sp = a["ms"], med_spread
+        ratios.append(b["ms"] / best)
+        if b["ms"] < best - sp:
             wins += 1
         else:
             losses += 1
@@ -217,6 +224,7 @@ def summarize(rows) -> dict:
     return dict(
         scenes=len(rows), wins=wins, losses=losses, prior_never_reached=failed,
         plain_never_reached=sum(r["plain"]["ms"] is None for r in rows),
+        repeat_short_of_target=sum(r["plain_repeat"]["ms"] is None for r in rows),
         ms_ratio_median=float(np.median(ratios)) if ratios else None,
         ms_ratio_p10=float(np.percentile(ratios, 10)) if ratios else None,
         ms_ratio_p90=float(np.percentile(ratios, 90)) if ratios else None,
@@ -248,11 +256,29 @@ def best_plain_opacity(F, ctx, scenes, iters: int, choices=(0.1, 0.5, 0.9)):
     return best[1]
 
 
+def mean_predicted_opacity(F, ctx, weights, scenes) -> float:
+    """The prior's opacity averaged over every valid tile of the frames `scenes` (the constant a
+    plain rule would need to match it)."""
+    import torch
+    vals = []
+    for s in scenes:
+        fr = frame_of(s)
+        feat, valid = F.tile_features(ctx, torch.as_tensor(fr.rgb).cuda(), torch.as_tensor(fr.depth).cuda())
+        y = F.prior_forward(ctx, feat, weights)
+        ok = valid.cpu().numpy() >= 4
+        vals.append(1.0 / (1.0 + np.exp(-y[:, 3].cpu().numpy().astype(np.float64)[ok])))
+    return float(np.mean(np.concatenate(vals)))
+
+
 def run_experiment(F, ctx, train_scenes, test_scenes, iters: int = 200, tiles_per_scene: int = 100,
                    train_steps: int = 2000, lr: float = 1e-3, margin_db: float = 0.1, opacity=None,
-                   log=None) -> dict:
+                   log=None, mode: int = 3, other_modes=(), constant_control: bool = False) -> dict:
     """Build the training set from the plain method's converged maps, train the prior on the GPU,
-    and compare time and iterations to the plain method's final PSNR on held-out scenes. log
+    and compare time and iterations to the plain method's final PSNR on held-out scenes. mode: how
+    the prior seeds (fgs_seed_opts.use_prior: 1 shape and opacity, 2 shape, 3 opacity); the
+    summary is that mode's against the plain rule at `opacity` (swept over 0.1 / 0.5 / 0.9 when
+    None). other_modes: further modes, evaluated the same way ("modes"); constant_control: also
+    the plain rule at the prior's mean predicted opacity against `mode` ("constant_control"). log
     (optional) receives one progress line per phase."""
     import time
     log = log or (lambda msg: None)
@@ -267,7 +293,22 @@ def run_experiment(F, ctx, train_scenes, test_scenes, iters: int = 200, tiles_pe
     w, losses = train(F, ctx, X, Y, train_steps, lr)
     t_train = time.perf_counter() - t0 - t_data
     log(f"prior trained in {t_train:.1f} s")
-    rows = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=base)
-    summary = dict(opacity=opacity, train_rows=int(X.shape[0]), train_loss_first=float(losses[0]),
+
+    def prior_opts(m):
+        return F.SeedOpts(opacity_logit=logit(opacity), use_prior=m, prior=w)
+
+    rows = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=base, prior_opts=prior_opts(mode))
+    summary = dict(mode=mode, opacity=opacity, train_rows=int(X.shape[0]), train_loss_first=float(losses[0]),
                    train_loss_last=float(losses[-1]), data_s=t_data, train_s=t_train, **summarize(rows))
-    return dict(summary=summary, rows=rows, weights=w, losses=losses)
+    out = dict(summary=summary, rows=rows, weights=w, losses=losses, modes={})
+    for m in other_modes:
+        r = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=base, prior_opts=prior_opts(m))
+        out["modes"][m] = dict(summary=summarize(r), rows=r)
+        log(f"mode {m} evaluated")
+    if constant_control:
+        c = mean_predicted_opacity(F, ctx, w, test_scenes)
+        r = evaluate(F, ctx, w, test_scenes, iters, margin_db, plain_opts=F.SeedOpts(opacity_logit=logit(c)),
+                     prior_opts=prior_opts(mode))
+        out["constant_control"] = dict(opacity=c, summary=summarize(r), rows=r)
+        log(f"constant-opacity control ({c:.4f}) evaluated")
+    return out

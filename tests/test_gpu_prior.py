@@ -241,6 +241,21 @@ def test_seeding_with_the_prior(fgs, ctx, b3, inside):
     np.testing.assert_array_equal(pb[10, used], b3[3])
     Rq = quat_to_rot(pb[6:10, np.argmax(used)].astype(np.float64))
     np.testing.assert_allclose(Rq, np.asarray(R, np.float64).reshape(3, 3).T, atol=1e-6)
+    # the prior's shape alone (use_prior 2) and its opacity alone (3), on the same seeds
+    for mode in (2, 3):
+        part_p = torch.zeros((14, cap), device="cuda")
+        c = fgs.seed_gaussians(ctx, dev(rgb), dev(depth), cam,
+                               fgs.SeedOpts(opacity_logit=-0.5, use_prior=mode, prior=dev(w)), capacity=cap,
+                               params=part_p)
+        assert c["n"] == n
+        pc = host(part_p)[:, :n]
+        np.testing.assert_array_equal(host(c["from_prior"])[:n].astype(bool), used)
+        if mode == 2:
+            np.testing.assert_array_equal(pc[3:10], pb[3:10])
+            np.testing.assert_array_equal(pc[10], pa[10])
+        else:
+            np.testing.assert_array_equal(pc[3:10], pa[3:10])
+            np.testing.assert_array_equal(pc[10], pb[10])
 
 
 def test_learned_prior_reaches_the_plain_psnr_sooner(fgs, ctx):

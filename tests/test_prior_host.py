@@ -24,3 +24,11 @@ def test_summary_counts_failures_as_losses_and_needs_a_margin():
     assert s["ms_ratio_median"] == pytest.approx(0.995)
     assert s["prior_ms_mean"] == pytest.approx((8.0 + 9.95 + 11.0) / 3)
     assert s["plain_never_reached"] == 0
+
+
+def test_a_repeat_short_of_the_target_uses_the_median_spread():
+    rows = [row(0, 10.0, 9.0, 10.4), row(1, 10.0, 9.0, 10.2),  # spreads 0.4 and 0.2: median 0.3
+            row(2, 10.0, 9.8, None),   # 9.8 > 10 - 0.3: a loss
+            row(3, 10.0, 9.6, None)]   # 9.6 < 10 - 0.3: a win
+    s = prior.summarize(rows)
+    assert (s["wins"], s["losses"], s["repeat_short_of_target"]) == (3, 1, 2)
