@@ -44,8 +44,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "a84c0bf75d48f486d8d8792b01eb023c430275d23efb84518e0bbcd11d76aaa1",
-                     "tile": "16x16", "fetch_bytes": 46714745, "write_bytes": 16498766},
+    "k_raster_bwd": {"source_sha256": "13b5408d1f91f86552b20bfd503608d6ef73c13dbe02d53f3176cc66ce866e11",
+                     "tile": "16x16", "fetch_bytes": 46727117, "write_bytes": 16498766},
 }
 
 
@@ -76,13 +76,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the keyframe-window, seeding and learned-prior measurements")
+                    help="skip the small-scene latency, keyframe-window, full-loss, seeding and learned-prior "
+                         "measurements")
     ap.add_argument("--prior-train-scenes", type=int, default=50)
     ap.add_argument("--prior-test-scenes", type=int, default=20)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--oracle-job", default=None, help=argparse.SUPPRESS)  # child process of cpu_baseline
+    ap.add_argument("--full-loss-only", action="store_true",
+                    help="only run the full-loss (Eq. 16) mapping-step measurement, print its JSON object and exit")
     ap.add_argument("--window-only", action="store_true",
                     help="only run the 8-view keyframe window measurement (tuning, timed graph replays, "
                          "profiled steps), print its JSON object and exit")
@@ -548,6 +551,9 @@ def main():
     if args.window_only:
         print(json.dumps(window_extra(F, F.Context())), flush=True)
         return
+    if args.full_loss_only:
+        print(json.dumps(full_loss_extra(F, steps=20)), flush=True)
+        return
     if args.copy_calib:
         x = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -641,9 +647,9 @@ def main():
         "final_loss": float(loss), "final_psnr": float(psnr),
     }
     del params, adam, targets, tgt
-    line["c0_latency"] = c0_latency(F)
-    progress("c0 latency done")
     if not args.no_extras:
+        line["c0_latency"] = c0_latency(F)
+        progress("c0 latency done")
         # the extra measurements report their own failure in the line instead of losing it
         def extra(fn, *a):
             t0 = time.perf_counter()
