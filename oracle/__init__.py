@@ -123,6 +123,11 @@ def lib():
                                 C.c_double]
         L.fgso_ssim.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.fgso_scale_reg.argtypes = [C.c_int64, _dp, _dp, _dp]
+        L.fgso_prune_thresholds.argtypes = [C.c_double, C.c_double, _dp, _dp]
+        L.fgso_prune_keep.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _u8p]
+        L.fgso_prune_keep.restype = C.c_int64
+        L.fgso_compact.argtypes = [C.c_int64, C.c_int32, _dp, _u8p, _dp, C.c_int64]
+        L.fgso_compact.restype = C.c_int64
         L.fgso_highpass.argtypes = [C.c_int32, C.c_int32, _fp, C.c_double, _dp, _i64p, _i32p, _dp]
         L.fgso_triangle.argtypes = [_i64p]
         L.fgso_triangle.restype = C.c_int32
@@ -265,6 +270,43 @@ def scale_reg(log_scale):
     g = np.zeros_like(ls)
     _check(lib().fgso_scale_reg(ls.shape[1], _ptr(ls, _dp), C.byref(v), _ptr(g, _dp)), "scale_reg")
     return v.value, g
+
+
+def prune_thresholds(min_opacity, max_scale):
+    """(L_o, L_s): the pruning thresholds of Sec. III-D carried onto the opacity logit and the
+    log-scales, rounded to binary32 (-inf / +inf when a test is off)."""
+    lo, ls = C.c_double(), C.c_double()
+    _check(lib().fgso_prune_thresholds(float(min_opacity), float(max_scale), C.byref(lo), C.byref(ls)),
+           "prune_thresholds")
+    return lo.value, ls.value
+
+
+def prune_keep(params, min_opacity, max_scale):
+    """Keep mask (uint8, n) of the (14, n) block under the pruning test of Sec. III-D."""
+    p = _d(params)
+    n = p.shape[1]
+    keep = np.zeros(n, np.uint8)
+    k = lib().fgso_prune_keep(n, _ptr(p, _dp), float(min_opacity), float(max_scale), _ptr(keep, _u8p))
+    _check(k, "prune_keep")
+    return keep
+
+
+def compact(block, keep):
+    """Stable compaction of the (planes, n) block to its kept columns: (planes, kept)."""
+    b = _d(block)
+    planes, n = b.shape
+    kp = np.ascontiguousarray(keep, np.uint8)
+    kept = int(np.count_nonzero(kp))
+    out = np.zeros((planes, max(kept, 1)))
+    _check(lib().fgso_compact(n, planes, _ptr(b, _dp), _ptr(kp, _u8p), _ptr(out, _dp), out.shape[1]), "compact")
+    return out[:, :kept]
+
+
+def prune(params, min_opacity, max_scale, *companions):
+    """Pruning of Sec. III-D: (kept params (14, k), keep mask, compacted companions (e.g. Adam
+    moments of the same layout))."""
+    keep = prune_keep(params, min_opacity, max_scale)
+    return (compact(params, keep), keep) + tuple(compact(c, keep) for c in companions)
 
 
 def adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):

@@ -179,6 +179,19 @@ int fgso_mlp_fwd(int64_t rows, const double *x, const double *w, int bf16, doubl
 int fgso_mlp_bwd(int64_t rows, const double *x, const double *w, int bf16, const double *target,
                  double *gw, double *loss);
 
+/* ---------------------------------- Pruning ---------------------------------- */
+/* Thresholds of the pruning test (Sec. III-D) in the domains of the stored values: L_o on the
+ * opacity logit, L_s on each log-scale (binary32 values; -inf / +inf when a test is off).
+ * Returns -1 unless min_opacity is in [0, 1) and max_scale is not NaN. */
+int fgso_prune_thresholds(double min_opacity, double max_scale, double *L_o, double *L_s);
+/* keep[i] = 1 when gaussian i of the (14, n) block survives: logit >= L_o and every log-scale
+ * <= L_s. Returns the number kept (or < 0 on error). */
+int64_t fgso_prune_keep(int64_t n, const double *params, double min_opacity, double max_scale, uint8_t *keep);
+/* Stable compaction of `planes` planes of length n (stride n) to out (stride out_stride >= kept):
+ * the j-th kept index goes to position j. Returns the number kept. */
+int64_t fgso_compact(int64_t n, int32_t planes, const double *in, const uint8_t *keep, double *out,
+                     int64_t out_stride);
+
 #ifdef __cplusplus
 }
 #endif
