@@ -265,6 +265,29 @@ fgs_status fgs_adam_step(fgs_ctx *ctx, const fgs_gaussians *params, const fgs_ga
 
 /* ------------------------------------ keyframe window ------------------------------------ */
 
+/* [host] Pruning thresholds (Sec. III-D, "Gaussian Pruning": gaussians grown too large in any
+ * dimension and gaussians of low opacity are removed; the paper gives no values). A gaussian is
+ * removed when sigmoid(opacity logit) < min_opacity or when any of its three scales
+ * exp(log-scale) exceeds max_scale (world units). min_opacity in [0, 1) (0: no opacity test);
+ * max_scale <= 0 or +inf: no size test. The tests compare the stored values with the thresholds
+ * carried into their domains: a gaussian is kept when logit >= (float)log(min_opacity / (1 -
+ * min_opacity)) and every log-scale <= (float)log(max_scale), each threshold computed in double
+ * and rounded to float; a NaN logit or log-scale removes the gaussian. */
+typedef struct {
+    float min_opacity;
+    float max_scale;
+} fgs_prune_opts;
+
+/* Prunes src[0] (Sec. III-D) by stream compaction: the survivors are packed, in index order, into
+ * dst[0] at [0, kept), and the same columns of src[1 .. n_sets) (blocks of the same layout and n,
+ * such as the Adam moments m and v) into dst[1 .. n_sets). 1 <= n_sets <= 4. Each dst[k].stride
+ * must be at least src[0].n (dst[k].n is ignored); no destination block may overlap a source block
+ * or another destination. n_kept_dev (device int64, nullable) receives the survivor count; keep
+ * (device, src[0].n bytes, nullable) receives 1 for each survivor and 0 for each removed gaussian.
+ * n_kept_host [host] (nullable) waits for the stream and receives the count. */
+fgs_status fgs_prune(fgs_ctx *ctx, const fgs_prune_opts *o, int32_t n_sets, const fgs_gaussians *src,
+                     const fgs_gaussians *dst, int64_t *n_kept_dev, uint8_t *keep, int64_t *n_kept_host);
+
 typedef struct fgs_window fgs_window; /* opaque: per-view states, item counter, captured graph */
 
 /* A keyframe window (Sec. III-C, III-D: the co-visible and random keyframes optimised together)

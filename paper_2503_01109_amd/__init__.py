@@ -90,6 +90,10 @@ class CSeedOut(C.Structure):
                 ("threshold", _i32p), ("from_prior", C.POINTER(C.c_uint8)), ("missing", C.POINTER(C.c_uint8))]
 
 
+class CPruneOpts(C.Structure):
+    _fields_ = [("min_opacity", C.c_float), ("max_scale", C.c_float)]
+
+
 class CPriorAdam(C.Structure):
     _fields_ = [("m", _fp), ("v", _fp), ("step", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float)]
@@ -115,6 +119,8 @@ _sigs = {
     "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
     "fgs_ssim": [_vp, C.c_int32, C.c_int32, _fp, _fp, _fp, _fp],
     "fgs_adam_step": [_vp, _P(CGaussians), _P(CGaussians), _P(CAdam)],
+    "fgs_prune": [_vp, _P(CPruneOpts), C.c_int32, _P(CGaussians), _P(CGaussians), _P(C.c_int64), _P(C.c_uint8),
+                  _P(C.c_int64)],
     "fgs_ctx_profile": [_vp, C.c_int32],
     "fgs_ctx_profile_stage": [_vp, C.c_char_p, _P(C.c_double), _P(C.c_int64)],
     "fgs_ctx_profile_counts": [_vp, _P(C.c_int64)],
@@ -427,6 +433,41 @@ def adam_step(ctx: Context, params, grad, n: int, adam: Adam):
     _check(_lib.fgs_adam_step(ctx.handle, C.byref(gaussians(params, n)), C.byref(gaussians(grad, n)),
                               C.byref(ca)), ctx.handle)
     adam.step = ca.step
+
+
+@dataclass
+class PruneOpts:
+    """Pruning thresholds (Sec. III-D; see fgs_prune_opts): gaussians with opacity below
+    min_opacity or any scale above max_scale (world units; 0 = no size test) are removed."""
+    min_opacity: float = 0.005
+    max_scale: float = 0.0
+
+    def c(self) -> CPruneOpts:
+        return CPruneOpts(self.min_opacity, self.max_scale)
+
+
+def prune(ctx: Context, params, n: int, opts: PruneOpts | None = None, adam: Adam | None = None, keep=None,
+          n_kept=None, sync: bool = True):
+    """Prunes the first n gaussians of the (14, capacity) block `params` (Sec. III-D) into a new
+    block of the same capacity, and the Adam moments with them. Returns (params, n_kept, adam):
+    n_kept is an int when sync, else None (the count lands in the device int64 tensor n_kept when
+    given); the returned Adam keeps the step count. keep (optional uint8 device tensor of n
+    elements) receives 1 for survivors."""
+    import torch
+    blocks = [params] + ([adam.m, adam.v] if adam is not None else [])
+    # moments beyond the survivors start at zero, for gaussians a caller appends later
+    outs = [torch.empty_like(params)] + [torch.zeros_like(b) for b in blocks[1:]]
+    k = len(blocks)
+    src = (CGaussians * k)(*[gaussians(b, n) for b in blocks])
+    dst = (CGaussians * k)(*[gaussians(b, n) for b in outs])
+    host = C.c_int64(-1)
+    _check(_lib.fgs_prune(ctx.handle, C.byref((opts or PruneOpts()).c()), k, src, dst,
+                          _ptr(n_kept, C.POINTER(C.c_int64)), _ptr(keep, C.POINTER(C.c_uint8)),
+                          C.byref(host) if sync else None), ctx.handle)
+    new_adam = None
+    if adam is not None:
+        new_adam = Adam(outs[1], outs[2], step=adam.step, lr=adam.lr, beta1=adam.beta1, beta2=adam.beta2, eps=adam.eps)
+    return outs[0], (host.value if sync else None), new_adam
 
 
 def render(ctx: Context, params, n: int, cam, opts: RenderOpts | None = None, max_pairs: int | None = None,

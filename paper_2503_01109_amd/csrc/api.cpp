@@ -130,6 +130,7 @@ struct fgs_ctx {
     DBuf ms_state, ms_dl, ms_grad, ms_partials;
     DBuf ms_img, ms_ssim, ms_reg;  // rendered colour, per-tile SSIM sums, regulariser partials
     DBuf ssim_part, ssim_ws;       // SSIM: fgs_ssim's per-tile sums; the partials' workspace
+    DBuf prune_ws;                 // pruning: survivor total (int64), chunk counts and offsets
     DBuf seed_ws, seed_sc;
     // learned prior: network workspace (rows_cap rows) and per-frame tile buffers for seeding
     DBuf mlp_ws, prior_feat, prior_valid, prior_y;
@@ -1008,6 +1009,89 @@ fgs_status fgs_ssim(fgs_ctx *ctx, int32_t width, int32_t height, const float *im
         launch_sum_scaled(ctx->ssim_part.as<float>(), (int)T, 1.0 / (3.0 * (double)width * (double)height), ssim_dev,
                           ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+// Byte span [lo, hi) of the planes of a block of n gaussians.
+static void block_span(const fgs_gaussians &g, int64_t n, uintptr_t *lo, uintptr_t *hi)
+{
+    const float *planes[14];
+    for (int k = 0; k < 3; ++k) planes[k] = g.mean + k * g.stride;
+    for (int k = 0; k < 3; ++k) planes[3 + k] = g.log_scale + k * g.stride;
+    for (int k = 0; k < 4; ++k) planes[6 + k] = g.quat + k * g.stride;
+    planes[10] = g.opacity_logit;
+    for (int k = 0; k < 3; ++k) planes[11 + k] = g.rgb + k * g.stride;
+    *lo = UINTPTR_MAX;
+    *hi = 0;
+    for (const float *q : planes) {
+        const uintptr_t a = (uintptr_t)q, b = a + (uintptr_t)n * 4;
+        if (a < *lo) *lo = a;
+        if (b > *hi) *hi = b;
+    }
+}
+
+fgs_status fgs_prune(fgs_ctx *ctx, const fgs_prune_opts *o, int32_t n_sets, const fgs_gaussians *src,
+                     const fgs_gaussians *dst, int64_t *n_kept_dev, uint8_t *keep, int64_t *n_kept_host)
+{
+    const char *w = "fgs_prune";
+    if (!o) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: options are NULL", w);
+    if (n_sets < 1 || n_sets > kPruneSets || !src || !dst)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n_sets must be in [1, %d] with src and dst given", w, kPruneSets);
+    if (!(o->min_opacity >= 0.0f && o->min_opacity < 1.0f))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: min_opacity must be in [0, 1)", w);
+    if (std::isnan(o->max_scale)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: max_scale is NaN", w);
+    fgs_status st;
+    const int64_t n = src[0].n;
+    for (int k = 0; k < n_sets; ++k) {
+        if ((st = check_gauss(ctx, &src[k], w, "src")) != FGS_OK) return st;
+        if (src[k].n != n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: src[%d].n != src[0].n", w, k);
+        if (dst[k].stride < n) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: dst[%d].stride < n", w, k);
+        if (n > 0 && (!dst[k].mean || !dst[k].log_scale || !dst[k].quat || !dst[k].opacity_logit || !dst[k].rgb))
+            return fail(ctx, FGS_ERR_INVALID_ARG, "%s: dst[%d] has a NULL plane", w, k);
+    }
+    if (n > 0) {
+        uintptr_t lo[2 * kPruneSets], hi[2 * kPruneSets];
+        for (int k = 0; k < n_sets; ++k) {
+            block_span(src[k], n, &lo[k], &hi[k]);
+            block_span(dst[k], n, &lo[n_sets + k], &hi[n_sets + k]);
+        }
+        for (int a = n_sets; a < 2 * n_sets; ++a)  // each destination against every other block
+            for (int b = 0; b < 2 * n_sets; ++b)
+                if (a != b && lo[a] < hi[b] && lo[b] < hi[a])
+                    return fail(ctx, FGS_ERR_INVALID_ARG, "%s: dst[%d] overlaps %s[%d]", w, a - n_sets,
+                                b < n_sets ? "src" : "dst", b < n_sets ? b : b - n_sets);
+    }
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    PruneK pk{};
+    pk.n = n;
+    const double tau = (double)o->min_opacity, smax = (double)o->max_scale;
+    pk.L_o = tau > 0.0 ? (float)log(tau / (1.0 - tau)) : -INFINITY;
+    pk.L_s = (smax > 0.0 && std::isfinite(smax)) ? (float)log(smax) : INFINITY;
+    pk.n_sets = n_sets;
+    for (int k = 0; k < n_sets; ++k) {
+        pk.src[k] = to_pk(src[k]);
+        pk.dst[k] = to_gk(dst[k]);
+    }
+    pk.keep = keep;
+    const int64_t nb = prune_chunks(n);
+    const size_t need = 256 + align256((size_t)nb * 4) * 2;
+    if (need > ctx->prune_ws.bytes) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, ctx->prune_ws.ensure(need));
+    }
+    int64_t *total = ctx->prune_ws.as<int64_t>();
+    uint32_t *cnt = ctx->prune_ws.as<uint32_t>(256), *off = ctx->prune_ws.as<uint32_t>(256 + align256((size_t)nb * 4));
+    {
+        Stage st_(ctx, "prune");
+        launch_prune(pk, cnt, off, total, n_kept_dev, ctx->stream);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (n_kept_host) {
+        int64_t v = -1;
+        HIP_TRY(ctx, hipMemcpyAsync(&v, total, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        *n_kept_host = v;
+    }
     return FGS_OK;
 }
 

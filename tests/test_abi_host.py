@@ -46,7 +46,7 @@ int main(void) {
   S(fgs_gaussians) O(fgs_gaussians, rgb)
   S(fgs_render_opts) O(fgs_render_opts, bg) O(fgs_render_opts, tile_h)
   S(fgs_image) S(fgs_adam) O(fgs_adam, step) O(fgs_adam, lr) O(fgs_adam, eps)
-  S(fgs_target) S(fgs_loss_opts)
+  S(fgs_target) S(fgs_loss_opts) S(fgs_prune_opts) O(fgs_prune_opts, max_scale)
   S(fgs_prior_adam) O(fgs_prior_adam, step) O(fgs_prior_adam, eps)
   %EXTRA%
   return 0;
@@ -74,6 +74,7 @@ def test_struct_layouts_match_header(tmp_path):
         "fgs_image": C.sizeof(F.CImage), "fgs_adam": C.sizeof(F.CAdam), "fgs_adam.step": F.CAdam.step.offset,
         "fgs_adam.lr": F.CAdam.lr.offset, "fgs_adam.eps": F.CAdam.eps.offset,
         "fgs_target": C.sizeof(F.CTarget), "fgs_loss_opts": C.sizeof(F.CLossOpts),
+        "fgs_prune_opts": C.sizeof(F.CPruneOpts), "fgs_prune_opts.max_scale": F.CPruneOpts.max_scale.offset,
         "fgs_prior_adam": C.sizeof(F.CPriorAdam), "fgs_prior_adam.step": F.CPriorAdam.step.offset,
         "fgs_prior_adam.eps": F.CPriorAdam.eps.offset,
     }
@@ -238,3 +239,43 @@ def test_noalloc_backward_rejects_more_gaussians_than_its_scratch_on_host():
     st = F._lib.fgs_render_bwd_noalloc(None, C.byref(g), C.byref(F.camera(_cam())), C.byref(F.RenderOpts().c()),
                                       C.c_void_p(0x2000), 1 << 30, d, d, None, C.byref(g))
     assert st == F.ERR_INVALID_ARG and "ctx is NULL" in F.last_error()
+
+
+def test_prune_rejects_bad_arguments_on_host():
+    def block(base, n, stride):
+        g = F.CGaussians()
+        g.n, g.stride = n, stride
+        f = lambda k: C.cast(C.c_void_p(base + 4 * k * stride), C.POINTER(C.c_float))
+        g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb = f(0), f(3), f(6), f(10), f(11)
+        return g
+
+    def call(opts, src, dst, n_sets=None):
+        k = len(src) if n_sets is None else n_sets
+        a = (F.CGaussians * max(len(src), 1))(*src)
+        b = (F.CGaussians * max(len(dst), 1))(*dst)
+        st = F._lib.fgs_prune(None, C.byref(opts), k, a, b, None, None, None)
+        return st, F.last_error()
+
+    ok = F.CPruneOpts(0.005, 0.5)
+    A, B, M, Mo = 0x100000, 0x200000, 0x300000, 0x400000
+    n = 1000
+    assert call(ok, [block(A, n, n)], [block(B, n, n)]) == (F.ERR_INVALID_ARG, "fgs_prune: ctx is NULL")
+    for bad in (F.CPruneOpts(1.0, 0.5), F.CPruneOpts(-0.1, 0.5), F.CPruneOpts(float("nan"), 0.5)):
+        st, msg = call(bad, [block(A, n, n)], [block(B, n, n)])
+        assert st == F.ERR_INVALID_ARG and "min_opacity" in msg
+    st, msg = call(F.CPruneOpts(0.005, float("nan")), [block(A, n, n)], [block(B, n, n)])
+    assert st == F.ERR_INVALID_ARG and "max_scale" in msg
+    assert call(ok, [block(A, n, n)], [block(B, n, n)], n_sets=0)[0] == F.ERR_INVALID_ARG
+    assert call(ok, [block(A, n, n)] * 5, [block(B, n, n)] * 5)[0] == F.ERR_INVALID_ARG
+    st, msg = call(ok, [block(A, n, n)], [block(B, n, n - 1)])
+    assert st == F.ERR_INVALID_ARG and "stride" in msg
+    st, msg = call(ok, [block(A, n, n), block(M, n - 1, n)], [block(B, n, n), block(Mo, n, n)])
+    assert st == F.ERR_INVALID_ARG and "src[1].n" in msg
+    # a destination overlapping a source, or another destination
+    st, msg = call(ok, [block(A, n, n)], [block(A + 4 * 13 * n, n, n)])
+    assert st == F.ERR_INVALID_ARG and "overlaps src[0]" in msg
+    st, msg = call(ok, [block(A, n, n), block(M, n, n)], [block(B, n, n), block(B + 8, n, n)])
+    assert st == F.ERR_INVALID_ARG and "overlaps dst" in msg
+    # disjoint blocks pass every check before the context's
+    assert call(ok, [block(A, n, n), block(M, n, n)], [block(B, n, n), block(Mo, n, n)]) == (
+        F.ERR_INVALID_ARG, "fgs_prune: ctx is NULL")

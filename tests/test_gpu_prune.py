@@ -1,0 +1,182 @@
+"""Pruning (Sec. III-D, "Gaussian Pruning") on the GPU against the oracle: the keep decisions, the
+survivor count and the compacted planes of the parameters and of their companion blocks (the Adam
+moments) are bit-exact, from a few gaussians through several 2048-gaussian chunks with a ragged
+tail to the 300k and 500k maps of the benchmark scenes; with input and output strides wider than
+n; with every gaussian kept, none kept, and none at all."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+TAU, SMAX = 0.005, 0.5
+
+
+@pytest.fixture(scope="module")
+def fgs():
+    need_gpu()
+    import paper_2503_01109_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fgs):
+    c = fgs.Context()
+    yield c
+    c.close()
+
+
+def map_block(n, seed):
+    """Parameters of a map after some optimisation: logits N(-3, 3) (a quarter below the 0.005
+    opacity threshold), log-scales N(-2.5, 1) (about a tenth of the gaussians have an axis above
+    0.5 m), a few NaN logits and log-scales."""
+    g = synth.rng(seed)
+    p = g.normal(size=(14, n)).astype(np.float32)
+    p[10] = g.normal(-3.0, 3.0, n)
+    p[3:6] = g.normal(-2.5, 1.0, (3, n))
+    if n >= 100:
+        p[10, g.choice(n, n // 100, replace=False)] = np.nan
+        p[3 + g.integers(0, 3), g.choice(n, n // 100, replace=False)] = np.nan
+    return p
+
+
+def bits(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32)).view(np.uint32)
+
+
+def check(fgs, ctx, p, m, v, cap_in=None, cap_out=None, tau=TAU, smax=SMAX):
+    """Runs fgs_prune through the C ABI on (params, m, v) held in blocks of capacity cap_in and
+    cap_out, and compares everything with the oracle."""
+    import torch
+    n = p.shape[1]
+    cap_in = cap_in or max(n, 1)
+    cap_out = cap_out or max(n, 1)
+    blocks = []
+    for a in (p, m, v):
+        b = np.full((14, cap_in), 7.0, np.float32)
+        b[:, :n] = a
+        blocks.append(dev(b))
+    outs = [torch.full((14, cap_out), -1.0, device="cuda") for _ in range(3)]
+    src = (fgs.CGaussians * 3)(*[fgs.gaussians(b, n) for b in blocks])
+    dst = (fgs.CGaussians * 3)(*[fgs.gaussians(b, n) for b in outs])
+    keep = torch.full((max(n, 1),), 9, dtype=torch.uint8, device="cuda")
+    kdev = torch.full((1,), -5, dtype=torch.int64, device="cuda")
+    khost = C.c_int64(-7)
+    st = fgs._lib.fgs_prune(ctx.handle, C.byref(fgs.PruneOpts(tau, smax).c()), 3, src, dst,
+                            C.cast(C.c_void_p(kdev.data_ptr()), C.POINTER(C.c_int64)),
+                            C.cast(C.c_void_p(keep.data_ptr()), C.POINTER(C.c_uint8)), C.byref(khost))
+    assert st == fgs.OK, fgs.last_error(ctx.handle)
+    ctx.check()
+    ref_p, ref_keep, ref_m, ref_v = oracle.prune(p.astype(np.float64), tau, smax, m.astype(np.float64),
+                                                 v.astype(np.float64))
+    k = int(ref_keep.sum())
+    assert khost.value == k and int(kdev.item()) == k
+    np.testing.assert_array_equal(host(keep)[:n], ref_keep)
+    for got, ref, what in zip(outs, (ref_p, ref_m, ref_v), ("params", "m", "v")):
+        g = host(got)
+        assert np.array_equal(bits(g[:, :k]), bits(ref)), what
+        assert (g[:, k:] == -1.0).all(), f"{what}: written past the survivors"
+    return k
+
+
+@pytest.mark.parametrize("n", [1, 63, 2047, 2048, 2049, 5003, 40_000])
+def test_prune_matches_oracle(fgs, ctx, n):
+    g = synth.rng(100 + n)
+    p = map_block(n, n)
+    m, v = g.normal(size=(14, n)).astype(np.float32), g.uniform(size=(14, n)).astype(np.float32)
+    k = check(fgs, ctx, p, m, v)
+    print(f"prune n={n}: kept {k}")
+    if n >= 2047:
+        assert 0.5 * n < k < 0.8 * n
+
+
+def test_prune_with_wider_strides(fgs, ctx):
+    n = 7000
+    p = map_block(n, 3)
+    g = synth.rng(4)
+    check(fgs, ctx, p, g.normal(size=(14, n)).astype(np.float32), g.normal(size=(14, n)).astype(np.float32),
+          cap_in=9001, cap_out=12345)
+
+
+@pytest.mark.parametrize("n", [300_000, 500_000])
+def test_prune_at_benchmark_map_sizes(fgs, ctx, n):
+    """The 300k scene of the splatting workload and the 500k scene of the keyframe window, with
+    the spread of opacities of an optimised map."""
+    p = (synth.scene_replica(0) if n == 300_000 else synth.scene_window(0)).astype(np.float32)
+    g = synth.rng(6)
+    p[10] = g.normal(-3.0, 3.0, n)
+    k = check(fgs, ctx, p, g.normal(size=(14, n)).astype(np.float32), g.uniform(size=(14, n)).astype(np.float32))
+    print(f"prune n={n}: kept {k}")
+
+
+def test_prune_all_kept_none_kept_and_empty(fgs, ctx):
+    n = 4100
+    p = map_block(n, 7)
+    p[10] = 4.0
+    p[3:6] = -3.0
+    z = np.zeros((14, n), np.float32)
+    assert check(fgs, ctx, p, z + 1, z + 2) == n
+    p[10] = -8.0
+    assert check(fgs, ctx, p, z + 1, z + 2) == 0
+    assert check(fgs, ctx, np.zeros((14, 0), np.float32), np.zeros((14, 0), np.float32),
+                 np.zeros((14, 0), np.float32)) == 0
+
+
+def test_prune_with_tests_off(fgs, ctx):
+    """min_opacity 0 and no size bound: only the gaussians with a NaN in the tested values go."""
+    n = 3000
+    p = map_block(n, 8)
+    z = np.zeros((14, n), np.float32)
+    k = check(fgs, ctx, p, z, z, tau=0.0, smax=0.0)
+    assert k == n - int((np.isnan(p[10]) | np.isnan(p[3:6]).any(0)).sum())
+
+
+def test_python_prune_carries_adam_and_leaves_zero_moments_past_the_survivors(fgs, ctx):
+    import torch
+    n, cap = 6000, 8000
+    p = np.zeros((14, cap), np.float32)
+    p[:, :n] = map_block(n, 9)
+    g = synth.rng(10)
+    pd = dev(p)
+    adam = fgs.Adam(dev(g.normal(size=(14, cap)).astype(np.float32)), dev(g.uniform(size=(14, cap)).astype(np.float32)),
+                    step=17)
+    keep = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    q, k, a2 = fgs.prune(ctx, pd, n, fgs.PruneOpts(TAU, SMAX), adam=adam, keep=keep)
+    ref_p, ref_keep, ref_m, ref_v = oracle.prune(p[:, :n].astype(np.float64), TAU, SMAX,
+                                                 host(adam.m)[:, :n].astype(np.float64),
+                                                 host(adam.v)[:, :n].astype(np.float64))
+    assert k == int(ref_keep.sum()) and q.shape == (14, cap) and a2.step == 17
+    np.testing.assert_array_equal(host(keep), ref_keep)
+    assert np.array_equal(bits(host(q)[:, :k]), bits(ref_p))
+    assert np.array_equal(bits(host(a2.m)[:, :k]), bits(ref_m))
+    assert np.array_equal(bits(host(a2.v)[:, :k]), bits(ref_v))
+    assert (host(a2.m)[:, k:] == 0).all() and (host(a2.v)[:, k:] == 0).all()
+    # the count on the device without waiting
+    kd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _, none, _ = fgs.prune(ctx, pd, n, fgs.PruneOpts(TAU, SMAX), n_kept=kd, sync=False)
+    assert none is None and int(kd.item()) == k
+
+
+def test_four_sets(fgs, ctx):
+    import torch
+    n = 2500
+    p = map_block(n, 11)
+    g = synth.rng(12)
+    comp = [g.normal(size=(14, n)).astype(np.float32) for _ in range(3)]
+    srcb = [dev(p)] + [dev(c) for c in comp]
+    outs = [torch.zeros((14, n), device="cuda") for _ in range(4)]
+    src = (fgs.CGaussians * 4)(*[fgs.gaussians(b, n) for b in srcb])
+    dst = (fgs.CGaussians * 4)(*[fgs.gaussians(b, n) for b in outs])
+    kh = C.c_int64(-1)
+    assert fgs._lib.fgs_prune(ctx.handle, C.byref(fgs.PruneOpts(TAU, SMAX).c()), 4, src, dst, None, None,
+                              C.byref(kh)) == fgs.OK
+    ref = oracle.prune(p.astype(np.float64), TAU, SMAX, *[c.astype(np.float64) for c in comp])
+    k = int(ref[1].sum())
+    assert kh.value == k
+    for o, r in zip(outs, (ref[0],) + ref[2:]):
+        assert np.array_equal(bits(host(o)[:, :k]), bits(r))
