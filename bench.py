@@ -76,9 +76,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the small-scene latency, keyframe-window, full-loss, seeding and learned-prior "
-                         "measurements")
+                    help="skip the small-scene latency, keyframe-window, full-loss, seeding, pruning, "
+                         "densification-ablation and learned-prior measurements")
     ap.add_argument("--prior-train-scenes", type=int, default=50)
+    ap.add_argument("--densify-scenes", type=int, default=10)
     ap.add_argument("--prior-test-scenes", type=int, default=20)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain elementwise copy of MB mebibytes 5 times (the reference kernel for "
@@ -86,6 +87,10 @@ def parse():
     ap.add_argument("--oracle-job", default=None, help=argparse.SUPPRESS)  # child process of cpu_baseline
     ap.add_argument("--full-loss-only", action="store_true",
                     help="only run the full-loss (Eq. 16) mapping-step measurement, print its JSON object and exit")
+    ap.add_argument("--prune-only", action="store_true",
+                    help="only run the pruning measurement, print its JSON object and exit")
+    ap.add_argument("--densify-only", action="store_true",
+                    help="only run the densification ablation, print its JSON object and exit")
     ap.add_argument("--window-only", action="store_true",
                     help="only run the 8-view keyframe window measurement (tuning, timed graph replays, "
                          "profiled steps), print its JSON object and exit")
@@ -505,6 +510,69 @@ def seeding_extra(F, ctx, iters: int = 200, reps: int = 20) -> dict:
                               "missing_pixels": int(again["missing"].sum().item())}}
 
 
+def prune_bytes(n: int, kept: int, sets: int) -> int:
+    """Algorithmic HBM bytes of one pruning call: the keep test reads the logit and three
+    log-scales of every gaussian (16 n); each survivor's other planes are read (56 sets - 16) and
+    all its planes written (56 sets)."""
+    return 16 * n + (112 * sets - 16) * kept
+
+
+def prune_extra(F, ctx, reps: int = 50) -> dict:
+    """Pruning (Sec. III-D) of the 500k-gaussian window scene with the opacity spread of an
+    optimised map (logits N(-3, 3)), with its Adam moments (3 blocks), thresholds opacity 0.005 and
+    scale 0.5 m; device time per call and the fraction of HBM bandwidth its algorithmic bytes take."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    import synth
+    p = synth.scene_window(0).astype(np.float32)
+    g = np.random.default_rng(6)
+    p[10] = g.normal(-3.0, 3.0, p.shape[1])
+    n = p.shape[1]
+    blocks = [torch.as_tensor(p).cuda().contiguous(),
+              torch.as_tensor(g.normal(size=(14, n)).astype(np.float32)).cuda(),
+              torch.as_tensor(g.uniform(size=(14, n)).astype(np.float32)).cuda()]
+    outs = [torch.empty_like(b) for b in blocks]
+    src = (F.CGaussians * 3)(*[F.gaussians(b, n) for b in blocks])
+    dst = (F.CGaussians * 3)(*[F.gaussians(b, n) for b in outs])
+    kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    opts = F.PruneOpts(0.005, 0.5).c()
+    kptr = C.cast(C.c_void_p(kdev.data_ptr()), C.POINTER(C.c_int64))
+    call = lambda: F._lib.fgs_prune(ctx.handle, C.byref(opts), 3, src, dst, kptr, None, None)
+    for _ in range(5):
+        assert call() == F.OK, F.last_error(ctx.handle)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for k in range(reps):
+        call()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    ctx.check()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+    kept = int(kdev.item())
+    b = prune_bytes(n, kept, 3)
+    us = float(np.median(per)) * 1e3
+    return {"workload": "prune 500k gaussians with their Adam moments (opacity < 0.005 or a scale > 0.5 m)",
+            "n": n, "kept": kept, "us_per_call_median": round(us, 2), "algorithmic_bytes": b,
+            "achieved_GBs": round(b / (us * 1e-6) / 1e9, 1), "frac_hbm": round(b / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 3)}
+
+
+def densify_extra(F, ctx, scenes: int) -> dict:
+    """The synthetic analogue of Table 6: sparse / dense equidistant seeding with large / small
+    gaussians against the adaptive seeding, on `scenes` 640x480 frames (2000, 2001, ...), 200
+    mapping iterations each with pruning every 50."""
+    from paper_2503_01109_amd import densify
+    r = densify.run(F, ctx, range(2000, 2000 + scenes), iters=200, prune_every=50, log=progress)
+    rnd = lambda v: round(v, 4) if isinstance(v, float) else v
+    return {"workload": "seed a 640x480 synthetic RGB-D frame, 200 mapping iterations (L1 colour + depth), "
+                        "prune (opacity < 0.005, scale > 0.25 m) every 50; initial opacity 0.9",
+            "scenes": scenes, "variants": {v: {k: rnd(x) for k, x in d.items()} for v, d in r["summary"].items()}}
+
+
 def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
     """Learned prior: trained on 100 tiles of each of the converged maps of frames 0..n_train-1,
     compared with the plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on the held-out frames
@@ -553,6 +621,12 @@ def main():
         return
     if args.full_loss_only:
         print(json.dumps(full_loss_extra(F, steps=20)), flush=True)
+        return
+    if args.prune_only:
+        print(json.dumps(prune_extra(F, F.Context())), flush=True)
+        return
+    if args.densify_only:
+        print(json.dumps(densify_extra(F, F.Context(), args.densify_scenes)), flush=True)
         return
     if args.copy_calib:
         x = torch.ones(args.copy_calib * (1 << 18), dtype=torch.float32, device="cuda")
@@ -662,6 +736,8 @@ def main():
         line["window"] = extra(window_extra, F, ctx)
         line["full_loss"] = extra(full_loss_extra, F)
         line["seeding"] = extra(seeding_extra, F, ctx)
+        line["prune"] = extra(prune_extra, F, ctx)
+        line["densification_ablation"] = extra(densify_extra, F, ctx, args.densify_scenes)
         pr = extra(prior_extra, F, ctx, args.prior_train_scenes, args.prior_test_scenes)
         line["learned_prior"] = pr
         if "error" not in pr:

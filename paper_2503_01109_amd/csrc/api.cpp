@@ -1067,23 +1067,35 @@ fgs_status fgs_prune(fgs_ctx *ctx, const fgs_prune_opts *o, int32_t n_sets, cons
     const double tau = (double)o->min_opacity, smax = (double)o->max_scale;
     pk.L_o = tau > 0.0 ? (float)log(tau / (1.0 - tau)) : -INFINITY;
     pk.L_s = (smax > 0.0 && std::isfinite(smax)) ? (float)log(smax) : INFINITY;
-    pk.n_sets = n_sets;
+    pk.logit = src[0].opacity_logit;
+    pk.ls0 = src[0].log_scale;
+    pk.ls1 = src[0].log_scale + src[0].stride;
+    pk.ls2 = src[0].log_scale + 2 * src[0].stride;
+    pk.n_planes = 14 * n_sets;
     for (int k = 0; k < n_sets; ++k) {
-        pk.src[k] = to_pk(src[k]);
-        pk.dst[k] = to_gk(dst[k]);
+        const fgs_gaussians &a = src[k], &b = dst[k];
+        const float *sp[14] = {a.mean, a.mean + a.stride, a.mean + 2 * a.stride, a.log_scale,
+                               a.log_scale + a.stride, a.log_scale + 2 * a.stride, a.quat, a.quat + a.stride,
+                               a.quat + 2 * a.stride, a.quat + 3 * a.stride, a.opacity_logit, a.rgb,
+                               a.rgb + a.stride, a.rgb + 2 * a.stride};
+        float *dp[14] = {b.mean, b.mean + b.stride, b.mean + 2 * b.stride, b.log_scale, b.log_scale + b.stride,
+                         b.log_scale + 2 * b.stride, b.quat, b.quat + b.stride, b.quat + 2 * b.stride,
+                         b.quat + 3 * b.stride, b.opacity_logit, b.rgb, b.rgb + b.stride, b.rgb + 2 * b.stride};
+        for (int j = 0; j < 14; ++j) {
+            pk.src[14 * k + j] = sp[j];
+            pk.dst[14 * k + j] = dp[j];
+        }
     }
     pk.keep = keep;
-    const int64_t nb = prune_chunks(n);
-    const size_t need = 256 + align256((size_t)nb * 4) * 2;
+    const size_t need = 256 + (size_t)prune_ws_words(n) * 4;
     if (need > ctx->prune_ws.bytes) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         HIP_TRY(ctx, ctx->prune_ws.ensure(need));
     }
     int64_t *total = ctx->prune_ws.as<int64_t>();
-    uint32_t *cnt = ctx->prune_ws.as<uint32_t>(256), *off = ctx->prune_ws.as<uint32_t>(256 + align256((size_t)nb * 4));
     {
         Stage st_(ctx, "prune");
-        launch_prune(pk, cnt, off, total, n_kept_dev, ctx->stream);
+        launch_prune(pk, ctx->prune_ws.as<uint32_t>(256), total, n_kept_dev, ctx->stream);
     }
     HIP_TRY(ctx, hipGetLastError());
     if (n_kept_host) {

@@ -339,23 +339,25 @@ void launch_adam(const GradK &p, const ParamsK &g, const GradK &m, const GradK &
 
 // *step += 1 on the device unless *skip (nullable) is non-zero (the Adam step counter a captured
 // window step reads and advances; an overflowed step leaves it unchanged).
-// Pruning (prune.hip): survivors have logit >= L_o and every log-scale <= L_s in src[0]; their
-// columns of src[0 .. n_sets) are packed in index order into dst[0 .. n_sets) (which must not
-// overlap the sources). keep (nullable): one byte per gaussian.
-constexpr int kPruneSets = 4;
+// Pruning (prune.hip): survivors have logit >= L_o and every log-scale <= L_s in the test planes;
+// their columns of the n_planes source planes are packed in index order into the destination
+// planes (which must not overlap the sources). keep (nullable): one byte per gaussian.
+constexpr int kPruneSets = 4, kPrunePlanes = 14 * kPruneSets;
 struct PruneK {
     int64_t n;
     float L_o, L_s;
-    int32_t n_sets;
-    ParamsK src[kPruneSets];
-    GradK dst[kPruneSets];
+    const float *logit, *ls0, *ls1, *ls2;  // the test planes
+    int32_t n_planes;
+    const float *src[kPrunePlanes];
+    float *dst[kPrunePlanes];
     uint8_t *keep;
 };
 int64_t prune_chunks(int64_t n);
-// chunk_count, chunk_off: prune_chunks(n) words each; total: the survivor count (int64, device),
-// also written to total_out when that is not null.
-void launch_prune(const PruneK &k, uint32_t *chunk_count, uint32_t *chunk_off, int64_t *total, int64_t *total_out,
-                  hipStream_t s);
+// Workspace of launch_prune in 32-bit words for n gaussians.
+int64_t prune_ws_words(int64_t n);
+// ws: prune_ws_words(n) words (256-byte aligned); total: the survivor count (int64, device), also
+// written to total_out when that is not null.
+void launch_prune(const PruneK &k, uint32_t *ws, int64_t *total, int64_t *total_out, hipStream_t s);
 void launch_step_advance(int64_t *step, const uint32_t *skip, hipStream_t s);
 
 }  // namespace fgs

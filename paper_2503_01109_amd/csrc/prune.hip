@@ -2,18 +2,23 @@
 //
 // A gaussian survives when its opacity logit is at least L_o and each of its three log-scales is
 // at most L_s (the opacity and size thresholds carried into the stored values' domains on the
-// host; a NaN fails its comparison). Survivors are packed in index order into the output planes,
-// together with the same columns of up to three companion blocks of the same layout (the Adam
-// moments).
+// host; a NaN fails its comparison). Survivors are packed in index order into the output planes:
+// the 14 planes of the parameters and the same columns of up to three companion blocks of the
+// same layout (the Adam moments).
 //
-// Three launches over chunks of kChunk = 2048 gaussians per 256-thread workgroup; element k of a
-// thread is chunk + k * 256 + thread, so every plane is read in whole 1 KiB rows per wave:
-//   k_prune_count:   the keep test, and the chunk's survivor count (wave ballots);
-//   k_prune_offsets: one workgroup scans the chunk counts into exclusive offsets and the total;
-//   k_prune_scatter: the keep test again (the same arithmetic, so the same answer), each
-//     survivor's rank inside its chunk from the ballots, and the copy of its columns.
-// The test reads 16 bytes per gaussian and the copy moves 56 bytes per plane block and survivor
-// each way; the scan touches 8 bytes per chunk.
+// Gaussians are taken in chunks of kChunk = 2048 (256 threads x 8 rounds; element r of a thread
+// is chunk + r * 256 + thread, so every plane is read in whole 1 KiB rows per wave). Two or three
+// launches:
+//   k_prune_count:   the keep test; per chunk, the 32 wave ballots and the survivor count;
+//   k_prune_offsets: one workgroup scans the chunk counts into exclusive offsets and the total
+//     (maps above kFoldChunks chunks; below, each scatter workgroup sums the counts before its
+//     chunk itself, which saves a launch);
+//   k_prune_scatter: one workgroup per (chunk, group of kGroup planes): a survivor's position is
+//     its chunk's offset plus the survivors of the earlier ballots and of the lower lanes of its
+//     own; every thread loads its survivors of all the group's planes before it stores any, so
+//     each wave keeps up to 56 loads in flight (the copy is bound by HBM latency otherwise: a
+//     500k-gaussian map gives only some 1,000 waves per plane group).
+// The test reads 16 bytes per gaussian; the copy reads and writes 56 bytes per block and survivor.
 #include "fgs_internal.h"
 
 namespace fgs {
@@ -22,43 +27,45 @@ namespace {
 
 constexpr int kThreads = 256, kRounds = 8, kChunk = kThreads * kRounds;
 constexpr int kWavesPB = kThreads / kWave;
+constexpr int kSlots = kChunk / kWave;      // ballots of a chunk: slot q holds elements 64 q .. 64 q + 63
+constexpr int kCountThreads = 1024;
+constexpr int kGroup = 7;                   // planes per scatter workgroup
 constexpr int kScanThreads = 1024;
+constexpr int64_t kFoldChunks = 4096;       // chunks whose offsets the scatter sums itself (8M gaussians)
 
-__device__ inline bool keep_of(const PruneK &k, int64_t i)
+// One 1024-thread workgroup per chunk, two elements per thread, so that the test's loads of a
+// chunk are spread over 16 waves. Ballot slot q of a chunk holds its elements 64 q .. 64 q + 63,
+// whatever the workgroup shape that computes it.
+__global__ void __launch_bounds__(kCountThreads)
+k_prune_count(PruneK k, uint64_t *__restrict__ ballots, uint32_t *__restrict__ chunk_count)
 {
-    const float *ls = k.src[0].log_scale;
-    const int64_t s = k.src[0].stride;
-    return k.src[0].logit[i] >= k.L_o && ls[i] <= k.L_s && ls[s + i] <= k.L_s && ls[2 * s + i] <= k.L_s;
-}
-
-// Ballots of the chunk's kRounds rounds for this wave, and the survivors in each (round, wave)
-// slot written to cnt.
-__device__ inline void chunk_ballots(const PruneK &k, int64_t base, uint64_t (&bal)[kRounds], uint8_t *keep_out,
-                                     uint32_t (*cnt)[kWavesPB])
-{
+    constexpr int kR = kChunk / kCountThreads, kW = kCountThreads / kWave;
+    __shared__ uint32_t wcount[kW];
     const int tid = threadIdx.x, w = tid / kWave;
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kThreads + tid;
-        const bool ok = i < k.n && keep_of(k, i);
-        bal[r] = __ballot(ok);
-        if (keep_out && i < k.n) keep_out[i] = ok ? 1 : 0;
-        if (__lane_id() == 0) cnt[r][w] = (uint32_t)__popcll(bal[r]);
-    }
-}
-
-__global__ void __launch_bounds__(kThreads) k_prune_count(PruneK k, uint32_t *chunk_count)
-{
-    __shared__ uint32_t cnt[kRounds][kWavesPB];
-    uint64_t bal[kRounds];
     const int64_t base = (int64_t)blockIdx.x * kChunk;
-    chunk_ballots(k, base, bal, k.keep, cnt);
+    uint32_t ok = 0;  // bit r: element of round r survives
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int64_t i = base + (int64_t)r * kCountThreads + tid;
+        if (i < k.n && k.logit[i] >= k.L_o && k.ls0[i] <= k.L_s && k.ls1[i] <= k.L_s && k.ls2[i] <= k.L_s)
+            ok |= 1u << r;
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const uint64_t b = __ballot((ok >> r) & 1u);
+        c += (uint32_t)__popcll(b);
+        if (__lane_id() == 0) ballots[(int64_t)blockIdx.x * kSlots + r * kW + w] = b;
+        const int64_t i = base + (int64_t)r * kCountThreads + tid;
+        if (k.keep && i < k.n) k.keep[i] = (uint8_t)((ok >> r) & 1u);
+    }
+    if (__lane_id() == 0) wcount[w] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int r = 0; r < kRounds; ++r)
-            for (int w = 0; w < kWavesPB; ++w) t += cnt[r][w];
-        chunk_count[blockIdx.x] = t;
+    if (tid < kWave) {
+        uint32_t t = tid < kW ? wcount[tid] : 0u;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (tid == 0) chunk_count[blockIdx.x] = t;
     }
 }
 
@@ -96,58 +103,75 @@ k_prune_offsets(const uint32_t *chunk_count, int64_t nb, uint32_t *chunk_off, in
     }
 }
 
-__device__ inline void copy_plane(const float *src, float *dst, int64_t base, int64_t off,
-                                  const uint64_t (&bal)[kRounds], const uint32_t (&rank0)[kRounds], int64_t n)
+// Offset of chunk b: the sum of the counts of the chunks before it, summed by the whole workgroup
+// (up to kFoldChunks chunks: 16 loads per thread from L2). The workgroup of the last chunk's first
+// plane group also writes the total.
+__device__ uint32_t fold_offset(const uint32_t *__restrict__ chunk_count, int64_t nb, int64_t *total,
+                                int64_t *total_out)
 {
+    __shared__ uint32_t part[kWavesPB];
     const int tid = threadIdx.x;
-    const uint64_t below = (1ull << __lane_id()) - 1ull;
+    const int64_t b = blockIdx.x;
+    uint32_t t = 0;
+    for (int64_t q = tid; q < b; q += kThreads) t += chunk_count[q];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kThreads + tid;
-        if (i < n && ((bal[r] >> __lane_id()) & 1ull))
-            dst[off + rank0[r] + (uint32_t)__popcll(bal[r] & below)] = src[i];
+    for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (__lane_id() == 0) part[tid / kWave] = t;
+    __syncthreads();
+    uint32_t off = 0;
+#pragma unroll
+    for (int q = 0; q < kWavesPB; ++q) off += part[q];
+    if (b == nb - 1 && blockIdx.y == 0 && tid == 0) {
+        const int64_t all = (int64_t)off + chunk_count[b];
+        *total = all;
+        if (total_out) *total_out = all;
     }
+    return off;
 }
 
-__global__ void __launch_bounds__(kThreads) k_prune_scatter(PruneK k, const uint32_t *chunk_off)
+// chunk_off: the scanned offsets, or null to sum them here from chunk_count (nb <= kFoldChunks).
+__global__ void __launch_bounds__(kThreads)
+k_prune_scatter(PruneK k, const uint64_t *__restrict__ ballots, const uint32_t *__restrict__ chunk_off,
+                const uint32_t *__restrict__ chunk_count, int64_t nb, int64_t *total, int64_t *total_out)
 {
-    __shared__ uint32_t cnt[kRounds][kWavesPB];
-    uint64_t bal[kRounds];
+    const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+    const int p0 = blockIdx.y * kGroup;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
-    chunk_ballots(k, base, bal, nullptr, cnt);
-    __syncthreads();
-    // rank of this wave's first survivor in each round: the survivors of earlier rounds and of
-    // earlier waves in the same round
-    const int w = threadIdx.x / kWave;
-    uint32_t rank0[kRounds];
-    uint32_t run = 0;
+    const uint64_t *B = ballots + (int64_t)blockIdx.x * kSlots;
+    const uint64_t below = (1ull << lane) - 1ull;
+    // destination of this thread's element in each round (kept[r]: it survives)
+    uint32_t pos[kRounds];
+    bool kept[kRounds];
+    uint32_t run = chunk_off ? chunk_off[blockIdx.x] : fold_offset(chunk_count, nb, total, total_out);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         uint32_t before = 0, all = 0;
 #pragma unroll
         for (int q = 0; q < kWavesPB; ++q) {
-            const uint32_t c = cnt[r][q];
+            const uint32_t c = (uint32_t)__popcll(B[r * kWavesPB + q]);
             before += q < w ? c : 0u;
             all += c;
         }
-        rank0[r] = run + before;
+        const uint64_t mine = B[r * kWavesPB + w];
+        kept[r] = (mine >> lane) & 1ull;
+        pos[r] = run + before + (uint32_t)__popcll(mine & below);
         run += all;
     }
-    const int64_t off = chunk_off[blockIdx.x];
+    float v[kGroup][kRounds];
 #pragma unroll
-    for (int s = 0; s < kPruneSets; ++s) {
-        if (s >= k.n_sets) break;
-        const ParamsK &a = k.src[s];
-        const GradK &b = k.dst[s];
-        const float *sp[14] = {a.mean, a.mean + a.stride, a.mean + 2 * a.stride, a.log_scale,
-                               a.log_scale + a.stride, a.log_scale + 2 * a.stride, a.quat, a.quat + a.stride,
-                               a.quat + 2 * a.stride, a.quat + 3 * a.stride, a.logit, a.rgb, a.rgb + a.stride,
-                               a.rgb + 2 * a.stride};
-        float *dp[14] = {b.mean, b.mean + b.stride, b.mean + 2 * b.stride, b.log_scale, b.log_scale + b.stride,
-                         b.log_scale + 2 * b.stride, b.quat, b.quat + b.stride, b.quat + 2 * b.stride,
-                         b.quat + 3 * b.stride, b.logit, b.rgb, b.rgb + b.stride, b.rgb + 2 * b.stride};
+    for (int j = 0; j < kGroup; ++j) {
+        if (p0 + j >= k.n_planes) break;
+        const float *__restrict__ sp = k.src[p0 + j];
 #pragma unroll
-        for (int p = 0; p < 14; ++p) copy_plane(sp[p], dp[p], base, off, bal, rank0, k.n);
+        for (int r = 0; r < kRounds; ++r) v[j][r] = kept[r] ? sp[base + (int64_t)r * kThreads + tid] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kGroup; ++j) {
+        if (p0 + j >= k.n_planes) break;
+        float *__restrict__ dp = k.dst[p0 + j];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r)
+            if (kept[r]) dp[pos[r]] = v[j][r];
     }
 }
 
@@ -155,14 +179,26 @@ __global__ void __launch_bounds__(kThreads) k_prune_scatter(PruneK k, const uint
 
 int64_t prune_chunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
-void launch_prune(const PruneK &k, uint32_t *chunk_count, uint32_t *chunk_off, int64_t *total, int64_t *total_out,
-                  hipStream_t s)
+int64_t prune_ws_words(int64_t n)
+{
+    const int64_t nb = prune_chunks(n);
+    const int64_t a = (nb * kSlots * 2 + 63) / 64 * 64, b = (nb + 63) / 64 * 64;
+    return a + 2 * b;
+}
+
+void launch_prune(const PruneK &k, uint32_t *ws, int64_t *total, int64_t *total_out, hipStream_t s)
 {
     const int64_t nb = prune_chunks(k.n);
-    if (nb > 0) hipLaunchKernelGGL(k_prune_count, dim3((unsigned)nb), dim3(kThreads), 0, s, k, chunk_count);
-    hipLaunchKernelGGL(k_prune_offsets, dim3(1), dim3(kScanThreads), 0, s, chunk_count, nb, chunk_off, total,
-                       total_out);
-    if (nb > 0) hipLaunchKernelGGL(k_prune_scatter, dim3((unsigned)nb), dim3(kThreads), 0, s, k, chunk_off);
+    uint64_t *ballots = (uint64_t *)ws;
+    uint32_t *count = ws + (nb * kSlots * 2 + 63) / 64 * 64;
+    uint32_t *off = count + (nb + 63) / 64 * 64;
+    if (nb > 0) hipLaunchKernelGGL(k_prune_count, dim3((unsigned)nb), dim3(kCountThreads), 0, s, k, ballots, count);
+    // up to kFoldChunks chunks the scatter sums the offsets itself; beyond, one workgroup scans them
+    const bool fold = nb > 0 && nb <= kFoldChunks && k.n_planes > 0;
+    if (!fold) hipLaunchKernelGGL(k_prune_offsets, dim3(1), dim3(kScanThreads), 0, s, count, nb, off, total, total_out);
+    if (nb > 0 && k.n_planes > 0)
+        hipLaunchKernelGGL(k_prune_scatter, dim3((unsigned)nb, (unsigned)((k.n_planes + kGroup - 1) / kGroup)),
+                           dim3(kThreads), 0, s, k, ballots, fold ? nullptr : off, count, nb, total, total_out);
 }
 
 }  // namespace fgs

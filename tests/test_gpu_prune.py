@@ -180,3 +180,30 @@ def test_four_sets(fgs, ctx):
     assert kh.value == k
     for o, r in zip(outs, (ref[0],) + ref[2:]):
         assert np.array_equal(bits(host(o)[:, :k]), bits(r))
+
+
+def test_prune_of_a_map_beyond_the_folded_offsets(fgs, ctx):
+    """8.39M gaussians: more than 4096 chunks of 2048, where the chunk offsets are scanned by a
+    launch of their own instead of being summed by each scatter workgroup (parameters only)."""
+    import torch
+    n = 4097 * 2048 + 5
+    g = synth.rng(13)
+    p = np.empty((14, n), np.float32)
+    p[:] = g.standard_normal((14, n), dtype=np.float32)
+    p[10] = g.normal(-3.0, 3.0, n).astype(np.float32)
+    p[3:6] = g.normal(-2.5, 1.0, (3, n)).astype(np.float32)
+    pd = dev(p)
+    out = torch.full((14, n), -1.0, device="cuda")
+    src = (fgs.CGaussians * 1)(fgs.gaussians(pd, n))
+    dst = (fgs.CGaussians * 1)(fgs.gaussians(out, n))
+    kh = C.c_int64(-1)
+    assert fgs._lib.fgs_prune(ctx.handle, C.byref(fgs.PruneOpts(TAU, SMAX).c()), 1, src, dst, None, None,
+                              C.byref(kh)) == fgs.OK
+    del pd
+    ref_p, ref_keep = oracle.prune(p, TAU, SMAX)
+    k = int(ref_keep.sum())
+    print(f"prune n={n}: kept {k}")
+    assert kh.value == k
+    got = host(out)
+    assert np.array_equal(bits(got[:, :k]), bits(ref_p))
+    assert (got[:, k:] == -1.0).all()
