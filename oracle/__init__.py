@@ -128,6 +128,18 @@ def lib():
         L.fgso_prune_keep.restype = C.c_int64
         L.fgso_compact.argtypes = [C.c_int64, C.c_int32, _dp, _u8p, _dp, C.c_int64]
         L.fgso_compact.restype = C.c_int64
+        L.fgso_frame_points.argtypes = [C.c_int32, C.c_int32, _fp, C.c_float, C.c_float, C.c_float, C.c_float, _fp,
+                                        _fp, C.c_int32, C.c_float, C.c_float, C.c_int64, _fp]
+        L.fgso_frame_points.restype = C.c_int64
+        L.fgso_knn.argtypes = [C.c_int64, _fp, C.c_int32, _i32p, _fp]
+        L.fgso_sym3_eigen.argtypes = [_dp, _dp, _dp]
+        L.fgso_cloud_cov.argtypes = [C.c_int64, _fp, C.c_int32, C.c_double, _dp]
+        L.fgso_gicp_linearize.argtypes = [C.c_int64, _fp, _dp, C.c_int64, _fp, _dp, _dp, _dp, C.c_float, _dp, _dp,
+                                          _dp, _i64p, _i32p]
+        L.fgso_so3_exp.argtypes = [_dp, _dp]
+        L.fgso_so3_exp.restype = None
+        L.fgso_gicp_align.argtypes = [C.c_int64, _fp, _dp, C.c_int64, _fp, _dp, _dp, _dp, C.c_float, C.c_int32,
+                                      C.c_double, C.c_double, _dp, _dp, _i32p, _i32p, _dp, _i64p]
         L.fgso_highpass.argtypes = [C.c_int32, C.c_int32, _fp, C.c_double, _dp, _i64p, _i32p, _dp]
         L.fgso_triangle.argtypes = [_i64p]
         L.fgso_triangle.restype = C.c_int32
@@ -307,6 +319,93 @@ def prune(params, min_opacity, max_scale, *companions):
     moments of the same layout))."""
     keep = prune_keep(params, min_opacity, max_scale)
     return (compact(params, keep), keep) + tuple(compact(c, keep) for c in companions)
+
+
+def _f32c(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def frame_points(depth, cam, stride=4, dmin=0.1, dmax=10.0, pose_wc=None):
+    """Lattice points of a depth frame (Sec. III-B, uniform downsampling): (3, count) binary32 in
+    the camera frame, or in the world with pose_wc = (R_wc (3x3), t_wc (3,))."""
+    d = _f32c(depth)
+    H, W = d.shape
+    cap = ((W + stride - 1) // stride) * ((H + stride - 1) // stride)
+    out = np.zeros((3, max(cap, 1)), np.float32)
+    R = t = None
+    if pose_wc is not None:
+        R, t = _f32c(np.asarray(pose_wc[0]).reshape(9)), _f32c(np.asarray(pose_wc[1]).reshape(3))
+    n = lib().fgso_frame_points(W, H, _ptr(d, _fp), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                                _ptr(R, _fp), _ptr(t, _fp), int(stride), float(dmin), float(dmax), out.shape[1],
+                                _ptr(out, _fp))
+    _check(n, "frame_points")
+    return np.ascontiguousarray(out[:, :n])
+
+
+def knn(xyz, k):
+    """(idx (n, k) int32, d2 (n, k) binary32): the k nearest points of every point of the (3, n)
+    binary32 cloud, itself included, in (distance, index) order."""
+    p = _f32c(xyz)
+    n = p.shape[1]
+    idx = np.zeros((n, k), np.int32)
+    d2 = np.zeros((n, k), np.float32)
+    _check(lib().fgso_knn(n, _ptr(p, _fp), int(k), _ptr(idx, _i32p), _ptr(d2, _fp)), "knn")
+    return idx, d2
+
+
+def sym3_eigen(A6):
+    """(evals (3,), evecs (3, 3) with eigenvector c in column c) of the symmetric matrix given by
+    (xx, xy, xz, yy, yz, zz)."""
+    a = _d(A6)
+    ev = np.zeros(3)
+    V = np.zeros(9)
+    lib().fgso_sym3_eigen(_ptr(a, _dp), _ptr(ev, _dp), _ptr(V, _dp))
+    return ev, V.reshape(3, 3).T.copy()
+
+
+def cloud_cov(xyz, k=20, eps=1e-3):
+    """Regularised local covariances (6, n) FP64 (xx, xy, xz, yy, yz, zz) of the (3, n) cloud."""
+    p = _f32c(xyz)
+    n = p.shape[1]
+    cov = np.zeros((6, n))
+    _check(lib().fgso_cloud_cov(n, _ptr(p, _fp), int(k), float(eps), _ptr(cov, _dp)), "cloud_cov")
+    return cov
+
+
+def gicp_linearize(src, src_cov, tgt, tgt_cov, R, t, d_max):
+    """One linearisation of Eq. 14 at (R, t): dict(H (6, 6), b (6,), cost, count, corr (ns,))."""
+    s, tg = _f32c(src), _f32c(tgt)
+    sc, tc = _d(src_cov), _d(tgt_cov)
+    Rm, tv = _d(np.asarray(R).reshape(9)), _d(np.asarray(t).reshape(3))
+    H, b = np.zeros(36), np.zeros(6)
+    cost, count = C.c_double(), C.c_int64()
+    corr = np.zeros(max(s.shape[1], 1), np.int32)
+    _check(lib().fgso_gicp_linearize(s.shape[1], _ptr(s, _fp), _ptr(sc, _dp), tg.shape[1], _ptr(tg, _fp),
+                                     _ptr(tc, _dp), _ptr(Rm, _dp), _ptr(tv, _dp), float(d_max), _ptr(H, _dp),
+                                     _ptr(b, _dp), C.byref(cost), C.byref(count), _ptr(corr, _i32p)), "gicp_linearize")
+    return dict(H=H.reshape(6, 6), b=b, cost=cost.value, count=count.value, corr=corr[:s.shape[1]])
+
+
+def so3_exp(w):
+    w = _d(w)
+    E = np.zeros(9)
+    lib().fgso_so3_exp(_ptr(w, _dp), _ptr(E, _dp))
+    return E.reshape(3, 3)
+
+
+def gicp_align(src, src_cov, tgt, tgt_cov, R0, t0, d_max, max_iter=30, eps_rot=1e-6, eps_trans=1e-6):
+    """Gauss-Newton alignment of Eq. 14: dict(R, t, iterations, status, cost, count)."""
+    s, tg = _f32c(src), _f32c(tgt)
+    sc, tc = _d(src_cov), _d(tgt_cov)
+    R0m, t0v = _d(np.asarray(R0).reshape(9)), _d(np.asarray(t0).reshape(3))
+    R, t = np.zeros(9), np.zeros(3)
+    it, st = C.c_int32(), C.c_int32()
+    cost, count = C.c_double(), C.c_int64()
+    _check(lib().fgso_gicp_align(s.shape[1], _ptr(s, _fp), _ptr(sc, _dp), tg.shape[1], _ptr(tg, _fp),
+                                 _ptr(tc, _dp), _ptr(R0m, _dp), _ptr(t0v, _dp), float(d_max), int(max_iter),
+                                 float(eps_rot), float(eps_trans), _ptr(R, _dp), _ptr(t, _dp), C.byref(it),
+                                 C.byref(st), C.byref(cost), C.byref(count)), "gicp_align")
+    return dict(R=R.reshape(3, 3), t=t, iterations=it.value, status=st.value, cost=cost.value, count=count.value)
 
 
 def adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["render.c", "optim.c", "seed.c", "mlp.c", "loss.c", "prune.c"]
+SOURCES = ["render.c", "optim.c", "seed.c", "mlp.c", "loss.c", "prune.c", "gicp.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -192,6 +192,34 @@ int64_t fgso_prune_keep(int64_t n, const double *params, double min_opacity, dou
 int64_t fgso_compact(int64_t n, int32_t planes, const double *in, const uint8_t *keep, double *out,
                      int64_t out_stride);
 
+/* ------------------------------ GICP tracking (Sec. III-B) ------------------------------ */
+/* Points are 3 binary32 planes (x, y, z) of stride n; covariances 6 FP64 planes (xx, xy, xz, yy,
+ * yz, zz) of stride n; rotations row-major. See gicp.c for the readings. */
+/* Lattice points of a depth frame (camera frame, or world with R_wc, t_wc both given); returns
+ * the count (the first `capacity` are written, planes of stride capacity). */
+int64_t fgso_frame_points(int32_t W, int32_t H, const float *depth, float fx, float fy, float cx, float cy,
+                          const float *R_wc, const float *t_wc, int32_t stride, float dmin, float dmax,
+                          int64_t capacity, float *xyz);
+/* k nearest points of every point in its own cloud (itself included): idx [n][k], d2 [n][k]
+ * (nullable) in (binary32 squared distance, index) order. */
+int fgso_knn(int64_t n, const float *xyz, int32_t k, int32_t *idx, float *d2);
+/* Jacobi eigen-decomposition of a symmetric 3x3 (6 values); evecs column-major. */
+int fgso_sym3_eigen(const double A6[6], double evals[3], double evecs[9]);
+/* Regularised local covariances (eigenvalues 1, 1, eps) from k nearest neighbours. */
+int fgso_cloud_cov(int64_t n, const float *xyz, int32_t k, double eps, double *cov);
+/* One Gauss-Newton linearisation of Eq. 14 at (R, t): H (6x6 row-major), b (6), cost, the number
+ * of correspondences, corr (nullable, ns: target index or -1). */
+int fgso_gicp_linearize(int64_t ns, const float *src, const double *src_cov, int64_t nt, const float *tgt,
+                        const double *tgt_cov, const double R[9], const double t[3], float d_max, double H[36],
+                        double b[6], double *cost, int64_t *count, int32_t *corr);
+/* Rotation Exp(w) (Rodrigues). */
+void fgso_so3_exp(const double w[3], double E[9]);
+/* Gauss-Newton alignment from (R0, t0); status 0 converged, 1 iteration limit, 2 degenerate. */
+int fgso_gicp_align(int64_t ns, const float *src, const double *src_cov, int64_t nt, const float *tgt,
+                    const double *tgt_cov, const double R0[9], const double t0[3], float d_max, int32_t max_iter,
+                    double eps_rot, double eps_trans, double R[9], double t[3], int32_t *iters, int32_t *status,
+                    double *cost, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

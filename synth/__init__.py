@@ -255,3 +255,90 @@ def window_cameras(seed: int = 0):
 def random_planes(seed: int, shape, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     """Uniform random float32 planes, e.g. upstream gradients or stand-in targets."""
     return rng(seed).uniform(lo, hi, size=shape).astype(np.float32)
+
+
+# ----------------------------------- tracking frames -----------------------------------
+
+@dataclass
+class Room:
+    """An axis-aligned room (interior box lo..hi) with axis-aligned boxes standing in it."""
+    lo: np.ndarray
+    hi: np.ndarray
+    boxes: np.ndarray  # (n, 2, 3): lower and upper corner of each box
+
+
+def room_scene(seed: int, n_boxes: int = 12) -> Room:
+    """The 6x6x3 m room [-3,3]x[-3,3]x[0,3] with n_boxes boxes on the floor. Per box, in order:
+    size ~ U([0.3, 0.3, 0.3], [1.0, 1.0, 1.5]); centre (x, y) ~ U within 0.3 m of the walls."""
+    g = rng(seed)
+    lo, hi = np.array([-3.0, -3.0, 0.0]), np.array([3.0, 3.0, 3.0])
+    boxes = []
+    for _ in range(n_boxes):
+        size = g.uniform([0.3, 0.3, 0.3], [1.0, 1.0, 1.5])
+        c = g.uniform(lo[:2] + 0.3 + size[:2] / 2, hi[:2] - 0.3 - size[:2] / 2)
+        blo = np.array([c[0] - size[0] / 2, c[1] - size[1] / 2, 0.0])
+        boxes.append([blo, blo + size])
+    return Room(lo, hi, np.asarray(boxes, np.float64).reshape(-1, 2, 3))
+
+
+def room_depth(room: Room, cam: Camera, seed: int, noise: float = 0.002) -> np.ndarray:
+    """Depth frame (H, W) float32 of `room` seen by `cam`, ray-cast at pixel centres (camera z of
+    the first surface hit: the walls from inside, the boxes from outside), plus N(0, noise^2)."""
+    H, W = cam.height, cam.width
+    R = np.asarray(cam.R, np.float64)
+    o = -R.T @ np.asarray(cam.t, np.float64)
+    ys, xs = np.mgrid[0:H, 0:W]
+    dc = np.stack([(xs + 0.5 - cam.cx) / cam.fx, (ys + 0.5 - cam.cy) / cam.fy, np.ones((H, W))], -1)
+    dw = dc @ R  # rows: R^T dc; the ray parameter is the camera depth (dc_z = 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        exit_t = np.where(dw > 0, (room.hi - o) / dw, np.where(dw < 0, (room.lo - o) / dw, np.inf))
+        s = exit_t.min(-1)
+        for blo, bhi in room.boxes:
+            t1, t2 = (blo - o) / dw, (bhi - o) / dw
+            tmin = np.nan_to_num(np.minimum(t1, t2), nan=-np.inf).max(-1)
+            tmax = np.nan_to_num(np.maximum(t1, t2), nan=np.inf).min(-1)
+            hit = (tmin <= tmax) & (tmin > 0)
+            s = np.where(hit & (tmin < s), tmin, s)
+    return (s + rng(seed).normal(0.0, noise, size=(H, W))).astype(np.float32)
+
+
+def pose_wc(cam: Camera):
+    """Camera-to-world pose (R_wc, t_wc) of `cam` in float64."""
+    R = np.asarray(cam.R, np.float64)
+    return R.T, -R.T @ np.asarray(cam.t, np.float64)
+
+
+def camera_from_pose(R_wc, t_wc, like: Camera) -> Camera:
+    """A camera with `like`'s intrinsics at the camera-to-world pose (R_wc, t_wc)."""
+    R = np.asarray(R_wc, np.float64).T
+    return Camera(like.width, like.height, like.fx, like.fy, like.cx, like.cy, R=R, t=-R @ np.asarray(t_wc),
+                  z_near=like.z_near)
+
+
+def tracking_cameras(seed: int, n_key: int = 8, width: int = 640, height: int = 480, f: float = 525.0,
+                     rot_deg=(1.0, 3.0), trans_m=(0.03, 0.06)):
+    """Keyframe cameras in the room and a current camera near the first one. Per keyframe, in order:
+    centre ~ U([-2,-2,1.6], [2,2,2.2]), target ~ U([-2.5,-2.5,0.2], [2.5,2.5,1.5]), redrawn while
+    closer than 1.5 m. Then the current camera: keyframe 0's camera-to-world pose moved by a rotation
+    about a uniformly random axis by an angle ~ U(rot_deg) degrees (applied in the camera frame)
+    and a translation of length ~ U(trans_m) along a uniformly random direction (world frame)."""
+    from scipy.spatial.transform import Rotation
+    g = rng(seed)
+    keys = []
+    for _ in range(n_key):
+        while True:
+            c = g.uniform([-2.0, -2.0, 1.6], [2.0, 2.0, 2.2])
+            tg = g.uniform([-2.5, -2.5, 0.2], [2.5, 2.5, 1.5])
+            if np.linalg.norm(tg - c) >= 1.5:
+                break
+        keys.append(look_at_camera(width, height, f, c, tg))
+    axis = g.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    ang = np.deg2rad(g.uniform(*rot_deg))
+    tdir = g.normal(size=3)
+    tdir /= np.linalg.norm(tdir)
+    tlen = g.uniform(*trans_m)
+    R0, t0 = pose_wc(keys[0])
+    R1 = R0 @ Rotation.from_rotvec(axis * ang).as_matrix()
+    t1 = t0 + tdir * tlen
+    return keys, camera_from_pose(R1, t1, keys[0])
