@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the small-scene latency, keyframe-window, full-loss, seeding, pruning, "
-                         "densification-ablation and learned-prior measurements")
+                         "densification-ablation, tracking and learned-prior measurements")
     ap.add_argument("--prior-train-scenes", type=int, default=50)
     ap.add_argument("--densify-scenes", type=int, default=10)
     ap.add_argument("--prior-test-scenes", type=int, default=20)
@@ -89,6 +89,8 @@ def parse():
                     help="only run the full-loss (Eq. 16) mapping-step measurement, print its JSON object and exit")
     ap.add_argument("--prune-only", action="store_true",
                     help="only run the pruning measurement, print its JSON object and exit")
+    ap.add_argument("--tracking-only", action="store_true",
+                    help="only run the GICP tracking measurement, print its JSON object and exit")
     ap.add_argument("--densify-only", action="store_true",
                     help="only run the densification ablation, print its JSON object and exit")
     ap.add_argument("--window-only", action="store_true",
@@ -573,6 +575,70 @@ def densify_extra(F, ctx, scenes: int) -> dict:
             "scenes": scenes, "variants": {v: {k: rnd(x) for k, x in d.items()} for v, d in r["summary"].items()}}
 
 
+def tracking_extra(F, ctx, reps: int = 10) -> dict:
+    """GICP tracking (Sec. III-B, Eq. 12-14) of a 640x480 ray-cast room frame against a sparse map
+    of 8 keyframes (both sampled at stride 4): device ms per frame for the frame's points, its
+    cloud (grid, 20 neighbours, covariances) and the Gauss-Newton alignment from the first
+    keyframe's pose (d_max 0.1 m, at most 30 updates); the map's build; the pose error."""
+    import numpy as np
+    import torch
+
+    import synth
+    room = synth.room_scene(8)
+    keys, cur = synth.tracking_cameras(8, n_key=8)
+
+    def pose4(R, t):
+        T = np.eye(4)
+        T[:3, :3], T[:3, 3] = R, t
+        return T
+
+    opts = F.CloudOpts(cell=0.12, k=20, eps=1e-3)
+    stream = torch.cuda.current_stream()
+    kd = [torch.as_tensor(synth.room_depth(room, c, 100 + i)).cuda() for i, c in enumerate(keys)]
+    cd = torch.as_tensor(synth.room_depth(room, cur, 99)).cuda()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(stream)
+    parts = []
+    for c, d in zip(keys, kd):
+        xyz, n = F.frame_points(ctx, d, c, 4, pose_wc=pose4(*synth.pose_wc(c)))
+        parts.append(xyz[:, :n])
+    tgt = torch.cat(parts, 1).contiguous()
+    target = F.Cloud(ctx, tgt, None, opts)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    map_ms = e[0].elapsed_time(e[1])
+    R0, t0 = synth.pose_wc(keys[0])
+    R1, t1 = synth.pose_wc(cur)
+    gopts = F.GicpOpts(0.1, 30, 1e-6, 1e-6)
+    rows = []
+    for k in range(reps + 1):
+        e[0].record(stream)
+        xyz, n = F.frame_points(ctx, cd, cur, 4)
+        e[1].record(stream)
+        source = F.Cloud(ctx, xyz, n, opts)
+        e[2].record(stream)
+        r = F.gicp_align(ctx, source, target, pose4(R0, t0), gopts)
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        if k:
+            rows.append((e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])))
+        source.close()
+    ctx.check()
+    pts_ms, cloud_ms, align_ms = (float(np.median([row[q] for row in rows])) for q in range(3))
+    ang = float(np.degrees(np.arccos(np.clip((np.trace(r["T"][:3, :3].T @ R1) - 1) / 2, -1, 1))))
+    a0 = float(np.degrees(np.arccos(np.clip((np.trace(R0.T @ R1) - 1) / 2, -1, 1))))
+    out = {"workload": "GICP: 640x480 ray-cast room frame vs a sparse map of 8 keyframes, stride 4, k 20, "
+                       "cell 0.12 m, d_max 0.1 m, <= 30 Gauss-Newton updates",
+           "source_points": int(n), "target_points": int(tgt.shape[1]), "iterations": r["iterations"],
+           "status": r["status"], "correspondences": r["correspondences"],
+           "frame_points_ms": round(pts_ms, 4), "source_cloud_ms": round(cloud_ms, 4), "align_ms": round(align_ms, 4),
+           "ms_per_frame": round(pts_ms + cloud_ms + align_ms, 4), "map_build_ms": round(map_ms, 3),
+           "error_deg": round(ang, 5), "error_mm": round(float(np.linalg.norm(r["T"][:3, 3] - t1)) * 1e3, 3),
+           "start_error_deg": round(a0, 3), "start_error_mm": round(float(np.linalg.norm(t0 - t1)) * 1e3, 2)}
+    target.close()
+    return out
+
+
 def prior_extra(F, ctx, n_train: int, n_test: int) -> dict:
     """Learned prior: trained on 100 tiles of each of the converged maps of frames 0..n_train-1,
     compared with the plain rule (best initial opacity of 0.1 / 0.5 / 0.9) on the held-out frames
@@ -624,6 +690,9 @@ def main():
         return
     if args.prune_only:
         print(json.dumps(prune_extra(F, F.Context())), flush=True)
+        return
+    if args.tracking_only:
+        print(json.dumps(tracking_extra(F, F.Context())), flush=True)
         return
     if args.densify_only:
         print(json.dumps(densify_extra(F, F.Context(), args.densify_scenes)), flush=True)
@@ -738,6 +807,7 @@ def main():
         line["seeding"] = extra(seeding_extra, F, ctx)
         line["prune"] = extra(prune_extra, F, ctx)
         line["densification_ablation"] = extra(densify_extra, F, ctx, args.densify_scenes)
+        line["tracking"] = extra(tracking_extra, F, ctx)
         pr = extra(prior_extra, F, ctx, args.prior_train_scenes, args.prior_test_scenes)
         line["learned_prior"] = pr
         if "error" not in pr:

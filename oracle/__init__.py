@@ -132,6 +132,10 @@ def lib():
                                         _fp, C.c_int32, C.c_float, C.c_float, C.c_int64, _fp]
         L.fgso_frame_points.restype = C.c_int64
         L.fgso_knn.argtypes = [C.c_int64, _fp, C.c_int32, _i32p, _fp]
+        L.fgso_knn_some.argtypes = [C.c_int64, _fp, C.c_int32, C.c_int64, _i64p, _i32p, _fp]
+        L.fgso_cloud_cov_some.argtypes = [C.c_int64, _fp, C.c_int32, C.c_double, C.c_int64, _i64p, _dp]
+        L.fgso_gicp_corr_some.argtypes = [C.c_int64, _fp, C.c_int64, _fp, _dp, _dp, C.c_float, C.c_int64, _i64p,
+                                          _i32p]
         L.fgso_sym3_eigen.argtypes = [_dp, _dp, _dp]
         L.fgso_cloud_cov.argtypes = [C.c_int64, _fp, C.c_int32, C.c_double, _dp]
         L.fgso_gicp_linearize.argtypes = [C.c_int64, _fp, _dp, C.c_int64, _fp, _dp, _dp, _dp, C.c_float, _dp, _dp,
@@ -351,6 +355,39 @@ def knn(xyz, k):
     d2 = np.zeros((n, k), np.float32)
     _check(lib().fgso_knn(n, _ptr(p, _fp), int(k), _ptr(idx, _i32p), _ptr(d2, _fp)), "knn")
     return idx, d2
+
+
+def knn_some(xyz, k, q):
+    """(idx (len(q), k), d2 (len(q), k)): knn() for the points q only."""
+    p = _f32c(xyz)
+    qq = np.ascontiguousarray(q, np.int64)
+    idx = np.zeros((qq.size, k), np.int32)
+    d2 = np.zeros((qq.size, k), np.float32)
+    _check(lib().fgso_knn_some(p.shape[1], _ptr(p, _fp), int(k), qq.size, _ptr(qq, _i64p), _ptr(idx, _i32p),
+                               _ptr(d2, _fp)), "knn_some")
+    return idx, d2
+
+
+def cloud_cov_some(xyz, q, k=20, eps=1e-3):
+    """cloud_cov() for the points q only: (6, len(q))."""
+    p = _f32c(xyz)
+    qq = np.ascontiguousarray(q, np.int64)
+    cov = np.zeros((6, max(qq.size, 1)))
+    _check(lib().fgso_cloud_cov_some(p.shape[1], _ptr(p, _fp), int(k), float(eps), qq.size, _ptr(qq, _i64p),
+                                     _ptr(cov, _dp)), "cloud_cov_some")
+    return cov[:, :qq.size]
+
+
+def gicp_corr_some(src, tgt, R, t, d_max, q):
+    """Correspondences (target index or -1) of the source points q at the pose (R, t)."""
+    s, tg = _f32c(src), _f32c(tgt)
+    Rm, tv = _d(np.asarray(R).reshape(9)), _d(np.asarray(t).reshape(3))
+    qq = np.ascontiguousarray(q, np.int64)
+    out = np.zeros(max(qq.size, 1), np.int32)
+    _check(lib().fgso_gicp_corr_some(s.shape[1], _ptr(s, _fp), tg.shape[1], _ptr(tg, _fp), _ptr(Rm, _dp),
+                                     _ptr(tv, _dp), float(d_max), qq.size, _ptr(qq, _i64p), _ptr(out, _i32p)),
+           "gicp_corr_some")
+    return out[:qq.size]
 
 
 def sym3_eigen(A6):

@@ -203,10 +203,18 @@ int64_t fgso_frame_points(int32_t W, int32_t H, const float *depth, float fx, fl
 /* k nearest points of every point in its own cloud (itself included): idx [n][k], d2 [n][k]
  * (nullable) in (binary32 squared distance, index) order. */
 int fgso_knn(int64_t n, const float *xyz, int32_t k, int32_t *idx, float *d2);
+/* The same for the nq points q[] only (q NULL: the first nq); idx [nq][k], d2 [nq][k]. */
+int fgso_knn_some(int64_t n, const float *xyz, int32_t k, int64_t nq, const int64_t *q, int32_t *idx, float *d2);
 /* Jacobi eigen-decomposition of a symmetric 3x3 (6 values); evecs column-major. */
 int fgso_sym3_eigen(const double A6[6], double evals[3], double evecs[9]);
 /* Regularised local covariances (eigenvalues 1, 1, eps) from k nearest neighbours. */
 int fgso_cloud_cov(int64_t n, const float *xyz, int32_t k, double eps, double *cov);
+/* The covariances of the nq points q[] only: 6 planes of stride nq. */
+int fgso_cloud_cov_some(int64_t n, const float *xyz, int32_t k, double eps, int64_t nq, const int64_t *q,
+                        double *cov);
+/* Correspondences (target index or -1) of the nq source points q[] at (R, t). */
+int fgso_gicp_corr_some(int64_t ns, const float *src, int64_t nt, const float *tgt, const double R[9],
+                        const double t[3], float d_max, int64_t nq, const int64_t *q, int32_t *corr);
 /* One Gauss-Newton linearisation of Eq. 14 at (R, t): H (6x6 row-major), b (6), cost, the number
  * of correspondences, corr (nullable, ns: target index or -1). */
 int fgso_gicp_linearize(int64_t ns, const float *src, const double *src_cov, int64_t nt, const float *tgt,

@@ -78,13 +78,14 @@ int64_t fgso_frame_points(int32_t W, int32_t H, const float *depth, float fx, fl
     return count;
 }
 
-int fgso_knn(int64_t n, const float *xyz, int32_t k, int32_t *idx, float *d2)
+int fgso_knn_some(int64_t n, const float *xyz, int32_t k, int64_t nq, const int64_t *q, int32_t *idx, float *d2)
 {
-    if (n < 0 || k <= 0 || k > n || !xyz || !idx) return -1;
+    if (n < 0 || k <= 0 || k > n || !xyz || !idx || nq < 0) return -1;
     const float *X = xyz, *Y = xyz + n, *Z = xyz + 2 * n;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
-        int32_t *bi = idx + i * k;
+    for (int64_t a = 0; a < nq; ++a) {
+        const int64_t i = q ? q[a] : a;
+        int32_t *bi = idx + a * k;
         float bd[256];
         float *bdp = k <= 256 ? bd : (float *)malloc(sizeof(float) * (size_t)k);
         int32_t m = 0; /* entries held, sorted by (distance, index) */
@@ -101,10 +102,15 @@ int fgso_knn(int64_t n, const float *xyz, int32_t k, int32_t *idx, float *d2)
             bi[s] = (int32_t)j;
         }
         if (d2)
-            for (int32_t s = 0; s < k; ++s) d2[i * k + s] = bdp[s];
+            for (int32_t s = 0; s < k; ++s) d2[a * k + s] = bdp[s];
         if (bdp != bd) free(bdp);
     }
     return 0;
+}
+
+int fgso_knn(int64_t n, const float *xyz, int32_t k, int32_t *idx, float *d2)
+{
+    return fgso_knn_some(n, xyz, k, n, NULL, idx, d2);
 }
 
 /* Eigen-decomposition of the symmetric matrix A (xx, xy, xz, yy, yz, zz) by cyclic Jacobi
@@ -150,17 +156,18 @@ int fgso_sym3_eigen(const double A6[6], double evals[3], double evecs[9])
     return 0;
 }
 
-int fgso_cloud_cov(int64_t n, const float *xyz, int32_t k, double eps, double *cov)
+int fgso_cloud_cov_some(int64_t n, const float *xyz, int32_t k, double eps, int64_t nq, const int64_t *q,
+                        double *cov)
 {
-    if (n < 0 || k <= 0 || k > n || !xyz || !cov) return -1;
-    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n * k));
+    if (n < 0 || k <= 0 || k > n || !xyz || !cov || nq < 0) return -1;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)((nq > 0 ? nq : 1) * k));
     if (!idx) return -2;
-    if (fgso_knn(n, xyz, k, idx, NULL) != 0) {
+    if (fgso_knn_some(n, xyz, k, nq, q, idx, NULL) != 0) {
         free(idx);
         return -1;
     }
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < nq; ++i) {
         double mu[3] = {0, 0, 0};
         for (int32_t s = 0; s < k; ++s)
             for (int r = 0; r < 3; ++r) mu[r] += (double)xyz[r * n + idx[i * k + s]];
@@ -179,15 +186,20 @@ int fgso_cloud_cov(int64_t n, const float *xyz, int32_t k, double eps, double *c
         for (int c = 1; c < 3; ++c)
             if (ev[c] < ev[lo]) lo = c;
         const double *nrm = V + 3 * lo, f = 1.0 - eps;
-        cov[0 * n + i] = 1.0 - f * nrm[0] * nrm[0];
-        cov[1 * n + i] = -f * nrm[0] * nrm[1];
-        cov[2 * n + i] = -f * nrm[0] * nrm[2];
-        cov[3 * n + i] = 1.0 - f * nrm[1] * nrm[1];
-        cov[4 * n + i] = -f * nrm[1] * nrm[2];
-        cov[5 * n + i] = 1.0 - f * nrm[2] * nrm[2];
+        cov[0 * nq + i] = 1.0 - f * nrm[0] * nrm[0];
+        cov[1 * nq + i] = -f * nrm[0] * nrm[1];
+        cov[2 * nq + i] = -f * nrm[0] * nrm[2];
+        cov[3 * nq + i] = 1.0 - f * nrm[1] * nrm[1];
+        cov[4 * nq + i] = -f * nrm[1] * nrm[2];
+        cov[5 * nq + i] = 1.0 - f * nrm[2] * nrm[2];
     }
     free(idx);
     return 0;
+}
+
+int fgso_cloud_cov(int64_t n, const float *xyz, int32_t k, double eps, double *cov)
+{
+    return fgso_cloud_cov_some(n, xyz, k, eps, n, NULL, cov);
 }
 
 /* full symmetric 3x3 from 6 planes at index i */
@@ -217,6 +229,41 @@ static int inverse3(const double A[3][3], double B[3][3])
     return 0;
 }
 
+/* Correspondence of source point i at the pose rounded to binary32 (R32, t32): the nearest
+ * target point within d_max (binary32 squared distances, ties by index), or -1. */
+static int32_t corr_of(int64_t i, int64_t ns, const float *src, int64_t nt, const float *tgt, const float R32[9],
+                       const float t32[3], float dm2)
+{
+    const float x = src[i], y = src[ns + i], z = src[2 * ns + i];
+    float P[3];
+    for (int r = 0; r < 3; ++r)
+        P[r] = b_add(b_add(b_add(b_mul(R32[3 * r], x), b_mul(R32[3 * r + 1], y)), b_mul(R32[3 * r + 2], z)), t32[r]);
+    int64_t best = -1;
+    float bd = 0.0f;
+    for (int64_t j = 0; j < nt; ++j) {
+        const float e = dist2_b32(P[0], P[1], P[2], tgt[j], tgt[nt + j], tgt[2 * nt + j]);
+        if (!(e <= dm2)) continue;
+        if (best < 0 || before(e, j, bd, best)) {
+            best = j;
+            bd = e;
+        }
+    }
+    return (int32_t)best;
+}
+
+int fgso_gicp_corr_some(int64_t ns, const float *src, int64_t nt, const float *tgt, const double R[9],
+                        const double t[3], float d_max, int64_t nq, const int64_t *q, int32_t *corr)
+{
+    if (ns < 0 || nt < 0 || nq < 0 || !src || (nt > 0 && !tgt) || !R || !t || !corr) return -1;
+    float R32[9], t32[3];
+    for (int k = 0; k < 9; ++k) R32[k] = (float)R[k];
+    for (int k = 0; k < 3; ++k) t32[k] = (float)t[k];
+    const float dm2 = b_mul(d_max, d_max);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t a = 0; a < nq; ++a) corr[a] = corr_of(q ? q[a] : a, ns, src, nt, tgt, R32, t32, dm2);
+    return 0;
+}
+
 int fgso_gicp_linearize(int64_t ns, const float *src, const double *src_cov, int64_t nt, const float *tgt,
                         const double *tgt_cov, const double R[9], const double t[3], float d_max, double H[36],
                         double b[6], double *cost, int64_t *count, int32_t *corr)
@@ -224,31 +271,9 @@ int fgso_gicp_linearize(int64_t ns, const float *src, const double *src_cov, int
     if (ns < 0 || nt < 0 || (ns > 0 && (!src || !src_cov)) || (nt > 0 && (!tgt || !tgt_cov)) || !R || !t || !H ||
         !b)
         return -1;
-    float R32[9], t32[3];
-    for (int q = 0; q < 9; ++q) R32[q] = (float)R[q];
-    for (int q = 0; q < 3; ++q) t32[q] = (float)t[q];
-    const float dm2 = b_mul(d_max, d_max);
     int32_t *cj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
     if (!cj) return -2;
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < ns; ++i) {
-        const float x = src[i], y = src[ns + i], z = src[2 * ns + i];
-        float P[3];
-        for (int r = 0; r < 3; ++r)
-            P[r] = b_add(b_add(b_add(b_mul(R32[3 * r], x), b_mul(R32[3 * r + 1], y)), b_mul(R32[3 * r + 2], z)),
-                         t32[r]);
-        int64_t best = -1;
-        float bd = 0.0f;
-        for (int64_t j = 0; j < nt; ++j) {
-            const float e = dist2_b32(P[0], P[1], P[2], tgt[j], tgt[nt + j], tgt[2 * nt + j]);
-            if (!(e <= dm2)) continue;
-            if (best < 0 || before(e, j, bd, best)) {
-                best = j;
-                bd = e;
-            }
-        }
-        cj[i] = (int32_t)best;
-    }
+    fgso_gicp_corr_some(ns, src, nt, tgt, R, t, d_max, ns, NULL, cj);
     for (int q = 0; q < 36; ++q) H[q] = 0.0;
     for (int q = 0; q < 6; ++q) b[q] = 0.0;
     double c = 0.0;

@@ -16,6 +16,8 @@ import ctypes as C
 import os
 from dataclasses import dataclass, field
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfgs.so")
 
@@ -94,6 +96,19 @@ class CPruneOpts(C.Structure):
     _fields_ = [("min_opacity", C.c_float), ("max_scale", C.c_float)]
 
 
+class CCloudOpts(C.Structure):
+    _fields_ = [("cell", C.c_float), ("k", C.c_int32), ("eps", C.c_double), ("keep_knn", C.c_int32)]
+
+
+class CGicpOpts(C.Structure):
+    _fields_ = [("d_max", C.c_float), ("max_iter", C.c_int32), ("eps_rot", C.c_double), ("eps_trans", C.c_double)]
+
+
+class CGicpResult(C.Structure):
+    _fields_ = [("T", C.c_double * 16), ("iterations", C.c_int32), ("status", C.c_int32),
+                ("correspondences", C.c_int64), ("cost", C.c_double)]
+
+
 class CPriorAdam(C.Structure):
     _fields_ = [("m", _fp), ("v", _fp), ("step", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float)]
@@ -119,6 +134,13 @@ _sigs = {
     "fgs_loss_l1": [_vp, C.c_int64, _fp, _fp, _P(CTarget), _P(CLossOpts), _fp, _fp, _fp, _fp],
     "fgs_ssim": [_vp, C.c_int32, C.c_int32, _fp, _fp, _fp, _fp],
     "fgs_adam_step": [_vp, _P(CGaussians), _P(CGaussians), _P(CAdam)],
+    "fgs_frame_points": [_vp, _fp, _P(CCamera), _P(C.c_double), C.c_int32, C.c_float, C.c_float, _fp, C.c_int64,
+                         _P(C.c_int64), _P(C.c_int64)],
+    "fgs_cloud_create": [_vp, C.c_int64, C.c_int64, _fp, _P(CCloudOpts), _P(_vp)],
+    "fgs_cloud_destroy": [_vp],
+    "fgs_cloud_read": [_vp, _P(C.c_double), _P(C.c_int32), _P(C.c_int64), _P(C.c_int32)],
+    "fgs_gicp_linearize": [_vp, _vp, _vp, _P(C.c_double), C.c_float, _P(C.c_double), _P(C.c_int32)],
+    "fgs_gicp_align": [_vp, _vp, _vp, _P(C.c_double), _P(CGicpOpts), _P(CGicpResult)],
     "fgs_prune": [_vp, _P(CPruneOpts), C.c_int32, _P(CGaussians), _P(CGaussians), _P(C.c_int64), _P(C.c_uint8),
                   _P(C.c_int64)],
     "fgs_ctx_profile": [_vp, C.c_int32],
@@ -468,6 +490,115 @@ def prune(ctx: Context, params, n: int, opts: PruneOpts | None = None, adam: Ada
     if adam is not None:
         new_adam = Adam(outs[1], outs[2], step=adam.step, lr=adam.lr, beta1=adam.beta1, beta2=adam.beta2, eps=adam.eps)
     return outs[0], (host.value if sync else None), new_adam
+
+
+# ------------------------------------ GICP tracking ------------------------------------
+
+def _pose16(T):
+    a = (C.c_double * 16)(*[float(v) for v in np.asarray(T, np.float64).reshape(16)])
+    return a
+
+
+def frame_points(ctx: Context, depth, cam, stride: int = 4, depth_min: float = 0.1, depth_max: float = 10.0,
+                 pose_wc=None, capacity: int | None = None):
+    """Lattice points of a depth frame ((H, W) float32 device tensor) as a (3, capacity) float32
+    device tensor and their count (Sec. III-B, uniform downsampling). pose_wc: optional 4x4
+    camera-to-world pose (host array); without it the points stay in the camera frame."""
+    import torch
+    H, W = int(cam.height), int(cam.width)
+    cap = capacity if capacity is not None else ((W + stride - 1) // stride) * ((H + stride - 1) // stride)
+    xyz = torch.empty((3, max(cap, 1)), dtype=torch.float32, device=depth.device)
+    n = C.c_int64(-1)
+    pose = None if pose_wc is None else _pose16(pose_wc)
+    _check(_lib.fgs_frame_points(ctx.handle, _f32(depth), C.byref(camera(cam)), pose, int(stride), float(depth_min),
+                                 float(depth_max), _f32(xyz), cap, None, C.byref(n)), ctx.handle)
+    return xyz, n.value
+
+
+@dataclass
+class CloudOpts:
+    """Grid cell (world units), neighbours per covariance, the regularised smallest eigenvalue,
+    and whether to keep the neighbour lists (see fgs_cloud_opts)."""
+    cell: float = 0.1
+    k: int = 20
+    eps: float = 1e-3
+    keep_knn: bool = False
+
+    def c(self) -> CCloudOpts:
+        return CCloudOpts(self.cell, self.k, self.eps, int(bool(self.keep_knn)))
+
+
+class Cloud:
+    """A point cloud on the GPU with its grid, neighbours and plane-regularised covariances
+    (fgs_cloud). xyz: (3, >= n) float32 device tensor; its first n columns are copied."""
+
+    def __init__(self, ctx: Context, xyz, n: int | None = None, opts: CloudOpts | None = None):
+        assert xyz.dim() == 2 and xyz.shape[0] == 3 and xyz.is_contiguous()
+        self.ctx = ctx
+        self.n = int(xyz.shape[1] if n is None else n)
+        self.opts = opts or CloudOpts()
+        h = C.c_void_p()
+        _check(_lib.fgs_cloud_create(ctx.handle, self.n, xyz.shape[1], _f32(xyz), C.byref(self.opts.c()),
+                                     C.byref(h)), ctx.handle)
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def read(self):
+        """(cov (6, n) float64 device tensor, knn (n, k) int32 device tensor or None)."""
+        import torch
+        cov = torch.empty((6, self.n), dtype=torch.float64, device="cuda")
+        knn = torch.empty((self.n, self.opts.k), dtype=torch.int32, device="cuda") if self.opts.keep_knn else None
+        _check(_lib.fgs_cloud_read(self._h, C.cast(C.c_void_p(cov.data_ptr()), C.POINTER(C.c_double)),
+                                   _ptr(knn, _i32p), None, None), self.ctx.handle)
+        return cov, knn
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fgs_cloud_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+@dataclass
+class GicpOpts:
+    """Correspondence radius, iteration limit and convergence thresholds (see fgs_gicp_opts)."""
+    d_max: float = 0.1
+    max_iter: int = 30
+    eps_rot: float = 1e-6
+    eps_trans: float = 1e-6
+
+    def c(self) -> CGicpOpts:
+        return CGicpOpts(self.d_max, self.max_iter, self.eps_rot, self.eps_trans)
+
+
+def gicp_align(ctx: Context, source: Cloud, target: Cloud, T_init, opts: GicpOpts | None = None) -> dict:
+    """Aligns source to target from the 4x4 pose T_init (Eq. 14); waits for the result:
+    dict(T (4, 4) float64 numpy, iterations, status, correspondences, cost)."""
+    r = CGicpResult()
+    _check(_lib.fgs_gicp_align(ctx.handle, source.handle, target.handle, _pose16(T_init),
+                               C.byref((opts or GicpOpts()).c()), C.byref(r)), ctx.handle)
+    return dict(T=np.array(r.T[:], np.float64).reshape(4, 4), iterations=r.iterations, status=r.status,
+                correspondences=r.correspondences, cost=r.cost)
+
+
+def gicp_linearize(ctx: Context, source: Cloud, target: Cloud, T, d_max: float, corr: bool = True):
+    """One linearisation of Eq. 14 at the 4x4 pose T: (29 float64 device tensor: H's upper
+    triangle, b, cost, count; correspondences (n int32 device tensor) or None)."""
+    import torch
+    out = torch.empty(29, dtype=torch.float64, device="cuda")
+    cr = torch.empty(source.n, dtype=torch.int32, device="cuda") if corr else None
+    _check(_lib.fgs_gicp_linearize(ctx.handle, source.handle, target.handle, _pose16(T), float(d_max),
+                                   C.cast(C.c_void_p(out.data_ptr()), C.POINTER(C.c_double)), _ptr(cr, _i32p)),
+           ctx.handle)
+    return out, cr
 
 
 def render(ctx: Context, params, n: int, cam, opts: RenderOpts | None = None, max_pairs: int | None = None,

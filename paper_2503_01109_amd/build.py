@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfgs.so")
-SOURCES = ["api.cpp", "project.hip", "sort.hip", "raster.hip", "optim.hip", "seed.hip", "mlp.hip", "ssim.hip", "prune.hip"]
+SOURCES = ["api.cpp", "project.hip", "sort.hip", "raster.hip", "optim.hip", "seed.hip", "mlp.hip", "ssim.hip", "prune.hip", "gicp.hip"]
 ARCH = "gfx950"
 
 

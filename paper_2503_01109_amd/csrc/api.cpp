@@ -1,6 +1,7 @@
 // C ABI of the FGS HIP library: context, workspace, argument checks and the enqueueing of the
 // forward, backward and mapping-step pipelines. See include/fgs.h for the contract of every call.
 #include "fgs.h"
+#include "fgs_gicp.h"
 #include "fgs_internal.h"
 #include "fgs_prior.h"
 #include "mlp_internal.h"
@@ -13,6 +14,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -131,6 +133,10 @@ struct fgs_ctx {
     DBuf ms_img, ms_ssim, ms_reg;  // rendered colour, per-tile SSIM sums, regulariser partials
     DBuf ssim_part, ssim_ws;       // SSIM: fgs_ssim's per-tile sums; the partials' workspace
     DBuf prune_ws;                 // pruning: survivor total (int64), chunk counts and offsets
+    // tracking: frame-point row counts; a cloud build's sort keys, values and histograms; the
+    // Gauss-Newton state and partial sums
+    DBuf fp_rows, cl_sort, cl_hist, cl_box, gicp_state, gicp_part;
+    void *gicp_host = nullptr;  // pinned copy of the Gauss-Newton state
     DBuf seed_ws, seed_sc;
     // learned prior: network workspace (rows_cap rows) and per-frame tile buffers for seeding
     DBuf mlp_ws, prior_feat, prior_valid, prior_y;
@@ -726,6 +732,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (ctx->host_words) (void)hipHostFree(ctx->host_words);
     if (ctx->ms_host) (void)hipHostFree(ctx->ms_host);
     if (ctx->step_host) (void)hipHostFree(ctx->step_host);
+    if (ctx->gicp_host) (void)hipHostFree(ctx->gicp_host);
     delete ctx;
     return FGS_OK;
 }
@@ -2033,3 +2040,278 @@ fgs_status fgs_window_step(fgs_window *w, const fgs_gaussians *params, fgs_adam 
 }
 
 }  // extern "C"
+
+/* ------------------------------------ GICP tracking ------------------------------------ */
+
+struct fgs_cloud {
+    fgs_ctx *ctx = nullptr;
+    int64_t n = 0;
+    int32_t k = 0;
+    GridK grid{};
+    int64_t cells = 0;
+    DBuf xyz, pts, ranges, cov, knn;
+};
+
+namespace {
+
+// Grows a context buffer after the stream has drained (work in flight may still use the old one).
+hipError_t grow(fgs_ctx *ctx, DBuf &b, size_t bytes)
+{
+    if (bytes <= b.bytes && b.p) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? b.ensure(bytes) : e;
+}
+
+bool finite_pose(const double *T)
+{
+    for (int q = 0; q < 16; ++q)
+        if (!std::isfinite(T[q])) return false;
+    return true;
+}
+
+fgs_status gicp_setup(fgs_ctx *ctx, const fgs_cloud *src, const fgs_cloud *tgt, const double *T, float d_max,
+                      const char *w, GicpK *K)
+{
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    if (!src || !tgt) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: source or target cloud is NULL", w);
+    if (!T || !finite_pose(T)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: pose is NULL or not finite", w);
+    if (!(d_max > 0.0f) || !std::isfinite(d_max)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: d_max must be > 0", w);
+    const double rings = floor((double)d_max / (double)tgt->grid.c + (double)tgt->grid.margin) + 1.0;
+    if (rings > 8.0)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: d_max %g spans more than 8 cells of the target grid (cell %g)", w,
+                    (double)d_max, (double)tgt->grid.c);
+    K->g = tgt->grid;
+    K->ranges = tgt->ranges.as<uint2>();
+    K->tpts = tgt->pts.as<float4>();
+    K->tx = tgt->xyz.as<float>();
+    K->ty = K->tx + tgt->n;
+    K->tz = K->tx + 2 * tgt->n;
+    K->tcov = tgt->cov.as<double>();
+    K->nt = tgt->n;
+    K->sx = src->xyz.as<float>();
+    K->sy = K->sx + src->n;
+    K->sz = K->sx + 2 * src->n;
+    K->scov = src->cov.as<double>();
+    K->ns = src->n;
+    K->dm2 = d_max * d_max;
+    K->rings = (int32_t)rings;
+    HIP_TRY(ctx, grow(ctx, ctx->gicp_state, sizeof(GicpState)));
+    HIP_TRY(ctx, grow(ctx, ctx->gicp_part, (size_t)std::max<int64_t>(gicp_partials(src->n), 1) * 29 * 8));
+    double R[9], t[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = T[4 * r + c];
+        t[r] = T[4 * r + 3];
+    }
+    launch_gicp_init(ctx->gicp_state.as<GicpState>(), R, t, ctx->stream);
+    return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_frame_points(fgs_ctx *ctx, const float *depth, const fgs_camera *cam, const double *pose_wc,
+                            int32_t stride, float depth_min, float depth_max, float *xyz, int64_t capacity,
+                            int64_t *n_dev, int64_t *n_host)
+{
+    const char *w = "fgs_frame_points";
+    fgs_status st;
+    if ((st = check_camera(ctx, cam, w)) != FGS_OK) return st;
+    if (!depth) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: depth is NULL", w);
+    if (stride <= 0) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: stride must be positive", w);
+    if (capacity < 0 || (capacity > 0 && !xyz)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: bad output", w);
+    if (std::isnan(depth_min) || std::isnan(depth_max))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: depth range is NaN", w);
+    if (pose_wc && !finite_pose(pose_wc)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: pose not finite", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    FrameK f{};
+    f.depth = depth;
+    f.W = cam->width;
+    f.H = cam->height;
+    f.stride = stride;
+    f.fx = cam->fx;
+    f.fy = cam->fy;
+    f.cx = cam->cx;
+    f.cy = cam->cy;
+    f.dmin = depth_min;
+    f.dmax = depth_max;
+    f.has_pose = pose_wc != nullptr;
+    if (pose_wc)
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) f.R[3 * r + c] = (float)pose_wc[4 * r + c];
+            f.t[r] = (float)pose_wc[4 * r + 3];
+        }
+    const int rows = (cam->height + stride - 1) / stride;
+    HIP_TRY(ctx, grow(ctx, ctx->fp_rows, (size_t)rows * 4 + 8));
+    int64_t *cnt = n_dev ? n_dev : ctx->fp_rows.as<int64_t>();
+    uint32_t *row_count = ctx->fp_rows.as<uint32_t>(8);
+    launch_frame_points(f, row_count, xyz, capacity, cnt, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    if (n_host) {
+        int64_t v = -1;
+        HIP_TRY(ctx, hipMemcpyAsync(&v, cnt, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        *n_host = v;
+        if (v > capacity)
+            return fail(ctx, FGS_ERR_CAPACITY, "%s: %lld points, capacity %lld", w, (long long)v, (long long)capacity);
+    }
+    return FGS_OK;
+}
+
+fgs_status fgs_cloud_create(fgs_ctx *ctx, int64_t n, int64_t stride, const float *xyz, const fgs_cloud_opts *o,
+                            fgs_cloud **out)
+{
+    const char *w = "fgs_cloud_create";
+    if (!out) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: out is NULL", w);
+    *out = nullptr;
+    if (!o) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: options are NULL", w);
+    if (o->k < 3 || o->k > 32) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: k must be in [3, 32]", w);
+    if (n < o->k || n > ((int64_t)1 << 30))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: n = %lld outside [k, 2^30]", w, (long long)n);
+    if (stride < n || !xyz) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: xyz is NULL or stride < n", w);
+    if (!(o->cell > 0.0f) || !std::isfinite(o->cell)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: cell must be > 0", w);
+    if (!(o->eps > 0.0 && o->eps <= 1.0)) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: eps must be in (0, 1]", w);
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: ctx is NULL", w);
+    fgs_cloud *c = new (std::nothrow) fgs_cloud();
+    if (!c) return fail(ctx, FGS_ERR_HIP, "%s: out of host memory", w);
+    std::unique_ptr<fgs_cloud> own(c);
+    c->ctx = ctx;
+    c->n = n;
+    c->k = o->k;
+    hipStream_t s = ctx->stream;
+    HIP_TRY(ctx, c->xyz.ensure((size_t)n * 3 * 4));
+    for (int r = 0; r < 3; ++r)
+        HIP_TRY(ctx, hipMemcpyAsync(c->xyz.as<float>() + r * n, xyz + r * stride, (size_t)n * 4,
+                                    hipMemcpyDeviceToDevice, s));
+    const float *X = c->xyz.as<float>(), *Y = X + n, *Z = X + 2 * n;
+    // bounding box -> grid
+    // cl_box: the box (6 floats, padded to 8), the partial boxes, then the point count for the sort
+    HIP_TRY(ctx, grow(ctx, ctx->cl_box, ((size_t)8 + 6 * (size_t)bbox_partials() + 8) * 4));
+    float *box = ctx->cl_box.as<float>();
+    uint32_t *ndev = (uint32_t *)(box + 8 + 6 * bbox_partials());
+    launch_bbox(X, Y, Z, n, box + 8, box, s);
+    float hb[6];
+    HIP_TRY(ctx, hipMemcpyAsync(hb, box, 24, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (int q = 0; q < 6; ++q)
+        if (!std::isfinite(hb[q])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: points are not finite", w);
+    const double cell = (double)o->cell;
+    GridK &g = c->grid;
+    g.c = o->cell;
+    g.inv_c = 1.0f / o->cell;
+    g.ox = (float)(hb[0] - 0.5 * cell);
+    g.oy = (float)(hb[1] - 0.5 * cell);
+    g.oz = (float)(hb[2] - 0.5 * cell);
+    const double dims[3] = {floor(((double)hb[3] - g.ox) / cell) + 2.0, floor(((double)hb[4] - g.oy) / cell) + 2.0,
+                            floor(((double)hb[5] - g.oz) / cell) + 2.0};
+    const double cells = dims[0] * dims[1] * dims[2];
+    if (cells > (double)((int64_t)1 << 25))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %.0f grid cells of %g over the cloud's extent (at most 2^25)", w,
+                    cells, cell);
+    g.gx = (int32_t)dims[0];
+    g.gy = (int32_t)dims[1];
+    g.gz = (int32_t)dims[2];
+    c->cells = (int64_t)cells;
+    const double gmax = std::max(dims[0], std::max(dims[1], dims[2]));
+    g.margin = (float)(1e-3 + 6.0 * ldexp(1.0, -24) * gmax);
+    // points sorted by cell
+    const int G = sort_blocks(n, kPairSortPerBlock);
+    HIP_TRY(ctx, grow(ctx, ctx->cl_sort, (size_t)n * 5 * 4 + 16));
+    HIP_TRY(ctx, grow(ctx, ctx->cl_hist, ((size_t)G * 256 + 256) * 4));
+    uint32_t *ka = ctx->cl_sort.as<uint32_t>(), *va = ka + n, *kb = va + n, *vb = kb + n, *vf = vb + n;
+    HIP_TRY(ctx, hipMemsetD32Async((hipDeviceptr_t)ndev, (int)n, 1, s));
+    launch_cell_keys(g, X, Y, Z, n, ka, va, s);
+    SortWS sws;
+    sws.G = G;
+    sws.hist = ctx->cl_hist.as<uint32_t>();
+    sws.totals = sws.hist + (size_t)G * 256;
+    int bits = 1;
+    while (((int64_t)1 << bits) < c->cells) ++bits;
+    uint32_t *sk = launch_radix_sort(ka, va, kb, vb, vf, ndev, n, bits, sws, s);
+    HIP_TRY(ctx, c->ranges.ensure((size_t)c->cells * sizeof(uint2)));
+    launch_ranges(sk, ndev, c->ranges.as<uint2>(), c->cells, 0xffffffffu, s);
+    HIP_TRY(ctx, c->pts.ensure((size_t)n * sizeof(float4)));
+    launch_gather_cells(vf, X, Y, Z, n, c->pts.as<float4>(), s);
+    HIP_TRY(ctx, c->cov.ensure((size_t)n * 6 * 8));
+    if (o->keep_knn) HIP_TRY(ctx, c->knn.ensure((size_t)n * o->k * 4));
+    launch_knn_cov(g, c->ranges.as<uint2>(), c->pts.as<float4>(), n, o->k, o->eps, X, Y, Z,
+                   o->keep_knn ? c->knn.as<int32_t>() : nullptr, c->cov.as<double>(), s);
+    HIP_TRY(ctx, hipGetLastError());
+    *out = own.release();
+    return FGS_OK;
+}
+
+fgs_status fgs_cloud_destroy(fgs_cloud *c)
+{
+    if (!c) return FGS_OK;
+    if (c->ctx) (void)hipStreamSynchronize(c->ctx->stream);
+    delete c;
+    return FGS_OK;
+}
+
+fgs_status fgs_cloud_read(const fgs_cloud *c, double *cov, int32_t *knn, int64_t *n_out, int32_t *k_out)
+{
+    const char *w = "fgs_cloud_read";
+    if (!c) return fail(nullptr, FGS_ERR_INVALID_ARG, "%s: cloud is NULL", w);
+    fgs_ctx *ctx = c->ctx;
+    if (knn && !c->knn.p) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: the cloud kept no neighbour lists", w);
+    if (n_out) *n_out = c->n;
+    if (k_out) *k_out = c->k;
+    if (cov) HIP_TRY(ctx, hipMemcpyAsync(cov, c->cov.p, (size_t)c->n * 6 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (knn)
+        HIP_TRY(ctx, hipMemcpyAsync(knn, c->knn.p, (size_t)c->n * c->k * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return FGS_OK;
+}
+
+fgs_status fgs_gicp_linearize(fgs_ctx *ctx, const fgs_cloud *source, const fgs_cloud *target, const double T[16],
+                              float d_max, double *out, int32_t *corr)
+{
+    const char *w = "fgs_gicp_linearize";
+    if (!out) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: out is NULL", w);
+    GicpK K;
+    fgs_status st = gicp_setup(ctx, source, target, T, d_max, w, &K);
+    if (st != FGS_OK) return st;
+    launch_gicp_iteration(K, ctx->gicp_state.as<GicpState>(), ctx->gicp_part.as<double>(), corr, 0, 1, 0.0, 0.0, out,
+                          ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
+}
+
+fgs_status fgs_gicp_align(fgs_ctx *ctx, const fgs_cloud *source, const fgs_cloud *target, const double T_init[16],
+                          const fgs_gicp_opts *o, fgs_gicp_result *result)
+{
+    const char *w = "fgs_gicp_align";
+    if (!o || !result) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: options or result is NULL", w);
+    if (o->max_iter < 1 || o->max_iter > 1000) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: max_iter outside [1, 1000]", w);
+    if (!(o->eps_rot >= 0.0) || !(o->eps_trans >= 0.0))
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: eps_rot and eps_trans must be >= 0", w);
+    GicpK K;
+    fgs_status st = gicp_setup(ctx, source, target, T_init, o->d_max, w, &K);
+    if (st != FGS_OK) return st;
+    GicpState *sd = ctx->gicp_state.as<GicpState>();
+    {
+        Stage st_(ctx, "gicp");
+        for (int it = 0; it < o->max_iter; ++it)
+            launch_gicp_iteration(K, sd, ctx->gicp_part.as<double>(), nullptr, 1, o->max_iter, o->eps_rot,
+                                  o->eps_trans, nullptr, ctx->stream);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (!ctx->gicp_host) HIP_TRY(ctx, hipHostMalloc(&ctx->gicp_host, sizeof(GicpState), hipHostMallocDefault));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->gicp_host, sd, sizeof(GicpState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const GicpState &hs = *(const GicpState *)ctx->gicp_host;
+    for (int q = 0; q < 16; ++q) result->T[q] = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) result->T[4 * r + c] = hs.R[3 * r + c];
+        result->T[4 * r + 3] = hs.t[r];
+    }
+    result->T[15] = 1.0;
+    result->iterations = hs.iters;
+    result->status = hs.status;
+    result->correspondences = hs.count;
+    result->cost = hs.cost;
+    return FGS_OK;
+}
+
+}  // extern "C"
+

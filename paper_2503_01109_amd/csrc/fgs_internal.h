@@ -358,6 +358,64 @@ int64_t prune_ws_words(int64_t n);
 // ws: prune_ws_words(n) words (256-byte aligned); total: the survivor count (int64, device), also
 // written to total_out when that is not null.
 void launch_prune(const PruneK &k, uint32_t *ws, int64_t *total, int64_t *total_out, hipStream_t s);
+// ---------------------------- GICP tracking (gicp.hip) ----------------------------
+// Lattice points of a depth frame (Sec. III-B): row_count holds one word per lattice row.
+struct FrameK {
+    const float *depth;
+    int32_t W, H, stride;
+    float fx, fy, cx, cy, dmin, dmax;
+    int32_t has_pose;
+    float R[9], t[3];  // camera to world
+};
+void launch_frame_points(const FrameK &f, uint32_t *row_count, float *xyz, int64_t capacity, int64_t *n_dev,
+                         hipStream_t s);
+// Uniform grid of cubic cells: cell (floor((x - ox) inv_c), ...) in binary32, dims gx, gy, gz;
+// margin: the slack in cells of that rounding plus the distances', kept off every ring bound.
+struct GridK {
+    float ox, oy, oz, inv_c, c;
+    int32_t gx, gy, gz;
+    float margin;
+};
+int bbox_partials();
+// min x, y, z and max x, y, z of n points into out (6 floats); part: bbox_partials() x 6 floats.
+void launch_bbox(const float *x, const float *y, const float *z, int64_t n, float *part, float *out, hipStream_t s);
+void launch_cell_keys(const GridK &g, const float *x, const float *y, const float *z, int64_t n, uint32_t *keys,
+                      uint32_t *vals, hipStream_t s);
+// pts[r] = (x, y, z, index bits) of the point vals[r] (the points in cell order).
+void launch_gather_cells(const uint32_t *vals, const float *x, const float *y, const float *z, int64_t n, float4 *pts,
+                         hipStream_t s);
+// k (<= 32) nearest neighbours of every point of the cloud and its plane-regularised covariance
+// (6 FP64 planes of stride n, by point index); knn_out (nullable): [n][k] indices.
+void launch_knn_cov(const GridK &g, const uint2 *ranges, const float4 *pts, int64_t n, int k, double eps,
+                    const float *x, const float *y, const float *z, int32_t *knn_out, double *cov, hipStream_t s);
+// Pose and progress of a Gauss-Newton alignment, on the device.
+struct GicpState {
+    double R[9], t[3];
+    float R32[9], t32[3];
+    int32_t done, iters, status, pad;
+    int64_t count;
+    double cost;
+};
+struct GicpK {
+    GridK g;  // the target's grid
+    const uint2 *ranges;
+    const float4 *tpts;
+    const float *tx, *ty, *tz;
+    const double *tcov;
+    int64_t nt;
+    const float *sx, *sy, *sz;
+    const double *scov;
+    int64_t ns;
+    float dm2;
+    int32_t rings;  // search block of (2 rings + 1)^3 cells
+};
+int64_t gicp_partials(int64_t ns);  // partial sums of 29 doubles
+// Starts an alignment at (R, t): not done, no iterations, status 1 (iteration limit).
+void launch_gicp_init(GicpState *st, const double R[9], const double t[3], hipStream_t s);
+// One Gauss-Newton iteration: correspondences and partial sums, then (update != 0) the solve and
+// pose update in st, or (update == 0) only the totals into out (29 doubles, nullable otherwise).
+void launch_gicp_iteration(const GicpK &k, GicpState *st, double *partials, int32_t *corr, int update, int max_iter,
+                           double eps_rot, double eps_trans, double *out, hipStream_t s);
 void launch_step_advance(int64_t *step, const uint32_t *skip, hipStream_t s);
 
 }  // namespace fgs

@@ -4,6 +4,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2503_01109_amd as F
@@ -39,6 +40,7 @@ LAYOUT_PROBE = r"""
 #include <stdio.h>
 #include "fgs.h"
 #include "fgs_prior.h"
+#include "fgs_gicp.h"
 #define S(T) printf(#T " %zu\n", sizeof(T));
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
@@ -47,6 +49,8 @@ int main(void) {
   S(fgs_render_opts) O(fgs_render_opts, bg) O(fgs_render_opts, tile_h)
   S(fgs_image) S(fgs_adam) O(fgs_adam, step) O(fgs_adam, lr) O(fgs_adam, eps)
   S(fgs_target) S(fgs_loss_opts) S(fgs_prune_opts) O(fgs_prune_opts, max_scale)
+  S(fgs_cloud_opts) O(fgs_cloud_opts, eps) O(fgs_cloud_opts, keep_knn)
+  S(fgs_gicp_opts) O(fgs_gicp_opts, eps_rot) S(fgs_gicp_result) O(fgs_gicp_result, status) O(fgs_gicp_result, cost)
   S(fgs_prior_adam) O(fgs_prior_adam, step) O(fgs_prior_adam, eps)
   %EXTRA%
   return 0;
@@ -75,6 +79,10 @@ def test_struct_layouts_match_header(tmp_path):
         "fgs_adam.lr": F.CAdam.lr.offset, "fgs_adam.eps": F.CAdam.eps.offset,
         "fgs_target": C.sizeof(F.CTarget), "fgs_loss_opts": C.sizeof(F.CLossOpts),
         "fgs_prune_opts": C.sizeof(F.CPruneOpts), "fgs_prune_opts.max_scale": F.CPruneOpts.max_scale.offset,
+        "fgs_cloud_opts": C.sizeof(F.CCloudOpts), "fgs_cloud_opts.eps": F.CCloudOpts.eps.offset,
+        "fgs_cloud_opts.keep_knn": F.CCloudOpts.keep_knn.offset, "fgs_gicp_opts": C.sizeof(F.CGicpOpts),
+        "fgs_gicp_opts.eps_rot": F.CGicpOpts.eps_rot.offset, "fgs_gicp_result": C.sizeof(F.CGicpResult),
+        "fgs_gicp_result.status": F.CGicpResult.status.offset, "fgs_gicp_result.cost": F.CGicpResult.cost.offset,
         "fgs_prior_adam": C.sizeof(F.CPriorAdam), "fgs_prior_adam.step": F.CPriorAdam.step.offset,
         "fgs_prior_adam.eps": F.CPriorAdam.eps.offset,
     }
@@ -279,3 +287,42 @@ def test_prune_rejects_bad_arguments_on_host():
     # disjoint blocks pass every check before the context's
     assert call(ok, [block(A, n, n), block(M, n, n)], [block(B, n, n), block(Mo, n, n)]) == (
         F.ERR_INVALID_ARG, "fgs_prune: ctx is NULL")
+
+
+def test_tracking_calls_reject_bad_arguments_on_host():
+    d = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    cam = F.camera(_cam())
+    n = C.c_int64(0)
+    assert F._lib.fgs_frame_points(None, d, C.byref(cam), None, 0, 0.1, 10.0, d, 10, None, None) == F.ERR_INVALID_ARG
+    assert "stride" in F.last_error()
+    assert F._lib.fgs_frame_points(None, d, C.byref(cam), None, 2, float("nan"), 10.0, d, 10, None, None) == \
+        F.ERR_INVALID_ARG
+    bad_pose = (C.c_double * 16)(*([float("nan")] + [0.0] * 15))
+    assert F._lib.fgs_frame_points(None, d, C.byref(cam), bad_pose, 2, 0.1, 10.0, d, 10, None, None) == \
+        F.ERR_INVALID_ARG and "pose" in F.last_error()
+    assert F._lib.fgs_frame_points(None, d, C.byref(cam), None, 2, 0.1, 10.0, d, 10, None, C.byref(n)) == \
+        F.ERR_INVALID_ARG and "ctx is NULL" in F.last_error()
+    h = C.c_void_p()
+
+    def create(n, stride, opts):
+        st = F._lib.fgs_cloud_create(None, n, stride, d, C.byref(opts), C.byref(h))
+        return st, F.last_error()
+
+    ok = F.CCloudOpts(0.1, 20, 1e-3, 0)
+    assert create(100, 100, ok) == (F.ERR_INVALID_ARG, "fgs_cloud_create: ctx is NULL")
+    assert "k must be" in create(100, 100, F.CCloudOpts(0.1, 40, 1e-3, 0))[1]
+    assert "k must be" in create(100, 100, F.CCloudOpts(0.1, 2, 1e-3, 0))[1]
+    assert "outside [k" in create(10, 10, ok)[1]
+    assert "stride" in create(100, 50, ok)[1]
+    assert "cell" in create(100, 100, F.CCloudOpts(0.0, 20, 1e-3, 0))[1]
+    assert "eps" in create(100, 100, F.CCloudOpts(0.1, 20, 0.0, 0))[1]
+    T = (C.c_double * 16)(*np.eye(4).reshape(16))
+    r = F.CGicpResult()
+    assert F._lib.fgs_gicp_align(None, None, None, T, C.byref(F.CGicpOpts(0.1, 0, 1e-6, 1e-6)), C.byref(r)) == \
+        F.ERR_INVALID_ARG and "max_iter" in F.last_error()
+    assert F._lib.fgs_gicp_align(None, None, None, T, C.byref(F.CGicpOpts(0.1, 10, 1e-6, 1e-6)), C.byref(r)) == \
+        F.ERR_INVALID_ARG and "ctx is NULL" in F.last_error()
+    out = C.cast(C.c_void_p(0x2000), C.POINTER(C.c_double))
+    assert F._lib.fgs_gicp_linearize(None, None, None, T, 0.1, out, None) == F.ERR_INVALID_ARG
+    assert F._lib.fgs_cloud_read(None, None, None, None, None) == F.ERR_INVALID_ARG
+    assert F._lib.fgs_cloud_destroy(None) == F.OK
