@@ -91,7 +91,8 @@ typedef struct {
 
 /* Aligns the source cloud to the target cloud (Eq. 14) from T_init [host] by Gauss-Newton, every
  * iteration on the GPU (correspondences and the sums of H, b in one launch, the 6x6 solve and the
- * pose update in a second; iterations after convergence do nothing). Waits for the stream and
+ * pose update in a second). Iterations are enqueued in small batches with a wait for the stream
+ * between batches, and none is enqueued once the pose has converged. Waits for the stream and
  * fills *result [host]. */
 fgs_status fgs_gicp_align(fgs_ctx *ctx, const fgs_cloud *source, const fgs_cloud *target, const double T_init[16],
                           const fgs_gicp_opts *o, fgs_gicp_result *result);

@@ -2054,6 +2054,9 @@ struct fgs_cloud {
 
 namespace {
 
+// Gauss-Newton iterations enqueued before the first and between later reads of the done flag.
+constexpr int kGicpFirstBatch = 4, kGicpBatch = 2;
+
 // Grows a context buffer after the stream has drained (work in flight may still use the old one).
 hipError_t grow(fgs_ctx *ctx, DBuf &b, size_t bytes)
 {
@@ -2289,14 +2292,27 @@ fgs_status fgs_gicp_align(fgs_ctx *ctx, const fgs_cloud *source, const fgs_cloud
     fgs_status st = gicp_setup(ctx, source, target, T_init, o->d_max, w, &K);
     if (st != FGS_OK) return st;
     GicpState *sd = ctx->gicp_state.as<GicpState>();
+    if (!ctx->gicp_host) HIP_TRY(ctx, hipHostMalloc(&ctx->gicp_host, sizeof(GicpState), hipHostMallocDefault));
     {
+        // Iterations are enqueued a few at a time and the done flag is read back between batches:
+        // once the pose has converged the rest of the iterations are not launched at all (each
+        // would still cost two launches that find the flag set).
         Stage st_(ctx, "gicp");
-        for (int it = 0; it < o->max_iter; ++it)
-            launch_gicp_iteration(K, sd, ctx->gicp_part.as<double>(), nullptr, 1, o->max_iter, o->eps_rot,
-                                  o->eps_trans, nullptr, ctx->stream);
+        int launched = 0;
+        volatile int32_t *done_host = &((GicpState *)ctx->gicp_host)->done;
+        while (launched < o->max_iter) {
+            const int batch = std::min(launched == 0 ? kGicpFirstBatch : kGicpBatch, o->max_iter - launched);
+            for (int it = 0; it < batch; ++it)
+                launch_gicp_iteration(K, sd, ctx->gicp_part.as<double>(), nullptr, 1, o->max_iter, o->eps_rot,
+                                      o->eps_trans, nullptr, ctx->stream);
+            launched += batch;
+            if (launched >= o->max_iter) break;
+            HIP_TRY(ctx, hipMemcpyAsync((void *)done_host, &sd->done, 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            if (*done_host) break;
+        }
     }
     HIP_TRY(ctx, hipGetLastError());
-    if (!ctx->gicp_host) HIP_TRY(ctx, hipHostMalloc(&ctx->gicp_host, sizeof(GicpState), hipHostMallocDefault));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->gicp_host, sd, sizeof(GicpState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const GicpState &hs = *(const GicpState *)ctx->gicp_host;

@@ -35,6 +35,8 @@ constexpr int kKMax = 32;
 constexpr int kKnnThreads = 128;
 constexpr int kKnnRings = 4;  // rings of cells searched before a query scans the whole cloud
 constexpr int kCorrThreads = 256, kCorrLanes = 16, kCorrQueries = kCorrThreads / kCorrLanes;
+constexpr int kCorrBatches = 1;  // batches of kCorrQueries source points per workgroup (more serialise the
+                                 // groups' latency chains: 4 batches made the launch 1.5x slower)
 constexpr int kBoxBlocks = 256, kBoxThreads = 256;
 
 struct PoseK {
@@ -198,6 +200,27 @@ __global__ void k_gather_cells(const uint32_t *__restrict__ vals, const float *_
 
 // ------------------------------- neighbours, covariances -------------------------------
 
+// Squared distance from p to the box of cell (X, Y, Z) widened by the grid's margin on every side:
+// every point filed in that cell lies inside the widened box (its cell index carries at most that
+// much rounding), so none of them is closer than this. The box bounds' own rounding stays far
+// below the margin.
+__device__ inline float cell_box_d2(const GridK &g, int X, int Y, int Z, const float p[3])
+{
+    const float m = g.margin * g.c;
+    const float lo[3] = {g.ox + (float)X * g.c - m, g.oy + (float)Y * g.c - m, g.oz + (float)Z * g.c - m};
+    float d2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float e = fmaxf(0.0f, fmaxf(lo[a] - p[a], p[a] - (lo[a] + g.c + 2.0f * m)));
+        d2 += e * e;
+    }
+    return d2;
+}
+
+// A cell whose widened box is this far cannot hold a point at squared distance `best` or less
+// (the 1e-5 absorbs the binary32 rounding of both distances).
+__device__ inline bool cell_beyond(float box_d2, float best) { return box_d2 > best * (1.0f + 1e-5f); }
+
 // (d, j) comes before (e, l)
 __device__ inline bool ahead(float d, uint32_t j, float e, uint32_t l) { return d < e || (d == e && j < l); }
 
@@ -287,6 +310,17 @@ k_knn_cov(GridK g, const uint2 *__restrict__ ranges, const float4 *__restrict__ 
     const int cy = clampi(cell_of(q.y, g.oy, g.inv_c), 0, g.gy - 1);
     const int cz = clampi(cell_of(q.z, g.oz, g.inv_c), 0, g.gz - 1);
     const int rmax = max(g.gx, max(g.gy, g.gz));
+    const float qp[3] = {q.x, q.y, q.z};
+    auto visit = [&](int X, int Y, int Z) {
+        const uint2 rg = ranges[((int64_t)Z * g.gy + Y) * g.gx + X];
+        for (uint32_t p = rg.x; p < rg.y; ++p) {
+            const float4 c = pts[p];
+            const float ex = c.x - q.x, ey = c.y - q.y, ez = c.z - q.z;
+            knn_insert(bd, bi, (ex * ex + ey * ey) + ez * ez, __float_as_uint(c.w));
+        }
+    };
+    // the point's own cell first, so that its neighbours prune the cells around it
+    visit(cx, cy, cz);
     bool found = false;
     for (int ring = 1; ring <= kKnnRings; ++ring) {
         for (int dz = -ring; dz <= ring; ++dz) {
@@ -299,13 +333,9 @@ k_knn_cov(GridK g, const uint2 *__restrict__ ranges, const float4 *__restrict__ 
                 // on an inner (y, z) line of a shell only its two end cells are new
                 for (int dx = -ring; dx <= ring; dx += inner ? 2 * ring : 1) {
                     const int X = cx + dx;
-                    if (X < 0 || X >= g.gx) continue;
-                    const uint2 rg = ranges[((int64_t)Z * g.gy + Y) * g.gx + X];
-                    for (uint32_t p = rg.x; p < rg.y; ++p) {
-                        const float4 c = pts[p];
-                        const float ex = c.x - q.x, ey = c.y - q.y, ez = c.z - q.z;
-                        knn_insert(bd, bi, (ex * ex + ey * ey) + ez * ez, __float_as_uint(c.w));
-                    }
+                    if (X < 0 || X >= g.gx || (dx == 0 && dy == 0 && dz == 0)) continue;
+                    if (cell_beyond(cell_box_d2(g, X, Y, Z, qp), bd[kKMax - 1])) continue;
+                    visit(X, Y, Z);
                 }
             }
         }
@@ -370,6 +400,20 @@ k_knn_cov(GridK g, const uint2 *__restrict__ ranges, const float4 *__restrict__ 
 
 constexpr int kSums = 29;  // H upper triangle (21), b (6), cost, count
 
+// (bd, bj) <- the first by (distance, index) over the kCorrLanes lanes of a query's group
+__device__ inline void group_min(float &bd, uint32_t &bj)
+{
+#pragma unroll
+    for (int o = kCorrLanes / 2; o > 0; o >>= 1) {
+        const float od = __shfl_xor(bd, o, kCorrLanes);
+        const uint32_t oj = __shfl_xor(bj, o, kCorrLanes);
+        if (ahead(od, oj, bd, bj)) {
+            bd = od;
+            bj = oj;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kCorrThreads)
 k_gicp_corr(GridK g, const uint2 *__restrict__ ranges, const float4 *__restrict__ tpts, const float *__restrict__ tx,
             const float *__restrict__ ty, const float *__restrict__ tz, const double *__restrict__ tcov, int64_t nt,
@@ -380,109 +424,121 @@ k_gicp_corr(GridK g, const uint2 *__restrict__ ranges, const float4 *__restrict_
     __shared__ double red[kCorrQueries][kSums + 1];
     if (st->done) return;
     const int tid = threadIdx.x, ql = tid / kCorrLanes, lane = tid % kCorrLanes;
-    const int64_t i = (int64_t)blockIdx.x * kCorrQueries + ql;
-    float bd = INFINITY;
-    uint32_t bj = 0xffffffffu;
-    if (i < ns) {
-        const float x = sx[i], y = sy[i], z = sz[i];
-        float p[3];
-        for (int r = 0; r < 3; ++r) {
-            float w = st->R32[3 * r] * x;
-            w = w + st->R32[3 * r + 1] * y;
-            w = w + st->R32[3 * r + 2] * z;
-            p[r] = w + st->t32[r];
-        }
-        const int cx = cell_of(p[0], g.ox, g.inv_c), cy = cell_of(p[1], g.oy, g.inv_c),
-                  cz = cell_of(p[2], g.oz, g.inv_c);
-        const int side = 2 * rings + 1, cells = side * side * side;
-        for (int c = lane; c < cells; c += kCorrLanes) {
-            const int X = cx + c % side - rings, Y = cy + (c / side) % side - rings, Z = cz + c / (side * side) - rings;
-            if (X < 0 || X >= g.gx || Y < 0 || Y >= g.gy || Z < 0 || Z >= g.gz) continue;
-            const uint2 rg = ranges[((int64_t)Z * g.gy + Y) * g.gx + X];
-            for (uint32_t k = rg.x; k < rg.y; ++k) {
-                const float4 q = tpts[k];
-                const uint32_t j = __float_as_uint(q.w);
-                const float ex = q.x - p[0], ey = q.y - p[1], ez = q.z - p[2];
-                const float d2 = (ex * ex + ey * ey) + ez * ez;
-                if (d2 <= dm2 && ahead(d2, j, bd, bj)) {
-                    bd = d2;
-                    bj = j;
-                }
+    if (lane == 0)
+        for (int k = 0; k < kSums; ++k) red[ql][k] = 0.0;
+    // the workgroup's kCorrBatches batches of kCorrQueries source points, one point per group
+    for (int batch = 0; batch < kCorrBatches; ++batch) {
+        const int64_t i = ((int64_t)blockIdx.x * kCorrBatches + batch) * kCorrQueries + ql;
+        float bd = INFINITY;
+        uint32_t bj = 0xffffffffu;
+        float p[3] = {0.0f, 0.0f, 0.0f};
+        int cx = 0, cy = 0, cz = 0;
+        auto scan_point = [&](const float4 q) {
+            const uint32_t j = __float_as_uint(q.w);
+            const float ex = q.x - p[0], ey = q.y - p[1], ez = q.z - p[2];
+            const float d2 = (ex * ex + ey * ey) + ez * ez;
+            if (d2 <= dm2 && ahead(d2, j, bd, bj)) {
+                bd = d2;
+                bj = j;
+            }
+        };
+        if (i < ns) {
+            const float x = sx[i], y = sy[i], z = sz[i];
+            for (int r = 0; r < 3; ++r) {
+                float w = st->R32[3 * r] * x;
+                w = w + st->R32[3 * r + 1] * y;
+                w = w + st->R32[3 * r + 2] * z;
+                p[r] = w + st->t32[r];
+            }
+            cx = cell_of(p[0], g.ox, g.inv_c);
+            cy = cell_of(p[1], g.oy, g.inv_c);
+            cz = cell_of(p[2], g.oz, g.inv_c);
+            // the query's own cell first, its points split over the group's lanes
+            if (cx >= 0 && cx < g.gx && cy >= 0 && cy < g.gy && cz >= 0 && cz < g.gz) {
+                const uint2 rg = ranges[((int64_t)cz * g.gy + cy) * g.gx + cx];
+                for (uint32_t k = rg.x + lane; k < rg.y; k += kCorrLanes) scan_point(tpts[k]);
             }
         }
-    }
-    for (int o = kCorrLanes / 2; o > 0; o >>= 1) {
-        const float od = __shfl_xor(bd, o, kCorrLanes);
-        const uint32_t oj = __shfl_xor(bj, o, kCorrLanes);
-        if (ahead(od, oj, bd, bj)) {
-            bd = od;
-            bj = oj;
+        group_min(bd, bj);
+        if (i < ns) {
+            // the other cells of the search block, skipping those that cannot beat the group's best
+            const int side = 2 * rings + 1, cells = side * side * side, centre = (rings * side + rings) * side + rings;
+            const float best = fminf(bd, dm2);
+            for (int c = lane; c < cells; c += kCorrLanes) {
+                if (c == centre) continue;
+                const int X = cx + c % side - rings, Y = cy + (c / side) % side - rings, Z = cz + c / (side * side) - rings;
+                if (X < 0 || X >= g.gx || Y < 0 || Y >= g.gy || Z < 0 || Z >= g.gz) continue;
+                if (cell_beyond(cell_box_d2(g, X, Y, Z, p), best)) continue;
+                const uint2 rg = ranges[((int64_t)Z * g.gy + Y) * g.gx + X];
+                for (uint32_t k = rg.x; k < rg.y; ++k) scan_point(tpts[k]);
+            }
         }
-    }
-    if (lane == 0) {
-        double v[kSums];
-        for (int k = 0; k < kSums; ++k) v[k] = 0.0;
-        if (i < ns && corr) corr[i] = bj == 0xffffffffu ? -1 : (int32_t)bj;
-        if (i < ns && bj != 0xffffffffu) {
-            const double *R = st->R, *t = st->t;
-            const double p0 = sx[i], p1 = sy[i], p2 = sz[i];
-            double Tp[3], d[3];
-            for (int r = 0; r < 3; ++r) Tp[r] = R[3 * r] * p0 + R[3 * r + 1] * p1 + R[3 * r + 2] * p2 + t[r];
-            d[0] = (double)tx[bj] - Tp[0];
-            d[1] = (double)ty[bj] - Tp[1];
-            d[2] = (double)tz[bj] - Tp[2];
-            // C = C_q + R C_p R^T (Eq. 13)
-            const double cp[6] = {scov[i], scov[ns + i], scov[2 * ns + i], scov[3 * ns + i], scov[4 * ns + i],
-                                  scov[5 * ns + i]};
-            const double Cp[3][3] = {{cp[0], cp[1], cp[2]}, {cp[1], cp[3], cp[4]}, {cp[2], cp[4], cp[5]}};
-            double M[3][3];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    double s = 0.0;
-                    for (int u = 0; u < 3; ++u) {
-                        double rc = 0.0;
-                        for (int w = 0; w < 3; ++w) rc += R[3 * a + w] * Cp[w][u];
-                        s += rc * R[3 * b + u];
+        group_min(bd, bj);
+        if (lane == 0) {
+            double v[kSums];
+            for (int k = 0; k < kSums; ++k) v[k] = 0.0;
+            if (i < ns && corr) corr[i] = bj == 0xffffffffu ? -1 : (int32_t)bj;
+            if (i < ns && bj != 0xffffffffu) {
+                const double *R = st->R, *t = st->t;
+                const double p0 = sx[i], p1 = sy[i], p2 = sz[i];
+                double Tp[3], d[3];
+                for (int r = 0; r < 3; ++r) Tp[r] = R[3 * r] * p0 + R[3 * r + 1] * p1 + R[3 * r + 2] * p2 + t[r];
+                d[0] = (double)tx[bj] - Tp[0];
+                d[1] = (double)ty[bj] - Tp[1];
+                d[2] = (double)tz[bj] - Tp[2];
+                // C = C_q + R C_p R^T (Eq. 13)
+                const double cp[6] = {scov[i], scov[ns + i], scov[2 * ns + i], scov[3 * ns + i], scov[4 * ns + i],
+                                      scov[5 * ns + i]};
+                const double Cp[3][3] = {{cp[0], cp[1], cp[2]}, {cp[1], cp[3], cp[4]}, {cp[2], cp[4], cp[5]}};
+                double M[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double s = 0.0;
+                        for (int u = 0; u < 3; ++u) {
+                            double rc = 0.0;
+                            for (int w = 0; w < 3; ++w) rc += R[3 * a + w] * Cp[w][u];
+                            s += rc * R[3 * b + u];
+                        }
+                        M[a][b] = s;
                     }
-                    M[a][b] = s;
+                M[0][0] += tcov[bj];
+                M[0][1] += tcov[nt + bj];
+                M[0][2] += tcov[2 * nt + bj];
+                M[1][0] += tcov[nt + bj];
+                M[1][1] += tcov[3 * nt + bj];
+                M[1][2] += tcov[4 * nt + bj];
+                M[2][0] += tcov[2 * nt + bj];
+                M[2][1] += tcov[4 * nt + bj];
+                M[2][2] += tcov[5 * nt + bj];
+                // W = M^-1 from the cofactors (M is symmetric positive definite)
+                const double k00 = M[1][1] * M[2][2] - M[1][2] * M[2][1], k01 = M[0][2] * M[2][1] - M[0][1] * M[2][2],
+                             k02 = M[0][1] * M[1][2] - M[0][2] * M[1][1], k11 = M[0][0] * M[2][2] - M[0][2] * M[2][0],
+                             k12 = M[0][2] * M[1][0] - M[0][0] * M[1][2], k22 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+                const double det = M[0][0] * k00 + M[1][0] * k01 + M[2][0] * k02;
+                if (det != 0.0 && isfinite(det)) {
+                    const double id = 1.0 / det;
+                    const double W[3][3] = {{k00 * id, k01 * id, k02 * id},
+                                            {k01 * id, k11 * id, k12 * id},
+                                            {k02 * id, k12 * id, k22 * id}};
+                    // J = [[Tp]_x, -I]
+                    const double J[3][6] = {{0.0, -Tp[2], Tp[1], -1.0, 0.0, 0.0},
+                                            {Tp[2], 0.0, -Tp[0], 0.0, -1.0, 0.0},
+                                            {-Tp[1], Tp[0], 0.0, 0.0, 0.0, -1.0}};
+                    double WJ[3][6], Wd[3];
+                    for (int r = 0; r < 3; ++r) {
+                        Wd[r] = W[r][0] * d[0] + W[r][1] * d[1] + W[r][2] * d[2];
+                        for (int c = 0; c < 6; ++c) WJ[r][c] = W[r][0] * J[0][c] + W[r][1] * J[1][c] + W[r][2] * J[2][c];
+                    }
+                    int h = 0;
+                    for (int a = 0; a < 6; ++a)
+                        for (int b = a; b < 6; ++b) v[h++] = J[0][a] * WJ[0][b] + J[1][a] * WJ[1][b] + J[2][a] * WJ[2][b];
+                    for (int a = 0; a < 6; ++a) v[21 + a] = J[0][a] * Wd[0] + J[1][a] * Wd[1] + J[2][a] * Wd[2];
+                    v[27] = d[0] * Wd[0] + d[1] * Wd[1] + d[2] * Wd[2];
+                    v[28] = 1.0;
                 }
-            M[0][0] += tcov[bj];
-            M[0][1] += tcov[nt + bj];
-            M[0][2] += tcov[2 * nt + bj];
-            M[1][0] += tcov[nt + bj];
-            M[1][1] += tcov[3 * nt + bj];
-            M[1][2] += tcov[4 * nt + bj];
-            M[2][0] += tcov[2 * nt + bj];
-            M[2][1] += tcov[4 * nt + bj];
-            M[2][2] += tcov[5 * nt + bj];
-            // W = M^-1 from the cofactors (M is symmetric positive definite)
-            const double k00 = M[1][1] * M[2][2] - M[1][2] * M[2][1], k01 = M[0][2] * M[2][1] - M[0][1] * M[2][2],
-                         k02 = M[0][1] * M[1][2] - M[0][2] * M[1][1], k11 = M[0][0] * M[2][2] - M[0][2] * M[2][0],
-                         k12 = M[0][2] * M[1][0] - M[0][0] * M[1][2], k22 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-            const double det = M[0][0] * k00 + M[1][0] * k01 + M[2][0] * k02;
-            if (det != 0.0 && isfinite(det)) {
-                const double id = 1.0 / det;
-                const double W[3][3] = {{k00 * id, k01 * id, k02 * id},
-                                        {k01 * id, k11 * id, k12 * id},
-                                        {k02 * id, k12 * id, k22 * id}};
-                // J = [[Tp]_x, -I]
-                const double J[3][6] = {{0.0, -Tp[2], Tp[1], -1.0, 0.0, 0.0},
-                                        {Tp[2], 0.0, -Tp[0], 0.0, -1.0, 0.0},
-                                        {-Tp[1], Tp[0], 0.0, 0.0, 0.0, -1.0}};
-                double WJ[3][6], Wd[3];
-                for (int r = 0; r < 3; ++r) {
-                    Wd[r] = W[r][0] * d[0] + W[r][1] * d[1] + W[r][2] * d[2];
-                    for (int c = 0; c < 6; ++c) WJ[r][c] = W[r][0] * J[0][c] + W[r][1] * J[1][c] + W[r][2] * J[2][c];
-                }
-                int h = 0;
-                for (int a = 0; a < 6; ++a)
-                    for (int b = a; b < 6; ++b) v[h++] = J[0][a] * WJ[0][b] + J[1][a] * WJ[1][b] + J[2][a] * WJ[2][b];
-                for (int a = 0; a < 6; ++a) v[21 + a] = J[0][a] * Wd[0] + J[1][a] * Wd[1] + J[2][a] * Wd[2];
-                v[27] = d[0] * Wd[0] + d[1] * Wd[1] + d[2] * Wd[2];
-                v[28] = 1.0;
             }
+            for (int k = 0; k < kSums; ++k) red[ql][k] += v[k];
         }
-        for (int k = 0; k < kSums; ++k) red[ql][k] = v[k];
     }
     __syncthreads();
     if (tid < kSums) {
@@ -522,9 +578,18 @@ k_gicp_solve(const double *__restrict__ partials, int nb, GicpState *st, int upd
     const int tid = threadIdx.x;
     if (tid < kSums * 32) {
         const int v = tid / 32, s = tid % 32;
-        double a = 0.0;
-        for (int b = s; b < nb; b += 32) a += partials[(int64_t)b * kSums + v];
-        part[v][s] = a;
+        // four loads in flight per step (the partials come from every XCD, so each is a trip to
+        // memory); the order of the sums is fixed
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = s;
+        for (; b + 96 < nb; b += 128) {
+            a0 += partials[(int64_t)b * kSums + v];
+            a1 += partials[(int64_t)(b + 32) * kSums + v];
+            a2 += partials[(int64_t)(b + 64) * kSums + v];
+            a3 += partials[(int64_t)(b + 96) * kSums + v];
+        }
+        for (; b < nb; b += 32) a0 += partials[(int64_t)b * kSums + v];
+        part[v][s] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
     if (tid < kSums) {
@@ -537,25 +602,26 @@ k_gicp_solve(const double *__restrict__ partials, int nb, GicpState *st, int upd
     if (!update || tid != 0) return;
     st->cost = tot[27];
     st->count = (int64_t)tot[28];
-    double H[6][6], x[6];
-    int h = 0;
-    for (int a = 0; a < 6; ++a)
-        for (int b = a; b < 6; ++b) H[a][b] = H[b][a] = tot[h++];
-    // Cholesky H = L L^T, then L y = -b, L^T x = y
-    double L[6][6];
+    // Cholesky H = L L^T, then L y = -b, L^T x = y; fully unrolled so that H and L stay in
+    // registers (indexed at run time they would live in scratch memory)
+    double H[6][6], L[6][6], x[6], yv[6];
+#pragma unroll
+    for (int a = 0, h = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b, ++h) H[a][b] = H[b][a] = tot[h];
     bool ok = st->count >= 6;
-    for (int a = 0; a < 6 && ok; ++a)
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
         for (int b = 0; b <= a; ++b) {
-            double s = H[a][b];
-            for (int c = 0; c < b; ++c) s -= L[a][c] * L[b][c];
+            double v = H[a][b];
+#pragma unroll
+            for (int c = 0; c < b; ++c) v -= L[a][c] * L[b][c];
             if (a == b) {
-                if (!(s > 0.0)) {
-                    ok = false;
-                    break;
-                }
-                L[a][a] = sqrt(s);
+                ok = ok && v > 0.0;
+                L[a][a] = sqrt(ok ? v : 1.0);
             } else {
-                L[a][b] = s / L[b][b];
+                L[a][b] = v / L[b][b];
             }
         }
     if (!ok) {
@@ -563,16 +629,19 @@ k_gicp_solve(const double *__restrict__ partials, int nb, GicpState *st, int upd
         st->done = 1;
         return;
     }
-    double yv[6];
+#pragma unroll
     for (int a = 0; a < 6; ++a) {
-        double s = -tot[21 + a];
-        for (int c = 0; c < a; ++c) s -= L[a][c] * yv[c];
-        yv[a] = s / L[a][a];
+        double v = -tot[21 + a];
+#pragma unroll
+        for (int c = 0; c < a; ++c) v -= L[a][c] * yv[c];
+        yv[a] = v / L[a][a];
     }
+#pragma unroll
     for (int a = 5; a >= 0; --a) {
-        double s = yv[a];
-        for (int c = a + 1; c < 6; ++c) s -= L[c][a] * x[c];
-        x[a] = s / L[a][a];
+        double v = yv[a];
+#pragma unroll
+        for (int c = a + 1; c < 6; ++c) v -= L[c][a] * x[c];
+        x[a] = v / L[a][a];
     }
     double E[3][3];
     rot_exp(x, E);
@@ -669,7 +738,10 @@ void launch_knn_cov(const GridK &g, const uint2 *ranges, const float4 *pts, int6
                        ranges, pts, n, k, eps, x, y, z, knn_out, cov);
 }
 
-int64_t gicp_partials(int64_t ns) { return (ns + kCorrQueries - 1) / kCorrQueries; }
+int64_t gicp_partials(int64_t ns)
+{
+    return (ns + kCorrQueries * kCorrBatches - 1) / (kCorrQueries * kCorrBatches);
+}
 
 void launch_gicp_iteration(const GicpK &k, GicpState *st, double *partials, int32_t *corr, int update, int max_iter,
                            double eps_rot, double eps_trans, double *out, hipStream_t s)
