@@ -61,7 +61,8 @@ typedef struct {
 
 /* Builds a cloud from n >= k points (xyz: 3 planes of stride `stride`, copied; the caller's
  * buffer may be reused afterwards): bounding box, grid (points sorted by cell), neighbours and
- * covariances. Waits for the stream once (for the bounding box that sizes the grid). */
+ * covariances. Waits for the stream once (for the bounding box that sizes the grid); points with a
+ * non-finite coordinate make it return FGS_ERR_INVALID_ARG. */
 fgs_status fgs_cloud_create(fgs_ctx *ctx, int64_t n, int64_t stride, const float *xyz, const fgs_cloud_opts *o,
                             fgs_cloud **out);
 fgs_status fgs_cloud_destroy(fgs_cloud *c);

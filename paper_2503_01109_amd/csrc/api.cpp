@@ -2188,14 +2188,17 @@ fgs_status fgs_cloud_create(fgs_ctx *ctx, int64_t n, int64_t stride, const float
                                     hipMemcpyDeviceToDevice, s));
     const float *X = c->xyz.as<float>(), *Y = X + n, *Z = X + 2 * n;
     // bounding box -> grid
-    // cl_box: the box (6 floats, padded to 8), the partial boxes, then the point count for the sort
-    HIP_TRY(ctx, grow(ctx, ctx->cl_box, ((size_t)8 + 6 * (size_t)bbox_partials() + 8) * 4));
+    // cl_box: the box and the non-finite count (7 floats, padded to 8), the partial results, then
+    // the point count for the sort
+    HIP_TRY(ctx, grow(ctx, ctx->cl_box, ((size_t)8 + (size_t)bbox_partials() + 8) * 4));
     float *box = ctx->cl_box.as<float>();
-    uint32_t *ndev = (uint32_t *)(box + 8 + 6 * bbox_partials());
+    uint32_t *ndev = (uint32_t *)(box + 8 + bbox_partials());
     launch_bbox(X, Y, Z, n, box + 8, box, s);
-    float hb[6];
-    HIP_TRY(ctx, hipMemcpyAsync(hb, box, 24, hipMemcpyDeviceToHost, s));
+    float hb[7];
+    HIP_TRY(ctx, hipMemcpyAsync(hb, box, 28, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (hb[6] != 0.0f)
+        return fail(ctx, FGS_ERR_INVALID_ARG, "%s: %.0f points have a non-finite coordinate", w, (double)hb[6]);
     for (int q = 0; q < 6; ++q)
         if (!std::isfinite(hb[q])) return fail(ctx, FGS_ERR_INVALID_ARG, "%s: points are not finite", w);
     const double cell = (double)o->cell;

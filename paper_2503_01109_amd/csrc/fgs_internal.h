@@ -376,8 +376,9 @@ struct GridK {
     int32_t gx, gy, gz;
     float margin;
 };
-int bbox_partials();
-// min x, y, z and max x, y, z of n points into out (6 floats); part: bbox_partials() x 6 floats.
+int bbox_partials();  // floats of launch_bbox's partial results
+// min x, y, z, max x, y, z of n points and (as a float) the number of points with a non-finite
+// coordinate into out (7 floats); part: bbox_partials() floats.
 void launch_bbox(const float *x, const float *y, const float *z, int64_t n, float *part, float *out, hipStream_t s);
 void launch_cell_keys(const GridK &g, const float *x, const float *y, const float *z, int64_t n, uint32_t *keys,
                       uint32_t *vals, hipStream_t s);

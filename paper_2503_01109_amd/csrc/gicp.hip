@@ -37,7 +37,7 @@ constexpr int kKnnRings = 4;  // rings of cells searched before a query scans th
 constexpr int kCorrThreads = 256, kCorrLanes = 16, kCorrQueries = kCorrThreads / kCorrLanes;
 constexpr int kCorrBatches = 1;  // batches of kCorrQueries source points per workgroup (more serialise the
                                  // groups' latency chains: 4 batches made the launch 1.5x slower)
-constexpr int kBoxBlocks = 256, kBoxThreads = 256;
+constexpr int kBoxBlocks = 256, kBoxThreads = 256, kBoxOut = 7;
 
 struct PoseK {
     double R[9], t[3];
@@ -136,38 +136,45 @@ __global__ void __launch_bounds__(kBoxThreads)
 k_bbox_part(const float *__restrict__ x, const float *__restrict__ y, const float *__restrict__ z, int64_t n,
             float *__restrict__ part)
 {
-    __shared__ float red[6][kBoxThreads / kWave];
-    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    __shared__ float red[kBoxOut][kBoxThreads / kWave];
+    // min x, y, z, max x, y, z, and the number of points with a non-finite coordinate (fminf and
+    // fmaxf pass over NaN, so those are counted apart)
+    float v[kBoxOut] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0f};
     for (int64_t i = (int64_t)blockIdx.x * kBoxThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBoxThreads) {
         const float a[3] = {x[i], y[i], z[i]};
         for (int c = 0; c < 3; ++c) {
             v[c] = fminf(v[c], a[c]);
             v[3 + c] = fmaxf(v[3 + c], a[c]);
         }
+        v[6] += (isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2])) ? 0.0f : 1.0f;
     }
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < kBoxOut; ++c) {
         float t = v[c];
         for (int o = kWave / 2; o > 0; o >>= 1) {
             const float u = __shfl_xor(t, o);
-            t = c < 3 ? fminf(t, u) : fmaxf(t, u);
+            t = c < 3 ? fminf(t, u) : (c < 6 ? fmaxf(t, u) : t + u);
         }
         if (__lane_id() == 0) red[c][threadIdx.x / kWave] = t;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < kBoxOut) {
         const int c = threadIdx.x;
         float t = red[c][0];
-        for (int w = 1; w < kBoxThreads / kWave; ++w) t = c < 3 ? fminf(t, red[c][w]) : fmaxf(t, red[c][w]);
-        part[blockIdx.x * 6 + c] = t;
+        for (int w = 1; w < kBoxThreads / kWave; ++w)
+            t = c < 3 ? fminf(t, red[c][w]) : (c < 6 ? fmaxf(t, red[c][w]) : t + red[c][w]);
+        part[blockIdx.x * kBoxOut + c] = t;
     }
 }
 
 __global__ void k_bbox_final(const float *__restrict__ part, int nb, float *__restrict__ out)
 {
     const int c = threadIdx.x;
-    if (c >= 6) return;
+    if (c >= kBoxOut) return;
     float t = part[c];
-    for (int b = 1; b < nb; ++b) t = c < 3 ? fminf(t, part[b * 6 + c]) : fmaxf(t, part[b * 6 + c]);
+    for (int b = 1; b < nb; ++b) {
+        const float u = part[b * kBoxOut + c];
+        t = c < 3 ? fminf(t, u) : (c < 6 ? fmaxf(t, u) : t + u);
+    }
     out[c] = t;
 }
 
@@ -706,7 +713,7 @@ void launch_frame_points(const FrameK &f, uint32_t *row_count, float *xyz, int64
     hipLaunchKernelGGL(k_fp_emit, dim3(rows), dim3(kFPThreads), 0, s, f, row_count, rows, xyz, capacity, n_dev);
 }
 
-int bbox_partials() { return kBoxBlocks; }
+int bbox_partials() { return kBoxBlocks * kBoxOut; }
 
 void launch_bbox(const float *x, const float *y, const float *z, int64_t n, float *part, float *out, hipStream_t s)
 {

@@ -136,6 +136,27 @@ def check_rings_cloud(fgs, ctx, cell, k):
     cl.close()
 
 
+def test_cloud_rejects_non_finite_points(fgs, ctx):
+    p = rings_cloud()[:, :500].copy()
+    for bad in (np.nan, np.inf):
+        q = p.copy()
+        q[1, 17] = bad
+        with pytest.raises(fgs.FgsError) as ei:
+            fgs.Cloud(ctx, dev(q), None, fgs.CloudOpts(cell=0.1, k=10))
+        assert ei.value.status == fgs.ERR_INVALID_ARG and "non-finite" in str(ei.value)
+
+
+def test_cloud_of_exactly_k_points(fgs, ctx):
+    """n = k: every point's neighbours are the whole cloud, in (distance, index) order."""
+    p = rings_cloud()[:, :16].copy()
+    cl = fgs.Cloud(ctx, dev(p), None, fgs.CloudOpts(cell=0.05, k=16, eps=1e-3, keep_knn=True))
+    cov, knn = cl.read()
+    idx, _ = oracle.knn(p, 16)
+    assert np.array_equal(host(knn), idx)
+    assert np.abs(host(cov) - oracle.cloud_cov(p, 16, 1e-3)).max() < 1e-9
+    cl.close()
+
+
 def test_linearisation_matches_oracle(fgs, ctx):
     S, T, src, tgt, keys, _ = clouds(fgs, ctx, 5)
     R0, t0 = synth.pose_wc(keys[0])
