@@ -251,7 +251,7 @@ def stage_work(w: dict, N: int, K: float, P: int, T: int) -> dict:
     their sum over the groups is B_alg = 768 N + 44 K + 44 (L_f + L_b) + 40 K_c + 96 P + 24 T."""
     return {
         "project": (108.0 * N, 0.0, ("project",)),
-        "binning": (20.0 * N + B_PER_PAIR * K + B_PER_TILE * T, 0.0, ("depth_sort", "bin", "tile_sort")),
+        "binning": (20.0 * N + B_PER_PAIR * K + B_PER_TILE * T, 0.0, ("depth_sort", "bin", "tile_sort", "tile_bin")),
         "raster_fwd": (B_PER_ENTRY * w["L_f"] + 72.0 * P, F_FWD_EXAMINED * w["E_f"] + F_FWD_BLENDED * w["E_c"],
                        ("raster_fwd", "loss")),
         "raster_bwd": (B_PER_ENTRY * w["L_b"] + B_PER_KC * w["K_c"] + 24.0 * P, F_BWD_BLENDED * w["E_c"],

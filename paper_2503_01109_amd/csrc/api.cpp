@@ -119,8 +119,9 @@ struct fgs_ctx {
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
     DBuf rect_sorted, start_rank, kpart;
+    DBuf segA, segB, segC, segD;  // sorted chunks (keys, positions) of super-tile lists being merged
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
-    DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words;
+    DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words, bin_sstart;
     int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
     DBuf words;  // status words (ST_WORDS) + small device scalars
     int64_t ws_n = -1, ws_cap = -1;
@@ -311,6 +312,10 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvB.ensure(C * 4));
+    HIP_TRY(ctx, ctx->segA.ensure(C * 4));
+    HIP_TRY(ctx, ctx->segB.ensure(C * 4));
+    HIP_TRY(ctx, ctx->segC.ensure(C * 4));
+    HIP_TRY(ctx, ctx->segD.ensure(C * 4));
     const int G = std::max(sort_blocks(nn, kDepthSortPerBlock), sort_blocks(cc > nn ? cc : nn, kPairSortPerBlock));
     HIP_TRY(ctx, ctx->hist.ensure(((size_t)G * 256 + 256) * 4));
     ctx->hist_G = G;
@@ -335,6 +340,7 @@ fgs_status ensure_bin(fgs_ctx *ctx, int64_t nsup, int64_t T, int64_t cap)
     ctx->ws_gen++;
     HIP_TRY(ctx, ctx->bin_sranges.ensure((size_t)ns * 8));
     HIP_TRY(ctx, ctx->bin_cstart.ensure((size_t)(ns + 1) * 4));
+    HIP_TRY(ctx, ctx->bin_sstart.ensure((size_t)(ns + 1) * 4));
     HIP_TRY(ctx, ctx->bin_csuper.ensure((size_t)mc * 4));
     HIP_TRY(ctx, ctx->bin_chist.ensure((size_t)mc * kSuper * kSuper * 4));
     HIP_TRY(ctx, ctx->bin_tile_total.ensure((size_t)tt * 4));
@@ -371,7 +377,7 @@ SortWS sort_ws(fgs_ctx *ctx, int64_t elems, int per_block = kPairSortPerBlock)
 
 struct StatePtrs {
     Rec *rec;
-    uint32_t *ids, *last, *vals;
+    uint32_t *last, *vals;
     uint2 *ranges;
     float *tfinal;
 };
@@ -379,7 +385,7 @@ struct StatePtrs {
 StatePtrs state_ptrs(void *state, const StateLayout &L)
 {
     char *b = (char *)state;
-    return StatePtrs{(Rec *)(b + L.off_rec), (uint32_t *)(b + L.off_ids), (uint32_t *)(b + L.off_last),
+    return StatePtrs{(Rec *)(b + L.off_rec), (uint32_t *)(b + L.off_last),
                      (uint32_t *)(b + L.off_vals), (uint2 *)(b + L.off_ranges), (float *)(b + L.off_tfinal)};
 }
 
@@ -503,10 +509,11 @@ struct ProjOut {
     uint32_t *count, *kpart;
 };
 
-// Enqueue the binning of a projected, depth-sorted view (the state's ids hold its depth order)
-// and, with raster, its forward rasterization. With K_check, the call waits for the pair count
-// after the scan and, when it exceeds the state's capacity, returns FGS_ERR_CAPACITY with the
-// count in *K_check before enqueueing the rest.
+// Enqueue the binning of a projected view and, with raster, its forward rasterization: one pair
+// per covered super-tile in gaussian order, the pairs sorted by super-tile (stably), every
+// super-tile list put in (depth, index) order, then expanded into the tile lists. With K_check,
+// the call waits for the pair count after the scan and, when it exceeds the state's capacity,
+// returns FGS_ERR_CAPACITY with the count in *K_check before enqueueing the rest.
 fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                               int tw, int th, const ImageK &img, void *state, const StateLayout &L, const ProjOut &po,
                               int64_t *K_check, uint32_t *host_status, bool raster, const LossK *loss,
@@ -524,15 +531,20 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     uint32_t *ktotal = words + W_KTOTAL;
     const BinWS bw = bin_ws(ctx);
     const int sbits = key_bits_for(nsup);
-    uint32_t *svals = (sbits + 7) / 8 == 1 ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
+    const bool one_pass = sbits <= 8;
+    // the super-tile sort leaves its values in svals and its keys in the other key buffer; the
+    // depth order goes into the remaining pair of buffers
+    uint32_t *svals = one_pass ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
+    uint32_t *okeys = one_pass ? ctx->pkA.as<uint32_t>() : ctx->pkB.as<uint32_t>();
+    uint32_t *ovals = one_pass ? ctx->pvA.as<uint32_t>() : ctx->pvB.as<uint32_t>();
     {
-        // one pair per covered super-tile, in depth order
+        // one pair per covered super-tile, in gaussian order (the projection wrote ids 0..n-1)
         Stage st_(ctx, "bin");
-        launch_scan_counts(sp.ids, po.count, g.n, ctx->blocksums.as<uint32_t>(), s);
-        launch_emit(sp.ids, po.count, po.rect, ctx->blocksums.as<uint32_t>(), ctx->offsets.as<uint32_t>(), g.n,
-                    supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(),
-                    ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(), status_words(ctx), nsup_pairs,
-                    nullptr, po.kpart, project_blocks(g.n), ktotal, s);
+        launch_scan_counts(ctx->idA.as<uint32_t>(), po.count, g.n, ctx->blocksums.as<uint32_t>(), s);
+        launch_emit(ctx->idA.as<uint32_t>(), po.count, po.rect, ctx->blocksums.as<uint32_t>(),
+                    ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(),
+                    ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(),
+                    status_words(ctx), nsup_pairs, nullptr, po.kpart, project_blocks(g.n), ktotal, s);
     }
     if (K_check) {
         // the pair count is known once the scan is complete (the emission of an oversized set
@@ -542,19 +554,27 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         *K_check = ctx->host_words[ST_PAIRS];
         if (*K_check > L.cap) return FGS_ERR_CAPACITY;
     }
-    const uint2 *sranges = ctx->bin_sranges.as<uint2>();
+    uint2 *sranges = ctx->bin_sranges.as<uint2>();
     {
-        // super-tile lists, then the tile ranges
+        // super-tile lists (stable: each in gaussian order), their ranges and chunk table
         Stage st_(ctx, "tile_sort");
         const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
         uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
                                            ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
-        const bool one_pass = sbits <= 8;
-        if (!one_pass) launch_ranges(keys, nsup_pairs, ctx->bin_sranges.as<uint2>(), nsup, kSuperKeyMask, s);
-        launch_bin_counts(bw, keys, ctx->bin_sranges.as<uint2>(), one_pass ? sws.totals : nullptr, nsup, s);
+        if (!one_pass) launch_ranges(keys, nsup_pairs, sranges, nsup, kSuperKeyMask, s);
+        uint32_t *sstart = ctx->bin_sstart.as<uint32_t>();
+        launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart);
+        launch_seg_sort(keys, svals, okeys, ovals, sranges, sstart, nsup, seg_max_chunks(L.cap, nsup),
+                        ctx->dkA.as<uint32_t>(), ctx->segA.as<uint32_t>(), ctx->segB.as<uint32_t>(),
+                        ctx->segC.as<uint32_t>(), ctx->segD.as<uint32_t>(), s);
+    }
+    {
+        // tile ranges, then the tile lists
+        Stage st_(ctx, "tile_bin");
+        launch_bin_count(bw, okeys, sranges, s);
         launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, step_ovf,
                          first_of_step, s);
-        launch_bin_place(bw, keys, svals, sranges, sp.ranges, sp.vals, s);
+        launch_bin_place(bw, okeys, ovals, sranges, sp.ranges, sp.vals, s);
     }
     if (raster) {
         Stage st_(ctx, "raster_fwd");
@@ -567,8 +587,8 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     return FGS_OK;
 }
 
-// Enqueue the forward pipeline of one view into a state with layout L: projection, depth sort,
-// binning (enqueue_bin_raster, with its K_check) and, with raster, the rasterization.
+// Enqueue the forward pipeline of one view into a state with layout L: projection, binning
+// (enqueue_bin_raster, with its K_check) and, with raster, the rasterization.
 fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                            int tw, int th, const ImageK &img, void *state, const StateLayout &L,
                            int64_t *K_check = nullptr, uint32_t *host_status = nullptr, bool raster = true,
@@ -586,11 +606,6 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
         Stage st_(ctx, "project");
         launch_project(to_pk(g), to_camk(cam), rk, sp.rec, po.rect, po.count, ctx->dkA.as<uint32_t>(),
                        ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part);
-    }
-    {
-        Stage st_(ctx, "depth_sort");
-        launch_radix_sort(ctx->dkA.as<uint32_t>(), ctx->idA.as<uint32_t>(), ctx->dkB.as<uint32_t>(),
-                          ctx->idB.as<uint32_t>(), sp.ids, ndev, g.n, 32, sort_ws(ctx, g.n, kDepthSortPerBlock), s);
     }
     return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss, step_ovf,
                               first_of_step);
@@ -643,7 +658,6 @@ bool state_layout(int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64
     l.P = (int64_t)W * H;
     size_t o = 0;
     l.off_rec = o; o = align256(o + (size_t)n * sizeof(Rec));
-    l.off_ids = o; o = align256(o + (size_t)n * 4);
     l.off_ranges = o; o = align256(o + (size_t)l.T * 8);
     l.off_last = o; o = align256(o + (size_t)l.P * 4);
     l.off_tfinal = o; o = align256(o + (size_t)l.P * 4);
@@ -724,7 +738,8 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
-                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->hist, &ctx->grad2d,
+                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->segA, &ctx->segB, &ctx->segC, &ctx->segD,
+                    &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets, &ctx->ms_img, &ctx->ms_ssim, &ctx->ms_reg,
                     &ctx->ssim_part, &ctx->ssim_ws};

@@ -56,7 +56,7 @@ struct GradK {
     float *mean, *log_scale, *quat, *logit, *rgb;
 };
 
-// Projected record of one gaussian, 3 x float4, in depth order inside a forward state:
+// Projected record of one gaussian, 3 x float4, by gaussian id inside a forward state:
 //  r0 = {ix, iy (int bits), fx, fy}: the projected mean as integer pixel + fraction
 //  r1 = {conic a, conic b, conic c, opacity}
 //  r2 = {r, g, b, depth}
@@ -80,7 +80,6 @@ struct StateLayout {
     int64_t n = 0, P = 0, T = 0;
     int32_t W = 0, H = 0, tw = 0, th = 0, tiles_x = 0, tiles_y = 0;
     size_t off_rec = 0;    // Rec x n, by gaussian id
-    size_t off_ids = 0;    // u32 x n: gaussian id of depth rank r (used by the binning)
     size_t off_ranges = 0; // uint2 x T: [start, end) into vals per tile item (super-tile-major)
     size_t off_last = 0;   // u32 x P: list position after a pixel's last blended gaussian
     size_t off_tfinal = 0; // f32 x P: final transmittance
@@ -136,14 +135,14 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             const uint32_t *n_dev, int64_t n_cap, int key_bits, const SortWS &ws,
                             hipStream_t s);
 
-// Per-block sums of count[ids[r]] over depth ranks r (scan_blocks(n) words of blocksums, at most
+// Per-block sums of count[ids[r]] over ranks r (scan_blocks(n) words of blocksums, at most
 // scan_blocks_cap(n) for any count up to n), the first half of the scan that launch_emit completes.
 int64_t scan_blocks(int64_t n);
 int64_t scan_blocks_cap(int64_t n);
 void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, uint32_t *blocksums, hipStream_t s);
 
 // Completes the scan (each block adds the block sums before it) and emits one (key, gaussian id)
-// pair per covered tile in depth order; with shift > 0 the keys are
+// pair per covered tile in the order of ids (rank r: gaussian ids[r]); with shift > 0 the keys are
 // super-tiles (tile rectangle >> shift, keys_x super-tiles per row) and carry, above bit
 // kBoxShift, the box of the super-tile's tiles that the gaussian covers. Several views binned at
 // once (view_tab non-null): ids are values v view_n + i, view v's keys are view_tab[v].y + its
@@ -151,7 +150,7 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 // words (per-rank exclusive offsets). If the pairs exceed cap, nothing is emitted for sorting
 // (*n_pairs_dev = 0) and the required count is recorded in status. host_status (nullable,
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
-// depth order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk. The
+// rank order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk. The
 // projection's per-workgroup counts kpart (proj_blocks workgroups) are summed into *ktotal and
 // status[ST_PAIRS] ((tile, gaussian) pairs) and status[ST_VISIBLE].
 int64_t emit_chunks(int64_t cap);
@@ -186,6 +185,22 @@ int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 // super-tile ranges are written into sranges; else sranges holds them already.
 void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
                        hipStream_t s);
+// The two halves of launch_bin_counts: the chunk table (and sranges from digit_totals; with
+// sstart non-null, also the first depth-order chunk of every super-tile list, nsup + 1 words), then
+// the per-chunk tile counts.
+void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
+                       uint32_t *sstart = nullptr);
+void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s);
+// Depth order inside every super-tile list: (kin, vin) hold the lists in ascending gaussian id
+// (ranges sranges, nsup lists, chunk table sstart from launch_bin_chunks); each list is written
+// to (kout, vout) at the same place, stably reordered by dkey[gaussian id] (so in (depth, id)
+// order). tkey, tpos, tkey2 and tpos2 (as many words as the pairs each) hold the sorted chunks of
+// lists longer than one chunk while they are merged. max_chunks = seg_max_chunks(pair capacity,
+// nsup).
+int64_t seg_max_chunks(int64_t cap, int64_t nsup);
+void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint2 *sranges,
+                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *tkey,
+                     uint32_t *tpos, uint32_t *tkey2, uint32_t *tpos2, hipStream_t s);
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
                       uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
                       hipStream_t s);

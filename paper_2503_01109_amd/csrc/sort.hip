@@ -1,14 +1,16 @@
 // Binning of projected gaussians into screen tiles and the (tile, depth) ordering of every
 // tile's list.
 //
-// Ordering scheme: the n gaussians are first sorted by depth (32-bit keys, the bits of the
-// positive FP32 depth; ids emitted in ascending order and a stable sort, so equal depths keep
-// ascending index). Every gaussian then emits one (super-tile, depth rank) pair per covered
-// square of kSuper x kSuper tiles, in depth order; a stable sort of those pairs by super-tile
-// alone leaves each super-tile's list in (depth, index) order, and an in-order expansion of each
-// super-tile list into the lists of its tiles keeps that order. The result is exactly the stable
-// (tile, depth rank) order of one pair per covered tile, while the sort only moves one pair per
-// covered super-tile; no pair ever carries a depth key of its own.
+// Ordering scheme of one view: every gaussian emits one (super-tile, id) pair per covered square
+// of kSuper x kSuper tiles, in id order; a stable sort of those pairs by super-tile alone gives
+// each super-tile's list in id order, and each list is then put in (depth, index) order by a sort
+// of its own on the depth keys (k_seg_chunk_sort, k_seg_merge: stable, so equal depths keep
+// ascending index). An in-order expansion of each super-tile list into the lists of its tiles keeps
+// that order. The result is exactly the stable (tile, depth, index) order of one pair per covered
+// tile, while the sorts only move one pair per covered super-tile. A keyframe window orders all
+// its views at once the other way round: the gaussians of every view are sorted by depth first
+// (ids in ascending order and a stable sort), their pairs emitted in that order and sorted stably
+// by super-tile.
 //
 // The radix sort is an LSD sort with 8-bit digits and a fixed grid: block b handles the b-th
 // contiguous chunk of the input, whose length is read from device memory, so no host round
@@ -325,7 +327,7 @@ k_scan_top(uint32_t *__restrict__ blocksums, int nb, uint32_t *__restrict__ stat
 
 // Per-rank exclusive offsets: offsets[r] = block offset + prefix of count[ids[.]] inside the
 // block (same partition as k_count_reduce); offsets[n] = total. Also gathers the tile rectangles
-// of the gaussians that cover at least one tile into depth order, and the first rank of every
+// of the gaussians that cover at least one tile into rank order, and the first rank of every
 // emission chunk.
 // scanned: blocksums already hold exclusive prefixes (k_scan_top ran); otherwise each block adds
 // the block sums before it and block 0 sums the projection's counts.
@@ -387,6 +389,10 @@ __device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, 
     return lo;
 }
 
+// depth order inside the super-tile lists (k_seg_chunk_sort, k_seg_merge)
+constexpr int kSegItems = 16;
+constexpr int kChunkThreads = 256, kSegChunk = kChunkThreads * kSegItems;  // 4,096 entries per chunk
+constexpr int kMergeThreads = 1024, kMergeLds = 16384;  // lists up to kMergeLds keys merge in LDS
 constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion chunk
 constexpr int kBinGrid = 4096;         // workgroups of the expansion kernels (each loops over chunks)
 
@@ -402,7 +408,7 @@ __device__ inline uint32_t cover_box(uint2 rc, uint32_t sx, uint32_t sy)
 }
 
 // Load-balanced emission: the K pairs are cut into chunks of kEmitChunk consecutive pair
-// indices; a block takes a chunk, finds the depth ranks it spans by binary search over the
+// indices; a block takes a chunk, finds the ranks it spans by binary search over the
 // per-rank offsets, and its threads write consecutive pair indices (coalesced), each finding its
 // rank by a binary search inside that span. A gaussian's pairs are its tile rectangle in
 // row-major order; each pair carries the gaussian's id.
@@ -470,19 +476,19 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
 
 /* ------------------------- tile lists from super-tile lists ------------------------- */
 // A super-tile is a square of kSuper x kSuper tiles. Every gaussian first emits one pair per
-// covered super-tile (in depth order) and the pairs are sorted by super-tile; each super-tile's
-// list is then cut into chunks of kBinChunk entries, and a workgroup per chunk expands its
-// entries into the tiles they cover: a count pass, a prefix over the super-tile's chunks and
-// over all tiles, and a placement pass. Entries stay in depth order within every tile (the
-// super-tile sort is stable and chunks are placed in order), so the tile lists are exactly the
-// stable (tile, depth rank) order.
+// covered super-tile and the pairs are sorted by super-tile, each super-tile's list ending in
+// (depth, index) order; each list is then cut into chunks of kBinChunk entries, and a workgroup
+// per chunk expands its entries into the tiles they cover: a count pass, a prefix over the
+// super-tile's chunks and over all tiles, and a placement pass. Entries keep the list's order
+// within every tile (chunks are placed in order), so the tile lists are exactly the stable (tile,
+// depth, index) order.
 
 // Chunk table: chunk c covers entries [sranges[s].x + (c - cstart[s]) kBinChunk, ...) of
 // super-tile s = csuper[c]; *nchunks = number of chunks (capped at max_chunks).
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
              uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-             uint32_t *__restrict__ nchunks)
+             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart)
 {
     __shared__ uint32_t w[8];
     if (digit_totals) {
@@ -498,13 +504,14 @@ k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_tot
         }
         __syncthreads();
     }
-    uint32_t carry = 0;
+    uint32_t carry = 0, scarry = 0;
     for (int base = 0; base < nsup; base += kSortThreads) {
         const int sidx = base + threadIdx.x;
-        uint32_t nch = 0;
+        uint32_t nch = 0, nsc = 0;
         if (sidx < nsup) {
             const uint2 r = sranges[sidx];
             nch = (r.y - r.x + kBinChunk - 1) / kBinChunk;
+            nsc = (r.y - r.x + kSegChunk - 1) / kSegChunk;
         }
         uint32_t tot;
         const uint32_t ex = carry + block_excl_scan(nch, w, &tot);
@@ -513,10 +520,17 @@ k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_tot
             for (uint32_t c = 0; c < nch && ex + c < max_chunks; ++c) csuper[ex + c] = (uint32_t)sidx;
         }
         carry += tot;
+        if (sstart) {
+            // the depth-order chunks of kSegChunk entries: first chunk of every super-tile
+            const uint32_t sex = scarry + block_excl_scan(nsc, w, &tot);
+            if (sidx < nsup) sstart[sidx] = sex;
+            scarry += tot;
+        }
     }
     if (threadIdx.x == 0) {
         cstart[nsup] = carry;
         *nchunks = min(carry, max_chunks);
+        if (sstart) sstart[nsup] = scarry;
     }
 }
 
@@ -712,6 +726,453 @@ k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, 
     ranges[t] = make_uint2(lower_bound_u32(keys, K, (uint32_t)t, mask), lower_bound_u32(keys, K, (uint32_t)t + 1, mask));
 }
 
+/* ------------------------- depth order inside every super-tile list ------------------------- */
+// Each super-tile list arrives in ascending gaussian id (the pairs are emitted in id order and
+// the super-tile sort is stable) and is reordered, stably, by the gaussian's depth key, so that it
+// ends in (depth, index) order. Two launches:
+//  - k_seg_chunk_sort: every list is cut into chunks of kSegChunk consecutive entries, and each
+//    chunk is sorted in LDS by a workgroup: 16 consecutive entries per thread in registers, an LSD
+//    radix sort over 4-bit digits of only the bits that differ within the chunk (key - min, whose
+//    bits above those of max - min are zero), each entry ranked by its thread's own digit counts
+//    and a scan of those counts over the workgroup, the permuted (key, position) pairs written to
+//    LDS and read back. A list of one chunk is then final; the chunks of a longer list go to
+//    scratch as sorted (key, position) runs.
+//  - k_seg_merge: a workgroup per list of several chunks gives each entry its place in the list:
+//    its rank in its own chunk plus, for every other chunk, the number of that chunk's keys that
+//    come before it (binary searches: keys <= it in earlier chunks, < it in later ones, which keeps
+//    equal keys in index order).
+
+template <int NW>
+struct SegShared {
+    uint32_t wtot[NW][8];  // per wave: digit counts (two 16-bit fields per word), then their prefix
+    uint32_t tot[8];       // the workgroup's digit counts
+};
+
+// Inclusive sum over the wave's lanes by DPP: shifts by 1, 2, 4 and 8 within each row of 16 lanes
+// (lanes shifted in from outside the row add 0), then the last lane of row 0 broadcast into row 1
+// and row 2's into row 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return x;
+}
+
+// Ranks the workgroup's NT * 16 elements (thread t holds elements 16 t .. 16 t + 15) by the 4-bit
+// digit at `shift`. Element j of this thread goes to off(d) + lr(j), d its digit: off(d) (written
+// to toff, 16-bit fields, two per word, by digit pair then thread) counts every element of a
+// smaller digit and the elements of digit d in earlier threads; lr(j) = the elements of digit d
+// among this thread's before j (byte j & 3 of lr[j >> 2]). The thread's digit counts are 4-bit
+// fields of one 64-bit word (a count reaches 16 only when all 16 elements share a digit, which is
+// caught separately); the scans run on two 16-bit fields per word, which add without carries
+// since every sum stays below 2^16.
+template <int NT>
+__device__ __forceinline__ void seg_rank(const uint32_t (&k)[kSegItems], int shift, uint32_t (&lr)[kSegItems / 4],
+                                         uint32_t *toff, SegShared<NT / kWave> &S)
+{
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    uint64_t c = 0;
+    uint32_t r = 0, d = 0;
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        d = (k[j] >> shift) & 15u;
+        const uint32_t s4 = d << 2;
+        r = (uint32_t)(c >> s4) & 15u;
+        lr[j >> 2] = (j & 3) ? (lr[j >> 2] | (r << ((j & 3) * 8))) : r;
+        c += 1ull << s4;
+    }
+    // the local ranks are final here: keep them in their four registers rather than have the
+    // compiler recompute them after the scan
+#pragma unroll
+    for (int q = 0; q < kSegItems / 4; ++q) asm volatile("" : "+v"(lr[q]));
+    const bool all_same = r == kSegItems - 1;  // the last element has 15 of its digit before it
+    const uint32_t lo = (uint32_t)c, hi = (uint32_t)(c >> 32);
+    uint32_t p[8], s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t w = q < 4 ? lo : hi, b = (q & 3) * 8;
+        p[q] = all_same ? (q == (int)(d >> 1) ? (uint32_t)kSegItems << ((d & 1u) << 4) : 0u)
+                        : (((w >> b) & 15u) | (((w >> (b + 4)) & 15u) << 16));
+        s[q] = wave_incl_sum(p[q]);
+    }
+    if (lane == kWave - 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) S.wtot[wid][q] = s[q];
+    __syncthreads();
+    if (tid < 8 * NW) {
+        // NW lanes per register q, lane w holding wave w's count: a scan over the NW lanes
+        const int q = tid / NW, w = tid % NW;
+        const uint32_t v = S.wtot[w][q];
+        uint32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, NW);
+            incl += w >= o ? y : 0u;
+        }
+        S.wtot[w][q] = incl - v;
+        if (w == NW - 1) S.tot[q] = incl;
+    }
+    __syncthreads();
+    uint32_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t t = S.tot[q], tlo = t & 0xFFFFu;
+        const uint32_t dig = acc | ((acc + tlo) << 16);
+        acc += tlo + (t >> 16);
+        toff[q * NT + tid] = dig + S.wtot[wid][q] + (s[q] - p[q]);  // smaller digits, earlier waves, earlier lanes
+    }
+}
+
+// This thread's element j: its digit's offset plus its local rank.
+template <int NT>
+__device__ __forceinline__ uint32_t seg_slot(const uint32_t *toff, uint32_t d, const uint32_t (&lr)[kSegItems / 4],
+                                             int j)
+{
+    const uint32_t w = toff[(d >> 1) * NT + threadIdx.x];
+    return ((w >> ((d & 1u) << 4)) & 0xFFFFu) + ((lr[j >> 2] >> ((j & 3) * 8)) & 0xFFu);
+}
+
+// LDS word of key slot r: bits 2-3 of r flipped by bits 5-6, so that the 16-byte reads of the
+// 16 consecutive keys of neighbouring threads spread over all banks (a bijection on each aligned
+// run of 128 slots that keeps every aligned group of four slots together).
+__device__ __forceinline__ uint32_t seg_swz(uint32_t r) { return r ^ (((r >> 5) & 3u) << 2); }
+
+// Number of 4-bit passes that order keys in [mn, mx] once mn is subtracted from them.
+__device__ __forceinline__ int seg_passes(uint32_t mn, uint32_t mx)
+{
+    const uint32_t x = mx - mn;
+    return x ? (32 - __clz(x) + 3) / 4 : 0;
+}
+
+// Largest s in [0, nsup) with a[s] <= v (a non-decreasing, a[0] = 0 <= v).
+__device__ inline int last_le_i(const uint32_t *__restrict__ a, int nsup, uint32_t v)
+{
+    int lo = 0, hi = nsup - 1;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if (a[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kChunkThreads)
+k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                 uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ sstart,
+                 int nsup, const uint32_t *__restrict__ dkey, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tpos)
+{
+    constexpr int NT = kChunkThreads, NW = NT / kWave;
+    __shared__ __align__(16) uint32_t lkey[kSegChunk];
+    __shared__ __align__(16) uint16_t lpos[kSegChunk];
+    __shared__ uint32_t toff[8 * NT];
+    __shared__ uint32_t lid[kSegChunk];  // the entries' gaussian ids and coverage boxes (a one-chunk
+    __shared__ uint8_t lbox[kSegChunk];  // list is written out from LDS)
+    __shared__ SegShared<NW> S;
+    __shared__ uint32_t red[2 * NW];
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    const uint32_t c = blockIdx.x;
+    if (c >= sstart[nsup]) return;
+    const int sidx = last_le_i(sstart, nsup, c);
+    const uint2 rg = sranges[sidx];
+    const uint32_t x0 = rg.x + (c - sstart[sidx]) * (uint32_t)kSegChunk;  // the chunk's first entry
+    const uint32_t n = min((uint32_t)kSegChunk, rg.y - x0);
+    const bool single = rg.y - rg.x <= (uint32_t)kSegChunk;
+    // the chunk's depth keys in LDS (coalesced reads of the ids, all issued before the gathers that
+    // depend on them), padded with all ones; the chunk's smallest and largest key
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    {
+        // (loads at clamped indices, n >= 1, and the results masked: no branch per element, so
+        // the compiler keeps all of them in flight)
+        uint32_t id[kSegItems], bx[kSegItems];
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            const uint32_t i = x0 + min((uint32_t)(tid + j * NT), n - 1);
+            id[j] = vin[i];
+            bx[j] = single ? kin[i] >> kBoxShift : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            const uint32_t i = tid + j * NT;
+            const uint32_t key = i < n ? dkey[id[j]] : 0xFFFFFFFFu;
+            mn = min(mn, key);
+            mx = max(mx, i < n ? key : 0u);
+            lkey[seg_swz(i)] = key;
+            lpos[i] = (uint16_t)i;
+            lid[i] = id[j];
+            lbox[i] = (uint8_t)bx[j];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, (uint32_t)__shfl_xor(mn, o));
+        mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+    }
+    if (lane == 0) {
+        red[2 * wid] = mn;
+        red[2 * wid + 1] = mx;
+    }
+    __syncthreads();  // (also orders the stores above before the reads below)
+    mn = 0xFFFFFFFFu;
+    mx = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mn = min(mn, red[2 * w]);
+        mx = max(mx, red[2 * w + 1]);
+    }
+    // The passes sort key - mn (order-preserving for keys >= mn) on its low 4 passes bits; the
+    // first pass reads the keys and subtracts, later passes read the differences. Depth keys are
+    // the bits of finite positive floats, below 2^31, so the padding keys (all ones) are told apart
+    // and stay all ones: at least as large as every difference in the sorted bits, and after the
+    // chunk's entries, so a stable sort keeps them last.
+    const int passes = seg_passes(mn, mx);
+    uint32_t k[kSegItems], lr[kSegItems / 4];
+    for (int pass = 0; pass < passes; ++pass) {
+        uint32_t pos2[kSegItems / 2];  // positions, two 16-bit fields per word
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(lpos + kSegItems * tid);
+#pragma unroll
+        for (int j = 0; j < kSegItems / 4; ++j) {
+            // four consecutive slots stay together under the swizzle
+            const uint4 v = *reinterpret_cast<const uint4 *>(lkey + seg_swz(kSegItems * tid + 4 * j));
+            k[4 * j] = v.x;
+            k[4 * j + 1] = v.y;
+            k[4 * j + 2] = v.z;
+            k[4 * j + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < kSegItems / 8; ++j) {
+            const uint4 v = p4[j];
+            pos2[4 * j] = v.x;
+            pos2[4 * j + 1] = v.y;
+            pos2[4 * j + 2] = v.z;
+            pos2[4 * j + 3] = v.w;
+        }
+        if (pass == 0)
+#pragma unroll
+            for (int j = 0; j < kSegItems; ++j) k[j] = k[j] == 0xFFFFFFFFu ? k[j] : k[j] - mn;
+        const int shift = 4 * pass;
+        seg_rank<NT>(k, shift, lr, toff, S);  // (its barriers order the reads above before the writes below)
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            const uint32_t r = seg_slot<NT>(toff, (k[j] >> shift) & 15u, lr, j);
+            lkey[seg_swz(r)] = k[j];
+            lpos[r] = (uint16_t)(pos2[j >> 1] >> ((j & 1) * 16));
+        }
+        __syncthreads();
+    }
+    // out: a one-chunk list in its final place; else the sorted run (the keys themselves, restored
+    // from key - mn, and the entries' offsets in the list) for the merge
+    // (every load at an index inside the chunk; the stores without a branch per element when all of
+    // this thread's outputs are inside it)
+    const uint32_t add = passes > 0 ? mn : 0u;
+    const bool full = tid + (kSegItems - 1) * NT < n;
+    uint32_t q[kSegItems], kk[kSegItems], vv[kSegItems];
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        const uint32_t r = min((uint32_t)(tid + j * NT), n - 1);
+        q[j] = lpos[r];
+        kk[j] = lkey[seg_swz(r)] + add;
+    }
+    if (single) {
+        // every key of a super-tile list holds the same super-tile below kBoxShift
+        const uint32_t sid = kin[x0] & kSuperKeyMask;
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            kk[j] = sid | (uint32_t)lbox[q[j]] << kBoxShift;
+            vv[j] = lid[q[j]];
+        }
+        if (full) {
+#pragma unroll
+            for (int j = 0; j < kSegItems; ++j) {
+                kout[x0 + tid + j * NT] = kk[j];
+                vout[x0 + tid + j * NT] = vv[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kSegItems; ++j)
+                if (tid + j * NT < n) {
+                    kout[x0 + tid + j * NT] = kk[j];
+                    vout[x0 + tid + j * NT] = vv[j];
+                }
+        }
+    } else {
+        const uint32_t off = x0 - rg.x;
+        if (full) {
+#pragma unroll
+            for (int j = 0; j < kSegItems; ++j) {
+                tkey[x0 + tid + j * NT] = kk[j];
+                tpos[x0 + tid + j * NT] = off + q[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kSegItems; ++j)
+                if (tid + j * NT < n) {
+                    tkey[x0 + tid + j * NT] = kk[j];
+                    tpos[x0 + tid + j * NT] = off + q[j];
+                }
+        }
+    }
+}
+
+// Merge path of output index o when merging sorted runs a[0, la) and b[0, lb) stably (a first on
+// equal keys): the number of elements of a among the first o outputs.
+__device__ __forceinline__ uint32_t merge_split(const uint32_t *a, uint32_t la, const uint32_t *b, uint32_t lb,
+                                                uint32_t o)
+{
+    uint32_t lo = o > lb ? o - lb : 0u, hi = min(o, la);
+    while (lo < hi) {
+        const uint32_t i = (lo + hi) >> 1;  // a[i] is taken before b[o - 1 - i] iff a[i] <= b[o - 1 - i]
+        if (a[i] <= b[o - 1 - i]) lo = i + 1;
+        else hi = i;
+    }
+    return lo;
+}
+
+// The merge levels of one list of n entries (n > kSegChunk): runs of L = kSegChunk, 2 kSegChunk,
+// ... entries merged pairwise until one is left, each thread producing kMergeItems consecutive
+// outputs of a level at a time from its start on the merge path, branch-free (the heads of both
+// runs are loaded at clamped indices every step, an exhausted run's head reads as all ones). Keys
+// go from ka to kb and back (LDS arrays, or global scratch), the entries' offsets in the list from
+// pa to pb and back; the last level writes the list's (key, value) pairs in their final order to
+// (kout, vout) + x.
+constexpr int kMergeItems = 8;
+template <bool STAGED>
+__device__ __forceinline__ void merge_levels(uint32_t *ka, uint32_t *kb, uint32_t *pa, uint32_t *pb, uint32_t n,
+                                             uint32_t x, const uint32_t *__restrict__ kin,
+                                             const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                                             uint32_t *__restrict__ vout, uint8_t *lbox)
+{
+    const uint32_t sid = kin[x] & kSuperKeyMask;  // the super-tile of every key of the list
+    for (uint32_t L = kSegChunk; L < n; L *= 2) {
+        const bool last = 2 * L >= n;
+        if (STAGED && last) {
+            // the last level writes no keys: its key array holds the entries' gaussian ids, lbox
+            // their coverage boxes, so that the outputs are read from LDS
+            uint32_t v[kMergeLds / kMergeThreads], b[kMergeLds / kMergeThreads];
+#pragma unroll
+            for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
+                const uint32_t i = x + min((uint32_t)(threadIdx.x + j * kMergeThreads), n - 1);
+                v[j] = vin[i];
+                b[j] = kin[i] >> kBoxShift;
+            }
+#pragma unroll
+            for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
+                const uint32_t i = threadIdx.x + j * kMergeThreads;
+                if (i < n) {
+                    kb[i] = v[j];
+                    lbox[i] = (uint8_t)b[j];
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
+            // the pair of runs holding outputs o0 .. o0 + 7 (a pair spans 2 L >= 8 outputs)
+            const uint32_t base = o0 / (2 * L) * (2 * L);
+            const uint32_t la = min(L, n - base), lb = min(L, n - base - la);
+            const uint32_t *A = ka + base, *B = A + la;
+            const uint32_t o = o0 - base;
+            uint32_t i = merge_split(A, la, B, lb, o), j = o - i;
+            uint32_t src[kMergeItems], key[kMergeItems];
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t) {
+                // both loads stay inside the pair's entries (la >= 1; with lb = 0 the second one
+                // reads A[0] and is not used)
+                const uint32_t ha = i < la ? A[min(i, la - 1)] : 0xFFFFFFFFu;
+                const uint32_t hb = j < lb ? (lb ? B[min(j, lb - 1)] : A[0]) : 0xFFFFFFFFu;
+                const bool takeA = i < la && (j >= lb || ha <= hb);
+                src[t] = takeA ? base + i : base + la + j;
+                key[t] = takeA ? ha : hb;
+                i += takeA ? 1u : 0u;
+                j += takeA ? 0u : 1u;
+            }
+            // loads at indices inside the list (an output past its end reads entry n - 1); stores
+            // without a branch per output when all of them are inside the list
+            const bool full = o0 + kMergeItems <= n;
+            uint32_t pos[kMergeItems];
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t) pos[t] = pa[min(src[t], n - 1)];
+            if (!last) {
+                if (full) {
+#pragma unroll
+                    for (int t = 0; t < kMergeItems; ++t) {
+                        kb[o0 + t] = key[t];
+                        pb[o0 + t] = pos[t];
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < kMergeItems; ++t)
+                        if (o0 + t < n) {
+                            kb[o0 + t] = key[t];
+                            pb[o0 + t] = pos[t];
+                        }
+                }
+            } else {
+                uint32_t kk[kMergeItems], vv[kMergeItems];
+#pragma unroll
+                for (int t = 0; t < kMergeItems; ++t) {
+                    kk[t] = STAGED ? sid | (uint32_t)lbox[pos[t]] << kBoxShift : kin[x + pos[t]];
+                    vv[t] = STAGED ? kb[pos[t]] : vin[x + pos[t]];
+                }
+                if (full) {
+#pragma unroll
+                    for (int t = 0; t < kMergeItems; ++t) {
+                        kout[x + o0 + t] = kk[t];
+                        vout[x + o0 + t] = vv[t];
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < kMergeItems; ++t)
+                        if (o0 + t < n) {
+                            kout[x + o0 + t] = kk[t];
+                            vout[x + o0 + t] = vv[t];
+                        }
+                }
+            }
+        }
+        __syncthreads();  // the level's outputs are the next level's runs
+        uint32_t *const tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tp = pa;
+        pa = pb;
+        pb = tp;
+    }
+}
+
+// Every list of several chunks, one workgroup each: its keys staged in LDS when it fits
+// (kMergeLds entries, the levels then move keys between two LDS arrays), else merged through
+// tkey and tkey2; the offsets go between tpos and tpos2.
+__global__ void __launch_bounds__(kMergeThreads)
+k_seg_merge(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+            uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges, uint32_t *__restrict__ tkey,
+            uint32_t *__restrict__ tpos, uint32_t *__restrict__ tkey2, uint32_t *__restrict__ tpos2)
+{
+    __shared__ uint32_t lk0[kMergeLds], lk1[kMergeLds];
+    __shared__ uint8_t lbox[kMergeLds];
+    const uint2 rg = sranges[blockIdx.x];
+    const uint32_t x = rg.x, n = rg.y - rg.x;
+    if (n <= (uint32_t)kSegChunk) return;  // one chunk: already in place
+    if (n <= (uint32_t)kMergeLds) {
+        // all of a thread's loads in flight at once
+        uint32_t v[kMergeLds / kMergeThreads];
+#pragma unroll
+        for (int j = 0; j < kMergeLds / kMergeThreads; ++j) v[j] = tkey[x + min((uint32_t)(threadIdx.x + j * kMergeThreads), n - 1)];
+#pragma unroll
+        for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
+            const uint32_t i = threadIdx.x + j * kMergeThreads;
+            if (i < n) lk0[i] = v[j];
+        }
+        __syncthreads();
+        merge_levels<true>(lk0, lk1, tpos + x, tpos2 + x, n, x, kin, vin, kout, vout, lbox);
+    } else {
+        merge_levels<false>(tkey + x, tkey2 + x, tpos + x, tpos2 + x, n, x, kin, vin, kout, vout, lbox);
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -823,13 +1284,37 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
+void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
+                       uint32_t *sstart)
+{
+    hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
+                       b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart);
+}
+
+void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, sranges,
+                       b.cstart, b.csuper, b.nchunks, b.chist);
+}
+
 void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
-                       b.csuper, (uint32_t)b.max_chunks, b.nchunks);
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, sranges,
-                       b.cstart, b.csuper, b.nchunks, b.chist);
+    launch_bin_chunks(b, sranges, digit_totals, nsup, s);
+    launch_bin_count(b, skeys, sranges, s);
+}
+
+int64_t seg_max_chunks(int64_t cap, int64_t nsup) { return (cap + kSegChunk - 1) / kSegChunk + nsup; }
+
+void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint2 *sranges,
+                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *tkey,
+                     uint32_t *tpos, uint32_t *tkey2, uint32_t *tpos2, hipStream_t s)
+{
+    if (nsup <= 0 || max_chunks <= 0) return;
+    hipLaunchKernelGGL(k_seg_chunk_sort, dim3((unsigned)max_chunks), dim3(kChunkThreads), 0, s, kin, vin, kout, vout,
+                       sranges, sstart, nsup, dkey, tkey, tpos);
+    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nsup), dim3(kMergeThreads), 0, s, kin, vin, kout, vout, sranges,
+                       tkey, tpos, tkey2, tpos2);
 }
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,

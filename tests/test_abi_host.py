@@ -102,7 +102,7 @@ def test_state_bytes_layout_and_errors():
     b0 = F.state_bytes(100, 64, 48, 0, o)
     b1 = F.state_bytes(100, 64, 48, 1000, o)
     assert b1 - b0 == 4000
-    assert b0 >= 100 * 48 + 100 * 4 + 12 * 8 + 64 * 48 * 8
+    assert b0 >= 100 * 48 + 12 * 8 + 64 * 48 * 8  # records, tile ranges, per-pixel words
     with pytest.raises(F.FgsError) as e:
         F.state_bytes(100, 0, 48, 10, o)
     assert e.value.status == F.ERR_INVALID_ARG

@@ -245,6 +245,21 @@ def test_many_gaussians_take_the_two_level_scan(fgs, ctx):
     del b, big
 
 
+@pytest.mark.parametrize("n", [16_384, 16_385, 40_000])
+def test_super_tile_list_longer_than_lds(fgs, ctx, n):
+    """A 64x48 frame is one super-tile, whose list holds every gaussian (each covers at least the
+    pixel nearest its centre). Up to 16,384 entries the list is put in depth order in LDS; 16,385
+    and 40,000 take the path through global memory, 16,384 entries at a time in each pass. Forward
+    against the oracle, and the gradient in the 16,385 case."""
+    cam = synth.camera_small()
+    p = synth.frustum_scene(40 + n % 7, n, cam, 1.0, 5.0)
+    opts = fgs.RenderOpts()
+    out, ref = check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.02)
+    assert ctx.stats()["visible"] == n
+    if n == 16_385:
+        check_backward(fgs, ctx, p, cam, opts, out, ref, seed=3)
+
+
 def test_invariant_weights_sum_to_one(fgs, ctx):
     """P4 on the GPU: alpha + T_final = 1 within FP32 rounding, at every pixel."""
     p = synth.scene_small(4)
