@@ -391,7 +391,7 @@ __device__ inline uint32_t last_le(const uint32_t *__restrict__ a, uint32_t lo, 
 
 // depth order inside the super-tile lists (k_seg_chunk_sort, k_seg_merge)
 constexpr int kSegItems = 16;
-constexpr int kChunkThreads = 256, kSegChunk = kChunkThreads * kSegItems;  // 4,096 entries per chunk
+constexpr int kChunkThreads = 512, kSegChunk = kChunkThreads * kSegItems;  // 8,192 entries per chunk
 constexpr int kMergeThreads = 1024, kMergeLds = 16384;  // lists up to kMergeLds keys merge in LDS
 constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion chunk
 constexpr int kBinGrid = 4096;         // workgroups of the expansion kernels (each loops over chunks)
