@@ -119,7 +119,7 @@ struct fgs_ctx {
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
     DBuf rect_sorted, start_rank, kpart;
-    DBuf segA, segB, segC, segD;  // sorted chunks (keys, positions) of super-tile lists being merged
+    DBuf seg[6];  // sorted chunks (depth keys, ids, super-tile keys, twice) of super-tile lists being merged
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
     DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words, bin_sstart;
     int64_t bin_nsup = -1, bin_T = -1, bin_cap = -1;
@@ -312,10 +312,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->pkB.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvA.ensure(C * 4));
     HIP_TRY(ctx, ctx->pvB.ensure(C * 4));
-    HIP_TRY(ctx, ctx->segA.ensure(C * 4));
-    HIP_TRY(ctx, ctx->segB.ensure(C * 4));
-    HIP_TRY(ctx, ctx->segC.ensure(C * 4));
-    HIP_TRY(ctx, ctx->segD.ensure(C * 4));
+    for (DBuf &b : ctx->seg) HIP_TRY(ctx, b.ensure(C * 4));
     const int G = std::max(sort_blocks(nn, kDepthSortPerBlock), sort_blocks(cc > nn ? cc : nn, kPairSortPerBlock));
     HIP_TRY(ctx, ctx->hist.ensure(((size_t)G * 256 + 256) * 4));
     ctx->hist_G = G;
@@ -564,9 +561,10 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         if (!one_pass) launch_ranges(keys, nsup_pairs, sranges, nsup, kSuperKeyMask, s);
         uint32_t *sstart = ctx->bin_sstart.as<uint32_t>();
         launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart);
+        uint32_t *const tmp[6] = {ctx->seg[0].as<uint32_t>(), ctx->seg[1].as<uint32_t>(), ctx->seg[2].as<uint32_t>(),
+                                  ctx->seg[3].as<uint32_t>(), ctx->seg[4].as<uint32_t>(), ctx->seg[5].as<uint32_t>()};
         launch_seg_sort(keys, svals, okeys, ovals, sranges, sstart, nsup, seg_max_chunks(L.cap, nsup),
-                        ctx->dkA.as<uint32_t>(), ctx->segA.as<uint32_t>(), ctx->segB.as<uint32_t>(),
-                        ctx->segC.as<uint32_t>(), ctx->segD.as<uint32_t>(), s);
+                        ctx->dkA.as<uint32_t>(), tmp, s);
     }
     {
         // tile ranges, then the tile lists
@@ -738,7 +736,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
-                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->segA, &ctx->segB, &ctx->segC, &ctx->segD,
+                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->seg[0], &ctx->seg[1], &ctx->seg[2], &ctx->seg[3], &ctx->seg[4], &ctx->seg[5],
                     &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets, &ctx->ms_img, &ctx->ms_ssim, &ctx->ms_reg,

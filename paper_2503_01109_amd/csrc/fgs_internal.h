@@ -194,13 +194,13 @@ void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *srange
 // Depth order inside every super-tile list: (kin, vin) hold the lists in ascending gaussian id
 // (ranges sranges, nsup lists, chunk table sstart from launch_bin_chunks); each list is written
 // to (kout, vout) at the same place, stably reordered by dkey[gaussian id] (so in (depth, id)
-// order). tkey, tpos, tkey2 and tpos2 (as many words as the pairs each) hold the sorted chunks of
-// lists longer than one chunk while they are merged. max_chunks = seg_max_chunks(pair capacity,
-// nsup).
+// order). t[0..5] (as many words as the pairs each) hold the sorted chunks of lists longer than
+// one chunk (depth keys, gaussian ids, super-tile keys, and a second set for merge levels in
+// global memory) while they are merged. max_chunks = seg_max_chunks(pair capacity, nsup).
 int64_t seg_max_chunks(int64_t cap, int64_t nsup);
 void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint2 *sranges,
-                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *tkey,
-                     uint32_t *tpos, uint32_t *tkey2, uint32_t *tpos2, hipStream_t s);
+                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *const t[6],
+                     hipStream_t s);
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
                       uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
                       hipStream_t s);

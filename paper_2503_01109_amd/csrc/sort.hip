@@ -864,7 +864,8 @@ __device__ inline int last_le_i(const uint32_t *__restrict__ a, int nsup, uint32
 __global__ void __launch_bounds__(kChunkThreads)
 k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                  uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ sstart,
-                 int nsup, const uint32_t *__restrict__ dkey, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tpos)
+                 int nsup, const uint32_t *__restrict__ dkey, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tids,
+                 uint32_t *__restrict__ tsk)
 {
     constexpr int NT = kChunkThreads, NW = NT / kWave;
     __shared__ __align__(16) uint32_t lkey[kSegChunk];
@@ -893,7 +894,7 @@ k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
         for (int j = 0; j < kSegItems; ++j) {
             const uint32_t i = x0 + min((uint32_t)(tid + j * NT), n - 1);
             id[j] = vin[i];
-            bx[j] = single ? kin[i] >> kBoxShift : 0u;
+            bx[j] = kin[i] >> kBoxShift;
         }
 #pragma unroll
         for (int j = 0; j < kSegItems; ++j) {
@@ -964,57 +965,39 @@ k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
         }
         __syncthreads();
     }
-    // out: a one-chunk list in its final place; else the sorted run (the keys themselves, restored
-    // from key - mn, and the entries' offsets in the list) for the merge
-    // (every load at an index inside the chunk; the stores without a branch per element when all of
-    // this thread's outputs are inside it)
+    // out: a one-chunk list in its final place, else the sorted run (the keys themselves, restored
+    // from key - mn, the gaussian ids and the super-tile keys) for the merge. Every key of a
+    // super-tile list holds the same super-tile below kBoxShift. (Every load at an index inside
+    // the chunk; the stores without a branch per element when all of this thread's outputs are
+    // inside it.)
     const uint32_t add = passes > 0 ? mn : 0u;
     const bool full = tid + (kSegItems - 1) * NT < n;
-    uint32_t q[kSegItems], kk[kSegItems], vv[kSegItems];
+    const uint32_t sid = kin[x0] & kSuperKeyMask;
+    uint32_t kk[kSegItems], vv[kSegItems], dk[kSegItems];
 #pragma unroll
     for (int j = 0; j < kSegItems; ++j) {
         const uint32_t r = min((uint32_t)(tid + j * NT), n - 1);
-        q[j] = lpos[r];
-        kk[j] = lkey[seg_swz(r)] + add;
+        const uint32_t q = lpos[r];
+        dk[j] = lkey[seg_swz(r)] + add;
+        kk[j] = sid | (uint32_t)lbox[q] << kBoxShift;
+        vv[j] = lid[q];
     }
-    if (single) {
-        // every key of a super-tile list holds the same super-tile below kBoxShift
-        const uint32_t sid = kin[x0] & kSuperKeyMask;
+    uint32_t *ok = single ? kout : tsk, *ov = single ? vout : tids;
+    if (full) {
 #pragma unroll
         for (int j = 0; j < kSegItems; ++j) {
-            kk[j] = sid | (uint32_t)lbox[q[j]] << kBoxShift;
-            vv[j] = lid[q[j]];
-        }
-        if (full) {
-#pragma unroll
-            for (int j = 0; j < kSegItems; ++j) {
-                kout[x0 + tid + j * NT] = kk[j];
-                vout[x0 + tid + j * NT] = vv[j];
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kSegItems; ++j)
-                if (tid + j * NT < n) {
-                    kout[x0 + tid + j * NT] = kk[j];
-                    vout[x0 + tid + j * NT] = vv[j];
-                }
+            ok[x0 + tid + j * NT] = kk[j];
+            ov[x0 + tid + j * NT] = vv[j];
+            if (!single) tkey[x0 + tid + j * NT] = dk[j];
         }
     } else {
-        const uint32_t off = x0 - rg.x;
-        if (full) {
 #pragma unroll
-            for (int j = 0; j < kSegItems; ++j) {
-                tkey[x0 + tid + j * NT] = kk[j];
-                tpos[x0 + tid + j * NT] = off + q[j];
+        for (int j = 0; j < kSegItems; ++j)
+            if (tid + j * NT < n) {
+                ok[x0 + tid + j * NT] = kk[j];
+                ov[x0 + tid + j * NT] = vv[j];
+                if (!single) tkey[x0 + tid + j * NT] = dk[j];
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kSegItems; ++j)
-                if (tid + j * NT < n) {
-                    tkey[x0 + tid + j * NT] = kk[j];
-                    tpos[x0 + tid + j * NT] = off + q[j];
-                }
-        }
     }
 }
 
@@ -1032,145 +1015,144 @@ __device__ __forceinline__ uint32_t merge_split(const uint32_t *a, uint32_t la, 
     return lo;
 }
 
-// The merge levels of one list of n entries (n > kSegChunk): runs of L = kSegChunk, 2 kSegChunk,
-// ... entries merged pairwise until one is left, each thread producing kMergeItems consecutive
-// outputs of a level at a time from its start on the merge path, branch-free (the heads of both
-// runs are loaded at clamped indices every step, an exhausted run's head reads as all ones). Keys
-// go from ka to kb and back (LDS arrays, or global scratch), the entries' offsets in the list from
-// pa to pb and back; the last level writes the list's (key, value) pairs in their final order to
-// (kout, vout) + x.
+// One thread's kMergeItems consecutive outputs o0 .. of a merge level: runs of L entries of the
+// keys ka[0, n) merged pairwise, stably (the earlier run first on equal keys). Found from the
+// thread's start on the merge path, then branch-free (the heads of both runs are loaded at clamped
+// indices every step, an exhausted run's head reads as all ones). src: each output's index in ka,
+// key: its key. Outputs past n get src = n - 1.
 constexpr int kMergeItems = 8;
-template <bool STAGED>
-__device__ __forceinline__ void merge_levels(uint32_t *ka, uint32_t *kb, uint32_t *pa, uint32_t *pb, uint32_t n,
-                                             uint32_t x, const uint32_t *__restrict__ kin,
-                                             const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-                                             uint32_t *__restrict__ vout, uint8_t *lbox)
+__device__ __forceinline__ void merge_round(const uint32_t *ka, uint32_t n, uint32_t L, uint32_t o0,
+                                            uint32_t (&src)[kMergeItems], uint32_t (&key)[kMergeItems])
 {
-    const uint32_t sid = kin[x] & kSuperKeyMask;  // the super-tile of every key of the list
-    for (uint32_t L = kSegChunk; L < n; L *= 2) {
-        const bool last = 2 * L >= n;
-        if (STAGED && last) {
-            // the last level writes no keys: its key array holds the entries' gaussian ids, lbox
-            // their coverage boxes, so that the outputs are read from LDS
-            uint32_t v[kMergeLds / kMergeThreads], b[kMergeLds / kMergeThreads];
+    // the pair of runs holding outputs o0 .. o0 + 7 (a pair spans 2 L >= 8 outputs)
+    const uint32_t base = o0 / (2 * L) * (2 * L);
+    const uint32_t la = min(L, n - base), lb = min(L, n - base - la);
+    const uint32_t *A = ka + base, *B = A + la;
+    const uint32_t o = o0 - base;
+    uint32_t i = merge_split(A, la, B, lb, o), j = o - i;
 #pragma unroll
-            for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
-                const uint32_t i = x + min((uint32_t)(threadIdx.x + j * kMergeThreads), n - 1);
-                v[j] = vin[i];
-                b[j] = kin[i] >> kBoxShift;
-            }
-#pragma unroll
-            for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
-                const uint32_t i = threadIdx.x + j * kMergeThreads;
-                if (i < n) {
-                    kb[i] = v[j];
-                    lbox[i] = (uint8_t)b[j];
-                }
-            }
-            __syncthreads();
-        }
-        for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
-            // the pair of runs holding outputs o0 .. o0 + 7 (a pair spans 2 L >= 8 outputs)
-            const uint32_t base = o0 / (2 * L) * (2 * L);
-            const uint32_t la = min(L, n - base), lb = min(L, n - base - la);
-            const uint32_t *A = ka + base, *B = A + la;
-            const uint32_t o = o0 - base;
-            uint32_t i = merge_split(A, la, B, lb, o), j = o - i;
-            uint32_t src[kMergeItems], key[kMergeItems];
-#pragma unroll
-            for (int t = 0; t < kMergeItems; ++t) {
-                // both loads stay inside the pair's entries (la >= 1; with lb = 0 the second one
-                // reads A[0] and is not used)
-                const uint32_t ha = i < la ? A[min(i, la - 1)] : 0xFFFFFFFFu;
-                const uint32_t hb = j < lb ? (lb ? B[min(j, lb - 1)] : A[0]) : 0xFFFFFFFFu;
-                const bool takeA = i < la && (j >= lb || ha <= hb);
-                src[t] = takeA ? base + i : base + la + j;
-                key[t] = takeA ? ha : hb;
-                i += takeA ? 1u : 0u;
-                j += takeA ? 0u : 1u;
-            }
-            // loads at indices inside the list (an output past its end reads entry n - 1); stores
-            // without a branch per output when all of them are inside the list
-            const bool full = o0 + kMergeItems <= n;
-            uint32_t pos[kMergeItems];
-#pragma unroll
-            for (int t = 0; t < kMergeItems; ++t) pos[t] = pa[min(src[t], n - 1)];
-            if (!last) {
-                if (full) {
-#pragma unroll
-                    for (int t = 0; t < kMergeItems; ++t) {
-                        kb[o0 + t] = key[t];
-                        pb[o0 + t] = pos[t];
-                    }
-                } else {
-#pragma unroll
-                    for (int t = 0; t < kMergeItems; ++t)
-                        if (o0 + t < n) {
-                            kb[o0 + t] = key[t];
-                            pb[o0 + t] = pos[t];
-                        }
-                }
-            } else {
-                uint32_t kk[kMergeItems], vv[kMergeItems];
-#pragma unroll
-                for (int t = 0; t < kMergeItems; ++t) {
-                    kk[t] = STAGED ? sid | (uint32_t)lbox[pos[t]] << kBoxShift : kin[x + pos[t]];
-                    vv[t] = STAGED ? kb[pos[t]] : vin[x + pos[t]];
-                }
-                if (full) {
-#pragma unroll
-                    for (int t = 0; t < kMergeItems; ++t) {
-                        kout[x + o0 + t] = kk[t];
-                        vout[x + o0 + t] = vv[t];
-                    }
-                } else {
-#pragma unroll
-                    for (int t = 0; t < kMergeItems; ++t)
-                        if (o0 + t < n) {
-                            kout[x + o0 + t] = kk[t];
-                            vout[x + o0 + t] = vv[t];
-                        }
-                }
-            }
-        }
-        __syncthreads();  // the level's outputs are the next level's runs
-        uint32_t *const tk = ka;
-        ka = kb;
-        kb = tk;
-        uint32_t *tp = pa;
-        pa = pb;
-        pb = tp;
+    for (int t = 0; t < kMergeItems; ++t) {
+        // both loads stay inside the pair's entries (la >= 1; with lb = 0 the second one reads
+        // A[0] and is not used)
+        const uint32_t ha = i < la ? A[min(i, la - 1)] : 0xFFFFFFFFu;
+        const uint32_t hb = j < lb ? (lb ? B[min(j, lb - 1)] : A[0]) : 0xFFFFFFFFu;
+        const bool takeA = i < la && (j >= lb || ha <= hb);
+        src[t] = min(takeA ? base + i : base + la + j, n - 1);
+        key[t] = takeA ? ha : hb;
+        i += takeA ? 1u : 0u;
+        j += takeA ? 0u : 1u;
     }
 }
 
-// Every list of several chunks, one workgroup each: its keys staged in LDS when it fits
-// (kMergeLds entries, the levels then move keys between two LDS arrays), else merged through
-// tkey and tkey2; the offsets go between tpos and tpos2.
-__global__ void __launch_bounds__(kMergeThreads)
-k_seg_merge(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-            uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges, uint32_t *__restrict__ tkey,
-            uint32_t *__restrict__ tpos, uint32_t *__restrict__ tkey2, uint32_t *__restrict__ tpos2)
+// A list of two chunks (kSegChunk < n <= kMergeLds): one merge level in LDS, the runs' keys, ids
+// and coverage boxes staged first, the outputs read from LDS.
+__device__ __forceinline__ void merge_staged(uint32_t *lk, uint32_t *lid, uint8_t *lbox, uint32_t n, uint32_t x,
+                                             const uint32_t *__restrict__ tkey, const uint32_t *__restrict__ tid,
+                                             const uint32_t *__restrict__ tsk, uint32_t *__restrict__ kout,
+                                             uint32_t *__restrict__ vout)
 {
-    __shared__ uint32_t lk0[kMergeLds], lk1[kMergeLds];
+    constexpr int J = kMergeLds / kMergeThreads;
+    {
+        uint32_t k[J], v[J], b[J];  // all of a thread's loads in flight at once
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t i = x + min((uint32_t)(threadIdx.x + j * kMergeThreads), n - 1);
+            k[j] = tkey[i];
+            v[j] = tid[i];
+            b[j] = tsk[i] >> kBoxShift;
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t i = threadIdx.x + j * kMergeThreads;
+            if (i < n) {
+                lk[i] = k[j];
+                lid[i] = v[j];
+                lbox[i] = (uint8_t)b[j];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t sid = tsk[x] & kSuperKeyMask;  // the super-tile of every key of the list
+    for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
+        uint32_t src[kMergeItems], key[kMergeItems];
+        merge_round(lk, n, kSegChunk, o0, src, key);
+        uint32_t kk[kMergeItems], vv[kMergeItems];
+#pragma unroll
+        for (int t = 0; t < kMergeItems; ++t) {
+            kk[t] = sid | (uint32_t)lbox[src[t]] << kBoxShift;
+            vv[t] = lid[src[t]];
+        }
+        if (o0 + kMergeItems <= n) {
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t) {
+                kout[x + o0 + t] = kk[t];
+                vout[x + o0 + t] = vv[t];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t)
+                if (o0 + t < n) {
+                    kout[x + o0 + t] = kk[t];
+                    vout[x + o0 + t] = vv[t];
+                }
+        }
+    }
+}
+
+// A longer list: merge levels through global memory, (key, id, super-tile key) moving from the
+// arrays a to the arrays b and back, the last level writing the outputs.
+__device__ void merge_global(uint32_t *ka, uint32_t *ia, uint32_t *sa, uint32_t *kb, uint32_t *ib, uint32_t *sb,
+                             uint32_t n, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout)
+{
+    for (uint32_t L = kSegChunk; L < n; L *= 2) {
+        const bool last = 2 * L >= n;
+        for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
+            uint32_t src[kMergeItems], key[kMergeItems];
+            merge_round(ka, n, L, o0, src, key);
+            uint32_t iv[kMergeItems], sv[kMergeItems];
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t) {
+                iv[t] = ia[src[t]];
+                sv[t] = sa[src[t]];
+            }
+#pragma unroll
+            for (int t = 0; t < kMergeItems; ++t)
+                if (o0 + t < n) {
+                    if (last) {
+                        kout[o0 + t] = sv[t];
+                        vout[o0 + t] = iv[t];
+                    } else {
+                        kb[o0 + t] = key[t];
+                        ib[o0 + t] = iv[t];
+                        sb[o0 + t] = sv[t];
+                    }
+                }
+        }
+        __syncthreads();  // the level's outputs are the next level's runs
+        uint32_t *t;
+        t = ka; ka = kb; kb = t;
+        t = ia; ia = ib; ib = t;
+        t = sa; sa = sb; sb = t;
+    }
+}
+
+// Every list of several chunks, one workgroup each (the sorted runs in (tkey, tid, tsk); tkey2,
+// tid2 and tsk2 are scratch for lists longer than kMergeLds).
+__global__ void __launch_bounds__(kMergeThreads)
+k_seg_merge(uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges,
+            uint32_t *__restrict__ tkey, uint32_t *__restrict__ tid, uint32_t *__restrict__ tsk,
+            uint32_t *__restrict__ tkey2, uint32_t *__restrict__ tid2, uint32_t *__restrict__ tsk2)
+{
+    static_assert(2 * kSegChunk == kMergeLds, "a list that fits in LDS has two chunks: one merge level");
+    __shared__ uint32_t lk[kMergeLds], lid[kMergeLds];
     __shared__ uint8_t lbox[kMergeLds];
     const uint2 rg = sranges[blockIdx.x];
     const uint32_t x = rg.x, n = rg.y - rg.x;
     if (n <= (uint32_t)kSegChunk) return;  // one chunk: already in place
-    if (n <= (uint32_t)kMergeLds) {
-        // all of a thread's loads in flight at once
-        uint32_t v[kMergeLds / kMergeThreads];
-#pragma unroll
-        for (int j = 0; j < kMergeLds / kMergeThreads; ++j) v[j] = tkey[x + min((uint32_t)(threadIdx.x + j * kMergeThreads), n - 1)];
-#pragma unroll
-        for (int j = 0; j < kMergeLds / kMergeThreads; ++j) {
-            const uint32_t i = threadIdx.x + j * kMergeThreads;
-            if (i < n) lk0[i] = v[j];
-        }
-        __syncthreads();
-        merge_levels<true>(lk0, lk1, tpos + x, tpos2 + x, n, x, kin, vin, kout, vout, lbox);
-    } else {
-        merge_levels<false>(tkey + x, tkey2 + x, tpos + x, tpos2 + x, n, x, kin, vin, kout, vout, lbox);
-    }
+    if (n <= (uint32_t)kMergeLds)
+        merge_staged(lk, lid, lbox, n, x, tkey, tid, tsk, kout, vout);
+    else
+        merge_global(tkey + x, tid + x, tsk + x, tkey2 + x, tid2 + x, tsk2 + x, n, kout + x, vout + x);
 }
 
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
@@ -1307,14 +1289,14 @@ void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, co
 int64_t seg_max_chunks(int64_t cap, int64_t nsup) { return (cap + kSegChunk - 1) / kSegChunk + nsup; }
 
 void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, const uint2 *sranges,
-                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *tkey,
-                     uint32_t *tpos, uint32_t *tkey2, uint32_t *tpos2, hipStream_t s)
+                     const uint32_t *sstart, int nsup, int64_t max_chunks, const uint32_t *dkey, uint32_t *const t[6],
+                     hipStream_t s)
 {
     if (nsup <= 0 || max_chunks <= 0) return;
     hipLaunchKernelGGL(k_seg_chunk_sort, dim3((unsigned)max_chunks), dim3(kChunkThreads), 0, s, kin, vin, kout, vout,
-                       sranges, sstart, nsup, dkey, tkey, tpos);
-    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nsup), dim3(kMergeThreads), 0, s, kin, vin, kout, vout, sranges,
-                       tkey, tpos, tkey2, tpos2);
+                       sranges, sstart, nsup, dkey, t[0], t[1], t[2]);
+    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nsup), dim3(kMergeThreads), 0, s, kout, vout, sranges, t[0], t[1],
+                       t[2], t[3], t[4], t[5]);
 }
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
