@@ -118,7 +118,7 @@ struct fgs_ctx {
     std::string err;
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
-    DBuf rect_sorted, start_rank, kpart;
+    DBuf rect_sorted, start_rank, kpart, csum;
     DBuf seg[6];  // sorted chunks (depth keys, ids, super-tile keys, twice) of super-tile lists being merged
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
     DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words, bin_sstart;
@@ -306,6 +306,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->blocksums.ensure(((size_t)scan_blocks_cap(nn) + 2) * 4));
     HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
     HIP_TRY(ctx, ctx->kpart.ensure((size_t)project_blocks(nn) * 2 * 4));
+    HIP_TRY(ctx, ctx->csum.ensure((size_t)project_blocks(nn) * 4));
     HIP_TRY(ctx, ctx->rect_sorted.ensure(N * sizeof(uint2)));
     HIP_TRY(ctx, ctx->start_rank.ensure((size_t)emit_chunks((int64_t)C) * 4));
     HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
@@ -535,13 +536,14 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     uint32_t *okeys = one_pass ? ctx->pkA.as<uint32_t>() : ctx->pkB.as<uint32_t>();
     uint32_t *ovals = one_pass ? ctx->pvA.as<uint32_t>() : ctx->pvB.as<uint32_t>();
     {
-        // one pair per covered super-tile, in gaussian order (the projection wrote ids 0..n-1)
+        // one pair per covered super-tile, in gaussian order (the projection wrote ids 0..n-1 and
+        // the block sums of its counts)
         Stage st_(ctx, "bin");
-        launch_scan_counts(ctx->idA.as<uint32_t>(), po.count, g.n, ctx->blocksums.as<uint32_t>(), s);
         launch_emit(ctx->idA.as<uint32_t>(), po.count, po.rect, ctx->blocksums.as<uint32_t>(),
                     ctx->offsets.as<uint32_t>(), g.n, supers_x, kSuperShift, L.cap, ctx->pkA.as<uint32_t>(),
                     ctx->pvA.as<uint32_t>(), ctx->rect_sorted.as<uint2>(), ctx->start_rank.as<uint32_t>(),
-                    status_words(ctx), nsup_pairs, nullptr, po.kpart, project_blocks(g.n), ktotal, s);
+                    status_words(ctx), nsup_pairs, nullptr, po.kpart, project_blocks(g.n), ktotal, s, nullptr, 0,
+                    ctx->csum.as<uint32_t>());
     }
     if (K_check) {
         // the pair count is known once the scan is complete (the emission of an oversized set
@@ -603,7 +605,7 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     {
         Stage st_(ctx, "project");
         launch_project(to_pk(g), to_camk(cam), rk, sp.rec, po.rect, po.count, ctx->dkA.as<uint32_t>(),
-                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part);
+                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part, ctx->csum.as<uint32_t>());
     }
     return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss, step_ovf,
                               first_of_step);
@@ -736,7 +738,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
-                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->seg[0], &ctx->seg[1], &ctx->seg[2], &ctx->seg[3], &ctx->seg[4], &ctx->seg[5],
+                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->csum, &ctx->seg[0], &ctx->seg[1], &ctx->seg[2], &ctx->seg[3], &ctx->seg[4], &ctx->seg[5],
                     &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets, &ctx->ms_img, &ctx->ms_ssim, &ctx->ms_reg,

@@ -122,11 +122,14 @@ void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // rectangle; kpart (2 words per workgroup, project_blocks(n) workgroups) the workgroups'
 // (tile, gaussian) pair and visible gaussian counts, summed by launch_scan_counts. reg_part
 // (nullable, project_blocks(n) floats): each workgroup's sum of the scale regulariser's terms
-// |s1 - s2| + s3 (s = exp(log-scale); Eq. 15).
+// |s1 - s2| + s3 (s = exp(log-scale); Eq. 15). csum (nullable, project_blocks(n) words): each
+// workgroup's sum of count[], the block sums of a scan of the counts in gaussian order (see
+// launch_emit).
 int64_t project_blocks(int64_t n);
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
-                    uint32_t *kpart, hipStream_t s, uint32_t id_base = 0, float *reg_part = nullptr);
+                    uint32_t *kpart, hipStream_t s, uint32_t id_base = 0, float *reg_part = nullptr,
+                    uint32_t *csum = nullptr);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
@@ -152,13 +155,16 @@ void launch_scan_counts(const uint32_t *ids, const uint32_t *count, int64_t n, u
 // host-mapped): [0] = pairs, [1] |= overflow. rect_sorted (n) receives the tile rectangles in
 // rank order, start_rank (emit_chunks(cap) words) the first rank of every emission chunk. The
 // projection's per-workgroup counts kpart (proj_blocks workgroups) are summed into *ktotal and
-// status[ST_PAIRS] ((tile, gaussian) pairs) and status[ST_VISIBLE].
+// status[ST_PAIRS] ((tile, gaussian) pairs) and status[ST_VISIBLE]. csum (nullable): the
+// projection's per-workgroup sums of count[] when ids is the identity (ranks in gaussian order),
+// used as the scan's block sums in place of launch_scan_counts' (which then need not run); it is
+// scanned in place when there are more than 4,096 scan blocks.
 int64_t emit_chunks(int64_t cap);
 void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, uint32_t *blocksums,
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
                  uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,
-                 const uint2 *view_tab = nullptr, uint32_t view_n = 0);
+                 const uint2 *view_tab = nullptr, uint32_t view_n = 0, uint32_t *csum = nullptr);
 
 // Tile lists from super-tile lists (kSuper x kSuper tiles per super-tile). The gaussians' pairs
 // are emitted per covered super-tile (launch_emit with shift log2(kSuper)), sorted by the key bits

@@ -113,39 +113,44 @@ __device__ inline bool pixel_span(double c, double r, int32_t size, int32_t &lo,
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
-                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i);
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i,
+                                uint32_t &cnt);
 
 // Projects every gaussian (one thread each): record, tile rectangle, count of covered tiles or
 // super-tiles, depth key; kpart[2 b], kpart[2 b + 1] receive block b's number of (tile, gaussian)
-// pairs and of gaussians that cover a tile (summed by the scan, so nothing needs zeroing first).
+// pairs and of gaussians that cover a tile (summed by the scan, so nothing needs zeroing first);
+// csum[b] (nullable) block b's sum of the counts (the scan's block sums in gaussian order).
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
           uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart, uint32_t id_base,
-          float *__restrict__ reg_part)
+          float *__restrict__ reg_part, uint32_t *__restrict__ csum)
 {
-    __shared__ uint32_t wsum[2][4];
+    __shared__ uint32_t wsum[3][4];
     __shared__ float wreg[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n_out = id_base + (uint32_t)g.n;
-    uint32_t tiles = 0;  // (tile, gaussian) pairs of this gaussian
+    uint32_t tiles = 0, cnt = 0;  // (tile, gaussian) pairs of this gaussian; its count
     if (i < g.n) {
-        tiles = project_one(g, cam, rk, rec, rect, count, dkey, shift, i);
+        tiles = project_one(g, cam, rk, rec, rect, count, dkey, shift, i, cnt);
         ids[i] = id_base + (uint32_t)i;
     }
     uint32_t vis = tiles != 0u;
     for (int o = 32; o > 0; o >>= 1) {
         tiles += __shfl_xor(tiles, o);
         vis += __shfl_xor(vis, o);
+        cnt += __shfl_xor(cnt, o);
     }
     if ((threadIdx.x & 63) == 0) {
         wsum[0][threadIdx.x >> 6] = tiles;
         wsum[1][threadIdx.x >> 6] = vis;
+        wsum[2][threadIdx.x >> 6] = cnt;
     }
     __syncthreads();
     if (threadIdx.x < 2)
         kpart[2 * blockIdx.x + threadIdx.x] =
             wsum[threadIdx.x][0] + wsum[threadIdx.x][1] + wsum[threadIdx.x][2] + wsum[threadIdx.x][3];
+    if (csum && threadIdx.x == 2) csum[blockIdx.x] = wsum[2][0] + wsum[2][1] + wsum[2][2] + wsum[2][3];
     if (reg_part) {
         // the scale regulariser's terms (Eq. 15): |s1 - s2| + s3 with s = exp(log-scale)
         float r = 0.0f;
@@ -161,7 +166,8 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
 }
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
-                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i)
+                                uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i,
+                                uint32_t &cnt_out)
 {
     Proj p;
     project_gaussian(g, i, cam, rk.lowpass, p);
@@ -196,6 +202,7 @@ __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict
     count[i] = cnt;
     dkey[i] = key;
     rect[i] = rc;
+    cnt_out = cnt;
     return tiles;
 }
 
@@ -430,10 +437,10 @@ int64_t project_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
                     uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *kpart,
-                    hipStream_t s, uint32_t id_base, float *reg_part)
+                    hipStream_t s, uint32_t id_base, float *reg_part, uint32_t *csum)
 {
     hipLaunchKernelGGL(k_project, dim3((unsigned)project_blocks(g.n)), dim3(256), 0, s, g, cam, rk, rec, rect, count,
-                       dkey, ids, n_out, shift, kpart, id_base, reg_part);
+                       dkey, ids, n_out, shift, kpart, id_base, reg_part, csum);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,

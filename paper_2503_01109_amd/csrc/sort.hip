@@ -337,16 +337,17 @@ k_scan_apply(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ coun
              int64_t n, const uint32_t *__restrict__ blocksums, bool scanned, uint32_t *__restrict__ offsets,
              uint2 *__restrict__ rect_sorted, uint32_t *__restrict__ start_rank, uint32_t max_chunks,
              uint32_t *__restrict__ status, const uint32_t *__restrict__ kpart, int npb,
-             uint32_t *__restrict__ ktotal)
+             uint32_t *__restrict__ ktotal, uint32_t per)
 {
     __shared__ uint32_t w[8];
-    // this block's first offset: the sum of the block sums before it
+    // this block's first offset: the sum of the block sums before it (per of them for each block of
+    // this scan: 1 for k_count_reduce's, ITEMS for the projection's workgroups of 256 gaussians)
     uint32_t boff;
     if (scanned) {
-        boff = blocksums[blockIdx.x];
+        boff = blocksums[blockIdx.x * per];
     } else {
         uint32_t pre = 0;
-        for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kSortThreads) pre += blocksums[j];
+        for (uint32_t j = threadIdx.x; j < blockIdx.x * per; j += kSortThreads) pre += blocksums[j];
         block_excl_scan(pre, w, &boff);
         if (blockIdx.x == 0) sum_kpart(kpart, npb, status, ktotal, w);
     }
@@ -1242,23 +1243,27 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
                  uint32_t *offsets, int64_t n, int32_t keys_x, int shift, int64_t cap, uint32_t *keys, uint32_t *vals,
                  uint2 *rect_sorted, uint32_t *start_rank, uint32_t *status, uint32_t *n_pairs_dev,
                  uint32_t *host_status, const uint32_t *kpart, int64_t proj_blocks, uint32_t *ktotal, hipStream_t s,
-                 const uint2 *view_tab, uint32_t view_n)
+                 const uint2 *view_tab, uint32_t view_n, uint32_t *csum)
 {
-    // blocksums holds the per-block sums of the counts in [0, nb)
+    // the block sums: blocksums (launch_scan_counts, one per scan block in [0, nb)) or csum (the
+    // projection's, one per 256 ranks, so scan_items(n) per scan block)
     const int nb = (int)scan_blocks(n);
     const bool scanned = nb > kScanFold;
+    uint32_t *sums = csum ? csum : blocksums;
+    const uint32_t per = csum ? (uint32_t)scan_items(n) : 1u;
+    const int nsums = csum ? (int)project_blocks(n) : nb;
     if (scanned)
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, blocksums, nb, status, kpart,
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortThreads), 0, s, sums, nsums, status, kpart,
                            (int)proj_blocks, ktotal);
     const dim3 grid(nb > 0 ? nb : 1);
     if (scan_items(n) == 2)
-        hipLaunchKernelGGL(k_scan_apply<2>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums, scanned,
+        hipLaunchKernelGGL(k_scan_apply<2>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, sums, scanned,
                            offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart,
-                           (int)proj_blocks, ktotal);
+                           (int)proj_blocks, ktotal, per);
     else
-        hipLaunchKernelGGL(k_scan_apply<4>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, blocksums, scanned,
+        hipLaunchKernelGGL(k_scan_apply<4>, grid, dim3(kSortThreads), 0, s, ids, count, rect, n, sums, scanned,
                            offsets, rect_sorted, start_rank, (uint32_t)emit_chunks(cap), status, kpart,
-                           (int)proj_blocks, ktotal);
+                           (int)proj_blocks, ktotal, per);
     hipLaunchKernelGGL(k_emit, dim3(grid_for(cap, kEmitChunk, 2048)), dim3(kSortThreads), 0, s, rect_sorted, ids,
                        offsets, start_rank, n, keys_x, shift, cap, view_tab, view_n, keys, vals, status, n_pairs_dev,
                        host_status);
