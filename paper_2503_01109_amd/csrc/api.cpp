@@ -119,6 +119,7 @@ struct fgs_ctx {
     // workspace of one forward (sized for the largest n / pair capacity seen)
     DBuf rect, count, dkA, dkB, idA, idB, blocksums, offsets, pkA, pkB, pvA, pvB, hist, grad2d;
     DBuf rect_sorted, start_rank, kpart, csum;
+    DBuf shist;  // per projection workgroup and super-tile: covering gaussians (views of <= 256 super-tiles)
     DBuf seg[6];  // sorted chunks (depth keys, ids, super-tile keys, twice) of super-tile lists being merged
     // tile lists from super-tile lists (sized for bin_nsup super-tiles, bin_T tiles, bin_cap pairs)
     DBuf bin_sranges, bin_cstart, bin_csuper, bin_chist, bin_tile_total, bin_words, bin_sstart;
@@ -307,6 +308,7 @@ fgs_status ensure_ws(fgs_ctx *ctx, int64_t n, int64_t cap)
     HIP_TRY(ctx, ctx->offsets.ensure((N + 1) * 4));
     HIP_TRY(ctx, ctx->kpart.ensure((size_t)project_blocks(nn) * 2 * 4));
     HIP_TRY(ctx, ctx->csum.ensure((size_t)project_blocks(nn) * 4));
+    HIP_TRY(ctx, ctx->shist.ensure(((size_t)project_blocks(nn) + 1) * 256 * 4));
     HIP_TRY(ctx, ctx->rect_sorted.ensure(N * sizeof(uint2)));
     HIP_TRY(ctx, ctx->start_rank.ensure((size_t)emit_chunks((int64_t)C) * 4));
     HIP_TRY(ctx, ctx->pkA.ensure(C * 4));
@@ -530,12 +532,19 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     const BinWS bw = bin_ws(ctx);
     const int sbits = key_bits_for(nsup);
     const bool one_pass = sbits <= 8;
+    // up to 256 super-tiles the pairs go straight from the projection's histograms to their lists
+    const bool direct = nsup <= 256;
+    uint32_t *shist = ctx->shist.as<uint32_t>(), *stot = shist + (size_t)project_blocks(g.n) * 256;
     // the super-tile sort leaves its values in svals and its keys in the other key buffer; the
     // depth order goes into the remaining pair of buffers
     uint32_t *svals = one_pass ? ctx->pvB.as<uint32_t>() : ctx->pvA.as<uint32_t>();
     uint32_t *okeys = one_pass ? ctx->pkA.as<uint32_t>() : ctx->pkB.as<uint32_t>();
     uint32_t *ovals = one_pass ? ctx->pvA.as<uint32_t>() : ctx->pvB.as<uint32_t>();
-    {
+    if (direct) {
+        // the projection's super-tile counts per workgroup, scanned; the pair counts summed
+        Stage st_(ctx, "bin");
+        launch_super_scan(g.n, shist, stot, po.kpart, status_words(ctx), ktotal, s);
+    } else {
         // one pair per covered super-tile, in gaussian order (the projection wrote ids 0..n-1 and
         // the block sums of its counts)
         Stage st_(ctx, "bin");
@@ -557,12 +566,19 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     {
         // super-tile lists (stable: each in gaussian order), their ranges and chunk table
         Stage st_(ctx, "tile_sort");
-        const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
-        uint32_t *keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
-                                           ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
-        if (!one_pass) launch_ranges(keys, nsup_pairs, sranges, nsup, kSuperKeyMask, s);
         uint32_t *sstart = ctx->bin_sstart.as<uint32_t>();
-        launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart);
+        uint32_t *keys;
+        if (direct) {
+            keys = ctx->pkB.as<uint32_t>();  // (one_pass: svals is pvB)
+            launch_super_scatter(po.rect, po.count, g.n, supers_x, shist, stot, ktotal, L.cap, keys, svals, s);
+            launch_bin_chunks(bw, sranges, stot, nsup, s, sstart, ktotal, L.cap);
+        } else {
+            const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
+            keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
+                                     ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
+            if (!one_pass) launch_ranges(keys, nsup_pairs, sranges, nsup, kSuperKeyMask, s);
+            launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart);
+        }
         uint32_t *const tmp[6] = {ctx->seg[0].as<uint32_t>(), ctx->seg[1].as<uint32_t>(), ctx->seg[2].as<uint32_t>(),
                                   ctx->seg[3].as<uint32_t>(), ctx->seg[4].as<uint32_t>(), ctx->seg[5].as<uint32_t>()};
         launch_seg_sort(keys, svals, okeys, ovals, sranges, sstart, nsup, seg_max_chunks(L.cap, nsup),
@@ -604,8 +620,11 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
     const ProjOut po{ctx->rect.as<uint2>(), ctx->count.as<uint32_t>(), ctx->kpart.as<uint32_t>()};
     {
         Stage st_(ctx, "project");
+        const int supers_x = (rk.tiles_x + kSuper - 1) / kSuper, supers_y = (rk.tiles_y + kSuper - 1) / kSuper;
+        const bool direct = supers_x * supers_y <= 256;  // (as enqueue_bin_raster decides)
         launch_project(to_pk(g), to_camk(cam), rk, sp.rec, po.rect, po.count, ctx->dkA.as<uint32_t>(),
-                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part, ctx->csum.as<uint32_t>());
+                       ctx->idA.as<uint32_t>(), ndev, kSuperShift, po.kpart, s, 0, reg_part, ctx->csum.as<uint32_t>(),
+                       direct ? ctx->shist.as<uint32_t>() : nullptr, supers_x);
     }
     return enqueue_bin_raster(ctx, g, cam, o, tw, th, img, state, L, po, K_check, host_status, raster, loss, step_ovf,
                               first_of_step);
@@ -738,7 +757,7 @@ fgs_status fgs_ctx_destroy(fgs_ctx *ctx)
     if (ctx->stream || true) (void)hipStreamSynchronize(ctx->stream);
     clear_profile(ctx, true);
     DBuf *bufs[] = {&ctx->prof_counts, &ctx->rect, &ctx->count, &ctx->dkA, &ctx->dkB, &ctx->idA, &ctx->idB,
-                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->csum, &ctx->seg[0], &ctx->seg[1], &ctx->seg[2], &ctx->seg[3], &ctx->seg[4], &ctx->seg[5],
+                    &ctx->blocksums, &ctx->pkA, &ctx->pkB, &ctx->pvA, &ctx->pvB, &ctx->csum, &ctx->shist, &ctx->seg[0], &ctx->seg[1], &ctx->seg[2], &ctx->seg[3], &ctx->seg[4], &ctx->seg[5],
                     &ctx->hist, &ctx->grad2d,
                     &ctx->words, &ctx->ms_state, &ctx->ms_dl, &ctx->ms_grad, &ctx->ms_partials,
                     &ctx->seed_ws, &ctx->seed_sc, &ctx->offsets, &ctx->ms_img, &ctx->ms_ssim, &ctx->ms_reg,

@@ -124,12 +124,14 @@ void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // (nullable, project_blocks(n) floats): each workgroup's sum of the scale regulariser's terms
 // |s1 - s2| + s3 (s = exp(log-scale); Eq. 15). csum (nullable, project_blocks(n) words): each
 // workgroup's sum of count[], the block sums of a scan of the counts in gaussian order (see
-// launch_emit).
+// launch_emit). shist (nullable; at most 256 super-tiles, supers_x per row; 256 x
+// project_blocks(n) words): shist[s project_blocks(n) + b] = the number of workgroup b's gaussians
+// that cover super-tile s (see launch_super_pairs).
 int64_t project_blocks(int64_t n);
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec,
                     uint2 *rect, uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift,
                     uint32_t *kpart, hipStream_t s, uint32_t id_base = 0, float *reg_part = nullptr,
-                    uint32_t *csum = nullptr);
+                    uint32_t *csum = nullptr, uint32_t *shist = nullptr, int supers_x = 0);
 
 // LSD radix sort of (key, value) pairs over key bits [0, key_bits) with 8-bit digits; the
 // element count is read from *n_dev (clamped to n_cap). Ping-pongs between (ka, va) and
@@ -195,7 +197,20 @@ void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, co
 // sstart non-null, also the first depth-order chunk of every super-tile list, nsup + 1 words), then
 // the per-chunk tile counts.
 void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
-                       uint32_t *sstart = nullptr);
+                       uint32_t *sstart = nullptr, const uint32_t *ktotal = nullptr, int64_t cap = 0);
+// Super-tile lists of one view with at most 256 super-tiles, straight from the projection
+// (launch_project with shist): launch_super_scan scans the per-workgroup super-tile counts hist
+// (256 x project_blocks(n) words) over the workgroups in place, writes the super-tile totals
+// (256 words) and sums the projection's counts kpart (into *ktotal, status[ST_PAIRS] and
+// status[ST_VISIBLE], as launch_emit does); launch_super_scatter then writes every covered
+// super-tile's (key with box, gaussian id) pair to (keys, vals), each super-tile's list in
+// gaussian order, or nothing when *ktotal exceeds cap. Ranges: launch_bin_chunks with the
+// totals as digit_totals and (ktotal, cap).
+void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32_t *kpart, uint32_t *status,
+                       uint32_t *ktotal, hipStream_t s);
+void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
+                          const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
+                          hipStream_t s);
 void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s);
 // Depth order inside every super-tile list: (kin, vin) hold the lists in ascending gaussian id
 // (ranges sranges, nsup lists, chunk table sstart from launch_bin_chunks); each list is written

@@ -114,26 +114,42 @@ __device__ inline bool pixel_span(double c, double r, int32_t size, int32_t &lo,
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
                                 uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i,
-                                uint32_t &cnt);
+                                uint32_t &cnt, uint2 &rc);
 
 // Projects every gaussian (one thread each): record, tile rectangle, count of covered tiles or
 // super-tiles, depth key; kpart[2 b], kpart[2 b + 1] receive block b's number of (tile, gaussian)
 // pairs and of gaussians that cover a tile (summed by the scan, so nothing needs zeroing first);
-// csum[b] (nullable) block b's sum of the counts (the scan's block sums in gaussian order).
+// csum[b] (nullable) block b's sum of the counts (the scan's block sums in gaussian order);
+// shist (nullable; at most 256 super-tiles, supers_x per row): shist[s G + b], G = gridDim.x, the
+// number of block b's gaussians covering super-tile s.
 __global__ void __launch_bounds__(256)
 k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
           uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, uint32_t *__restrict__ ids,
           uint32_t *__restrict__ n_out, int shift, uint32_t *__restrict__ kpart, uint32_t id_base,
-          float *__restrict__ reg_part, uint32_t *__restrict__ csum)
+          float *__restrict__ reg_part, uint32_t *__restrict__ csum, uint32_t *__restrict__ shist, int supers_x)
 {
     __shared__ uint32_t wsum[3][4];
     __shared__ float wreg[4];
+    __shared__ uint32_t lh[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *n_out = id_base + (uint32_t)g.n;
+    if (shist) lh[threadIdx.x] = 0u;  // (ordered before the adds by the barrier below)
     uint32_t tiles = 0, cnt = 0;  // (tile, gaussian) pairs of this gaussian; its count
+    uint2 rc = make_uint2(1u, 0u);
     if (i < g.n) {
-        tiles = project_one(g, cam, rk, rec, rect, count, dkey, shift, i, cnt);
+        tiles = project_one(g, cam, rk, rec, rect, count, dkey, shift, i, cnt, rc);
         ids[i] = id_base + (uint32_t)i;
+    }
+    if (shist) {
+        __syncthreads();
+        if (cnt) {
+            const uint32_t sx0 = (rc.x & 0xFFFFu) >> shift, sx1 = (rc.x >> 16) >> shift;
+            const uint32_t sy0 = (rc.y & 0xFFFFu) >> shift, sy1 = (rc.y >> 16) >> shift;
+            for (uint32_t sy = sy0; sy <= sy1; ++sy)
+                for (uint32_t sx = sx0; sx <= sx1; ++sx) atomicAdd(&lh[sy * (uint32_t)supers_x + sx], 1u);
+        }
+        __syncthreads();
+        shist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = lh[threadIdx.x];
     }
     uint32_t vis = tiles != 0u;
     for (int o = 32; o > 0; o >>= 1) {
@@ -167,7 +183,7 @@ k_project(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restr
 
 __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict__ rec, uint2 *__restrict__ rect,
                                 uint32_t *__restrict__ count, uint32_t *__restrict__ dkey, int shift, int64_t i,
-                                uint32_t &cnt_out)
+                                uint32_t &cnt_out, uint2 &rc_out)
 {
     Proj p;
     project_gaussian(g, i, cam, rk.lowpass, p);
@@ -203,6 +219,7 @@ __device__ uint32_t project_one(ParamsK g, CamK cam, RasterK rk, Rec *__restrict
     dkey[i] = key;
     rect[i] = rc;
     cnt_out = cnt;
+    rc_out = rc;
     return tiles;
 }
 
@@ -437,10 +454,10 @@ int64_t project_blocks(int64_t n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 void launch_project(const ParamsK &g, const CamK &cam, const RasterK &rk, Rec *rec, uint2 *rect,
                     uint32_t *count, uint32_t *dkey, uint32_t *ids, uint32_t *n_out, int shift, uint32_t *kpart,
-                    hipStream_t s, uint32_t id_base, float *reg_part, uint32_t *csum)
+                    hipStream_t s, uint32_t id_base, float *reg_part, uint32_t *csum, uint32_t *shist, int supers_x)
 {
     hipLaunchKernelGGL(k_project, dim3((unsigned)project_blocks(g.n)), dim3(256), 0, s, g, cam, rk, rec, rect, count,
-                       dkey, ids, n_out, shift, kpart, id_base, reg_part, csum);
+                       dkey, ids, n_out, shift, kpart, id_base, reg_part, csum, shist, supers_x);
 }
 
 void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, float lowpass, float *grad2d,

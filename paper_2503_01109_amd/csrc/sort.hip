@@ -86,8 +86,13 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
 // thread scans a contiguous run of the row serially, so one block-wide scan covers rows of up to
 // 256 x kRowRun blocks (longer rows take several rounds).
 constexpr int kRowRun = 16;
+__device__ inline void sum_kpart(const uint32_t *__restrict__ kpart, int npb, uint32_t *__restrict__ status,
+                                 uint32_t *__restrict__ ktotal, uint32_t *w);
+
+// kpart (nullable): block 0 also sums the projection's counts (see sum_kpart).
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ totals)
+k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ totals, const uint32_t *__restrict__ kpart,
+                int npb, uint32_t *__restrict__ status, uint32_t *__restrict__ ktotal)
 {
     __shared__ uint32_t w[8];
     uint32_t *row = hist + (size_t)blockIdx.x * G;
@@ -112,6 +117,7 @@ k_radix_rowscan(uint32_t *__restrict__ hist, int G, uint32_t *__restrict__ total
         carry += tot;
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (kpart && blockIdx.x == 0) sum_kpart(kpart, npb, status, ktotal, w);
 }
 
 // Stable scatter of the workgroup's chunk by one digit, through LDS (for digits spread over many
@@ -408,6 +414,122 @@ __device__ inline uint32_t cover_box(uint2 rc, uint32_t sx, uint32_t sy)
     return (uint32_t)lx0 | (uint32_t)lx1 << 2 | (uint32_t)ly0 << 4 | (uint32_t)ly1 << 6;
 }
 
+// The super-tile pairs of one view straight from the projection, for at most 256 super-tiles (one
+// 8-bit digit): a workgroup per projection workgroup b of 256 gaussians generates b's pairs in
+// gaussian order (per gaussian its covered super-tiles row by row, each key carrying the box of
+// covered tiles above kBoxShift, the value the gaussian's id) and scatters them stably by
+// super-tile, kScatterTile at a time through LDS like k_radix_scatter_lds, to the offsets of hist
+// (the projection's per-workgroup super-tile counts, hist[s G + b], scanned per super-tile by
+// k_radix_rowscan) after the totals of the super-tiles before. The lists come out in gaussian
+// order. Nothing is written when the (tile, gaussian) pairs *ktotal exceed cap.
+__global__ void __launch_bounds__(kSortThreads)
+k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ count, int64_t n, int32_t supers_x,
+                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
+                const uint32_t *__restrict__ ktotal, int64_t cap, uint32_t *__restrict__ kout,
+                uint32_t *__restrict__ vout)
+{
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t gbase[256];   // next global slot of each super-tile
+    __shared__ uint32_t tstart[256];  // first tile slot of each super-tile
+    __shared__ uint32_t run[256];     // super-tile counts of the tile, then its next tile slots
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t skey[kScatterTile], sval[kScatterTile];
+    __shared__ uint32_t soff[kSortThreads];  // the gaussians' first pair in the workgroup
+    __shared__ uint2 srect[kSortThreads];
+    __shared__ uint32_t w8[8];
+    const int tid = threadIdx.x, wid = tid / kWave;
+    if ((int64_t)*ktotal > cap) return;  // (uniform) overflow: nothing is placed
+    {
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(totals[tid], w8, &tot);
+        gbase[tid] = ex + hist[(size_t)tid * gridDim.x + blockIdx.x];
+        run[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    }
+    const int64_t gi = (int64_t)blockIdx.x * kSortThreads + tid;
+    const uint32_t c = gi < n ? count[gi] : 0u;
+    uint32_t P;
+    soff[tid] = block_excl_scan(c, w8, &P);  // (synchronizes the block)
+    srect[tid] = gi < n ? rect[gi] : make_uint2(1u, 0u);
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < P; t0 += kScatterTile) {
+        const uint32_t nt = min((uint32_t)kScatterTile, P - t0);
+        const int rounds = (int)((nt + kSortThreads - 1) / kSortThreads);
+        uint32_t key[kScatterItems], val[kScatterItems], rank[kScatterItems], cnt[kScatterItems];
+        // the tile's pairs and their super-tile counts (one add per wave and super-tile)
+#pragma unroll
+        for (int r = 0; r < kScatterItems; ++r) {
+            if (r >= rounds) break;
+            const uint32_t j = t0 + (uint32_t)(r * kSortThreads + tid);
+            const bool valid = j < t0 + nt;
+            key[r] = 0u;
+            val[r] = 0u;
+            if (valid) {
+                const uint32_t g = last_le(soff, 0, kSortThreads - 1, j);  // the gaussian holding pair j
+                const uint32_t idx = j - soff[g];
+                const uint2 rc = srect[g];
+                const uint32_t sx0 = (rc.x & 0xFFFFu) >> kSuperShift, sx1 = (rc.x >> 16) >> kSuperShift;
+                const uint32_t sy0 = (rc.y & 0xFFFFu) >> kSuperShift;
+                const uint32_t wd = sx1 - sx0 + 1;
+                const uint32_t dy = idx / wd;
+                const uint32_t kx = sx0 + (idx - dy * wd), ky = sy0 + dy;
+                key[r] = (ky * (uint32_t)supers_x + kx) | cover_box(rc, kx, ky) << kBoxShift;
+                val[r] = (uint32_t)(blockIdx.x * kSortThreads) + g;
+            }
+            const uint32_t d = key[r] & 0xFFu;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            rank[r] = valid ? __popcll(peers & lanemask_lt()) : kSortThreads;  // invalid: no leader
+            cnt[r] = __popcll(peers);
+            if (rank[r] == 0) atomicAdd(&run[d], cnt[r]);
+        }
+        __syncthreads();
+        {
+            uint32_t tot;
+            const uint32_t c2 = run[tid];
+            tstart[tid] = block_excl_scan(c2, w8, &tot);  // (synchronizes the block)
+            run[tid] = tstart[tid];
+        }
+        // local slots, round by round: the leaders publish their wave's count of their super-tile,
+        // every lane adds the waves before it, then the leaders advance their super-tile's slot
+#pragma unroll
+        for (int r = 0; r < kScatterItems; ++r) {
+            if (r >= rounds) break;
+            const uint32_t d = key[r] & 0xFFu;
+            if (rank[r] == 0) wcnt[wid][d] = cnt[r];
+            __syncthreads();
+            if (rank[r] < (uint32_t)kSortThreads) {
+                uint32_t pos = run[d] + rank[r];
+                for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+                skey[pos] = key[r];
+                sval[pos] = val[r];
+            }
+            __syncthreads();
+            if (rank[r] == 0) {
+                atomicAdd(&run[d], cnt[r]);
+                wcnt[wid][d] = 0;
+            }
+        }
+        __syncthreads();
+        // out in tile order: slot j of super-tile d goes to gbase[d] + (j - tstart[d])
+        for (uint32_t j = tid; j < nt; j += kSortThreads) {
+            const uint32_t k = skey[j], d = k & 0xFFu;
+            const uint32_t gpos = gbase[d] + (j - tstart[d]);
+            kout[gpos] = k;
+            vout[gpos] = sval[j];
+        }
+        __syncthreads();
+        gbase[tid] += run[tid] - tstart[tid];
+        run[tid] = 0;
+        __syncthreads();
+    }
+}
+
 // Load-balanced emission: the K pairs are cut into chunks of kEmitChunk consecutive pair
 // indices; a block takes a chunk, finds the ranks it spans by binary search over the
 // per-rank offsets, and its threads write consecutive pair indices (coalesced), each finding its
@@ -489,15 +611,18 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
              uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart)
+             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, const uint32_t *__restrict__ ktotal,
+             int64_t cap)
 {
     __shared__ uint32_t w[8];
     if (digit_totals) {
         // one radix pass sorted the super-tile keys: their ranges are the scanned digit totals
+        // (empty when the pairs overflowed the capacity, ktotal non-null: nothing was placed)
+        const bool ovf = ktotal && (int64_t)*ktotal > cap;
         uint32_t carry = 0;
         for (int base = 0; base < nsup; base += kSortThreads) {
             const int sidx = base + threadIdx.x;
-            const uint32_t v = sidx < nsup ? digit_totals[sidx] : 0u;
+            const uint32_t v = sidx < nsup && !ovf ? digit_totals[sidx] : 0u;
             uint32_t tot;
             const uint32_t ex = carry + block_excl_scan(v, w, &tot);
             if (sidx < nsup) sranges[sidx] = make_uint2(ex, ex + v);
@@ -1203,7 +1328,8 @@ uint32_t *launch_radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
         uint32_t *ok = dk, *ov = p == passes - 1 ? v_final : dv;
         hipLaunchKernelGGL(k_radix_hist, dim3(ws.G), dim3(kSortThreads), 0, s, sk, n_dev, (uint32_t)n_cap, shift,
                            mask, ws.hist);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, s, ws.hist, ws.G, ws.totals);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, s, ws.hist, ws.G, ws.totals, nullptr, 0,
+                           nullptr, nullptr);
         // the last pass of several sorts the top bits, whose few values already give long runs
         if (p == passes - 1 && passes > 1)
             hipLaunchKernelGGL(k_radix_scatter, dim3(ws.G), dim3(kSortThreads), 0, s, sk, sv, ok, ov, n_dev,
@@ -1269,13 +1395,29 @@ void launch_emit(const uint32_t *ids, const uint32_t *count, const uint2 *rect, 
                        host_status);
 }
 
+void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32_t *kpart, uint32_t *status,
+                       uint32_t *ktotal, hipStream_t s)
+{
+    const int G = (int)project_blocks(n);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, s, hist, G, totals, kpart, G, status, ktotal);
+}
+
+void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
+                          const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
+                          hipStream_t s)
+{
+    const int G = (int)project_blocks(n);
+    hipLaunchKernelGGL(k_super_scatter, dim3((unsigned)G), dim3(kSortThreads), 0, s, rect, count, n, supers_x, hist,
+                       totals, ktotal, cap, keys, vals);
+}
+
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
 void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
-                       uint32_t *sstart)
+                       uint32_t *sstart, const uint32_t *ktotal, int64_t cap)
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
-                       b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart);
+                       b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart, ktotal, cap);
 }
 
 void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s)
