@@ -1,11 +1,12 @@
 // Binning of projected gaussians into screen tiles and the (tile, depth) ordering of every
 // tile's list.
 //
-// Ordering scheme of one view: every gaussian emits one (super-tile, id) pair per covered square
-// of kSuper x kSuper tiles, in id order; a stable sort of those pairs by super-tile alone gives
-// each super-tile's list in id order, and each list is then put in (depth, index) order by a sort
-// of its own on the depth keys (k_seg_chunk_sort, k_seg_merge: stable, so equal depths keep
-// ascending index). An in-order expansion of each super-tile list into the lists of its tiles keeps
+// Ordering scheme of one view: every gaussian has one (super-tile, id) pair per covered square of
+// kSuper x kSuper tiles; the pairs are placed into per-super-tile lists in id order (up to 256
+// super-tiles straight from the projection's per-workgroup histograms by k_super_scatter, else
+// emitted in id order and sorted stably by super-tile), and each list is then put in (depth,
+// index) order by a sort of its own on the depth keys (k_seg_chunk_sort, k_seg_merge: stable, so
+// equal depths keep ascending index). An in-order expansion of each super-tile list into the lists of its tiles keeps
 // that order. The result is exactly the stable (tile, depth, index) order of one pair per covered
 // tile, while the sorts only move one pair per covered super-tile. A keyframe window orders all
 // its views at once the other way round: the gaussians of every view are sorted by depth first
