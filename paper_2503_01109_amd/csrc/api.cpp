@@ -570,8 +570,8 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         uint32_t *keys;
         if (direct) {
             keys = ctx->pkB.as<uint32_t>();  // (one_pass: svals is pvB)
-            launch_super_scatter(po.rect, po.count, g.n, supers_x, shist, stot, ktotal, L.cap, keys, svals, s);
-            launch_bin_chunks(bw, sranges, stot, nsup, s, sstart, ktotal, L.cap);
+            launch_super_scatter(po.rect, po.count, g.n, supers_x, shist, stot, ktotal, L.cap, keys, svals, bw,
+                                 sranges, nsup, sstart, s);
         } else {
             const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
             keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),

@@ -204,13 +204,13 @@ void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_tot
 // (256 words) and sums the projection's counts kpart (into *ktotal, status[ST_PAIRS] and
 // status[ST_VISIBLE], as launch_emit does); launch_super_scatter then writes every covered
 // super-tile's (key with box, gaussian id) pair to (keys, vals), each super-tile's list in
-// gaussian order, or nothing when *ktotal exceeds cap. Ranges: launch_bin_chunks with the
-// totals as digit_totals and (ktotal, cap).
+// gaussian order, or nothing when *ktotal exceeds cap, and writes what launch_bin_chunks would
+// (the ranges sranges, the chunk table of b and sstart; empty lists on overflow).
 void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32_t *kpart, uint32_t *status,
                        uint32_t *ktotal, hipStream_t s);
 void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
                           const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
-                          hipStream_t s);
+                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, hipStream_t s);
 void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s);
 // Depth order inside every super-tile list: (kin, vin) hold the lists in ascending gaussian id
 // (ranges sranges, nsup lists, chunk table sstart from launch_bin_chunks); each list is written

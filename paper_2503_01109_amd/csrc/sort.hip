@@ -422,12 +422,19 @@ __device__ inline uint32_t cover_box(uint2 rc, uint32_t sx, uint32_t sy)
 // super-tile, kScatterTile at a time through LDS like k_radix_scatter_lds, to the offsets of hist
 // (the projection's per-workgroup super-tile counts, hist[s G + b], scanned per super-tile by
 // k_radix_rowscan) after the totals of the super-tiles before. The lists come out in gaussian
-// order. Nothing is written when the (tile, gaussian) pairs *ktotal exceed cap.
+// order. Nothing is written when the (tile, gaussian) pairs *ktotal exceed cap. Workgroup 0 also
+// writes the lists' ranges and chunk tables (as k_bin_chunks; empty on overflow).
+__device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
+                             uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
+                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, bool ovf, uint32_t *w);
+
 __global__ void __launch_bounds__(kSortThreads)
 k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ count, int64_t n, int32_t supers_x,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
                 const uint32_t *__restrict__ ktotal, int64_t cap, uint32_t *__restrict__ kout,
-                uint32_t *__restrict__ vout)
+                uint32_t *__restrict__ vout, uint2 *__restrict__ sranges, int nsup, uint32_t *__restrict__ cstart,
+                uint32_t *__restrict__ csuper, uint32_t max_chunks, uint32_t *__restrict__ nchunks,
+                uint32_t *__restrict__ sstart)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t gbase[256];   // next global slot of each super-tile
@@ -439,7 +446,9 @@ k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ cou
     __shared__ uint2 srect[kSortThreads];
     __shared__ uint32_t w8[8];
     const int tid = threadIdx.x, wid = tid / kWave;
-    if ((int64_t)*ktotal > cap) return;  // (uniform) overflow: nothing is placed
+    const bool ovf = (int64_t)*ktotal > cap;  // (uniform) overflow: nothing is placed
+    if (blockIdx.x == 0) chunk_tables(sranges, totals, nsup, cstart, csuper, max_chunks, nchunks, sstart, ovf, w8);
+    if (ovf) return;
     {
         uint32_t tot;
         const uint32_t ex = block_excl_scan(totals[tid], w8, &tot);
@@ -609,17 +618,13 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
 
 // Chunk table: chunk c covers entries [sranges[s].x + (c - cstart[s]) kBinChunk, ...) of
 // super-tile s = csuper[c]; *nchunks = number of chunks (capped at max_chunks).
-__global__ void __launch_bounds__(kSortThreads)
-k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
-             uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, const uint32_t *__restrict__ ktotal,
-             int64_t cap)
+__device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
+                             uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
+                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, bool ovf, uint32_t *w)
 {
-    __shared__ uint32_t w[8];
     if (digit_totals) {
         // one radix pass sorted the super-tile keys: their ranges are the scanned digit totals
-        // (empty when the pairs overflowed the capacity, ktotal non-null: nothing was placed)
-        const bool ovf = ktotal && (int64_t)*ktotal > cap;
+        // (empty when the pairs overflowed the capacity: nothing was placed)
         uint32_t carry = 0;
         for (int base = 0; base < nsup; base += kSortThreads) {
             const int sidx = base + threadIdx.x;
@@ -659,6 +664,17 @@ k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_tot
         *nchunks = min(carry, max_chunks);
         if (sstart) sstart[nsup] = scarry;
     }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
+             uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
+             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, const uint32_t *__restrict__ ktotal,
+             int64_t cap)
+{
+    __shared__ uint32_t w[8];
+    chunk_tables(sranges, digit_totals, nsup, cstart, csuper, max_chunks, nchunks, sstart,
+                 ktotal && (int64_t)*ktotal > cap, w);
 }
 
 // Coverage of one super-tile entry from the box in its key's top byte: bit (ly * kSuper + lx)
@@ -1405,11 +1421,12 @@ void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32
 
 void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
                           const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
-                          hipStream_t s)
+                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, hipStream_t s)
 {
     const int G = (int)project_blocks(n);
     hipLaunchKernelGGL(k_super_scatter, dim3((unsigned)G), dim3(kSortThreads), 0, s, rect, count, n, supers_x, hist,
-                       totals, ktotal, cap, keys, vals);
+                       totals, ktotal, cap, keys, vals, sranges, nsup, b.cstart, b.csuper, (uint32_t)b.max_chunks,
+                       b.nchunks, sstart);
 }
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
