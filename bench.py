@@ -461,7 +461,6 @@ def full_loss_extra(F, steps: int = 50) -> dict:
                          **{f"ms_{k}": v for k, v in pct(per).items()})
         if name == "full":
             out[name]["ssim_ms_per_step"] = round(rep["ssim"][0] / 10, 4)
-            out[name]["loss_ms_per_step"] = round(rep["loss"][0] / 10, 4)
             out[name]["scale_regulariser"] = float(reg)
     return out
 

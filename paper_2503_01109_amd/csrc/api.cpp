@@ -344,7 +344,7 @@ fgs_status ensure_bin(fgs_ctx *ctx, int64_t nsup, int64_t T, int64_t cap)
     HIP_TRY(ctx, ctx->bin_csuper.ensure((size_t)mc * 4));
     HIP_TRY(ctx, ctx->bin_chist.ensure((size_t)mc * kSuper * kSuper * 4));
     HIP_TRY(ctx, ctx->bin_tile_total.ensure((size_t)tt * 4));
-    HIP_TRY(ctx, ctx->bin_words.ensure(64));
+    HIP_TRY(ctx, ctx->bin_words.ensure((size_t)(16 + kBinGrid) * 4));
     ctx->bin_nsup = ns;
     ctx->bin_T = tt;
     ctx->bin_cap = cc;
@@ -360,6 +360,7 @@ BinWS bin_ws(fgs_ctx *ctx)
     b.tile_total = ctx->bin_tile_total.as<uint32_t>();
     b.nchunks = ctx->bin_words.as<uint32_t>();
     b.ok = ctx->bin_words.as<uint32_t>() + 1;
+    b.vpart = ctx->bin_words.as<uint32_t>() + 16;
     b.max_chunks = bin_max_chunks(ctx->bin_cap, ctx->bin_nsup);
     return b;
 }
@@ -587,9 +588,11 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
     {
         // tile ranges, then the tile lists
         Stage st_(ctx, "tile_bin");
-        launch_bin_count(bw, okeys, sranges, s);
+        // (with a mapping loss, also the depth term's 1/P_v)
+        const bool dsc = loss && loss->ddepth_scale;
+        launch_bin_count(bw, okeys, sranges, s, dsc ? loss->tdepth : nullptr, (int64_t)cam.width * cam.height);
         launch_bin_tiles(bw, nsup, L.cap, ktotal, sp.ranges, status_words(ctx), npairs, host_status, step_ovf,
-                         first_of_step, s);
+                         first_of_step, s, dsc ? loss->ddepth_scale : nullptr);
         launch_bin_place(bw, okeys, ovals, sranges, sp.ranges, sp.vals, s);
     }
     if (raster) {
@@ -632,11 +635,12 @@ fgs_status enqueue_forward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camer
 
 
 // Enqueue the backward of one view: grad_out (nullable) = grad_in (nullable) + this view's
-// gradient; adam (nullable) applies that sum to g.
+// gradient; adam (nullable) applies that sum to g; lf (nullable) is the view's loss reduction,
+// done by the projection backward.
 fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_camera &cam, const fgs_render_opts &o,
                             int tw, int th, const void *state, const StateLayout &L, const float *drgb,
                             const float *ddepth, const float *dalpha, const float *dscale, const fgs_gaussians *grad_in,
-                            const fgs_gaussians *grad_out, const AdamK *adam)
+                            const fgs_gaussians *grad_out, const AdamK *adam, const LossFinalK *lf = nullptr)
 {
     fgs_status st = ensure_ws(ctx, g.n, 0);
     if (st != FGS_OK) return st;
@@ -656,7 +660,7 @@ fgs_status enqueue_backward(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_came
         const GradK none{g.n, g.n, nullptr, nullptr, nullptr, nullptr, nullptr};
         AdamK no_adam{};
         launch_project_bwd(to_pk(g), ck, rk, g2, grad_in ? to_gk(*grad_in) : none, grad_out ? to_gk(*grad_out) : none,
-                           adam ? *adam : no_adam, s);
+                           adam ? *adam : no_adam, s, lf ? *lf : LossFinalK{});
     }
     HIP_TRY(ctx, hipGetLastError());
     return FGS_OK;
@@ -1300,6 +1304,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             lk.lrgb = l->lambda_rgb;
             lk.ldepth = l->lambda_depth;
             lk.inv3P = (float)(1.0 / (3.0 * (double)P));
+            lk.ddepth_scale = n > 0 ? dscale : nullptr;  // 1/P_v, written by the binning
             // The pair count is data dependent. A view is checked synchronously (the forward waits
             // for the count after the scan and restarts with a larger state when it does not fit)
             // the first time it is seen (a new index, camera or gaussian count) and whenever its last
@@ -1344,7 +1349,19 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
             ex.reg_scale = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
             ex.reg_out = l->reg_dev;
         }
-        {
+        // the loss and PSNR: reduced by the projection backward's first workgroup (the backward
+        // needs only 1/P_v, which the binning wrote); without gaussians by a launch of their own
+        LossFinalK lf{};
+        if (n > 0) {
+            lf.partials = ctx->ms_partials.as<float>();
+            lf.nb = (int)L.T;
+            lf.P = P;
+            lf.lrgb = l->lambda_rgb;
+            lf.ldepth = l->lambda_depth;
+            lf.loss = loss_dev ? loss_dev + v : nullptr;
+            lf.psnr = psnr_dev ? psnr_dev + v : nullptr;
+            lf.extra = ex;
+        } else {
             Stage st_(ctx, "loss");
             launch_loss_final(ctx->ms_partials.as<float>(), (int)L.T, P, l->lambda_rgb, l->lambda_depth, dscale,
                               loss_dev ? loss_dev + v : nullptr, psnr_dev ? psnr_dev + v : nullptr, s, ex);
@@ -1375,7 +1392,7 @@ fgs_status fgs_map_step(fgs_ctx *ctx, const fgs_gaussians *params, fgs_adam *opt
         }
         if ((st = enqueue_backward(ctx, *params, cam, *o, tw, th, ctx->ms_state.p, L, dl, dl + 3 * P, nullptr, dscale,
                                    v > 0 ? &grad : nullptr, !last || grad_out ? &grad : nullptr,
-                                   last ? &ak : nullptr)) != FGS_OK)
+                                   last ? &ak : nullptr, &lf)) != FGS_OK)
             return st;
     }
     ctx->ms_n = n;

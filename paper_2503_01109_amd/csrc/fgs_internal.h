@@ -186,8 +186,10 @@ struct BinWS {
     uint32_t *tile_total;  // T
     uint32_t *nchunks;     // 1 word
     uint32_t *ok;          // 1 word
+    uint32_t *vpart;       // kBinGrid: valid target-depth pixels per counting workgroup
     int64_t max_chunks;
 };
+constexpr int kBinGrid = 4096;  // workgroups of the expansion kernels (each loops over chunks)
 int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 // digit_totals (nullable): the per-digit totals of a single-pass super-tile sort, from which the
 // super-tile ranges are written into sranges; else sranges holds them already.
@@ -211,7 +213,11 @@ void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32
 void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
                           const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
                           const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, hipStream_t s);
-void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s);
+// With tdepth set (P target depths of the view), the count also sums the valid pixels of the
+// mapping loss's depth term per workgroup, and launch_bin_tiles with dscale set turns them into
+// the term's scale 1/P_v before the rasterizer runs.
+void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s,
+                      const float *tdepth = nullptr, int64_t P = 0);
 // Depth order inside every super-tile list: (kin, vin) hold the lists in ascending gaussian id
 // (ranges sranges, nsup lists, chunk table sstart from launch_bin_chunks); each list is written
 // to (kout, vout) at the same place, stably reordered by dkey[gaussian id] (so in (depth, id)
@@ -224,7 +230,7 @@ void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, u
                      hipStream_t s);
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
                       uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
-                      hipStream_t s);
+                      hipStream_t s, float *dscale = nullptr);
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
                       const uint2 *ranges, uint32_t *vals, hipStream_t s);
 
@@ -316,12 +322,39 @@ struct AdamK {
     float reg_w;
 };
 
+// The structural-similarity term and the scale regulariser (Sec. III-D, Eq. 15 and 16) as reduced
+// by launch_loss_final: ssim_part (ssim_nb per-tile sums of the index, nullable) adds
+// ssim_w (1 - sum / (3 P)) to the loss; reg_part (reg_nb per-workgroup sums of |s1 - s2| + s3,
+// nullable) gives reg_out = reg_scale sum (nullable).
+struct LossExtraK {
+    const float *ssim_part;
+    int ssim_nb;
+    float ssim_w;
+    const float *reg_part;
+    int reg_nb;
+    float reg_scale;
+    float *reg_out;
+};
+
+// A loss reduction handed to the projection backward (partials null: none): the nb per-tile
+// quadruples of the fused forward loss of a W x H = P view with weights lrgb, ldepth (and the
+// extra terms) into the device scalars loss and psnr (nullable), as launch_loss_final computes them.
+struct LossFinalK {
+    const float *partials;
+    int nb;
+    int64_t P;
+    float lrgb, ldepth;
+    float *loss, *psnr;
+    LossExtraK extra;
+};
+
 // Chain rule from the 2D gradient records (by gaussian id) to the 14 parameter gradients of every
 // gaussian: grad_out (nullable) = grad_in (nullable: an earlier views' sum) + this view's, and
 // Adam (when adam.m.mean is set) applies that sum. grad2d is left zeroed. grad_in may equal
-// grad_out (accumulation in place).
+// grad_out (accumulation in place). With lf.partials set, one more workgroup reduces the view's
+// loss (it reads nothing the gradient work writes).
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad_in,
-                        const GradK &grad_out, const AdamK &adam, hipStream_t s);
+                        const GradK &grad_out, const AdamK &adam, hipStream_t s, const LossFinalK &lf = LossFinalK{});
 
 
 // Window backward: sums every view's 2D gradients through its projection per gaussian (view v's
@@ -336,19 +369,6 @@ void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, f
 int64_t loss_partials_size(int64_t P);
 // Reduction of nb partial quadruples (as written by the fused forward loss) into loss, psnr and
 // the depth term's 1/P_v (all device scalars, nullable).
-// The structural-similarity term and the scale regulariser (Sec. III-D, Eq. 15 and 16) as reduced
-// by launch_loss_final: ssim_part (ssim_nb per-tile sums of the index, nullable) adds
-// ssim_w (1 - sum / (3 P)) to the loss; reg_part (reg_nb per-workgroup sums of |s1 - s2| + s3,
-// nullable) gives reg_out = reg_scale sum (nullable).
-struct LossExtraK {
-    const float *ssim_part;
-    int ssim_nb;
-    float ssim_w;
-    const float *reg_part;
-    int reg_nb;
-    float reg_scale;
-    float *reg_out;
-};
 void launch_loss_final(const float *partials, int nb, int64_t P, float lrgb, float ldepth, float *ddepth_scale,
                        float *loss, float *psnr, hipStream_t s, const LossExtraK &extra = LossExtraK{});
 

@@ -6,6 +6,7 @@
 // pixels with a positive target depth, a count only known after the reduction; its gradient is
 // written unscaled and the factor 1/P_v is left in device memory for the consumer.
 #include "fgs_internal.h"
+#include "loss_reduce.h"
 
 namespace fgs {
 
@@ -58,91 +59,17 @@ k_loss_partial(int64_t P, const float *__restrict__ rgb, const float *__restrict
     if (threadIdx.x < 4) partials[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Sum of n floats by one workgroup of kFinalThreads in FP64 and a fixed order (every thread gets
-// the sum).
-__device__ double block_sum(const float *__restrict__ a, int n)
-{
-    constexpr int NW = kFinalThreads / kWave;
-    __shared__ double wred[NW];
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += kFinalThreads) s += (double)a[k];
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    __syncthreads();  // wred may still be read by an earlier call
-    if (__lane_id() == 0) wred[threadIdx.x / kWave] = s;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < NW; ++w) t += wred[w];
-    return t;
-}
-
-// Loss and PSNR from nb per-tile partial quadruples (one workgroup of kFinalThreads), in FP64 and
-// a fixed order. A quadruple is one 16-byte load (partials is 16-byte aligned); each thread puts
-// up to four of them in flight before adding, so the kernel waits on memory about once. The
-// structural-similarity and regulariser terms (extra) are reduced the same way.
-__device__ void loss_reduce(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
-                            float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr,
-                            const LossExtraK &extra = LossExtraK{})
-{
-    const double ssim_sum = extra.ssim_part ? block_sum(extra.ssim_part, extra.ssim_nb) : 0.0;
-    const double reg_sum = extra.reg_part ? block_sum(extra.reg_part, extra.reg_nb) : 0.0;
-    constexpr int NW = kFinalThreads / kWave, U = 4;
-    __shared__ double red[NW][4];
-    const float4 *__restrict__ p4 = reinterpret_cast<const float4 *>(partials);
-    double acc[4] = {0, 0, 0, 0};
-    for (int b0 = 0; b0 < nb; b0 += U * kFinalThreads) {
-        float4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int b = b0 + u * kFinalThreads + (int)threadIdx.x;
-            v[u] = b < nb ? p4[b] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            acc[0] += (double)v[u].x;
-            acc[1] += (double)v[u].y;
-            acc[2] += (double)v[u].z;
-            acc[3] += (double)v[u].w;
-        }
-    }
-    // wave sums (butterfly over the 64 lanes), then the waves' sums in order
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
-    const int wid = threadIdx.x / kWave;
-    if (__lane_id() == 0)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) red[wid][q] = acc[q];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t[4] = {0, 0, 0, 0};
-        for (int w = 0; w < NW; ++w)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) t[q] += red[w][q];
-        const double l1c = t[0], se = t[1], l1d = t[2], nv = t[3];
-        const double scale = nv > 0 ? 1.0 / nv : 0.0;
-        if (ddepth_scale) *ddepth_scale = (float)scale;
-        double L = (double)lrgb * l1c / (3.0 * (double)P) + (double)ldepth * l1d * scale;
-        if (extra.ssim_part) L += (double)extra.ssim_w * (1.0 - ssim_sum / (3.0 * (double)P));
-        if (loss) *loss = (float)L;
-        if (extra.reg_out) *extra.reg_out = (float)(reg_sum * (double)extra.reg_scale);
-        const double mse = se / (3.0 * (double)P);
-        if (psnr) *psnr = (float)(mse > 0 ? 10.0 * log10(1.0 / mse) : INFINITY);
-    }
-}
-
 __global__ void __launch_bounds__(kFinalThreads)
 k_loss_final(const float *__restrict__ partials, int nb, int64_t P, float lrgb, float ldepth,
              float *__restrict__ ddepth_scale, float *__restrict__ loss, float *__restrict__ psnr, LossExtraK extra)
 {
-    loss_reduce(partials, nb, P, lrgb, ldepth, ddepth_scale, loss, psnr, extra);
+    loss_reduce<kFinalThreads>(partials, nb, P, lrgb, ldepth, ddepth_scale, loss, psnr, extra);
 }
 
 __global__ void __launch_bounds__(kFinalThreads)
 k_sum_scaled(const float *__restrict__ a, int n, double scale, float *__restrict__ out)
 {
-    const double t = block_sum(a, n);
+    const double t = block_sum<kFinalThreads>(a, n);
     if (threadIdx.x == 0) *out = (float)(t * scale);
 }
 
@@ -154,7 +81,7 @@ k_loss_final_views(const ViewK *__restrict__ views, int nv, uint32_t total_items
     const int v = blockIdx.x;
     const ViewK &V = views[v];
     const uint32_t end = v + 1 < nv ? views[v + 1].tile_base : total_items;
-    loss_reduce(V.loss.partials, (int)(end - V.tile_base), (int64_t)V.W * V.H, V.loss.lrgb, V.loss.ldepth,
+    loss_reduce<kFinalThreads>(V.loss.partials, (int)(end - V.tile_base), (int64_t)V.W * V.H, V.loss.lrgb, V.loss.ldepth,
                 V.loss.ddepth_scale, loss ? loss + v : nullptr, psnr ? psnr + v : nullptr);
 }
 

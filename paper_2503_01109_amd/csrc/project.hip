@@ -6,6 +6,7 @@
 // fraction so that the rasterizer can form tile-local offsets without losing the fraction to
 // the magnitude of the pixel coordinate.
 #include "fgs_internal.h"
+#include "loss_reduce.h"
 
 namespace fgs {
 
@@ -377,9 +378,19 @@ __device__ inline void adam_update(const AdamK &adam, const ParamsK &g, int64_t 
 // Four waves per SIMD (at most 128 VGPRs, no spills) hide more of the memory latency than the
 // three its FP64 chain rule would otherwise leave room for.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad_in, GradK grad_out, AdamK adam)
+k_project_bwd(ParamsK g, CamK cam, RasterK rk, float *__restrict__ grad2d, GradK grad_in, GradK grad_out, AdamK adam,
+              LossFinalK lf)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t blk = blockIdx.x;
+    if (lf.partials) {
+        // the view's loss, by the first workgroup (dispatched first, so it ends well before the rest)
+        if (blk == 0) {
+            loss_reduce<256>(lf.partials, lf.nb, lf.P, lf.lrgb, lf.ldepth, nullptr, lf.loss, lf.psnr, lf.extra);
+            return;
+        }
+        --blk;
+    }
+    const int64_t i = blk * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
     if (i >= n) return;
     // an overflowed step (incomplete gradient) changes no parameter, moment or step count
@@ -470,12 +481,12 @@ void launch_project_bwd_window(const ParamsK &g, const CamK *cams_dev, int nv, f
 }
 
 void launch_project_bwd(const ParamsK &g, const CamK &cam, const RasterK &rk, float *grad2d, const GradK &grad_in,
-                        const GradK &grad_out, const AdamK &adam, hipStream_t s)
+                        const GradK &grad_out, const AdamK &adam, hipStream_t s, const LossFinalK &lf)
 {
     if (g.n <= 0) return;
-    const int64_t blocks = (g.n + 255) / 256;
+    const int64_t blocks = (g.n + 255) / 256 + (lf.partials ? 1 : 0);
     hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, rk, grad2d, grad_in, grad_out,
-                       adam);
+                       adam, lf);
 }
 
 }  // namespace fgs

@@ -402,7 +402,6 @@ constexpr int kSegItems = 16;
 constexpr int kChunkThreads = 512, kSegChunk = kChunkThreads * kSegItems;  // 8,192 entries per chunk
 constexpr int kMergeThreads = 1024, kMergeLds = 16384;  // lists up to kMergeLds keys merge in LDS
 constexpr uint32_t kBinChunk = 512;    // super-tile list entries per expansion chunk
-constexpr int kBinGrid = 4096;         // workgroups of the expansion kernels (each loops over chunks)
 
 // The tiles of super-tile (sx, sy) that a gaussian's tile rectangle rc covers, as a box of
 // super-tile-local tile coordinates: lx0 | lx1 << 2 | ly0 << 4 | ly1 << 6 (never empty when the
@@ -705,12 +704,32 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
     return cs;
 }
 
-// Per chunk: how many of its entries cover each tile of its super-tile.
+// Per chunk: how many of its entries cover each tile of its super-tile. With tdepth set, every
+// workgroup also counts the pixels of its share of the P target depths that are positive (the
+// valid pixels of the mapping loss's depth term) into vpart[blockIdx.x].
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
-            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist)
+            const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist,
+            const float *__restrict__ tdepth, int64_t P, uint32_t *__restrict__ vpart)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
+    if (tdepth) {
+        __shared__ uint32_t wv[kSortThreads / kWave];
+        const int64_t per = (P + gridDim.x - 1) / gridDim.x, p0 = (int64_t)blockIdx.x * per;
+        const int64_t p1 = min(P, p0 + per);
+        uint32_t v = 0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += kSortThreads) v += tdepth[p] > 0.0f ? 1u : 0u;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0) wv[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < kSortThreads / kWave; ++w) t += wv[w];
+            vpart[blockIdx.x] = t;
+        }
+    }
     const uint32_t nc = *nchunks;
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
@@ -749,15 +768,23 @@ __global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, uint32_t *__re
 
 // Single block: tile ranges from the tile totals (super-tile-major items: each thread takes one
 // super-tile's 16 tiles, the block scans the super-tile sums), the pair count K, and the capacity
-// check; on overflow every range is empty and the condition is recorded.
+// check; on overflow every range is empty and the condition is recorded. With dscale set, also
+// 1/P_v from the nv valid-pixel counts vpart (0 when no pixel is valid), as the loss reduction
+// computes it.
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, const uint32_t *__restrict__ ktotal,
             uint2 *__restrict__ ranges, uint32_t *__restrict__ status, uint32_t *__restrict__ n_pairs_dev,
             uint32_t *__restrict__ host_status, uint32_t *__restrict__ ok, uint32_t *__restrict__ step_ovf,
-            int first_of_step)
+            int first_of_step, const uint32_t *__restrict__ vpart, int nv, float *__restrict__ dscale)
 {
-    constexpr int NB = kSuper * kSuper;
+    constexpr int NB = kSuper * kSuper, R = kBinGrid / kSortThreads;
     __shared__ uint32_t w[8];
+    // the valid-pixel counts (nv <= kBinGrid), loaded together with the tile totals below and
+    // summed after them
+    uint32_t vc[R];
+    if (dscale)
+#pragma unroll
+        for (int r = 0; r < R; ++r) vc[r] = vpart[min((int)threadIdx.x + r * kSortThreads, nv - 1)];
     // K counted by the projection equals the sum of the tile totals whenever the super-tile pairs
     // fit (they are at most K); beyond the capacity nothing is placed
     const uint32_t K = *ktotal;
@@ -780,6 +807,14 @@ k_bin_tiles(const uint32_t *__restrict__ tile_total, int nsup, int64_t cap, cons
                 at += v[l];
             }
         carry += tot;
+    }
+    if (dscale) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v += (int)threadIdx.x + r * kSortThreads < nv ? vc[r] : 0u;
+        uint32_t tot;
+        block_excl_scan(v, w, &tot);
+        if (threadIdx.x == 0) *dscale = tot > 0 ? (float)(1.0 / (double)tot) : 0.0f;
     }
     if (threadIdx.x == 0) {
         status[ST_PAIRS] = K;
@@ -1438,10 +1473,11 @@ void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_tot
                        b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart, ktotal, cap);
 }
 
-void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s)
+void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s,
+                      const float *tdepth, int64_t P)
 {
     hipLaunchKernelGGL(k_bin_count, dim3(grid_for(b.max_chunks, 1, kBinGrid)), dim3(kSortThreads), 0, s, skeys, sranges,
-                       b.cstart, b.csuper, b.nchunks, b.chist);
+                       b.cstart, b.csuper, b.nchunks, b.chist, tdepth, P, b.vpart);
 }
 
 void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
@@ -1466,12 +1502,13 @@ void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, u
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
                       uint32_t *n_pairs_dev, uint32_t *host_status, uint32_t *step_ovf, bool first_of_step,
-                      hipStream_t s)
+                      hipStream_t s, float *dscale)
 {
     hipLaunchKernelGGL(k_bin_prefix, dim3((unsigned)nsup), dim3(kSuper * kSuper), 0, s, b.cstart, b.chist,
                        b.tile_total);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(kSortThreads), 0, s, b.tile_total, nsup, cap, ktotal, ranges, status,
-                       n_pairs_dev, host_status, b.ok, step_ovf, first_of_step ? 1 : 0);
+                       n_pairs_dev, host_status, b.ok, step_ovf, first_of_step ? 1 : 0, b.vpart,
+                       (int)grid_for(b.max_chunks, 1, kBinGrid), dscale);
 }
 
 void launch_bin_place(const BinWS &b, const uint32_t *skeys, const uint32_t *svals, const uint2 *sranges,
