@@ -704,32 +704,16 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
     return cs;
 }
 
-// Per chunk: how many of its entries cover each tile of its super-tile. With tdepth set, every
-// workgroup also counts the pixels of its share of the P target depths that are positive (the
-// valid pixels of the mapping loss's depth term) into vpart[blockIdx.x].
+// Per chunk: how many of its entries cover each tile of its super-tile. With tdepth set, the
+// workgroups without a chunk (all of them when every one has a chunk) also count, each for its
+// share of the P target depths, the positive ones (the valid pixels of the mapping loss's depth
+// term) into vpart[blockIdx.x] (0 for the others).
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist,
             const float *__restrict__ tdepth, int64_t P, uint32_t *__restrict__ vpart)
 {
     __shared__ uint32_t cnt[kSuper * kSuper];
-    if (tdepth) {
-        __shared__ uint32_t wv[kSortThreads / kWave];
-        const int64_t per = (P + gridDim.x - 1) / gridDim.x, p0 = (int64_t)blockIdx.x * per;
-        const int64_t p1 = min(P, p0 + per);
-        uint32_t v = 0;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += kSortThreads) v += tdepth[p] > 0.0f ? 1u : 0u;
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (__lane_id() == 0) wv[threadIdx.x / kWave] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int w = 0; w < kSortThreads / kWave; ++w) t += wv[w];
-            vpart[blockIdx.x] = t;
-        }
-    }
     const uint32_t nc = *nchunks;
     for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
         const ChunkSpan cs = chunk_span(c, sranges, cstart, csuper);
@@ -748,6 +732,28 @@ k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ srange
         if (threadIdx.x < kSuper * kSuper) chist[(size_t)c * (kSuper * kSuper) + threadIdx.x] = cnt[threadIdx.x];
         __syncthreads();  // cnt is cleared for the next chunk
     }
+    if (tdepth) {
+        const uint32_t G = gridDim.x, first = nc < G ? nc : 0u;  // the counting workgroups [first, G)
+        if (blockIdx.x < first) {
+            if (threadIdx.x == 0) vpart[blockIdx.x] = 0u;
+            return;
+        }
+        __shared__ uint32_t wv[kSortThreads / kWave];
+        const int64_t per = (P + (G - first) - 1) / (G - first), p0 = (int64_t)(blockIdx.x - first) * per;
+        const int64_t p1 = min(P, p0 + per);
+        uint32_t v = 0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += kSortThreads) v += tdepth[p] > 0.0f ? 1u : 0u;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0) wv[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < kSortThreads / kWave; ++w) t += wv[w];
+            vpart[blockIdx.x] = t;
+        }
+    }
 }
 
 // Per super-tile (kSuper^2 threads): exclusive prefix of each tile's counts over the super-tile's
@@ -755,15 +761,23 @@ k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ srange
 __global__ void k_bin_prefix(const uint32_t *__restrict__ cstart, uint32_t *__restrict__ chist,
                              uint32_t *__restrict__ tile_total)
 {
+    constexpr int NB = kSuper * kSuper, U = 8;
     const int sidx = blockIdx.x, b = threadIdx.x;
+    const uint32_t c0 = cstart[sidx], c1 = cstart[sidx + 1];
     uint32_t run = 0;
-    for (uint32_t c = cstart[sidx]; c < cstart[sidx + 1]; ++c) {
-        uint32_t *h = chist + (size_t)c * (kSuper * kSuper) + b;
-        const uint32_t v = *h;
-        *h = run;
-        run += v;
+    for (uint32_t c = c0; c < c1; c += U) {
+        // U chunks' counts in flight at once (loads clamped to the last chunk), then their prefixes
+        uint32_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = chist[(size_t)min(c + j, c1 - 1u) * NB + b];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (c + j < c1) {
+                chist[(size_t)(c + j) * NB + b] = run;
+                run += v[j];
+            }
     }
-    tile_total[(size_t)sidx * (kSuper * kSuper) + b] = run;  // zero for tiles beyond the image
+    tile_total[(size_t)sidx * NB + b] = run;  // zero for tiles beyond the image
 }
 
 // Single block: tile ranges from the tile totals (super-tile-major items: each thread takes one
