@@ -927,12 +927,12 @@ k_ranges(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, 
 //    radix sort over 4-bit digits of only the bits that differ within the chunk (key - min, whose
 //    bits above those of max - min are zero), each entry ranked by its thread's own digit counts
 //    and a scan of those counts over the workgroup, the permuted (key, position) pairs written to
-//    LDS and read back. A list of one chunk is then final; the chunks of a longer list go to
-//    scratch as sorted (key, position) runs.
-//  - k_seg_merge: a workgroup per list of several chunks gives each entry its place in the list:
-//    its rank in its own chunk plus, for every other chunk, the number of that chunk's keys that
-//    come before it (binary searches: keys <= it in earlier chunks, < it in later ones, which keeps
-//    equal keys in index order).
+//    LDS and read back. A list of one chunk is then written out whole; the chunks of a longer
+//    list go to scratch as sorted runs (depth key, gaussian id, super-tile key).
+//  - k_seg_merge: the runs of a list are merged stably (the earlier run first on equal keys, which
+//    keeps equal keys in index order) by merge path. A list of two chunks is merged in LDS by
+//    kMergeParts workgroups, each staging both runs and writing its part of the list; a longer
+//    list is merged by one workgroup, level by level through global memory.
 
 template <int NW>
 struct SegShared {
@@ -1193,41 +1193,56 @@ k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
     }
 }
 
-// Merge path of output index o when merging sorted runs a[0, la) and b[0, lb) stably (a first on
-// equal keys): the number of elements of a among the first o outputs.
-__device__ __forceinline__ uint32_t merge_split(const uint32_t *a, uint32_t la, const uint32_t *b, uint32_t lb,
+// Reads of the keys being merged: straight from global memory, or from LDS at the swizzled slot
+// i + i / 64 (one spare word per 64 entries), so that the merge's reads, which step about four
+// entries from lane to lane, fall into distinct banks.
+struct GlobalKeys {
+    const uint32_t *k;
+    __device__ uint32_t operator()(uint32_t i) const { return k[i]; }
+};
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + (i >> 6); }
+struct LdsKeys {
+    const uint32_t *k;
+    __device__ uint32_t operator()(uint32_t i) const { return k[lds_slot(i)]; }
+};
+
+// Merge path of output index o when merging sorted runs a = key[a0, a0 + la) and b = key[b0,
+// b0 + lb) stably (a first on equal keys): the number of elements of a among the first o outputs.
+template <class Keys>
+__device__ __forceinline__ uint32_t merge_split(Keys key, uint32_t a0, uint32_t la, uint32_t b0, uint32_t lb,
                                                 uint32_t o)
 {
     uint32_t lo = o > lb ? o - lb : 0u, hi = min(o, la);
     while (lo < hi) {
         const uint32_t i = (lo + hi) >> 1;  // a[i] is taken before b[o - 1 - i] iff a[i] <= b[o - 1 - i]
-        if (a[i] <= b[o - 1 - i]) lo = i + 1;
+        if (key(a0 + i) <= key(b0 + o - 1 - i)) lo = i + 1;
         else hi = i;
     }
     return lo;
 }
 
 // One thread's kMergeItems consecutive outputs o0 .. of a merge level: runs of L entries of the
-// keys ka[0, n) merged pairwise, stably (the earlier run first on equal keys). Found from the
+// keys [0, n) merged pairwise, stably (the earlier run first on equal keys). Found from the
 // thread's start on the merge path, then branch-free (the heads of both runs are loaded at clamped
-// indices every step, an exhausted run's head reads as all ones). src: each output's index in ka,
-// key: its key. Outputs past n get src = n - 1.
+// indices every step, both loads issued together; an exhausted run's head reads as all ones). src:
+// each output's index in the keys, key: its key. Outputs past n get src = n - 1.
 constexpr int kMergeItems = 8;
-__device__ __forceinline__ void merge_round(const uint32_t *ka, uint32_t n, uint32_t L, uint32_t o0,
+template <class Keys>
+__device__ __forceinline__ void merge_round(Keys keys, uint32_t n, uint32_t L, uint32_t o0,
                                             uint32_t (&src)[kMergeItems], uint32_t (&key)[kMergeItems])
 {
     // the pair of runs holding outputs o0 .. o0 + 7 (a pair spans 2 L >= 8 outputs)
     const uint32_t base = o0 / (2 * L) * (2 * L);
     const uint32_t la = min(L, n - base), lb = min(L, n - base - la);
-    const uint32_t *A = ka + base, *B = A + la;
     const uint32_t o = o0 - base;
-    uint32_t i = merge_split(A, la, B, lb, o), j = o - i;
+    uint32_t i = merge_split(keys, base, la, base + la, lb, o), j = o - i;
+    // the second run's reads stay inside the pair's entries (la >= 1; with lb = 0 they read the
+    // first run's head and are not used)
+    const uint32_t b0 = lb ? base + la : base, bl = lb ? lb - 1u : 0u;
 #pragma unroll
     for (int t = 0; t < kMergeItems; ++t) {
-        // both loads stay inside the pair's entries (la >= 1; with lb = 0 the second one reads
-        // A[0] and is not used)
-        const uint32_t ha = i < la ? A[min(i, la - 1)] : 0xFFFFFFFFu;
-        const uint32_t hb = j < lb ? (lb ? B[min(j, lb - 1)] : A[0]) : 0xFFFFFFFFu;
+        const uint32_t va = keys(base + min(i, la - 1u)), vb = keys(b0 + min(j, bl));
+        const uint32_t ha = i < la ? va : 0xFFFFFFFFu, hb = j < lb ? vb : 0xFFFFFFFFu;
         const bool takeA = i < la && (j >= lb || ha <= hb);
         src[t] = min(takeA ? base + i : base + la + j, n - 1);
         key[t] = takeA ? ha : hb;
@@ -1237,8 +1252,12 @@ __device__ __forceinline__ void merge_round(const uint32_t *ka, uint32_t n, uint
 }
 
 // A list of two chunks (kSegChunk < n <= kMergeLds): one merge level in LDS, the runs' keys, ids
-// and coverage boxes staged first, the outputs read from LDS.
+// and coverage boxes staged first (keys and ids at their swizzled slots), the outputs read from
+// LDS. The workgroup writes the outputs [part P, (part + 1) P) of the list, P = kMergeLds /
+// kMergeParts (its first P / kMergeItems threads).
+constexpr int kMergeParts = 4;
 __device__ __forceinline__ void merge_staged(uint32_t *lk, uint32_t *lid, uint8_t *lbox, uint32_t n, uint32_t x,
+                                             uint32_t part,
                                              const uint32_t *__restrict__ tkey, const uint32_t *__restrict__ tid,
                                              const uint32_t *__restrict__ tsk, uint32_t *__restrict__ kout,
                                              uint32_t *__restrict__ vout)
@@ -1257,22 +1276,25 @@ __device__ __forceinline__ void merge_staged(uint32_t *lk, uint32_t *lid, uint8_
         for (int j = 0; j < J; ++j) {
             const uint32_t i = threadIdx.x + j * kMergeThreads;
             if (i < n) {
-                lk[i] = k[j];
-                lid[i] = v[j];
+                lk[lds_slot(i)] = k[j];
+                lid[lds_slot(i)] = v[j];
                 lbox[i] = (uint8_t)b[j];
             }
         }
     }
     __syncthreads();
     const uint32_t sid = tsk[x] & kSuperKeyMask;  // the super-tile of every key of the list
-    for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
+    constexpr uint32_t P = kMergeLds / kMergeParts;
+    static_assert(P <= kMergeThreads * kMergeItems, "a workgroup's part is one round of its threads");
+    const uint32_t o0 = part * P + threadIdx.x * kMergeItems;
+    if (threadIdx.x * kMergeItems < P && o0 < n) {
         uint32_t src[kMergeItems], key[kMergeItems];
-        merge_round(lk, n, kSegChunk, o0, src, key);
+        merge_round(LdsKeys{lk}, n, kSegChunk, o0, src, key);
         uint32_t kk[kMergeItems], vv[kMergeItems];
 #pragma unroll
         for (int t = 0; t < kMergeItems; ++t) {
             kk[t] = sid | (uint32_t)lbox[src[t]] << kBoxShift;
-            vv[t] = lid[src[t]];
+            vv[t] = lid[lds_slot(src[t])];
         }
         if (o0 + kMergeItems <= n) {
 #pragma unroll
@@ -1300,7 +1322,7 @@ __device__ void merge_global(uint32_t *ka, uint32_t *ia, uint32_t *sa, uint32_t 
         const bool last = 2 * L >= n;
         for (uint32_t o0 = threadIdx.x * kMergeItems; o0 < n; o0 += kMergeThreads * kMergeItems) {
             uint32_t src[kMergeItems], key[kMergeItems];
-            merge_round(ka, n, L, o0, src, key);
+            merge_round(GlobalKeys{ka}, n, L, o0, src, key);
             uint32_t iv[kMergeItems], sv[kMergeItems];
 #pragma unroll
             for (int t = 0; t < kMergeItems; ++t) {
@@ -1328,22 +1350,25 @@ __device__ void merge_global(uint32_t *ka, uint32_t *ia, uint32_t *sa, uint32_t 
     }
 }
 
-// Every list of several chunks, one workgroup each (the sorted runs in (tkey, tid, tsk); tkey2,
-// tid2 and tsk2 are scratch for lists longer than kMergeLds).
+// Every list of several chunks, kMergeParts workgroups per list (blockIdx.x = kMergeParts list +
+// part): a list of two chunks is merged by all of them, each writing its part; a longer one by
+// the first (the sorted runs in (tkey, tid, tsk); tkey2, tid2 and tsk2 are scratch for lists
+// longer than kMergeLds).
 __global__ void __launch_bounds__(kMergeThreads)
 k_seg_merge(uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges,
             uint32_t *__restrict__ tkey, uint32_t *__restrict__ tid, uint32_t *__restrict__ tsk,
             uint32_t *__restrict__ tkey2, uint32_t *__restrict__ tid2, uint32_t *__restrict__ tsk2)
 {
     static_assert(2 * kSegChunk == kMergeLds, "a list that fits in LDS has two chunks: one merge level");
-    __shared__ uint32_t lk[kMergeLds], lid[kMergeLds];
+    __shared__ uint32_t lk[kMergeLds + kMergeLds / 64], lid[kMergeLds + kMergeLds / 64];
     __shared__ uint8_t lbox[kMergeLds];
-    const uint2 rg = sranges[blockIdx.x];
+    const uint32_t part = blockIdx.x % kMergeParts;
+    const uint2 rg = sranges[blockIdx.x / kMergeParts];
     const uint32_t x = rg.x, n = rg.y - rg.x;
     if (n <= (uint32_t)kSegChunk) return;  // one chunk: already in place
-    if (n <= (uint32_t)kMergeLds)
-        merge_staged(lk, lid, lbox, n, x, tkey, tid, tsk, kout, vout);
-    else
+    if (n <= (uint32_t)kMergeLds) {
+        if (part * (kMergeLds / kMergeParts) < n) merge_staged(lk, lid, lbox, n, x, part, tkey, tid, tsk, kout, vout);
+    } else if (part == 0)
         merge_global(tkey + x, tid + x, tsk + x, tkey2 + x, tid2 + x, tsk2 + x, n, kout + x, vout + x);
 }
 
@@ -1510,8 +1535,8 @@ void launch_seg_sort(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, u
     if (nsup <= 0 || max_chunks <= 0) return;
     hipLaunchKernelGGL(k_seg_chunk_sort, dim3((unsigned)max_chunks), dim3(kChunkThreads), 0, s, kin, vin, kout, vout,
                        sranges, sstart, nsup, dkey, t[0], t[1], t[2]);
-    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nsup), dim3(kMergeThreads), 0, s, kout, vout, sranges, t[0], t[1],
-                       t[2], t[3], t[4], t[5]);
+    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)(kMergeParts * nsup)), dim3(kMergeThreads), 0, s, kout, vout, sranges,
+                       t[0], t[1], t[2], t[3], t[4], t[5]);
 }
 
 void launch_bin_tiles(const BinWS &b, int nsup, int64_t cap, const uint32_t *ktotal, uint2 *ranges, uint32_t *status,
