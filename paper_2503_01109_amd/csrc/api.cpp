@@ -340,7 +340,7 @@ fgs_status ensure_bin(fgs_ctx *ctx, int64_t nsup, int64_t T, int64_t cap)
     ctx->ws_gen++;
     HIP_TRY(ctx, ctx->bin_sranges.ensure((size_t)ns * 8));
     HIP_TRY(ctx, ctx->bin_cstart.ensure((size_t)(ns + 1) * 4));
-    HIP_TRY(ctx, ctx->bin_sstart.ensure((size_t)(ns + 1) * 4));
+    HIP_TRY(ctx, ctx->bin_sstart.ensure((size_t)(ns + 1 + seg_max_chunks(cc, ns)) * 4));
     HIP_TRY(ctx, ctx->bin_csuper.ensure((size_t)mc * 4));
     HIP_TRY(ctx, ctx->bin_chist.ensure((size_t)mc * kSuper * kSuper * 4));
     HIP_TRY(ctx, ctx->bin_tile_total.ensure((size_t)tt * 4));
@@ -572,13 +572,14 @@ fgs_status enqueue_bin_raster(fgs_ctx *ctx, const fgs_gaussians &g, const fgs_ca
         if (direct) {
             keys = ctx->pkB.as<uint32_t>();  // (one_pass: svals is pvB)
             launch_super_scatter(po.rect, po.count, g.n, supers_x, shist, stot, ktotal, L.cap, keys, svals, bw,
-                                 sranges, nsup, sstart, s);
+                                 sranges, nsup, sstart, seg_max_chunks(L.cap, nsup), s);
         } else {
             const SortWS sws = sort_ws(ctx, L.cap, kSuperSortPerBlock);
             keys = launch_radix_sort(ctx->pkA.as<uint32_t>(), ctx->pvA.as<uint32_t>(), ctx->pkB.as<uint32_t>(),
                                      ctx->pvB.as<uint32_t>(), svals, nsup_pairs, L.cap, sbits, sws, s);
             if (!one_pass) launch_ranges(keys, nsup_pairs, sranges, nsup, kSuperKeyMask, s);
-            launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart);
+            launch_bin_chunks(bw, sranges, one_pass ? sws.totals : nullptr, nsup, s, sstart,
+                              seg_max_chunks(L.cap, nsup));
         }
         uint32_t *const tmp[6] = {ctx->seg[0].as<uint32_t>(), ctx->seg[1].as<uint32_t>(), ctx->seg[2].as<uint32_t>(),
                                   ctx->seg[3].as<uint32_t>(), ctx->seg[4].as<uint32_t>(), ctx->seg[5].as<uint32_t>()};

@@ -196,10 +196,12 @@ int64_t bin_max_chunks(int64_t cap, int64_t nsup);
 void launch_bin_counts(const BinWS &b, const uint32_t *skeys, uint2 *sranges, const uint32_t *digit_totals, int nsup,
                        hipStream_t s);
 // The two halves of launch_bin_counts: the chunk table (and sranges from digit_totals; with
-// sstart non-null, also the first depth-order chunk of every super-tile list, nsup + 1 words), then
-// the per-chunk tile counts.
+// sstart non-null, also the first depth-order chunk of every super-tile list, nsup + 1 words,
+// followed by the super-tile of each of the at most smax depth-order chunks), then the per-chunk
+// tile counts.
 void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
-                       uint32_t *sstart = nullptr, const uint32_t *ktotal = nullptr, int64_t cap = 0);
+                       uint32_t *sstart = nullptr, int64_t smax = 0, const uint32_t *ktotal = nullptr,
+                       int64_t cap = 0);
 // Super-tile lists of one view with at most 256 super-tiles, straight from the projection
 // (launch_project with shist): launch_super_scan scans the per-workgroup super-tile counts hist
 // (256 x project_blocks(n) words) over the workgroups in place, writes the super-tile totals
@@ -212,7 +214,7 @@ void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32
                        uint32_t *ktotal, hipStream_t s);
 void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
                           const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
-                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, hipStream_t s);
+                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, int64_t smax, hipStream_t s);
 // With tdepth set (P target depths of the view), the count also sums the valid pixels of the
 // mapping loss's depth term per workgroup, and launch_bin_tiles with dscale set turns them into
 // the term's scale 1/P_v before the rasterizer runs.

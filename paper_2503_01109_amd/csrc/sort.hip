@@ -421,11 +421,13 @@ __device__ inline uint32_t cover_box(uint2 rc, uint32_t sx, uint32_t sy)
 // super-tile, kScatterTile at a time through LDS like k_radix_scatter_lds, to the offsets of hist
 // (the projection's per-workgroup super-tile counts, hist[s G + b], scanned per super-tile by
 // k_radix_rowscan) after the totals of the super-tiles before. The lists come out in gaussian
-// order. Nothing is written when the (tile, gaussian) pairs *ktotal exceed cap. Workgroup 0 also
-// writes the lists' ranges and chunk tables (as k_bin_chunks; empty on overflow).
+// order. Nothing is written when the (tile, gaussian) pairs *ktotal exceed cap. One more
+// workgroup (the last) writes the lists' ranges and chunk tables (as k_bin_chunks; empty on
+// overflow).
 __device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
                              uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, bool ovf, uint32_t *w);
+                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, uint32_t smax, bool ovf,
+                             uint32_t *w);
 
 __global__ void __launch_bounds__(kSortThreads)
 k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ count, int64_t n, int32_t supers_x,
@@ -433,7 +435,7 @@ k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ cou
                 const uint32_t *__restrict__ ktotal, int64_t cap, uint32_t *__restrict__ kout,
                 uint32_t *__restrict__ vout, uint2 *__restrict__ sranges, int nsup, uint32_t *__restrict__ cstart,
                 uint32_t *__restrict__ csuper, uint32_t max_chunks, uint32_t *__restrict__ nchunks,
-                uint32_t *__restrict__ sstart)
+                uint32_t *__restrict__ sstart, uint32_t smax)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t gbase[256];   // next global slot of each super-tile
@@ -445,22 +447,29 @@ k_super_scatter(const uint2 *__restrict__ rect, const uint32_t *__restrict__ cou
     __shared__ uint2 srect[kSortThreads];
     __shared__ uint32_t w8[8];
     const int tid = threadIdx.x, wid = tid / kWave;
+    const uint32_t G = gridDim.x - 1;  // the projection's workgroups; the last one writes the tables
     const bool ovf = (int64_t)*ktotal > cap;  // (uniform) overflow: nothing is placed
-    if (blockIdx.x == 0) chunk_tables(sranges, totals, nsup, cstart, csuper, max_chunks, nchunks, sstart, ovf, w8);
+    if (blockIdx.x == G) {
+        chunk_tables(sranges, totals, nsup, cstart, csuper, max_chunks, nchunks, sstart, smax, ovf, w8);
+        return;
+    }
+    // every load that does not depend on another issued first
+    const int64_t gi = (int64_t)blockIdx.x * kSortThreads + tid;
+    const uint32_t c = gi < n ? count[gi] : 0u;
+    const uint2 rc0 = gi < n ? rect[gi] : make_uint2(1u, 0u);
+    const uint32_t tv = totals[tid], hv = hist[(size_t)tid * G + blockIdx.x];
     if (ovf) return;
     {
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(totals[tid], w8, &tot);
-        gbase[tid] = ex + hist[(size_t)tid * gridDim.x + blockIdx.x];
+        const uint32_t ex = block_excl_scan(tv, w8, &tot);
+        gbase[tid] = ex + hv;
         run[tid] = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
     }
-    const int64_t gi = (int64_t)blockIdx.x * kSortThreads + tid;
-    const uint32_t c = gi < n ? count[gi] : 0u;
     uint32_t P;
     soff[tid] = block_excl_scan(c, w8, &P);  // (synchronizes the block)
-    srect[tid] = gi < n ? rect[gi] : make_uint2(1u, 0u);
+    srect[tid] = rc0;
     __syncthreads();
     for (uint32_t t0 = 0; t0 < P; t0 += kScatterTile) {
         const uint32_t nt = min((uint32_t)kScatterTile, P - t0);
@@ -619,7 +628,8 @@ k_emit(const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ ids, 
 // super-tile s = csuper[c]; *nchunks = number of chunks (capped at max_chunks).
 __device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
                              uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, bool ovf, uint32_t *w)
+                             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, uint32_t smax, bool ovf,
+                             uint32_t *w)
 {
     if (digit_totals) {
         // one radix pass sorted the super-tile keys: their ranges are the scanned digit totals
@@ -652,9 +662,13 @@ __device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__rest
         }
         carry += tot;
         if (sstart) {
-            // the depth-order chunks of kSegChunk entries: first chunk of every super-tile
+            // the depth-order chunks of kSegChunk entries: first chunk of every super-tile, and
+            // after the nsup + 1 starts the super-tile of every chunk (at most smax chunks)
             const uint32_t sex = scarry + block_excl_scan(nsc, w, &tot);
-            if (sidx < nsup) sstart[sidx] = sex;
+            if (sidx < nsup) {
+                sstart[sidx] = sex;
+                for (uint32_t k = 0; k < nsc && sex + k < smax; ++k) sstart[nsup + 1 + sex + k] = (uint32_t)sidx;
+            }
             scarry += tot;
         }
     }
@@ -668,11 +682,11 @@ __device__ void chunk_tables(uint2 *__restrict__ sranges, const uint32_t *__rest
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_chunks(uint2 *__restrict__ sranges, const uint32_t *__restrict__ digit_totals, int nsup,
              uint32_t *__restrict__ cstart, uint32_t *__restrict__ csuper, uint32_t max_chunks,
-             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, const uint32_t *__restrict__ ktotal,
-             int64_t cap)
+             uint32_t *__restrict__ nchunks, uint32_t *__restrict__ sstart, uint32_t smax,
+             const uint32_t *__restrict__ ktotal, int64_t cap)
 {
     __shared__ uint32_t w[8];
-    chunk_tables(sranges, digit_totals, nsup, cstart, csuper, max_chunks, nchunks, sstart,
+    chunk_tables(sranges, digit_totals, nsup, cstart, csuper, max_chunks, nchunks, sstart, smax,
                  ktotal && (int64_t)*ktotal > cap, w);
 }
 
@@ -1041,18 +1055,6 @@ __device__ __forceinline__ int seg_passes(uint32_t mn, uint32_t mx)
     return x ? (32 - __clz(x) + 3) / 4 : 0;
 }
 
-// Largest s in [0, nsup) with a[s] <= v (a non-decreasing, a[0] = 0 <= v).
-__device__ inline int last_le_i(const uint32_t *__restrict__ a, int nsup, uint32_t v)
-{
-    int lo = 0, hi = nsup - 1;
-    while (lo < hi) {
-        const int mid = lo + ((hi - lo + 1) >> 1);
-        if (a[mid] <= v) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ void __launch_bounds__(kChunkThreads)
 k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                  uint32_t *__restrict__ vout, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ sstart,
@@ -1068,9 +1070,10 @@ k_seg_chunk_sort(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
     __shared__ SegShared<NW> S;
     __shared__ uint32_t red[2 * NW];
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
-    const uint32_t c = blockIdx.x;
-    if (c >= sstart[nsup]) return;
-    const int sidx = last_le_i(sstart, nsup, c);
+    const uint32_t c = blockIdx.x;  // (< the chunks sstart has room for: the grid)
+    const uint32_t nchunk = sstart[nsup], ssup = sstart[nsup + 1 + c];
+    if (c >= nchunk) return;
+    const int sidx = (int)ssup;
     const uint2 rg = sranges[sidx];
     const uint32_t x0 = rg.x + (c - sstart[sidx]) * (uint32_t)kSegChunk;  // the chunk's first entry
     const uint32_t n = min((uint32_t)kSegChunk, rg.y - x0);
@@ -1495,21 +1498,21 @@ void launch_super_scan(int64_t n, uint32_t *hist, uint32_t *totals, const uint32
 
 void launch_super_scatter(const uint2 *rect, const uint32_t *count, int64_t n, int32_t supers_x, const uint32_t *hist,
                           const uint32_t *totals, const uint32_t *ktotal, int64_t cap, uint32_t *keys, uint32_t *vals,
-                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, hipStream_t s)
+                          const BinWS &b, uint2 *sranges, int nsup, uint32_t *sstart, int64_t smax, hipStream_t s)
 {
-    const int G = (int)project_blocks(n);
-    hipLaunchKernelGGL(k_super_scatter, dim3((unsigned)G), dim3(kSortThreads), 0, s, rect, count, n, supers_x, hist,
+    const int G = (int)project_blocks(n);  // (and one more workgroup for the chunk tables)
+    hipLaunchKernelGGL(k_super_scatter, dim3((unsigned)G + 1u), dim3(kSortThreads), 0, s, rect, count, n, supers_x, hist,
                        totals, ktotal, cap, keys, vals, sranges, nsup, b.cstart, b.csuper, (uint32_t)b.max_chunks,
-                       b.nchunks, sstart);
+                       b.nchunks, sstart, (uint32_t)smax);
 }
 
 int64_t bin_max_chunks(int64_t cap, int64_t nsup) { return (cap + kBinChunk - 1) / kBinChunk + nsup; }
 
 void launch_bin_chunks(const BinWS &b, uint2 *sranges, const uint32_t *digit_totals, int nsup, hipStream_t s,
-                       uint32_t *sstart, const uint32_t *ktotal, int64_t cap)
+                       uint32_t *sstart, int64_t smax, const uint32_t *ktotal, int64_t cap)
 {
     hipLaunchKernelGGL(k_bin_chunks, dim3(1), dim3(kSortThreads), 0, s, sranges, digit_totals, nsup, b.cstart,
-                       b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart, ktotal, cap);
+                       b.csuper, (uint32_t)b.max_chunks, b.nchunks, sstart, (uint32_t)smax, ktotal, cap);
 }
 
 void launch_bin_count(const BinWS &b, const uint32_t *skeys, const uint2 *sranges, hipStream_t s,
