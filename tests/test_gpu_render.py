@@ -245,18 +245,19 @@ def test_many_gaussians_take_the_two_level_scan(fgs, ctx):
     del b, big
 
 
-@pytest.mark.parametrize("n", [16_384, 16_385, 40_000])
+@pytest.mark.parametrize("n", [8_193, 12_289, 16_384, 16_385, 40_000])
 def test_super_tile_list_longer_than_lds(fgs, ctx, n):
     """A 64x48 frame is one super-tile, whose list holds every gaussian (each covers at least the
-    pixel nearest its centre). Up to 16,384 entries the list is put in depth order in LDS; 16,385
-    and 40,000 take the path through global memory, 16,384 entries at a time in each pass. Forward
-    against the oracle, and the gradient in the 16,385 case."""
+    pixel nearest its centre). A list of two chunks (up to 16,384 entries) is merged in LDS by four
+    workgroups, a quarter each (8,193 and 12,289 leave the last quarters short or empty); 16,385 and
+    40,000 take the path through global memory. Forward against the oracle, and the gradient in the
+    12,289 and 16,385 cases."""
     cam = synth.camera_small()
     p = synth.frustum_scene(40 + n % 7, n, cam, 1.0, 5.0)
     opts = fgs.RenderOpts()
     out, ref = check_forward(fgs, ctx, p, cam, opts, max_amb_frac=0.02)
     assert ctx.stats()["visible"] == n
-    if n == 16_385:
+    if n in (12_289, 16_385):
         check_backward(fgs, ctx, p, cam, opts, out, ref, seed=3)
 
 
