@@ -115,6 +115,59 @@ def test_map_step_matches_oracle(fgs, ctx):
     np.testing.assert_allclose(host(pd)[big], expect[big], rtol=1e-6, atol=1e-6)
 
 
+def test_map_step_invalid_target_depths(fgs, ctx):
+    """The depth term averages over the P_v pixels whose target depth is positive (Sec. III-D,
+    Eq. 16), a count the mapping step takes from the target before the forward: a target with a
+    band of zero and a band of negative depths gives the oracle's loss, PSNR and gradient."""
+    import torch
+    p, cam, seed = zero_ambiguity_scene()
+    n = p.shape[1]
+    ref = oracle.render_fwd(p.astype(np.float64), cam, oracle_opts(), amb_rel=0)
+    g = synth.rng(seed)
+    trgb = g.uniform(size=(3, cam.height, cam.width)).astype(np.float32)
+    td = g.uniform(1.0, 5.0, (cam.height, cam.width)).astype(np.float32)
+    td[:9] = 0.0
+    td[30:34] = -1.0
+    near = np.abs(ref["rgb"] - trgb) < 1e-3
+    trgb[near] += 0.01
+    dnear = np.abs(ref["depth"] - td) < 1e-3
+    td[dnear & (td > 0)] += 0.01
+    L, ps, gr, gd = oracle.loss_l1(ref["rgb"], ref["depth"], trgb, td, 1.0, 0.1)
+    gref, _, mass = oracle.render_bwd(p.astype(np.float64), cam, gr, gd, None, oracle_opts(), mass=True)
+    pd = dev(p)
+    adam = fgs.Adam.like(pd, lr=(0, 0, 0, 0, 0))
+    grad = torch.zeros_like(pd)
+    loss, psnr = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    fgs.map_step(ctx, pd, n, adam, [cam], [(dev(trgb), dev(td))], fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1),
+                 loss, psnr, grad_out=grad)
+    ctx.check()
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert abs(float(psnr) - ps) <= 1e-5 * ps
+    assert_grad_close(host(grad), gref, mass, "map step, invalid target depths")
+
+
+def test_map_step_without_gaussians(fgs, ctx):
+    """With no gaussians the rendered view is the background (colour 0, depth 0): the loss and PSNR
+    are the oracle's for that image, and the step leaves the (empty) parameters alone."""
+    import torch
+    cam = synth.camera_small()
+    g = synth.rng(7)
+    trgb = g.uniform(size=(3, cam.height, cam.width)).astype(np.float32)
+    td = g.uniform(1.0, 5.0, (cam.height, cam.width)).astype(np.float32)
+    td[:5] = 0.0
+    zc = np.zeros((3, cam.height, cam.width))
+    zd = np.zeros((cam.height, cam.width))
+    L, ps, _, _ = oracle.loss_l1(zc, zd, trgb, td, 1.0, 0.1)
+    pd = torch.zeros((14, 0), device="cuda")
+    adam = fgs.Adam.like(pd, lr=LR)
+    loss, psnr = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    fgs.map_step(ctx, pd, 0, adam, [cam], [(dev(trgb), dev(td))], fgs.RenderOpts(), fgs.LossOpts(1.0, 0.1),
+                 loss, psnr)
+    ctx.check()
+    assert abs(float(loss) - L) <= 1e-5 * L
+    assert abs(float(psnr) - ps) <= 1e-5 * ps
+
+
 def test_map_step_multiview_sums_views(fgs, ctx):
     """The mapping step's gradient over three views equals the sum of single-view gradients
     (render_fwd + loss + render_bwd through the ABI)."""
