@@ -443,7 +443,11 @@ __device__ __forceinline__ BwdPair bwd_decide(const float4 &a4, const float4 &b4
     p.e = eval_pair(a4, b4, px, py);
     p.ar = b4.y * p.e.G;
     p.alpha = fminf(rk.alpha_max, p.ar);
-    p.take = before_last && !(p.e.q < qcut) && !(p.alpha < rk.alpha_min);
+    // before the last blended position and inside the cutoff, else -1 (below every alpha_min,
+    // which is at least 0): one comparison decides, so that the wave's ballot of the decision is
+    // that comparison's own lane mask
+    const float a_in = before_last && !(p.e.q < qcut) ? p.alpha : -1.0f;
+    p.take = !(a_in < rk.alpha_min);
     return p;
 }
 
@@ -598,7 +602,9 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
             const BwdPair p1 = bwd_decide(a1, b1, base + k1 < L, px, py, qcut, rk);
-            const uint64_t t0 = __ballot(p0.take), t1 = __ballot(p1.take);
+            // (the lane-mask ballot of the decision itself: through an int it would cost a select
+            // and a compare per entry)
+            const uint64_t t0 = __builtin_amdgcn_ballot_w64(p0.take), t1 = __builtin_amdgcn_ballot_w64(p1.take);
             if (COUNT) {
                 count_entry(t0);
                 count_entry(t1);
@@ -609,21 +615,26 @@ __device__ void tile_bwd(const ViewK &V, int tile)
                 bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
                 const float t = reduce20(g0, g1, lane);
                 if (slot20 >= 0) atomicAdd(&sacc[slot20 < 10 ? k0 : k1][slot20 % 10], t);
-            } else if (t0 || t1) {
+            } else if (t0) {
                 // one entry blended by some lane: the other leaves every lane's T and S as they are
-                const int k = t0 ? k0 : k1;
                 float g[10];
-                bwd_grad(t0 ? p0 : p1, t0 ? b0 : b1, sc[k], rk, gC0, gC1, gC2, gD, T, S, g);
+                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g);
                 const float t = reduce10(g, lane);
-                if (red_lane) atomicAdd(&sacc[k][term], t);
+                if (red_lane) atomicAdd(&sacc[k0][term], t);
+            } else if (t1) {
+                float g[10];
+                bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g);
+                const float t = reduce10(g, lane);
+                if (red_lane) atomicAdd(&sacc[k1][term], t);
             }
         }
         if (i == 0) {
             const int k0 = slist[wid][0];
             const float4 a0 = sa[k0], b0 = sb[k0];
             const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
-            if (COUNT) count_entry(__ballot(p0.take));
-            if (__ballot(p0.take)) {
+            const uint64_t t0 = __builtin_amdgcn_ballot_w64(p0.take);
+            if (COUNT) count_entry(t0);
+            if (t0) {
                 float g0[10];
                 bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
                 const float t0 = reduce10(g0, lane);
