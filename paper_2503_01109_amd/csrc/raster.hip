@@ -263,6 +263,8 @@ __device__ void tile_fwd(const ViewK &V, int tile)
     const uint2 range = V.ranges[tile];
     const float cut2 = rk.sigma_cut * rk.sigma_cut;
     const float qcut = kConicScale * cut2;
+    // (canonical once here, so that the pair loop's minimum needs no canonicalising of its own)
+    const float amax = __builtin_canonicalizef(rk.alpha_max);
 
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
     uint32_t last = 0, ntest = 0, staged = 0;
@@ -308,7 +310,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             const float4 a4 = sa[k], b4 = sb[k];
             const PairEval e = eval_pair(a4, b4, px, py);
             const bool near = !(e.q < qc);
-            const float alpha = fminf(rk.alpha_max, b4.y * e.G);
+            const float alpha = fminf(amax, b4.y * e.G);
             const bool take = near && !(alpha < rk.alpha_min);
             const float u = alpha * T, Tn = T - u;
             const bool low = Tn < rk.T_min;
