@@ -183,8 +183,11 @@ __device__ __forceinline__ float reduce10(const float v[10], int lane)
     const float r0 = dpp_add<0xB1, 1>(q0, q2, lane);
     const float r1 = q1 + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(q1), 0xB1, 0xf, 0xf, false));
     float d = dpp_add<0x4E, 2>(r0, r1, lane);
-    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x124, 0xf, 0xf, false));  // row_ror:4
-    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, false));  // row_ror:8
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x124, 0xf, 0xf, true));  // row_ror:4
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, true));  // row_ror:8
+    // (kept here, where the rotation and the add fuse into one instruction, rather than moved
+    // into the lanes that use the sum)
+    asm volatile("" : "+v"(d));
     return d;
 }
 
@@ -220,7 +223,8 @@ __device__ __forceinline__ float reduce20(const float u[10], const float v[10], 
     const float send = b2 ? t0 : t1, mine = b2 ? t1 : t0;
     // ds_swizzle bitmask mode: and 0x1f, or 0, xor 4 (the partner across lane distance 4)
     float d = mine + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(send), 0x101F));
-    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, false));  // row_ror:8
+    d += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x128, 0xf, 0xf, true));  // row_ror:8
+    asm volatile("" : "+v"(d));  // (as in reduce10)
     return d;
 }
 
@@ -594,6 +598,9 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         }
         __syncthreads();
         const uint32_t base = bstart - range.x;
+        // this pixel's last blended position relative to the batch (negative: before it), so that
+        // an entry's test is one comparison of its batch slot (list positions stay below 2^31)
+        const int Lb = (int)L - (int)base;
         const int len = wave_compact(smask, (int)min((uint32_t)cnt, wL > base ? wL - base : 0u), wid, slist[wid]);
         // Branch-free per pair, like the forward: the decisions select what is kept, and a lane
         // that does not take the pair contributes exact zeros. Two entries per iteration: their
@@ -602,8 +609,8 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         for (; i >= 1; i -= 2) {
             const int k0 = slist[wid][i], k1 = slist[wid][i - 1];
             const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
-            const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
-            const BwdPair p1 = bwd_decide(a1, b1, base + k1 < L, px, py, qcut, rk);
+            const BwdPair p0 = bwd_decide(a0, b0, k0 < Lb, px, py, qcut, rk);
+            const BwdPair p1 = bwd_decide(a1, b1, k1 < Lb, px, py, qcut, rk);
             // (the lane-mask ballot of the decision itself: through an int it would cost a select
             // and a compare per entry)
             const uint64_t t0 = __builtin_amdgcn_ballot_w64(p0.take), t1 = __builtin_amdgcn_ballot_w64(p1.take);
@@ -633,7 +640,7 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         if (i == 0) {
             const int k0 = slist[wid][0];
             const float4 a0 = sa[k0], b0 = sb[k0];
-            const BwdPair p0 = bwd_decide(a0, b0, base + k0 < L, px, py, qcut, rk);
+            const BwdPair p0 = bwd_decide(a0, b0, k0 < Lb, px, py, qcut, rk);
             const uint64_t t0 = __builtin_amdgcn_ballot_w64(p0.take);
             if (COUNT) count_entry(t0);
             if (t0) {
