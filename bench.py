@@ -44,8 +44,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "46737eeeedf26c11b929a5d1080e5911ece8339c7698296e22460dc8f6d11561",
-                     "tile": "16x16", "fetch_bytes": 46727259, "write_bytes": 16498766},
+    "k_raster_bwd": {"source_sha256": "00a0cf42abdd946a7ce44d7419b6bff60fac46bbbf9bea069c2c870d85c8396c",
+                     "tile": "16x16", "fetch_bytes": 46715978, "write_bytes": 16498766},
 }
 
 
