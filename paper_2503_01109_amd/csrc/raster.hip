@@ -126,8 +126,9 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float ca, floa
     return m;
 }
 
-// Compacts the indices k < cnt whose mask has this wave's bit into this wave's list (ascending);
-// returns the list length. Wave-local: no block barrier needed.
+// Compacts the indices k < cnt whose mask has this wave's bit into this wave's list (ascending), as
+// byte offsets 16 k of the staged 16-byte records; returns the list length. Wave-local: no block
+// barrier needed.
 __device__ __forceinline__ int wave_compact(const uint8_t *smask, int cnt, int wid, uint16_t *list)
 {
     const int lane = __lane_id();
@@ -136,13 +137,20 @@ __device__ __forceinline__ int wave_compact(const uint8_t *smask, int cnt, int w
         const int e = q + lane;
         const bool bit = e < cnt && ((smask[e] >> wid) & 1u);
         const uint64_t bal = __ballot(bit);
-        if (bit) list[len + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)e;
+        if (bit) list[len + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)(e << 4);
         len += __popcll(bal);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return len;
+}
+
+// The staged 16-byte record at byte offset o of an LDS array (the lists hold byte offsets, so a
+// pair's loads take no scaling of their index).
+__device__ __forceinline__ float4 rec_at(const float4 *a, int o)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(a) + o);
 }
 
 // Exchange across lane distance 32 (D = 32) or 16 (D = 16) without selects: lanes whose bit D is
@@ -308,10 +316,10 @@ __device__ void tile_fwd(const ViewK &V, int tile)
         const uint32_t base = b - range.x + 1;
         // Branch-free per pair: every lane evaluates the entry and the decisions select what is
         // kept; T - alpha T is the new transmittance (T (1 - alpha) up to rounding). The last
-        // blended entry of this chunk is kept as its list index and folded into `last` after it.
+        // blended entry of this chunk is kept as its byte offset and folded into `last` after it.
         int lastk = -1;
-        auto pair = [&](int k) {
-            const float4 a4 = sa[k], b4 = sb[k];
+        auto pair = [&](int o) {
+            const float4 a4 = rec_at(sa, o), b4 = rec_at(sb, o);
             const PairEval e = eval_pair(a4, b4, px, py);
             const bool near = !(e.q < qc);
             const float alpha = fminf(amax, b4.y * e.G);
@@ -320,7 +328,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             const bool low = Tn < rk.T_min;
             const bool blend = take && !low;
             const float w = blend ? u : 0.0f;
-            const float4 c4 = sc[k];
+            const float4 c4 = rec_at(sc, o);
             C0 = __builtin_fmaf(w, c4.x, C0);
             C1 = __builtin_fmaf(w, c4.y, C1);
             C2 = __builtin_fmaf(w, c4.z, C2);
@@ -330,11 +338,11 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             qc = take && low ? INFINITY : qc;
             if (COUNT) {
                 ntest += near ? 1u : 0u;
-                if (blend) sblend[k] = 1;
-                if (take && low) cons = base + (uint32_t)k;
+                if (blend) sblend[o >> 4] = 1;
+                if (take && low) cons = base + (uint32_t)(o >> 4);
             }
             if (COUNT || NCON) ncon += blend ? 1 : 0;
-            lastk = blend ? k : lastk;
+            lastk = blend ? o : lastk;
         };
         // two entries per round: the wave leaves the list once all of its pixels are done
         for (int i = 0; i < len; i += 2) {
@@ -342,7 +350,7 @@ __device__ void tile_fwd(const ViewK &V, int tile)
             pair(slist[wid][i]);
             if (i + 1 < len) pair(slist[wid][i + 1]);
         }
-        if (lastk >= 0) last = base + (uint32_t)lastk;
+        if (lastk >= 0) last = base + (uint32_t)(lastk >> 4);
     }
     if (COUNT) {
         // work counters (profiling only): block sums and maxima, one atomic per block and counter
@@ -598,17 +606,18 @@ __device__ void tile_bwd(const ViewK &V, int tile)
         }
         __syncthreads();
         const uint32_t base = bstart - range.x;
-        // this pixel's last blended position relative to the batch (negative: before it), so that
-        // an entry's test is one comparison of its batch slot (list positions stay below 2^31)
-        const int Lb = (int)L - (int)base;
+        // this pixel's last blended position relative to the batch, clamped to [-1, NT] and as a
+        // byte offset, so that an entry's test is one comparison of its list word (list positions
+        // stay below 2^31)
+        const int Lb = min(max((int)L - (int)base, -1), NT) * 16;
         const int len = wave_compact(smask, (int)min((uint32_t)cnt, wL > base ? wL - base : 0u), wid, slist[wid]);
         // Branch-free per pair, like the forward: the decisions select what is kept, and a lane
         // that does not take the pair contributes exact zeros. Two entries per iteration: their
         // evaluations and wave reductions are independent, only T and S pass from one to the next.
         int i = len - 1;
         for (; i >= 1; i -= 2) {
-            const int k0 = slist[wid][i], k1 = slist[wid][i - 1];
-            const float4 a0 = sa[k0], b0 = sb[k0], a1 = sa[k1], b1 = sb[k1];
+            const int k0 = slist[wid][i], k1 = slist[wid][i - 1];  // (byte offsets)
+            const float4 a0 = rec_at(sa, k0), b0 = rec_at(sb, k0), a1 = rec_at(sa, k1), b1 = rec_at(sb, k1);
             const BwdPair p0 = bwd_decide(a0, b0, k0 < Lb, px, py, qcut, rk);
             const BwdPair p1 = bwd_decide(a1, b1, k1 < Lb, px, py, qcut, rk);
             // (the lane-mask ballot of the decision itself: through an int it would cost a select
@@ -620,34 +629,34 @@ __device__ void tile_bwd(const ViewK &V, int tile)
             }
             if (t0 && t1) {
                 float g0[10], g1[10];
-                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
-                bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g1);
+                bwd_grad(p0, b0, rec_at(sc, k0), rk, gC0, gC1, gC2, gD, T, S, g0);
+                bwd_grad(p1, b1, rec_at(sc, k1), rk, gC0, gC1, gC2, gD, T, S, g1);
                 const float t = reduce20(g0, g1, lane);
-                if (slot20 >= 0) atomicAdd(&sacc[slot20 < 10 ? k0 : k1][slot20 % 10], t);
+                if (slot20 >= 0) atomicAdd(&sacc[(slot20 < 10 ? k0 : k1) >> 4][slot20 % 10], t);
             } else if (t0) {
                 // one entry blended by some lane: the other leaves every lane's T and S as they are
                 float g[10];
-                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g);
+                bwd_grad(p0, b0, rec_at(sc, k0), rk, gC0, gC1, gC2, gD, T, S, g);
                 const float t = reduce10(g, lane);
-                if (red_lane) atomicAdd(&sacc[k0][term], t);
+                if (red_lane) atomicAdd(&sacc[k0 >> 4][term], t);
             } else if (t1) {
                 float g[10];
-                bwd_grad(p1, b1, sc[k1], rk, gC0, gC1, gC2, gD, T, S, g);
+                bwd_grad(p1, b1, rec_at(sc, k1), rk, gC0, gC1, gC2, gD, T, S, g);
                 const float t = reduce10(g, lane);
-                if (red_lane) atomicAdd(&sacc[k1][term], t);
+                if (red_lane) atomicAdd(&sacc[k1 >> 4][term], t);
             }
         }
         if (i == 0) {
-            const int k0 = slist[wid][0];
-            const float4 a0 = sa[k0], b0 = sb[k0];
+            const int k0 = slist[wid][0];  // (a byte offset)
+            const float4 a0 = rec_at(sa, k0), b0 = rec_at(sb, k0);
             const BwdPair p0 = bwd_decide(a0, b0, k0 < Lb, px, py, qcut, rk);
             const uint64_t t0 = __builtin_amdgcn_ballot_w64(p0.take);
             if (COUNT) count_entry(t0);
             if (t0) {
                 float g0[10];
-                bwd_grad(p0, b0, sc[k0], rk, gC0, gC1, gC2, gD, T, S, g0);
+                bwd_grad(p0, b0, rec_at(sc, k0), rk, gC0, gC1, gC2, gD, T, S, g0);
                 const float t0 = reduce10(g0, lane);
-                if (red_lane) atomicAdd(&sacc[k0][term], t0);
+                if (red_lane) atomicAdd(&sacc[k0 >> 4][term], t0);
             }
         }
         __syncthreads();
