@@ -44,8 +44,8 @@ F_FWD_EXAMINED, F_FWD_BLENDED, F_BWD_BLENDED = 14.0, 12.0, 80.0
 # read for a 256 MiB elementwise copy (FETCH x 1.9998, WRITE x 1.0). Valid only for the kernel
 # source it was taken on: reported as null once the rasterizer's source changes.
 MEASURED_TRAFFIC = {
-    "k_raster_bwd": {"source_sha256": "00a0cf42abdd946a7ce44d7419b6bff60fac46bbbf9bea069c2c870d85c8396c",
-                     "tile": "16x16", "fetch_bytes": 46715978, "write_bytes": 16498766},
+    "k_raster_bwd": {"source_sha256": "ebf60f21858de649b92a88a857b9ef4cc8e378490ffe1da23784439ea57d64ec",
+                     "tile": "16x16", "fetch_bytes": 46727177, "write_bytes": 16498766},
 }
 
 
