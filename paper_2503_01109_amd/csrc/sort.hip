@@ -719,9 +719,9 @@ __device__ inline ChunkSpan chunk_span(uint32_t c, const uint2 *sranges, const u
 }
 
 // Per chunk: how many of its entries cover each tile of its super-tile. With tdepth set, the
-// workgroups without a chunk (all of them when every one has a chunk) also count, each for its
-// share of the P target depths, the positive ones (the valid pixels of the mapping loss's depth
-// term) into vpart[blockIdx.x] (0 for the others).
+// workgroups that have no chunk (or, when every workgroup has one, all of them) also count, each
+// for its share of the P target depths, the positive ones (the valid pixels of the mapping loss's
+// depth term) into vpart[blockIdx.x] (0 for the others).
 __global__ void __launch_bounds__(kSortThreads)
 k_bin_count(const uint32_t *__restrict__ skeys, const uint2 *__restrict__ sranges, const uint32_t *__restrict__ cstart,
             const uint32_t *__restrict__ csuper, const uint32_t *__restrict__ nchunks, uint32_t *__restrict__ chist,
